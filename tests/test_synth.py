@@ -1,0 +1,238 @@
+"""Pins of the seeded input generator against closed forms and invariants of the paper's
+discretisation (Sec. 3): generalized-alpha constants, P1 stiffness on the Kuhn grid, the metric
+tensor's vertex-permutation invariance, rigid-motion kernels of the deviatoric operator, the
+block structure [A G; D C] with D = -G^T, interface pressure duplication, Dirichlet rows."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+from tests.conftest import bsr_to_dense
+
+
+def test_genalpha_constants():
+    # Sec. 3.4: alpha_m = (3 - rho)/(2(1 + rho)), alpha_f = gamma = 1/(1 + rho); rho = 0.5
+    am, af, g = synth.genalpha(0.5)
+    assert am == pytest.approx(5.0 / 6.0, abs=1e-15)
+    assert af == pytest.approx(2.0 / 3.0, abs=1e-15)
+    assert g == pytest.approx(2.0 / 3.0, abs=1e-15)
+    am, af, g = synth.genalpha(1.0)          # rho_inf = 1: trapezoidal (1/2, 1/2, 1/2)
+    assert (am, af, g) == (0.5, 0.5, 0.5)
+
+
+def _box(nx, ny, nz, h, **kw):
+    p = synth.default_params(mode=1, m_core=nx, n_bl=ny, n_wall=0, nz=nz, R=h, **kw)
+    return synth.generate(p, tets=True)
+
+
+def test_box_stiffness_is_seven_point_stencil():
+    # P1 on the Kuhn triangulation of a uniform grid reproduces the 7-point Laplacian:
+    # stiffness = h * [6 on the diagonal, -1 on the six axis neighbours, 0 elsewhere].
+    # The C block of the fluid is tau_M * stiffness (all Kuhn tets are congruent, one tau_M).
+    h = 0.25
+    s = _box(4, 4, 4, h, terms=16, apply_bc=0)
+    C = bsr_to_dense(s.rp, s.ci, s.val[:, 3:4, 3:4])
+    nx = ny = nz = 5
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    tauM = C[idx(2, 2, 2), idx(2, 2, 2)] / (6 * h)
+    for (i, j, k) in [(1, 1, 1), (2, 2, 2), (3, 2, 1), (1, 3, 3)]:
+        row = C[idx(i, j, k)] / (tauM * h)
+        expect = np.zeros_like(row)
+        expect[idx(i, j, k)] = 6.0
+        for d in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+            expect[idx(i + d[0], j + d[1], k + d[2])] = -1.0
+        assert np.abs(row - expect).max() < 1e-12
+
+
+def test_mesh_laplacian_dirichlet_eigenvalues_closed_form():
+    # L_ab = sum over elements of grad N_a . grad N_b (element factor 1/V).  On the uniform Kuhn
+    # grid this is (6/h^2) * 7-point stencil; with Dirichlet on the boundary its interior
+    # eigenvalues are (6/h^2) * sum_d 4 sin^2(k_d pi / (2 (n_d + 1))).
+    h = 0.5
+    nx, ny, nz = 5, 4, 3                       # cells
+    s = _box(nx, ny, nz, h)
+    L = bsr_to_dense(s.Lrp, s.Lci, s.Lval)
+    interior = np.where(s.Lmask == 0)[0]
+    ev = np.sort(np.linalg.eigvalsh(L[np.ix_(interior, interior)]))
+    n = [nx - 1, ny - 1, nz - 1]
+    closed = sorted((6 / h**2) * sum(4 * np.sin(k[d] * np.pi / (2 * (n[d] + 1)))**2 for d in range(3))
+                    for k in itertools.product(*[range(1, n[d] + 1) for d in range(3)]))
+    assert np.allclose(ev, closed, rtol=1e-12, atol=1e-12)
+    # Dirichlet rows are identity rows with zeroed columns
+    bnd = np.where(s.Lmask)[0]
+    assert np.array_equal(L[np.ix_(bnd, bnd)], np.eye(bnd.size))
+    assert not L[np.ix_(bnd, interior)].any() and not L[np.ix_(interior, bnd)].any()
+
+
+def test_box_volume_and_mass():
+    # sum of element volumes = box volume; consistent mass row sums = lumped volume
+    h = 0.3
+    s = _box(3, 2, 4, h, terms=1, apply_bc=0)
+    p = synth.default_params()
+    am, af, g = synth.genalpha(p.rho_inf)
+    ct = am / (af * g * p.dt)
+    A = bsr_to_dense(s.rp, s.ci, s.val[:, :3, :3])
+    total = A.sum() / (3 * p.rho_f * ct)      # mass entries sum to the volume per component
+    assert total == pytest.approx(3 * 2 * 4 * h**3, rel=1e-13)
+
+
+def _random_tet(rng):
+    while True:
+        x = rng.normal(size=(4, 3))
+        if abs(np.linalg.det(x[1:] - x[0])) > 0.2:
+            return x
+
+
+def test_tau_metric_is_vertex_permutation_invariant():
+    # The regular-simplex matrix M makes G = J^-T M J^-1 independent of the vertex order (Sec. 3.2).
+    rng = np.random.default_rng(3)
+    p = synth.default_params()
+    for _ in range(5):
+        x = _random_tet(rng)
+        vals = np.array([synth.tau(x[list(perm)], p) for perm in itertools.permutations(range(4))])
+        assert np.ptp(vals[:, 0]) <= 1e-13 * vals[0, 0]
+        assert np.ptp(vals[:, 1]) <= 1e-12 * vals[0, 1]
+
+
+def test_tau_M_without_viscosity_is_dt_over_two_rho():
+    # tau_M = rho^-1 (C_T/dt^2 + ...)^-1/2 with C_T = 4 and mu = 0 reduces to dt / (2 rho).
+    p = synth.default_params(mu_f=0.0)
+    x = _random_tet(np.random.default_rng(1))
+    tm, _ = synth.tau(x, p)
+    assert tm == pytest.approx(p.dt / (2 * p.rho_f), rel=1e-14)
+
+
+def _rigid(x4):
+    x = x4 - x4.mean(0)
+    modes = []
+    for c in range(3):
+        m = np.zeros((4, 4)); m[:, c] = 1.0; modes.append(m)
+    for (i, j) in [(0, 1), (1, 2), (2, 0)]:
+        m = np.zeros((4, 4)); m[:, i] = -x[:, j]; m[:, j] = x[:, i]; modes.append(m)
+    return [m.reshape(16) for m in modes]
+
+
+@pytest.mark.parametrize("solid", [False, True])
+def test_deviatoric_and_graddiv_annihilate_rigid_motions(solid):
+    rng = np.random.default_rng(7)
+    x = _random_tet(rng)
+    for terms in (2, 4) if not solid else (2,):
+        Ke, V = synth.element(x, synth.default_params(terms=terms), solid)
+        vel = np.array([4 * a + i for a in range(4) for i in range(3)])
+        for m in _rigid(x):
+            assert np.abs(Ke @ m).max() <= 1e-10 * np.abs(Ke).max()
+        Av = Ke[np.ix_(vel, vel)]
+        assert np.allclose(Av, Av.T, atol=1e-12 * np.abs(Av).max())
+    # grad-div is rank one (outer product of the divergence row)
+    Ke, _ = synth.element(x, synth.default_params(terms=4), False)
+    sv = np.linalg.svd(Ke, compute_uv=False)
+    assert sv[1] <= 1e-12 * sv[0]
+
+
+def test_element_G_D_C_structure():
+    rng = np.random.default_rng(11)
+    x = _random_tet(rng)
+    p = synth.default_params()
+    for solid in (False, True):
+        Ke, V = synth.element(x, p, solid)
+        vel = [4 * a + i for a in range(4) for i in range(3)]
+        pre = [4 * a + 3 for a in range(4)]
+        G = Ke[np.ix_(vel, pre)]
+        D = Ke[np.ix_(pre, vel)]
+        assert np.array_equal(D, -G.T)                       # D = -G^T exactly
+        assert np.abs(G.reshape(4, 3, 4).sum(0)).max() < 1e-14  # sum_a dN_a = 0
+        Cb = Ke[np.ix_(pre, pre)]
+        assert np.allclose(Cb, Cb.T) and np.linalg.eigvalsh(Cb).min() > -1e-14 * np.abs(Cb).max()
+        if solid:
+            am, af, g = synth.genalpha(p.rho_inf)
+            ct = am / (af * g * p.dt)
+            kappa = p.E_s / (3 * (1 - 2 * p.nu_s))
+            assert Cb.sum() == pytest.approx(ct / kappa * V, rel=1e-13)   # (c_t/kappa) * mass
+
+
+def _pattern_bruteforce(s):
+    pairs = set()
+    for e in range(s.n_tets):
+        va, pa = s.tv[e], s.tp[e]
+        for a in range(4):
+            for b in range(4):
+                pairs.update({(va[a], va[b]), (va[a], pa[b]), (pa[a], va[b]), (pa[a], pa[b])})
+    pairs.update((i, i) for i in range(s.n_b))
+    return pairs
+
+
+def test_K_pattern_matches_element_connectivity(tiny):
+    got = {(i, int(c)) for i in range(tiny.n_b) for c in tiny.ci[tiny.rp[i]:tiny.rp[i + 1]]}
+    assert got == _pattern_bruteforce(tiny)
+    assert all(np.all(np.diff(tiny.ci[tiny.rp[i]:tiny.rp[i + 1]]) > 0) for i in range(tiny.n_b))
+
+
+def test_cfg0_counts(cfg0):
+    assert cfg0.n_phys == 13 * 13 * 41 == cfg0.n_b
+    assert cfg0.n_tets == 6 * 12 * 12 * 40
+    assert cfg0.nnzb == 94321
+    dirichlet_nodes = int((cfg0.mask.reshape(-1, 4)[:, 0] > 0).sum())
+    assert dirichlet_nodes == 48 * 41 + 11 * 11     # wall shell (48 nodes x 41 layers) + inlet interior
+    assert not cfg0.mask.reshape(-1, 4)[:, 3].any()  # no pressure Dirichlet
+    assert np.all(cfg0.kind == 0)
+
+
+def test_block_structure_and_dirichlet(small_fsi):
+    s = small_fsi
+    nb = s.n_b
+    Kd = bsr_to_dense(s.rp, s.ci, s.val)
+    vel = np.array([4 * i + c for i in range(nb) for c in range(3)])
+    pre = np.arange(nb) * 4 + 3
+    A = Kd[np.ix_(vel, vel)]; G = Kd[np.ix_(vel, pre)]; D = Kd[np.ix_(pre, vel)]; Cb = Kd[np.ix_(pre, pre)]
+    assert np.allclose(A, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+    assert np.array_equal(D, -G.T)
+    assert np.allclose(Cb, Cb.T, atol=1e-14 * np.abs(Cb).max())
+    # Dirichlet dofs: identity row and zero column
+    dd = np.where(s.mask)[0]
+    for d in dd[:200]:
+        row = Kd[d].copy(); col = Kd[:, d].copy()
+        assert row[d] == 1.0 and col[d] == 1.0
+        row[d] = 0; col[d] = 0
+        assert not row.any() and not col.any()
+    # interface duplication: one virtual block row per interface node, velocity slots Dirichlet
+    virt = np.where(s.kind == 3)[0]
+    assert virt.size == s.n_iface == np.sum(s.kind == 2)
+    assert np.all(virt - 1 == np.where(s.kind == 2)[0])      # virtual row right after its node
+    assert np.all(s.mask.reshape(-1, 4)[virt, :3] == 1)
+    # solid elements use the virtual node's pressure, fluid elements the physical one
+    virt_set = set(virt.tolist())
+    for e in range(s.n_tets):
+        uses_virtual = any(int(q) in virt_set for q in s.tp[e])
+        if uses_virtual:
+            assert s.tsolid[e] == 1
+        if not s.tsolid[e]:
+            assert np.array_equal(s.tp[e], s.tv[e])
+    # the Schur-like pressure operator C + G^T diag(A)^-1 G is SPD (A SPD)
+    free = np.where(s.mask.reshape(-1, 4)[:, :3].reshape(-1) == 0)[0]
+    assert np.linalg.eigvalsh(A[np.ix_(free, free)]).min() > 0
+
+
+def test_positive_volumes_and_conformity(small_fsi):
+    s = small_fsi
+    x = s.xyz
+    vols = []
+    for e in range(s.n_tets):
+        v = x[s.tv[e]]
+        vols.append(np.linalg.det(v[1:] - v[0]) / 6)
+    vols = np.array(vols)
+    assert vols.min() > 0
+    # faces are shared by at most two tets (conforming triangulation)
+    faces = {}
+    for e in range(s.n_tets):
+        for f in itertools.combinations(sorted(s.tv[e].tolist()), 3):
+            faces[f] = faces.get(f, 0) + 1
+    assert max(faces.values()) == 2
+
+
+def test_rhs_determinism_and_range():
+    mask = np.zeros(1000, np.uint8); mask[::7] = 1
+    a = synth.rhs(5, 1000, mask); b = synth.rhs(5, 1000, mask); c = synth.rhs(6, 1000, mask)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert np.all(a[mask == 1] == 0) and a.min() >= -1 and a.max() < 1
+    assert abs(a[mask == 0].mean()) < 0.1
