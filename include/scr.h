@@ -1,0 +1,185 @@
+/*
+ * scr.h -- C ABI of the MI355X SCR+AMG linear-solve library (libscr.so).
+ *
+ * The library solves the two linear systems of every Newton corrector of the fully implicit
+ * unified-continuum FSI method (Liu, Huang, Lu & Sun, arXiv 2206.06996):
+ *
+ *   (1) the 2x2 velocity/pressure block system  [A G; D C] [dv; dp] = b   (Sec. 3.5, the
+ *       corrector linear system; the paper writes the blocks [A B; C D]), by flexible GMRES
+ *       preconditioned with the Schur-complement-reduction preconditioner of Sec. 5.2.1 and
+ *       Appendix B (Algorithm 1), whose Schur action is the matrix-free Algorithm 2.  GMRES
+ *       on A is preconditioned by smoothed-aggregation AMG built on A; GMRES on the Schur
+ *       complement by AMG built on the sparse approximation S^ = C - D diag(A)^-1 G
+ *       (Sec. 5.2.1);
+ *   (2) the mesh-motion system (harmonic extension, Sec. 2.2.2; solver of Sec. 5.2.2): CG
+ *       preconditioned by AMG on a fixed Laplacian, three right-hand sides (x, y, z).
+ *
+ * Conventions (every function):
+ *   - Pointers are DEVICE pointers (memory of the context's GPU) unless marked "host".
+ *   - Inputs are borrowed for the duration of the call only; amg_setup copies what it keeps.
+ *   - Calls enqueue work on `stream` (a hipStream_t passed as void*; NULL = the null stream)
+ *     and return after that work has completed: Krylov control runs on the host.  Distinct
+ *     handles may be used concurrently from different host threads on different streams.
+ *     One handle must not be used by two threads at once.
+ *   - No exception crosses the ABI.  Errors return a negative scr_status; scr_last_error()
+ *     gives a message for the calling thread.  On error nothing is leaked.
+ *   - Index arrays are 0-based int32; block values are row-major within a block; columns are
+ *     strictly ascending within each block row; every block row stores its diagonal block.
+ */
+#ifndef SCR_H
+#define SCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCR_OK = 0,
+    SCR_NOT_CONVERGED = 1,     /* warning: x holds the last iterate, stats are filled */
+    SCR_E_INVALID = -1,        /* malformed input (message in scr_last_error) */
+    SCR_E_OOM = -2,            /* device allocation failed or the context budget is exceeded */
+    SCR_E_HIP = -3,            /* HIP runtime error */
+    SCR_E_BREAKDOWN = -4,      /* NaN/Inf in a Krylov recurrence */
+    SCR_E_UNIMPLEMENTED = -5,
+    SCR_E_NO_DEVICE = -6
+} scr_status;
+
+typedef enum { SCR_SYSTEM = 0, MESH_SYSTEM = 1 } scr_kind;
+typedef enum { SCR_FP64 = 0, SCR_MIXED = 1 } scr_precision;
+typedef enum { SCR_SMOOTH_JACOBI = 0, SCR_SMOOTH_CHEBYSHEV = 1 } scr_smoother;
+
+/* A square block-sparse matrix.  SCR_SYSTEM: bs = 4, block (i,j) = [[A_ij G_ij],[D_ij C_ij]]
+ * with node-interleaved unknowns [vx vy vz p] (Sec. 3.5, corrector system; interface nodes
+ * carry a duplicated pressure row as in Sec. 3.3, its velocity slots as identity rows).
+ * MESH_SYSTEM: bs = 1, the scalar mesh Laplacian (the same operator acts on x, y and z). */
+typedef struct {
+    int32_t n_brows;
+    int32_t bs;
+    int64_t nnzb;
+    const int32_t* row_ptr;    /* device, n_brows + 1 */
+    const int32_t* col_idx;    /* device, nnzb */
+    const double* val;         /* device, nnzb * bs * bs */
+} scr_bsr;
+
+/* Smoothed-aggregation AMG options (the paper uses BoomerAMG, Sec. 5.2 table of settings;
+ * these are the SA replacements).  Defaults from scr_default_amg_opts. */
+typedef struct {
+    int precision;             /* SCR_FP64: hierarchy and V-cycle in FP64; SCR_MIXED: FP32 */
+    double theta;              /* strength threshold at level 0 (halved per level), 0.08 */
+    int smoother;              /* scr_smoother, default Chebyshev */
+    int cheb_degree;           /* 2 */
+    double cheb_ratio;         /* lower end of the Chebyshev interval = lambda_hat / ratio, 30 */
+    int jacobi_sweeps;         /* 2 */
+    int coarse_max;            /* direct solve once a level has <= coarse_max unknowns, 1024 */
+    int max_levels;            /* 10 */
+    double max_coarse_ratio;   /* stop coarsening when n_{l+1} > ratio * n_l, 0.8 */
+    uint64_t seed;             /* seed of the MIS-2 priorities, 0 */
+} scr_amg_opts;
+
+/* Krylov options.  Defaults: tol 1e-8 (outer), tol_A = tol_S = tol_I = 1e-3 and 200
+ * iterations at every level (the paper's solver-settings table, Sec. 6), restart 50 for the
+ * outer FGMRES and 30 for the inner GMRES levels; the mesh solve uses tol and max_it. */
+typedef struct {
+    double tol, tol_A, tol_S, tol_I;
+    int max_it, max_it_A, max_it_S, max_it_I;
+    int restart, restart_inner;
+    int use_x0;                /* 1: x holds the initial guess on entry */
+    int flexible_cg;           /* mesh solve: 1 = flexible CG (Notay), 0 = PCG; MIXED forces 1 */
+} scr_solve_opts;
+
+typedef struct {
+    int outer_it;              /* outer FGMRES iterations (or max mesh CG iterations) */
+    int converged;
+    double rel_res_true;       /* ||b - K x|| / ||b|| recomputed at exit (FP64) */
+    int64_t calls_A, its_A;    /* Algorithm 1 steps 1 and 5 */
+    int64_t calls_S, its_S;    /* Algorithm 1 step 3 */
+    int64_t calls_I, its_I;    /* Algorithm 2 step 2 */
+    int64_t vcycles_A, vcycles_S, vcycles_L;
+    int64_t mesh_its[3];
+    double mesh_rel[3];
+    double t_setup_ms, t_solve_ms;
+    int64_t device_bytes;      /* device memory held by the handle */
+} scr_stats;
+
+typedef struct scr_ctx scr_ctx;
+typedef struct scr_handle scr_handle;
+
+void scr_default_amg_opts(scr_amg_opts* o);        /* o: host */
+void scr_default_solve_opts(scr_solve_opts* o);    /* o: host */
+
+/* A context binds a device and an optional device-memory budget (bytes, 0 = unlimited) that
+ * every handle created from it counts against.  Thread-safe. */
+scr_status scr_ctx_create(int device, int64_t hbm_budget, scr_ctx** out /* host */);
+void scr_ctx_destroy(scr_ctx* ctx);
+int64_t scr_ctx_bytes_in_use(const scr_ctx* ctx);
+
+/* Validate K and build everything the solves need (Sec. 5.2.1 for SCR_SYSTEM, Sec. 5.2.2 for
+ * MESH_SYSTEM): for SCR_SYSTEM the block split A, G, D, C, the sparse Schur approximation S^,
+ * AMG(A) with the six rigid-body modes of `coords` as near-null space, AMG(S^) with the
+ * constant, and the Krylov workspaces; for MESH_SYSTEM AMG(L) with the constant.
+ * coords: device, n_brows x 3 FP64 (node coordinates; required for SCR_SYSTEM, ignored for
+ * MESH_SYSTEM).  K is copied.  Errors: SCR_E_INVALID for a malformed K (unsorted or
+ * out-of-range columns, missing or zero diagonal, non-finite values, bs not 4/1 for the
+ * kind), SCR_E_OOM, SCR_E_HIP. */
+scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coords,
+                     const scr_amg_opts* opts /* host, NULL = defaults */, void* stream,
+                     scr_handle** out /* host */);
+
+/* Solve K x = b (SCR_SYSTEM handle) by FGMRES(P_SCR) to ||b - K x|| <= tol ||b|| (true FP64
+ * residual, checked at exit).  b, x: device, 4 * n_brows FP64, node-interleaved [vx vy vz p].
+ * x is the initial guess if use_x0, else it is overwritten.  Returns SCR_OK, or
+ * SCR_NOT_CONVERGED with x = last iterate; stats (host, may be NULL) are filled either way. */
+scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts /* host */,
+                     void* stream, scr_stats* stats /* host */);
+
+/* Solve L X = B (MESH_SYSTEM handle) for three right-hand sides by CG + AMG(L), each column to
+ * ||B_c - L X_c|| <= tol ||B_c||.  b, x: device, n_brows x 3 FP64 interleaved [ux uy uz]. */
+scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts /* host */,
+                             void* stream, scr_stats* stats /* host */);
+
+scr_status scr_handle_destroy(scr_handle* h);
+int64_t scr_handle_bytes(const scr_handle* h);
+
+/* Upper bound of the device memory a handle of this size will hold (host-side model, used
+ * for admission control). */
+int64_t scr_footprint_estimate(int kind, int64_t n_brows, int64_t nnzb, const scr_amg_opts* amg,
+                               const scr_solve_opts* solve);
+
+const char* scr_status_str(scr_status s);
+const char* scr_last_error(void);
+
+/* ---------------------------------------------------------------- inspection / components
+ * Hierarchies: which = 0 AMG(A), 1 AMG(S^), 2 AMG(L).  Fields of a level (copied to host):
+ *   0 A.row_ptr (int32, nr+1)   1 A.col_idx (int32, nnzb)   2 A.val (FP64, nnzb*b*b)
+ *   3 aggregate of each block row (int32, nr; -1 = isolated)
+ *   4 P.row_ptr  5 P.col_idx  6 P.val (FP64, b x k blocks)
+ *   7 R.row_ptr  8 R.col_idx  9 R.val (FP64, k x b blocks)
+ *   10 strong flag per stored block of A (uint8)   11 dead coarse dof flags (uint8, nagg*k)
+ *   12 D^-1 blocks (FP64, nr*b*b)   13 near-null space B (FP64, nr*b x k)
+ * info = [nr, b, k, nnzb(A), nagg, nnzb(P), nnzb(R), n_coarsest]; lam = lambda_hat. */
+scr_status scr_hier_levels(scr_handle* h, int which, int* nlev /* host */);
+scr_status scr_hier_level_info(scr_handle* h, int which, int level, int64_t* info /* host, 8 */,
+                               double* lam /* host */);
+scr_status scr_hier_level_copy(scr_handle* h, int which, int level, int field, void* dst /* host */);
+
+/* Split matrices of an SCR handle: which 0 A, 1 G, 2 D, 3 C, 4 S^; field 0 row_ptr, 1 col_idx,
+ * 2 values (FP64); info (host, 4) = [nr, nnzb, br, bc] is always filled. */
+scr_status scr_matrix_copy(scr_handle* h, int which, int field, void* dst /* host, may be NULL */,
+                           int64_t* info /* host */);
+
+/* Component operators on split vectors (velocity part 3n node-interleaved, then pressure n):
+ *   0 y = K x (4n -> 4n)          1 y = A x (3n)              2 y = V-cycle of AMG(A) (3n)
+ *   3 y = V-cycle of AMG(S^) (n)  4 y = S x by Algorithm 2 (n) 5 y = P_SCR^-1 x, Algorithm 1 (4n)
+ *   6 y = G x (n -> 3n)           7 y = D x (3n -> n)          8 y = C x (n)
+ *   9 y = S^ x (n)               10 y = L x (mesh handle, n)  11 y = V-cycle of AMG(L) (n)
+ * x, y: device FP64. */
+scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const scr_solve_opts* opts,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

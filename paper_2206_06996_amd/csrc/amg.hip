@@ -1,0 +1,1001 @@
+// amg.hip -- smoothed-aggregation AMG setup on the GPU and the V-cycle.
+//
+// Per level: strength graph (squared Frobenius block norms f_ij, strong iff
+// f_ij^2 >= theta^4 f_ii f_jj, symmetrised by OR) -> distance-2 maximal independent set by
+// synchronous rounds over seeded priorities (equal to the sequential greedy set in descending
+// priority order) -> aggregates -> tentative prolongator by Gram-Schmidt of the near-null space
+// on each aggregate -> P = (I - omega D^-1 A) P_tent, omega = 4/(3 lambda_hat) -> R = P^T ->
+// A_c = R (A P), all products on structural patterns -> dense inverse of the coarsest level.
+// The paper (Sec. 5.2) preconditions with BoomerAMG; smoothed aggregation replaces it here.
+//
+// Built with -ffp-contract=off: the strength predicate and the Gram-Schmidt decisions are
+// evaluated as written, without fused multiply-adds.
+#include <algorithm>
+#include <cmath>
+
+#include "solver.h"
+
+namespace scr {
+
+// ====================================================================== helpers
+__device__ __forceinline__ int32_t find_col(const int32_t* __restrict__ ci, int32_t lo, int32_t hi, int32_t c) {
+    int32_t e = hi;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (ci[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    return (lo < e && ci[lo] == c) ? lo : -1;
+}
+
+__device__ __forceinline__ uint64_t sm64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+// priority of node i at a level: 30 bits of splitmix64(seed, level, i) above the index
+__device__ __forceinline__ uint64_t mis_key(uint64_t seed, int level, int64_t i) {
+    uint64_t h = sm64(seed ^ ((uint64_t)level << 56) ^ ((uint64_t)i * 0xD1B54A32D192ED03ULL));
+    return ((h >> 34) << 32) | (uint64_t)(uint32_t)i;
+}
+
+static DBsr bsr_alloc(int64_t nr, int64_t nc, int br, int bc, int64_t nnzb, Arena& ar) {
+    DBsr M;
+    M.nr = nr; M.nc = nc; M.br = br; M.bc = bc; M.nnzb = nnzb;
+    M.rp = ar.make<int32_t>(nr + 1);
+    M.ci = ar.make<int32_t>(nnzb > 0 ? nnzb : 1);
+    M.v = ar.make<double>((nnzb > 0 ? nnzb : 1) * br * bc);
+    return M;
+}
+static void bsr_release(DBsr& M, Arena& ar) {
+    ar.free(M.rp); ar.free(M.ci); ar.free(M.v);
+    M = DBsr();
+}
+
+// ====================================================================== block split and S^
+__global__ void split_k(int64_t nnzb, const double* __restrict__ K, double* __restrict__ A, double* __restrict__ G,
+                        double* __restrict__ D, double* __restrict__ C) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnzb) return;
+    const double* k = K + q * 16;
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) A[q * 9 + 3 * i + j] = k[4 * i + j];
+        G[q * 3 + i] = k[4 * i + 3];
+        D[q * 3 + i] = k[12 + i];
+    }
+    C[q] = k[15];
+}
+
+void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, hipStream_t s) {
+    auto mk = [&](DBsr& M, int br, int bc) {
+        M.nr = K.nr; M.nc = K.nc; M.br = br; M.bc = bc; M.nnzb = K.nnzb;
+        M.rp = K.rp; M.ci = K.ci;          // index arrays shared with K
+        M.v = ar.make<double>(K.nnzb * br * bc);
+    };
+    mk(A, 3, 3); mk(G, 3, 1); mk(D, 1, 3); mk(C, 1, 1);
+    if (K.nnzb > 0) split_k<<<cdiv(K.nnzb, 256), 256, 0, s>>>(K.nnzb, K.v, A.v, G.v, D.v, C.v);
+    check_launch("split");
+}
+
+// ====================================================================== generic SpGEMM (one wave per row)
+constexpr int HS = 8192;           // LDS hash slots per row
+constexpr int HMAX = HS / 2;       // unique columns allowed per row
+
+__device__ __forceinline__ void hash_clear(int* t) {
+    for (int i = threadIdx.x; i < HS; i += WAVE) t[i] = -1;
+}
+// returns 1 if newly inserted
+__device__ __forceinline__ int hash_insert(int* t, int key) {
+    unsigned h = ((unsigned)key * 2654435761u) & (HS - 1);
+    for (;;) {
+        int prev = atomicCAS(&t[h], -1, key);
+        if (prev == -1) return 1;
+        if (prev == key) return 0;
+        h = (h + 1) & (HS - 1);
+    }
+}
+
+// count (phase 0) or emit sorted (phase 1) the structural pattern of row i of X*Y
+template <int PHASE>
+__global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci,
+                                                     const int32_t* __restrict__ yrp, const int32_t* __restrict__ yci,
+                                                     const uint8_t* __restrict__ rowmask, int32_t* __restrict__ cnt,
+                                                     const int32_t* __restrict__ crp, int32_t* __restrict__ cci,
+                                                     int* __restrict__ overflow) {
+    __shared__ int table[HS];
+    __shared__ int nuniq;
+    __shared__ int list[HMAX + WAVE];
+    int64_t i = blockIdx.x;
+    if (i >= nr) return;
+    int lane = threadIdx.x;
+    if (rowmask && !rowmask[i]) {
+        if (PHASE == 0 && lane == 0) cnt[i] = 0;
+        return;
+    }
+    hash_clear(table);
+    if (lane == 0) nuniq = 0;
+    __syncthreads();
+    for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) {
+        int32_t k = xci[q];
+        for (int32_t t = yrp[k] + lane; t < yrp[k + 1]; t += WAVE) {
+            if (nuniq >= HMAX) break;
+            int c = yci[t];
+            if (hash_insert(table, c)) {
+                int pos = atomicAdd(&nuniq, 1);
+                if (pos < HMAX + WAVE) list[pos] = c;
+            }
+        }
+        __syncthreads();
+    }
+    int w = nuniq;
+    if (w >= HMAX) {
+        if (lane == 0) atomicOr(overflow, 1);
+        return;
+    }
+    if (PHASE == 0) {
+        if (lane == 0) cnt[i] = w;
+        return;
+    }
+    // rank sort of the unique columns
+    int32_t base = crp[i];
+    for (int a = lane; a < w; a += WAVE) {
+        int key = list[a], rank = 0;
+        for (int b = 0; b < w; ++b) rank += list[b] < key;
+        cci[base + rank] = key;
+    }
+}
+
+// numeric phase: lane owns output blocks; accumulates X_iq * Y_kc over q in ascending order
+template <int M, int N, int P>
+__global__ void __launch_bounds__(256) spg_numeric(int64_t nr, const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci,
+                                                   const double* __restrict__ xv, const int32_t* __restrict__ yrp,
+                                                   const int32_t* __restrict__ yci, const double* __restrict__ yv,
+                                                   const int32_t* __restrict__ crp, const int32_t* __restrict__ cci,
+                                                   double* __restrict__ cv) {
+    int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (i >= nr) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    for (int32_t p = crp[i] + lane; p < crp[i + 1]; p += WAVE) {
+        int32_t c = cci[p];
+        double acc[M * P];
+        for (int e = 0; e < M * P; ++e) acc[e] = 0.0;
+        for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) {
+            int32_t k = xci[q];
+            int32_t t = find_col(yci, yrp[k], yrp[k + 1], c);
+            if (t < 0) continue;
+            const double* xb = xv + (int64_t)q * M * N;
+            const double* yb = yv + (int64_t)t * N * P;
+            for (int r = 0; r < M; ++r)
+                for (int cc = 0; cc < P; ++cc) {
+                    double sum = 0.0;
+                    for (int l = 0; l < N; ++l) sum += xb[r * N + l] * yb[l * P + cc];
+                    acc[r * P + cc] += sum;
+                }
+        }
+        double* o = cv + (int64_t)p * M * P;
+        for (int e = 0; e < M * P; ++e) o[e] = acc[e];
+    }
+}
+
+static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hipStream_t s) {
+    DBsr C;
+    C.nr = X.nr; C.nc = Y.nc; C.br = X.br; C.bc = Y.bc;
+    C.rp = ar.make<int32_t>(X.nr + 1);
+    int32_t* cnt = ar.make<int32_t>(X.nr + 1);
+    int* ovf = ar.make<int>(1);
+    HIPCHK(hipMemsetAsync(ovf, 0, sizeof(int), s));
+    if (X.nr > 0)
+        spg_symbolic<0><<<X.nr, WAVE, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr, ovf);
+    check_launch("spg_count");
+    C.nnzb = scan_i32(cnt, C.rp, X.nr, ar, s);
+    int hovf = 0;
+    HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hovf) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
+    ar.free(cnt);
+    C.ci = ar.make<int32_t>(C.nnzb > 0 ? C.nnzb : 1);
+    C.v = ar.make<double>((C.nnzb > 0 ? C.nnzb : 1) * C.br * C.bc);
+    if (X.nr > 0)
+        spg_symbolic<1><<<X.nr, WAVE, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, ovf);
+    check_launch("spg_fill");
+    ar.free(ovf);
+    int64_t nb = cdiv(X.nr, 4);
+    int key = X.br * 100 + X.bc * 10 + Y.bc;
+#define SPN(m, n, p) spg_numeric<m, n, p><<<nb, 256, 0, s>>>(X.nr, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v)
+    if (nb > 0) {
+        switch (key) {
+            case 111: SPN(1, 1, 1); break;
+            case 131: SPN(1, 3, 1); break;
+            case 336: SPN(3, 3, 6); break;
+            case 636: SPN(6, 3, 6); break;
+            case 666: SPN(6, 6, 6); break;
+            default: throw Error(SCR_E_UNIMPLEMENTED, "spgemm block shape " + std::to_string(key));
+        }
+    }
+#undef SPN
+    check_launch("spg_numeric");
+    return C;
+}
+
+// ---------------------------------------------------------------------- S^ = C - D diag(A)^-1 G
+__global__ void diag_scale_D(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const double* __restrict__ Av, const double* __restrict__ Dv, double* __restrict__ X) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        int32_t j = ci[q];
+        int32_t dq = find_col(ci, rp[j], rp[j + 1], j);
+        for (int c = 0; c < 3; ++c) X[(int64_t)q * 3 + c] = Dv[(int64_t)q * 3 + c] / Av[(int64_t)dq * 9 + 4 * c];
+    }
+}
+// union pattern of C and DG (both sorted): count, then fill with C - DG
+template <int PHASE>
+__global__ void merge_sub_k(int64_t nr, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                            const double* __restrict__ av, const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
+                            const double* __restrict__ bv, int32_t* __restrict__ cnt, const int32_t* __restrict__ crp,
+                            int32_t* __restrict__ cci, double* __restrict__ cv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int32_t a = arp[i], ae = arp[i + 1], b = brp[i], be = brp[i + 1];
+    int32_t o = PHASE ? crp[i] : 0;
+    int32_t n = 0;
+    while (a < ae || b < be) {
+        int32_t ca = a < ae ? aci[a] : INT32_MAX, cb = b < be ? bci[b] : INT32_MAX;
+        if (PHASE) {
+            if (ca == cb) { cci[o + n] = ca; cv[o + n] = av[a] - bv[b]; }
+            else if (ca < cb) { cci[o + n] = ca; cv[o + n] = av[a]; }
+            else { cci[o + n] = cb; cv[o + n] = -bv[b]; }
+        }
+        if (ca <= cb) ++a;
+        if (cb <= ca) ++b;
+        ++n;
+    }
+    if (!PHASE) cnt[i] = n;
+}
+
+DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, Arena& ar, hipStream_t s) {
+    DBsr X = D;
+    X.v = ar.make<double>(D.nnzb * 3);
+    if (D.nr > 0) diag_scale_D<<<cdiv(D.nr, 256), 256, 0, s>>>(D.nr, D.rp, D.ci, A.v, D.v, X.v);
+    check_launch("diag_scale_D");
+    DBsr DG = spgemm(X, G, nullptr, ar, s);
+    ar.free(X.v);
+    DBsr S;
+    S.nr = C.nr; S.nc = C.nc; S.br = 1; S.bc = 1;
+    S.rp = ar.make<int32_t>(C.nr + 1);
+    int32_t* cnt = ar.make<int32_t>(C.nr + 1);
+    int64_t nb = cdiv(C.nr, 256);
+    if (nb) merge_sub_k<0><<<nb, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, cnt, nullptr, nullptr, nullptr);
+    S.nnzb = scan_i32(cnt, S.rp, C.nr, ar, s);
+    ar.free(cnt);
+    S.ci = ar.make<int32_t>(S.nnzb);
+    S.v = ar.make<double>(S.nnzb);
+    if (nb) merge_sub_k<1><<<nb, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, nullptr, S.rp, S.ci, S.v);
+    check_launch("merge_sub");
+    bsr_release(DG, ar);
+    return S;
+}
+
+// ---------------------------------------------------------------------- rigid-body modes
+__global__ void centroid_partial(int64_t nb, const double* __restrict__ xyz, double* __restrict__ part) {
+    __shared__ double red[3][256];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nb; i += (int64_t)gridDim.x * 256)
+        for (int d = 0; d < 3; ++d) a[d] += xyz[3 * i + d];
+    for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = a[d];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int d = 0; d < 3; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) part[blockIdx.x * 3 + d] = red[d][0];
+}
+__global__ void rigid_k(int64_t nb, const double* __restrict__ xyz, const double* __restrict__ part, int np,
+                        double* __restrict__ B) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int p = 0; p < np; ++p)
+        for (int d = 0; d < 3; ++d) c[d] += part[p * 3 + d];
+    double x = xyz[3 * i] - c[0] / (double)nb, y = xyz[3 * i + 1] - c[1] / (double)nb, z = xyz[3 * i + 2] - c[2] / (double)nb;
+    double* r0 = B + (3 * i) * 6;
+    double* r1 = r0 + 6;
+    double* r2 = r1 + 6;
+    for (int t = 0; t < 6; ++t) { r0[t] = 0.0; r1[t] = 0.0; r2[t] = 0.0; }
+    r0[0] = 1.0; r1[1] = 1.0; r2[2] = 1.0;
+    r0[3] = -y; r1[3] = x;
+    r1[4] = -z; r2[4] = y;
+    r0[5] = z; r2[5] = -x;
+}
+void rigid_modes(int64_t nb, const double* xyz, double* B, Arena& ar, hipStream_t s) {
+    int np = 64;
+    double* part = ar.make<double>(np * 3);
+    centroid_partial<<<np, 256, 0, s>>>(nb, xyz, part);
+    if (nb > 0) rigid_k<<<cdiv(nb, 256), 256, 0, s>>>(nb, xyz, part, np, B);
+    check_launch("rigid_modes");
+    ar.free(part);
+}
+
+// ====================================================================== strength and MIS-2
+__device__ __forceinline__ double block_f(const double* __restrict__ v, int bb) {
+    double f = 0.0;
+    for (int e = 0; e < bb; ++e) f = f + v[e] * v[e];
+    return f;
+}
+__global__ void fdiag_k(int64_t nr, int bb, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                        const double* __restrict__ v, double* __restrict__ fd) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int32_t q = find_col(ci, rp[i], rp[i + 1], (int32_t)i);
+    fd[i] = q >= 0 ? block_f(v + (int64_t)q * bb, bb) : 0.0;
+}
+__global__ void strength_k(int64_t nr, int bb, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ v, const double* __restrict__ fd, double th4,
+                           uint8_t* __restrict__ flags, uint8_t* __restrict__ iso) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    uint8_t any = 0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        int32_t j = ci[q];
+        uint8_t f = 0;
+        if (j != i) {
+            double fij = block_f(v + (int64_t)q * bb, bb);
+            bool s1 = (fij * fij) >= ((th4 * fd[i]) * fd[j]);
+            bool s2 = false;
+            int32_t t = find_col(ci, rp[j], rp[j + 1], (int32_t)i);
+            if (t >= 0) {
+                double fji = block_f(v + (int64_t)t * bb, bb);
+                s2 = (fji * fji) >= ((th4 * fd[j]) * fd[i]);
+            }
+            f = (s1 || s2) ? 1 : 0;
+        }
+        flags[q] = f;
+        any |= f;
+    }
+    iso[i] = any ? 0 : 1;
+}
+
+// state word: top 2 bits = 0 out/isolated, 1 undecided, 2 in; low 62 bits = priority
+constexpr uint64_t ST_UND = 1ULL << 62, ST_IN = 2ULL << 62, KEYMASK = (1ULL << 62) - 1;
+
+__global__ void mis_init_k(int64_t nr, const uint8_t* __restrict__ iso, uint64_t seed, int level, uint64_t* __restrict__ st) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    st[i] = iso[i] ? 0ULL : (ST_UND | mis_key(seed, level, i));
+}
+__global__ void mis_max_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const uint8_t* __restrict__ flags, const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    uint64_t m = in[i];
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+        if (flags[q]) {
+            uint64_t v = in[ci[q]];
+            m = v > m ? v : m;
+        }
+    out[i] = m;
+}
+__global__ void mis_decide_k(int64_t nr, uint64_t* __restrict__ st, const uint64_t* __restrict__ m2, int* __restrict__ und) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    uint64_t s = st[i];
+    if ((s >> 62) != 1) return;
+    uint64_t m = m2[i];
+    if ((m >> 62) == 2) st[i] = s & KEYMASK;               // an IN node within distance 2
+    else if (m == s) st[i] = ST_IN | (s & KEYMASK);        // largest undecided priority within distance 2
+    else atomicAdd(und, 1);
+}
+
+__global__ void root_flag_k(int64_t nr, const uint64_t* __restrict__ st, int32_t* __restrict__ isroot) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) isroot[i] = (st[i] >> 62) == 2 ? 1 : 0;
+}
+__global__ void agg_roots_k(int64_t nr, const uint64_t* __restrict__ st, const int32_t* __restrict__ rid,
+                            int32_t* __restrict__ agg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) agg[i] = (st[i] >> 62) == 2 ? rid[i] : -1;
+}
+__global__ void agg_dist1_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const uint8_t* __restrict__ flags, const uint8_t* __restrict__ iso, const uint64_t* __restrict__ st,
+                            const int32_t* __restrict__ rid, int32_t* __restrict__ agg, uint8_t* __restrict__ step1) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    step1[i] = 0;
+    if (iso[i] || (st[i] >> 62) == 2) return;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        int32_t j = ci[q];
+        if (flags[q] && (st[j] >> 62) == 2) {
+            agg[i] = rid[j];
+            step1[i] = 1;
+            return;
+        }
+    }
+}
+__global__ void agg_dist2_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const uint8_t* __restrict__ flags, const uint8_t* __restrict__ iso,
+                            const uint8_t* __restrict__ step1, uint64_t seed, int level, int32_t* __restrict__ agg,
+                            int* __restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    if (iso[i] || agg[i] >= 0) return;
+    uint64_t best = 0;
+    int32_t bj = -1;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        int32_t j = ci[q];
+        if (!flags[q] || !step1[j]) continue;
+        uint64_t kj = mis_key(seed, level, j);
+        if (bj < 0 || kj > best) { best = kj; bj = j; }
+    }
+    if (bj < 0) { atomicOr(err, 1); return; }
+    agg[i] = agg[bj];   // bj joined in the distance-1 step: its aggregate is final
+}
+
+// ====================================================================== tentative prolongator
+__global__ void agg_count_k(int64_t nr, const int32_t* __restrict__ agg, int32_t* __restrict__ cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr && agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
+}
+__global__ void agg_fill_k(int64_t nr, const int32_t* __restrict__ agg, const int32_t* __restrict__ mrp,
+                           int32_t* __restrict__ fillc, int32_t* __restrict__ mem) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr && agg[i] >= 0) mem[mrp[agg[i]] + atomicAdd(&fillc[agg[i]], 1)] = (int32_t)i;
+}
+__global__ void agg_sort_k(int64_t na, const int32_t* __restrict__ mrp, int32_t* __restrict__ mem) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    int32_t lo = mrp[a], hi = mrp[a + 1];
+    for (int32_t t = lo + 1; t < hi; ++t) {
+        int32_t v = mem[t], u = t - 1;
+        while (u >= lo && mem[u] > v) { mem[u + 1] = mem[u]; --u; }
+        mem[u + 1] = v;
+    }
+}
+
+// Gram-Schmidt (two modified-GS passes) of B restricted to the aggregate's rows (members in
+// ascending order, b rows each).  Column j is dead when its remainder is <= 1e-10 of its norm.
+__global__ void tentative_k(int64_t na, int b, int k, const int32_t* __restrict__ mrp, const int32_t* __restrict__ mem,
+                            const double* __restrict__ B, double* __restrict__ Q, double* __restrict__ Bc,
+                            uint8_t* __restrict__ dead) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    int32_t lo = mrp[a], hi = mrp[a + 1];
+    double* Rk = Bc + a * k * k;
+    for (int e = 0; e < k * k; ++e) Rk[e] = 0.0;
+    // Q rows of the members start as B rows
+    for (int32_t t = lo; t < hi; ++t) {
+        int64_t node = mem[t];
+        for (int r = 0; r < b; ++r)
+            for (int c = 0; c < k; ++c) Q[(node * b + r) * k + c] = B[(node * b + r) * k + c];
+    }
+    for (int j = 0; j < k; ++j) {
+        double nb = 0.0;
+        for (int32_t t = lo; t < hi; ++t)
+            for (int r = 0; r < b; ++r) {
+                double w = Q[((int64_t)mem[t] * b + r) * k + j];
+                nb += w * w;
+            }
+        nb = sqrt(nb);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < j; ++i) {
+                if (dead[a * k + i]) continue;
+                double c = 0.0;
+                for (int32_t t = lo; t < hi; ++t)
+                    for (int r = 0; r < b; ++r) {
+                        int64_t row = ((int64_t)mem[t] * b + r) * k;
+                        c += Q[row + i] * Q[row + j];
+                    }
+                for (int32_t t = lo; t < hi; ++t)
+                    for (int r = 0; r < b; ++r) {
+                        int64_t row = ((int64_t)mem[t] * b + r) * k;
+                        Q[row + j] -= c * Q[row + i];
+                    }
+                Rk[i * k + j] += c;
+            }
+        double nv = 0.0;
+        for (int32_t t = lo; t < hi; ++t)
+            for (int r = 0; r < b; ++r) {
+                double w = Q[((int64_t)mem[t] * b + r) * k + j];
+                nv += w * w;
+            }
+        nv = sqrt(nv);
+        bool isdead = (nb == 0.0) || (nv <= 1e-10 * nb);
+        dead[a * k + j] = isdead ? 1 : 0;
+        for (int32_t t = lo; t < hi; ++t)
+            for (int r = 0; r < b; ++r) {
+                int64_t row = ((int64_t)mem[t] * b + r) * k;
+                Q[row + j] = isdead ? 0.0 : Q[row + j] / nv;
+            }
+        Rk[j * k + j] = isdead ? 0.0 : nv;
+    }
+}
+
+// P_tent as BSR: one b x k block per aggregated row
+__global__ void ptent_cnt_k(int64_t nr, const int32_t* __restrict__ agg, int32_t* __restrict__ cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) cnt[i] = agg[i] >= 0 ? 1 : 0;
+}
+__global__ void ptent_fill_k(int64_t nr, int bk, const int32_t* __restrict__ agg, const int32_t* __restrict__ rp,
+                             const double* __restrict__ Q, int32_t* __restrict__ ci, double* __restrict__ v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr || agg[i] < 0) return;
+    int32_t q = rp[i];
+    ci[q] = agg[i];
+    for (int e = 0; e < bk; ++e) v[(int64_t)q * bk + e] = Q[i * bk + e];
+}
+
+// ====================================================================== D^-1 and lambda_hat
+template <int B>
+__device__ bool invert_small(const double* __restrict__ a, double* __restrict__ out) {
+    double m[B][2 * B];
+    for (int r = 0; r < B; ++r)
+        for (int c = 0; c < B; ++c) {
+            m[r][c] = a[r * B + c];
+            m[r][B + c] = r == c ? 1.0 : 0.0;
+        }
+    for (int k = 0; k < B; ++k) {
+        int p = k;
+        double best = fabs(m[k][k]);
+        for (int r = k + 1; r < B; ++r)
+            if (fabs(m[r][k]) > best) { best = fabs(m[r][k]); p = r; }
+        if (best == 0.0) return false;
+        if (p != k)
+            for (int c = 0; c < 2 * B; ++c) { double t = m[k][c]; m[k][c] = m[p][c]; m[p][c] = t; }
+        double piv = m[k][k];
+        for (int c = 0; c < 2 * B; ++c) m[k][c] /= piv;
+        for (int r = 0; r < B; ++r) {
+            if (r == k) continue;
+            double f = m[r][k];
+            for (int c = 0; c < 2 * B; ++c) m[r][c] -= f * m[k][c];
+        }
+    }
+    for (int r = 0; r < B; ++r)
+        for (int c = 0; c < B; ++c) out[r * B + c] = m[r][B + c];
+    return true;
+}
+
+template <int B>
+__global__ void dinv_lambda_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              const double* __restrict__ v, double* __restrict__ Dinv, unsigned long long* __restrict__ lam,
+                              int* __restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int32_t q = find_col(ci, rp[i], rp[i + 1], (int32_t)i);
+    double Di[B * B];
+    if (q < 0 || !invert_small<B>(v + (int64_t)q * B * B, Di)) {
+        atomicOr(err, 1);
+        return;
+    }
+    for (int e = 0; e < B * B; ++e) Dinv[i * B * B + e] = Di[e];
+    double rs[B];
+    for (int r = 0; r < B; ++r) rs[r] = 0.0;
+    for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
+        const double* blk = v + (int64_t)t * B * B;
+        for (int r = 0; r < B; ++r)
+            for (int c = 0; c < B; ++c) {
+                double sum = 0.0;
+                for (int l = 0; l < B; ++l) sum += Di[r * B + l] * blk[l * B + c];
+                rs[r] += fabs(sum);
+            }
+    }
+    double m = 0.0;
+    for (int r = 0; r < B; ++r) m = rs[r] > m ? rs[r] : m;
+    atomicMax(lam, (unsigned long long)__double_as_longlong(m));
+}
+
+// P = -omega D^-1 (A P_tent) + P_tent  (rows of AP_t are those of P)
+template <int B, int K>
+__global__ void smooth_p_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           double* __restrict__ v, const double* __restrict__ Dinv, const int32_t* __restrict__ agg,
+                           const double* __restrict__ Q, double omega) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr || agg[i] < 0) return;
+    const double* Di = Dinv + i * B * B;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        double* blk = v + (int64_t)q * B * K;
+        double t[B * K];
+        for (int r = 0; r < B; ++r)
+            for (int c = 0; c < K; ++c) {
+                double sum = 0.0;
+                for (int l = 0; l < B; ++l) sum += Di[r * B + l] * blk[l * K + c];
+                t[r * K + c] = -omega * sum;
+            }
+        if (ci[q] == agg[i])
+            for (int e = 0; e < B * K; ++e) t[e] += Q[i * B * K + e];
+        for (int e = 0; e < B * K; ++e) blk[e] = t[e];
+    }
+}
+
+// ====================================================================== transpose
+__global__ void tr_count_k(int64_t nnz, const int32_t* __restrict__ ci, int32_t* __restrict__ cnt) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) atomicAdd(&cnt[ci[q]], 1);
+}
+__global__ void tr_fill_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const int32_t* __restrict__ trp, int32_t* __restrict__ fillc, int32_t* __restrict__ tci,
+                          int32_t* __restrict__ src) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        int32_t c = ci[q];
+        int32_t pos = trp[c] + atomicAdd(&fillc[c], 1);
+        tci[pos] = (int32_t)i;
+        src[pos] = q;
+    }
+}
+// place each entry of a transposed row at its rank (source rows are unique within a row)
+__global__ void tr_rank_k(int64_t nnz, int64_t ntr, const int32_t* __restrict__ trp, const int32_t* __restrict__ tci,
+                          const int32_t* __restrict__ src, const double* __restrict__ v, int br, int bc,
+                          int32_t* __restrict__ oci, double* __restrict__ ov, const int32_t* __restrict__ rowof) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    int32_t r = rowof[p];
+    int32_t lo = trp[r], hi = trp[r + 1];
+    int32_t key = tci[p], rank = 0;
+    for (int32_t u = lo; u < hi; ++u) rank += tci[u] < key;
+    int64_t dst = lo + rank;
+    oci[dst] = key;
+    const double* s = v + (int64_t)src[p] * br * bc;
+    double* d = ov + dst * br * bc;
+    for (int r0 = 0; r0 < br; ++r0)
+        for (int c0 = 0; c0 < bc; ++c0) d[c0 * br + r0] = s[r0 * bc + c0];
+}
+__global__ void row_of_k(int64_t nr, const int32_t* __restrict__ rp, int32_t* __restrict__ rowof) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) rowof[q] = (int32_t)i;
+}
+
+static DBsr transpose(const DBsr& M, Arena& ar, hipStream_t s) {
+    DBsr T;
+    T.nr = M.nc; T.nc = M.nr; T.br = M.bc; T.bc = M.br; T.nnzb = M.nnzb;
+    int32_t* cnt = ar.make<int32_t>(M.nc + 1);
+    HIPCHK(hipMemsetAsync(cnt, 0, (M.nc + 1) * sizeof(int32_t), s));
+    if (M.nnzb) tr_count_k<<<cdiv(M.nnzb, 256), 256, 0, s>>>(M.nnzb, M.ci, cnt);
+    T.rp = ar.make<int32_t>(M.nc + 1);
+    scan_i32(cnt, T.rp, M.nc, ar, s);
+    HIPCHK(hipMemsetAsync(cnt, 0, (M.nc + 1) * sizeof(int32_t), s));
+    int32_t* tci = ar.make<int32_t>(M.nnzb + 1);
+    int32_t* src = ar.make<int32_t>(M.nnzb + 1);
+    if (M.nr) tr_fill_k<<<cdiv(M.nr, 256), 256, 0, s>>>(M.nr, M.rp, M.ci, T.rp, cnt, tci, src);
+    int32_t* rowof = ar.make<int32_t>(M.nnzb + 1);
+    if (T.nr) row_of_k<<<cdiv(T.nr, 256), 256, 0, s>>>(T.nr, T.rp, rowof);
+    T.ci = ar.make<int32_t>(M.nnzb + 1);
+    T.v = ar.make<double>((M.nnzb + 1) * M.br * M.bc);
+    if (M.nnzb)
+        tr_rank_k<<<cdiv(M.nnzb, 256), 256, 0, s>>>(M.nnzb, T.nr, T.rp, tci, src, M.v, M.br, M.bc, T.ci, T.v, rowof);
+    check_launch("transpose");
+    ar.free(cnt); ar.free(tci); ar.free(src); ar.free(rowof);
+    return T;
+}
+
+__global__ void dead_diag_k(int64_t na, int k, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            double* __restrict__ v, const uint8_t* __restrict__ dead) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= na) return;
+    int32_t q = find_col(ci, rp[a], rp[a + 1], (int32_t)a);
+    if (q < 0) return;
+    for (int c = 0; c < k; ++c)
+        if (dead[a * k + c]) v[(int64_t)q * k * k + c * k + c] = 1.0;
+}
+
+// ====================================================================== coarsest level: dense inverse
+__global__ void densify_k(int64_t nr, int b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ M, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+        for (int r = 0; r < b; ++r)
+            for (int c = 0; c < b; ++c) M[(i * b + r) * n + (int64_t)ci[q] * b + c] = v[((int64_t)q * b + r) * b + c];
+}
+// one Gauss-Jordan exchange step on pivot k (src -> dst); after all n steps dst = A^-1 (SPD A)
+__global__ void gj_step_k(int64_t n, int64_t k, const double* __restrict__ src, double* __restrict__ dst) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    int64_t i = idx / n, j = idx % n;
+    double p = src[k * n + k];
+    double out;
+    if (i == k) out = (j == k) ? 1.0 / p : src[k * n + j] / p;
+    else if (j == k) out = -src[i * n + k] / p;
+    else out = src[i * n + j] - src[i * n + k] * src[k * n + j] / p;
+    dst[idx] = out;
+}
+__global__ void finite_k(int64_t n, const double* __restrict__ a, int* __restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(a[i])) atomicOr(err, 1);
+}
+
+// ====================================================================== hierarchy with solve-phase data in T
+template <typename T>
+class HierT : public Hierarchy {
+   public:
+    struct LS {
+        DSell<T> A, P;
+        DBsrT<T> R;
+        T* Dinv = nullptr;
+        T *b = nullptr, *x = nullptr, *w = nullptr, *t1 = nullptr, *t2 = nullptr, *d = nullptr, *r = nullptr;
+        std::vector<double> c1, c2;    // smoothing-step coefficients
+        bool cheb = false;
+    };
+    std::vector<LS> S;
+    Arena* ar = nullptr;
+
+    void prepare(Arena& a, hipStream_t s) {
+        ar = &a;
+        S.resize(L.size());
+        for (size_t l = 0; l < L.size(); ++l) {
+            LevelSetup& ls = L[l];
+            LS& q = S[l];
+            int64_t n = ls.A.nr * ls.b;
+            q.b = a.make<T>(n); q.x = a.make<T>(n);
+            if (l + 1 == L.size()) continue;
+            q.A = sell_from_bsr<T>(ls.A, a, s);
+            q.P = sell_from_bsr<T>(ls.P, a, s);
+            q.R = bsrt_from_bsr<T>(ls.R, a, s);
+            int64_t bb = (int64_t)ls.A.nr * ls.b * ls.b;
+            q.Dinv = a.make<T>(bb);
+            if (std::is_same<T, double>::value) copy_d(bb, ls.Dinv, (double*)q.Dinv, s);
+            else cast_d2f(ls.Dinv, (float*)q.Dinv, bb, s);
+            q.w = a.make<T>(n); q.t1 = a.make<T>(n); q.t2 = a.make<T>(n); q.d = a.make<T>(n); q.r = a.make<T>(n);
+            // smoothing coefficients: step t computes dn = c1[t] d + c2[t] Dinv (b - A x)
+            if (opts.smoother == SCR_SMOOTH_CHEBYSHEV) {
+                q.cheb = true;
+                double lmax = ls.lam, lmin = ls.lam / opts.cheb_ratio;
+                double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+                double sigma = theta / delta, rho_prev = 1.0 / sigma;
+                q.c1.push_back(0.0); q.c2.push_back(1.0 / theta);
+                for (int t = 1; t < opts.cheb_degree; ++t) {
+                    double rho = 1.0 / (2.0 * sigma - rho_prev);
+                    q.c1.push_back(rho * rho_prev); q.c2.push_back(2.0 * rho / delta);
+                    rho_prev = rho;
+                }
+            } else {
+                double w = 4.0 / (3.0 * ls.lam);
+                for (int t = 0; t < opts.jacobi_sweeps; ++t) { q.c1.push_back(0.0); q.c2.push_back(w); }
+            }
+        }
+    }
+
+    // smoothing sweeps from xin (nullptr = zero) into dst
+    void smooth(LS& q, const T* b, const T* xin, T* dst, hipStream_t s) {
+        int ns = (int)q.c1.size();
+        const T* cur = xin;
+        for (int t = 0; t < ns; ++t) {
+            T* out = (t == ns - 1) ? dst : ((t % 2 == 0) ? q.t1 : q.t2);
+            smooth_step<T>(q.A, q.Dinv, b, cur, q.d, out, q.c1[t], q.c2[t], q.cheb && t > 0, q.cheb && t + 1 < ns,
+                           cur == nullptr, s);
+            cur = out;
+        }
+    }
+
+    void cycle(size_t l, const T* b, T* x, hipStream_t s) {
+        if (l + 1 == S.size()) {
+            dense_mv<T>(ncoarse, cinv, b, x, s);
+            return;
+        }
+        LS& q = S[l];
+        smooth(q, b, nullptr, q.w, s);
+        sell_mv<T>(q.A, q.w, b, q.r, 1, s);
+        bsrt_mv<T>(q.R, q.r, S[l + 1].b, s);
+        cycle(l + 1, S[l + 1].b, S[l + 1].x, s);
+        sell_mv<T>(q.P, S[l + 1].x, nullptr, q.w, 2, s);
+        smooth(q, b, q.w, x, s);
+    }
+
+    void vcycle(const double* x, double* y, hipStream_t s) override {
+        ++vcycles;
+        int64_t n = n0();
+        if (std::is_same<T, double>::value) {
+            cycle(0, (const T*)x, (T*)y, s);
+        } else {
+            cast_d2f(x, (float*)S[0].b, n, s);
+            cycle(0, S[0].b, S[0].x, s);
+            cast_f2d((const float*)S[0].x, y, n, s);
+        }
+    }
+};
+
+__global__ void rowmask_k(int64_t nr, const int32_t* __restrict__ agg, uint8_t* __restrict__ m) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) m[i] = agg[i] >= 0 ? 1 : 0;
+}
+
+// ====================================================================== hierarchy construction
+static int64_t read_i32(const int32_t* p, hipStream_t s) {
+    int32_t v = 0;
+    HIPCHK(hipMemcpyAsync(&v, p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return v;
+}
+
+std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
+                                           hipStream_t s) {
+    std::unique_ptr<Hierarchy> H;
+    HierT<double>* hd = nullptr;
+    HierT<float>* hf = nullptr;
+    if (o.precision == SCR_MIXED) { hf = new HierT<float>(); H.reset(hf); }
+    else { hd = new HierT<double>(); H.reset(hd); }
+    H->opts = o;
+    int* err = ar.make<int>(1);
+    unsigned long long* lamd = ar.make<unsigned long long>(1);
+    // level 0: copy of A0 and B0
+    {
+        LevelSetup l0;
+        l0.A = bsr_alloc(A0.nr, A0.nc, A0.br, A0.bc, A0.nnzb, ar);
+        HIPCHK(hipMemcpyAsync(l0.A.rp, A0.rp, (A0.nr + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(l0.A.ci, A0.ci, A0.nnzb * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(l0.A.v, A0.v, A0.nnzb * A0.br * A0.bc * sizeof(double), hipMemcpyDeviceToDevice, s));
+        l0.b = A0.br; l0.k = k;
+        l0.B = ar.make<double>(A0.nr * A0.br * k);
+        HIPCHK(hipMemcpyAsync(l0.B, B0, A0.nr * A0.br * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+        H->L.push_back(l0);
+    }
+    for (int l = 0;; ++l) {
+        LevelSetup& L = H->L[l];
+        const int64_t nr = L.A.nr;
+        const int b = L.b, bb = b * b;
+        const int64_t n = nr * b;
+        const int64_t g = cdiv(nr, 256);
+        // D^-1 and lambda_hat (every level but the coarsest needs them; computed here for all)
+        L.Dinv = ar.make<double>(nr * bb);
+        HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+        HIPCHK(hipMemsetAsync(lamd, 0, sizeof(unsigned long long), s));
+        if (g) {
+            if (b == 1) dinv_lambda_k<1><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
+            else if (b == 3) dinv_lambda_k<3><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
+            else if (b == 6) dinv_lambda_k<6><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
+            else throw Error(SCR_E_UNIMPLEMENTED, "AMG block size");
+        }
+        check_launch("dinv_lambda");
+        unsigned long long hl = 0;
+        int he = 0;
+        HIPCHK(hipMemcpyAsync(&hl, lamd, sizeof(hl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (he) throw Error(SCR_E_INVALID, "singular or missing diagonal block at AMG level " + std::to_string(l));
+        double lam;
+        std::memcpy(&lam, &hl, sizeof(double));
+        L.lam = lam;
+        if (n <= o.coarse_max || l + 1 >= o.max_levels || l + 1 >= 16) break;
+        // strength
+        double* fd = ar.make<double>(nr);
+        L.strong = ar.make<uint8_t>(L.A.nnzb > 0 ? L.A.nnzb : 1);
+        uint8_t* iso = ar.make<uint8_t>(nr);
+        fdiag_k<<<g, 256, 0, s>>>(nr, bb, L.A.rp, L.A.ci, L.A.v, fd);
+        double theta = std::ldexp(o.theta, -l);
+        double th4 = ((theta * theta) * theta) * theta;
+        strength_k<<<g, 256, 0, s>>>(nr, bb, L.A.rp, L.A.ci, L.A.v, fd, th4, L.strong, iso);
+        check_launch("strength");
+        ar.free(fd);
+        // MIS-2 rounds
+        uint64_t* st = ar.make<uint64_t>(nr);
+        uint64_t* m1 = ar.make<uint64_t>(nr);
+        uint64_t* m2 = ar.make<uint64_t>(nr);
+        int* und = ar.make<int>(1);
+        mis_init_k<<<g, 256, 0, s>>>(nr, iso, o.seed, l, st);
+        for (int round = 0;; ++round) {
+            if (round > 100000) throw Error(SCR_E_HIP, "MIS-2 did not terminate");
+            HIPCHK(hipMemsetAsync(und, 0, sizeof(int), s));
+            mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1);
+            mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2);
+            mis_decide_k<<<g, 256, 0, s>>>(nr, st, m2, und);
+            check_launch("mis2");
+            int hu = 0;
+            HIPCHK(hipMemcpyAsync(&hu, und, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (hu == 0) break;
+        }
+        ar.free(m1); ar.free(m2); ar.free(und);
+        // aggregates
+        int32_t* isroot = ar.make<int32_t>(nr + 1);
+        int32_t* rid = ar.make<int32_t>(nr + 1);
+        root_flag_k<<<g, 256, 0, s>>>(nr, st, isroot);
+        int64_t na = scan_i32(isroot, rid, nr, ar, s);
+        ar.free(isroot);
+        L.agg = ar.make<int32_t>(nr);
+        uint8_t* step1 = ar.make<uint8_t>(nr);
+        agg_roots_k<<<g, 256, 0, s>>>(nr, st, rid, L.agg);
+        agg_dist1_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, iso, st, rid, L.agg, step1);
+        HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+        agg_dist2_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, iso, step1, o.seed, l, L.agg, err);
+        check_launch("aggregate");
+        HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ar.free(step1); ar.free(rid); ar.free(st); ar.free(iso);
+        if (he) throw Error(SCR_E_HIP, "aggregation left a node unassigned");
+        if (na <= 0 || (double)(na * L.k) > o.max_coarse_ratio * (double)n) {
+            ar.free(L.agg); L.agg = nullptr;
+            ar.free(L.strong); L.strong = nullptr;
+            break;
+        }
+        L.nagg = na;
+        const int kk = L.k;
+        // members of each aggregate, ascending
+        int32_t* mcnt = ar.make<int32_t>(na + 1);
+        HIPCHK(hipMemsetAsync(mcnt, 0, (na + 1) * sizeof(int32_t), s));
+        agg_count_k<<<g, 256, 0, s>>>(nr, L.agg, mcnt);
+        int32_t* mrp = ar.make<int32_t>(na + 1);
+        int64_t nmem = scan_i32(mcnt, mrp, na, ar, s);
+        HIPCHK(hipMemsetAsync(mcnt, 0, (na + 1) * sizeof(int32_t), s));
+        int32_t* mem = ar.make<int32_t>(nmem + 1);
+        agg_fill_k<<<g, 256, 0, s>>>(nr, L.agg, mrp, mcnt, mem);
+        agg_sort_k<<<cdiv(na, 64), 64, 0, s>>>(na, mrp, mem);
+        // tentative prolongator and coarse near-null space
+        double* Q = ar.make<double>(nr * b * kk);
+        HIPCHK(hipMemsetAsync(Q, 0, nr * b * kk * sizeof(double), s));
+        LevelSetup N;
+        N.b = kk; N.k = kk;
+        N.B = ar.make<double>(na * kk * kk);
+        L.dead = ar.make<uint8_t>(na * kk);
+        HIPCHK(hipMemsetAsync(L.dead, 0, na * kk, s));
+        tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, kk, mrp, mem, L.B, Q, N.B, L.dead);
+        check_launch("tentative");
+        ar.free(mcnt); ar.free(mrp); ar.free(mem);
+        DBsr Pt;
+        Pt.nr = nr; Pt.nc = na; Pt.br = b; Pt.bc = kk;
+        Pt.rp = ar.make<int32_t>(nr + 1);
+        int32_t* pc = ar.make<int32_t>(nr + 1);
+        ptent_cnt_k<<<g, 256, 0, s>>>(nr, L.agg, pc);
+        Pt.nnzb = scan_i32(pc, Pt.rp, nr, ar, s);
+        ar.free(pc);
+        Pt.ci = ar.make<int32_t>(Pt.nnzb + 1);
+        Pt.v = ar.make<double>((Pt.nnzb + 1) * b * kk);
+        ptent_fill_k<<<g, 256, 0, s>>>(nr, b * kk, L.agg, Pt.rp, Q, Pt.ci, Pt.v);
+        check_launch("ptent");
+        // smoothed prolongator on the pattern of A * P_tent (aggregated rows only)
+        uint8_t* rowmask = ar.make<uint8_t>(nr);
+        rowmask_k<<<g, 256, 0, s>>>(nr, L.agg, rowmask);
+        DBsr P = spgemm(L.A, Pt, rowmask, ar, s);
+        ar.free(rowmask);
+        bsr_release(Pt, ar);
+        double omega = 4.0 / (3.0 * L.lam);
+        if (b == 1 && kk == 1) smooth_p_k<1, 1><<<g, 256, 0, s>>>(nr, P.rp, P.ci, P.v, L.Dinv, L.agg, Q, omega);
+        else if (b == 3 && kk == 6) smooth_p_k<3, 6><<<g, 256, 0, s>>>(nr, P.rp, P.ci, P.v, L.Dinv, L.agg, Q, omega);
+        else if (b == 6 && kk == 6) smooth_p_k<6, 6><<<g, 256, 0, s>>>(nr, P.rp, P.ci, P.v, L.Dinv, L.agg, Q, omega);
+        else throw Error(SCR_E_UNIMPLEMENTED, "prolongator block shape");
+        check_launch("smooth_p");
+        ar.free(Q);
+        L.P = P;
+        L.R = transpose(L.P, ar, s);
+        // Galerkin product A_c = R (A P) on structural patterns; dead coarse dofs get a unit diagonal
+        DBsr AP = spgemm(L.A, L.P, nullptr, ar, s);
+        N.A = spgemm(L.R, AP, nullptr, ar, s);
+        bsr_release(AP, ar);
+        if (na) dead_diag_k<<<cdiv(na, 256), 256, 0, s>>>(na, kk, N.A.rp, N.A.ci, N.A.v, L.dead);
+        check_launch("dead_diag");
+        H->L.push_back(N);   // invalidates L
+    }
+    // coarsest level: explicit inverse by Gauss-Jordan exchange steps (the matrix is SPD)
+    {
+        LevelSetup& C = H->L.back();
+        int64_t nc = C.A.nr * C.b;
+        H->ncoarse = nc;
+        if (nc > 8192) throw Error(SCR_E_INVALID, "coarsest AMG level too large for a direct solve (" + std::to_string(nc) + ")");
+        double* M0 = ar.make<double>(nc * nc + 1);
+        double* M1 = ar.make<double>(nc * nc + 1);
+        HIPCHK(hipMemsetAsync(M0, 0, nc * nc * sizeof(double), s));
+        if (C.A.nr) densify_k<<<cdiv(C.A.nr, 256), 256, 0, s>>>(C.A.nr, C.b, C.A.rp, C.A.ci, C.A.v, M0, nc);
+        for (int64_t kp = 0; kp < nc; ++kp) {
+            gj_step_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc, kp, M0, M1);
+            std::swap(M0, M1);
+        }
+        check_launch("coarse inverse");
+        HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+        if (nc) finite_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc * nc, M0, err);
+        int he = 0;
+        HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (he) throw Error(SCR_E_INVALID, "coarsest AMG matrix is singular");
+        ar.free(M1);
+        H->cinv = M0;
+    }
+    ar.free(err);
+    ar.free(lamd);
+    if (hf) hf->prepare(ar, s);
+    else hd->prepare(ar, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return H;
+}
+
+}  // namespace scr

@@ -1,0 +1,529 @@
+// krylov.hip -- FP64 vector kernels, deterministic reductions and the Krylov drivers:
+// flexible GMRES with classical Gram-Schmidt applied twice (CGS2) and device-resident Givens
+// rotations, and (flexible) preconditioned CG.  Every reduction uses a grid fixed by the
+// vector length and sums per-block partials in block order, so results are bitwise
+// reproducible run to run.
+#include <cmath>
+
+#include "solver.h"
+
+namespace scr {
+
+constexpr int RTPB = 256;
+constexpr int RMAXJ = 64;   // partial slots per block
+
+// ------------------------------------------------------------------ vector kernels
+__global__ void axpby_k(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+    if (n > 0) axpby_k<<<cdiv(n, 256), 256, 0, s>>>(n, a, x, b, y);
+    check_launch("axpby");
+}
+void copy_d(int64_t n, const double* x, double* y, hipStream_t s) {
+    if (n > 0) HIPCHK(hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+__global__ void i2s_k(int64_t nb, const double* __restrict__ a, double* __restrict__ sv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    sv[3 * i] = a[4 * i]; sv[3 * i + 1] = a[4 * i + 1]; sv[3 * i + 2] = a[4 * i + 2];
+    sv[3 * nb + i] = a[4 * i + 3];
+}
+__global__ void s2i_k(int64_t nb, const double* __restrict__ sv, double* __restrict__ a) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    a[4 * i] = sv[3 * i]; a[4 * i + 1] = sv[3 * i + 1]; a[4 * i + 2] = sv[3 * i + 2];
+    a[4 * i + 3] = sv[3 * nb + i];
+}
+void interleaved_to_split(int64_t nb, const double* a, double* sv, hipStream_t s) {
+    if (nb > 0) i2s_k<<<cdiv(nb, 256), 256, 0, s>>>(nb, a, sv);
+    check_launch("i2s");
+}
+void split_to_interleaved(int64_t nb, const double* sv, double* a, hipStream_t s) {
+    if (nb > 0) s2i_k<<<cdiv(nb, 256), 256, 0, s>>>(nb, sv, a);
+    check_launch("s2i");
+}
+__global__ void gcol_k(int64_t n, const double* __restrict__ a, int c, double* __restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a[3 * i + c];
+}
+__global__ void scol_k(int64_t n, const double* __restrict__ y, int c, double* __restrict__ a) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[3 * i + c] = y[i];
+}
+void gather_col3(int64_t n, const double* a, int c, double* y, hipStream_t s) {
+    if (n > 0) gcol_k<<<cdiv(n, 256), 256, 0, s>>>(n, a, c, y);
+}
+void scatter_col3(int64_t n, const double* y, int c, double* a, hipStream_t s) {
+    if (n > 0) scol_k<<<cdiv(n, 256), 256, 0, s>>>(n, y, c, a);
+}
+
+// ------------------------------------------------------------------ reduction machinery
+void Reducer::init(int64_t n_, Arena& ar, hipStream_t s) {
+    n = n_;
+    int64_t g = cdiv(n, 2 * RTPB);
+    grid = (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+    partials = ar.make<double>((size_t)grid * RMAXJ);
+    counter = ar.make<unsigned>(1);
+    out = ar.make<double>(RMAXJ);
+    HIPCHK(hipMemsetAsync(counter, 0, sizeof(unsigned), s));
+}
+
+template <int J>
+__device__ __forceinline__ void block_partials(const double (&acc)[J], int jn, double* __restrict__ partials) {
+    __shared__ double red[RTPB / WAVE][J];
+    int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        if (j < jn) {
+            double v = wave_sum(acc[j]);
+            if (lane == 0) red[w][j] = v;
+        }
+    __syncthreads();
+    for (int j = threadIdx.x; j < jn; j += RTPB) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < RTPB / WAVE; ++q) t += red[q][j];
+        partials[(int64_t)blockIdx.x * RMAXJ + j] = t;
+    }
+}
+
+__device__ __forceinline__ bool last_block(unsigned* counter) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+// sum of the partials in block order, for j < jn, into out[j]; thread-parallel over j
+__device__ __forceinline__ void final_sums(const double* __restrict__ partials, int jn, double* __restrict__ out) {
+    for (int j = threadIdx.x; j < jn; j += blockDim.x) {
+        double t = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) t += partials[(int64_t)b * RMAXJ + j];
+        out[j] = t;
+    }
+}
+
+// ------------------------------------------------------------------ plain dot
+__global__ void __launch_bounds__(RTPB) dot_k(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                              double* __restrict__ partials, unsigned* counter, double* __restrict__ out) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) acc[0] += x[i] * y[i];
+    block_partials<1>(acc, 1, partials);
+    if (last_block(counter)) {
+        final_sums(partials, 1, out);
+        if (threadIdx.x == 0) *counter = 0;
+    }
+}
+
+double device_norm(const double* x, int64_t n, Reducer& red, double* host, hipStream_t s) {
+    dot_k<<<red.grid, RTPB, 0, s>>>(n, x, x, red.partials, red.counter, red.out);
+    check_launch("dot");
+    HIPCHK(hipMemcpyAsync(host, red.out, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return std::sqrt(host[0]);
+}
+
+// ------------------------------------------------------------------ GMRES kernels
+// state layout (doubles): H[(m+1)*m] | cs[m] | sn[m] | g[m+1] | y[m] | h1[64] | h2[64] | scal[8]
+struct GLay {
+    int m;
+    __host__ __device__ int H() const { return 0; }
+    __host__ __device__ int cs() const { return (m + 1) * m; }
+    __host__ __device__ int sn() const { return cs() + m; }
+    __host__ __device__ int g() const { return sn() + m; }
+    __host__ __device__ int y() const { return g() + m + 1; }
+    __host__ __device__ int h1() const { return y() + m; }
+    __host__ __device__ int h2() const { return h1() + 64; }
+    __host__ __device__ int scal() const { return h2() + 64; }
+    __host__ __device__ int size() const { return scal() + 8; }
+};
+enum { S_BETA = 0, S_EST = 1, S_HN = 2, S_INV = 3, S_FLAG = 4 };
+
+// beta = ||v||; g = [beta, 0, ...]; inv = 1/beta
+__global__ void __launch_bounds__(RTPB) gm_init_k(int64_t n, const double* __restrict__ v, double* __restrict__ partials,
+                                                  unsigned* counter, double* __restrict__ st, int m) {
+    GLay L{m};
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) acc[0] += v[i] * v[i];
+    block_partials<1>(acc, 1, partials);
+    if (last_block(counter)) {
+        final_sums(partials, 1, st + L.scal() + S_HN);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double beta = sqrt(st[L.scal() + S_HN]);
+            double* sc = st + L.scal();
+            sc[S_BETA] = beta;
+            sc[S_EST] = beta;
+            sc[S_INV] = beta > 0.0 ? 1.0 / beta : 0.0;
+            sc[S_FLAG] = isfinite(beta) ? 0.0 : 1.0;
+            double* g = st + L.g();
+            g[0] = beta;
+            for (int i = 1; i <= m; ++i) g[i] = 0.0;
+            *counter = 0;
+        }
+    }
+}
+
+__global__ void scale_by_k(int64_t n, double* __restrict__ v, const double* __restrict__ s) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double f = *s;
+    if (i < n) v[i] *= f;
+}
+
+// out[i] = V_i . w  (i < jn)
+template <int J>
+__global__ void __launch_bounds__(RTPB) mdot_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
+                                               const double* __restrict__ w, double* __restrict__ partials, unsigned* counter,
+                                               double* __restrict__ out) {
+    double acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * RTPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * RTPB) {
+        double we = w[e];
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < jn) acc[j] += V[j * ld + e] * we;
+    }
+    block_partials<J>(acc, jn, partials);
+    if (last_block(counter)) {
+        final_sums(partials, jn, out);
+        if (threadIdx.x == 0) *counter = 0;
+    }
+}
+
+// w -= sum_i h_i V_i ;  out[i] = V_i . w
+template <int J>
+__global__ void __launch_bounds__(RTPB) upd_dot_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
+                                                  double* __restrict__ w, const double* __restrict__ h,
+                                                  double* __restrict__ partials, unsigned* counter, double* __restrict__ out) {
+    __shared__ double hs[J];
+    for (int j = threadIdx.x; j < jn; j += RTPB) hs[j] = h[j];
+    __syncthreads();
+    double acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * RTPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * RTPB) {
+        double v[J];
+        double we = w[e];
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < jn) {
+                v[j] = V[j * ld + e];
+                we -= hs[j] * v[j];
+            }
+        w[e] = we;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < jn) acc[j] += v[j] * we;
+    }
+    block_partials<J>(acc, jn, partials);
+    if (last_block(counter)) {
+        final_sums(partials, jn, out);
+        if (threadIdx.x == 0) *counter = 0;
+    }
+}
+
+// w -= sum_i h2_i V_i ; ||w||^2 ; then (one thread) the Arnoldi column j: H[:,j] = h1 + h2,
+// H[j+1,j] = ||w||, previous rotations, new rotation, g update, estimate |g[j+1]|.
+template <int J>
+__global__ void __launch_bounds__(RTPB) upd_norm_finish_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
+                                                          double* __restrict__ w, double* __restrict__ partials,
+                                                          unsigned* counter, double* __restrict__ st, int m, int j) {
+    GLay L{m};
+    __shared__ double hs[J];
+    const double* h2 = st + L.h2();
+    for (int t = threadIdx.x; t < jn; t += RTPB) hs[t] = h2[t];
+    __syncthreads();
+    double acc[1] = {0.0};
+    for (int64_t e = (int64_t)blockIdx.x * RTPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * RTPB) {
+        double we = w[e];
+#pragma unroll
+        for (int t = 0; t < J; ++t)
+            if (t < jn) we -= hs[t] * V[t * ld + e];
+        w[e] = we;
+        acc[0] += we * we;
+    }
+    block_partials<1>(acc, 1, partials);
+    if (last_block(counter)) {
+        double* sc = st + L.scal();
+        final_sums(partials, 1, sc + S_HN);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double* H = st + L.H();
+            double* cs = st + L.cs();
+            double* sn = st + L.sn();
+            double* g = st + L.g();
+            const double* h1 = st + L.h1();
+            double hn = sqrt(sc[S_HN]);
+            for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * m + j], c = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[j * m + j], c = H[(j + 1) * m + j];
+            double rr = sqrt(a * a + c * c);
+            cs[j] = rr == 0.0 ? 1.0 : a / rr;
+            sn[j] = rr == 0.0 ? 0.0 : c / rr;
+            H[j * m + j] = rr;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            sc[S_HN] = hn;
+            sc[S_EST] = fabs(g[j + 1]);
+            sc[S_INV] = hn > 0.0 ? 1.0 / hn : 0.0;
+            sc[S_FLAG] = (isfinite(hn) && isfinite(sc[S_EST]) && isfinite(rr)) ? 0.0 : 1.0;
+            *counter = 0;
+        }
+    }
+}
+
+// back substitution of the j x j upper triangle: y = R^-1 g
+__global__ void ysolve_k(double* __restrict__ st, int m, int j) {
+    GLay L{m};
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double* H = st + L.H();
+    const double* g = st + L.g();
+    double* y = st + L.y();
+    for (int i = j - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int t = i + 1; t < j; ++t) s -= H[i * m + t] * y[t];
+        y[i] = s / H[i * m + i];
+    }
+}
+
+// x += sum_i y_i Z_i
+__global__ void __launch_bounds__(RTPB) maxpy_k(int64_t n, int jn, const double* __restrict__ Z, int64_t ld,
+                                                const double* __restrict__ y, double* __restrict__ x) {
+    __shared__ double ys[RMAXJ];
+    for (int j = threadIdx.x; j < jn; j += RTPB) ys[j] = y[j];
+    __syncthreads();
+    int64_t e = (int64_t)blockIdx.x * RTPB + threadIdx.x;
+    if (e >= n) return;
+    double xe = x[e];
+    for (int j = 0; j < jn; ++j) xe += ys[j] * Z[j * ld + e];
+    x[e] = xe;
+}
+
+#define JDISPATCH(jn, KERNEL, ...)                                         \
+    do {                                                                   \
+        if ((jn) <= 4) KERNEL<4>__VA_ARGS__;                               \
+        else if ((jn) <= 8) KERNEL<8>__VA_ARGS__;                          \
+        else if ((jn) <= 16) KERNEL<16>__VA_ARGS__;                        \
+        else if ((jn) <= 32) KERNEL<32>__VA_ARGS__;                        \
+        else KERNEL<64>__VA_ARGS__;                                        \
+    } while (0)
+
+Gmres::Gmres(int64_t n, int m, Arena& ar, hipStream_t s) : n_(n), m_(m), ar_(&ar) {
+    if (m < 1 || m > 63) throw Error(SCR_E_INVALID, "restart length must be in [1, 63]");
+    V_ = ar.make<double>((size_t)(m + 1) * n);
+    Z_ = ar.make<double>((size_t)m * n);
+    GLay L{m};
+    st_ = ar.make<double>(L.size());
+    red_.init(n, ar, s);
+    HIPCHK(hipHostMalloc((void**)&host_, 16 * sizeof(double), hipHostMallocDefault));
+}
+Gmres::~Gmres() {
+    if (host_) (void)hipHostFree(host_);
+    ar_->free(V_); ar_->free(Z_); ar_->free(st_);
+    red_.release(*ar_);
+}
+
+KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool use_x0, bool check_true,
+                   hipStream_t s) {
+    KStat st;
+    const int64_t n = n_;
+    const int m = m_;
+    GLay L{m};
+    double bn = device_norm(b, n, red_, host_, s);
+    if (!use_x0 || bn == 0.0) HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    if (bn == 0.0) {
+        st.converged = true;
+        HIPCHK(hipStreamSynchronize(s));
+        return st;
+    }
+    if (!std::isfinite(bn)) throw Error(SCR_E_BREAKDOWN, "non-finite right-hand side");
+    bool first = true;
+    double est = INFINITY;
+    int64_t nblk = cdiv(n, 256);
+    for (;;) {
+        double* V0 = V_;
+        if (first && !use_x0) {
+            copy_d(n, b, V0, s);
+        } else {
+            A.apply(x, V0, s);
+            axpby(n, 1.0, b, -1.0, V0, s);
+        }
+        first = false;
+        gm_init_k<<<red_.grid, RTPB, 0, s>>>(n, V0, red_.partials, red_.counter, st_, m);
+        check_launch("gm_init");
+        HIPCHK(hipMemcpyAsync(host_, st_ + L.scal(), 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double beta = host_[S_BETA];
+        if (host_[S_FLAG] != 0.0) throw Error(SCR_E_BREAKDOWN, "non-finite residual in GMRES");
+        st.rel_res = beta / bn;
+        if (beta <= tol * bn) { st.converged = true; break; }
+        if (!check_true && est <= tol * bn) { st.converged = true; break; }
+        if (st.iters >= maxit) break;
+        scale_by_k<<<nblk, 256, 0, s>>>(n, V0, st_ + L.scal() + S_INV);
+        int j = 0;
+        while (j < m) {
+            double* Vj = V_ + (int64_t)j * n;
+            double* Zj = Z_ + (int64_t)j * n;
+            double* w = V_ + (int64_t)(j + 1) * n;
+            M.apply(Vj, Zj, s);
+            A.apply(Zj, w, s);
+            int jn = j + 1;
+            JDISPATCH(jn, mdot_k, <<<red_.grid, RTPB, 0, s>>>(n, jn, V_, n, w, red_.partials, red_.counter, st_ + L.h1()));
+            JDISPATCH(jn, upd_dot_k, <<<red_.grid, RTPB, 0, s>>>(n, jn, V_, n, w, st_ + L.h1(), red_.partials, red_.counter, st_ + L.h2()));
+            JDISPATCH(jn, upd_norm_finish_k, <<<red_.grid, RTPB, 0, s>>>(n, jn, V_, n, w, red_.partials, red_.counter, st_, m, j));
+            check_launch("cgs2");
+            scale_by_k<<<nblk, 256, 0, s>>>(n, w, st_ + L.scal() + S_INV);
+            HIPCHK(hipMemcpyAsync(host_, st_ + L.scal(), 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ++st.iters;
+            ++j;
+            if (host_[S_FLAG] != 0.0) throw Error(SCR_E_BREAKDOWN, "non-finite value in the Arnoldi process");
+            est = host_[S_EST];
+            if (host_[S_HN] == 0.0) break;   // happy breakdown: the Krylov space is invariant
+            if (est <= tol * bn || st.iters >= maxit) break;
+        }
+        ysolve_k<<<1, 64, 0, s>>>(st_, m, j);
+        maxpy_k<<<nblk, RTPB, 0, s>>>(n, j, Z_, n, st_ + L.y(), x);
+        check_launch("gmres update");
+        st.rel_res = est / bn;
+        if (!check_true && (est <= tol * bn || st.iters >= maxit)) {
+            st.converged = est <= tol * bn;
+            HIPCHK(hipStreamSynchronize(s));
+            break;
+        }
+    }
+    return st;
+}
+
+// ------------------------------------------------------------------ CG kernels
+enum { C_RZ = 0, C_ALPHA = 1, C_BETA = 2, C_RN2 = 3, C_PQ = 4 };
+
+// st[ALPHA] = st[RZ] / (p . q)
+__global__ void __launch_bounds__(RTPB) cg_alpha_k(int64_t n, const double* __restrict__ p, const double* __restrict__ q,
+                                                   double* __restrict__ partials, unsigned* counter, double* __restrict__ st) {
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) acc[0] += p[i] * q[i];
+    block_partials<1>(acc, 1, partials);
+    if (last_block(counter)) {
+        final_sums(partials, 1, st + C_PQ);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            st[C_ALPHA] = st[C_RZ] / st[C_PQ];
+            *counter = 0;
+        }
+    }
+}
+
+// (rold = r;) x += alpha p; r -= alpha q; st[RN2] = r . r
+__global__ void __launch_bounds__(RTPB) cg_update_k(int64_t n, double* __restrict__ x, const double* __restrict__ p,
+                                                    double* __restrict__ r, const double* __restrict__ q,
+                                                    double* __restrict__ rold, double* __restrict__ partials,
+                                                    unsigned* counter, double* __restrict__ st) {
+    double alpha = st[C_ALPHA];
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) {
+        double ri = r[i];
+        if (rold) rold[i] = ri;
+        x[i] += alpha * p[i];
+        ri -= alpha * q[i];
+        r[i] = ri;
+        acc[0] += ri * ri;
+    }
+    block_partials<1>(acc, 1, partials);
+    if (last_block(counter)) {
+        final_sums(partials, 1, st + C_RN2);
+        __syncthreads();
+        if (threadIdx.x == 0) *counter = 0;
+    }
+}
+
+// rz_new = r . z; (flexible) num = z . (r - rold); beta = (flex ? num : rz_new) / rz; rz = rz_new.
+// init: only rz = r . z.
+__global__ void __launch_bounds__(RTPB) cg_beta_k(int64_t n, const double* __restrict__ r, const double* __restrict__ z,
+                                                  const double* __restrict__ rold, int init, double* __restrict__ partials,
+                                                  unsigned* counter, double* __restrict__ st) {
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) {
+        double zi = z[i], ri = r[i];
+        acc[0] += ri * zi;
+        if (rold) acc[1] += zi * (ri - rold[i]);
+    }
+    block_partials<2>(acc, 2, partials);
+    if (last_block(counter)) {
+        __shared__ double res[2];
+        final_sums(partials, 2, res);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (!init) st[C_BETA] = (rold ? res[1] : res[0]) / st[C_RZ];
+            st[C_RZ] = res[0];
+            *counter = 0;
+        }
+    }
+}
+
+__global__ void cg_p_k(int64_t n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ st) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double beta = st[C_BETA];
+    if (i < n) p[i] = z[i] + beta * p[i];
+}
+
+Pcg::Pcg(int64_t n, Arena& ar, hipStream_t s) : n_(n), ar_(&ar) {
+    r_ = ar.make<double>(n); z_ = ar.make<double>(n); p_ = ar.make<double>(n);
+    q_ = ar.make<double>(n); rold_ = ar.make<double>(n); st_ = ar.make<double>(8);
+    red_.init(n, ar, s);
+    HIPCHK(hipHostMalloc((void**)&host_, 16 * sizeof(double), hipHostMallocDefault));
+}
+Pcg::~Pcg() {
+    if (host_) (void)hipHostFree(host_);
+    ar_->free(r_); ar_->free(z_); ar_->free(p_); ar_->free(q_); ar_->free(rold_); ar_->free(st_);
+    red_.release(*ar_);
+}
+
+KStat Pcg::solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool flexible, hipStream_t s) {
+    KStat st;
+    const int64_t n = n_;
+    int64_t nblk = cdiv(n, 256);
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    double bn = device_norm(b, n, red_, host_, s);
+    if (bn == 0.0) { st.converged = true; return st; }
+    if (!std::isfinite(bn)) throw Error(SCR_E_BREAKDOWN, "non-finite right-hand side");
+    copy_d(n, b, r_, s);
+    M.apply(r_, z_, s);
+    copy_d(n, z_, p_, s);
+    cg_beta_k<<<red_.grid, RTPB, 0, s>>>(n, r_, z_, nullptr, 1, red_.partials, red_.counter, st_);
+    double* rold = flexible ? rold_ : nullptr;
+    for (;;) {
+        A.apply(p_, q_, s);
+        cg_alpha_k<<<red_.grid, RTPB, 0, s>>>(n, p_, q_, red_.partials, red_.counter, st_);
+        cg_update_k<<<red_.grid, RTPB, 0, s>>>(n, x, p_, r_, q_, rold, red_.partials, red_.counter, st_);
+        check_launch("cg");
+        HIPCHK(hipMemcpyAsync(host_, st_, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ++st.iters;
+        double rn = std::sqrt(host_[C_RN2]);
+        if (!std::isfinite(rn)) throw Error(SCR_E_BREAKDOWN, "non-finite residual in CG");
+        st.rel_res = rn / bn;
+        if (rn <= tol * bn) { st.converged = true; break; }
+        if (st.iters >= maxit) break;
+        M.apply(r_, z_, s);
+        cg_beta_k<<<red_.grid, RTPB, 0, s>>>(n, r_, z_, rold, 0, red_.partials, red_.counter, st_);
+        cg_p_k<<<nblk, 256, 0, s>>>(n, p_, z_, st_);
+        check_launch("cg");
+    }
+    return st;
+}
+
+}  // namespace scr

@@ -1,0 +1,563 @@
+// scr.hip -- handles, the SCR preconditioner (Appendix B, Algorithms 1 and 2), the outer FGMRES
+// (Sec. 5.2.1), the mesh-motion CG (Sec. 5.2.2) and the extern "C" boundary declared in scr.h.
+#include <chrono>
+#include <cmath>
+#include <memory>
+
+#include "solver.h"
+
+using namespace scr;
+
+namespace scr {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& m) { g_last_error = m; }
+}  // namespace scr
+
+struct scr_ctx {
+    Ctx c;
+};
+
+struct scr_handle {
+    Ctx* ctx = nullptr;
+    int kind = SCR_SYSTEM;
+    scr_amg_opts opts{};
+    std::unique_ptr<Arena> ar;
+    int64_t nb = 0;
+    // SCR system (FP64 setup form; A, G, D, C share K's index arrays)
+    DBsr K, A, G, D, C, Sh;
+    DSell<double> Ks, As, Gs, Ds, Cs, Ls;
+    double* B = nullptr;
+    std::unique_ptr<Hierarchy> hA, hS, hL;
+    std::unique_ptr<Gmres> gOuter, gA, gS;
+    std::unique_ptr<Pcg> cg;
+    int restart = 0, restart_inner = 0;
+    double *bs = nullptr, *xs = nullptr, *yhat = nullptr, *tv = nullptr, *tp = nullptr, *xbar = nullptr,
+           *xtil = nullptr, *col_b = nullptr, *col_x = nullptr;
+    scr_stats st{};
+    scr_solve_opts so{};
+};
+
+namespace {
+
+struct MatOp : Op {
+    const DSell<double>* M;
+    explicit MatOp(const DSell<double>* m) : M(m) {}
+    void apply(const double* x, double* y, hipStream_t s) override { sell_mv<double>(*M, x, nullptr, y, 0, s); }
+};
+struct KOp : Op {
+    const DSell<double>* K;
+    explicit KOp(const DSell<double>* k) : K(k) {}
+    void apply(const double* x, double* y, hipStream_t s) override { sell_mv_split4(*K, x, nullptr, y, 0, s); }
+};
+struct VOp : Op {
+    Hierarchy* H;
+    int64_t* count;
+    VOp(Hierarchy* h, int64_t* c) : H(h), count(c) {}
+    void apply(const double* x, double* y, hipStream_t s) override {
+        H->vcycle(x, y, s);
+        ++*count;
+    }
+};
+
+// Algorithm 2: y = S x_p = C x_p - D A^-1 (G x_p), A^-1 by GMRES + AMG(A) to delta_I
+struct SchurOp : Op {
+    scr_handle* h;
+    explicit SchurOp(scr_handle* hh) : h(hh) {}
+    void apply(const double* xp, double* y, hipStream_t s) override {
+        sell_mv<double>(h->Gs, xp, nullptr, h->xbar, 0, s);
+        MatOp aop(&h->As);
+        VOp pa(h->hA.get(), &h->st.vcycles_A);
+        KStat k = h->gA->solve(aop, pa, h->xbar, h->xtil, h->so.tol_I, h->so.max_it_I, false, false, s);
+        h->st.calls_I++;
+        h->st.its_I += k.iters;
+        sell_mv<double>(h->Cs, xp, nullptr, y, 0, s);
+        sell_mv<double>(h->Ds, h->xtil, nullptr, y, 3, s);
+    }
+};
+
+// Algorithm 1 (step 2 read as r_p <- r_p - D y^_v):  y = P_SCR^-1 r on split vectors
+struct ScrPrec : Op {
+    scr_handle* h;
+    explicit ScrPrec(scr_handle* hh) : h(hh) {}
+    void apply(const double* r, double* y, hipStream_t s) override {
+        const int64_t n = h->nb;
+        const double* rv = r;
+        const double* rp = r + 3 * n;
+        double* yv = y;
+        double* yp = y + 3 * n;
+        MatOp aop(&h->As);
+        VOp pa(h->hA.get(), &h->st.vcycles_A);
+        KStat k = h->gA->solve(aop, pa, rv, h->yhat, h->so.tol_A, h->so.max_it_A, false, false, s);
+        h->st.calls_A++;
+        h->st.its_A += k.iters;
+        sell_mv<double>(h->Ds, h->yhat, rp, h->tp, 1, s);            // r_p - D y^_v
+        SchurOp sop(h);
+        VOp ps(h->hS.get(), &h->st.vcycles_S);
+        k = h->gS->solve(sop, ps, h->tp, yp, h->so.tol_S, h->so.max_it_S, false, false, s);
+        h->st.calls_S++;
+        h->st.its_S += k.iters;
+        sell_mv<double>(h->Gs, yp, rv, h->tv, 1, s);                 // r_v - G y_p
+        k = h->gA->solve(aop, pa, h->tv, yv, h->so.tol_A, h->so.max_it_A, false, false, s);
+        h->st.calls_A++;
+        h->st.its_A += k.iters;
+    }
+};
+
+scr_status fail(const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+}
+
+void ensure_workspaces(scr_handle* h, const scr_solve_opts& o, hipStream_t s) {
+    if (o.restart < 1 || o.restart > 63 || o.restart_inner < 1 || o.restart_inner > 63)
+        throw Error(SCR_E_INVALID, "restart lengths must be in [1, 63]");
+    h->ar->set_stream(s);
+    if (h->kind == SCR_SYSTEM) {
+        if (!h->gOuter || h->restart != o.restart) {
+            h->gOuter.reset();
+            h->gOuter.reset(new Gmres(4 * h->nb, o.restart, *h->ar, s));
+            h->restart = o.restart;
+        }
+        if (!h->gA || h->restart_inner != o.restart_inner) {
+            h->gA.reset(new Gmres(3 * h->nb, o.restart_inner, *h->ar, s));
+            h->gS.reset(new Gmres(h->nb, o.restart_inner, *h->ar, s));
+            h->restart_inner = o.restart_inner;
+        }
+    } else if (!h->cg) {
+        h->cg.reset(new Pcg(h->nb, *h->ar, s));
+    }
+}
+
+void check_opts(const scr_solve_opts& o) {
+    if (!(o.tol > 0) || !(o.tol_A > 0) || !(o.tol_S > 0) || !(o.tol_I > 0) || o.max_it < 1 || o.max_it_A < 1 ||
+        o.max_it_S < 1 || o.max_it_I < 1)
+        throw Error(SCR_E_INVALID, "tolerances must be positive and iteration limits >= 1");
+}
+
+}  // namespace
+
+extern "C" {
+
+void scr_default_amg_opts(scr_amg_opts* o) {
+    o->precision = SCR_FP64;
+    o->theta = 0.08;
+    o->smoother = SCR_SMOOTH_CHEBYSHEV;
+    o->cheb_degree = 2;
+    o->cheb_ratio = 30.0;
+    o->jacobi_sweeps = 2;
+    o->coarse_max = 1024;
+    o->max_levels = 10;
+    o->max_coarse_ratio = 0.8;
+    o->seed = 0;
+}
+
+void scr_default_solve_opts(scr_solve_opts* o) {
+    o->tol = 1e-8;
+    o->tol_A = o->tol_S = o->tol_I = 1e-3;
+    o->max_it = o->max_it_A = o->max_it_S = o->max_it_I = 200;
+    o->restart = 50;
+    o->restart_inner = 30;
+    o->use_x0 = 0;
+    o->flexible_cg = 0;
+}
+
+const char* scr_status_str(scr_status s) {
+    switch (s) {
+        case SCR_OK: return "ok";
+        case SCR_NOT_CONVERGED: return "not converged";
+        case SCR_E_INVALID: return "invalid input";
+        case SCR_E_OOM: return "out of device memory";
+        case SCR_E_HIP: return "HIP error";
+        case SCR_E_BREAKDOWN: return "Krylov breakdown (non-finite value)";
+        case SCR_E_UNIMPLEMENTED: return "unimplemented";
+        case SCR_E_NO_DEVICE: return "no device";
+    }
+    return "unknown status";
+}
+
+const char* scr_last_error(void) { return g_last_error.c_str(); }
+
+scr_status scr_ctx_create(int device, int64_t hbm_budget, scr_ctx** out) {
+    try {
+        if (!out) throw Error(SCR_E_INVALID, "out is NULL");
+        *out = nullptr;
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) throw Error(SCR_E_NO_DEVICE, "no HIP device");
+        if (device < 0 || device >= n) throw Error(SCR_E_INVALID, "device index out of range");
+        HIPCHK(hipSetDevice(device));
+        hipDeviceProp_t p;
+        HIPCHK(hipGetDeviceProperties(&p, device));
+        // keep freed stream-ordered memory in the pool (solves allocate nothing once warm)
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        auto* c = new scr_ctx();
+        c->c.device = device;
+        c->c.budget = hbm_budget;
+        c->c.cu_count = p.multiProcessorCount;
+        *out = c;
+        return SCR_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+void scr_ctx_destroy(scr_ctx* ctx) { delete ctx; }
+int64_t scr_ctx_bytes_in_use(const scr_ctx* ctx) { return ctx ? ctx->c.in_use.load() : 0; }
+
+scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coords, const scr_amg_opts* opts,
+                     void* stream, scr_handle** out) {
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<scr_handle> h;
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!ctx || !K || !out) throw Error(SCR_E_INVALID, "NULL argument");
+        *out = nullptr;
+        if (kind != SCR_SYSTEM && kind != MESH_SYSTEM) throw Error(SCR_E_INVALID, "unknown kind");
+        int want = kind == SCR_SYSTEM ? 4 : 1;
+        if (K->bs != want) throw Error(SCR_E_INVALID, "block size must be 4 (SCR_SYSTEM) or 1 (MESH_SYSTEM)");
+        if (K->n_brows <= 0 || K->nnzb < K->n_brows) throw Error(SCR_E_INVALID, "empty matrix or missing diagonal");
+        if (!K->row_ptr || !K->col_idx || !K->val) throw Error(SCR_E_INVALID, "NULL matrix array");
+        if (kind == SCR_SYSTEM && !coords) throw Error(SCR_E_INVALID, "coords are required for SCR_SYSTEM");
+        HIPCHK(hipSetDevice(ctx->c.device));
+        h.reset(new scr_handle());
+        h->ctx = &ctx->c;
+        h->kind = kind;
+        if (opts) h->opts = *opts;
+        else scr_default_amg_opts(&h->opts);
+        const scr_amg_opts& o = h->opts;
+        if (o.precision != SCR_FP64 && o.precision != SCR_MIXED) throw Error(SCR_E_INVALID, "precision");
+        if (!(o.theta > 0) || o.coarse_max < 1 || o.max_levels < 1 || o.cheb_degree < 1 || o.jacobi_sweeps < 1 ||
+            !(o.cheb_ratio > 1) || !(o.max_coarse_ratio > 0))
+            throw Error(SCR_E_INVALID, "AMG options out of range");
+        h->ar.reset(new Arena(&ctx->c, s));
+        Arena& ar = *h->ar;
+        const int64_t nb = K->n_brows;
+        h->nb = nb;
+        // row_ptr endpoints first, so that the validation kernel never reads outside col_idx
+        int32_t ends[2];
+        HIPCHK(hipMemcpyAsync(&ends[0], K->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&ends[1], K->row_ptr + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (ends[0] != 0 || ends[1] != K->nnzb) throw Error(SCR_E_INVALID, "row_ptr[0] != 0 or row_ptr[n] != nnzb");
+        int bits = validate_bsr(nb, K->bs, K->nnzb, K->row_ptr, K->col_idx, K->val, ar, s);
+        if (bits) {
+            std::string m = "malformed matrix:";
+            if (bits & 1) m += " row_ptr";
+            if (bits & 2) m += " column-out-of-range";
+            if (bits & 4) m += " unsorted-or-duplicate-columns";
+            if (bits & 8) m += " missing-diagonal";
+            if (bits & 16) m += " non-finite-value";
+            if (bits & 32) m += " zero-diagonal";
+            throw Error(SCR_E_INVALID, m);
+        }
+        DBsr& Km = h->K;
+        Km.nr = Km.nc = nb; Km.br = Km.bc = K->bs; Km.nnzb = K->nnzb;
+        Km.rp = ar.make<int32_t>(nb + 1);
+        Km.ci = ar.make<int32_t>(K->nnzb);
+        Km.v = ar.make<double>(K->nnzb * K->bs * K->bs);
+        HIPCHK(hipMemcpyAsync(Km.rp, K->row_ptr, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(Km.ci, K->col_idx, K->nnzb * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(Km.v, K->val, K->nnzb * K->bs * K->bs * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (kind == SCR_SYSTEM) {
+            split_blocks(Km, h->A, h->G, h->D, h->C, ar, s);
+            h->Sh = schur_approx(h->A, h->G, h->D, h->C, ar, s);
+            double* xyz = ar.make<double>(nb * 3);
+            HIPCHK(hipMemcpyAsync(xyz, coords, nb * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            h->B = ar.make<double>(nb * 18);
+            rigid_modes(nb, xyz, h->B, ar, s);
+            ar.free(xyz);
+            h->hA = build_hierarchy(h->A, h->B, 6, o, ar, s);
+            double* ones = ar.make<double>(nb);
+            fill<double>(ones, 1.0, nb, s);
+            h->hS = build_hierarchy(h->Sh, ones, 1, o, ar, s);
+            ar.free(ones);
+            h->Ks = sell_from_bsr<double>(Km, ar, s);
+            h->As = sell_from_bsr<double>(h->A, ar, s);
+            h->Gs = sell_from_bsr<double>(h->G, ar, s);
+            h->Ds = sell_from_bsr<double>(h->D, ar, s);
+            h->Cs = sell_from_bsr<double>(h->C, ar, s);
+            h->bs = ar.make<double>(4 * nb);
+            h->xs = ar.make<double>(4 * nb);
+            h->yhat = ar.make<double>(3 * nb);
+            h->tv = ar.make<double>(3 * nb);
+            h->tp = ar.make<double>(nb);
+            h->xbar = ar.make<double>(3 * nb);
+            h->xtil = ar.make<double>(3 * nb);
+        } else {
+            double* ones = ar.make<double>(nb);
+            fill<double>(ones, 1.0, nb, s);
+            h->hL = build_hierarchy(Km, ones, 1, o, ar, s);
+            ar.free(ones);
+            h->Ls = sell_from_bsr<double>(Km, ar, s);
+            h->col_b = ar.make<double>(nb);
+            h->col_x = ar.make<double>(nb);
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        h->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = h.release();
+        return SCR_OK;
+    } catch (const Error& e) {
+        if (h) {
+            h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->cg.reset();
+            (void)hipStreamSynchronize(s);
+            h->ar.reset();
+            (void)hipStreamSynchronize(s);
+        }
+        return fail(e);
+    }
+}
+
+scr_status scr_handle_destroy(scr_handle* h) {
+    if (!h) return SCR_OK;
+    try {
+        hipStream_t s = h->ar ? h->ar->stream() : nullptr;
+        h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->cg.reset();
+        h->hA.reset(); h->hS.reset(); h->hL.reset();
+        h->ar.reset();
+        (void)hipStreamSynchronize(s);
+        delete h;
+        return SCR_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+int64_t scr_handle_bytes(const scr_handle* h) { return (h && h->ar) ? h->ar->bytes() : 0; }
+
+scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts, void* stream,
+                     scr_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!h || !b || !x) throw Error(SCR_E_INVALID, "NULL argument");
+        if (h->kind != SCR_SYSTEM) throw Error(SCR_E_INVALID, "scr_solve needs an SCR_SYSTEM handle");
+        HIPCHK(hipSetDevice(h->ctx->device));
+        scr_solve_opts o;
+        if (opts) o = *opts;
+        else scr_default_solve_opts(&o);
+        check_opts(o);
+        ensure_workspaces(h, o, s);
+        double setup_ms = h->st.t_setup_ms;
+        h->st = scr_stats{};
+        h->st.t_setup_ms = setup_ms;
+        h->so = o;
+        const int64_t nb = h->nb;
+        interleaved_to_split(nb, b, h->bs, s);
+        if (o.use_x0) interleaved_to_split(nb, x, h->xs, s);
+        KOp kop(&h->Ks);
+        ScrPrec prec(h);
+        KStat k = h->gOuter->solve(kop, prec, h->bs, h->xs, o.tol, o.max_it, o.use_x0 != 0, true, s);
+        split_to_interleaved(nb, h->xs, x, s);
+        HIPCHK(hipStreamSynchronize(s));
+        h->st.outer_it = (int)k.iters;
+        h->st.rel_res_true = k.rel_res;
+        h->st.converged = k.converged ? 1 : 0;
+        h->st.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        h->st.device_bytes = h->ar->bytes();
+        if (stats) *stats = h->st;
+        return k.converged ? SCR_OK : SCR_NOT_CONVERGED;
+    } catch (const Error& e) {
+        (void)hipStreamSynchronize(s);
+        if (stats && h) *stats = h->st;
+        return fail(e);
+    }
+}
+
+scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts, void* stream,
+                             scr_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!h || !b || !x) throw Error(SCR_E_INVALID, "NULL argument");
+        if (h->kind != MESH_SYSTEM) throw Error(SCR_E_INVALID, "mesh_motion_solve needs a MESH_SYSTEM handle");
+        HIPCHK(hipSetDevice(h->ctx->device));
+        scr_solve_opts o;
+        if (opts) o = *opts;
+        else scr_default_solve_opts(&o);
+        check_opts(o);
+        ensure_workspaces(h, o, s);
+        double setup_ms = h->st.t_setup_ms;
+        h->st = scr_stats{};
+        h->st.t_setup_ms = setup_ms;
+        const int64_t n = h->nb;
+        MatOp lop(&h->Ls);
+        VOp pl(h->hL.get(), &h->st.vcycles_L);
+        bool flexible = o.flexible_cg || h->opts.precision == SCR_MIXED;
+        bool ok = true;
+        for (int c = 0; c < 3; ++c) {
+            gather_col3(n, b, c, h->col_b, s);
+            KStat k = h->cg->solve(lop, pl, h->col_b, h->col_x, o.tol, o.max_it, flexible, s);
+            scatter_col3(n, h->col_x, c, x, s);
+            h->st.mesh_its[c] = k.iters;
+            h->st.mesh_rel[c] = k.rel_res;
+            ok &= k.converged;
+            if (k.iters > h->st.outer_it) h->st.outer_it = (int)k.iters;
+            if (k.rel_res > h->st.rel_res_true) h->st.rel_res_true = k.rel_res;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        h->st.converged = ok ? 1 : 0;
+        h->st.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        h->st.device_bytes = h->ar->bytes();
+        if (stats) *stats = h->st;
+        return ok ? SCR_OK : SCR_NOT_CONVERGED;
+    } catch (const Error& e) {
+        (void)hipStreamSynchronize(s);
+        if (stats && h) *stats = h->st;
+        return fail(e);
+    }
+}
+
+int64_t scr_footprint_estimate(int kind, int64_t n_brows, int64_t nnzb, const scr_amg_opts* amg,
+                               const scr_solve_opts* solve) {
+    scr_solve_opts so;
+    if (solve) so = *solve;
+    else scr_default_solve_opts(&so);
+    const double pad = 1.15;     // sliced-ELL padding
+    const double amgf = (amg && amg->precision == SCR_MIXED) ? 0.5 : 1.0;
+    double bytes;
+    if (kind == SCR_SYSTEM) {
+        double perblk = 132.0 + (76.0 + 28.0 + 28.0 + 12.0)          // K and its split (FP64 + indices)
+                        + pad * (132.0 + 76.0 + 28.0 + 28.0 + 12.0)  // solve-phase copies
+                        + 5.0 * 12.0 * 2.0;                          // S^ (about 5 entries per K block) and its copy
+        double hier = 3.0 * nnzb * (76.0 * 1.8 * (1.0 + amgf)) + 5.0 * nnzb * 12.0 * 2.0 * (1.0 + amgf);
+        double krylov = 8.0 * n_brows * (4.0 * (2 * so.restart + 1) + 3.0 * (2 * so.restart_inner + 1) +
+                                         1.0 * (2 * so.restart_inner + 1) + 24.0);
+        bytes = perblk * nnzb + hier + krylov + 64.0 * 1024 * 1024 + 8.0 * 1024 * 1024 * 2;
+    } else {
+        double hier = nnzb * 12.0 * 3.0 * (1.0 + amgf);
+        bytes = nnzb * 12.0 * (1.0 + pad) + hier + 8.0 * n_brows * 12.0 + 16.0 * 1024 * 1024;
+    }
+    return (int64_t)bytes;
+}
+
+// ---------------------------------------------------------------- inspection
+static Hierarchy* which_hier(scr_handle* h, int which) {
+    Hierarchy* H = which == 0 ? h->hA.get() : which == 1 ? h->hS.get() : which == 2 ? h->hL.get() : nullptr;
+    if (!H) throw Error(SCR_E_INVALID, "no such hierarchy on this handle");
+    return H;
+}
+
+scr_status scr_hier_levels(scr_handle* h, int which, int* nlev) {
+    try {
+        if (!h || !nlev) throw Error(SCR_E_INVALID, "NULL argument");
+        *nlev = (int)which_hier(h, which)->L.size();
+        return SCR_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+scr_status scr_hier_level_info(scr_handle* h, int which, int level, int64_t* info, double* lam) {
+    try {
+        if (!h || !info || !lam) throw Error(SCR_E_INVALID, "NULL argument");
+        Hierarchy* H = which_hier(h, which);
+        if (level < 0 || level >= (int)H->L.size()) throw Error(SCR_E_INVALID, "level out of range");
+        LevelSetup& L = H->L[level];
+        info[0] = L.A.nr; info[1] = L.b; info[2] = L.k; info[3] = L.A.nnzb; info[4] = L.nagg;
+        info[5] = L.P.nnzb; info[6] = L.R.nnzb; info[7] = H->ncoarse;
+        *lam = L.lam;
+        return SCR_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+scr_status scr_hier_level_copy(scr_handle* h, int which, int level, int field, void* dst) {
+    try {
+        if (!h || !dst) throw Error(SCR_E_INVALID, "NULL argument");
+        HIPCHK(hipSetDevice(h->ctx->device));
+        Hierarchy* H = which_hier(h, which);
+        if (level < 0 || level >= (int)H->L.size()) throw Error(SCR_E_INVALID, "level out of range");
+        LevelSetup& L = H->L[level];
+        const void* src = nullptr;
+        size_t bytes = 0;
+        auto mat = [&](const DBsr& M, int f) {
+            if (!M.rp) throw Error(SCR_E_INVALID, "level has no such matrix");
+            if (f == 0) { src = M.rp; bytes = (M.nr + 1) * sizeof(int32_t); }
+            else if (f == 1) { src = M.ci; bytes = M.nnzb * sizeof(int32_t); }
+            else { src = M.v; bytes = M.nnzb * M.br * M.bc * sizeof(double); }
+        };
+        switch (field) {
+            case 0: case 1: case 2: mat(L.A, field); break;
+            case 3: src = L.agg; bytes = L.A.nr * sizeof(int32_t); break;
+            case 4: case 5: case 6: mat(L.P, field - 4); break;
+            case 7: case 8: case 9: mat(L.R, field - 7); break;
+            case 10: src = L.strong; bytes = L.A.nnzb; break;
+            case 11: src = L.dead; bytes = L.nagg * L.k; break;
+            case 12: src = L.Dinv; bytes = L.A.nr * L.b * L.b * sizeof(double); break;
+            case 13: src = L.B; bytes = L.A.nr * L.b * L.k * sizeof(double); break;
+            default: throw Error(SCR_E_INVALID, "unknown field");
+        }
+        if (!src) throw Error(SCR_E_INVALID, "field not present on this level");
+        if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+        return SCR_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+scr_status scr_matrix_copy(scr_handle* h, int which, int field, void* dst, int64_t* info) {
+    try {
+        if (!h || !info) throw Error(SCR_E_INVALID, "NULL argument");
+        if (h->kind != SCR_SYSTEM) throw Error(SCR_E_INVALID, "not an SCR_SYSTEM handle");
+        HIPCHK(hipSetDevice(h->ctx->device));
+        const DBsr* M = which == 0 ? &h->A : which == 1 ? &h->G : which == 2 ? &h->D : which == 3 ? &h->C
+                        : which == 4 ? &h->Sh : nullptr;
+        if (!M) throw Error(SCR_E_INVALID, "unknown matrix");
+        info[0] = M->nr; info[1] = M->nnzb; info[2] = M->br; info[3] = M->bc;
+        if (!dst) return SCR_OK;
+        if (field == 0) HIPCHK(hipMemcpy(dst, M->rp, (M->nr + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        else if (field == 1) HIPCHK(hipMemcpy(dst, M->ci, M->nnzb * sizeof(int32_t), hipMemcpyDeviceToHost));
+        else HIPCHK(hipMemcpy(dst, M->v, M->nnzb * M->br * M->bc * sizeof(double), hipMemcpyDeviceToHost));
+        return SCR_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const scr_solve_opts* opts, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!h || !x || !y) throw Error(SCR_E_INVALID, "NULL argument");
+        HIPCHK(hipSetDevice(h->ctx->device));
+        scr_solve_opts o;
+        if (opts) o = *opts;
+        else scr_default_solve_opts(&o);
+        check_opts(o);
+        ensure_workspaces(h, o, s);
+        h->so = o;
+        bool scr = h->kind == SCR_SYSTEM;
+        if ((op <= 9) != scr) throw Error(SCR_E_INVALID, "operator not available on this handle kind");
+        switch (op) {
+            case 0: sell_mv_split4(h->Ks, x, nullptr, y, 0, s); break;
+            case 1: sell_mv<double>(h->As, x, nullptr, y, 0, s); break;
+            case 2: h->hA->vcycle(x, y, s); break;
+            case 3: h->hS->vcycle(x, y, s); break;
+            case 4: { SchurOp so(h); so.apply(x, y, s); break; }
+            case 5: { ScrPrec p(h); p.apply(x, y, s); break; }
+            case 6: sell_mv<double>(h->Gs, x, nullptr, y, 0, s); break;
+            case 7: sell_mv<double>(h->Ds, x, nullptr, y, 0, s); break;
+            case 8: sell_mv<double>(h->Cs, x, nullptr, y, 0, s); break;
+            case 9: {
+                DSell<double> S = sell_from_bsr<double>(h->Sh, *h->ar, s);
+                sell_mv<double>(S, x, nullptr, y, 0, s);
+                HIPCHK(hipStreamSynchronize(s));
+                sell_free(S, *h->ar);
+                break;
+            }
+            case 10: sell_mv<double>(h->Ls, x, nullptr, y, 0, s); break;
+            case 11: h->hL->vcycle(x, y, s); break;
+            default: throw Error(SCR_E_INVALID, "unknown operator");
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        return SCR_OK;
+    } catch (const Error& e) {
+        (void)hipStreamSynchronize(s);
+        return fail(e);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// solver.h -- Krylov drivers (krylov.hip), AMG hierarchies (amg.hip) and the handle (scr.hip).
+#pragma once
+#include <memory>
+
+#include "kernels.h"
+
+namespace scr {
+
+// A linear operator or preconditioner on FP64 device vectors.
+struct Op {
+    virtual void apply(const double* x, double* y, hipStream_t s) = 0;
+    virtual ~Op() = default;
+};
+
+struct KStat {
+    int64_t iters = 0;
+    double rel_res = 0.0;
+    bool converged = false;
+};
+
+// Deterministic FP64 reductions: a fixed grid per vector length, per-block partials summed in
+// block order by the last block to finish.
+struct Reducer {
+    int64_t n = 0;
+    int grid = 0;
+    double* partials = nullptr;      // grid * 64
+    unsigned* counter = nullptr;
+    double* out = nullptr;           // 64 results
+    void init(int64_t n_, Arena& ar, hipStream_t s);
+    void release(Arena& ar) {
+        ar.free(partials); ar.free(counter); ar.free(out);
+        partials = nullptr; counter = nullptr; out = nullptr;
+    }
+};
+
+// Right-preconditioned flexible GMRES(m) (Saad 1993) with CGS2 Arnoldi; the Hessenberg matrix,
+// Givens rotations and least-squares solve stay in device memory; the host reads one residual
+// estimate per iteration.
+class Gmres {
+   public:
+    Gmres(int64_t n, int m, Arena& ar, hipStream_t s);
+    ~Gmres();
+    KStat solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool use_x0, bool check_true,
+                hipStream_t s);
+    int64_t n() const { return n_; }
+
+   private:
+    int64_t n_;
+    int m_;
+    Arena* ar_;
+    double *V_, *Z_, *st_;
+    Reducer red_;
+    double* host_ = nullptr;         // pinned
+};
+
+// Preconditioned CG, or flexible CG with the Polak-Ribiere beta (Notay 2000).
+class Pcg {
+   public:
+    Pcg(int64_t n, Arena& ar, hipStream_t s);
+    ~Pcg();
+    KStat solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool flexible, hipStream_t s);
+
+   private:
+    int64_t n_;
+    Arena* ar_;
+    double *r_, *z_, *p_, *q_, *rold_, *st_;
+    Reducer red_;
+    double* host_ = nullptr;
+};
+
+double device_norm(const double* x, int64_t n, Reducer& red, double* host, hipStream_t s);
+
+// ---------------------------------------------------------------- AMG (amg.hip)
+struct LevelSetup {
+    DBsr A, P, R;
+    int b = 0, k = 0;
+    int64_t nagg = 0;
+    int32_t* agg = nullptr;
+    uint8_t* strong = nullptr;
+    uint8_t* dead = nullptr;
+    double* Dinv = nullptr;
+    double* B = nullptr;
+    double lam = 0.0;
+};
+
+class Hierarchy {
+   public:
+    virtual ~Hierarchy() = default;
+    // y = V-cycle(x), zero initial guess; FP64 in and out (cast at the boundary in MIXED).
+    virtual void vcycle(const double* x, double* y, hipStream_t s) = 0;
+    std::vector<LevelSetup> L;
+    double* cinv = nullptr;          // dense inverse of the coarsest matrix (FP64)
+    int64_t ncoarse = 0;
+    scr_amg_opts opts{};
+    int64_t vcycles = 0;
+    int64_t n0() const { return L.empty() ? 0 : L[0].A.nr * L[0].b; }
+};
+
+std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
+                                           hipStream_t s);
+
+// rigid-body modes (6 columns) of nb nodes from coordinates, shifted by their mean
+void rigid_modes(int64_t nb, const double* xyz, double* B, Arena& ar, hipStream_t s);
+
+// split K (4x4) into A (3x3), G (3x1), D (1x3), C (1x1) and build S^ = C - D diag(A)^-1 G
+void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, hipStream_t s);
+DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, Arena& ar, hipStream_t s);
+
+}  // namespace scr
