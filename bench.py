@@ -1,0 +1,294 @@
+"""Benchmark: SCR+AMG solves/s at a 1e-8 relative residual on the unified fluid+solid tube
+(lumen R=1 with 4 boundary-layer shells, wall 1.0-1.2, L=10; 41x41x179 = 300,899 nodes,
+323,811 block rows with the interface pressure rows, 5.05M 4x4 blocks) plus its mesh-motion solve.
+
+One step = one Newton corrector's linear work on the GPU:
+    amg_setup(SCR_SYSTEM)  (block split, S^, AMG(A), AMG(S^), sliced-ELL copies)
+  + scr_solve              (FGMRES(P_SCR) to ||b - Kx|| <= 1e-8 ||b||)
+  + mesh_motion_solve      (CG + AMG(L), 3 right-hand sides, tol 1e-8; the mesh hierarchy is
+                            built once before the timed region, as the paper's Sec. 5.2.2 does)
+Inputs are resident in HBM before the timed region.  Each step uses its own seeded RHS.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB elementwise copy (read 1 GiB, write 1 GiB) before the steps, "
+                         "as the calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/ and exit")
+    return ap.parse_args()
+
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KERNEL_SOURCES = ["paper_2206_06996_amd/csrc/sparse.hip", "paper_2206_06996_amd/csrc/amg.hip",
+                  "paper_2206_06996_amd/csrc/common.h"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "smooth_a0_cfg1_pmc.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic():
+    """HBM bytes per launch of the profiled kernel from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when the kernel
+    sources changed since the counters were taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    d = json.load(open(PMC_SUMMARY))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
+SMOOTH_KERNEL = "smooth_k<double, 3, true, false, false>"
+
+
+def _pmc_rows(d, counter):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") == counter:
+                rows.append(r)
+    return rows
+
+
+def pmc_summary(fetch_dir, write_dir):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the level-0 smoother kernel and of the
+    calibration copy; the copy's known 1 GiB read and 1 GiB write give the counter scale."""
+    out = {"kernel": SMOOTH_KERNEL, "source_hash": kernel_source_hash(), "workload": "cfg1 fp64, 1 step"}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _pmc_rows(d, counter)
+        sm = [float(r["Counter_Value"]) for r in rows if SMOOTH_KERNEL in r["Kernel_Name"]]
+        cp = [float(r["Counter_Value"]) for r in rows if "elementwise" in r["Kernel_Name"]
+              and float(r["Counter_Value"]) > 0.25 * COPY_BYTES / 1024]
+        if not sm or not cp:
+            raise SystemExit(f"no {counter} rows for the smoother or the copy in {d}")
+        scale = (COPY_BYTES / 1024.0) / float(np.median(cp))
+        out[counter] = {"smoother_kib_per_dispatch_median": float(np.median(sm)), "dispatches": len(sm),
+                        "copy_kib_per_dispatch_median": float(np.median(cp)), "copy_expected_kib": COPY_BYTES / 1024.0,
+                        "scale": scale, "smoother_bytes_scaled": float(np.median(sm)) * 1024.0 * scale}
+    out["traffic_bytes_per_launch"] = out["FETCH_SIZE"]["smoother_bytes_scaled"] + out["WRITE_SIZE"]["smoother_bytes_scaled"]
+    os.makedirs(os.path.dirname(PMC_SUMMARY), exist_ok=True)
+    with open(PMC_SUMMARY, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def cpu_baseline(s, b, bm, args):
+    """The FP64 oracle on a bounded sample of the same workload: its full AMG setup of the
+    SCR system and its full mesh-motion solve, run live, plus 3 V-cycles on AMG(A) and 3 on
+    AMG(S^), whose per-cycle times are multiplied by the V-cycle counts of the oracle's own full
+    solve of this workload (oracle/cfg1_reference.json, written by oracle/reference_run.py).
+    Krylov vector work and SpMVs of the solve are not counted, so the time is a lower bound
+    and the rate an upper bound for the oracle."""
+    ref_path = os.path.join(ROOT, "oracle", "cfg1_reference.json")
+    if not os.path.exists(ref_path):
+        return None
+    import oracle
+    ref = json.load(open(ref_path))
+    t0 = time.perf_counter()
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz)
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    tv = {}
+    for op, n in (("VA", 3 * s.n_b), ("VS", s.n_b)):
+        x = rng.uniform(-1, 1, n)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            o.apply(op, x)
+        tv[op] = (time.perf_counter() - t0) / 3
+    m = oracle.Mesh(s.Lrp, s.Lci, s.Lval)
+    t0 = time.perf_counter()
+    m.solve(bm, tol=1e-8)
+    t_mesh = time.perf_counter() - t0
+    st = ref["stats_1e-8"]
+    t_solve = st["vcycles_A"] * tv["VA"] + st["vcycles_S"] * tv["VS"]
+    total = t_setup + t_solve + t_mesh
+    log(f"[bench] oracle sample: setup {t_setup:.1f}s vcycle A {tv['VA']:.3f}s S {tv['VS']:.3f}s mesh {t_mesh:.1f}s "
+        f"-> step {total:.1f}s", args)
+    return {"value": round(1.0 / total, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"live: oracle AMG setup of the full cfg1 SCR system ({t_setup:.1f} s), full mesh-motion "
+                       f"solve ({t_mesh:.1f} s), 3 V-cycles each of AMG(A) ({tv['VA']:.3f} s) and AMG(S^) "
+                       f"({tv['VS']:.3f} s); solve time = the oracle's own full-solve V-cycle counts "
+                       f"({st['vcycles_A']} A, {st['vcycles_S']} S^) x live per-cycle times "
+                       f"(Krylov vector work excluded: a lower bound on oracle time); single-threaded"),
+            "step_s_estimate": round(total, 2)}
+
+
+def log(msg, args=None):
+    if not (args and args.quiet):
+        print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2206_06996_amd.scr as scr
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    t0 = time.time()
+    s = synth.generate(synth.cfg1_params())
+    log(f"[bench] cfg1 generated: n_b={s.n_b} nnzb={s.nnzb} nodes={s.n_phys} ({time.time() - t0:.1f}s)", args)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    rp, ci, val, xyz = dev(s.rp), dev(s.ci), dev(s.val.reshape(-1)), dev(s.xyz.reshape(-1))
+    Lrp, Lci, Lval = dev(s.Lrp), dev(s.Lci), dev(s.Lval)
+    nsteps = args.warmup + args.steps
+    B = [dev(synth.rhs(1000 + i, 4 * s.n_b, s.mask)) for i in range(nsteps)]
+    BM = [dev(synth.rhs(2000 + i, 3 * s.n_phys, np.repeat(s.Lmask, 3))) for i in range(nsteps)]
+    BM_host = synth.rhs(2000, 3 * s.n_phys, np.repeat(s.Lmask, 3))
+    x = torch.zeros(4 * s.n_b, dtype=torch.float64, device="cuda")
+    xm = torch.zeros(3 * s.n_phys, dtype=torch.float64, device="cuda")
+    ctx = scr.Context(0)
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    results = {}
+    for prec in precisions:
+        p = scr.SCR_MIXED if prec == "mixed" else scr.SCR_FP64
+        ao = scr.amg_opts(precision=p)
+        so = scr.solve_opts()
+        hm = scr.amg_setup(ctx, scr.MESH_SYSTEM, Lrp, Lci, Lval, None, ao)
+        lat, setup_ms, solve_ms, mesh_ms, destroy_ms, stats = [], [], [], [], [], []
+        region = None
+        for i in range(nsteps):
+            if i == args.warmup:
+                if not args.no_roofline:
+                    ctx.profile(scr.SCR_PROF_SMOOTH_A0)
+                    ctx.profile_read()
+                torch.cuda.synchronize()
+                region = time.perf_counter()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            h = scr.amg_setup(ctx, scr.SCR_SYSTEM, rp, ci, val, xyz, ao)
+            t1 = time.perf_counter()
+            rc, st = scr.scr_solve(h, B[i], x, so)
+            t2 = time.perf_counter()
+            rcm, stm = scr.mesh_motion_solve(hm, BM[i], xm, so)
+            t3 = time.perf_counter()
+            h.destroy()
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            if rc != 0 or rcm != 0:
+                raise RuntimeError(f"step {i} {prec}: not converged (scr {rc}, mesh {rcm})")
+            if i >= args.warmup:
+                lat.append(te - ts); setup_ms.append((t1 - ts) * 1e3); solve_ms.append((t2 - t1) * 1e3)
+                mesh_ms.append((t3 - t2) * 1e3); destroy_ms.append((te - t3) * 1e3)
+                stats.append((st, stm))
+            log(f"[bench] {prec} step {i}: setup {1e3 * (t1 - ts):.1f} ms solve {1e3 * (t2 - t1):.1f} ms "
+                f"mesh {1e3 * (t3 - t2):.1f} ms free {1e3 * (te - t3):.1f} ms outer={st['outer_it']} its_A={st['its_A']} its_S={st['its_S']} "
+                f"its_I={st['its_I']} vA={st['vcycles_A']} rel={st['rel_res_true']:.2e} mesh_its={stm['mesh_its']}",
+                args)
+        torch.cuda.synchronize()
+        region = time.perf_counter() - region
+        hm.destroy()
+        prof = None
+        if not args.no_roofline:
+            n, ms, by = ctx.profile_read()
+            ctx.profile(scr.SCR_PROF_OFF)
+            if n:
+                prof = dict(launches=n, avg_us=1e3 * ms / n, bytes_per_launch=by / n, gbs=(by / n) / (ms / n * 1e-3) / 1e9)
+        results[prec] = dict(lat=lat, setup=setup_ms, solve=solve_ms, mesh=mesh_ms, destroy=destroy_ms, stats=stats, prof=prof,
+                             region=region)
+    main_prec = "fp64" if "fp64" in results else precisions[0]
+    r = results[main_prec]
+    total = r["region"]
+    value = len(r["lat"]) / total
+    out = {
+        "metric": "SCR+AMG solves/s at 1e-8 rel. resid (FP64 vs mixed); p50/p99 solve latency",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / len(r["lat"]), 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_prec == "fp64" else "f32/f64",
+        "data": "synthetic (seeded tube mesh, seeded RHS)",
+        "config": {"workload": "cfg1 unified fluid+solid tube 41x41x179 (300,899 nodes, 323,811 block rows, "
+                               "5,051,767 4x4 blocks) + mesh motion (300,899 x 3)",
+                   "precision": main_prec, "tol": 1e-8},
+    }
+    for prec, rr in results.items():
+        lat = np.array(rr["lat"]) * 1e3
+        st = [a for a, _ in rr["stats"]]
+        out[prec] = {
+            "solves_per_s": round(len(lat) / rr["region"], 4),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "setup_ms": round(float(np.median(rr["setup"])), 2),
+            "scr_solve_ms": round(float(np.median(rr["solve"])), 2),
+            "mesh_solve_ms": round(float(np.median(rr["mesh"])), 2),
+            "handle_free_ms": round(float(np.median(rr["destroy"])), 2),
+            "outer_it": int(np.median([a["outer_it"] for a in st])),
+            "its_A": int(np.median([a["its_A"] for a in st])),
+            "its_S": int(np.median([a["its_S"] for a in st])),
+            "its_I": int(np.median([a["its_I"] for a in st])),
+            "vcycles_A": int(np.median([a["vcycles_A"] for a in st])),
+            "max_rel_res": float(max(a["rel_res_true"] for a in st)),
+        }
+        if rr["prof"]:
+            out[prec]["smoother_l0_avg_us"] = round(rr["prof"]["avg_us"], 2)
+            out[prec]["smoother_l0_GBps"] = round(rr["prof"]["gbs"], 1)
+    pr = r["prof"]
+    if pr:
+        traffic = pmc_traffic() if main_prec == "fp64" else None
+        out["roofline"] = {"bound": "hbm", "achieved": round(pr["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(pr["gbs"] / HBM_PEAK_GBS, 4),
+                           "traffic": None if traffic is None else round(traffic / (pr["avg_us"] * 1e-6) / 1e9, 1),
+                           "traffic_bytes_per_launch": traffic,
+                           "kernel": "smooth_k: fused Chebyshev step on level 0 of AMG(A) (3x3 FP64 blocks)",
+                           "launches": pr["launches"], "avg_us": round(pr["avg_us"], 2),
+                           "alg_bytes_per_launch": int(pr["bytes_per_launch"])}
+    else:
+        out["roofline"] = None
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(s, None, BM_host, args)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,17 @@ scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const sc
 scr_status scr_handle_destroy(scr_handle* h);
 int64_t scr_handle_bytes(const scr_handle* h);
 
+/* Opt-in kernel timing (roofline measurement).  After scr_ctx_profile(ctx, kernel), every launch
+ * of that kernel family on handles created from ctx afterwards is bracketed by HIP events on the
+ * stream it runs on; scr_ctx_profile_read returns the number of launches, their summed duration
+ * (ms) and the summed algorithmic bytes (each matrix and vector byte the kernel must move, once)
+ * and resets the counters.  SCR_PROF_SMOOTH_A0: the fused smoother steps (with a matrix
+ * product) on level 0 of AMG(A).  Costs two event records per launch; off by default. */
+typedef enum { SCR_PROF_OFF = 0, SCR_PROF_SMOOTH_A0 = 1 } scr_prof_kernel;
+scr_status scr_ctx_profile(scr_ctx* ctx, int kernel);
+scr_status scr_ctx_profile_read(scr_ctx* ctx, int64_t* launches /* host */, double* total_ms /* host */,
+                                double* bytes /* host */);
+
 /* Upper bound of the device memory a handle of this size will hold (host-side model, used
  * for admission control). */
 int64_t scr_footprint_estimate(int kind, int64_t n_brows, int64_t nnzb, const scr_amg_opts* amg,

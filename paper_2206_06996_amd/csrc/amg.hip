@@ -78,33 +78,43 @@ void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, 
 }
 
 // ====================================================================== generic SpGEMM (one wave per row)
-constexpr int HS = 8192;           // LDS hash slots per row
-constexpr int HMAX = HS / 2;       // unique columns allowed per row
+constexpr int HS_MAX = 8192;       // largest LDS hash table per row
+constexpr int HMAX = HS_MAX / 2;   // unique columns allowed per row
 
-__device__ __forceinline__ void hash_clear(int* t) {
-    for (int i = threadIdx.x; i < HS; i += WAVE) t[i] = -1;
-}
-// returns 1 if newly inserted
-__device__ __forceinline__ int hash_insert(int* t, int key) {
-    unsigned h = ((unsigned)key * 2654435761u) & (HS - 1);
+// returns 1 if newly inserted (table of hs slots, hs a power of two, never more than half full)
+__device__ __forceinline__ int hash_insert(int* t, int hs, int key) {
+    unsigned h = ((unsigned)key * 2654435761u) & (unsigned)(hs - 1);
     for (;;) {
         int prev = atomicCAS(&t[h], -1, key);
         if (prev == -1) return 1;
         if (prev == key) return 0;
-        h = (h + 1) & (HS - 1);
+        h = (h + 1) & (unsigned)(hs - 1);
     }
 }
 
-// count (phase 0) or emit sorted (phase 1) the structural pattern of row i of X*Y
+// upper bound of the candidates of each row of X*Y (sum of the lengths of the Y rows it meets)
+__global__ void spg_bound_k(int64_t nr, const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci,
+                            const int32_t* __restrict__ yrp, int* __restrict__ maxub) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int64_t ub = 0;
+    for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) ub += yrp[xci[q] + 1] - yrp[xci[q]];
+    atomicMax(maxub, (int)(ub < (1 << 30) ? ub : (1 << 30)));
+}
+
+// count (phase 0) or emit sorted (phase 1) the structural pattern of row i of X*Y.
+// Dynamic LDS: hs hash slots, then hs/2 + 64 list entries.
 template <int PHASE>
-__global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci,
-                                                     const int32_t* __restrict__ yrp, const int32_t* __restrict__ yci,
-                                                     const uint8_t* __restrict__ rowmask, int32_t* __restrict__ cnt,
-                                                     const int32_t* __restrict__ crp, int32_t* __restrict__ cci,
-                                                     int* __restrict__ overflow) {
-    __shared__ int table[HS];
+__global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const int32_t* __restrict__ xrp,
+                                                     const int32_t* __restrict__ xci, const int32_t* __restrict__ yrp,
+                                                     const int32_t* __restrict__ yci, const uint8_t* __restrict__ rowmask,
+                                                     int32_t* __restrict__ cnt, const int32_t* __restrict__ crp,
+                                                     int32_t* __restrict__ cci, int* __restrict__ overflow) {
+    extern __shared__ int smem[];
+    int* table = smem;
+    int* list = smem + hs;
     __shared__ int nuniq;
-    __shared__ int list[HMAX + WAVE];
+    const int hmax = hs / 2;
     int64_t i = blockIdx.x;
     if (i >= nr) return;
     int lane = threadIdx.x;
@@ -112,23 +122,23 @@ __global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, const int32_t* 
         if (PHASE == 0 && lane == 0) cnt[i] = 0;
         return;
     }
-    hash_clear(table);
+    for (int t = lane; t < hs; t += WAVE) table[t] = -1;
     if (lane == 0) nuniq = 0;
     __syncthreads();
     for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) {
         int32_t k = xci[q];
         for (int32_t t = yrp[k] + lane; t < yrp[k + 1]; t += WAVE) {
-            if (nuniq >= HMAX) break;
+            if (nuniq >= hmax) break;
             int c = yci[t];
-            if (hash_insert(table, c)) {
+            if (hash_insert(table, hs, c)) {
                 int pos = atomicAdd(&nuniq, 1);
-                if (pos < HMAX + WAVE) list[pos] = c;
+                if (pos < hmax + WAVE) list[pos] = c;
             }
         }
         __syncthreads();
     }
     int w = nuniq;
-    if (w >= HMAX) {
+    if (w >= hmax) {
         if (lane == 0) atomicOr(overflow, 1);
         return;
     }
@@ -182,23 +192,30 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
     C.nr = X.nr; C.nc = Y.nc; C.br = X.br; C.bc = Y.bc;
     C.rp = ar.make<int32_t>(X.nr + 1);
     int32_t* cnt = ar.make<int32_t>(X.nr + 1);
-    int* ovf = ar.make<int>(1);
-    HIPCHK(hipMemsetAsync(ovf, 0, sizeof(int), s));
+    int* flags = ar.make<int>(2);      // [overflow, max candidate bound]
+    HIPCHK(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
+    if (X.nr > 0) spg_bound_k<<<cdiv(X.nr, 256), 256, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, flags + 1);
+    int hflags[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int need = 2 * (hflags[1] < HMAX ? hflags[1] : HMAX) + 2;
+    int hs = 64;
+    while (hs < need && hs < HS_MAX) hs <<= 1;
+    size_t lds = (size_t)(hs + hs / 2 + WAVE) * sizeof(int);
     if (X.nr > 0)
-        spg_symbolic<0><<<X.nr, WAVE, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr, ovf);
+        spg_symbolic<0><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr, flags);
     check_launch("spg_count");
     C.nnzb = scan_i32(cnt, C.rp, X.nr, ar, s);
-    int hovf = 0;
-    HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hovf) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
+    if (hflags[0]) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
     ar.free(cnt);
     C.ci = ar.make<int32_t>(C.nnzb > 0 ? C.nnzb : 1);
     C.v = ar.make<double>((C.nnzb > 0 ? C.nnzb : 1) * C.br * C.bc);
     if (X.nr > 0)
-        spg_symbolic<1><<<X.nr, WAVE, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, ovf);
+        spg_symbolic<1><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, flags);
     check_launch("spg_fill");
-    ar.free(ovf);
+    ar.free(flags);
     int64_t nb = cdiv(X.nr, 4);
     int key = X.br * 100 + X.bc * 10 + Y.bc;
 #define SPN(m, n, p) spg_numeric<m, n, p><<<nb, 256, 0, s>>>(X.nr, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v)
@@ -720,6 +737,7 @@ class HierT : public Hierarchy {
     };
     std::vector<LS> S;
     Arena* ar = nullptr;
+    Profiler* prof = nullptr;
 
     void prepare(Arena& a, hipStream_t s) {
         ar = &a;
@@ -757,14 +775,26 @@ class HierT : public Hierarchy {
         }
     }
 
+    // algorithmic bytes of one smoother step with a matrix product: every stored block (values
+    // and column index) once, x once, the right-hand side, D^-1, the output and d as used
+    double step_bytes(const LS& q, bool rd, bool wd) const {
+        const double b = q.A.br, t = sizeof(T);
+        double rows = (double)q.A.nr;
+        return (double)q.A.nnzb * (b * b * t + 4.0) + rows * (b * t * 3.0 + b * b * t + (rd ? b * t : 0.0) + (wd ? b * t : 0.0));
+    }
+
     // smoothing sweeps from xin (nullptr = zero) into dst
-    void smooth(LS& q, const T* b, const T* xin, T* dst, hipStream_t s) {
+    void smooth(size_t l, LS& q, const T* b, const T* xin, T* dst, hipStream_t s) {
         int ns = (int)q.c1.size();
         const T* cur = xin;
         for (int t = 0; t < ns; ++t) {
             T* out = (t == ns - 1) ? dst : ((t % 2 == 0) ? q.t1 : q.t2);
-            smooth_step<T>(q.A, q.Dinv, b, cur, q.d, out, q.c1[t], q.c2[t], q.cheb && t > 0, q.cheb && t + 1 < ns,
-                           cur == nullptr, s);
+            bool rd = q.cheb && t > 0, wd = q.cheb && t + 1 < ns, zero = cur == nullptr;
+            bool timed = prof && l == 0 && !zero;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) { e0 = prof->get(); e1 = prof->get(); HIPCHK(hipEventRecord(e0, s)); }
+            smooth_step<T>(q.A, q.Dinv, b, cur, q.d, out, q.c1[t], q.c2[t], rd, wd, zero, s);
+            if (timed) { HIPCHK(hipEventRecord(e1, s)); prof->push(e0, e1, step_bytes(q, rd, wd)); }
             cur = out;
         }
     }
@@ -775,12 +805,12 @@ class HierT : public Hierarchy {
             return;
         }
         LS& q = S[l];
-        smooth(q, b, nullptr, q.w, s);
+        smooth(l, q, b, nullptr, q.w, s);
         sell_mv<T>(q.A, q.w, b, q.r, 1, s);
         bsrt_mv<T>(q.R, q.r, S[l + 1].b, s);
         cycle(l + 1, S[l + 1].b, S[l + 1].x, s);
         sell_mv<T>(q.P, S[l + 1].x, nullptr, q.w, 2, s);
-        smooth(q, b, q.w, x, s);
+        smooth(l, q, b, q.w, x, s);
     }
 
     void vcycle(const double* x, double* y, hipStream_t s) override {
@@ -810,12 +840,12 @@ static int64_t read_i32(const int32_t* p, hipStream_t s) {
 }
 
 std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
-                                           hipStream_t s) {
+                                           hipStream_t s, Profiler* prof) {
     std::unique_ptr<Hierarchy> H;
     HierT<double>* hd = nullptr;
     HierT<float>* hf = nullptr;
-    if (o.precision == SCR_MIXED) { hf = new HierT<float>(); H.reset(hf); }
-    else { hd = new HierT<double>(); H.reset(hd); }
+    if (o.precision == SCR_MIXED) { hf = new HierT<float>(); hf->prof = prof; H.reset(hf); }
+    else { hd = new HierT<double>(); hd->prof = prof; H.reset(hd); }
     H->opts = o;
     int* err = ar.make<int>(1);
     unsigned long long* lamd = ar.make<unsigned long long>(1);

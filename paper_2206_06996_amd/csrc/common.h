@@ -39,11 +39,85 @@ inline void check_launch(const char* what) {
 }
 
 // ---------------------------------------------------------------- device memory accounting
+// Event-pair timing of one kernel family (opt-in, for the roofline measurement).
+struct Profiler {
+    std::atomic<int> kernel{0};
+    std::mutex mu;
+    struct Pending { hipEvent_t a, b; double bytes; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+    hipEvent_t get() {
+        std::lock_guard<std::mutex> g(mu);
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+        return e;
+    }
+    void push(hipEvent_t a, hipEvent_t b, double by) {
+        std::lock_guard<std::mutex> g(mu);
+        pending.push_back({a, b, by});
+    }
+    // fold completed pairs into the totals (callers have synchronised the streams)
+    void harvest() {
+        std::lock_guard<std::mutex> g(mu);
+        std::vector<Pending> keep;
+        for (auto& p : pending) {
+            float t = 0.f;
+            if (hipEventQuery(p.b) != hipSuccess) { keep.push_back(p); continue; }
+            if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) { ms += t; bytes += p.bytes; ++launches; }
+            pool.push_back(p.a); pool.push_back(p.b);
+        }
+        pending.swap(keep);
+        (void)hipGetLastError();
+    }
+};
+
+// Pinned, device-mapped host slots (16 doubles each) through which single-block finishing
+// kernels publish Krylov status (residual estimates, flags) with a sequence number the host
+// spins on; shared by all handles of a context (handles are created and destroyed per Newton
+// corrector, and pinned allocation and release are synchronous and slow).
+struct PinnedPool {
+    std::mutex mu;
+    std::vector<double*> free_;
+    std::vector<void*> chunks;
+    double* get() {
+        std::lock_guard<std::mutex> g(mu);
+        if (free_.empty()) {
+            void* c = nullptr;
+            if (hipHostMalloc(&c, 64 * 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+                throw std::runtime_error("hipHostMalloc failed");
+            std::memset(c, 0, 64 * 16 * sizeof(double));
+            chunks.push_back(c);
+            for (int i = 0; i < 64; ++i) free_.push_back(static_cast<double*>(c) + 16 * i);
+        }
+        double* p = free_.back();
+        free_.pop_back();
+        return p;
+    }
+    // device address of a slot
+    static double* device_ptr(double* h) {
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) throw std::runtime_error("hipHostGetDevicePointer failed");
+        return static_cast<double*>(d);
+    }
+    void put(double* p) {
+        std::lock_guard<std::mutex> g(mu);
+        free_.push_back(p);
+    }
+    ~PinnedPool() {
+        for (void* c : chunks) (void)hipHostFree(c);
+    }
+};
+
 struct Ctx {
     int device = 0;
     int64_t budget = 0;
     std::atomic<int64_t> in_use{0};
     int cu_count = 256;
+    Profiler prof;
+    PinnedPool pinned;
 };
 
 // Every allocation of a handle goes through an Arena: stream-ordered, counted against the
@@ -95,6 +169,7 @@ class Arena {
     }
     int64_t bytes() const { return bytes_; }
     hipStream_t stream() const { return stream_; }
+    Ctx* ctx() const { return ctx_; }
 
    private:
     struct A { void* p; size_t n; };
@@ -115,20 +190,29 @@ struct DBsr {
     double* v = nullptr;
 };
 
-// Sliced ELL with 64-row slices (one wavefront per slice, one lane per block row).  Within a
-// slice, slot t of every row is stored lane-contiguously, and each block entry e of that slot
-// is a 64-wide contiguous vector: loads are fully coalesced and need no cross-lane reduction.
-//   col of (slice s, slot t, lane l):   ci[(off[s] + t) * 64 + l]
-//   entry e of that block:              v[((off[s] + t) * br*bc + e) * 64 + l]
-// Short rows are padded with zero blocks whose column is a valid index.
+// Sliced ELL with one lane per SCALAR row.  A slice is one wavefront covering rps = 64/br block
+// rows (lanes = rps*br; the rest idle), so the br lanes of a block row share a wavefront.  Lane
+// (block row i, row r) reads, for every slot t of the slice, the column block index of block row
+// i (stored once per block row) and row r of that block (bc values); each of the bc entries of a
+// slot is a 64-wide contiguous vector, so every load is fully coalesced and no cross-lane sum
+// is needed.
+//   col of (slice s, slot t, block row j of the slice):   ci[(off[s] + t) * rps + j]
+//   entry k of lane l's row segment:                       v[((off[s] + t) * bc + k) * 64 + l]
+// Rows shorter than the slice are padded with zero entries pointing at a valid column.  Within
+// windows of SELL_SIGMA slices, block rows are ordered by decreasing length (ties by index) so
+// that rows of similar length share a slice; rowid maps slice positions back to block rows
+// (-1 = empty position).
+constexpr int SELL_SIGMA = 16;
 template <typename T>
 struct DSell {
     int64_t nr = 0, nc = 0;
     int br = 0, bc = 0;
+    int rps = 0;                // block rows per slice
     int64_t nslices = 0;
     int64_t slots = 0;          // sum over slices of the slice length
     int64_t nnzb = 0;           // stored blocks before padding (algorithmic count)
     int32_t* off = nullptr;     // nslices + 1 (slot offsets)
+    int32_t* rowid = nullptr;   // nslices * rps
     int32_t* ci = nullptr;
     T* v = nullptr;
 };

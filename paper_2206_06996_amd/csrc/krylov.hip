@@ -3,6 +3,8 @@
 // rotations, and (flexible) preconditioned CG.  Every reduction uses a grid fixed by the
 // vector length and sums per-block partials in block order, so results are bitwise
 // reproducible run to run.
+#include <immintrin.h>
+
 #include <cmath>
 
 #include "solver.h"
@@ -63,7 +65,7 @@ void scatter_col3(int64_t n, const double* y, int c, double* a, hipStream_t s) {
 // ------------------------------------------------------------------ reduction machinery
 void Reducer::init(int64_t n_, Arena& ar, hipStream_t s) {
     n = n_;
-    int64_t g = cdiv(n, 2 * RTPB);
+    int64_t g = cdiv(n, 4 * RTPB);
     grid = (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
     partials = ar.make<double>((size_t)grid * RMAXJ);
     counter = ar.make<unsigned>(1);
@@ -90,43 +92,89 @@ __device__ __forceinline__ void block_partials(const double (&acc)[J], int jn, d
     }
 }
 
-__device__ __forceinline__ bool last_block(unsigned* counter) {
-    __shared__ int last;
-    __threadfence();
+// Final sum of the per-block partials (j < jn) by one block launched after the partials kernel:
+// thread t adds blocks t, t + 256, ... in order, then a fixed shuffle/LDS tree.  Deterministic
+// for a fixed grid; the kernel boundary makes every block's partials visible (no fences).
+template <int J>
+__device__ __forceinline__ void final_sums(const double* __restrict__ partials, int nblk, int jn,
+                                           double* __restrict__ out) {
+    __shared__ double red[RTPB / WAVE][J];
+    double acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RTPB) {
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (j < jn) acc[j] += partials[(int64_t)b * RMAXJ + j];
+    }
+    int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        if (j < jn) {
+            double v = wave_sum(acc[j]);
+            if (lane == 0) red[w][j] = v;
+        }
     __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
-}
-
-// sum of the partials in block order, for j < jn, into out[j]; thread-parallel over j
-__device__ __forceinline__ void final_sums(const double* __restrict__ partials, int jn, double* __restrict__ out) {
-    for (int j = threadIdx.x; j < jn; j += blockDim.x) {
+    for (int j = threadIdx.x; j < jn; j += RTPB) {
         double t = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) t += partials[(int64_t)b * RMAXJ + j];
+#pragma unroll
+        for (int q = 0; q < RTPB / WAVE; ++q) t += red[q][j];
         out[j] = t;
     }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ plain dot
-__global__ void __launch_bounds__(RTPB) dot_k(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
-                                              double* __restrict__ partials, unsigned* counter, double* __restrict__ out) {
+__global__ void __launch_bounds__(RTPB) dot_part_k(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                                   double* __restrict__ partials) {
     double acc[1] = {0.0};
     for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) acc[0] += x[i] * y[i];
     block_partials<1>(acc, 1, partials);
-    if (last_block(counter)) {
-        final_sums(partials, 1, out);
-        if (threadIdx.x == 0) *counter = 0;
+}
+template <int J>
+__global__ void __launch_bounds__(RTPB) sum_k(const double* __restrict__ partials, int nblk, int jn, double* __restrict__ out) {
+    final_sums<J>(partials, nblk, jn, out);
+}
+
+// thread 0 of a finishing kernel: copy n status values to the host slot, then the sequence
+// number (system-scope fence in between, so the host never sees the number before the values)
+__device__ __forceinline__ void publish(double* __restrict__ hslot, const double* __restrict__ vals, int n, double seq) {
+    for (int i = 0; i < n; ++i) hslot[i] = vals[i];
+    __threadfence_system();
+    *(volatile double*)(hslot + 15) = seq;
+}
+
+void StatusSlot::wait(hipStream_t s) const {
+    volatile double* flag = h + 15;
+    for (uint64_t it = 0;; ++it) {
+        if (*flag == seq) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return;
+        }
+        if ((it & 4095) == 4095) {
+            hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (*flag == seq) continue;
+                throw Error(SCR_E_HIP, "Krylov status was not published");
+            }
+            if (e != hipErrorNotReady) throw Error(SCR_E_HIP, std::string("stream error: ") + hipGetErrorString(e));
+        }
+        _mm_pause();
     }
 }
 
-double device_norm(const double* x, int64_t n, Reducer& red, double* host, hipStream_t s) {
-    dot_k<<<red.grid, RTPB, 0, s>>>(n, x, x, red.partials, red.counter, red.out);
+__global__ void __launch_bounds__(RTPB) sum_pub_k(const double* __restrict__ partials, int nblk, double* __restrict__ out,
+                                                  double* __restrict__ hslot, double seq) {
+    final_sums<1>(partials, nblk, 1, out);
+    if (threadIdx.x == 0) publish(hslot, out, 1, seq);
+}
+
+double device_norm(const double* x, int64_t n, Reducer& red, StatusSlot& slot, hipStream_t s) {
+    dot_part_k<<<red.grid, RTPB, 0, s>>>(n, x, x, red.partials);
+    sum_pub_k<<<1, RTPB, 0, s>>>(red.partials, red.grid, red.out, slot.d, slot.next());
     check_launch("dot");
-    HIPCHK(hipMemcpyAsync(host, red.out, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return std::sqrt(host[0]);
+    slot.wait(s);
+    return std::sqrt(slot.h[0]);
 }
 
 // ------------------------------------------------------------------ GMRES kernels
@@ -145,28 +193,23 @@ struct GLay {
 };
 enum { S_BETA = 0, S_EST = 1, S_HN = 2, S_INV = 3, S_FLAG = 4 };
 
-// beta = ||v||; g = [beta, 0, ...]; inv = 1/beta
-__global__ void __launch_bounds__(RTPB) gm_init_k(int64_t n, const double* __restrict__ v, double* __restrict__ partials,
-                                                  unsigned* counter, double* __restrict__ st, int m) {
+// beta = ||v|| (from the partials of v.v); g = [beta, 0, ...]; inv = 1/beta
+__global__ void __launch_bounds__(RTPB) gm_init_fin_k(const double* __restrict__ partials, int nblk,
+                                                      double* __restrict__ st, int m, double* __restrict__ hslot,
+                                                      double seq) {
     GLay L{m};
-    double acc[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) acc[0] += v[i] * v[i];
-    block_partials<1>(acc, 1, partials);
-    if (last_block(counter)) {
-        final_sums(partials, 1, st + L.scal() + S_HN);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double beta = sqrt(st[L.scal() + S_HN]);
-            double* sc = st + L.scal();
-            sc[S_BETA] = beta;
-            sc[S_EST] = beta;
-            sc[S_INV] = beta > 0.0 ? 1.0 / beta : 0.0;
-            sc[S_FLAG] = isfinite(beta) ? 0.0 : 1.0;
-            double* g = st + L.g();
-            g[0] = beta;
-            for (int i = 1; i <= m; ++i) g[i] = 0.0;
-            *counter = 0;
-        }
+    double* sc = st + L.scal();
+    final_sums<1>(partials, nblk, 1, sc + S_HN);
+    if (threadIdx.x == 0) {
+        double beta = sqrt(sc[S_HN]);
+        sc[S_BETA] = beta;
+        sc[S_EST] = beta;
+        sc[S_INV] = beta > 0.0 ? 1.0 / beta : 0.0;
+        sc[S_FLAG] = isfinite(beta) ? 0.0 : 1.0;
+        double* g = st + L.g();
+        g[0] = beta;
+        for (int i = 1; i <= m; ++i) g[i] = 0.0;
+        publish(hslot, sc, 8, seq);
     }
 }
 
@@ -176,11 +219,10 @@ __global__ void scale_by_k(int64_t n, double* __restrict__ v, const double* __re
     if (i < n) v[i] *= f;
 }
 
-// out[i] = V_i . w  (i < jn)
+// partials of V_i . w  (i < jn)
 template <int J>
 __global__ void __launch_bounds__(RTPB) mdot_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
-                                               const double* __restrict__ w, double* __restrict__ partials, unsigned* counter,
-                                               double* __restrict__ out) {
+                                               const double* __restrict__ w, double* __restrict__ partials) {
     double acc[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) acc[j] = 0.0;
@@ -191,17 +233,13 @@ __global__ void __launch_bounds__(RTPB) mdot_k(int64_t n, int jn, const double* 
             if (j < jn) acc[j] += V[j * ld + e] * we;
     }
     block_partials<J>(acc, jn, partials);
-    if (last_block(counter)) {
-        final_sums(partials, jn, out);
-        if (threadIdx.x == 0) *counter = 0;
-    }
 }
 
-// w -= sum_i h_i V_i ;  out[i] = V_i . w
+// w -= sum_i h_i V_i ;  partials of V_i . w
 template <int J>
 __global__ void __launch_bounds__(RTPB) upd_dot_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
                                                   double* __restrict__ w, const double* __restrict__ h,
-                                                  double* __restrict__ partials, unsigned* counter, double* __restrict__ out) {
+                                                  double* __restrict__ partials) {
     __shared__ double hs[J];
     for (int j = threadIdx.x; j < jn; j += RTPB) hs[j] = h[j];
     __syncthreads();
@@ -223,21 +261,14 @@ __global__ void __launch_bounds__(RTPB) upd_dot_k(int64_t n, int jn, const doubl
             if (j < jn) acc[j] += v[j] * we;
     }
     block_partials<J>(acc, jn, partials);
-    if (last_block(counter)) {
-        final_sums(partials, jn, out);
-        if (threadIdx.x == 0) *counter = 0;
-    }
 }
 
-// w -= sum_i h2_i V_i ; ||w||^2 ; then (one thread) the Arnoldi column j: H[:,j] = h1 + h2,
-// H[j+1,j] = ||w||, previous rotations, new rotation, g update, estimate |g[j+1]|.
+// w -= sum_i h2_i V_i ; partials of ||w||^2
 template <int J>
-__global__ void __launch_bounds__(RTPB) upd_norm_finish_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
-                                                          double* __restrict__ w, double* __restrict__ partials,
-                                                          unsigned* counter, double* __restrict__ st, int m, int j) {
-    GLay L{m};
+__global__ void __launch_bounds__(RTPB) upd_norm_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
+                                                   double* __restrict__ w, const double* __restrict__ h2,
+                                                   double* __restrict__ partials) {
     __shared__ double hs[J];
-    const double* h2 = st + L.h2();
     for (int t = threadIdx.x; t < jn; t += RTPB) hs[t] = h2[t];
     __syncthreads();
     double acc[1] = {0.0};
@@ -250,39 +281,44 @@ __global__ void __launch_bounds__(RTPB) upd_norm_finish_k(int64_t n, int jn, con
         acc[0] += we * we;
     }
     block_partials<1>(acc, 1, partials);
-    if (last_block(counter)) {
-        double* sc = st + L.scal();
-        final_sums(partials, 1, sc + S_HN);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double* H = st + L.H();
-            double* cs = st + L.cs();
-            double* sn = st + L.sn();
-            double* g = st + L.g();
-            const double* h1 = st + L.h1();
-            double hn = sqrt(sc[S_HN]);
-            for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
-            H[(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                double a = H[i * m + j], c = H[(i + 1) * m + j];
-                H[i * m + j] = cs[i] * a + sn[i] * c;
-                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-            }
-            double a = H[j * m + j], c = H[(j + 1) * m + j];
-            double rr = sqrt(a * a + c * c);
-            cs[j] = rr == 0.0 ? 1.0 : a / rr;
-            sn[j] = rr == 0.0 ? 0.0 : c / rr;
-            H[j * m + j] = rr;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            sc[S_HN] = hn;
-            sc[S_EST] = fabs(g[j + 1]);
-            sc[S_INV] = hn > 0.0 ? 1.0 / hn : 0.0;
-            sc[S_FLAG] = (isfinite(hn) && isfinite(sc[S_EST]) && isfinite(rr)) ? 0.0 : 1.0;
-            *counter = 0;
-        }
+}
+
+// Arnoldi column j (one block): ||w||, H[:,j] = h1 + h2, H[j+1,j] = ||w||, previous rotations,
+// new rotation, g update, estimate |g[j+1]|, 1/||w|| for the normalisation.
+__global__ void __launch_bounds__(RTPB) arnoldi_fin_k(const double* __restrict__ partials, int nblk,
+                                                      double* __restrict__ st, int m, int j, double* __restrict__ hslot,
+                                                      double seq) {
+    GLay L{m};
+    double* sc = st + L.scal();
+    final_sums<1>(partials, nblk, 1, sc + S_HN);
+    if (threadIdx.x != 0) return;
+    double* H = st + L.H();
+    double* cs = st + L.cs();
+    double* sn = st + L.sn();
+    double* g = st + L.g();
+    const double* h1 = st + L.h1();
+    const double* h2 = st + L.h2();
+    double hn = sqrt(sc[S_HN]);
+    for (int i = 0; i <= j; ++i) H[i * m + j] = h1[i] + h2[i];
+    H[(j + 1) * m + j] = hn;
+    for (int i = 0; i < j; ++i) {
+        double a = H[i * m + j], c = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * c;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
     }
+    double a = H[j * m + j], c = H[(j + 1) * m + j];
+    double rr = sqrt(a * a + c * c);
+    cs[j] = rr == 0.0 ? 1.0 : a / rr;
+    sn[j] = rr == 0.0 ? 0.0 : c / rr;
+    H[j * m + j] = rr;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    sc[S_HN] = hn;
+    sc[S_EST] = fabs(g[j + 1]);
+    sc[S_INV] = hn > 0.0 ? 1.0 / hn : 0.0;
+    sc[S_FLAG] = (isfinite(hn) && isfinite(sc[S_EST]) && isfinite(rr)) ? 0.0 : 1.0;
+    publish(hslot, sc, 8, seq);
 }
 
 // back substitution of the j x j upper triangle: y = R^-1 g
@@ -328,10 +364,12 @@ Gmres::Gmres(int64_t n, int m, Arena& ar, hipStream_t s) : n_(n), m_(m), ar_(&ar
     GLay L{m};
     st_ = ar.make<double>(L.size());
     red_.init(n, ar, s);
-    HIPCHK(hipHostMalloc((void**)&host_, 16 * sizeof(double), hipHostMallocDefault));
+    slot_.h = ar.ctx()->pinned.get();
+    slot_.d = PinnedPool::device_ptr(slot_.h);
+    slot_.h[15] = 0.0;
 }
 Gmres::~Gmres() {
-    if (host_) (void)hipHostFree(host_);
+    if (slot_.h) ar_->ctx()->pinned.put(slot_.h);
     ar_->free(V_); ar_->free(Z_); ar_->free(st_);
     red_.release(*ar_);
 }
@@ -341,12 +379,13 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
     KStat st;
     const int64_t n = n_;
     const int m = m_;
+    const int G = red_.grid;
+    double* part = red_.partials;
     GLay L{m};
-    double bn = device_norm(b, n, red_, host_, s);
+    double bn = device_norm(b, n, red_, slot_, s);
     if (!use_x0 || bn == 0.0) HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
     if (bn == 0.0) {
         st.converged = true;
-        HIPCHK(hipStreamSynchronize(s));
         return st;
     }
     if (!std::isfinite(bn)) throw Error(SCR_E_BREAKDOWN, "non-finite right-hand side");
@@ -362,10 +401,11 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
             axpby(n, 1.0, b, -1.0, V0, s);
         }
         first = false;
-        gm_init_k<<<red_.grid, RTPB, 0, s>>>(n, V0, red_.partials, red_.counter, st_, m);
+        dot_part_k<<<G, RTPB, 0, s>>>(n, V0, V0, part);
+        gm_init_fin_k<<<1, RTPB, 0, s>>>(part, G, st_, m, slot_.d, slot_.next());
         check_launch("gm_init");
-        HIPCHK(hipMemcpyAsync(host_, st_ + L.scal(), 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        slot_.wait(s);
+        const double* host_ = slot_.h;
         double beta = host_[S_BETA];
         if (host_[S_FLAG] != 0.0) throw Error(SCR_E_BREAKDOWN, "non-finite residual in GMRES");
         st.rel_res = beta / bn;
@@ -381,13 +421,16 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
             M.apply(Vj, Zj, s);
             A.apply(Zj, w, s);
             int jn = j + 1;
-            JDISPATCH(jn, mdot_k, <<<red_.grid, RTPB, 0, s>>>(n, jn, V_, n, w, red_.partials, red_.counter, st_ + L.h1()));
-            JDISPATCH(jn, upd_dot_k, <<<red_.grid, RTPB, 0, s>>>(n, jn, V_, n, w, st_ + L.h1(), red_.partials, red_.counter, st_ + L.h2()));
-            JDISPATCH(jn, upd_norm_finish_k, <<<red_.grid, RTPB, 0, s>>>(n, jn, V_, n, w, red_.partials, red_.counter, st_, m, j));
+            // CGS2: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2; ||w||
+            JDISPATCH(jn, mdot_k, <<<G, RTPB, 0, s>>>(n, jn, V_, n, w, part));
+            JDISPATCH(jn, sum_k, <<<1, RTPB, 0, s>>>(part, G, jn, st_ + L.h1()));
+            JDISPATCH(jn, upd_dot_k, <<<G, RTPB, 0, s>>>(n, jn, V_, n, w, st_ + L.h1(), part));
+            JDISPATCH(jn, sum_k, <<<1, RTPB, 0, s>>>(part, G, jn, st_ + L.h2()));
+            JDISPATCH(jn, upd_norm_k, <<<G, RTPB, 0, s>>>(n, jn, V_, n, w, st_ + L.h2(), part));
+            arnoldi_fin_k<<<1, RTPB, 0, s>>>(part, G, st_, m, j, slot_.d, slot_.next());
             check_launch("cgs2");
             scale_by_k<<<nblk, 256, 0, s>>>(n, w, st_ + L.scal() + S_INV);
-            HIPCHK(hipMemcpyAsync(host_, st_ + L.scal(), 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            slot_.wait(s);
             ++st.iters;
             ++j;
             if (host_[S_FLAG] != 0.0) throw Error(SCR_E_BREAKDOWN, "non-finite value in the Arnoldi process");
@@ -401,7 +444,6 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
         st.rel_res = est / bn;
         if (!check_true && (est <= tol * bn || st.iters >= maxit)) {
             st.converged = est <= tol * bn;
-            HIPCHK(hipStreamSynchronize(s));
             break;
         }
     }
@@ -411,27 +453,17 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
 // ------------------------------------------------------------------ CG kernels
 enum { C_RZ = 0, C_ALPHA = 1, C_BETA = 2, C_RN2 = 3, C_PQ = 4 };
 
-// st[ALPHA] = st[RZ] / (p . q)
-__global__ void __launch_bounds__(RTPB) cg_alpha_k(int64_t n, const double* __restrict__ p, const double* __restrict__ q,
-                                                   double* __restrict__ partials, unsigned* counter, double* __restrict__ st) {
-    double acc[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) acc[0] += p[i] * q[i];
-    block_partials<1>(acc, 1, partials);
-    if (last_block(counter)) {
-        final_sums(partials, 1, st + C_PQ);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            st[C_ALPHA] = st[C_RZ] / st[C_PQ];
-            *counter = 0;
-        }
-    }
+// st[ALPHA] = st[RZ] / (p . q)  (from the partials of p . q)
+__global__ void __launch_bounds__(RTPB) cg_alpha_fin_k(const double* __restrict__ partials, int nblk, double* __restrict__ st) {
+    final_sums<1>(partials, nblk, 1, st + C_PQ);
+    if (threadIdx.x == 0) st[C_ALPHA] = st[C_RZ] / st[C_PQ];
 }
 
-// (rold = r;) x += alpha p; r -= alpha q; st[RN2] = r . r
+// (rold = r;) x += alpha p; r -= alpha q; partials of r . r
 __global__ void __launch_bounds__(RTPB) cg_update_k(int64_t n, double* __restrict__ x, const double* __restrict__ p,
                                                     double* __restrict__ r, const double* __restrict__ q,
-                                                    double* __restrict__ rold, double* __restrict__ partials,
-                                                    unsigned* counter, double* __restrict__ st) {
+                                                    double* __restrict__ rold, const double* __restrict__ st,
+                                                    double* __restrict__ partials) {
     double alpha = st[C_ALPHA];
     double acc[1] = {0.0};
     for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) {
@@ -443,18 +475,11 @@ __global__ void __launch_bounds__(RTPB) cg_update_k(int64_t n, double* __restric
         acc[0] += ri * ri;
     }
     block_partials<1>(acc, 1, partials);
-    if (last_block(counter)) {
-        final_sums(partials, 1, st + C_RN2);
-        __syncthreads();
-        if (threadIdx.x == 0) *counter = 0;
-    }
 }
 
-// rz_new = r . z; (flexible) num = z . (r - rold); beta = (flex ? num : rz_new) / rz; rz = rz_new.
-// init: only rz = r . z.
-__global__ void __launch_bounds__(RTPB) cg_beta_k(int64_t n, const double* __restrict__ r, const double* __restrict__ z,
-                                                  const double* __restrict__ rold, int init, double* __restrict__ partials,
-                                                  unsigned* counter, double* __restrict__ st) {
+// partials of r . z and (flexible) z . (r - rold)
+__global__ void __launch_bounds__(RTPB) cg_rz_k(int64_t n, const double* __restrict__ r, const double* __restrict__ z,
+                                                const double* __restrict__ rold, double* __restrict__ partials) {
     double acc[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) {
         double zi = z[i], ri = r[i];
@@ -462,15 +487,15 @@ __global__ void __launch_bounds__(RTPB) cg_beta_k(int64_t n, const double* __res
         if (rold) acc[1] += zi * (ri - rold[i]);
     }
     block_partials<2>(acc, 2, partials);
-    if (last_block(counter)) {
-        __shared__ double res[2];
-        final_sums(partials, 2, res);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (!init) st[C_BETA] = (rold ? res[1] : res[0]) / st[C_RZ];
-            st[C_RZ] = res[0];
-            *counter = 0;
-        }
+}
+// beta = (flex ? num : rz_new) / rz; rz = rz_new   (init: only rz = rz_new)
+__global__ void __launch_bounds__(RTPB) cg_beta_fin_k(const double* __restrict__ partials, int nblk, int flexible,
+                                                      int init, double* __restrict__ st) {
+    __shared__ double res[2];
+    final_sums<2>(partials, nblk, 2, res);
+    if (threadIdx.x == 0) {
+        if (!init) st[C_BETA] = (flexible ? res[1] : res[0]) / st[C_RZ];
+        st[C_RZ] = res[0];
     }
 }
 
@@ -484,10 +509,12 @@ Pcg::Pcg(int64_t n, Arena& ar, hipStream_t s) : n_(n), ar_(&ar) {
     r_ = ar.make<double>(n); z_ = ar.make<double>(n); p_ = ar.make<double>(n);
     q_ = ar.make<double>(n); rold_ = ar.make<double>(n); st_ = ar.make<double>(8);
     red_.init(n, ar, s);
-    HIPCHK(hipHostMalloc((void**)&host_, 16 * sizeof(double), hipHostMallocDefault));
+    slot_.h = ar.ctx()->pinned.get();
+    slot_.d = PinnedPool::device_ptr(slot_.h);
+    slot_.h[15] = 0.0;
 }
 Pcg::~Pcg() {
-    if (host_) (void)hipHostFree(host_);
+    if (slot_.h) ar_->ctx()->pinned.put(slot_.h);
     ar_->free(r_); ar_->free(z_); ar_->free(p_); ar_->free(q_); ar_->free(rold_); ar_->free(st_);
     red_.release(*ar_);
 }
@@ -495,31 +522,36 @@ Pcg::~Pcg() {
 KStat Pcg::solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool flexible, hipStream_t s) {
     KStat st;
     const int64_t n = n_;
+    const int G = red_.grid;
+    double* part = red_.partials;
     int64_t nblk = cdiv(n, 256);
     HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
-    double bn = device_norm(b, n, red_, host_, s);
+    double bn = device_norm(b, n, red_, slot_, s);
     if (bn == 0.0) { st.converged = true; return st; }
     if (!std::isfinite(bn)) throw Error(SCR_E_BREAKDOWN, "non-finite right-hand side");
     copy_d(n, b, r_, s);
     M.apply(r_, z_, s);
     copy_d(n, z_, p_, s);
-    cg_beta_k<<<red_.grid, RTPB, 0, s>>>(n, r_, z_, nullptr, 1, red_.partials, red_.counter, st_);
+    cg_rz_k<<<G, RTPB, 0, s>>>(n, r_, z_, nullptr, part);
+    cg_beta_fin_k<<<1, RTPB, 0, s>>>(part, G, 0, 1, st_);
     double* rold = flexible ? rold_ : nullptr;
     for (;;) {
         A.apply(p_, q_, s);
-        cg_alpha_k<<<red_.grid, RTPB, 0, s>>>(n, p_, q_, red_.partials, red_.counter, st_);
-        cg_update_k<<<red_.grid, RTPB, 0, s>>>(n, x, p_, r_, q_, rold, red_.partials, red_.counter, st_);
+        dot_part_k<<<G, RTPB, 0, s>>>(n, p_, q_, part);
+        cg_alpha_fin_k<<<1, RTPB, 0, s>>>(part, G, st_);
+        cg_update_k<<<G, RTPB, 0, s>>>(n, x, p_, r_, q_, rold, st_, part);
+        sum_pub_k<<<1, RTPB, 0, s>>>(part, G, st_ + C_RN2, slot_.d, slot_.next());
         check_launch("cg");
-        HIPCHK(hipMemcpyAsync(host_, st_, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        slot_.wait(s);
         ++st.iters;
-        double rn = std::sqrt(host_[C_RN2]);
+        double rn = std::sqrt(slot_.h[0]);
         if (!std::isfinite(rn)) throw Error(SCR_E_BREAKDOWN, "non-finite residual in CG");
         st.rel_res = rn / bn;
         if (rn <= tol * bn) { st.converged = true; break; }
         if (st.iters >= maxit) break;
         M.apply(r_, z_, s);
-        cg_beta_k<<<red_.grid, RTPB, 0, s>>>(n, r_, z_, rold, 0, red_.partials, red_.counter, st_);
+        cg_rz_k<<<G, RTPB, 0, s>>>(n, r_, z_, rold, part);
+        cg_beta_fin_k<<<1, RTPB, 0, s>>>(part, G, flexible ? 1 : 0, 0, st_);
         cg_p_k<<<nblk, 256, 0, s>>>(n, p_, z_, st_);
         check_launch("cg");
     }

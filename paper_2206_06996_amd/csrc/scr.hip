@@ -204,7 +204,31 @@ scr_status scr_ctx_create(int device, int64_t hbm_budget, scr_ctx** out) {
     }
 }
 
-void scr_ctx_destroy(scr_ctx* ctx) { delete ctx; }
+void scr_ctx_destroy(scr_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    ctx->c.prof.harvest();
+    for (auto& p : ctx->c.prof.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : ctx->c.prof.pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+scr_status scr_ctx_profile(scr_ctx* ctx, int kernel) {
+    if (!ctx) { set_last_error("NULL context"); return SCR_E_INVALID; }
+    if (kernel != SCR_PROF_OFF && kernel != SCR_PROF_SMOOTH_A0) { set_last_error("unknown kernel"); return SCR_E_INVALID; }
+    ctx->c.prof.kernel.store(kernel);
+    return SCR_OK;
+}
+
+scr_status scr_ctx_profile_read(scr_ctx* ctx, int64_t* launches, double* total_ms, double* bytes) {
+    if (!ctx || !launches || !total_ms || !bytes) { set_last_error("NULL argument"); return SCR_E_INVALID; }
+    Profiler& p = ctx->c.prof;
+    p.harvest();
+    std::lock_guard<std::mutex> g(p.mu);
+    *launches = p.launches; *total_ms = p.ms; *bytes = p.bytes;
+    p.launches = 0; p.ms = 0.0; p.bytes = 0.0;
+    return SCR_OK;
+}
 int64_t scr_ctx_bytes_in_use(const scr_ctx* ctx) { return ctx ? ctx->c.in_use.load() : 0; }
 
 scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coords, const scr_amg_opts* opts,
@@ -269,7 +293,8 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
             h->B = ar.make<double>(nb * 18);
             rigid_modes(nb, xyz, h->B, ar, s);
             ar.free(xyz);
-            h->hA = build_hierarchy(h->A, h->B, 6, o, ar, s);
+            Profiler* pa = ctx->c.prof.kernel.load() == SCR_PROF_SMOOTH_A0 ? &ctx->c.prof : nullptr;
+            h->hA = build_hierarchy(h->A, h->B, 6, o, ar, s, pa);
             double* ones = ar.make<double>(nb);
             fill<double>(ones, 1.0, nb, s);
             h->hS = build_hierarchy(h->Sh, ones, 1, o, ar, s);
@@ -352,6 +377,7 @@ scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_
         KStat k = h->gOuter->solve(kop, prec, h->bs, h->xs, o.tol, o.max_it, o.use_x0 != 0, true, s);
         split_to_interleaved(nb, h->xs, x, s);
         HIPCHK(hipStreamSynchronize(s));
+        h->ctx->prof.harvest();
         h->st.outer_it = (int)k.iters;
         h->st.rel_res_true = k.rel_res;
         h->st.converged = k.converged ? 1 : 0;

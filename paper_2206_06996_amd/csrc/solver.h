@@ -33,6 +33,16 @@ struct Reducer {
     }
 };
 
+// Host side of a published status slot: spin until the sequence number arrives (the stream is
+// polled so that a failed launch surfaces as an error instead of a wait forever).
+struct StatusSlot {
+    double* h = nullptr;       // host address (pinned, mapped)
+    double* d = nullptr;       // device address of the same slot
+    double seq = 0.0;
+    double next() { return seq += 1.0; }
+    void wait(hipStream_t s) const;
+};
+
 // Right-preconditioned flexible GMRES(m) (Saad 1993) with CGS2 Arnoldi; the Hessenberg matrix,
 // Givens rotations and least-squares solve stay in device memory; the host reads one residual
 // estimate per iteration.
@@ -50,7 +60,7 @@ class Gmres {
     Arena* ar_;
     double *V_, *Z_, *st_;
     Reducer red_;
-    double* host_ = nullptr;         // pinned
+    StatusSlot slot_;
 };
 
 // Preconditioned CG, or flexible CG with the Polak-Ribiere beta (Notay 2000).
@@ -65,10 +75,10 @@ class Pcg {
     Arena* ar_;
     double *r_, *z_, *p_, *q_, *rold_, *st_;
     Reducer red_;
-    double* host_ = nullptr;
+    StatusSlot slot_;
 };
 
-double device_norm(const double* x, int64_t n, Reducer& red, double* host, hipStream_t s);
+double device_norm(const double* x, int64_t n, Reducer& red, StatusSlot& slot, hipStream_t s);
 
 // ---------------------------------------------------------------- AMG (amg.hip)
 struct LevelSetup {
@@ -96,8 +106,9 @@ class Hierarchy {
     int64_t n0() const { return L.empty() ? 0 : L[0].A.nr * L[0].b; }
 };
 
+// prof: the context profiler, or nullptr; when set, level-0 smoother steps are timed.
 std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
-                                           hipStream_t s);
+                                           hipStream_t s, Profiler* prof = nullptr);
 
 // rigid-body modes (6 columns) of nb nodes from coordinates, shifted by their mean
 void rigid_modes(int64_t nb, const double* xyz, double* B, Arena& ar, hipStream_t s);

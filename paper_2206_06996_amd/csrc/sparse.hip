@@ -129,12 +129,29 @@ void cast_f2d(const float* a, double* b, int64_t n, hipStream_t s) {
 }
 
 // ============================================================== sliced ELL
-__global__ void sell_slice_len(const int32_t* __restrict__ rp, int64_t nr, int64_t nslices, int32_t* __restrict__ len) {
+// rank of block row i within its window: rows ordered by decreasing length, ties by index
+__global__ void sell_rank_k(const int32_t* __restrict__ rp, int64_t nr, int64_t win, int32_t* __restrict__ rowid) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int64_t w0 = (i / win) * win, w1 = w0 + win < nr ? w0 + win : nr;
+    int32_t li = rp[i + 1] - rp[i];
+    int64_t rank = 0;
+    for (int64_t j = w0; j < w1; ++j) {
+        int32_t lj = rp[j + 1] - rp[j];
+        rank += (lj > li) || (lj == li && j < i);
+    }
+    rowid[w0 + rank] = (int32_t)i;
+}
+
+__global__ void sell_slice_len(const int32_t* __restrict__ rp, const int32_t* __restrict__ rowid, int rps,
+                               int64_t nslices, int32_t* __restrict__ len) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslices) return;
     int32_t m = 0;
-    for (int64_t r = s * WAVE; r < (s + 1) * WAVE && r < nr; ++r) {
-        int32_t l = rp[r + 1] - rp[r];
+    for (int64_t j = s * rps; j < (s + 1) * rps; ++j) {
+        int32_t i = rowid[j];
+        if (i < 0) continue;
+        int32_t l = rp[i + 1] - rp[i];
         m = l > m ? l : m;
     }
     len[s] = m;
@@ -142,23 +159,29 @@ __global__ void sell_slice_len(const int32_t* __restrict__ rp, int64_t nr, int64
 
 template <typename T>
 __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const double* __restrict__ v,
-                          int64_t nr, int64_t nc, int bb, const int32_t* __restrict__ off, int32_t* __restrict__ sci,
-                          T* __restrict__ sv, int64_t nslices) {
-    int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t s = row / WAVE;
+                          int br, int bc, int rps, const int32_t* __restrict__ rowid, const int32_t* __restrict__ off,
+                          int32_t* __restrict__ sci, T* __restrict__ sv, int64_t nslices) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = g / WAVE;
     if (s >= nslices) return;
-    int lane = (int)(row % WAVE);
+    int lane = (int)(g % WAVE);
+    int j = lane / br;
+    int r = lane % br;
+    int64_t i = j < rps ? rowid[s * rps + j] : -1;
+    bool valid = i >= 0;
     int64_t o0 = off[s], o1 = off[s + 1];
     int32_t lo = 0, hi = 0, pad = 0;
-    if (row < nr) {
-        lo = rp[row]; hi = rp[row + 1];
-        pad = hi > lo ? ci[hi - 1] : (row < nc ? (int32_t)row : 0);
+    if (valid) {
+        lo = rp[i]; hi = rp[i + 1];
+        pad = hi > lo ? ci[hi - 1] : 0;
     }
+    bool colwriter = j < rps && r == 0;
     for (int64_t t = o0; t < o1; ++t) {
         int64_t q = lo + (t - o0);
-        bool real = q < hi;
-        sci[t * WAVE + lane] = real ? ci[q] : pad;
-        for (int e = 0; e < bb; ++e) sv[(t * bb + e) * WAVE + lane] = real ? (T)v[q * bb + e] : (T)0;
+        bool real = valid && q < hi;
+        if (colwriter) sci[t * rps + j] = real ? ci[q] : pad;
+        for (int k = 0; k < bc; ++k)
+            sv[(t * bc + k) * WAVE + lane] = real ? (T)v[(q * br + r) * bc + k] : (T)0;
     }
 }
 
@@ -166,25 +189,28 @@ template <typename T>
 DSell<T> sell_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
     DSell<T> S;
     S.nr = A.nr; S.nc = A.nc; S.br = A.br; S.bc = A.bc; S.nnzb = A.nnzb;
-    S.nslices = cdiv(A.nr, WAVE);
+    S.rps = WAVE / A.br;
+    S.nslices = cdiv(A.nr, S.rps);
     if (S.nslices == 0) return S;
+    S.rowid = ar.make<int32_t>(S.nslices * S.rps);
+    fill_i32(S.rowid, -1, S.nslices * S.rps, s);
+    sell_rank_k<<<cdiv(A.nr, 256), 256, 0, s>>>(A.rp, A.nr, (int64_t)SELL_SIGMA * S.rps, S.rowid);
     int32_t* len = ar.make<int32_t>(S.nslices);
-    sell_slice_len<<<cdiv(S.nslices, 256), 256, 0, s>>>(A.rp, A.nr, S.nslices, len);
+    sell_slice_len<<<cdiv(S.nslices, 256), 256, 0, s>>>(A.rp, S.rowid, S.rps, S.nslices, len);
     check_launch("sell_slice_len");
     S.off = ar.make<int32_t>(S.nslices + 1);
     S.slots = scan_i32(len, S.off, S.nslices, ar, s);
     ar.free(len);
-    int bb = A.br * A.bc;
-    S.ci = ar.make<int32_t>(S.slots * WAVE);
-    S.v = ar.make<T>(S.slots * WAVE * bb);
-    sell_fill<T><<<cdiv(S.nslices * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.nr, A.nc, bb, S.off, S.ci, S.v,
-                                                            S.nslices);
+    S.ci = ar.make<int32_t>(S.slots * S.rps + 1);
+    S.v = ar.make<T>(S.slots * WAVE * A.bc + 1);
+    sell_fill<T><<<cdiv(S.nslices * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br, A.bc, S.rps, S.rowid, S.off,
+                                                            S.ci, S.v, S.nslices);
     check_launch("sell_fill");
     return S;
 }
 template <typename T>
 void sell_free(DSell<T>& A, Arena& ar) {
-    ar.free(A.off); ar.free(A.ci); ar.free(A.v);
+    ar.free(A.off); ar.free(A.rowid); ar.free(A.ci); ar.free(A.v);
     A = DSell<T>();
 }
 template DSell<double> sell_from_bsr<double>(const DBsr&, Arena&, hipStream_t);
@@ -211,50 +237,79 @@ DBsrT<T> bsrt_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
 template DBsrT<double> bsrt_from_bsr<double>(const DBsr&, Arena&, hipStream_t);
 template DBsrT<float> bsrt_from_bsr<float>(const DBsr&, Arena&, hipStream_t);
 
-// ============================================================== SpMV family (one lane per block row)
+// ============================================================== SpMV family (one lane per scalar row)
+// Unrolled slot loop: U slots' columns, then their values and x segments, are loaded before use.
+// Matrix values are read once per call: nontemporal loads keep them from evicting the gathered
+// x entries and the per-row vectors from the caches.
+// (measured: a gain for 3- and 6-wide FP64 row segments, a loss for scalar entries)
+template <int BC, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    if (BC >= 3 && sizeof(T) == 8) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <int BC> struct Unroll { static constexpr int U = BC == 1 ? 8 : (BC <= 4 ? 4 : 2); };
+
+// acc = sum over the lane's row segments of v . x[col*BC : col*BC+BC]; cl = the lane's block row
+// within the slice (column indices are stored once per block row, RPS per slot)
+template <typename T, int BC, int RPS, typename XF>
+__device__ __forceinline__ T sell_row_dot(int64_t o0, int64_t o1, int lane, int cl, const int32_t* __restrict__ ci,
+                                          const T* __restrict__ v, XF xat) {
+    constexpr int U = Unroll<BC>::U;
+    T acc = 0;
+    int64_t t = o0;
+    for (; t + U <= o1; t += U) {
+        int64_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = ci[(t + u) * RPS + cl];
+        T vv[U][BC];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < BC; ++k) vv[u][k] = ld_stream<BC>(v + ((t + u) * BC + k) * WAVE + lane);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < BC; ++k) acc += vv[u][k] * xat(c[u], k);
+    }
+    for (; t < o1; ++t) {
+        int64_t c = ci[t * RPS + cl];
+#pragma unroll
+        for (int k = 0; k < BC; ++k) acc += ld_stream<BC>(v + (t * BC + k) * WAVE + lane) * xat(c, k);
+    }
+    return acc;
+}
+
 template <typename T, int BR, int BC, int MODE>
-__global__ void __launch_bounds__(256) sell_mv_k(int64_t nr, int64_t nslices, const int32_t* __restrict__ off,
-                                                 const int32_t* __restrict__ ci, const T* __restrict__ v,
-                                                 const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y) {
-    int64_t row = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    int64_t sl = row / WAVE;
+__global__ void __launch_bounds__(256) sell_mv_k(int64_t nslices, const int32_t* __restrict__ off,
+                                                 const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
+                                                 const T* __restrict__ v, const T* __restrict__ x,
+                                                 const T* __restrict__ b, T* __restrict__ y) {
+    constexpr int RPS = WAVE / BR;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * 4 + threadIdx.x / WAVE;
     if (sl >= nslices) return;
     int lane = threadIdx.x & (WAVE - 1);
-    int64_t o0 = off[sl], o1 = off[sl + 1];
-    T acc[BR];
-#pragma unroll
-    for (int r = 0; r < BR; ++r) acc[r] = 0;
-    for (int64_t t = o0; t < o1; ++t) {
-        int64_t c = ci[t * WAVE + lane];
-        T xv[BC];
-#pragma unroll
-        for (int k = 0; k < BC; ++k) xv[k] = x[c * BC + k];
-        const T* vb = v + t * (BR * BC) * WAVE + lane;
-#pragma unroll
-        for (int r = 0; r < BR; ++r)
-#pragma unroll
-            for (int k = 0; k < BC; ++k) acc[r] += vb[(r * BC + k) * WAVE] * xv[k];
-    }
-    if (row >= nr) return;
-#pragma unroll
-    for (int r = 0; r < BR; ++r) {
-        int64_t o = row * BR + r;
-        if (MODE == 0) y[o] = acc[r];
-        else if (MODE == 1) y[o] = b[o] - acc[r];
-        else if (MODE == 2) y[o] += acc[r];
-        else y[o] -= acc[r];
-    }
+    auto xat = [&](int64_t c, int k) { return x[c * BC + k]; };
+    int cl = lane / BR < RPS ? lane / BR : RPS - 1;
+    T acc = sell_row_dot<T, BC, RPS>(off[sl], off[sl + 1], lane, cl, ci, v, xat);
+    if (lane >= RPS * BR) return;
+    int64_t i = rowid[sl * RPS + cl];
+    if (i < 0) return;
+    int64_t o = i * BR + lane % BR;
+    if (MODE == 0) y[o] = acc;
+    else if (MODE == 1) y[o] = b[o] - acc;
+    else if (MODE == 2) y[o] += acc;
+    else y[o] -= acc;
 }
 
 template <typename T, int BR, int BC>
 static void sell_mv_dispatch_mode(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStream_t s) {
-    int64_t nblk = cdiv(A.nslices * WAVE, 256);
+    int64_t nblk = cdiv(A.nslices, 4);
     if (nblk == 0) return;
     switch (mode) {
-        case 0: sell_mv_k<T, BR, BC, 0><<<nblk, 256, 0, s>>>(A.nr, A.nslices, A.off, A.ci, A.v, x, b, y); break;
-        case 1: sell_mv_k<T, BR, BC, 1><<<nblk, 256, 0, s>>>(A.nr, A.nslices, A.off, A.ci, A.v, x, b, y); break;
-        case 2: sell_mv_k<T, BR, BC, 2><<<nblk, 256, 0, s>>>(A.nr, A.nslices, A.off, A.ci, A.v, x, b, y); break;
-        default: sell_mv_k<T, BR, BC, 3><<<nblk, 256, 0, s>>>(A.nr, A.nslices, A.off, A.ci, A.v, x, b, y); break;
+        case 0: sell_mv_k<T, BR, BC, 0><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+        case 1: sell_mv_k<T, BR, BC, 1><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+        case 2: sell_mv_k<T, BR, BC, 2><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+        default: sell_mv_k<T, BR, BC, 3><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
     }
     check_launch("sell_mv");
 }
@@ -276,41 +331,32 @@ void sell_mv(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStrea
 template void sell_mv<double>(const DSell<double>&, const double*, const double*, double*, int, hipStream_t);
 template void sell_mv<float>(const DSell<float>&, const float*, const float*, float*, int, hipStream_t);
 
-// 4x4 system matrix on split vectors: x_v[3c..3c+2], x_p[c]
+// 4x4 system matrix on split vectors [x_v (3n); x_p (n)]
 template <int MODE>
 __global__ void __launch_bounds__(256) sell_mv_split4_k(int64_t nr, int64_t nslices, const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ rowid,
                                                         const int32_t* __restrict__ ci, const double* __restrict__ v,
                                                         const double* __restrict__ x, const double* __restrict__ b,
                                                         double* __restrict__ y) {
-    int64_t row = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    int64_t sl = row / WAVE;
+    constexpr int RPS = WAVE / 4;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * 4 + threadIdx.x / WAVE;
     if (sl >= nslices) return;
     int lane = threadIdx.x & (WAVE - 1);
-    int64_t o0 = off[sl], o1 = off[sl + 1];
     const double* xp = x + 3 * nr;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t t = o0; t < o1; ++t) {
-        int64_t c = ci[t * WAVE + lane];
-        double xv[4] = {x[3 * c], x[3 * c + 1], x[3 * c + 2], xp[c]};
-        const double* vb = v + t * 16 * WAVE + lane;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc[r] += vb[(r * 4 + k) * WAVE] * xv[k];
-    }
-    if (row >= nr) return;
-    int64_t o[4] = {3 * row, 3 * row + 1, 3 * row + 2, 3 * nr + row};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        if (MODE == 0) y[o[r]] = acc[r];
-        else y[o[r]] = b[o[r]] - acc[r];
-    }
+    auto xat = [&](int64_t c, int k) { return k < 3 ? x[3 * c + k] : xp[c]; };
+    double acc = sell_row_dot<double, 4, RPS>(off[sl], off[sl + 1], lane, lane / 4, ci, v, xat);
+    int64_t i = rowid[sl * RPS + lane / 4];
+    if (i < 0) return;
+    int r = lane & 3;
+    int64_t o = r < 3 ? 3 * i + r : 3 * nr + i;
+    if (MODE == 0) y[o] = acc;
+    else y[o] = b[o] - acc;
 }
 void sell_mv_split4(const DSell<double>& K, const double* x, const double* b, double* y, int mode, hipStream_t s) {
-    int64_t nblk = cdiv(K.nslices * WAVE, 256);
+    int64_t nblk = cdiv(K.nslices, 4);
     if (nblk == 0) return;
-    if (mode == 0) sell_mv_split4_k<0><<<nblk, 256, 0, s>>>(K.nr, K.nslices, K.off, K.ci, K.v, x, b, y);
-    else sell_mv_split4_k<1><<<nblk, 256, 0, s>>>(K.nr, K.nslices, K.off, K.ci, K.v, x, b, y);
+    if (mode == 0) sell_mv_split4_k<0><<<nblk, 256, 0, s>>>(K.nr, K.nslices, K.off, K.rowid, K.ci, K.v, x, b, y);
+    else sell_mv_split4_k<1><<<nblk, 256, 0, s>>>(K.nr, K.nslices, K.off, K.rowid, K.ci, K.v, x, b, y);
     check_launch("sell_mv_split4");
 }
 
@@ -355,56 +401,50 @@ template void bsrt_mv<double>(const DBsrT<double>&, const double*, double*, hipS
 template void bsrt_mv<float>(const DBsrT<float>&, const float*, float*, hipStream_t);
 
 // ---------------------------------------------------------------- fused smoother step
-// dn = c1*d + c2*Dinv*(b - A xin) ; xout = xin + dn.  One lane per block row.
+// dn = c1*d + c2*Dinv*(b - A xin) ; xout = xin + dn.  One lane per scalar row; the block
+// residual of a block row is gathered from its B lanes with shuffles to apply Dinv.
 template <typename T, int B, bool RD, bool WD, bool ZERO>
-__global__ void __launch_bounds__(256) smooth_k(int64_t nr, int64_t nslices, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* __restrict__ off,
+                                                const int32_t* __restrict__ rowid,
                                                 const int32_t* __restrict__ ci, const T* __restrict__ v,
                                                 const T* __restrict__ Dinv, const T* __restrict__ b,
                                                 const T* __restrict__ xin, T* __restrict__ d, T* __restrict__ xout,
                                                 T c1, T c2) {
-    int64_t row = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    int64_t sl = row / WAVE;
+    constexpr int RPS = WAVE / B;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * 4 + threadIdx.x / WAVE;
     if (sl >= nslices) return;
     int lane = threadIdx.x & (WAVE - 1);
-    T r[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) r[i] = 0;
+    int cl = lane / B < RPS ? lane / B : RPS - 1;
+    int64_t i = rowid[sl * RPS + cl];
+    int r = lane % B;
+    bool valid = lane < RPS * B && i >= 0;
+    T acc = 0;
     if (!ZERO) {
-        int64_t o0 = off[sl], o1 = off[sl + 1];
-        for (int64_t t = o0; t < o1; ++t) {
-            int64_t c = ci[t * WAVE + lane];
-            T xv[B];
-#pragma unroll
-            for (int k = 0; k < B; ++k) xv[k] = xin[c * B + k];
-            const T* vb = v + t * (B * B) * WAVE + lane;
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-#pragma unroll
-                for (int k = 0; k < B; ++k) r[i] += vb[(i * B + k) * WAVE] * xv[k];
-        }
+        auto xat = [&](int64_t c, int k) { return xin[c * B + k]; };
+        acc = sell_row_dot<T, B, RPS>(off[sl], off[sl + 1], lane, cl, ci, v, xat);
     }
-    if (row >= nr) return;
+    int64_t o = i * B + r;
+    T res = valid ? b[o] - acc : (T)0;
+    T z = 0;
+    int base = lane - r;
 #pragma unroll
-    for (int i = 0; i < B; ++i) r[i] = b[row * B + i] - r[i];
-    const T* D = Dinv + row * (B * B);
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-        T z = 0;
-#pragma unroll
-        for (int k = 0; k < B; ++k) z += D[i * B + k] * r[k];
-        T dn = c2 * z;
-        if (RD) dn += c1 * d[row * B + i];
-        if (WD) d[row * B + i] = dn;
-        xout[row * B + i] = ZERO ? dn : xin[row * B + i] + dn;
+    for (int k = 0; k < B; ++k) {
+        T rk = B == 1 ? res : __shfl(res, base + k, WAVE);
+        if (valid) z += Dinv[o * B + k] * rk;
     }
+    if (!valid) return;
+    T dn = c2 * z;
+    if (RD) dn += c1 * d[o];
+    if (WD) d[o] = dn;
+    xout[o] = ZERO ? dn : xin[o] + dn;
 }
 
 template <typename T, int B>
 static void smooth_dispatch(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, T c1, T c2,
                             bool rd, bool wd, bool zero, hipStream_t s) {
-    int64_t nblk = cdiv(A.nslices * WAVE, 256);
+    int64_t nblk = cdiv(A.nslices, 4);
     if (nblk == 0) return;
-#define SK(RD, WD, Z) smooth_k<T, B, RD, WD, Z><<<nblk, 256, 0, s>>>(A.nr, A.nslices, A.off, A.ci, A.v, Dinv, b, xin, d, xout, c1, c2)
+#define SK(RD, WD, Z) smooth_k<T, B, RD, WD, Z><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin, d, xout, c1, c2)
     if (zero) {
         if (wd) SK(false, true, true); else SK(false, false, true);
     } else if (rd) {

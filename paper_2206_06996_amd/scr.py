@@ -25,7 +25,9 @@ SCR_SMOOTH_JACOBI, SCR_SMOOTH_CHEBYSHEV = 0, 1
 EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", "scr_ctx_destroy",
             "scr_ctx_bytes_in_use", "amg_setup", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
             "scr_handle_bytes", "scr_footprint_estimate", "scr_status_str", "scr_last_error", "scr_hier_levels",
-            "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply"]
+            "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
+            "scr_ctx_profile_read"]
+SCR_PROF_OFF, SCR_PROF_SMOOTH_A0 = 0, 1
 
 
 class ScrError(RuntimeError):
@@ -95,8 +97,11 @@ def lib():
         L.scr_hier_level_copy.argtypes = [P, C.c_int, C.c_int, C.c_int, P]
         L.scr_matrix_copy.argtypes = [P, C.c_int, C.c_int, P, P]
         L.scr_apply.argtypes = [P, C.c_int, P, P, C.POINTER(SolveOpts), P]
+        L.scr_ctx_profile.argtypes = [P, C.c_int]
+        L.scr_ctx_profile_read.argtypes = [P, P, P, P]
         for f in ("amg_setup", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
-                  "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply"):
+                  "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
+                  "scr_ctx_profile", "scr_ctx_profile_read"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -147,6 +152,15 @@ class Context:
 
     def bytes_in_use(self) -> int:
         return lib().scr_ctx_bytes_in_use(self.ptr)
+
+    def profile(self, kernel: int):
+        _check(lib().scr_ctx_profile(self.ptr, kernel))
+
+    def profile_read(self):
+        """(launches, total_ms, algorithmic_bytes) of the profiled kernel since the last read."""
+        n = C.c_int64(); ms = C.c_double(); by = C.c_double()
+        _check(lib().scr_ctx_profile_read(self.ptr, C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
 
     def destroy(self):
         if self.ptr:
