@@ -190,6 +190,53 @@ scr_status scr_matrix_copy(scr_handle* h, int which, int field, void* dst /* hos
 scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const scr_solve_opts* opts,
                      void* stream);
 
+/* ---------------------------------------------------------------- serving
+ * A server keeps a FIFO queue of solve requests and max_slots worker threads, each with its own
+ * HIP stream.  A request is admitted when a slot is free and the sum of the footprint estimates
+ * (scr_footprint_estimate) of the admitted requests stays within hbm_budget (0 = the context's
+ * budget, or unlimited); requests that arrive while others run are admitted as slots and memory
+ * free up, and their kernels overlap on the device.  A request whose footprint alone exceeds the
+ * budget is rejected (SCR_E_OOM), never queued forever.  Each request builds its hierarchies
+ * once (amg_setup) and reuses them for its n_rhs successive corrections (the multi-corrector
+ * loop of Sec. 3.5 with a frozen tangent), and for its mesh-motion solves when L is given.
+ * All device arrays of a request are borrowed until srv_wait/srv_poll reports it done. */
+typedef struct scr_server scr_server;
+
+typedef struct {
+    scr_bsr K;                     /* SCR_SYSTEM matrix (device arrays) */
+    const double* coords;          /* device, n_brows x 3 */
+    int n_rhs;                     /* successive corrections, 1..64 */
+    const double* const* b;        /* host array of n_rhs device pointers (4 n_brows each) */
+    double* const* x;              /* host array of n_rhs device pointers (outputs) */
+    const scr_bsr* L;              /* optional mesh Laplacian (NULL = none) */
+    const double* const* bm;       /* n_rhs device pointers (n_L x 3 each), if L */
+    double* const* xm;             /* n_rhs device pointers (outputs), if L */
+} scr_request;
+
+typedef struct {
+    scr_status status;             /* worst status over the request's solves */
+    int64_t n_solves;
+    double latency_ms;             /* submit -> last correction done */
+    double queue_ms;               /* submit -> admission */
+    double setup_ms, solve_ms;     /* summed over the request */
+    int64_t footprint;             /* admission estimate (bytes) */
+    int64_t device_bytes;          /* measured peak of the request's handle(s) */
+    scr_stats last;                /* stats of the last SCR solve */
+} srv_result;
+
+scr_status srv_create(scr_ctx* ctx, int max_slots, int64_t hbm_budget, const scr_amg_opts* amg /* host */,
+                      const scr_solve_opts* solve /* host */, scr_server** out /* host */);
+/* Non-blocking; the request struct and its pointer arrays are copied. */
+scr_status srv_submit(scr_server* s, const scr_request* r /* host */, int64_t* id /* host */);
+/* done = 1 when the request has finished (result filled), 0 otherwise.  Non-blocking. */
+scr_status srv_poll(scr_server* s, int64_t id, int* done /* host */, srv_result* res /* host */);
+/* Block until the request has finished. */
+scr_status srv_wait(scr_server* s, int64_t id, srv_result* res /* host */);
+/* Block until every submitted request has finished; max_active (host, may be NULL) receives the
+ * largest number of requests that ran at the same time. */
+scr_status srv_drain(scr_server* s, int* max_active);
+void srv_destroy(scr_server* s);
+
 #ifdef __cplusplus
 }
 #endif

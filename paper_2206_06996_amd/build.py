@@ -25,6 +25,7 @@ SOURCES = {
     "krylov.hip": [],
     "amg.hip": ["-ffp-contract=off"],
     "scr.hip": [],
+    "serve.hip": [],
 }
 
 

@@ -792,9 +792,9 @@ class HierT : public Hierarchy {
             bool rd = q.cheb && t > 0, wd = q.cheb && t + 1 < ns, zero = cur == nullptr;
             bool timed = prof && l == 0 && !zero;
             hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (timed) { e0 = prof->get(); e1 = prof->get(); HIPCHK(hipEventRecord(e0, s)); }
-            smooth_step<T>(q.A, q.Dinv, b, cur, q.d, out, q.c1[t], q.c2[t], rd, wd, zero, s);
-            if (timed) { HIPCHK(hipEventRecord(e1, s)); prof->push(e0, e1, step_bytes(q, rd, wd)); }
+            if (timed) { e0 = prof->get(); e1 = prof->get(); }
+            smooth_step<T>(q.A, q.Dinv, b, cur, q.d, out, q.c1[t], q.c2[t], rd, wd, zero, s, e0, e1);
+            if (timed) prof->push(e0, e1, step_bytes(q, rd, wd));
             cur = out;
         }
     }

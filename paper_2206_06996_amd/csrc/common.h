@@ -236,3 +236,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 }  // namespace scr
+
+// The opaque context of the C ABI.
+struct scr_ctx {
+    scr::Ctx c;
+};

@@ -37,9 +37,11 @@ void sell_mv_split4(const DSell<double>& K, const double* x, const double* b, do
 template <typename T> void bsrt_mv(const DBsrT<T>& R, const T* x, T* y, hipStream_t s);
 // One smoothing step on block rows of size bs:  dn = c1*d + c2*Dinv (b - A xin);  xout = xin + dn
 // (d is read when read_d, written when write_d).  zero_in: xin = 0 (no SpMV; xout = dn).
+// e0/e1 (optional): events recorded by the kernel's own dispatch packet (kernel time only).
 template <typename T>
 void smooth_step(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, double c1,
-                 double c2, bool read_d, bool write_d, bool zero_in, hipStream_t s);
+                 double c2, bool read_d, bool write_d, bool zero_in, hipStream_t s, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr);
 // x = M b for a dense row-major n x n FP64 matrix M (coarsest-level inverse)
 template <typename T> void dense_mv(int64_t n, const double* M, const T* b, T* x, hipStream_t s);
 // validate a square BSR (device); returns error bits (synchronises)

@@ -13,10 +13,6 @@ static thread_local std::string g_last_error;
 void set_last_error(const std::string& m) { g_last_error = m; }
 }  // namespace scr
 
-struct scr_ctx {
-    Ctx c;
-};
-
 struct scr_handle {
     Ctx* ctx = nullptr;
     int kind = SCR_SYSTEM;

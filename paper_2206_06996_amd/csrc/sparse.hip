@@ -2,6 +2,8 @@
 // the solve phase: block SpMV/residual, fused smoother steps, restriction, coarse dense solve.
 // Every kernel here streams matrix values once per call (HBM-bound, no MFMA: sparse products
 // are not dense contractions).
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace scr {
@@ -441,10 +443,19 @@ __global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* 
 
 template <typename T, int B>
 static void smooth_dispatch(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, T c1, T c2,
-                            bool rd, bool wd, bool zero, hipStream_t s) {
+                            bool rd, bool wd, bool zero, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     int64_t nblk = cdiv(A.nslices, 4);
     if (nblk == 0) return;
-#define SK(RD, WD, Z) smooth_k<T, B, RD, WD, Z><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin, d, xout, c1, c2)
+#define SK(RD, WD, Z)                                                                                              \
+    do {                                                                                                           \
+        if (e0)                                                                                                    \
+            hipExtLaunchKernelGGL((smooth_k<T, B, RD, WD, Z>), dim3((unsigned)nblk), dim3(256), 0, s, e0, e1, 0,   \
+                                  A.nslices, (const int32_t*)A.off, (const int32_t*)A.rowid, (const int32_t*)A.ci, \
+                                  (const T*)A.v, Dinv, b, xin, d, xout, c1, c2);                                   \
+        else                                                                                                       \
+            smooth_k<T, B, RD, WD, Z><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin, d,  \
+                                                          xout, c1, c2);                                           \
+    } while (0)
     if (zero) {
         if (wd) SK(false, true, true); else SK(false, false, true);
     } else if (rd) {
@@ -458,18 +469,18 @@ static void smooth_dispatch(const DSell<T>& A, const T* Dinv, const T* b, const 
 
 template <typename T>
 void smooth_step(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, double c1, double c2,
-                 bool read_d, bool write_d, bool zero_in, hipStream_t s) {
+                 bool read_d, bool write_d, bool zero_in, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (A.br) {
-        case 1: smooth_dispatch<T, 1>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s); break;
-        case 3: smooth_dispatch<T, 3>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s); break;
-        case 6: smooth_dispatch<T, 6>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s); break;
+        case 1: smooth_dispatch<T, 1>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1); break;
+        case 3: smooth_dispatch<T, 3>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1); break;
+        case 6: smooth_dispatch<T, 6>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1); break;
         default: throw Error(SCR_E_UNIMPLEMENTED, "smooth_step: block size");
     }
 }
 template void smooth_step<double>(const DSell<double>&, const double*, const double*, const double*, double*, double*,
-                                  double, double, bool, bool, bool, hipStream_t);
+                                  double, double, bool, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void smooth_step<float>(const DSell<float>&, const float*, const float*, const float*, float*, float*,
-                                 double, double, bool, bool, bool, hipStream_t);
+                                 double, double, bool, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------- coarsest level: x = M b (M = A_c^-1, FP64)
 template <typename T>

@@ -26,7 +26,8 @@ EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", 
             "scr_ctx_bytes_in_use", "amg_setup", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
             "scr_handle_bytes", "scr_footprint_estimate", "scr_status_str", "scr_last_error", "scr_hier_levels",
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
-            "scr_ctx_profile_read"]
+            "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
+            "srv_destroy"]
 SCR_PROF_OFF, SCR_PROF_SMOOTH_A0 = 0, 1
 
 
@@ -68,6 +69,22 @@ class Stats(C.Structure):
         return d
 
 
+class ScrRequest(C.Structure):
+    _fields_ = [("K", ScrBsr), ("coords", P), ("n_rhs", C.c_int), ("b", C.POINTER(P)), ("x", C.POINTER(P)),
+                ("L", C.POINTER(ScrBsr)), ("bm", C.POINTER(P)), ("xm", C.POINTER(P))]
+
+
+class SrvResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("n_solves", C.c_int64), ("latency_ms", C.c_double), ("queue_ms", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("footprint", C.c_int64),
+                ("device_bytes", C.c_int64), ("last", Stats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "last"}
+        d["last"] = self.last.as_dict()
+        return d
+
+
 def lib():
     """Load libscr.so (built by paper_2206_06996_amd.build); raise if it is missing."""
     global _lib
@@ -99,9 +116,17 @@ def lib():
         L.scr_apply.argtypes = [P, C.c_int, P, P, C.POINTER(SolveOpts), P]
         L.scr_ctx_profile.argtypes = [P, C.c_int]
         L.scr_ctx_profile_read.argtypes = [P, P, P, P]
+        L.srv_create.argtypes = [P, C.c_int, C.c_int64, C.POINTER(AmgOpts), C.POINTER(SolveOpts), C.POINTER(P)]
+        L.srv_submit.argtypes = [P, C.POINTER(ScrRequest), C.POINTER(C.c_int64)]
+        L.srv_poll.argtypes = [P, C.c_int64, C.POINTER(C.c_int), C.POINTER(SrvResult)]
+        L.srv_wait.argtypes = [P, C.c_int64, C.POINTER(SrvResult)]
+        L.srv_drain.argtypes = [P, C.POINTER(C.c_int)]
+        L.srv_destroy.argtypes = [P]
+        L.srv_destroy.restype = None
         for f in ("amg_setup", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
-                  "scr_ctx_profile", "scr_ctx_profile_read"):
+                  "scr_ctx_profile", "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait",
+                  "srv_drain"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -267,3 +292,64 @@ def footprint_estimate(kind: int, n_brows: int, nnzb: int, amg: AmgOpts | None =
                        solve: SolveOpts | None = None) -> int:
     return lib().scr_footprint_estimate(kind, n_brows, nnzb, C.byref(amg) if amg else None,
                                         C.byref(solve) if solve else None)
+
+
+def _bsr(row_ptr, col_idx, val, bs):
+    import torch
+    return ScrBsr(n_brows=row_ptr.numel() - 1, bs=bs, nnzb=col_idx.numel(),
+                  row_ptr=_dev(row_ptr, torch.int32, "row_ptr"), col_idx=_dev(col_idx, torch.int32, "col_idx"),
+                  val=_dev(val, torch.float64, "val"))
+
+
+class Server:
+    """Continuous-batching server (srv_* in scr.h).  submit() keeps references to the tensors of
+    each request until it is waited for."""
+
+    def __init__(self, ctx: Context, max_slots: int = 4, hbm_budget: int = 0, amg: AmgOpts | None = None,
+                 solve: SolveOpts | None = None):
+        self.ptr = P()
+        self._keep = {}
+        _check(lib().srv_create(ctx.ptr, max_slots, hbm_budget, C.byref(amg) if amg else None,
+                                C.byref(solve) if solve else None, C.byref(self.ptr)))
+
+    def submit(self, K, coords, bs, xs, L=None, bms=None, xms=None) -> int:
+        """K = (row_ptr, col_idx, val) tensors of the 4x4 system; bs/xs lists of RHS/output tensors;
+        L = (row_ptr, col_idx, val) of the mesh Laplacian with bms/xms lists (optional)."""
+        import torch
+        n = len(bs)
+        barr = (P * n)(*[_dev(b, torch.float64, "b") for b in bs])
+        xarr = (P * n)(*[_dev(x, torch.float64, "x") for x in xs])
+        req = ScrRequest(K=_bsr(*K, 4), coords=_dev(coords, torch.float64, "coords"), n_rhs=n, b=barr, x=xarr)
+        keep = [K, coords, bs, xs, barr, xarr]
+        if L is not None:
+            Lb = _bsr(*L, 1)
+            bmarr = (P * n)(*[_dev(b, torch.float64, "bm") for b in bms])
+            xmarr = (P * n)(*[_dev(x, torch.float64, "xm") for x in xms])
+            req.L = C.pointer(Lb); req.bm = bmarr; req.xm = xmarr
+            keep += [L, bms, xms, Lb, bmarr, xmarr]
+        rid = C.c_int64()
+        _check(lib().srv_submit(self.ptr, C.byref(req), C.byref(rid)))
+        self._keep[rid.value] = keep
+        return rid.value
+
+    def poll(self, rid: int):
+        done = C.c_int(); res = SrvResult()
+        _check(lib().srv_poll(self.ptr, rid, C.byref(done), C.byref(res)))
+        return (res.as_dict() if done.value else None)
+
+    def wait(self, rid: int) -> dict:
+        res = SrvResult()
+        _check(lib().srv_wait(self.ptr, rid, C.byref(res)))
+        self._keep.pop(rid, None)
+        return res.as_dict()
+
+    def drain(self) -> int:
+        m = C.c_int()
+        _check(lib().srv_drain(self.ptr, C.byref(m)))
+        return m.value
+
+    def destroy(self):
+        if self.ptr:
+            lib().srv_destroy(self.ptr)
+            self.ptr = P()
+            self._keep.clear()

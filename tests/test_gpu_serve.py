@@ -1,0 +1,136 @@
+"""Serving (continuous batching) on the GPU: every request's results are the same alone and in the
+mix (bitwise: the kernels are deterministic and requests share no state), admission respects the
+device-memory budget, oversize requests are rejected, and a failing request does not disturb the
+others."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def scr():
+    import paper_2206_06996_amd.scr as m
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _systems():
+    ps = [synth.tiny_annulus_params(),
+          synth.default_params(mode=0, m_core=2, n_bl=1, n_wall=1, nz=8, R=1.0, L=2.0),
+          synth.cfg0_params(),
+          synth.tube_params(12000, 0.7, 3.0),
+          synth.tube_params(25000, 1.3, 6.0)]
+    out = []
+    for k, p in enumerate(ps):
+        s = synth.generate(p)
+        nrhs = 1 + k % 3
+        out.append(dict(
+            K=(dev(s.rp), dev(s.ci), dev(s.val.reshape(-1))), coords=dev(s.xyz.reshape(-1)),
+            L=(dev(s.Lrp), dev(s.Lci), dev(s.Lval)),
+            b=[dev(synth.rhs(100 * k + c, 4 * s.n_b, s.mask)) for c in range(nrhs)],
+            bm=[dev(synth.rhs(100 * k + 50 + c, 3 * s.n_phys, np.repeat(s.Lmask, 3))) for c in range(nrhs)],
+            nb=s.n_b, nphys=s.n_phys))
+    return out
+
+
+@pytest.fixture(scope="module")
+def systems():
+    return _systems()
+
+
+def _alone(scr, ctx, sysd):
+    xs, xms = [], []
+    h = scr.amg_setup(ctx, scr.SCR_SYSTEM, *sysd["K"], sysd["coords"])
+    hm = scr.amg_setup(ctx, scr.MESH_SYSTEM, *sysd["L"])
+    for b, bm in zip(sysd["b"], sysd["bm"]):
+        x = torch.zeros_like(b); xm = torch.zeros_like(bm)
+        rc, _ = scr.scr_solve(h, b, x)
+        rcm, _ = scr.mesh_motion_solve(hm, bm, xm)
+        assert rc == 0 and rcm == 0
+        xs.append(x.cpu().numpy()); xms.append(xm.cpu().numpy())
+    h.destroy(); hm.destroy()
+    return xs, xms
+
+
+def test_results_identical_alone_and_in_the_mix(scr, systems):
+    ctx = scr.Context(0)
+    alone = [_alone(scr, ctx, sd) for sd in systems]
+    srv = scr.Server(ctx, max_slots=3)
+    ids, outs = [], []
+    for rep in range(2):                      # every system twice: more requests than slots
+        for sd in systems:
+            xs = [torch.full_like(b, np.nan) for b in sd["b"]]
+            xms = [torch.full_like(b, np.nan) for b in sd["bm"]]
+            ids.append(srv.submit(sd["K"], sd["coords"], sd["b"], xs, L=sd["L"], bms=sd["bm"], xms=xms))
+            outs.append((xs, xms))
+    res = [srv.wait(i) for i in ids]
+    max_active = srv.drain()
+    torch.cuda.synchronize()
+    for k, (r, (xs, xms)) in enumerate(zip(res, outs)):
+        xa, xma = alone[k % len(systems)]
+        assert r["status"] == 0, r
+        assert r["n_solves"] == len(xs)
+        assert r["latency_ms"] >= r["queue_ms"] >= 0
+        for x, ref in zip(xs, xa):
+            assert np.array_equal(x.cpu().numpy(), ref)
+        for x, ref in zip(xms, xma):
+            assert np.array_equal(x.cpu().numpy(), ref)
+    assert max_active >= 2                     # requests really overlapped
+    srv.destroy()
+    assert ctx.bytes_in_use() == 0
+    ctx.destroy()
+
+
+def test_admission_by_footprint_and_rejection(scr, systems):
+    ctx = scr.Context(0)
+    big = systems[4]
+    fp = scr.footprint_estimate(scr.SCR_SYSTEM, big["nb"], big["K"][1].numel()) + \
+        scr.footprint_estimate(scr.MESH_SYSTEM, big["nphys"], big["L"][1].numel())
+    # room for one large request at a time: three of them must run one after the other
+    srv = scr.Server(ctx, max_slots=3, hbm_budget=int(fp * 1.5))
+    ids = []
+    for _ in range(3):
+        xs = [torch.zeros_like(b) for b in big["b"]]
+        xms = [torch.zeros_like(b) for b in big["bm"]]
+        ids.append(srv.submit(big["K"], big["coords"], big["b"], xs, L=big["L"], bms=big["bm"], xms=xms))
+    res = [srv.wait(i) for i in ids]
+    assert all(r["status"] == 0 for r in res)
+    assert srv.drain() == 1
+    assert res[2]["queue_ms"] > 0
+    srv.destroy()
+    # a request larger than the budget is rejected at submission, never queued
+    srv = scr.Server(ctx, max_slots=2, hbm_budget=int(fp * 0.5))
+    with pytest.raises(scr.ScrError) as e:
+        srv.submit(big["K"], big["coords"], big["b"], [torch.zeros_like(b) for b in big["b"]])
+    assert e.value.status == scr.SCR_E_OOM
+    srv.destroy()
+    ctx.destroy()
+
+
+def test_failing_request_is_isolated(scr, systems):
+    ctx = scr.Context(0)
+    srv = scr.Server(ctx, max_slots=2)
+    good = systems[1]
+    bad_ci = good["K"][1].clone()
+    bad_ci[[3, 4]] = bad_ci[[4, 3]]            # unsorted columns
+    xg = [torch.zeros_like(b) for b in good["b"]]
+    xb = [torch.zeros_like(b) for b in good["b"]]
+    i_bad = srv.submit((good["K"][0], bad_ci, good["K"][2]), good["coords"], good["b"], xb)
+    i_good = srv.submit(good["K"], good["coords"], good["b"], xg)
+    rb, rg = srv.wait(i_bad), srv.wait(i_good)
+    assert rb["status"] == scr.SCR_E_INVALID
+    assert rg["status"] == 0
+    xa, _ = _alone(scr, ctx, good)
+    assert np.array_equal(xg[0].cpu().numpy(), xa[0])
+    srv.destroy()
+    assert ctx.bytes_in_use() == 0
+    ctx.destroy()
