@@ -36,6 +36,12 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 1 GiB elementwise copy (read 1 GiB, write 1 GiB) before the steps, "
                          "as the calibration kernel of the rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving stream instead of the single-system step: seeded tube requests of random "
+                         "geometry through the continuous-batching server (mixed precision)")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturation")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/ and exit")
     return ap.parse_args()
@@ -145,6 +151,129 @@ def cpu_baseline(s, b, bm, args):
             "step_s_estimate": round(total, 2)}
 
 
+def _serve_requests(n, seed):
+    """Per request: length U[2,10], radius U[0.5,1.5], node count log-uniform in [20k, 400k],
+    1-4 successive corrections; unit-rate exponential gaps (scaled by the arrival rate later)."""
+    rng = np.random.default_rng(seed)
+    return dict(L=rng.uniform(2.0, 10.0, n), R=rng.uniform(0.5, 1.5, n),
+                N=np.exp(rng.uniform(math.log(2e4), math.log(4e5), n)), c=rng.integers(1, 5, n),
+                gaps=rng.exponential(1.0, n))
+
+
+def serve_bench(args):
+    """Serving stream: a saturation pass (every request submitted at t = 0; its makespan gives the
+    throughput) then a Poisson pass at args.load x that rate (request latency = arrival -> last
+    correction done).  Inputs of every request are resident in HBM before either pass."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    import synth
+    import paper_2206_06996_amd.scr as scr
+
+    spec = _serve_requests(args.requests, 0)
+    n = args.requests
+
+    def make(r):
+        s = synth.generate(synth.tube_params(spec["N"][r], spec["R"][r], spec["L"][r]))
+        mm = np.repeat(s.Lmask, 3)
+        b = [synth.rhs(1_000_003 * (r + 1) + c, 4 * s.n_b, s.mask) for c in range(spec["c"][r])]
+        bm = [synth.rhs(2_000_003 * (r + 1) + c, 3 * s.n_phys, mm) for c in range(spec["c"][r])]
+        return s, b, bm
+
+    t0 = time.time()
+    gen = ThreadPoolExecutor(8)
+    futs = [gen.submit(make, r) for r in range(n)]
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    reqs = []
+    for r, f in enumerate(futs):
+        s, b, bm = f.result()
+        futs[r] = None
+        reqs.append(dict(K=(dev(s.rp), dev(s.ci), dev(s.val.reshape(-1))), coords=dev(s.xyz.reshape(-1)),
+                         L=(dev(s.Lrp), dev(s.Lci), dev(s.Lval)), b=[dev(v) for v in b], bm=[dev(v) for v in bm],
+                         n_b=int(s.n_b), nnzb=int(s.nnzb), nodes=int(s.n_phys)))
+        if (r + 1) % 32 == 0:
+            log(f"[serve] generated {r + 1}/{n} requests ({time.time() - t0:.0f}s)", args)
+    gen.shutdown()
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    ctx = scr.Context(0)
+    ao = scr.amg_opts(precision=scr.SCR_MIXED)
+    so = scr.solve_opts()
+    n_rhs = int(sum(len(q["b"]) for q in reqs))
+    log(f"[serve] {n} requests, {n_rhs} right-hand sides, nodes {min(q['nodes'] for q in reqs)}-"
+        f"{max(q['nodes'] for q in reqs)}; budget {budget / 2**30:.1f} GiB, {args.slots} slots", args)
+
+    def run(arrivals):
+        srv = scr.Server(ctx, max_slots=args.slots, hbm_budget=budget, amg=ao, solve=so)
+        outs = [([torch.zeros_like(v) for v in q["b"]], [torch.zeros_like(v) for v in q["bm"]]) for q in reqs]
+        torch.cuda.synchronize()
+        ids = [None] * n
+        t_start = time.perf_counter()
+
+        def feeder():
+            for r in range(n):
+                dt = t_start + arrivals[r] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                q = reqs[r]
+                ids[r] = srv.submit(q["K"], q["coords"], q["b"], outs[r][0], L=q["L"], bms=q["bm"], xms=outs[r][1])
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        res = []
+        for r in range(n):
+            while ids[r] is None:
+                time.sleep(1e-4)
+            res.append(srv.wait(ids[r]))
+            if (r + 1) % 32 == 0:
+                log(f"[serve] {r + 1}/{n} done ({time.perf_counter() - t_start:.1f}s)", args)
+        th.join()
+        max_active = srv.drain()
+        makespan = time.perf_counter() - t_start
+        srv.destroy()
+        bad = [(r, x["status"], x["last"]["rel_res_true"]) for r, x in enumerate(res)
+               if x["status"] != 0 or x["last"]["rel_res_true"] > so.tol]
+        if bad:
+            raise RuntimeError(f"serving: requests failed or missed the tolerance: {bad[:5]}")
+        lat = np.array([x["latency_ms"] for x in res])
+        per_rhs = np.array([x["solve_ms"] / x["n_solves"] for x in res])
+        return dict(makespan_s=round(makespan, 3), solves_per_s=round(n_rhs / makespan, 4),
+                    requests_per_s=round(n / makespan, 4), max_active=max_active,
+                    p50_ms=round(float(np.percentile(lat, 50)), 1), p99_ms=round(float(np.percentile(lat, 99)), 1),
+                    queue_p50_ms=round(float(np.percentile([x["queue_ms"] for x in res], 50)), 1),
+                    per_rhs_p50_ms=round(float(np.percentile(per_rhs, 50)), 1),
+                    per_rhs_p99_ms=round(float(np.percentile(per_rhs, 99)), 1),
+                    outer_it_max=int(max(x["last"]["outer_it"] for x in res)),
+                    max_rel_res=float(max(x["last"]["rel_res_true"] for x in res)))
+
+    warm = reqs[0]
+    h = scr.amg_setup(ctx, scr.SCR_SYSTEM, *warm["K"], warm["coords"], ao)
+    scr.scr_solve(h, warm["b"][0], torch.zeros_like(warm["b"][0]), so)
+    h.destroy()
+    sat = run(np.zeros(n))
+    log(f"[serve] saturation: {sat}", args)
+    rate = args.load * sat["requests_per_s"]
+    arrivals = np.cumsum(spec["gaps"]) / rate
+    poi = run(arrivals)
+    poi["arrival_rate_per_s"] = round(rate, 4)
+    log(f"[serve] poisson: {poi}", args)
+    ctx.destroy()
+    out = {
+        "metric": "SCR+AMG solves/s at 1e-8 rel. resid (FP64 vs mixed); p50/p99 solve latency",
+        "value": sat["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": n, "warmup": 1,
+        "ms_per_step": round(1e3 * sat["makespan_s"] / n_rhs, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic (seeded tube requests, seeded RHS)",
+        "config": {"workload": f"serving stream: {n} unified tube requests (L U[2,10], R U[0.5,1.5], nodes "
+                               f"log-U[20k,400k], 1-4 corrections each, {n_rhs} right-hand sides) + mesh motion",
+                   "precision": "mixed", "tol": so.tol, "slots": args.slots},
+        "saturation": sat, "poisson": poi, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def log(msg, args=None):
     if not (args and args.quiet):
         print(msg, file=sys.stderr, flush=True)
@@ -159,6 +288,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
     import torch
     import synth
     import paper_2206_06996_amd.scr as scr
