@@ -74,7 +74,7 @@ def pmc_traffic():
 
 
 COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
-SMOOTH_KERNEL = "smooth_k<double, 3, true, false, false>"
+SMOOTH_KERNEL = "smooth_rl3_k<double, true, false, false>"
 
 
 def _pmc_rows(d, counter):
@@ -238,6 +238,12 @@ def serve_bench(args):
                if x["status"] != 0 or x["last"]["rel_res_true"] > so.tol]
         if bad:
             raise RuntimeError(f"serving: requests failed or missed the tolerance: {bad[:5]}")
+        if args.requests <= 32 or arrivals.max() == 0:
+            for r, x in enumerate(res):
+                st = x["last"]
+                log(f"[serve]   req {r:3d} nodes {reqs[r]['nodes']:6d} R {spec['R'][r]:.2f} L {spec['L'][r]:.2f} "
+                    f"rhs {x['n_solves']} queue {x['queue_ms']:8.1f} setup {x['setup_ms']:7.1f} solve {x['solve_ms']:8.1f} ms "
+                    f"outer {st['outer_it']} its_A {st['its_A']} its_S {st['its_S']} vA {st['vcycles_A']}", args)
         lat = np.array([x["latency_ms"] for x in res])
         per_rhs = np.array([x["solve_ms"] / x["n_solves"] for x in res])
         return dict(makespan_s=round(makespan, 3), solves_per_s=round(n_rhs / makespan, 4),
@@ -413,7 +419,7 @@ def main():
                            "frac": round(pr["gbs"] / HBM_PEAK_GBS, 4),
                            "traffic": None if traffic is None else round(traffic / (pr["avg_us"] * 1e-6) / 1e9, 1),
                            "traffic_bytes_per_launch": traffic,
-                           "kernel": "smooth_k: fused Chebyshev step on level 0 of AMG(A) (3x3 FP64 blocks)",
+                           "kernel": "smooth_rl3_k: fused Chebyshev step on level 0 of AMG(A) (3x3 FP64 blocks, block-row lanes)",
                            "launches": pr["launches"], "avg_us": round(pr["avg_us"], 2),
                            "alg_bytes_per_launch": int(pr["bytes_per_launch"])}
     else:

@@ -190,7 +190,9 @@ struct DBsr {
     double* v = nullptr;
 };
 
-// Sliced ELL with one lane per SCALAR row.  A slice is one wavefront covering rps = 64/br block
+// Sliced ELL, two lane mappings.
+//
+// Scalar-row lanes (every shape but 3x3).  A slice is one wavefront covering rps = 64/br block
 // rows (lanes = rps*br; the rest idle), so the br lanes of a block row share a wavefront.  Lane
 // (block row i, row r) reads, for every slot t of the slice, the column block index of block row
 // i (stored once per block row) and row r of that block (bc values); each of the bc entries of a
@@ -198,16 +200,27 @@ struct DBsr {
 // is needed.
 //   col of (slice s, slot t, block row j of the slice):   ci[(off[s] + t) * rps + j]
 //   entry k of lane l's row segment:                       v[((off[s] + t) * bc + k) * 64 + l]
+//
+// Block-row lanes (3x3 blocks: the velocity block and its FP32 copy).  A slice is one wavefront
+// covering rps = 64 block rows, one per lane; the lane computes all three rows of its block row.
+// Each lane gathers the 3-vector of x at its column once (the scalar-row mapping gathers it
+// three times, once per row lane), which is what the velocity block's sweeps are bound by.
+//   col of (slice s, slot t, lane l):                      ci[(off[s] + t) * 64 + l]
+//   entry e = 3r + k of the block at (s, t, l):            v[((off[s] + t) * 9 + e) * 64 + l]
+//
 // Rows shorter than the slice are padded with zero entries pointing at a valid column.  Within
-// windows of SELL_SIGMA slices, block rows are ordered by decreasing length (ties by index) so
-// that rows of similar length share a slice; rowid maps slice positions back to block rows
-// (-1 = empty position).
+// windows of sigma slices, block rows are ordered by decreasing length (ties by index) so that
+// rows of similar length share a slice; rowid maps slice positions back to block rows (-1 =
+// empty position).  sigma trades padding against the spread of the gathered x entries: 16
+// slices of 21 rows for scalar-row lanes, 6 slices of 64 rows for block-row lanes (measured).
 constexpr int SELL_SIGMA = 16;
+constexpr int SELL_SIGMA_ROWLANE = 6;
 template <typename T>
 struct DSell {
     int64_t nr = 0, nc = 0;
     int br = 0, bc = 0;
     int rps = 0;                // block rows per slice
+    bool rowlane = false;       // block-row lanes (3x3) instead of scalar-row lanes
     int64_t nslices = 0;
     int64_t slots = 0;          // sum over slices of the slice length
     int64_t nnzb = 0;           // stored blocks before padding (algorithmic count)

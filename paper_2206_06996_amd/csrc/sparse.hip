@@ -187,16 +187,43 @@ __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restr
     }
 }
 
+// block-row lanes: one thread per (slice, lane) = block row; all br*bc entries of each slot
+template <typename T>
+__global__ void sell_fill_rowlane(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  const double* __restrict__ v, int nb2, const int32_t* __restrict__ rowid,
+                                  const int32_t* __restrict__ off, int32_t* __restrict__ sci, T* __restrict__ sv,
+                                  int64_t nslices) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = g / WAVE;
+    if (s >= nslices) return;
+    int lane = (int)(g % WAVE);
+    int64_t i = rowid[g];
+    int32_t lo = 0, hi = 0, pad = 0;
+    if (i >= 0) {
+        lo = rp[i]; hi = rp[i + 1];
+        pad = hi > lo ? ci[hi - 1] : 0;
+    }
+    int64_t o0 = off[s], o1 = off[s + 1];
+    for (int64_t t = o0; t < o1; ++t) {
+        int64_t q = lo + (t - o0);
+        bool real = i >= 0 && q < hi;
+        sci[t * WAVE + lane] = real ? ci[q] : pad;
+        for (int e = 0; e < nb2; ++e) sv[(t * nb2 + e) * WAVE + lane] = real ? (T)v[q * nb2 + e] : (T)0;
+    }
+}
+
 template <typename T>
 DSell<T> sell_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
     DSell<T> S;
     S.nr = A.nr; S.nc = A.nc; S.br = A.br; S.bc = A.bc; S.nnzb = A.nnzb;
-    S.rps = WAVE / A.br;
+    S.rowlane = A.br == 3 && A.bc == 3;
+    S.rps = S.rowlane ? WAVE : WAVE / A.br;
     S.nslices = cdiv(A.nr, S.rps);
     if (S.nslices == 0) return S;
     S.rowid = ar.make<int32_t>(S.nslices * S.rps);
     fill_i32(S.rowid, -1, S.nslices * S.rps, s);
-    sell_rank_k<<<cdiv(A.nr, 256), 256, 0, s>>>(A.rp, A.nr, (int64_t)SELL_SIGMA * S.rps, S.rowid);
+    int64_t win = (int64_t)(S.rowlane ? SELL_SIGMA_ROWLANE : SELL_SIGMA) * S.rps;
+    sell_rank_k<<<cdiv(A.nr, 256), 256, 0, s>>>(A.rp, A.nr, win, S.rowid);
     int32_t* len = ar.make<int32_t>(S.nslices);
     sell_slice_len<<<cdiv(S.nslices, 256), 256, 0, s>>>(A.rp, S.rowid, S.rps, S.nslices, len);
     check_launch("sell_slice_len");
@@ -204,9 +231,15 @@ DSell<T> sell_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
     S.slots = scan_i32(len, S.off, S.nslices, ar, s);
     ar.free(len);
     S.ci = ar.make<int32_t>(S.slots * S.rps + 1);
-    S.v = ar.make<T>(S.slots * WAVE * A.bc + 1);
-    sell_fill<T><<<cdiv(S.nslices * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br, A.bc, S.rps, S.rowid, S.off,
-                                                            S.ci, S.v, S.nslices);
+    if (S.rowlane) {
+        S.v = ar.make<T>(S.slots * WAVE * A.br * A.bc + 1);
+        sell_fill_rowlane<T><<<cdiv(S.nslices * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br * A.bc, S.rowid, S.off,
+                                                                        S.ci, S.v, S.nslices);
+    } else {
+        S.v = ar.make<T>(S.slots * WAVE * A.bc + 1);
+        sell_fill<T><<<cdiv(S.nslices * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br, A.bc, S.rps, S.rowid, S.off,
+                                                                S.ci, S.v, S.nslices);
+    }
     check_launch("sell_fill");
     return S;
 }
@@ -303,6 +336,71 @@ __global__ void __launch_bounds__(256) sell_mv_k(int64_t nslices, const int32_t*
     else y[o] -= acc;
 }
 
+// ---- block-row lanes (3x3): r[0..2] = sum over the lane's slots of block * x[col]
+// Two slots per step: both slots' columns, then their 18 values and two x 3-vectors are loaded
+// before use.  FP64 values are streamed with nontemporal loads (read once per call; measured: a
+// gain in FP64, a loss in FP32).
+template <typename T>
+__device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, const int32_t* __restrict__ ci,
+                                             const T* __restrict__ v, const T* __restrict__ x, T r[3]) {
+    auto ld = [](const T* p) -> T {
+        if (sizeof(T) == 8) return __builtin_nontemporal_load(p);
+        return *p;
+    };
+    r[0] = r[1] = r[2] = 0;
+    for (; t + 2 <= o1; t += 2) {
+        int64_t c[2];
+        T vv[2][9], xx[2][3];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) c[u] = ci[(t + u) * WAVE + lane];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) vv[u][e] = ld(v + ((t + u) * 9 + e) * WAVE + lane);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xx[u][k] = x[c[u] * 3 + k];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                r[q] += vv[u][3 * q] * xx[u][0] + vv[u][3 * q + 1] * xx[u][1] + vv[u][3 * q + 2] * xx[u][2];
+    }
+    if (t < o1) {
+        int64_t c = ci[t * WAVE + lane];
+        T vv[9], xx[3];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) vv[e] = ld(v + (t * 9 + e) * WAVE + lane);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xx[k] = x[c * 3 + k];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) r[q] += vv[3 * q] * xx[0] + vv[3 * q + 1] * xx[1] + vv[3 * q + 2] * xx[2];
+    }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) sell_mv_rl3_k(int64_t nslices, const int32_t* __restrict__ off,
+                                                     const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
+                                                     const T* __restrict__ v, const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y) {
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * 4 + threadIdx.x / WAVE;
+    if (sl >= nslices) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    T r[3];
+    rowlane3_dot<T>(off[sl], off[sl + 1], lane, ci, v, x, r);
+    int64_t i = rowid[sl * WAVE + lane];
+    if (i < 0) return;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int64_t o = i * 3 + q;
+        if (MODE == 0) y[o] = r[q];
+        else if (MODE == 1) y[o] = b[o] - r[q];
+        else if (MODE == 2) y[o] += r[q];
+        else y[o] -= r[q];
+    }
+}
+
 template <typename T, int BR, int BC>
 static void sell_mv_dispatch_mode(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStream_t s) {
     int64_t nblk = cdiv(A.nslices, 4);
@@ -318,6 +416,18 @@ static void sell_mv_dispatch_mode(const DSell<T>& A, const T* x, const T* b, T* 
 
 template <typename T>
 void sell_mv(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStream_t s) {
+    if (A.rowlane) {
+        int64_t nblk = cdiv(A.nslices, 4);
+        if (nblk == 0) return;
+        switch (mode) {
+            case 0: sell_mv_rl3_k<T, 0><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+            case 1: sell_mv_rl3_k<T, 1><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+            case 2: sell_mv_rl3_k<T, 2><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+            default: sell_mv_rl3_k<T, 3><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+        }
+        check_launch("sell_mv");
+        return;
+    }
     int key = A.br * 10 + A.bc;
     switch (key) {
         case 11: sell_mv_dispatch_mode<T, 1, 1>(A, x, b, y, mode, s); break;
@@ -441,6 +551,62 @@ __global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* 
     xout[o] = ZERO ? dn : xin[o] + dn;
 }
 
+// block-row lanes (3x3): the lane holds its block row's whole residual, so D^-1 applies in-lane
+template <typename T, bool RD, bool WD, bool ZERO>
+__global__ void __launch_bounds__(256) smooth_rl3_k(int64_t nslices, const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ rowid,
+                                                    const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                    const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                    const T* __restrict__ xin, T* __restrict__ d, T* __restrict__ xout,
+                                                    T c1, T c2) {
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * 4 + threadIdx.x / WAVE;
+    if (sl >= nslices) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    T r[3] = {0, 0, 0};
+    if (!ZERO) rowlane3_dot<T>(off[sl], off[sl + 1], lane, ci, v, xin, r);
+    int64_t i = rowid[sl * WAVE + lane];
+    if (i < 0) return;
+    T res[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) res[q] = b[i * 3 + q] - r[q];
+    const T* Di = Dinv + i * 9;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int64_t o = i * 3 + q;
+        T z = Di[3 * q] * res[0] + Di[3 * q + 1] * res[1] + Di[3 * q + 2] * res[2];
+        T dn = c2 * z;
+        if (RD) dn += c1 * d[o];
+        if (WD) d[o] = dn;
+        xout[o] = ZERO ? dn : xin[o] + dn;
+    }
+}
+
+template <typename T>
+static void smooth_rl3(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, T c1, T c2,
+                       bool rd, bool wd, bool zero, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    int64_t nblk = cdiv(A.nslices, 4);
+    if (nblk == 0) return;
+#define SK(RD, WD, Z)                                                                                              \
+    do {                                                                                                           \
+        if (e0)                                                                                                    \
+            hipExtLaunchKernelGGL((smooth_rl3_k<T, RD, WD, Z>), dim3((unsigned)nblk), dim3(256), 0, s, e0, e1, 0,  \
+                                  A.nslices, (const int32_t*)A.off, (const int32_t*)A.rowid, (const int32_t*)A.ci, \
+                                  (const T*)A.v, Dinv, b, xin, d, xout, c1, c2);                                   \
+        else                                                                                                       \
+            smooth_rl3_k<T, RD, WD, Z><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin, d, \
+                                                           xout, c1, c2);                                          \
+    } while (0)
+    if (zero) {
+        if (wd) SK(false, true, true); else SK(false, false, true);
+    } else if (rd) {
+        if (wd) SK(true, true, false); else SK(true, false, false);
+    } else {
+        if (wd) SK(false, true, false); else SK(false, false, false);
+    }
+#undef SK
+    check_launch("smooth_step");
+}
+
 template <typename T, int B>
 static void smooth_dispatch(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, T c1, T c2,
                             bool rd, bool wd, bool zero, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -472,7 +638,10 @@ void smooth_step(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* 
                  bool read_d, bool write_d, bool zero_in, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (A.br) {
         case 1: smooth_dispatch<T, 1>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1); break;
-        case 3: smooth_dispatch<T, 3>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1); break;
+        case 3:
+            if (A.rowlane) smooth_rl3<T>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1);
+            else smooth_dispatch<T, 3>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1);
+            break;
         case 6: smooth_dispatch<T, 6>(A, Dinv, b, xin, d, xout, (T)c1, (T)c2, read_d, write_d, zero_in, s, e0, e1); break;
         default: throw Error(SCR_E_UNIMPLEMENTED, "smooth_step: block size");
     }
