@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("bl_ratio", C.c_double), ("rho_f", C.c_double), ("mu_f", C.c_double),
                 ("rho_s", C.c_double), ("E_s", C.c_double), ("nu_s", C.c_double), ("dt", C.c_double),
                 ("rho_inf", C.c_double), ("terms", C.c_int), ("apply_bc", C.c_int),
-                ("vms_dt_coupling", C.c_int), ("box_solid", C.c_int)]
+                ("vms_dt_coupling", C.c_int), ("box_solid", C.c_int), ("y_h", C.c_double),
+                ("y_rd", C.c_double), ("y_ld", C.c_double), ("y_th1", C.c_double), ("y_th2", C.c_double)]
 
 
 def _load():
@@ -71,7 +72,8 @@ def default_params(**kw) -> Params:
     rho_inf=0.5; solid E=1e6, nu=0.45, rho_s=1.0 (cgs units as in the paper's Section 6)."""
     p = Params(mode=0, m_core=6, n_bl=0, n_wall=0, nz=40, R=1.0, L=5.0, wall_ratio=1.2,
                bl_ratio=0.6, rho_f=1.06, mu_f=0.04, rho_s=1.0, E_s=1.0e6, nu_s=0.45, dt=1.0e-3,
-               rho_inf=0.5, terms=31, apply_bc=1, vms_dt_coupling=0, box_solid=0)
+               rho_inf=0.5, terms=31, apply_bc=1, vms_dt_coupling=0, box_solid=0, y_h=0.0, y_rd=0.7,
+               y_ld=5.0, y_th1=0.0, y_th2=0.0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -182,6 +184,27 @@ def tube_params(n_nodes: float, R: float, L: float) -> Params:
             best = (n, m_core, n_bl, n_wall, nz)
     _, m_core, n_bl, n_wall, nz = best
     return default_params(mode=0, m_core=m_core, n_bl=n_bl, n_wall=n_wall, nz=nz, R=R, L=L)
+
+
+def y_params(n_nodes: float | None = None, seed: int = 0, h: float | None = None, Lp: float = 5.0,
+             Ld: float = 5.0) -> Params:
+    """Y-bifurcation on a voxel grid: parent radius 1 and length Lp along +z up to the junction,
+    daughters of radius 0.7 and length Ld at seeded angles U[30, 60] degrees from the z axis in
+    the x-z plane (one toward +x, one toward -x), wall out to 1.2x the local radius.  The voxel
+    spacing is h, or chosen so that the mesh has about n_nodes nodes."""
+    rng = np.random.default_rng(seed)
+    th1, th2 = np.deg2rad(rng.uniform(30.0, 60.0, 2))
+    if h is None:
+        W, rd = 1.2, 0.7
+        vol = math.pi * W ** 2 * Lp + 2 * math.pi * (W * rd) ** 2 * Ld + 4.0 / 3.0 * math.pi * W ** 3 / 2
+        h = (vol / n_nodes) ** (1.0 / 3.0)
+    return default_params(mode=2, R=1.0, L=Lp, wall_ratio=1.2, y_h=h, y_rd=0.7, y_ld=Ld, y_th1=float(th1),
+                          y_th2=float(th2))
+
+
+def cfg4_params() -> Params:
+    """Largest single-GPU workload: the Y-bifurcation with about 4.0M nodes (angle seed 0)."""
+    return y_params(4.0e6, seed=0)
 
 
 def tiny_annulus_params() -> Params:

@@ -26,6 +26,17 @@
  * Interface pressure duplication (Sec. 3.3): every node on the lumen/wall interface gets a
  * "virtual" block row right after it; solid elements use it for pressure, the physical
  * node for velocity; its velocity slots are identity rows.
+ * Y-bifurcation (mode 2).  A uniform voxel grid of spacing h; the lumen is a union of three
+ * branches (parent of radius R along +z ending at the junction, two daughters of radius rd*R
+ * leaving the junction at angles th1, th2 from the z axis in the x-z plane), each a cylinder
+ * with a spherical cap at the junction end and a flat cut at its free end; the wall is every
+ * branch dilated to wall_ratio times its radius.  A voxel is kept when its centre lies in the
+ * wall region; each kept voxel is cut into the six Kuhn tetrahedra (unmirrored), and a tetrahedron
+ * is fluid when its centroid lies in the lumen.  The fluid/solid interface is the set of faces
+ * between fluid and solid tetrahedra (a staircase, conforming by construction).  Velocity
+ * Dirichlet: every node of the inlet plane, and solid-touching nodes within h of a daughter's
+ * outlet cut; mesh motion Dirichlet: every node touching a solid tetrahedron, the inlet plane and
+ * the outlet layers.
  * Mesh motion (Sec. 2.2.2 harmonic extension, stiffened by 1/element volume): scalar
  * Laplacian over all physical nodes; every node not strictly inside the lumen is Dirichlet.
  * Dirichlet dofs are eliminated symmetrically (row and column zeroed, unit diagonal).
@@ -36,7 +47,7 @@
 #include <string.h>
 
 typedef struct {
-    int mode;        /* 0 = tube (disk-mapped shells), 1 = box (uniform, unmirrored Kuhn) */
+    int mode;        /* 0 = tube (disk-mapped shells), 1 = box (uniform, unmirrored Kuhn), 2 = Y voxels */
     int m_core;      /* tube: uniform core shells;          box: nx */
     int n_bl;        /* tube: boundary-layer shells;         box: ny */
     int n_wall;      /* tube: solid wall shells (0 = fluid only) */
@@ -50,6 +61,10 @@ typedef struct {
     int apply_bc;    /* 1: Dirichlet elimination; 0: natural boundaries everywhere */
     int vms_dt_coupling; /* 1: add c_t*rho*tau_M*(V/4)*dN_a/dx_j to D (fluid) */
     int box_solid;   /* box only: 1 = every element is solid */
+    double y_h;      /* Y: voxel spacing */
+    double y_rd;     /* Y: daughter radius / parent radius */
+    double y_ld;     /* Y: daughter length (parent length is L) */
+    double y_th1, y_th2; /* Y: daughter angles from the z axis (radians), toward +x and -x */
 } synth_params;
 
 typedef struct {
@@ -248,6 +263,183 @@ static int cmp_i32(const void* a, const void* b) {
     return (x > y) - (x < y);
 }
 
+/* ---- Y-bifurcation geometry ---- */
+typedef struct {
+    double a[3], u[3];  /* branch start and unit direction */
+    double len, r;      /* length and lumen radius */
+    int cap_at_end;     /* 1: spherical cap at the far end (parent), 0: at the start (daughters) */
+} y_branch;
+
+static void y_branches(const synth_params* p, y_branch b[3]) {
+    double R = p->R, rd = p->y_rd * p->R;
+    y_branch* q = &b[0];
+    q->a[0] = 0.0; q->a[1] = 0.0; q->a[2] = -p->L; q->u[0] = 0.0; q->u[1] = 0.0; q->u[2] = 1.0;
+    q->len = p->L; q->r = R; q->cap_at_end = 1;
+    for (int d = 0; d < 2; ++d) {
+        q = &b[1 + d];
+        double th = d == 0 ? p->y_th1 : p->y_th2, sg = d == 0 ? 1.0 : -1.0;
+        q->a[0] = q->a[1] = q->a[2] = 0.0;
+        q->u[0] = sg * sin(th); q->u[1] = 0.0; q->u[2] = cos(th);
+        q->len = p->y_ld; q->r = rd; q->cap_at_end = 0;
+    }
+}
+
+/* distance from x to branch q relative to its radius; a large value outside the free-end cut */
+static double y_rel(const y_branch* q, const double* x) {
+    double d[3] = {x[0] - q->a[0], x[1] - q->a[1], x[2] - q->a[2]};
+    double t = d[0] * q->u[0] + d[1] * q->u[1] + d[2] * q->u[2];
+    if (q->cap_at_end ? t < 0.0 : t > q->len) return 1e30;
+    if (q->cap_at_end ? t > q->len : t < 0.0) {
+        double c = q->cap_at_end ? q->len : 0.0;
+        double e[3] = {d[0] - c * q->u[0], d[1] - c * q->u[1], d[2] - c * q->u[2]};
+        return sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]) / q->r;
+    }
+    double e[3] = {d[0] - t * q->u[0], d[1] - t * q->u[1], d[2] - t * q->u[2]};
+    return sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]) / q->r;
+}
+static double y_min_rel(const y_branch b[3], const double* x) {
+    double m = 1e30;
+    for (int k = 0; k < 3; ++k) { double v = y_rel(&b[k], x); if (v < m) m = v; }
+    return m;
+}
+
+/* Voxels, nodes, tetrahedra and Dirichlet flags of the Y (mode 2).  Fills the mesh part of s;
+ * vdir / mdir get one flag per physical node. */
+static int build_y(const synth_params* p, synth_sys* s, uint8_t** vdir_out, uint8_t** mdir_out) {
+    y_branch br[3];
+    y_branches(p, br);
+    double h = p->y_h, W = p->wall_ratio;
+    double lo[3] = {-W * p->R, -W * p->R, -p->L}, hi[3] = {W * p->R, W * p->R, 0.0};
+    for (int d = 1; d < 3; ++d) {
+        double ew = W * br[d].r;
+        for (int c = 0; c < 3; ++c) {
+            double e = br[d].a[c] + br[d].len * br[d].u[c];
+            if (e - ew < lo[c]) lo[c] = e - ew;
+            if (e + ew > hi[c]) hi[c] = e + ew;
+        }
+    }
+    lo[2] = -p->L;   /* the inlet plane is a grid plane */
+    int nc[3];
+    for (int c = 0; c < 3; ++c) nc[c] = (int)ceil((hi[c] - lo[c]) / h) + 1;
+    int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t ngn = (int64_t)(nc[0] + 1) * (nc[1] + 1) * (nc[2] + 1);
+    if (ngn > INT32_MAX) return -2;
+    uint8_t* keep = (uint8_t*)calloc(ncell, 1);
+    int32_t* gid = (int32_t*)malloc(sizeof(int32_t) * ngn);
+    if (!keep || !gid) { free(keep); free(gid); return -3; }
+    for (int64_t g = 0; g < ngn; ++g) gid[g] = -1;
+    int64_t nx1 = nc[0] + 1, nxy1 = (int64_t)(nc[0] + 1) * (nc[1] + 1);
+    int64_t nkept = 0;
+    for (int k = 0; k < nc[2]; ++k)
+        for (int j = 0; j < nc[1]; ++j)
+            for (int i = 0; i < nc[0]; ++i) {
+                double x[3] = {lo[0] + (i + 0.5) * h, lo[1] + (j + 0.5) * h, lo[2] + (k + 0.5) * h};
+                if (y_min_rel(br, x) < W) {
+                    keep[i + (int64_t)nc[0] * (j + (int64_t)nc[1] * k)] = 1;
+                    ++nkept;
+                    for (int c = 0; c < 8; ++c)
+                        gid[(i + (c & 1)) + nx1 * (j + ((c >> 1) & 1)) + nxy1 * (k + (c >> 2))] = 0;
+                }
+            }
+    /* physical nodes in grid order */
+    int64_t n_phys = 0;
+    for (int64_t g = 0; g < ngn; ++g) if (gid[g] == 0) gid[g] = (int32_t)n_phys++;
+    s->n_phys = n_phys; s->S = nc[0] + 1; s->nzn = nc[2] + 1;
+    s->xyz_phys = (double*)malloc(sizeof(double) * 3 * n_phys);
+    int32_t* gk = (int32_t*)malloc(sizeof(int32_t) * n_phys);
+    for (int64_t g = 0; g < ngn; ++g)
+        if (gid[g] >= 0) {
+            int64_t n = gid[g];
+            int i = (int)(g % nx1), j = (int)((g / nx1) % (nc[1] + 1)), k = (int)(g / nxy1);
+            s->xyz_phys[3 * n] = lo[0] + i * h; s->xyz_phys[3 * n + 1] = lo[1] + j * h;
+            s->xyz_phys[3 * n + 2] = lo[2] + k * h;
+            gk[n] = k;
+        }
+    /* tetrahedra (physical vertex ids for now) and their fluid/solid class */
+    s->n_tets = 6 * nkept;
+    s->tv = (int32_t*)malloc(sizeof(int32_t) * 4 * s->n_tets);
+    s->tp = (int32_t*)malloc(sizeof(int32_t) * 4 * s->n_tets);
+    s->tsolid = (uint8_t*)malloc(s->n_tets);
+    uint8_t* touch = (uint8_t*)calloc(n_phys, 1);   /* bit 1: fluid tet, bit 2: solid tet */
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int64_t t = 0;
+    for (int k = 0; k < nc[2]; ++k)
+        for (int j = 0; j < nc[1]; ++j)
+            for (int i = 0; i < nc[0]; ++i) {
+                if (!keep[i + (int64_t)nc[0] * (j + (int64_t)nc[1] * k)]) continue;
+                for (int q = 0; q < 6; ++q) {
+                    int off[4][3] = {{0, 0, 0}};
+                    int cur[3] = {0, 0, 0};
+                    for (int st = 0; st < 3; ++st) {
+                        cur[perm[q][st]] = 1;
+                        off[st + 1][0] = cur[0]; off[st + 1][1] = cur[1]; off[st + 1][2] = cur[2];
+                    }
+                    int32_t v[4];
+                    double x[12], cen[3] = {0.0, 0.0, 0.0};
+                    for (int a = 0; a < 4; ++a) {
+                        v[a] = gid[(i + off[a][0]) + nx1 * (j + off[a][1]) + nxy1 * (k + off[a][2])];
+                        memcpy(x + 3 * a, s->xyz_phys + 3 * (int64_t)v[a], 3 * sizeof(double));
+                        for (int c = 0; c < 3; ++c) cen[c] += 0.25 * x[3 * a + c];
+                    }
+                    double dN[4][3];
+                    if (tet_grad(x, dN) < 0.0) { int32_t tmp = v[2]; v[2] = v[3]; v[3] = tmp; }
+                    int solid = !(y_min_rel(br, cen) < 1.0);
+                    for (int a = 0; a < 4; ++a) { s->tv[4 * t + a] = v[a]; touch[v[a]] |= (uint8_t)(solid ? 2 : 1); }
+                    s->tsolid[t] = (uint8_t)solid;
+                    ++t;
+                }
+            }
+    free(keep); free(gid);
+    /* block numbering: each interface node followed by its virtual (pressure) node */
+    s->blk_of_phys = (int32_t*)malloc(sizeof(int32_t) * n_phys);
+    s->virt_of_phys = (int32_t*)malloc(sizeof(int32_t) * n_phys);
+    int64_t nb = 0, nif = 0;
+    for (int64_t n = 0; n < n_phys; ++n) {
+        s->blk_of_phys[n] = (int32_t)nb++;
+        if (touch[n] == 3) { s->virt_of_phys[n] = (int32_t)nb++; ++nif; }
+        else s->virt_of_phys[n] = -1;
+    }
+    s->n_b = nb; s->n_iface = nif;
+    s->node_kind = (uint8_t*)malloc(nb);
+    s->xyz = (double*)malloc(sizeof(double) * 3 * nb);
+    for (int64_t n = 0; n < n_phys; ++n) {
+        int32_t b = s->blk_of_phys[n];
+        s->node_kind[b] = (uint8_t)(touch[n] == 1 ? 0 : (touch[n] == 2 ? 1 : 2));
+        memcpy(s->xyz + 3 * b, s->xyz_phys + 3 * n, 3 * sizeof(double));
+        if (s->virt_of_phys[n] >= 0) {
+            int32_t vv = s->virt_of_phys[n];
+            s->node_kind[vv] = 3;
+            memcpy(s->xyz + 3 * vv, s->xyz_phys + 3 * n, 3 * sizeof(double));
+        }
+    }
+    for (int64_t e = 0; e < s->n_tets; ++e)
+        for (int a = 0; a < 4; ++a) {
+            int32_t n = s->tv[4 * e + a];
+            s->tv[4 * e + a] = s->blk_of_phys[n];
+            s->tp[4 * e + a] = (s->tsolid[e] && s->virt_of_phys[n] >= 0) ? s->virt_of_phys[n] : s->blk_of_phys[n];
+        }
+    /* Dirichlet flags */
+    uint8_t* vdir = (uint8_t*)calloc(n_phys, 1);
+    uint8_t* mdir = (uint8_t*)calloc(n_phys, 1);
+    for (int64_t n = 0; n < n_phys; ++n) {
+        const double* x = s->xyz_phys + 3 * n;
+        int outlet = 0;
+        for (int d = 1; d < 3; ++d) {
+            double dd[3] = {x[0] - br[d].a[0], x[1] - br[d].a[1], x[2] - br[d].a[2]};
+            double tt = dd[0] * br[d].u[0] + dd[1] * br[d].u[1] + dd[2] * br[d].u[2];
+            double e[3] = {dd[0] - tt * br[d].u[0], dd[1] - tt * br[d].u[1], dd[2] - tt * br[d].u[2]};
+            double rr = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+            if (tt > br[d].len - h && rr < W * br[d].r + h) outlet = 1;
+        }
+        int inlet = gk[n] == 0;
+        vdir[n] = (uint8_t)(inlet || (outlet && (touch[n] & 2)));
+        mdir[n] = (uint8_t)(inlet || outlet || (touch[n] & 2));
+    }
+    free(touch); free(gk);
+    *vdir_out = vdir; *mdir_out = mdir;
+    return 0;
+}
+
 void synth_free(synth_sys* s) {
     if (!s) return;
     free(s->blk_of_phys); free(s->virt_of_phys); free(s->node_kind); free(s->xyz); free(s->xyz_phys);
@@ -258,8 +450,8 @@ void synth_free(synth_sys* s) {
 }
 
 /* Build the system.  Returns 0 on success, <0 on failure. */
-int synth_build(const synth_params* p, synth_sys** out) {
-    synth_sys* s = (synth_sys*)calloc(1, sizeof(synth_sys));
+/* Mesh of the tube (mode 0) and box (mode 1): fills the mesh part of s and the Dirichlet flags. */
+static int build_structured(const synth_params* p, synth_sys* s, uint8_t** vdir_out, uint8_t** mdir_out) {
     int box = (p->mode == 1);
     int m = box ? 0 : p->m_core + p->n_bl + p->n_wall;
     int mf = p->m_core + p->n_bl;
@@ -351,6 +543,34 @@ int synth_build(const synth_params* p, synth_sys** out) {
                     ++t;
                 }
             }
+    /* Dirichlet flags per physical node */
+    uint8_t* vdir = (uint8_t*)calloc(n_phys, 1);
+    uint8_t* mdir = (uint8_t*)calloc(n_phys, 1);
+    for (int64_t n = 0; n < n_phys; ++n) {
+        int k = (int)(n / ((int64_t)Sx * Sy));
+        int sh = shell[n];
+        if (box) {
+            int64_t rem = n % ((int64_t)Sx * Sy);
+            int i = (int)(rem % Sx), j = (int)(rem / Sx);
+            int side = (i == 0 || i == Sx - 1 || j == 0 || j == Sy - 1);
+            vdir[n] = (uint8_t)(side || k == 0);
+            mdir[n] = (uint8_t)(side || k == 0 || k == p->nz);
+        } else {
+            vdir[n] = (uint8_t)(!has_wall ? ((sh == m) || (k == 0)) : ((k == 0) || (sh >= mf && k == p->nz)));
+            mdir[n] = (uint8_t)((sh >= mf) || k == 0 || k == p->nz);
+        }
+    }
+    free(shell);
+    *vdir_out = vdir; *mdir_out = mdir;
+    return 0;
+}
+
+int synth_build(const synth_params* p, synth_sys** out) {
+    synth_sys* s = (synth_sys*)calloc(1, sizeof(synth_sys));
+    uint8_t *vdir = NULL, *mdir = NULL;
+    int rc = p->mode == 2 ? build_y(p, s, &vdir, &mdir) : build_structured(p, s, &vdir, &mdir);
+    if (rc != 0) { free(vdir); free(mdir); synth_free(s); return rc; }
+    int64_t nb = s->n_b, n_phys = s->n_phys;
     /* K pattern */
     int32_t* cols = (int32_t*)malloc(sizeof(int32_t) * ROWCAP * nb);
     uint8_t* cnt = (uint8_t*)calloc(nb, 1);
@@ -366,7 +586,7 @@ int synth_build(const synth_params* p, synth_sys** out) {
                 bad |= row_insert(cols, cnt, pa[a], pa[b]);
             }
     }
-    if (bad) { free(cols); free(cnt); free(shell); synth_free(s); return -1; }
+    if (bad) { free(cols); free(cnt); free(vdir); free(mdir); synth_free(s); return -1; }
     s->rp = (int32_t*)malloc(sizeof(int32_t) * (nb + 1));
     s->rp[0] = 0;
     for (int64_t b = 0; b < nb; ++b) {
@@ -402,21 +622,8 @@ int synth_build(const synth_params* p, synth_sys** out) {
     /* Dirichlet mask (velocity dofs only) */
     s->mask = (uint8_t*)calloc(4 * nb, 1);
     if (p->apply_bc) {
-        for (int64_t n = 0; n < n_phys; ++n) {
-            int k = (int)(n / ((int64_t)Sx * Sy));
-            int sh = shell[n];
-            int dir;
-            if (box) {
-                int64_t rem = n % ((int64_t)Sx * Sy);
-                int i = (int)(rem % Sx), j = (int)(rem / Sx);
-                dir = (i == 0 || i == Sx - 1 || j == 0 || j == Sy - 1 || k == 0);
-            } else if (!has_wall) {
-                dir = (sh == m) || (k == 0);
-            } else {
-                dir = (k == 0) || (sh >= mf && k == p->nz);
-            }
-            if (dir) for (int c = 0; c < 3; ++c) s->mask[4 * s->blk_of_phys[n] + c] = 1;
-        }
+        for (int64_t n = 0; n < n_phys; ++n)
+            if (vdir[n]) for (int c = 0; c < 3; ++c) s->mask[4 * s->blk_of_phys[n] + c] = 1;
         for (int64_t n = 0; n < n_phys; ++n)
             if (s->virt_of_phys[n] >= 0)
                 for (int c = 0; c < 3; ++c) s->mask[4 * s->virt_of_phys[n] + c] = 1;
@@ -485,18 +692,7 @@ int synth_build(const synth_params* p, synth_sys** out) {
         free(phys_of_blk);
         s->Lmask = (uint8_t*)calloc(n_phys, 1);
         if (p->apply_bc) {
-            for (int64_t n = 0; n < n_phys; ++n) {
-                int k = (int)(n / ((int64_t)Sx * Sy));
-                int dir;
-                if (box) {
-                    int64_t rem = n % ((int64_t)Sx * Sy);
-                    int i = (int)(rem % Sx), j = (int)(rem / Sx);
-                    dir = (i == 0 || i == Sx - 1 || j == 0 || j == Sy - 1 || k == 0 || k == p->nz);
-                } else {
-                    dir = (shell[n] >= mf) || k == 0 || k == p->nz;
-                }
-                s->Lmask[n] = (uint8_t)dir;
-            }
+            for (int64_t n = 0; n < n_phys; ++n) s->Lmask[n] = mdir[n];
             for (int64_t r = 0; r < n_phys; ++r)
                 for (int32_t q = s->Lrp[r]; q < s->Lrp[r + 1]; ++q) {
                     int32_t c = s->Lci[q];
@@ -504,7 +700,7 @@ int synth_build(const synth_params* p, synth_sys** out) {
                 }
         }
     }
-    free(cols); free(cnt); free(shell);
+    free(cols); free(cnt); free(vdir); free(mdir);
     *out = s;
     return 0;
 }

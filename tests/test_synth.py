@@ -236,3 +236,129 @@ def test_rhs_determinism_and_range():
     assert np.array_equal(a, b) and not np.array_equal(a, c)
     assert np.all(a[mask == 1] == 0) and a.min() >= -1 and a.max() < 1
     assert abs(a[mask == 0].mean()) < 0.1
+
+
+# ---------------------------------------------------------------- Y-bifurcation (voxel) workload
+def _branches(p):
+    """(start, unit direction, length, radius, cap at far end) of the three branches, written
+    from the workload's definition (parent along +z into the junction at the origin, daughters
+    leaving it in the x-z plane)."""
+    t1, t2 = p.y_th1, p.y_th2
+    return [(np.array([0.0, 0.0, -p.L]), np.array([0.0, 0.0, 1.0]), p.L, p.R, True),
+            (np.zeros(3), np.array([np.sin(t1), 0.0, np.cos(t1)]), p.y_ld, p.y_rd * p.R, False),
+            (np.zeros(3), np.array([-np.sin(t2), 0.0, np.cos(t2)]), p.y_ld, p.y_rd * p.R, False)]
+
+
+def _rel_dist(p, x):
+    """min over branches of distance / radius (inf beyond a free-end cut), points x (n, 3)."""
+    best = np.full(len(x), np.inf)
+    for a, u, ln, r, cap_end in _branches(p):
+        d = x - a
+        t = d @ u
+        radial = np.linalg.norm(d - t[:, None] * u, axis=1)
+        junction = np.linalg.norm(d - (ln if cap_end else 0.0) * u, axis=1)
+        beyond_free = t < 0 if cap_end else t > ln
+        in_cap = t > ln if cap_end else t < 0
+        dist = np.where(in_cap, junction, radial) / r
+        dist[beyond_free] = np.inf
+        best = np.minimum(best, dist)
+    return best
+
+
+@pytest.fixture(scope="module")
+def ysmall():
+    p = synth.y_params(h=0.25, seed=3)
+    return p, synth.generate(p, tets=True)
+
+
+def test_y_angles_seeded_in_range():
+    for seed in range(5):
+        p = synth.y_params(h=0.5, seed=seed)
+        for th in (p.y_th1, p.y_th2):
+            assert np.deg2rad(30) <= th <= np.deg2rad(60)
+    assert synth.y_params(h=0.5, seed=1).y_th1 == synth.y_params(h=0.5, seed=1).y_th1
+    assert synth.y_params(h=0.5, seed=1).y_th1 != synth.y_params(h=0.5, seed=2).y_th1
+
+
+def test_y_voxels_tets_and_classification(ysmall):
+    p, s = ysmall
+    x = s.xyz
+    h = p.y_h
+    # every vertex on the voxel grid with the inlet plane z = -L as a grid plane
+    assert np.allclose((x[:, 2] + p.L) / h, np.round((x[:, 2] + p.L) / h), atol=1e-9)
+    # six congruent Kuhn tets per kept voxel, all positively oriented with volume h^3/6
+    v = x[s.tv]
+    vol = np.einsum("ij,ij->i", np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]), v[:, 3] - v[:, 0]) / 6
+    assert s.n_tets % 6 == 0 and np.allclose(vol, h ** 3 / 6, rtol=1e-9)
+    # voxels kept: centre inside the wall region (relative distance < 1.2); tets fluid iff the
+    # centroid is inside the lumen (relative distance < 1)
+    cen = v.mean(axis=1)
+    rel = _rel_dist(p, cen)
+    assert np.array_equal(s.tsolid == 0, rel < 1.0)
+    vox = (v.min(axis=1) + v.max(axis=1)) / 2
+    assert np.all(_rel_dist(p, vox) < p.wall_ratio)
+    # conforming: every face shared by at most two tets
+    faces = np.sort(np.concatenate([s.tv[:, [0, 1, 2]], s.tv[:, [0, 1, 3]], s.tv[:, [0, 2, 3]],
+                                    s.tv[:, [1, 2, 3]]]), axis=1)
+    _, counts = np.unique(faces, axis=0, return_counts=True)
+    assert counts.max() == 2
+
+
+def test_y_block_structure_interface_and_dirichlet(ysmall):
+    import scipy.sparse as sp
+    p, s = ysmall
+    nb = s.n_b
+    K = sp.bsr_matrix((s.val, s.ci, s.rp), shape=(4 * nb, 4 * nb)).tocsr()
+    K.eliminate_zeros()
+    vel = (np.arange(nb)[:, None] * 4 + np.arange(3)).reshape(-1)
+    pre = np.arange(nb) * 4 + 3
+    A = K[vel][:, vel]; G = K[vel][:, pre]; D = K[pre][:, vel]; Cb = K[pre][:, pre]
+    amax = abs(A).max()
+    assert abs(A - A.T).max() <= 1e-12 * amax
+    assert abs(D + G.T).max() == 0
+    assert abs(Cb - Cb.T).max() <= 1e-14 * abs(Cb).max()
+    # interface: nodes touching both fluid and solid tets, each followed by its virtual node
+    kind = s.kind
+    touch = np.zeros(nb, np.uint8)
+    np.bitwise_or.at(touch, s.tv[s.tsolid == 0].reshape(-1), 1)
+    np.bitwise_or.at(touch, s.tv[s.tsolid == 1].reshape(-1), 2)
+    phys = kind != 3
+    assert np.array_equal(kind[phys] == 2, touch[phys] == 3)
+    assert np.array_equal(kind[phys] == 0, touch[phys] == 1)
+    virt = np.where(kind == 3)[0]
+    assert np.array_equal(virt - 1, np.where(kind == 2)[0]) and virt.size == s.n_iface
+    # solid tets take pressure from the virtual node of interface vertices
+    solid_tp = s.tp[s.tsolid == 1]
+    assert np.all(np.isin(solid_tp[kind[s.tv[s.tsolid == 1]] == 2],
+                          virt)) and np.array_equal(s.tp[s.tsolid == 0], s.tv[s.tsolid == 0])
+    # Dirichlet velocity: the whole inlet plane, identity rows and zero columns
+    m = s.mask.reshape(-1, 4)
+    inlet = np.isclose(s.xyz[:, 2], -p.L) & phys
+    assert np.all(m[inlet, :3] == 1) and not m[:, 3].any()
+    d = np.where(s.mask)[0]
+    Kd = K[d]
+    assert np.array_equal(Kd.indices, d) and np.all(Kd.data == 1.0)
+    assert abs(K[:, d]).sum() == d.size
+    # the fluid part of the outlets stays free (traction-free); the solid ends are clamped
+    assert np.all(m[(kind == 0) & ~inlet, :3] == 0)
+
+
+def test_y_mesh_laplacian(ysmall):
+    import scipy.sparse as sp
+    p, s = ysmall
+    L = sp.csr_matrix((s.Lval, s.Lci, s.Lrp), shape=(s.n_phys, s.n_phys))
+    assert abs(L - L.T).max() <= 1e-13 * abs(L).max()
+    # every node not strictly inside the lumen is Dirichlet (identity row and column)
+    solid_nodes = np.zeros(s.n_b, bool)
+    solid_nodes[s.tv[s.tsolid == 1].reshape(-1)] = True
+    bop = s.blk_of_phys
+    assert np.all(s.Lmask[solid_nodes[bop]] == 1)
+    free = np.where(s.Lmask == 0)[0]
+    # P1 stiffness annihilates constants: interior free rows sum to zero where no Dirichlet
+    # neighbour was eliminated
+    Lf = L[free]
+    pat = sp.csr_matrix((np.ones(s.Lci.size), s.Lci, s.Lrp), shape=L.shape)   # stored pattern
+    nbr_dir = np.asarray(pat[free][:, np.where(s.Lmask == 1)[0]].sum(axis=1)).ravel()
+    full = nbr_dir == 0
+    raw = np.asarray(Lf.sum(axis=1)).ravel()
+    assert full.any() and np.abs(raw[full]).max() <= 1e-12 * abs(L).max()
