@@ -29,7 +29,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--workload", choices=["cfg1", "cfg4"], default="cfg1",
+                    help="cfg1: unified tube (300,899 nodes, FP64 headline); cfg4: Y-bifurcation (about 4.0M nodes, "
+                         "mixed headline)")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default=None,
+                    help="default: both for cfg1, mixed for cfg4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -303,8 +307,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     t0 = time.time()
-    s = synth.generate(synth.cfg1_params())
-    log(f"[bench] cfg1 generated: n_b={s.n_b} nnzb={s.nnzb} nodes={s.n_phys} ({time.time() - t0:.1f}s)", args)
+    if args.precision is None:
+        args.precision = "both" if args.workload == "cfg1" else "mixed"
+    s = synth.generate(synth.cfg1_params() if args.workload == "cfg1" else synth.cfg4_params())
+    log(f"[bench] {args.workload} generated: n_b={s.n_b} nnzb={s.nnzb} nodes={s.n_phys} ({time.time() - t0:.1f}s)", args)
+    if args.workload == "cfg1":
+        workload = ("cfg1 unified fluid+solid tube 41x41x179 (300,899 nodes, 323,811 block rows, "
+                    "5,051,767 4x4 blocks) + mesh motion (300,899 x 3)")
+    else:
+        workload = (f"cfg4 Y-bifurcation, voxel mesh (parent R=1, daughters 0.7 at seeded angles, wall 1.2x; "
+                    f"{s.n_phys:,} nodes, {s.n_b:,} block rows, {s.nnzb:,} 4x4 blocks) + mesh motion ({s.n_phys:,} x 3)")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     rp, ci, val, xyz = dev(s.rp), dev(s.ci), dev(s.val.reshape(-1)), dev(s.xyz.reshape(-1))
     Lrp, Lci, Lval = dev(s.Lrp), dev(s.Lci), dev(s.Lval)
@@ -387,9 +399,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f32/f64",
         "data": "synthetic (seeded tube mesh, seeded RHS)",
-        "config": {"workload": "cfg1 unified fluid+solid tube 41x41x179 (300,899 nodes, 323,811 block rows, "
-                               "5,051,767 4x4 blocks) + mesh motion (300,899 x 3)",
-                   "precision": main_prec, "tol": 1e-8},
+        "config": {"workload": workload, "precision": main_prec, "tol": 1e-8},
     }
     for prec, rr in results.items():
         lat = np.array(rr["lat"]) * 1e3
@@ -414,17 +424,19 @@ def main():
             out[prec]["smoother_l0_GBps"] = round(rr["prof"]["gbs"], 1)
     pr = r["prof"]
     if pr:
-        traffic = pmc_traffic() if main_prec == "fp64" else None
+        traffic = pmc_traffic() if (main_prec == "fp64" and args.workload == "cfg1") else None
         out["roofline"] = {"bound": "hbm", "achieved": round(pr["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(pr["gbs"] / HBM_PEAK_GBS, 4),
                            "traffic": None if traffic is None else round(traffic / (pr["avg_us"] * 1e-6) / 1e9, 1),
                            "traffic_bytes_per_launch": traffic,
-                           "kernel": "smooth_rl3_k: fused Chebyshev step on level 0 of AMG(A) (3x3 FP64 blocks, block-row lanes)",
+                           "kernel": ("smooth_rl3_k: fused Chebyshev step on level 0 of AMG(A) (3x3 %s blocks, "
+                                      "block-row lanes)" % ("FP64" if main_prec == "fp64" else "FP32")),
                            "launches": pr["launches"], "avg_us": round(pr["avg_us"], 2),
                            "alg_bytes_per_launch": int(pr["bytes_per_launch"])}
     else:
         out["roofline"] = None
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(s, None, BM_host, args)
+    out["cpu_baseline"] = None if (args.no_cpu_baseline or args.workload != "cfg1") else \
+        cpu_baseline(s, None, BM_host, args)
     print(json.dumps(out))
 
 
