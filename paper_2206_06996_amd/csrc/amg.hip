@@ -143,7 +143,10 @@ __global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const i
         return;
     }
     if (PHASE == 0) {
-        if (lane == 0) cnt[i] = w;
+        if (lane == 0) {
+            cnt[i] = w;
+            atomicMax(overflow + 2, w);
+        }
         return;
     }
     // rank sort of the unique columns
@@ -187,13 +190,70 @@ __global__ void __launch_bounds__(256) spg_numeric(int64_t nr, const int32_t* __
     }
 }
 
+// numeric phase, one wave per output row: the row's output columns go into an LDS hash (column ->
+// position), then the products X_iq * Y_kt are pushed into LDS accumulators, q ascending (the
+// lanes of one step hold distinct columns of one row of Y, so no two lanes meet the same
+// accumulator).  Each accumulator receives the same terms in the same order as in the pull
+// kernel above, so the results are identical; the work is the candidate count instead of
+// (output entries) x (X row length) binary searches.
+// Dynamic LDS: hs keys, hs positions, then wmax * M * P doubles.
+template <int M, int N, int P>
+__global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, const int32_t* __restrict__ xrp,
+                                                        const int32_t* __restrict__ xci, const double* __restrict__ xv,
+                                                        const int32_t* __restrict__ yrp, const int32_t* __restrict__ yci,
+                                                        const double* __restrict__ yv, const int32_t* __restrict__ crp,
+                                                        const int32_t* __restrict__ cci, double* __restrict__ cv) {
+    extern __shared__ int smem[];
+    int* keys = smem;
+    int* pos = smem + hs;
+    double* acc = reinterpret_cast<double*>(smem + 2 * hs);
+    constexpr int MP = M * P;
+    int64_t i = blockIdx.x;
+    if (i >= nr) return;
+    int lane = threadIdx.x;
+    int32_t c0 = crp[i];
+    int w = crp[i + 1] - c0;
+    if (w == 0) return;
+    for (int t = lane; t < hs; t += WAVE) keys[t] = -1;
+    __syncthreads();
+    for (int p = lane; p < w; p += WAVE) {
+        int c = cci[c0 + p];
+        unsigned h = ((unsigned)c * 2654435761u) & (unsigned)(hs - 1);
+        while (atomicCAS(&keys[h], -1, c) != -1) h = (h + 1) & (unsigned)(hs - 1);
+        pos[h] = p;
+        for (int e = 0; e < MP; ++e) acc[p * MP + e] = 0.0;
+    }
+    __syncthreads();
+    for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) {
+        int32_t k = xci[q];
+        const double* xb = xv + (int64_t)q * M * N;
+        for (int32_t t = yrp[k] + lane; t < yrp[k + 1]; t += WAVE) {
+            int c = yci[t];
+            unsigned h = ((unsigned)c * 2654435761u) & (unsigned)(hs - 1);
+            for (int g = 0; g < hs && keys[h] != c; ++g) h = (h + 1) & (unsigned)(hs - 1);
+            if (keys[h] != c) continue;       // not reached: every column met is in the pattern
+            double* a = acc + pos[h] * MP;
+            const double* yb = yv + (int64_t)t * N * P;
+            for (int r = 0; r < M; ++r)
+                for (int cc = 0; cc < P; ++cc) {
+                    double sum = 0.0;
+                    for (int l = 0; l < N; ++l) sum += xb[r * N + l] * yb[l * P + cc];
+                    a[r * P + cc] += sum;
+                }
+        }
+        __syncthreads();
+    }
+    for (int p = lane; p < w; p += WAVE)
+        for (int e = 0; e < MP; ++e) cv[(int64_t)(c0 + p) * MP + e] = acc[p * MP + e];
+}
+
 static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hipStream_t s) {
     DBsr C;
     C.nr = X.nr; C.nc = Y.nc; C.br = X.br; C.bc = Y.bc;
     C.rp = ar.make<int32_t>(X.nr + 1);
     int32_t* cnt = ar.make<int32_t>(X.nr + 1);
-    int* flags = ar.make<int>(2);      // [overflow, max candidate bound]
-    HIPCHK(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
+    int* flags = ar.make<int>(3);      // [overflow, max candidate bound, max output row length]
+    HIPCHK(hipMemsetAsync(flags, 0, 3 * sizeof(int), s));
     if (X.nr > 0) spg_bound_k<<<cdiv(X.nr, 256), 256, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, flags + 1);
     int hflags[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -206,9 +266,11 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
         spg_symbolic<0><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr, flags);
     check_launch("spg_count");
     C.nnzb = scan_i32(cnt, C.rp, X.nr, ar, s);
-    HIPCHK(hipMemcpyAsync(hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    int hf[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hflags[0]) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
+    if (hf[0]) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
+    const int wmax = hf[2];
     ar.free(cnt);
     C.ci = ar.make<int32_t>(C.nnzb > 0 ? C.nnzb : 1);
     C.v = ar.make<double>((C.nnzb > 0 ? C.nnzb : 1) * C.br * C.bc);
@@ -218,6 +280,25 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
     ar.free(flags);
     int64_t nb = cdiv(X.nr, 4);
     int key = X.br * 100 + X.bc * 10 + Y.bc;
+    int hsn = 64;
+    while (hsn < 2 * wmax) hsn <<= 1;
+    size_t lds_n = (size_t)2 * hsn * sizeof(int) + (size_t)wmax * C.br * C.bc * sizeof(double);
+    if (X.nr > 0 && lds_n <= 64 * 1024) {
+#define SPL(m, n, p)                                                                                          \
+    spg_numeric_lds<m, n, p><<<X.nr, WAVE, lds_n, s>>>(X.nr, hsn, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, \
+                                                       C.v)
+        switch (key) {
+            case 111: SPL(1, 1, 1); break;
+            case 131: SPL(1, 3, 1); break;
+            case 336: SPL(3, 3, 6); break;
+            case 636: SPL(6, 3, 6); break;
+            case 666: SPL(6, 6, 6); break;
+            default: throw Error(SCR_E_UNIMPLEMENTED, "spgemm block shape " + std::to_string(key));
+        }
+#undef SPL
+        check_launch("spg_numeric");
+        return C;
+    }
 #define SPN(m, n, p) spg_numeric<m, n, p><<<nb, 256, 0, s>>>(X.nr, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v)
     if (nb > 0) {
         switch (key) {
