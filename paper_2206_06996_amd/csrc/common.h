@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -111,6 +113,43 @@ struct PinnedPool {
     }
 };
 
+// Device blocks released by destroyed handles, kept for the next handles of the context (the
+// setup of a new matrix allocates the same sizes again).  Blocks enter only after the stream that
+// last used them has been synchronised, so any stream may take them.  Bounded by `cap` bytes.
+struct BlockCache {
+    std::mutex mu;
+    std::multimap<size_t, void*> blocks;
+    int64_t bytes = 0;
+    int64_t cap = int64_t(16) << 30;
+    void* take(size_t n) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = blocks.find(n);
+        if (it == blocks.end()) return nullptr;
+        void* p = it->second;
+        blocks.erase(it);
+        bytes -= (int64_t)n;
+        return p;
+    }
+    void put(void* p, size_t n) {
+        std::lock_guard<std::mutex> lk(mu);
+        blocks.emplace(n, p);
+        bytes += (int64_t)n;
+        while (bytes > cap && !blocks.empty()) {      // drop the largest blocks first
+            auto it = std::prev(blocks.end());
+            (void)hipFreeAsync(it->second, nullptr);
+            bytes -= (int64_t)it->first;
+            blocks.erase(it);
+        }
+    }
+    void flush() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : blocks) (void)hipFreeAsync(kv.second, nullptr);
+        if (!blocks.empty()) (void)hipStreamSynchronize(nullptr);
+        blocks.clear();
+        bytes = 0;
+    }
+};
+
 struct Ctx {
     int device = 0;
     int64_t budget = 0;
@@ -118,27 +157,56 @@ struct Ctx {
     int cu_count = 256;
     Profiler prof;
     PinnedPool pinned;
+    BlockCache cache;
 };
 
-// Every allocation of a handle goes through an Arena: stream-ordered, counted against the
-// context budget, and released in full when the arena is destroyed.
+// Every allocation of a handle goes through an Arena: counted against the context budget and
+// released in full when the arena is destroyed.  Sizes are rounded to classes (256 B, then eighths
+// of a power of two) so that freed blocks can serve later requests: a block freed during the
+// arena's life is reused by the same arena (its work is ordered on the same stream); at the end
+// every block goes, after a stream synchronisation, to the context's cache.  New memory comes
+// from hipMallocAsync only when neither has a block of the class.
 class Arena {
    public:
     Arena(Ctx* c, hipStream_t s) : ctx_(c), stream_(s) {}
     ~Arena() { release_all(); }
     Arena(const Arena&) = delete;
     Arena& operator=(const Arena&) = delete;
-    void set_stream(hipStream_t s) { stream_ = s; }
-    void* alloc(size_t bytes) {
+    void set_stream(hipStream_t s) {
+        if (s != stream_ && !spare_.empty()) (void)hipStreamSynchronize(stream_);
+        stream_ = s;
+    }
+    static size_t size_class(size_t bytes) {
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~size_t(255);
+        if (bytes <= 65536) return bytes;
+        size_t top = size_t(1) << (63 - __builtin_clzll(bytes));
+        size_t step = top >> 3;
+        return (bytes + step - 1) / step * step;
+    }
+    void* alloc(size_t req) {
+        size_t bytes = size_class(req);
         if (ctx_->budget > 0 && ctx_->in_use.load() + (int64_t)bytes > ctx_->budget)
             throw Error(SCR_E_OOM, "device memory budget exceeded");
         void* p = nullptr;
-        hipError_t e = hipMallocAsync(&p, bytes, stream_);
-        if (e != hipSuccess || !p) {
-            (void)hipGetLastError();
-            throw Error(SCR_E_OOM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+        auto it = spare_.find(bytes);
+        if (it != spare_.end()) {
+            p = it->second;
+            spare_.erase(it);
+        }
+        if (!p) p = ctx_->cache.take(bytes);
+        if (!p) {
+            hipError_t e = hipMallocAsync(&p, bytes, stream_);
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                ctx_->cache.flush();
+                p = nullptr;
+                e = hipMallocAsync(&p, bytes, stream_);
+                if (e != hipSuccess || !p) {
+                    (void)hipGetLastError();
+                    throw Error(SCR_E_OOM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+                }
+            }
         }
         ctx_->in_use += (int64_t)bytes;
         bytes_ += (int64_t)bytes;
@@ -151,7 +219,7 @@ class Arena {
         if (!p) return;
         for (size_t i = 0; i < live_.size(); ++i)
             if (live_[i].p == p) {
-                (void)hipFreeAsync(p, stream_);
+                spare_.emplace(live_[i].n, p);
                 ctx_->in_use -= (int64_t)live_[i].n;
                 bytes_ -= (int64_t)live_[i].n;
                 live_[i] = live_.back();
@@ -160,11 +228,15 @@ class Arena {
             }
     }
     void release_all() {
+        if (live_.empty() && spare_.empty()) return;
+        (void)hipStreamSynchronize(stream_);
         for (auto& a : live_) {
-            (void)hipFreeAsync(a.p, stream_);
+            ctx_->cache.put(a.p, a.n);
             ctx_->in_use -= (int64_t)a.n;
         }
+        for (auto& kv : spare_) ctx_->cache.put(kv.second, kv.first);
         live_.clear();
+        spare_.clear();
         bytes_ = 0;
     }
     int64_t bytes() const { return bytes_; }
@@ -176,6 +248,7 @@ class Arena {
     Ctx* ctx_;
     hipStream_t stream_;
     std::vector<A> live_;
+    std::multimap<size_t, void*> spare_;
     int64_t bytes_ = 0;
 };
 

@@ -203,6 +203,7 @@ scr_status scr_ctx_create(int device, int64_t hbm_budget, scr_ctx** out) {
 void scr_ctx_destroy(scr_ctx* ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
+    ctx->c.cache.flush();
     ctx->c.prof.harvest();
     for (auto& p : ctx->c.prof.pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : ctx->c.prof.pool) (void)hipEventDestroy(e);

@@ -253,10 +253,17 @@ template DSell<float> sell_from_bsr<float>(const DBsr&, Arena&, hipStream_t);
 template void sell_free<double>(DSell<double>&, Arena&);
 template void sell_free<float>(DSell<float>&, Arena&);
 
+// row-entry-major values: entry e of the j-th block of row i at v[rp[i]*E + e*len_i + j]
+// (E = br*bc), so that the lanes of a wave, one block each, read every entry coalesced
 template <typename T>
-__global__ void cast_vals(const double* __restrict__ a, T* __restrict__ b, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (T)a[i];
+__global__ void bsrt_fill_k(int64_t nr, int E, const int32_t* __restrict__ rp, const double* __restrict__ a,
+                            T* __restrict__ b) {
+    int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (i >= nr) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    int64_t q0 = rp[i], len = rp[i + 1] - q0;
+    for (int64_t j = lane; j < len; j += WAVE)
+        for (int e = 0; e < E; ++e) b[q0 * E + e * len + j] = (T)a[(q0 + j) * E + e];
 }
 template <typename T>
 DBsrT<T> bsrt_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
@@ -264,8 +271,8 @@ DBsrT<T> bsrt_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
     R.nr = A.nr; R.nc = A.nc; R.br = A.br; R.bc = A.bc; R.nnzb = A.nnzb;
     R.rp = A.rp; R.ci = A.ci;   // shares the index arrays of the FP64 matrix
     int64_t nv = A.nnzb * A.br * A.bc;
-    R.v = ar.make<T>(nv);
-    if (nv > 0) cast_vals<T><<<cdiv(nv, 256), 256, 0, s>>>(A.v, R.v, nv);
+    R.v = ar.make<T>(nv > 0 ? nv : 1);
+    if (nv > 0) bsrt_fill_k<T><<<cdiv(A.nr, 4), 256, 0, s>>>(A.nr, A.br * A.bc, A.rp, A.v, R.v);
     check_launch("bsrt_from_bsr");
     return R;
 }
@@ -314,19 +321,42 @@ __device__ __forceinline__ T sell_row_dot(int64_t o0, int64_t o1, int lane, int 
     return acc;
 }
 
-template <typename T, int BR, int BC, int MODE>
+// WPS waves share one slice when a matrix has too few slices to fill the chip (coarse levels):
+// wave w of the group takes the w-th contiguous chunk of the slice's slots, and the partial row
+// sums are added in LDS in the fixed order w = 0, 1, ... (deterministic).
+template <int WPS>
+__device__ __forceinline__ void slice_part(int64_t o0, int64_t o1, int part, int64_t& a, int64_t& b) {
+    int64_t len = o1 - o0;
+    a = o0 + len * part / WPS;
+    b = o0 + len * (part + 1) / WPS;
+}
+
+template <typename T, int BR, int BC, int MODE, int WPS>
 __global__ void __launch_bounds__(256) sell_mv_k(int64_t nslices, const int32_t* __restrict__ off,
                                                  const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
                                                  const T* __restrict__ v, const T* __restrict__ x,
                                                  const T* __restrict__ b, T* __restrict__ y) {
     constexpr int RPS = WAVE / BR;
-    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * 4 + threadIdx.x / WAVE;
-    if (sl >= nslices) return;
+    int wv = threadIdx.x / WAVE;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * (4 / WPS) + wv / WPS;
     int lane = threadIdx.x & (WAVE - 1);
+    bool live = sl < nslices;
     auto xat = [&](int64_t c, int k) { return x[c * BC + k]; };
     int cl = lane / BR < RPS ? lane / BR : RPS - 1;
-    T acc = sell_row_dot<T, BC, RPS>(off[sl], off[sl + 1], lane, cl, ci, v, xat);
-    if (lane >= RPS * BR) return;
+    T acc = 0;
+    if (live) {
+        int64_t a, e;
+        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        acc = sell_row_dot<T, BC, RPS>(a, e, lane, cl, ci, v, xat);
+    }
+    if (WPS > 1) {
+        __shared__ T red[4][WAVE];
+        red[wv][lane] = acc;
+        __syncthreads();
+        if (wv % WPS != 0) return;
+        for (int w = 1; w < WPS; ++w) acc += red[wv + w][lane];
+    }
+    if (!live || lane >= RPS * BR) return;
     int64_t i = rowid[sl * RPS + cl];
     if (i < 0) return;
     int64_t o = i * BR + lane % BR;
@@ -334,6 +364,16 @@ __global__ void __launch_bounds__(256) sell_mv_k(int64_t nslices, const int32_t*
     else if (MODE == 1) y[o] = b[o] - acc;
     else if (MODE == 2) y[o] += acc;
     else y[o] -= acc;
+}
+
+// waves per slice: enough waves for about 16 per CU, if the slices are long enough to split
+template <typename T>
+static int waves_per_slice(const DSell<T>& A) {
+    if (A.nslices <= 0) return 1;
+    int64_t avg = A.slots / A.nslices;
+    int w = 1;
+    while (w < 4 && A.nslices * w < 4096 && avg >= 8 * (w * 2)) w *= 2;
+    return w;
 }
 
 // ---- block-row lanes (3x3): r[0..2] = sum over the lane's slots of block * x[col]
@@ -403,14 +443,22 @@ __global__ void __launch_bounds__(256) sell_mv_rl3_k(int64_t nslices, const int3
 
 template <typename T, int BR, int BC>
 static void sell_mv_dispatch_mode(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStream_t s) {
-    int64_t nblk = cdiv(A.nslices, 4);
+    // splitting slices only pays on the square coarse-level shapes (6x6 A levels, 1x1 S^/L levels)
+    constexpr bool SPLIT = (BR == 6 && BC == 6) || (BR == 1 && BC == 1);
+    int wps = SPLIT ? waves_per_slice(A) : 1;
+    int64_t nblk = cdiv(A.nslices * wps, 4);
     if (nblk == 0) return;
-    switch (mode) {
-        case 0: sell_mv_k<T, BR, BC, 0><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
-        case 1: sell_mv_k<T, BR, BC, 1><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
-        case 2: sell_mv_k<T, BR, BC, 2><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
-        default: sell_mv_k<T, BR, BC, 3><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
+#define MV(W)                                                                                                  \
+    switch (mode) {                                                                                            \
+        case 0: sell_mv_k<T, BR, BC, 0, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        case 1: sell_mv_k<T, BR, BC, 1, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        case 2: sell_mv_k<T, BR, BC, 2, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        default: sell_mv_k<T, BR, BC, 3, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
     }
+    if (!SPLIT || wps == 1) { MV(1) }
+    else if (wps == 2) { MV((SPLIT ? 2 : 1)) }
+    else { MV((SPLIT ? 4 : 1)) }
+#undef MV
     check_launch("sell_mv");
 }
 
@@ -473,6 +521,7 @@ void sell_mv_split4(const DSell<double>& K, const double* x, const double* b, do
 }
 
 // ---------------------------------------------------------------- restriction (row per wave)
+// Values in row-entry-major order (bsrt_fill_k); lane j of the wave takes blocks j, j+64, ...
 template <typename T, int BR, int BC>
 __global__ void __launch_bounds__(256) bsrt_mv_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const T* __restrict__ v, const T* __restrict__ x, T* __restrict__ y) {
@@ -482,13 +531,17 @@ __global__ void __launch_bounds__(256) bsrt_mv_k(int64_t nr, const int32_t* __re
     T acc[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) acc[r] = 0;
-    for (int64_t q = rp[row] + lane; q < rp[row + 1]; q += WAVE) {
-        int64_t c = ci[q];
-        const T* vb = v + q * (BR * BC);
+    int64_t q0 = rp[row], len = rp[row + 1] - q0;
+    for (int64_t j = lane; j < len; j += WAVE) {
+        int64_t c = ci[q0 + j];
+        const T* vb = v + q0 * (BR * BC) + j;
+        T xx[BC];
+#pragma unroll
+        for (int k = 0; k < BC; ++k) xx[k] = x[c * BC + k];
 #pragma unroll
         for (int r = 0; r < BR; ++r)
 #pragma unroll
-            for (int k = 0; k < BC; ++k) acc[r] += vb[r * BC + k] * x[c * BC + k];
+            for (int k = 0; k < BC; ++k) acc[r] += ld_stream<BC>(vb + (r * BC + k) * len) * xx[k];
     }
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
@@ -515,7 +568,7 @@ template void bsrt_mv<float>(const DBsrT<float>&, const float*, float*, hipStrea
 // ---------------------------------------------------------------- fused smoother step
 // dn = c1*d + c2*Dinv*(b - A xin) ; xout = xin + dn.  One lane per scalar row; the block
 // residual of a block row is gathered from its B lanes with shuffles to apply Dinv.
-template <typename T, int B, bool RD, bool WD, bool ZERO>
+template <typename T, int B, bool RD, bool WD, bool ZERO, int WPS>
 __global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* __restrict__ off,
                                                 const int32_t* __restrict__ rowid,
                                                 const int32_t* __restrict__ ci, const T* __restrict__ v,
@@ -523,18 +576,29 @@ __global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* 
                                                 const T* __restrict__ xin, T* __restrict__ d, T* __restrict__ xout,
                                                 T c1, T c2) {
     constexpr int RPS = WAVE / B;
-    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * 4 + threadIdx.x / WAVE;
-    if (sl >= nslices) return;
+    int wv = threadIdx.x / WAVE;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * (4 / WPS) + wv / WPS;
+    bool live = sl < nslices;
     int lane = threadIdx.x & (WAVE - 1);
     int cl = lane / B < RPS ? lane / B : RPS - 1;
+    T acc = 0;
+    if (!ZERO && live) {
+        auto xat = [&](int64_t c, int k) { return xin[c * B + k]; };
+        int64_t a, e;
+        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        acc = sell_row_dot<T, B, RPS>(a, e, lane, cl, ci, v, xat);
+    }
+    if (WPS > 1) {
+        __shared__ T red[4][WAVE];
+        red[wv][lane] = acc;
+        __syncthreads();
+        if (wv % WPS != 0) return;
+        for (int w = 1; w < WPS; ++w) acc += red[wv + w][lane];
+    }
+    if (!live) return;
     int64_t i = rowid[sl * RPS + cl];
     int r = lane % B;
     bool valid = lane < RPS * B && i >= 0;
-    T acc = 0;
-    if (!ZERO) {
-        auto xat = [&](int64_t c, int k) { return xin[c * B + k]; };
-        acc = sell_row_dot<T, B, RPS>(off[sl], off[sl + 1], lane, cl, ci, v, xat);
-    }
     int64_t o = i * B + r;
     T res = valid ? b[o] - acc : (T)0;
     T z = 0;
@@ -610,26 +674,34 @@ static void smooth_rl3(const DSell<T>& A, const T* Dinv, const T* b, const T* xi
 template <typename T, int B>
 static void smooth_dispatch(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, T c1, T c2,
                             bool rd, bool wd, bool zero, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    int64_t nblk = cdiv(A.nslices, 4);
+    int wps = zero ? 1 : waves_per_slice(A);
+    int64_t nblk = cdiv(A.nslices * wps, 4);
     if (nblk == 0) return;
-#define SK(RD, WD, Z)                                                                                              \
+#define SKW(RD, WD, Z, W)                                                                                          \
     do {                                                                                                           \
         if (e0)                                                                                                    \
-            hipExtLaunchKernelGGL((smooth_k<T, B, RD, WD, Z>), dim3((unsigned)nblk), dim3(256), 0, s, e0, e1, 0,   \
-                                  A.nslices, (const int32_t*)A.off, (const int32_t*)A.rowid, (const int32_t*)A.ci, \
-                                  (const T*)A.v, Dinv, b, xin, d, xout, c1, c2);                                   \
+            hipExtLaunchKernelGGL((smooth_k<T, B, RD, WD, Z, W>), dim3((unsigned)nblk), dim3(256), 0, s, e0, e1,   \
+                                  0, A.nslices, (const int32_t*)A.off, (const int32_t*)A.rowid,                    \
+                                  (const int32_t*)A.ci, (const T*)A.v, Dinv, b, xin, d, xout, c1, c2);             \
         else                                                                                                       \
-            smooth_k<T, B, RD, WD, Z><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin, d,  \
-                                                          xout, c1, c2);                                           \
+            smooth_k<T, B, RD, WD, Z, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin,  \
+                                                             d, xout, c1, c2);                                     \
+    } while (0)
+#define SK(RD, WD, Z)                                                                                              \
+    do {                                                                                                           \
+        if (wps == 4) SKW(RD, WD, Z, 4);                                                                           \
+        else if (wps == 2) SKW(RD, WD, Z, 2);                                                                      \
+        else SKW(RD, WD, Z, 1);                                                                                    \
     } while (0)
     if (zero) {
-        if (wd) SK(false, true, true); else SK(false, false, true);
+        if (wd) SKW(false, true, true, 1); else SKW(false, false, true, 1);
     } else if (rd) {
         if (wd) SK(true, true, false); else SK(true, false, false);
     } else {
         if (wd) SK(false, true, false); else SK(false, false, false);
     }
 #undef SK
+#undef SKW
     check_launch("smooth_step");
 }
 
