@@ -265,7 +265,7 @@ struct DBsr {
 
 // Sliced ELL, two lane mappings.
 //
-// Scalar-row lanes (every shape but 3x3).  A slice is one wavefront covering rps = 64/br block
+// Scalar-row lanes (every shape but 3x3 and 3x6).  A slice is one wavefront covering rps = 64/br block
 // rows (lanes = rps*br; the rest idle), so the br lanes of a block row share a wavefront.  Lane
 // (block row i, row r) reads, for every slot t of the slice, the column block index of block row
 // i (stored once per block row) and row r of that block (bc values); each of the bc entries of a
@@ -274,12 +274,13 @@ struct DBsr {
 //   col of (slice s, slot t, block row j of the slice):   ci[(off[s] + t) * rps + j]
 //   entry k of lane l's row segment:                       v[((off[s] + t) * bc + k) * 64 + l]
 //
-// Block-row lanes (3x3 blocks: the velocity block and its FP32 copy).  A slice is one wavefront
-// covering rps = 64 block rows, one per lane; the lane computes all three rows of its block row.
-// Each lane gathers the 3-vector of x at its column once (the scalar-row mapping gathers it
-// three times, once per row lane), which is what the velocity block's sweeps are bound by.
+// Block-row lanes (3x3 blocks: the velocity block and its FP32 copy; 3x6: the prolongators of
+// AMG(A)).  A slice is one wavefront covering rps = 64 block rows, one per lane; the lane computes
+// all three rows of its block row.  Each lane gathers the bc-vector of x at its column once (the
+// scalar-row mapping gathers it three times, once per row lane), which is what these sweeps are
+// bound by.
 //   col of (slice s, slot t, lane l):                      ci[(off[s] + t) * 64 + l]
-//   entry e = 3r + k of the block at (s, t, l):            v[((off[s] + t) * 9 + e) * 64 + l]
+//   entry e = bc*r + k of the block at (s, t, l):          v[((off[s] + t) * 3*bc + e) * 64 + l]
 //
 // Rows shorter than the slice are padded with zero entries pointing at a valid column.  Within
 // windows of sigma slices, block rows are ordered by decreasing length (ties by index) so that

@@ -216,7 +216,7 @@ template <typename T>
 DSell<T> sell_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
     DSell<T> S;
     S.nr = A.nr; S.nc = A.nc; S.br = A.br; S.bc = A.bc; S.nnzb = A.nnzb;
-    S.rowlane = A.br == 3 && A.bc == 3;
+    S.rowlane = A.br == 3 && (A.bc == 3 || A.bc == 6);
     S.rps = S.rowlane ? WAVE : WAVE / A.br;
     S.nslices = cdiv(A.nr, S.rps);
     if (S.nslices == 0) return S;
@@ -376,50 +376,56 @@ static int waves_per_slice(const DSell<T>& A) {
     return w;
 }
 
-// ---- block-row lanes (3x3): r[0..2] = sum over the lane's slots of block * x[col]
-// Two slots per step: both slots' columns, then their 18 values and two x 3-vectors are loaded
-// before use.  FP64 values are streamed with nontemporal loads (read once per call; measured: a
-// gain in FP64, a loss in FP32).
-template <typename T>
+// ---- block-row lanes (3xBC, BC = 3 or 6): r[0..2] = sum over the lane's slots of block * x[col]
+// 3x3: two slots per step (both slots' columns, then their 18 values and two x 3-vectors are
+// loaded before use); 3x6: one slot per step (18 values and an x 6-vector).  FP64 values are
+// streamed with nontemporal loads (read once per call; measured: a gain in FP64, a loss in FP32).
+template <typename T, int BC>
 __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, const int32_t* __restrict__ ci,
                                              const T* __restrict__ v, const T* __restrict__ x, T r[3]) {
+    constexpr int U = BC == 3 ? 2 : 1, E = 3 * BC;
     auto ld = [](const T* p) -> T {
         if (sizeof(T) == 8) return __builtin_nontemporal_load(p);
         return *p;
     };
+    auto fma_block = [&](const T* vv, const T* xx) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            T sum = vv[BC * q] * xx[0];
+#pragma unroll
+            for (int k = 1; k < BC; ++k) sum += vv[BC * q + k] * xx[k];
+            r[q] += sum;
+        }
+    };
     r[0] = r[1] = r[2] = 0;
-    for (; t + 2 <= o1; t += 2) {
-        int64_t c[2];
-        T vv[2][9], xx[2][3];
+    for (; t + U <= o1; t += U) {
+        int64_t c[U];
+        T vv[U][E], xx[U][BC];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) c[u] = ci[(t + u) * WAVE + lane];
+        for (int u = 0; u < U; ++u) c[u] = ci[(t + u) * WAVE + lane];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int e = 0; e < 9; ++e) vv[u][e] = ld(v + ((t + u) * 9 + e) * WAVE + lane);
+            for (int e = 0; e < E; ++e) vv[u][e] = ld(v + ((t + u) * E + e) * WAVE + lane);
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) xx[u][k] = x[c[u] * 3 + k];
+            for (int k = 0; k < BC; ++k) xx[u][k] = x[c[u] * BC + k];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                r[q] += vv[u][3 * q] * xx[u][0] + vv[u][3 * q + 1] * xx[u][1] + vv[u][3 * q + 2] * xx[u][2];
+        for (int u = 0; u < U; ++u) fma_block(vv[u], xx[u]);
     }
-    if (t < o1) {
+    if (U > 1 && t < o1) {
         int64_t c = ci[t * WAVE + lane];
-        T vv[9], xx[3];
+        T vv[E], xx[BC];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) vv[e] = ld(v + (t * 9 + e) * WAVE + lane);
+        for (int e = 0; e < E; ++e) vv[e] = ld(v + (t * E + e) * WAVE + lane);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) xx[k] = x[c * 3 + k];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) r[q] += vv[3 * q] * xx[0] + vv[3 * q + 1] * xx[1] + vv[3 * q + 2] * xx[2];
+        for (int k = 0; k < BC; ++k) xx[k] = x[c * BC + k];
+        fma_block(vv, xx);
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int BC, int MODE>
 __global__ void __launch_bounds__(256) sell_mv_rl3_k(int64_t nslices, const int32_t* __restrict__ off,
                                                      const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
                                                      const T* __restrict__ v, const T* __restrict__ x,
@@ -428,7 +434,7 @@ __global__ void __launch_bounds__(256) sell_mv_rl3_k(int64_t nslices, const int3
     if (sl >= nslices) return;
     int lane = threadIdx.x & (WAVE - 1);
     T r[3];
-    rowlane3_dot<T>(off[sl], off[sl + 1], lane, ci, v, x, r);
+    rowlane3_dot<T, BC>(off[sl], off[sl + 1], lane, ci, v, x, r);
     int64_t i = rowid[sl * WAVE + lane];
     if (i < 0) return;
 #pragma unroll
@@ -467,12 +473,15 @@ void sell_mv(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStrea
     if (A.rowlane) {
         int64_t nblk = cdiv(A.nslices, 4);
         if (nblk == 0) return;
-        switch (mode) {
-            case 0: sell_mv_rl3_k<T, 0><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
-            case 1: sell_mv_rl3_k<T, 1><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
-            case 2: sell_mv_rl3_k<T, 2><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
-            default: sell_mv_rl3_k<T, 3><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break;
-        }
+#define RL(BC)                                                                                                     \
+    switch (mode) {                                                                                                \
+        case 0: sell_mv_rl3_k<T, BC, 0><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        case 1: sell_mv_rl3_k<T, BC, 1><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        case 2: sell_mv_rl3_k<T, BC, 2><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        default: sell_mv_rl3_k<T, BC, 3><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+    }
+        if (A.bc == 3) { RL(3) } else { RL(6) }
+#undef RL
         check_launch("sell_mv");
         return;
     }
@@ -627,7 +636,7 @@ __global__ void __launch_bounds__(256) smooth_rl3_k(int64_t nslices, const int32
     if (sl >= nslices) return;
     int lane = threadIdx.x & (WAVE - 1);
     T r[3] = {0, 0, 0};
-    if (!ZERO) rowlane3_dot<T>(off[sl], off[sl + 1], lane, ci, v, xin, r);
+    if (!ZERO) rowlane3_dot<T, 3>(off[sl], off[sl + 1], lane, ci, v, xin, r);
     int64_t i = rowid[sl * WAVE + lane];
     if (i < 0) return;
     T res[3];
