@@ -32,14 +32,15 @@ def build() -> str:
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("smoother", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("jacobi_sweeps", C.c_int), ("coarse_max", C.c_int),
-                ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64)]
+                ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
+                ("schur_diag", C.c_int)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_A", C.c_double), ("tol_S", C.c_double), ("tol_I", C.c_double),
                 ("max_it", C.c_int), ("max_it_A", C.c_int), ("max_it_S", C.c_int), ("max_it_I", C.c_int),
                 ("restart", C.c_int), ("restart_inner", C.c_int), ("use_x0", C.c_int),
-                ("flexible_cg", C.c_int)]
+                ("flexible_cg", C.c_int), ("precond", C.c_int)]
 
 
 class ScrStats(C.Structure):
@@ -56,7 +57,7 @@ def amg_opts(**kw) -> AmgOpts:
     """Defaults: theta=0.08 (halved per level), Chebyshev degree 2 on [lam/30, lam], coarse
     solve below 1024 unknowns, at most 10 levels, stop if coarsening is slower than 0.8."""
     o = AmgOpts(theta=0.08, smoother=1, cheb_degree=2, cheb_ratio=30.0, jacobi_sweeps=2,
-                coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0)
+                coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -66,7 +67,8 @@ def solve_opts(**kw) -> SolveOpts:
     """Defaults: outer delta 1e-8; delta_A = delta_S = delta_I = 1e-3 and 200 iterations at
     every level (the paper's solver-settings table, Sec. 6); restarts 50 outer / 30 inner."""
     o = SolveOpts(tol=1e-8, tol_A=1e-3, tol_S=1e-3, tol_I=1e-3, max_it=200, max_it_A=200,
-                  max_it_S=200, max_it_I=200, restart=50, restart_inner=30, use_x0=0, flexible_cg=0)
+                  max_it_S=200, max_it_I=200, restart=50, restart_inner=30, use_x0=0, flexible_cg=0,
+                  precond=0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -289,11 +291,12 @@ class Scr:
         return x, rc, st.as_dict()
 
     OPS = {"K": (4, 4), "A": (3, 3), "VA": (3, 3), "VS": (1, 1), "S": (1, 1), "SCR": (4, 4),
-           "G": (1, 3), "D": (3, 1), "C": (1, 1), "Shat": (1, 1)}
+           "G": (1, 3), "D": (3, 1), "C": (1, 1), "Shat": (1, 1), "SIMPLE": (4, 4), "d": (3, 3)}
 
     def apply(self, op, x, opts=None):
         """Split-layout component operators: see orc_scr_apply."""
-        code = {"K": 0, "A": 1, "VA": 2, "VS": 3, "S": 4, "SCR": 5, "G": 6, "D": 7, "C": 8, "Shat": 9}[op]
+        code = {"K": 0, "A": 1, "VA": 2, "VS": 3, "S": 4, "SCR": 5, "G": 6, "D": 7, "C": 8, "Shat": 9,
+                "SIMPLE": 10, "d": 11}[op]
         nin, nout = self.OPS[op]
         x = _c(x, np.float64)
         assert x.size == nin * self.nb

@@ -222,6 +222,8 @@ typedef struct {
     int max_levels;
     double max_coarse_ratio; /* stop if n_{l+1} > ratio * n_l */
     uint64_t seed;
+    int schur_diag;      /* SCR system setup: diagonal used in S^ = C - D d^-1 G:
+                            0 the diagonal of A (SCR, SIMPLE), 1 absolute row sums of A (SIMPLEC) */
 } amg_opts;
 
 #define MAXLEV 16
@@ -850,6 +852,7 @@ typedef struct {
     int restart, restart_inner;
     int use_x0;
     int flexible_cg;
+    int precond;         /* 0 SCR (Algorithm 1), 1 SIMPLE-type block preconditioner (Sec. 5.2.1) */
 } solve_opts;
 
 typedef struct {
@@ -929,6 +932,33 @@ static void prec_SCR(void* c, const double* r, double* y) {
     free(yhat); free(tp); free(tv);
 }
 
+/* SIMPLE (Sec. 5.2.1): the inverse of the product P = [I 0; D A^-1 I] [A 0; 0 S^] [I d^-1 G; 0 I]
+ * applied to r, with A^-1 by GMRES+AMG(A) to tol_A and S^^-1 by GMRES+AMG(S^) on the explicit
+ * sparse S^ to tol_S (no inner-level solver):
+ *   y*_v = A^-1 r_v;  y_p = S^^-1 (r_p - D y*_v);  y_v = y*_v - d^-1 (G y_p).
+ * d is the diagonal of A (SIMPLE) or its absolute row sums (SIMPLEC), the same d as in S^. */
+static void op_Sh(void* c, const double* x, double* y) { bsr_mv(((scr*)c)->Sh, x, y); }
+static void prec_SIMPLE(void* c, const double* r, double* y) {
+    scr* s = (scr*)c;
+    int64_t nb = s->nb;
+    const double* rv = r;
+    const double* rp = r + 3 * nb;
+    double* yv = y;
+    double* yp = y + 3 * nb;
+    double* ystar = (double*)malloc(sizeof(double) * 3 * nb);
+    double* tp = (double*)malloc(sizeof(double) * nb);
+    double* tv = (double*)malloc(sizeof(double) * 3 * nb);
+    kstat k = fgmres(3 * nb, op_A, s, prec_A, s, rv, ystar, s->so.tol_A, s->so.max_it_A, s->so.restart_inner, 0, 0);
+    s->st.calls_A++; s->st.its_A += k.iters;
+    bsr_mv(s->D, ystar, tp);
+    for (int64_t i = 0; i < nb; ++i) tp[i] = rp[i] - tp[i];
+    k = fgmres(nb, op_Sh, s, prec_S, s, tp, yp, s->so.tol_S, s->so.max_it_S, s->so.restart_inner, 0, 0);
+    s->st.calls_S++; s->st.its_S += k.iters;
+    bsr_mv(s->G, yp, tv);
+    for (int64_t i = 0; i < 3 * nb; ++i) yv[i] = ystar[i] - tv[i] / s->diagA[i];
+    free(ystar); free(tp); free(tv);
+}
+
 /* Split K (4x4 BSR) into A (3x3), G (3x1), D (1x3), C (1x1), all on K's block pattern. */
 static void split_blocks(const bsr* K, bsr** A, bsr** G, bsr** D, bsr** Cm) {
     int64_t nb = K->nr, nz = K->nnzb;
@@ -950,12 +980,23 @@ static void split_blocks(const bsr* K, bsr** A, bsr** G, bsr** D, bsr** Cm) {
     }
 }
 
-/* S^ = C - D diag(A)^-1 G on the union of the patterns of C and D*G (structural). */
-static bsr* schur_approx(const bsr* A, const bsr* G, const bsr* D, const bsr* Cm, double* diagA) {
+/* S^ = C - D d^-1 G on the union of the patterns of C and D*G (structural), with d (one entry per
+ * velocity dof) the diagonal of A (mode 0) or the sums of the absolute values of its rows (mode 1,
+ * the SIMPLEC lumping). */
+static bsr* schur_approx(const bsr* A, const bsr* G, const bsr* D, const bsr* Cm, double* diagA, int mode) {
     int64_t nb = A->nr;
     for (int64_t i = 0; i < nb; ++i) {
-        int32_t q = find_in_row(A, i, (int32_t)i);
-        for (int c = 0; c < 3; ++c) diagA[3 * i + c] = A->v[(int64_t)q * 9 + 4 * c];
+        if (mode == 0) {
+            int32_t q = find_in_row(A, i, (int32_t)i);
+            for (int c = 0; c < 3; ++c) diagA[3 * i + c] = A->v[(int64_t)q * 9 + 4 * c];
+        } else {
+            for (int c = 0; c < 3; ++c) {
+                double sum = 0.0;
+                for (int32_t q = A->rp[i]; q < A->rp[i + 1]; ++q)
+                    for (int k = 0; k < 3; ++k) sum += fabs(A->v[(int64_t)q * 9 + 3 * c + k]);
+                diagA[3 * i + c] = sum;
+            }
+        }
     }
     bsr* X = bsr_new(nb, nb, 1, 3, D->nnzb);
     memcpy(X->rp, D->rp, sizeof(int32_t) * (nb + 1));
@@ -1014,7 +1055,7 @@ int orc_scr_create(int64_t nb, const int32_t* rp, const int32_t* ci, const doubl
     memcpy(s->K->v, val, sizeof(double) * rp[nb] * 16);
     split_blocks(s->K, &s->A, &s->G, &s->D, &s->C);
     s->diagA = (double*)malloc(sizeof(double) * 3 * nb);
-    s->Sh = schur_approx(s->A, s->G, s->D, s->C, s->diagA);
+    s->Sh = schur_approx(s->A, s->G, s->D, s->C, s->diagA, ao->schur_diag);
     double* B = (double*)malloc(sizeof(double) * nb * 18);
     rigid_modes(nb, xyz, B);
     s->amgA = amg_build(s->A, B, 6, ao);
@@ -1071,7 +1112,8 @@ int orc_scr_solve(scr* s, const double* b, double* x, const solve_opts* so, scr_
     double* xs = (double*)malloc(sizeof(double) * n);
     to_split(nb, b, bs);
     if (so->use_x0) to_split(nb, x, xs);
-    kstat k = fgmres(n, op_K, s, prec_SCR, s, bs, xs, so->tol, so->max_it, so->restart, so->use_x0, 1);
+    kstat k = fgmres(n, op_K, s, so->precond == 1 ? prec_SIMPLE : prec_SCR, s, bs, xs, so->tol, so->max_it,
+                     so->restart, so->use_x0, 1);
     from_split(nb, xs, x);
     s->st.outer_it = (int)k.iters;
     s->st.rel_res_true = k.rel_res;
@@ -1085,7 +1127,8 @@ int orc_scr_solve(scr* s, const double* b, double* x, const solve_opts* so, scr_
 /* Component operators on split vectors (tests):
  * op 0: y = K x (split 4nb)   1: y = A x (3nb)   2: y = V-cycle_A(x)   3: y = V-cycle_S^(x)
  *    4: y = S x by Algorithm 2 (nb)   5: y = P_SCR^-1 x by Algorithm 1 (split 4nb)
- *    6: y = G x (nb -> 3nb)   7: y = D x (3nb -> nb)   8: y = C x   9: y = S^ x */
+ *    6: y = G x (nb -> 3nb)   7: y = D x (3nb -> nb)   8: y = C x   9: y = S^ x
+ *   10: y = P_SIMPLE^-1 x (split 4nb)   11: y = d, the diagonal used in S^ (3nb; x unused) */
 int orc_scr_apply(scr* s, int op, const double* x, double* y, const solve_opts* so) {
     if (so) s->so = *so;
     switch (op) {
@@ -1099,6 +1142,8 @@ int orc_scr_apply(scr* s, int op, const double* x, double* y, const solve_opts* 
         case 7: bsr_mv(s->D, x, y); break;
         case 8: bsr_mv(s->C, x, y); break;
         case 9: bsr_mv(s->Sh, x, y); break;
+        case 10: prec_SIMPLE(s, x, y); break;
+        case 11: memcpy(y, s->diagA, sizeof(double) * 3 * s->nb); break;
         default: return -1;
     }
     return 0;

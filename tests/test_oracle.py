@@ -371,6 +371,73 @@ def test_algorithm1_with_exact_inner_solves_is_the_inverse(small_fsi):
     assert rc == 0 and st["outer_it"] == 1
 
 
+# ----------------------------------------------------------------------------- SIMPLE / SIMPLEC (Sec. 5.2.1)
+def test_simple_with_exact_solves_is_the_inverse_of_its_product_form(small_fsi):
+    # P_SIMPLE = [I 0; D A^-1 I] [A 0; 0 S^] [I d^-1 G; 0 I], d = diag(A); its product closed form
+    # is [A  A d^-1 G; D  C] (S^ = C - D d^-1 G), so it differs from the 2x2 system only in the
+    # upper-right block
+    o = oracle.Scr(small_fsi.rp, small_fsi.ci, small_fsi.val, small_fsi.xyz)
+    A, G, D, Cb, _, _ = _dense_blocks(small_fsi)
+    n3, nb = A.shape[0], Cb.shape[0]
+    dinv = np.diag(1.0 / np.diag(A))
+    Sh = Cb - D @ dinv @ G
+    I3, Ip = np.eye(n3), np.eye(nb)
+    P = (np.block([[I3, np.zeros((n3, nb))], [D @ np.linalg.inv(A), Ip]])
+         @ np.block([[A, np.zeros((n3, nb))], [np.zeros((nb, n3)), Sh]])
+         @ np.block([[I3, dinv @ G], [np.zeros((nb, n3)), Ip]]))
+    closed = np.block([[A, A @ dinv @ G], [D, Cb]])
+    assert np.abs(P - closed).max() <= 1e-9 * np.abs(closed).max()
+    r = np.random.default_rng(9).normal(size=n3 + nb)
+    tight = oracle.solve_opts(tol_A=1e-14, tol_S=1e-14, max_it_S=400, max_it_A=400)
+    y = o.apply("SIMPLE", r, tight)
+    exact = np.linalg.solve(closed, r)
+    assert np.linalg.norm(y - exact) <= 1e-9 * np.linalg.norm(exact)
+
+
+def test_simplec_lumped_diagonal_and_schur(tiny):
+    # SIMPLEC: d = sums of the absolute values of the rows of A, used in S^ and in the update
+    o = oracle.Scr(tiny.rp, tiny.ci, tiny.val, tiny.xyz, oracle.amg_opts(schur_diag=1))
+    A, G, D, Cb, _, _ = _dense_blocks(tiny)
+    d = np.abs(A).sum(axis=1)
+    assert np.allclose(o.apply("d", np.zeros(A.shape[0])), d, rtol=1e-14, atol=0)
+    rp, ci, v = o.matrix("Shat")
+    S = bsr_to_dense(rp, ci, v, tiny.n_b)
+    Sd = Cb - D @ np.diag(1.0 / d) @ G
+    assert np.abs(S - Sd).max() <= 1e-13 * np.abs(Sd).max()
+    o0 = oracle.Scr(tiny.rp, tiny.ci, tiny.val, tiny.xyz)
+    assert np.array_equal(o0.apply("d", np.zeros(A.shape[0])), np.diag(A))
+
+
+def test_simple_is_exact_when_A_is_diagonal(small_fsi):
+    # with A = diag(A) the closed form [A  A d^-1 G; D  C] is the 2x2 system itself: FGMRES with
+    # exact block solves converges in one iteration
+    s = small_fsi
+    val = s.val.copy()
+    for r in range(s.n_b):
+        for q in range(s.rp[r], s.rp[r + 1]):
+            blk = val[q, :3, :3]
+            keep = np.diag(np.diag(blk)) if s.ci[q] == r else np.zeros((3, 3))
+            val[q, :3, :3] = keep
+    o = oracle.Scr(s.rp, s.ci, val, s.xyz)
+    b = synth.rhs(4, 4 * s.n_b, s.mask)
+    opts = oracle.solve_opts(tol=1e-10, tol_A=1e-14, tol_S=1e-14, max_it_S=400, precond=1)
+    x, rc, st = o.solve(b, opts)
+    xl = oracle.dense_solve(bsr_to_dense(s.rp, s.ci, val), b)
+    assert rc == 0 and st["outer_it"] == 1
+    assert np.linalg.norm(x - xl) <= 1e-9 * np.linalg.norm(xl)
+
+
+@pytest.mark.parametrize("schur_diag", [0, 1])
+def test_simple_fgmres_matches_dense_lu(small_fsi, schur_diag):
+    s = small_fsi
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(schur_diag=schur_diag))
+    b = synth.rhs(3, 4 * s.n_b, s.mask)
+    x, rc, st = o.solve(b, oracle.solve_opts(tol=1e-11, precond=1))
+    xl = oracle.dense_solve(bsr_to_dense(s.rp, s.ci, s.val), b)
+    assert rc == 0 and st["calls_I"] == 0 and st["calls_S"] == st["outer_it"]
+    assert np.linalg.norm(x - xl) <= 1e-9 * np.linalg.norm(xl)
+
+
 def test_full_solve_matches_dense_lu(tiny, small_fsi):
     for s in (tiny, small_fsi):
         o = oracle.Scr(s.rp, s.ci, s.val, s.xyz)
