@@ -32,6 +32,10 @@ def parse():
     ap.add_argument("--workload", choices=["cfg1", "cfg4"], default="cfg1",
                     help="cfg1: unified tube (300,899 nodes, FP64 headline); cfg4: Y-bifurcation (about 4.0M nodes, "
                          "mixed headline)")
+    ap.add_argument("--precond", choices=["scr", "simple", "simplec"], default="scr",
+                    help="outer preconditioner: SCR (Algorithm 1), SIMPLE or SIMPLEC (Sec. 5.2.1)")
+    ap.add_argument("--dt-sweep", action="store_true",
+                    help="compare SCR and SIMPLE iterations and times on cfg1 at dt = 1e-5, 1e-4, 1e-3 (FP64)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default=None,
                     help="default: both for cfg1, mixed for cfg4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -294,6 +298,42 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
+def dt_sweep(args):
+    """SCR against SIMPLE and SIMPLEC on the cfg1 tube as the time step grows (the paper's Sec. 6
+    comparison of the two preconditioners over dt): outer iterations, block iterations and solve
+    time per preconditioner, FP64, tol 1e-8, at most 200 outer iterations."""
+    import torch
+    import synth
+    import paper_2206_06996_amd.scr as scr
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    ctx = scr.Context(0)
+    rows = []
+    for dt in (1e-5, 1e-4, 1e-3):
+        s = synth.generate(synth.default_params(mode=0, m_core=12, n_bl=4, n_wall=4, nz=178, R=1.0, L=10.0, dt=dt))
+        K = (dev(s.rp), dev(s.ci), dev(s.val.reshape(-1)))
+        b = dev(synth.rhs(1000, 4 * s.n_b, s.mask))
+        for name, diag, pc in (("SCR", 0, scr.SCR_PRECOND_SCR), ("SIMPLE", 0, scr.SCR_PRECOND_SIMPLE),
+                               ("SIMPLEC", 1, scr.SCR_PRECOND_SIMPLE)):
+            h = scr.amg_setup(ctx, scr.SCR_SYSTEM, *K, dev(s.xyz.reshape(-1)), scr.amg_opts(schur_diag=diag))
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = scr.scr_solve(h, b, x, scr.solve_opts(precond=pc, max_it=200))
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            h.destroy()
+            row = dict(dt=dt, precond=name, converged=bool(st["converged"]), outer_it=st["outer_it"],
+                       its_A=st["its_A"], its_S=st["its_S"], its_I=st["its_I"], solve_ms=round(1e3 * t, 1),
+                       rel_res=st["rel_res_true"])
+            log(f"[dt-sweep] {row}", args)
+            rows.append(row)
+    ctx.destroy()
+    print(json.dumps({"metric": "SCR vs SIMPLE/SIMPLEC over the time step (outer iterations, solve ms)",
+                      "unit": "iterations", "config": {"workload": "cfg1 tube, dt in {1e-5, 1e-4, 1e-3}",
+                                                       "precision": "fp64", "tol": 1e-8, "max_it": 200},
+                      "rows": rows}))
+
+
 def log(msg, args=None):
     if not (args and args.quiet):
         print(msg, file=sys.stderr, flush=True)
@@ -310,6 +350,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.dt_sweep:
+        dt_sweep(args)
         return
     import torch
     import synth
@@ -348,8 +391,8 @@ def main():
     results = {}
     for prec in precisions:
         p = scr.SCR_MIXED if prec == "mixed" else scr.SCR_FP64
-        ao = scr.amg_opts(precision=p)
-        so = scr.solve_opts()
+        ao = scr.amg_opts(precision=p, schur_diag=1 if args.precond == "simplec" else 0)
+        so = scr.solve_opts(precond=scr.SCR_PRECOND_SCR if args.precond == "scr" else scr.SCR_PRECOND_SIMPLE)
         hm = scr.amg_setup(ctx, scr.MESH_SYSTEM, Lrp, Lci, Lval, None, ao)
         lat, setup_ms, solve_ms, mesh_ms, destroy_ms, stats = [], [], [], [], [], []
         region = None
@@ -409,7 +452,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f32/f64",
         "data": "synthetic (seeded tube mesh, seeded RHS)",
-        "config": {"workload": workload, "precision": main_prec, "tol": 1e-8},
+        "config": {"workload": workload, "precision": main_prec, "tol": 1e-8, "precond": args.precond},
     }
     for prec, rr in results.items():
         lat = np.array(rr["lat"]) * 1e3
@@ -445,7 +488,7 @@ def main():
                            "alg_bytes_per_launch": int(pr["bytes_per_launch"])}
     else:
         out["roofline"] = None
-    out["cpu_baseline"] = None if (args.no_cpu_baseline or args.workload != "cfg1") else \
+    out["cpu_baseline"] = None if (args.no_cpu_baseline or args.workload != "cfg1" or args.precond != "scr") else \
         cpu_baseline(s, None, BM_host, args)
     print(json.dumps(out))
 

@@ -51,6 +51,12 @@ typedef enum { SCR_SYSTEM = 0, MESH_SYSTEM = 1 } scr_kind;
 typedef enum { SCR_FP64 = 0, SCR_MIXED = 1 } scr_precision;
 typedef enum { SCR_SMOOTH_JACOBI = 0, SCR_SMOOTH_CHEBYSHEV = 1 } scr_smoother;
 
+/* diagonal used in S^ (scr_amg_opts.schur_diag) */
+typedef enum { SCR_DIAG_A = 0, SCR_DIAG_ABSROWSUM = 1 } scr_schur_diag;
+
+/* outer preconditioner (scr_solve_opts.precond) */
+typedef enum { SCR_PRECOND_SCR = 0, SCR_PRECOND_SIMPLE = 1 } scr_precond;
+
 /* A square block-sparse matrix.  SCR_SYSTEM: bs = 4, block (i,j) = [[A_ij G_ij],[D_ij C_ij]]
  * with node-interleaved unknowns [vx vy vz p] (Sec. 3.5, corrector system; interface nodes
  * carry a duplicated pressure row as in Sec. 3.3, its velocity slots as identity rows).
@@ -77,6 +83,9 @@ typedef struct {
     int max_levels;            /* 10 */
     double max_coarse_ratio;   /* stop coarsening when n_{l+1} > ratio * n_l, 0.8 */
     uint64_t seed;             /* seed of the MIS-2 priorities, 0 */
+    int schur_diag;            /* SCR_SYSTEM: the diagonal d in S^ = C - D d^-1 G (Sec. 5.2.1):
+                                  SCR_DIAG_A (default) the diagonal of A; SCR_DIAG_ABSROWSUM the sums
+                                  of the absolute values of A's rows (the SIMPLEC lumping) */
 } scr_amg_opts;
 
 /* Krylov options.  Defaults: tol 1e-8 (outer), tol_A = tol_S = tol_I = 1e-3 and 200
@@ -88,6 +97,9 @@ typedef struct {
     int restart, restart_inner;
     int use_x0;                /* 1: x holds the initial guess on entry */
     int flexible_cg;           /* mesh solve: 1 = flexible CG (Notay), 0 = PCG; MIXED forces 1 */
+    int precond;               /* scr_solve: SCR_PRECOND_SCR (default, Appendix B Algorithm 1) or
+                                  SCR_PRECOND_SIMPLE (Sec. 5.2.1: S^ in place of S, d^-1 in the upper
+                                  factor; SIMPLEC when the handle was set up with SCR_DIAG_ABSROWSUM) */
 } scr_solve_opts;
 
 typedef struct {
@@ -186,6 +198,7 @@ scr_status scr_matrix_copy(scr_handle* h, int which, int field, void* dst /* hos
  *   3 y = V-cycle of AMG(S^) (n)  4 y = S x by Algorithm 2 (n) 5 y = P_SCR^-1 x, Algorithm 1 (4n)
  *   6 y = G x (n -> 3n)           7 y = D x (3n -> n)          8 y = C x (n)
  *   9 y = S^ x (n)               10 y = L x (mesh handle, n)  11 y = V-cycle of AMG(L) (n)
+ *  12 y = P_SIMPLE^-1 x (4n)     13 y = d, the diagonal used in S^ (3n; x unused)
  * x, y: device FP64. */
 scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const scr_solve_opts* opts,
                      void* stream);

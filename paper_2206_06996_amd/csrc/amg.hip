@@ -315,15 +315,32 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
     return C;
 }
 
-// ---------------------------------------------------------------------- S^ = C - D diag(A)^-1 G
+// ---------------------------------------------------------------------- S^ = C - D d^-1 G
+// d per velocity dof: the diagonal of A (mode 0) or the sum of the absolute values of its row
+// (mode 1, SIMPLEC), summed block by block in column order
+__global__ void schur_diag_k(int64_t nr, int mode, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const double* __restrict__ Av, double* __restrict__ d) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    if (mode == 0) {
+        int32_t dq = find_col(ci, rp[i], rp[i + 1], (int32_t)i);
+        for (int c = 0; c < 3; ++c) d[3 * i + c] = Av[(int64_t)dq * 9 + 4 * c];
+        return;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double sum = 0.0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+            for (int k = 0; k < 3; ++k) sum += fabs(Av[(int64_t)q * 9 + 3 * c + k]);
+        d[3 * i + c] = sum;
+    }
+}
 __global__ void diag_scale_D(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                             const double* __restrict__ Av, const double* __restrict__ Dv, double* __restrict__ X) {
+                             const double* __restrict__ d, const double* __restrict__ Dv, double* __restrict__ X) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nr) return;
     for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
         int32_t j = ci[q];
-        int32_t dq = find_col(ci, rp[j], rp[j + 1], j);
-        for (int c = 0; c < 3; ++c) X[(int64_t)q * 3 + c] = Dv[(int64_t)q * 3 + c] / Av[(int64_t)dq * 9 + 4 * c];
+        for (int c = 0; c < 3; ++c) X[(int64_t)q * 3 + c] = Dv[(int64_t)q * 3 + c] / d[3 * (int64_t)j + c];
     }
 }
 // union pattern of C and DG (both sorted): count, then fill with C - DG
@@ -351,10 +368,12 @@ __global__ void merge_sub_k(int64_t nr, const int32_t* __restrict__ arp, const i
     if (!PHASE) cnt[i] = n;
 }
 
-DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, Arena& ar, hipStream_t s) {
+DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, int mode, double* d, Arena& ar,
+                  hipStream_t s) {
     DBsr X = D;
     X.v = ar.make<double>(D.nnzb * 3);
-    if (D.nr > 0) diag_scale_D<<<cdiv(D.nr, 256), 256, 0, s>>>(D.nr, D.rp, D.ci, A.v, D.v, X.v);
+    if (A.nr > 0) schur_diag_k<<<cdiv(A.nr, 256), 256, 0, s>>>(A.nr, mode, A.rp, A.ci, A.v, d);
+    if (D.nr > 0) diag_scale_D<<<cdiv(D.nr, 256), 256, 0, s>>>(D.nr, D.rp, D.ci, d, D.v, X.v);
     check_launch("diag_scale_D");
     DBsr DG = spgemm(X, G, nullptr, ar, s);
     ar.free(X.v);

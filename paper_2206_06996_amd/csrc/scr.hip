@@ -21,8 +21,9 @@ struct scr_handle {
     int64_t nb = 0;
     // SCR system (FP64 setup form; A, G, D, C share K's index arrays)
     DBsr K, A, G, D, C, Sh;
-    DSell<double> Ks, As, Gs, Ds, Cs, Ls;
+    DSell<double> Ks, As, Gs, Ds, Cs, Ls, Shs;   // Shs: S^ for SIMPLE, built on first use
     double* B = nullptr;
+    double* dvec = nullptr;                       // the diagonal d used in S^ (3n)
     std::unique_ptr<Hierarchy> hA, hS, hL;
     std::unique_ptr<Gmres> gOuter, gA, gS;
     std::unique_ptr<Pcg> cg;
@@ -99,6 +100,46 @@ struct ScrPrec : Op {
     }
 };
 
+// y_v = y*_v - (G y_p) / d   (the SIMPLE velocity update; division as in the definition)
+__global__ void simple_update_k(int64_t n, const double* __restrict__ ystar, const double* __restrict__ t,
+                                const double* __restrict__ d, double* __restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = ystar[i] - t[i] / d[i];
+}
+
+// SIMPLE / SIMPLEC (Sec. 5.2.1): P = [I 0; D A^-1 I] [A 0; 0 S^] [I d^-1 G; 0 I];
+//   y*_v = A^-1 r_v (GMRES + AMG(A), delta_A);  y_p = S^^-1 (r_p - D y*_v) (GMRES + AMG(S^) on the
+//   explicit S^, delta_S: no inner-level solver);  y_v = y*_v - d^-1 (G y_p)
+struct SimplePrec : Op {
+    scr_handle* h;
+    explicit SimplePrec(scr_handle* hh) : h(hh) {}
+    void apply(const double* r, double* y, hipStream_t s) override {
+        const int64_t n = h->nb;
+        const double* rv = r;
+        const double* rp = r + 3 * n;
+        double* yv = y;
+        double* yp = y + 3 * n;
+        MatOp aop(&h->As);
+        VOp pa(h->hA.get(), &h->st.vcycles_A);
+        KStat k = h->gA->solve(aop, pa, rv, h->yhat, h->so.tol_A, h->so.max_it_A, false, false, s);
+        h->st.calls_A++;
+        h->st.its_A += k.iters;
+        sell_mv<double>(h->Ds, h->yhat, rp, h->tp, 1, s);            // r_p - D y*_v
+        MatOp shop(&h->Shs);
+        VOp ps(h->hS.get(), &h->st.vcycles_S);
+        k = h->gS->solve(shop, ps, h->tp, yp, h->so.tol_S, h->so.max_it_S, false, false, s);
+        h->st.calls_S++;
+        h->st.its_S += k.iters;
+        sell_mv<double>(h->Gs, yp, nullptr, h->tv, 0, s);            // G y_p
+        simple_update_k<<<cdiv(3 * n, 256), 256, 0, s>>>(3 * n, h->yhat, h->tv, h->dvec, yv);
+        check_launch("simple_update");
+    }
+};
+
+void ensure_simple(scr_handle* h, hipStream_t s) {
+    if (h->Shs.nslices == 0 && h->Sh.nr > 0) h->Shs = sell_from_bsr<double>(h->Sh, *h->ar, s);
+}
+
 scr_status fail(const Error& e) {
     set_last_error(e.what());
     return e.code;
@@ -128,6 +169,8 @@ void check_opts(const scr_solve_opts& o) {
     if (!(o.tol > 0) || !(o.tol_A > 0) || !(o.tol_S > 0) || !(o.tol_I > 0) || o.max_it < 1 || o.max_it_A < 1 ||
         o.max_it_S < 1 || o.max_it_I < 1)
         throw Error(SCR_E_INVALID, "tolerances must be positive and iteration limits >= 1");
+    if (o.precond != SCR_PRECOND_SCR && o.precond != SCR_PRECOND_SIMPLE)
+        throw Error(SCR_E_INVALID, "precond must be SCR_PRECOND_SCR or SCR_PRECOND_SIMPLE");
 }
 
 }  // namespace
@@ -145,6 +188,7 @@ void scr_default_amg_opts(scr_amg_opts* o) {
     o->max_levels = 10;
     o->max_coarse_ratio = 0.8;
     o->seed = 0;
+    o->schur_diag = SCR_DIAG_A;
 }
 
 void scr_default_solve_opts(scr_solve_opts* o) {
@@ -155,6 +199,7 @@ void scr_default_solve_opts(scr_solve_opts* o) {
     o->restart_inner = 30;
     o->use_x0 = 0;
     o->flexible_cg = 0;
+    o->precond = SCR_PRECOND_SCR;
 }
 
 const char* scr_status_str(scr_status s) {
@@ -284,7 +329,10 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         HIPCHK(hipMemcpyAsync(Km.v, K->val, K->nnzb * K->bs * K->bs * sizeof(double), hipMemcpyDeviceToDevice, s));
         if (kind == SCR_SYSTEM) {
             split_blocks(Km, h->A, h->G, h->D, h->C, ar, s);
-            h->Sh = schur_approx(h->A, h->G, h->D, h->C, ar, s);
+            if (o.schur_diag != SCR_DIAG_A && o.schur_diag != SCR_DIAG_ABSROWSUM)
+                throw Error(SCR_E_INVALID, "schur_diag must be SCR_DIAG_A or SCR_DIAG_ABSROWSUM");
+            h->dvec = ar.make<double>(3 * nb);
+            h->Sh = schur_approx(h->A, h->G, h->D, h->C, o.schur_diag, h->dvec, ar, s);
             double* xyz = ar.make<double>(nb * 3);
             HIPCHK(hipMemcpyAsync(xyz, coords, nb * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
             h->B = ar.make<double>(nb * 18);
@@ -370,7 +418,10 @@ scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_
         interleaved_to_split(nb, b, h->bs, s);
         if (o.use_x0) interleaved_to_split(nb, x, h->xs, s);
         KOp kop(&h->Ks);
-        ScrPrec prec(h);
+        ScrPrec prec_scr(h);
+        SimplePrec prec_simple(h);
+        if (o.precond == SCR_PRECOND_SIMPLE) ensure_simple(h, s);
+        Op& prec = o.precond == SCR_PRECOND_SIMPLE ? static_cast<Op&>(prec_simple) : static_cast<Op&>(prec_scr);
         KStat k = h->gOuter->solve(kop, prec, h->bs, h->xs, o.tol, o.max_it, o.use_x0 != 0, true, s);
         split_to_interleaved(nb, h->xs, x, s);
         HIPCHK(hipStreamSynchronize(s));
@@ -553,7 +604,8 @@ scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const sc
         ensure_workspaces(h, o, s);
         h->so = o;
         bool scr = h->kind == SCR_SYSTEM;
-        if ((op <= 9) != scr) throw Error(SCR_E_INVALID, "operator not available on this handle kind");
+        if ((op <= 9 || op == 12 || op == 13) != scr)
+            throw Error(SCR_E_INVALID, "operator not available on this handle kind");
         switch (op) {
             case 0: sell_mv_split4(h->Ks, x, nullptr, y, 0, s); break;
             case 1: sell_mv<double>(h->As, x, nullptr, y, 0, s); break;
@@ -573,6 +625,8 @@ scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const sc
             }
             case 10: sell_mv<double>(h->Ls, x, nullptr, y, 0, s); break;
             case 11: h->hL->vcycle(x, y, s); break;
+            case 12: { ensure_simple(h, s); SimplePrec p(h); p.apply(x, y, s); break; }
+            case 13: copy_d(3 * h->nb, h->dvec, y, s); break;
             default: throw Error(SCR_E_INVALID, "unknown operator");
         }
         HIPCHK(hipStreamSynchronize(s));

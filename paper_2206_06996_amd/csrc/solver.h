@@ -115,6 +115,8 @@ void rigid_modes(int64_t nb, const double* xyz, double* B, Arena& ar, hipStream_
 
 // split K (4x4) into A (3x3), G (3x1), D (1x3), C (1x1) and build S^ = C - D diag(A)^-1 G
 void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, hipStream_t s);
-DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, Arena& ar, hipStream_t s);
+// S^ = C - D d^-1 G; d (3n, written) = diag(A) (mode 0) or the absolute row sums of A (mode 1)
+DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, int mode, double* d, Arena& ar,
+                  hipStream_t s);
 
 }  // namespace scr

@@ -324,6 +324,11 @@ __device__ __forceinline__ T sell_row_dot(int64_t o0, int64_t o1, int lane, int 
 // WPS waves share one slice when a matrix has too few slices to fill the chip (coarse levels):
 // wave w of the group takes the w-th contiguous chunk of the slice's slots, and the partial row
 // sums are added in LDS in the fixed order w = 0, 1, ... (deterministic).
+// slices per workgroup and threads per workgroup for WPS waves per slice (at least 256 threads)
+template <int WPS> struct SliceGroup {
+    static constexpr int SPB = WPS >= 4 ? 1 : 4 / WPS;
+    static constexpr int THREADS = SPB * WPS * 64;
+};
 template <int WPS>
 __device__ __forceinline__ void slice_part(int64_t o0, int64_t o1, int part, int64_t& a, int64_t& b) {
     int64_t len = o1 - o0;
@@ -332,13 +337,13 @@ __device__ __forceinline__ void slice_part(int64_t o0, int64_t o1, int part, int
 }
 
 template <typename T, int BR, int BC, int MODE, int WPS>
-__global__ void __launch_bounds__(256) sell_mv_k(int64_t nslices, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) sell_mv_k(int64_t nslices, const int32_t* __restrict__ off,
                                                  const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
                                                  const T* __restrict__ v, const T* __restrict__ x,
                                                  const T* __restrict__ b, T* __restrict__ y) {
     constexpr int RPS = WAVE / BR;
     int wv = threadIdx.x / WAVE;
-    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * (4 / WPS) + wv / WPS;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * SliceGroup<WPS>::SPB + wv / WPS;
     int lane = threadIdx.x & (WAVE - 1);
     bool live = sl < nslices;
     auto xat = [&](int64_t c, int k) { return x[c * BC + k]; };
@@ -350,7 +355,7 @@ __global__ void __launch_bounds__(256) sell_mv_k(int64_t nslices, const int32_t*
         acc = sell_row_dot<T, BC, RPS>(a, e, lane, cl, ci, v, xat);
     }
     if (WPS > 1) {
-        __shared__ T red[4][WAVE];
+        __shared__ T red[SliceGroup<WPS>::SPB * WPS][WAVE];
         red[wv][lane] = acc;
         __syncthreads();
         if (wv % WPS != 0) return;
@@ -366,13 +371,16 @@ __global__ void __launch_bounds__(256) sell_mv_k(int64_t nslices, const int32_t*
     else y[o] -= acc;
 }
 
-// waves per slice: enough waves for about 16 per CU, if the slices are long enough to split
+// waves per slice: enough waves for about 16 per CU while every wave keeps at least 8 slots; on
+// small matrices (fewer than 512 slices, where the time is the latency of each wave's chain of
+// dependent loads) down to 4 slots per wave and up to 16 waves per slice
 template <typename T>
 static int waves_per_slice(const DSell<T>& A) {
     if (A.nslices <= 0) return 1;
     int64_t avg = A.slots / A.nslices;
+    int wmax = A.nslices < 512 ? 16 : 4, per = A.nslices < 512 ? 4 : 8;
     int w = 1;
-    while (w < 4 && A.nslices * w < 4096 && avg >= 8 * (w * 2)) w *= 2;
+    while (w < wmax && A.nslices * w < 4096 && avg >= per * (w * 2)) w *= 2;
     return w;
 }
 
@@ -452,18 +460,24 @@ static void sell_mv_dispatch_mode(const DSell<T>& A, const T* x, const T* b, T* 
     // splitting slices only pays on the square coarse-level shapes (6x6 A levels, 1x1 S^/L levels)
     constexpr bool SPLIT = (BR == 6 && BC == 6) || (BR == 1 && BC == 1);
     int wps = SPLIT ? waves_per_slice(A) : 1;
-    int64_t nblk = cdiv(A.nslices * wps, 4);
-    if (nblk == 0) return;
+    if (A.nslices == 0) return;
 #define MV(W)                                                                                                  \
-    switch (mode) {                                                                                            \
-        case 0: sell_mv_k<T, BR, BC, 0, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
-        case 1: sell_mv_k<T, BR, BC, 1, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
-        case 2: sell_mv_k<T, BR, BC, 2, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
-        default: sell_mv_k<T, BR, BC, 3, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+    {                                                                                                          \
+        constexpr int W_ = W;                                                                                  \
+        int64_t nblk = cdiv(A.nslices, SliceGroup<W_>::SPB);                                                   \
+        dim3 g((unsigned)nblk), t(SliceGroup<W_>::THREADS);                                                     \
+        switch (mode) {                                                                                        \
+            case 0: sell_mv_k<T, BR, BC, 0, W_><<<g, t, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+            case 1: sell_mv_k<T, BR, BC, 1, W_><<<g, t, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+            case 2: sell_mv_k<T, BR, BC, 2, W_><<<g, t, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+            default: sell_mv_k<T, BR, BC, 3, W_><<<g, t, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        }                                                                                                      \
     }
-    if (!SPLIT || wps == 1) { MV(1) }
-    else if (wps == 2) { MV((SPLIT ? 2 : 1)) }
-    else { MV((SPLIT ? 4 : 1)) }
+    if (!SPLIT || wps == 1) MV(1)
+    else if (wps == 2) MV((SPLIT ? 2 : 1))
+    else if (wps == 4) MV((SPLIT ? 4 : 1))
+    else if (wps == 8) MV((SPLIT ? 8 : 1))
+    else MV((SPLIT ? 16 : 1))
 #undef MV
     check_launch("sell_mv");
 }
@@ -578,7 +592,7 @@ template void bsrt_mv<float>(const DBsrT<float>&, const float*, float*, hipStrea
 // dn = c1*d + c2*Dinv*(b - A xin) ; xout = xin + dn.  One lane per scalar row; the block
 // residual of a block row is gathered from its B lanes with shuffles to apply Dinv.
 template <typename T, int B, bool RD, bool WD, bool ZERO, int WPS>
-__global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) smooth_k(int64_t nslices, const int32_t* __restrict__ off,
                                                 const int32_t* __restrict__ rowid,
                                                 const int32_t* __restrict__ ci, const T* __restrict__ v,
                                                 const T* __restrict__ Dinv, const T* __restrict__ b,
@@ -586,7 +600,7 @@ __global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* 
                                                 T c1, T c2) {
     constexpr int RPS = WAVE / B;
     int wv = threadIdx.x / WAVE;
-    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * (4 / WPS) + wv / WPS;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * SliceGroup<WPS>::SPB + wv / WPS;
     bool live = sl < nslices;
     int lane = threadIdx.x & (WAVE - 1);
     int cl = lane / B < RPS ? lane / B : RPS - 1;
@@ -598,7 +612,7 @@ __global__ void __launch_bounds__(256) smooth_k(int64_t nslices, const int32_t* 
         acc = sell_row_dot<T, B, RPS>(a, e, lane, cl, ci, v, xat);
     }
     if (WPS > 1) {
-        __shared__ T red[4][WAVE];
+        __shared__ T red[SliceGroup<WPS>::SPB * WPS][WAVE];
         red[wv][lane] = acc;
         __syncthreads();
         if (wv % WPS != 0) return;
@@ -684,21 +698,23 @@ template <typename T, int B>
 static void smooth_dispatch(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, T c1, T c2,
                             bool rd, bool wd, bool zero, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     int wps = zero ? 1 : waves_per_slice(A);
-    int64_t nblk = cdiv(A.nslices * wps, 4);
-    if (nblk == 0) return;
+    if (A.nslices == 0) return;
 #define SKW(RD, WD, Z, W)                                                                                          \
     do {                                                                                                           \
+        dim3 g((unsigned)cdiv(A.nslices, SliceGroup<W>::SPB)), t(SliceGroup<W>::THREADS);                          \
         if (e0)                                                                                                    \
-            hipExtLaunchKernelGGL((smooth_k<T, B, RD, WD, Z, W>), dim3((unsigned)nblk), dim3(256), 0, s, e0, e1,   \
-                                  0, A.nslices, (const int32_t*)A.off, (const int32_t*)A.rowid,                    \
-                                  (const int32_t*)A.ci, (const T*)A.v, Dinv, b, xin, d, xout, c1, c2);             \
+            hipExtLaunchKernelGGL((smooth_k<T, B, RD, WD, Z, W>), g, t, 0, s, e0, e1, 0, A.nslices,                \
+                                  (const int32_t*)A.off, (const int32_t*)A.rowid, (const int32_t*)A.ci,            \
+                                  (const T*)A.v, Dinv, b, xin, d, xout, c1, c2);                                   \
         else                                                                                                       \
-            smooth_k<T, B, RD, WD, Z, W><<<nblk, 256, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin,  \
-                                                             d, xout, c1, c2);                                     \
+            smooth_k<T, B, RD, WD, Z, W><<<g, t, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin, d,    \
+                                                        xout, c1, c2);                                             \
     } while (0)
 #define SK(RD, WD, Z)                                                                                              \
     do {                                                                                                           \
-        if (wps == 4) SKW(RD, WD, Z, 4);                                                                           \
+        if (wps == 16) SKW(RD, WD, Z, 16);                                                                         \
+        else if (wps == 8) SKW(RD, WD, Z, 8);                                                                      \
+        else if (wps == 4) SKW(RD, WD, Z, 4);                                                                      \
         else if (wps == 2) SKW(RD, WD, Z, 2);                                                                      \
         else SKW(RD, WD, Z, 1);                                                                                    \
     } while (0)

@@ -45,13 +45,15 @@ class ScrBsr(C.Structure):
 class AmgOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("theta", C.c_double), ("smoother", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("jacobi_sweeps", C.c_int), ("coarse_max", C.c_int),
-                ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64)]
+                ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
+                ("schur_diag", C.c_int)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_A", C.c_double), ("tol_S", C.c_double), ("tol_I", C.c_double),
                 ("max_it", C.c_int), ("max_it_A", C.c_int), ("max_it_S", C.c_int), ("max_it_I", C.c_int),
-                ("restart", C.c_int), ("restart_inner", C.c_int), ("use_x0", C.c_int), ("flexible_cg", C.c_int)]
+                ("restart", C.c_int), ("restart_inner", C.c_int), ("use_x0", C.c_int), ("flexible_cg", C.c_int),
+                ("precond", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -279,7 +281,10 @@ def mesh_motion_solve(h: Handle, b, x, opts: SolveOpts | None = None, stream=Non
     return rc, st.as_dict()
 
 
-OPS = {"K": 0, "A": 1, "VA": 2, "VS": 3, "S": 4, "SCR": 5, "G": 6, "D": 7, "C": 8, "Shat": 9, "L": 10, "VL": 11}
+OPS = {"K": 0, "A": 1, "VA": 2, "VS": 3, "S": 4, "SCR": 5, "G": 6, "D": 7, "C": 8, "Shat": 9, "L": 10, "VL": 11,
+       "SIMPLE": 12, "d": 13}
+SCR_DIAG_A, SCR_DIAG_ABSROWSUM = 0, 1
+SCR_PRECOND_SCR, SCR_PRECOND_SIMPLE = 0, 1
 
 
 def scr_apply(h: Handle, op: str, x, y, opts: SolveOpts | None = None, stream=None):
