@@ -378,9 +378,9 @@ template <typename T>
 static int waves_per_slice(const DSell<T>& A) {
     if (A.nslices <= 0) return 1;
     int64_t avg = A.slots / A.nslices;
-    int wmax = A.nslices < 512 ? 16 : 4, per = A.nslices < 512 ? 4 : 8;
+    int wmax = A.nslices < 512 ? 16 : 8, per = A.nslices < 512 ? 4 : 3;
     int w = 1;
-    while (w < wmax && A.nslices * w < 4096 && avg >= per * (w * 2)) w *= 2;
+    while (w < wmax && A.nslices * w < 16384 && avg >= per * (w * 2)) w *= 2;
     return w;
 }
 
