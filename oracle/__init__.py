@@ -109,6 +109,12 @@ def lib():
         L.orc_scr_solve.restype = C.c_int
         L.orc_scr_apply.argtypes = [P, C.c_int, P, P, C.POINTER(SolveOpts)]
         L.orc_scr_apply.restype = C.c_int
+        L.orc_amg_update.argtypes = [P, P, P]
+        L.orc_amg_update.restype = C.c_int
+        L.orc_scr_update.argtypes = [P, P, P]
+        L.orc_scr_update.restype = C.c_int
+        L.orc_mesh_update.argtypes = [P, P]
+        L.orc_mesh_update.restype = C.c_int
         L.orc_mesh_create.argtypes = [C.c_int64, P, P, P, C.POINTER(AmgOpts), C.POINTER(P)]
         L.orc_mesh_create.restype = C.c_int
         L.orc_mesh_free.argtypes = [P]
@@ -242,6 +248,13 @@ class Amg(Hierarchy):
             raise RuntimeError("oracle AMG setup failed")
         super().__init__(h, None)
 
+    def update(self, val, B=None):
+        """Numeric re-setup for new values on the same pattern (aggregates kept); B optional."""
+        val = _c(val, np.float64)
+        B = None if B is None else _c(B, np.float64)
+        if lib().orc_amg_update(self.h, _p(val), None if B is None else _p(B)):
+            raise RuntimeError("oracle AMG update failed")
+
     def __del__(self):
         if getattr(self, "h", None):
             lib().orc_amg_free(self.h)
@@ -262,6 +275,14 @@ class Scr:
             raise RuntimeError("oracle SCR setup failed")
         self.amgA = Hierarchy(lib().orc_scr_amg(self.h, 0), self)
         self.amgS = Hierarchy(lib().orc_scr_amg(self.h, 1), self)
+
+    def update(self, val, xyz=None):
+        """Numeric re-setup for new values on the same pattern (aggregates kept)."""
+        self.val = _c(val, np.float64)
+        xyz = None if xyz is None else _c(xyz, np.float64)
+        rc = lib().orc_scr_update(self.h, _p(self.val), None if xyz is None else _p(xyz))
+        if rc:
+            raise RuntimeError(f"oracle SCR update failed ({rc})")
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -315,6 +336,12 @@ class Mesh:
         if rc:
             raise RuntimeError("oracle mesh setup failed")
         self.amg = Hierarchy(lib().orc_mesh_amg(self.h), self)
+
+    def update(self, val):
+        """Numeric re-setup for new Laplacian values on the same pattern (aggregates kept)."""
+        self.val = _c(val, np.float64)
+        if lib().orc_mesh_update(self.h, _p(self.val)):
+            raise RuntimeError("oracle mesh update failed")
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -516,6 +516,70 @@ void orc_amg_free(amg* h) {
     free(h);
 }
 
+/* The value-dependent part of level l, given its aggregates: D^-1 and lambda_hat, the tentative
+ * prolongator (with the coarse near-null space and dead coarse dofs), the smoothed prolongator,
+ * R = P^T and the Galerkin product A_{l+1} = R A P (dead coarse dofs get a unit diagonal).
+ * Replaces whatever these fields held. */
+static int level_numeric(amg* h, int l) {
+    level* L = &h->L[l];
+    level* N = &h->L[l + 1];
+    int64_t nr = L->A->nr;
+    free(L->Dinv); L->Dinv = NULL;
+    if (level_diag(L)) return -1;
+    free(L->Q); free(N->B); free(L->dead);
+    bsr_free(L->P); bsr_free(L->R); bsr_free(N->A);
+    double* Q = (double*)malloc(sizeof(double) * nr * L->b * L->k);
+    N->b = L->k; N->k = L->k;
+    N->B = (double*)malloc(sizeof(double) * L->n_agg * L->k * L->k);
+    L->dead = (uint8_t*)calloc(L->n_agg * L->k, 1);
+    tentative(nr, L->b, L->k, L->agg, L->n_agg, L->B, Q, N->B, L->dead);
+    L->P = smooth_prolongator(L, Q);
+    L->Q = Q;
+    L->R = transpose(L->P);
+    bsr* AP = spgemm(L->A, L->P);
+    N->A = spgemm(L->R, AP);
+    bsr_free(AP);
+    for (int64_t a = 0; a < L->n_agg; ++a)
+        for (int c = 0; c < L->k; ++c)
+            if (L->dead[a * L->k + c]) {
+                int32_t q = find_in_row(N->A, a, (int32_t)a);
+                N->A->v[(int64_t)q * L->k * L->k + c * L->k + c] = 1.0;
+            }
+    return 0;
+}
+
+/* Coarsest level: dense LU of A_c. */
+static int coarse_factor(amg* h) {
+    level* Lc = &h->L[h->nlev - 1];
+    int64_t nc = Lc->A->nr * Lc->b;
+    h->ncoarse = nc;
+    free(h->LU); free(h->piv);
+    h->LU = (double*)calloc((size_t)nc * nc, sizeof(double));
+    h->piv = (int64_t*)malloc(sizeof(int64_t) * (nc > 0 ? nc : 1));
+    int b = Lc->b;
+    for (int64_t i = 0; i < Lc->A->nr; ++i)
+        for (int32_t q = Lc->A->rp[i]; q < Lc->A->rp[i + 1]; ++q)
+            for (int r = 0; r < b; ++r)
+                for (int c = 0; c < b; ++c)
+                    h->LU[(i * b + r) * nc + (int64_t)Lc->A->ci[q] * b + c] = Lc->A->v[(int64_t)q * b * b + r * b + c];
+    return lu_factor(nc, h->LU, h->piv);
+}
+
+/* Numeric re-setup (a reuse of the hierarchy when the matrix values change and its pattern does
+ * not): level 0 takes the new values (and, if B0 is not NULL, a new near-null space); the
+ * strength flags, MIS-2 roots and aggregates of every level are kept; every value-dependent
+ * quantity is recomputed level by level exactly as in a full setup. */
+static int amg_update(amg* h, const double* vals0, const double* B0) {
+    level* L0 = &h->L[0];
+    memcpy(L0->A->v, vals0, sizeof(double) * L0->A->nnzb * L0->b * L0->b);
+    if (B0) memcpy(L0->B, B0, sizeof(double) * L0->A->nr * L0->b * L0->k);
+    for (int l = 0; l + 1 < h->nlev; ++l)
+        if (level_numeric(h, l)) return -1;
+    return coarse_factor(h);
+}
+
+int orc_amg_update(amg* h, const double* vals0, const double* B0) { return amg_update(h, vals0, B0); }
+
 /* Build the hierarchy for the square b x b BSR matrix A0 with near-null space B0 ((nr*b) x k).
  * A0 is copied.  Returns NULL on failure. */
 static amg* amg_build(const bsr* A0, const double* B0, int k, const amg_opts* o) {
@@ -550,43 +614,14 @@ static amg* amg_build(const bsr* A0, const double* B0, int k, const amg_opts* o)
             free(L->agg); L->agg = NULL; free(L->strong); L->strong = NULL; L->n_agg = 0;
             break;
         }
-        if (level_diag(L)) { orc_amg_free(h); return NULL; }
-        double* Q = (double*)malloc(sizeof(double) * nr * L->b * L->k);
-        level* N = &h->L[l + 1];
-        N->b = L->k; N->k = L->k;
-        N->B = (double*)malloc(sizeof(double) * L->n_agg * L->k * L->k);
-        L->dead = (uint8_t*)calloc(L->n_agg * L->k, 1);
-        tentative(nr, L->b, L->k, L->agg, L->n_agg, L->B, Q, N->B, L->dead);
-        L->P = smooth_prolongator(L, Q);
-        L->Q = Q;
-        L->R = transpose(L->P);
-        bsr* AP = spgemm(L->A, L->P);
-        N->A = spgemm(L->R, AP);
-        bsr_free(AP);
-        for (int64_t a = 0; a < L->n_agg; ++a)
-            for (int c = 0; c < L->k; ++c)
-                if (L->dead[a * L->k + c]) {
-                    int32_t q = find_in_row(N->A, a, (int32_t)a);
-                    N->A->v[(int64_t)q * L->k * L->k + c * L->k + c] = 1.0;
-                }
+        if (level_numeric(h, l)) { orc_amg_free(h); return NULL; }
         ++l;
     }
     h->nlev = l + 1;
     /* smoother data on every level above the coarsest */
     for (int t = 0; t + 1 < h->nlev; ++t)
         if (!h->L[t].Dinv && level_diag(&h->L[t])) { orc_amg_free(h); return NULL; }
-    level* Lc = &h->L[h->nlev - 1];
-    int64_t nc = Lc->A->nr * Lc->b;
-    h->ncoarse = nc;
-    h->LU = (double*)calloc((size_t)nc * nc, sizeof(double));
-    h->piv = (int64_t*)malloc(sizeof(int64_t) * (nc > 0 ? nc : 1));
-    int b = Lc->b;
-    for (int64_t i = 0; i < Lc->A->nr; ++i)
-        for (int32_t q = Lc->A->rp[i]; q < Lc->A->rp[i + 1]; ++q)
-            for (int r = 0; r < b; ++r)
-                for (int c = 0; c < b; ++c)
-                    h->LU[(i * b + r) * nc + (int64_t)Lc->A->ci[q] * b + c] = Lc->A->v[(int64_t)q * b * b + r * b + c];
-    if (lu_factor(nc, h->LU, h->piv)) { orc_amg_free(h); return NULL; }
+    if (coarse_factor(h)) { orc_amg_free(h); return NULL; }
     h->work = (double*)malloc(sizeof(double) * 6 * (maxn + 8));
     return h;
 }
@@ -867,6 +902,7 @@ typedef struct {
     bsr *K, *A, *G, *D, *C, *Sh;
     double* diagA;
     amg *amgA, *amgS;
+    int schur_diag;
     solve_opts so;
     scr_stats st;
     double *t1, *t2, *t3;   /* scratch */
@@ -1055,6 +1091,7 @@ int orc_scr_create(int64_t nb, const int32_t* rp, const int32_t* ci, const doubl
     memcpy(s->K->v, val, sizeof(double) * rp[nb] * 16);
     split_blocks(s->K, &s->A, &s->G, &s->D, &s->C);
     s->diagA = (double*)malloc(sizeof(double) * 3 * nb);
+    s->schur_diag = ao->schur_diag;
     s->Sh = schur_approx(s->A, s->G, s->D, s->C, s->diagA, ao->schur_diag);
     double* B = (double*)malloc(sizeof(double) * nb * 18);
     rigid_modes(nb, xyz, B);
@@ -1067,6 +1104,27 @@ int orc_scr_create(int64_t nb, const int32_t* rp, const int32_t* ci, const doubl
     *out = s;
     if (!s->amgA || !s->amgS) return -1;
     return 0;
+}
+
+/* Numeric re-setup for a new matrix with the same pattern (and, if xyz is not NULL, new node
+ * coordinates): the split, d and S^ are recomputed (S^ keeps its structural pattern), and both
+ * hierarchies are updated with their aggregates kept (amg_update). */
+int orc_scr_update(scr* s, const double* val, const double* xyz) {
+    int64_t nb = s->nb;
+    memcpy(s->K->v, val, sizeof(double) * s->K->nnzb * 16);
+    bsr_free(s->A); bsr_free(s->G); bsr_free(s->D); bsr_free(s->C); bsr_free(s->Sh);
+    split_blocks(s->K, &s->A, &s->G, &s->D, &s->C);
+    s->Sh = schur_approx(s->A, s->G, s->D, s->C, s->diagA, s->schur_diag);
+    double* B = NULL;
+    if (xyz) {
+        B = (double*)malloc(sizeof(double) * nb * 18);
+        rigid_modes(nb, xyz, B);
+    }
+    int rc = amg_update(s->amgA, s->A->v, B);
+    free(B);
+    if (rc) return -1;
+    if (s->amgS->L[0].A->nnzb != s->Sh->nnzb) return -2;
+    return amg_update(s->amgS, s->Sh->v, NULL);
 }
 
 void orc_scr_free(scr* s) {
@@ -1170,6 +1228,11 @@ int orc_mesh_create(int64_t n, const int32_t* rp, const int32_t* ci, const doubl
     return m->h ? 0 : -1;
 }
 void orc_mesh_free(mesh* m) { if (!m) return; bsr_free(m->L); orc_amg_free(m->h); free(m); }
+/* Numeric re-setup of the mesh hierarchy for new Laplacian values on the same pattern. */
+int orc_mesh_update(mesh* m, const double* val) {
+    memcpy(m->L->v, val, sizeof(double) * m->L->nnzb);
+    return amg_update(m->h, val, NULL);
+}
 amg* orc_mesh_amg(mesh* m) { return m->h; }
 
 /* Three independent CG solves (x, y, z components), b and x interleaved n x 3.

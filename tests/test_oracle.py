@@ -482,3 +482,95 @@ def test_mesh_motion_cg_amg_matches_dense(small_fsi):
     X = np.linalg.solve(L, b.reshape(-1, 3))
     assert rc == 0 and np.abs(x.reshape(-1, 3) - X).max() <= 1e-9 * np.abs(X).max()
     assert np.all(its > 0) and np.all(rel <= 1e-12)
+
+
+# ----------------------------------------------------------------------------- numeric re-setup
+_FIELDS = ("A.rp", "A.ci", "A.v", "agg", "strong", "dead", "P.rp", "P.ci", "P.v", "R.rp", "R.ci", "R.v", "Dinv", "B")
+
+
+def _same_hierarchy(h1, h2):
+    assert h1.nlevels == h2.nlevels
+    for l in range(h1.nlevels):
+        i1, i2 = h1.info(l), h2.info(l)
+        assert i1 == i2, (l, i1, i2)
+        fields = _FIELDS if l + 1 < h1.nlevels else ("A.rp", "A.ci", "A.v", "B")
+        for f in fields:
+            assert np.array_equal(h1.get(l, f), h2.get(l, f)), (l, f)
+
+
+def _node_scaling(nb, seed):
+    """powers of two per block row: a similarity S K S that changes every value but leaves
+    every strength ratio exactly as it was"""
+    return np.exp2(np.random.default_rng(seed).integers(-3, 4, nb)).astype(np.float64)
+
+
+def test_update_with_the_same_values_is_identical(small_fsi):
+    s = small_fsi
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(coarse_max=60))
+    ref = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(coarse_max=60))
+    o.update(s.val.copy())
+    _same_hierarchy(o.amgA, ref.amgA)
+    _same_hierarchy(o.amgS, ref.amgS)
+    b = synth.rhs(2, 4 * s.n_b, s.mask)
+    assert np.array_equal(o.solve(b)[0], ref.solve(b)[0])
+
+
+@pytest.mark.parametrize("case", ["similarity_two_level", "uniform_scaling"])
+def test_update_equals_a_fresh_setup_when_aggregates_coincide(small_fsi, case):
+    # A numeric re-setup must reproduce a full setup exactly whenever the full setup would pick
+    # the same aggregates, so that nothing value-dependent (d, S^, D^-1, lambda, P_tent, P, R,
+    # RAP, dead dofs, coarse LU) is stale.  Two such changes:
+    #  * K' = S K S with S a diagonal of powers of two per node: every value and every P changes,
+    #    the level-0 strength ratios cannot (two-level hierarchies: only level 0 aggregates);
+    #  * K' = 2 K: every level's strength ratios are unchanged (all levels).
+    s = small_fsi
+    rows = np.repeat(np.arange(s.n_b), np.diff(s.rp))
+    if case == "similarity_two_level":
+        sc = _node_scaling(s.n_b, 3)
+        val2 = s.val * (sc[rows] * sc[s.ci])[:, None, None]
+        ao = oracle.amg_opts(coarse_max=60, max_levels=2)
+    else:
+        val2 = 2.0 * s.val
+        ao = oracle.amg_opts(coarse_max=60)
+    fresh = oracle.Scr(s.rp, s.ci, val2, s.xyz, ao)
+    upd = oracle.Scr(s.rp, s.ci, s.val, s.xyz, ao)
+    upd.update(val2)
+    _same_hierarchy(upd.amgA, fresh.amgA)
+    _same_hierarchy(upd.amgS, fresh.amgS)
+    for name in ("A", "G", "D", "C", "Shat"):
+        for a, b_ in zip(upd.matrix(name), fresh.matrix(name)):
+            assert np.array_equal(a, b_), name
+    b = synth.rhs(5, 4 * s.n_b, s.mask)
+    x1, rc1, st1 = upd.solve(b)
+    x2, rc2, st2 = fresh.solve(b)
+    assert rc1 == rc2 == 0 and np.array_equal(x1, x2) and st1 == st2
+
+
+def test_update_keeps_aggregates_for_a_changed_time_step(small_fsi):
+    # a different dt changes the mass term, and a fresh setup would aggregate differently; the
+    # re-setup keeps the old aggregates and still solves the new system
+    s = small_fsi
+    p2 = synth.default_params(mode=0, m_core=2, n_bl=1, n_wall=1, nz=8, R=1.0, L=2.0, dt=2e-3)
+    s2 = synth.generate(p2)
+    assert np.array_equal(s.rp, s2.rp) and np.array_equal(s.ci, s2.ci)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(coarse_max=60))
+    agg0 = [o.amgA.get(l, "agg").copy() for l in range(o.amgA.nlevels - 1)]
+    o.update(s2.val)
+    for l, a in enumerate(agg0):
+        assert np.array_equal(o.amgA.get(l, "agg"), a)
+    b = synth.rhs(6, 4 * s.n_b, s2.mask)
+    x, rc, st = o.solve(b, oracle.solve_opts(tol=1e-11))
+    xl = oracle.dense_solve(bsr_to_dense(s2.rp, s2.ci, s2.val), b)
+    assert rc == 0 and np.linalg.norm(x - xl) <= 1e-9 * np.linalg.norm(xl)
+
+
+def test_mesh_update_equals_a_fresh_setup_when_aggregates_coincide(cfg0):
+    s = cfg0
+    sc = _node_scaling(s.n_phys, 4)
+    rows = np.repeat(np.arange(s.n_phys), np.diff(s.Lrp))
+    v2 = s.Lval * sc[rows] * sc[s.Lci]
+    ao = oracle.amg_opts(max_levels=2, coarse_max=4000)
+    fresh = oracle.Mesh(s.Lrp, s.Lci, v2, ao)
+    upd = oracle.Mesh(s.Lrp, s.Lci, s.Lval, ao)
+    upd.update(v2)
+    _same_hierarchy(upd.amg, fresh.amg)
