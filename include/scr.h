@@ -140,6 +140,21 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
                      const scr_amg_opts* opts /* host, NULL = defaults */, void* stream,
                      scr_handle** out /* host */);
 
+/* Numeric re-setup for a new matrix on the same sparsity pattern (successive Newton correctors
+ * and time steps, Sec. 3.5, change the values of the tangent matrix but not its pattern; the
+ * mesh-motion matrix of Sec. 2.2.2 may be rescaled): K must have the handle's kind, n_brows,
+ * nnzb, row_ptr and col_idx.  The strength flags, MIS-2 aggregates and every sparsity pattern of
+ * both hierarchies are kept; every value-dependent quantity (the split, d and S^, the tentative
+ * and smoothed prolongators, R, the Galerkin products, D^-1, lambda_hat, the coarse inverse, the
+ * solve-phase copies) is recomputed exactly as amg_setup would from the same aggregates.
+ * coords: device, n_brows x 3 FP64, or NULL to keep the rigid-body modes (SCR_SYSTEM only;
+ * ignored for MESH_SYSTEM).  Same stream rules as amg_setup; stats.t_setup_ms of the next solve
+ * reports this call's time.  Errors: SCR_E_INVALID with the handle unchanged for a different
+ * pattern or size, non-finite values or a zero diagonal; an error raised after the values were
+ * accepted (a singular block met on a coarse level, SCR_E_OOM, SCR_E_HIP) leaves the handle
+ * unusable: every later solve or update on it returns SCR_E_INVALID, destroy it. */
+scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, void* stream);
+
 /* Solve K x = b (SCR_SYSTEM handle) by FGMRES(P_SCR) to ||b - K x|| <= tol ||b|| (true FP64
  * residual, checked at exit).  b, x: device, 4 * n_brows FP64, node-interleaved [vx vy vz p].
  * x is the initial guess if use_x0, else it is overwritten.  Returns SCR_OK, or

@@ -66,6 +66,11 @@ __global__ void split_k(int64_t nnzb, const double* __restrict__ K, double* __re
     C[q] = k[15];
 }
 
+void split_values(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, hipStream_t s) {
+    if (K.nnzb > 0) split_k<<<cdiv(K.nnzb, 256), 256, 0, s>>>(K.nnzb, K.v, A.v, G.v, D.v, C.v);
+    check_launch("split");
+}
+
 void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, hipStream_t s) {
     auto mk = [&](DBsr& M, int br, int bc) {
         M.nr = K.nr; M.nc = K.nc; M.br = br; M.bc = bc; M.nnzb = K.nnzb;
@@ -247,6 +252,45 @@ __global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, cons
         for (int e = 0; e < MP; ++e) cv[(int64_t)(c0 + p) * MP + e] = acc[p * MP + e];
 }
 
+// numeric phase of C = X Y into C's pattern (wmax = longest row of C): the LDS form when its
+// accumulators fit, else the pull form
+static void spgemm_numeric_run(const DBsr& X, const DBsr& Y, DBsr& C, int wmax, hipStream_t s) {
+    int64_t nb = cdiv(X.nr, 4);
+    int key = X.br * 100 + X.bc * 10 + Y.bc;
+    int hsn = 64;
+    while (hsn < 2 * wmax) hsn <<= 1;
+    size_t lds_n = (size_t)2 * hsn * sizeof(int) + (size_t)wmax * C.br * C.bc * sizeof(double);
+    if (X.nr > 0 && lds_n <= 64 * 1024) {
+#define SPL(m, n, p)                                                                                          \
+    spg_numeric_lds<m, n, p><<<X.nr, WAVE, lds_n, s>>>(X.nr, hsn, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, \
+                                                       C.v)
+        switch (key) {
+            case 111: SPL(1, 1, 1); break;
+            case 131: SPL(1, 3, 1); break;
+            case 336: SPL(3, 3, 6); break;
+            case 636: SPL(6, 3, 6); break;
+            case 666: SPL(6, 6, 6); break;
+            default: throw Error(SCR_E_UNIMPLEMENTED, "spgemm block shape " + std::to_string(key));
+        }
+#undef SPL
+        check_launch("spg_numeric");
+        return;
+    }
+#define SPN(m, n, p) spg_numeric<m, n, p><<<nb, 256, 0, s>>>(X.nr, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v)
+    if (nb > 0) {
+        switch (key) {
+            case 111: SPN(1, 1, 1); break;
+            case 131: SPN(1, 3, 1); break;
+            case 336: SPN(3, 3, 6); break;
+            case 636: SPN(6, 3, 6); break;
+            case 666: SPN(6, 6, 6); break;
+            default: throw Error(SCR_E_UNIMPLEMENTED, "spgemm block shape " + std::to_string(key));
+        }
+    }
+#undef SPN
+    check_launch("spg_numeric");
+}
+
 static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hipStream_t s) {
     DBsr C;
     C.nr = X.nr; C.nc = Y.nc; C.br = X.br; C.bc = Y.bc;
@@ -278,41 +322,26 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
         spg_symbolic<1><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, flags);
     check_launch("spg_fill");
     ar.free(flags);
-    int64_t nb = cdiv(X.nr, 4);
-    int key = X.br * 100 + X.bc * 10 + Y.bc;
-    int hsn = 64;
-    while (hsn < 2 * wmax) hsn <<= 1;
-    size_t lds_n = (size_t)2 * hsn * sizeof(int) + (size_t)wmax * C.br * C.bc * sizeof(double);
-    if (X.nr > 0 && lds_n <= 64 * 1024) {
-#define SPL(m, n, p)                                                                                          \
-    spg_numeric_lds<m, n, p><<<X.nr, WAVE, lds_n, s>>>(X.nr, hsn, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, \
-                                                       C.v)
-        switch (key) {
-            case 111: SPL(1, 1, 1); break;
-            case 131: SPL(1, 3, 1); break;
-            case 336: SPL(3, 3, 6); break;
-            case 636: SPL(6, 3, 6); break;
-            case 666: SPL(6, 6, 6); break;
-            default: throw Error(SCR_E_UNIMPLEMENTED, "spgemm block shape " + std::to_string(key));
-        }
-#undef SPL
-        check_launch("spg_numeric");
-        return C;
-    }
-#define SPN(m, n, p) spg_numeric<m, n, p><<<nb, 256, 0, s>>>(X.nr, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v)
-    if (nb > 0) {
-        switch (key) {
-            case 111: SPN(1, 1, 1); break;
-            case 131: SPN(1, 3, 1); break;
-            case 336: SPN(3, 3, 6); break;
-            case 636: SPN(6, 3, 6); break;
-            case 666: SPN(6, 6, 6); break;
-            default: throw Error(SCR_E_UNIMPLEMENTED, "spgemm block shape " + std::to_string(key));
-        }
-    }
-#undef SPN
-    check_launch("spg_numeric");
+    spgemm_numeric_run(X, Y, C, wmax, s);
     return C;
+}
+
+// max row length of a pattern
+__global__ void rowlen_max_k(int64_t nr, const int32_t* __restrict__ rp, int* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) atomicMax(out, rp[i + 1] - rp[i]);
+}
+
+// numeric phase only, into the existing pattern of C (same terms and order as a full product)
+static void spgemm_numeric(const DBsr& X, const DBsr& Y, DBsr& C, Arena& ar, hipStream_t s) {
+    int* d = ar.make<int>(1);
+    HIPCHK(hipMemsetAsync(d, 0, sizeof(int), s));
+    if (C.nr > 0) rowlen_max_k<<<cdiv(C.nr, 256), 256, 0, s>>>(C.nr, C.rp, d);
+    int wmax = 0;
+    HIPCHK(hipMemcpyAsync(&wmax, d, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ar.free(d);
+    spgemm_numeric_run(X, Y, C, wmax, s);
 }
 
 // ---------------------------------------------------------------------- S^ = C - D d^-1 G
@@ -391,6 +420,21 @@ DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, in
     check_launch("merge_sub");
     bsr_release(DG, ar);
     return S;
+}
+
+void schur_update(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, int mode, double* d, DBsr& S, Arena& ar,
+                  hipStream_t s) {
+    DBsr X = D;
+    X.v = ar.make<double>(D.nnzb * 3);
+    if (A.nr > 0) schur_diag_k<<<cdiv(A.nr, 256), 256, 0, s>>>(A.nr, mode, A.rp, A.ci, A.v, d);
+    if (D.nr > 0) diag_scale_D<<<cdiv(D.nr, 256), 256, 0, s>>>(D.nr, D.rp, D.ci, d, D.v, X.v);
+    check_launch("diag_scale_D");
+    DBsr DG = spgemm(X, G, nullptr, ar, s);
+    ar.free(X.v);
+    int64_t nb = cdiv(C.nr, 256);
+    if (nb) merge_sub_k<1><<<nb, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, nullptr, S.rp, S.ci, S.v);
+    check_launch("merge_sub");
+    bsr_release(DG, ar);
 }
 
 // ---------------------------------------------------------------------- rigid-body modes
@@ -875,6 +919,17 @@ class HierT : public Hierarchy {
         }
     }
 
+    void refresh(Arena& a, hipStream_t s) override {
+        for (auto& q : S) {
+            sell_free(q.A, a);
+            sell_free(q.P, a);
+            a.free(q.R.v);
+            for (T* p : {q.Dinv, q.b, q.x, q.w, q.t1, q.t2, q.d, q.r}) a.free(p);
+        }
+        S.clear();
+        prepare(a, s);
+    }
+
     // algorithmic bytes of one smoother step with a matrix product: every stored block (values
     // and column index) once, x once, the right-hand side, D^-1, the output and d as used
     double step_bytes(const LS& q, bool rd, bool wd) const {
@@ -939,6 +994,57 @@ static int64_t read_i32(const int32_t* p, hipStream_t s) {
     return v;
 }
 
+// D^-1 (into L.Dinv) and lambda_hat = max abs row sum of D^-1 A (into L.lam)
+static void level_diag(LevelSetup& L, int l, int* err, unsigned long long* lamd, hipStream_t s) {
+    const int64_t nr = L.A.nr;
+    const int64_t g = cdiv(nr, 256);
+    const int b = L.b;
+    HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(lamd, 0, sizeof(unsigned long long), s));
+    if (g) {
+        if (b == 1) dinv_lambda_k<1><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
+        else if (b == 3) dinv_lambda_k<3><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
+        else if (b == 6) dinv_lambda_k<6><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
+        else throw Error(SCR_E_UNIMPLEMENTED, "AMG block size");
+    }
+    check_launch("dinv_lambda");
+    unsigned long long hl = 0;
+    int he = 0;
+    HIPCHK(hipMemcpyAsync(&hl, lamd, sizeof(hl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (he) throw Error(SCR_E_INVALID, "singular or missing diagonal block at AMG level " + std::to_string(l));
+    double lam;
+    std::memcpy(&lam, &hl, sizeof(double));
+    L.lam = lam;
+}
+
+// coarsest level: explicit inverse by Gauss-Jordan exchange steps (the matrix is SPD)
+static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
+    LevelSetup& C = H.L.back();
+    int64_t nc = C.A.nr * C.b;
+    H.ncoarse = nc;
+    if (nc > 8192) throw Error(SCR_E_INVALID, "coarsest AMG level too large for a direct solve (" + std::to_string(nc) + ")");
+    if (H.cinv) { ar.free(H.cinv); H.cinv = nullptr; }
+    double* M0 = ar.make<double>(nc * nc + 1);
+    double* M1 = ar.make<double>(nc * nc + 1);
+    HIPCHK(hipMemsetAsync(M0, 0, nc * nc * sizeof(double), s));
+    if (C.A.nr) densify_k<<<cdiv(C.A.nr, 256), 256, 0, s>>>(C.A.nr, C.b, C.A.rp, C.A.ci, C.A.v, M0, nc);
+    for (int64_t kp = 0; kp < nc; ++kp) {
+        gj_step_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc, kp, M0, M1);
+        std::swap(M0, M1);
+    }
+    check_launch("coarse inverse");
+    HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+    if (nc) finite_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc * nc, M0, err);
+    int he = 0;
+    HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (he) throw Error(SCR_E_INVALID, "coarsest AMG matrix is singular");
+    ar.free(M1);
+    H.cinv = M0;
+}
+
 std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
                                            hipStream_t s, Profiler* prof) {
     std::unique_ptr<Hierarchy> H;
@@ -969,24 +1075,8 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         const int64_t g = cdiv(nr, 256);
         // D^-1 and lambda_hat (every level but the coarsest needs them; computed here for all)
         L.Dinv = ar.make<double>(nr * bb);
-        HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
-        HIPCHK(hipMemsetAsync(lamd, 0, sizeof(unsigned long long), s));
-        if (g) {
-            if (b == 1) dinv_lambda_k<1><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
-            else if (b == 3) dinv_lambda_k<3><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
-            else if (b == 6) dinv_lambda_k<6><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
-            else throw Error(SCR_E_UNIMPLEMENTED, "AMG block size");
-        }
-        check_launch("dinv_lambda");
-        unsigned long long hl = 0;
+        level_diag(L, l, err, lamd, s);
         int he = 0;
-        HIPCHK(hipMemcpyAsync(&hl, lamd, sizeof(hl), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (he) throw Error(SCR_E_INVALID, "singular or missing diagonal block at AMG level " + std::to_string(l));
-        double lam;
-        std::memcpy(&lam, &hl, sizeof(double));
-        L.lam = lam;
         if (n <= o.coarse_max || l + 1 >= o.max_levels || l + 1 >= 16) break;
         // strength
         double* fd = ar.make<double>(nr);
@@ -1061,7 +1151,9 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         HIPCHK(hipMemsetAsync(L.dead, 0, na * kk, s));
         tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, kk, mrp, mem, L.B, Q, N.B, L.dead);
         check_launch("tentative");
-        ar.free(mcnt); ar.free(mrp); ar.free(mem);
+        ar.free(mcnt);
+        L.mrp = mrp;
+        L.mem = mem;
         DBsr Pt;
         Pt.nr = nr; Pt.nc = na; Pt.br = b; Pt.bc = kk;
         Pt.rp = ar.make<int32_t>(nr + 1);
@@ -1091,41 +1183,79 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         // Galerkin product A_c = R (A P) on structural patterns; dead coarse dofs get a unit diagonal
         DBsr AP = spgemm(L.A, L.P, nullptr, ar, s);
         N.A = spgemm(L.R, AP, nullptr, ar, s);
-        bsr_release(AP, ar);
+        ar.free(AP.v);
+        AP.v = nullptr;
+        L.AP = AP;
         if (na) dead_diag_k<<<cdiv(na, 256), 256, 0, s>>>(na, kk, N.A.rp, N.A.ci, N.A.v, L.dead);
         check_launch("dead_diag");
         H->L.push_back(N);   // invalidates L
     }
-    // coarsest level: explicit inverse by Gauss-Jordan exchange steps (the matrix is SPD)
-    {
-        LevelSetup& C = H->L.back();
-        int64_t nc = C.A.nr * C.b;
-        H->ncoarse = nc;
-        if (nc > 8192) throw Error(SCR_E_INVALID, "coarsest AMG level too large for a direct solve (" + std::to_string(nc) + ")");
-        double* M0 = ar.make<double>(nc * nc + 1);
-        double* M1 = ar.make<double>(nc * nc + 1);
-        HIPCHK(hipMemsetAsync(M0, 0, nc * nc * sizeof(double), s));
-        if (C.A.nr) densify_k<<<cdiv(C.A.nr, 256), 256, 0, s>>>(C.A.nr, C.b, C.A.rp, C.A.ci, C.A.v, M0, nc);
-        for (int64_t kp = 0; kp < nc; ++kp) {
-            gj_step_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc, kp, M0, M1);
-            std::swap(M0, M1);
-        }
-        check_launch("coarse inverse");
-        HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
-        if (nc) finite_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc * nc, M0, err);
-        int he = 0;
-        HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (he) throw Error(SCR_E_INVALID, "coarsest AMG matrix is singular");
-        ar.free(M1);
-        H->cinv = M0;
-    }
+    coarse_inverse(*H, err, ar, s);
     ar.free(err);
     ar.free(lamd);
     if (hf) hf->prepare(ar, s);
     else hd->prepare(ar, s);
     HIPCHK(hipStreamSynchronize(s));
     return H;
+}
+
+void update_hierarchy(Hierarchy& H, const double* vals0, const double* B0, Arena& ar, hipStream_t s) {
+    int* err = ar.make<int>(1);
+    unsigned long long* lamd = ar.make<unsigned long long>(1);
+    LevelSetup& L0 = H.L[0];
+    HIPCHK(hipMemcpyAsync(L0.A.v, vals0, L0.A.nnzb * L0.b * L0.b * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (B0) HIPCHK(hipMemcpyAsync(L0.B, B0, L0.A.nr * L0.b * L0.k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (size_t l = 0; l < H.L.size(); ++l) {
+        LevelSetup& L = H.L[l];
+        level_diag(L, (int)l, err, lamd, s);
+        if (l + 1 == H.L.size()) break;
+        LevelSetup& N = H.L[l + 1];
+        const int64_t nr = L.A.nr, na = L.nagg;
+        const int b = L.b, kk = L.k;
+        const int64_t g = cdiv(nr, 256);
+        // tentative prolongator, coarse near-null space and dead dofs from the kept aggregates
+        double* Q = ar.make<double>(nr * b * kk);
+        HIPCHK(hipMemsetAsync(Q, 0, nr * b * kk * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(L.dead, 0, na * kk, s));
+        tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, kk, L.mrp, L.mem, L.B, Q, N.B, L.dead);
+        check_launch("tentative");
+        DBsr Pt;
+        Pt.nr = nr; Pt.nc = na; Pt.br = b; Pt.bc = kk;
+        Pt.rp = ar.make<int32_t>(nr + 1);
+        int32_t* pc = ar.make<int32_t>(nr + 1);
+        ptent_cnt_k<<<g, 256, 0, s>>>(nr, L.agg, pc);
+        Pt.nnzb = scan_i32(pc, Pt.rp, nr, ar, s);
+        ar.free(pc);
+        Pt.ci = ar.make<int32_t>(Pt.nnzb + 1);
+        Pt.v = ar.make<double>((Pt.nnzb + 1) * b * kk);
+        ptent_fill_k<<<g, 256, 0, s>>>(nr, b * kk, L.agg, Pt.rp, Q, Pt.ci, Pt.v);
+        check_launch("ptent");
+        // smoothed prolongator into its kept pattern
+        spgemm_numeric(L.A, Pt, L.P, ar, s);
+        bsr_release(Pt, ar);
+        double omega = 4.0 / (3.0 * L.lam);
+        if (b == 1 && kk == 1) smooth_p_k<1, 1><<<g, 256, 0, s>>>(nr, L.P.rp, L.P.ci, L.P.v, L.Dinv, L.agg, Q, omega);
+        else if (b == 3 && kk == 6) smooth_p_k<3, 6><<<g, 256, 0, s>>>(nr, L.P.rp, L.P.ci, L.P.v, L.Dinv, L.agg, Q, omega);
+        else if (b == 6 && kk == 6) smooth_p_k<6, 6><<<g, 256, 0, s>>>(nr, L.P.rp, L.P.ci, L.P.v, L.Dinv, L.agg, Q, omega);
+        else throw Error(SCR_E_UNIMPLEMENTED, "prolongator block shape");
+        check_launch("smooth_p");
+        ar.free(Q);
+        bsr_release(L.R, ar);
+        L.R = transpose(L.P, ar, s);
+        // Galerkin product into the kept patterns of A P and A_{l+1}
+        L.AP.v = ar.make<double>((L.AP.nnzb > 0 ? L.AP.nnzb : 1) * L.AP.br * L.AP.bc);
+        spgemm_numeric(L.A, L.P, L.AP, ar, s);
+        spgemm_numeric(L.R, L.AP, N.A, ar, s);
+        ar.free(L.AP.v);
+        L.AP.v = nullptr;
+        if (na) dead_diag_k<<<cdiv(na, 256), 256, 0, s>>>(na, kk, N.A.rp, N.A.ci, N.A.v, L.dead);
+        check_launch("dead_diag");
+    }
+    coarse_inverse(H, err, ar, s);
+    ar.free(err);
+    ar.free(lamd);
+    H.refresh(ar, s);
+    HIPCHK(hipStreamSynchronize(s));
 }
 
 }  // namespace scr

@@ -32,6 +32,7 @@ struct scr_handle {
            *xtil = nullptr, *col_b = nullptr, *col_x = nullptr;
     scr_stats st{};
     scr_solve_opts so{};
+    bool broken = false;                          // a failed amg_update left the hierarchies half-updated
 };
 
 namespace {
@@ -163,6 +164,17 @@ void ensure_workspaces(scr_handle* h, const scr_solve_opts& o, hipStream_t s) {
     } else if (!h->cg) {
         h->cg.reset(new Pcg(h->nb, *h->ar, s));
     }
+}
+
+// flag = 1 if the pattern (rp, ci) differs from the stored one (rp already known to be in range)
+__global__ void pattern_diff_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                               const int32_t* __restrict__ rp0, const int32_t* __restrict__ ci0, int* __restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nr) return;
+    if (rp[i] != rp0[i]) { atomicOr(flag, 1); return; }
+    if (i == nr) return;
+    for (int32_t q = rp0[i]; q < rp0[i + 1]; ++q)
+        if (ci[q] != ci0[q]) { atomicOr(flag, 1); return; }
 }
 
 void check_opts(const scr_solve_opts& o) {
@@ -380,6 +392,76 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
     }
 }
 
+scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!h || !K) throw Error(SCR_E_INVALID, "NULL argument");
+        if (h->broken) throw Error(SCR_E_INVALID, "handle left unusable by a failed amg_update");
+        if (!K->row_ptr || !K->col_idx || !K->val) throw Error(SCR_E_INVALID, "NULL matrix array");
+        DBsr& Km = h->K;
+        if (K->bs != Km.br || K->n_brows != h->nb || K->nnzb != Km.nnzb)
+            throw Error(SCR_E_INVALID, "block size, row count or nnzb differ from the handle's matrix");
+        HIPCHK(hipSetDevice(h->ctx->device));
+        Arena& ar = *h->ar;
+        const int64_t nb = h->nb;
+        // the pattern must be the stored one: row_ptr first (bounds for the col_idx compare)
+        int* flag = ar.make<int>(1);
+        HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
+        pattern_diff_k<<<cdiv(nb + 1, 256), 256, 0, s>>>(nb, K->row_ptr, K->col_idx, Km.rp, Km.ci, flag);
+        check_launch("pattern_diff");
+        int hf = 0;
+        HIPCHK(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ar.free(flag);
+        if (hf) throw Error(SCR_E_INVALID, "sparsity pattern differs from the one the handle was set up with");
+        int bits = validate_bsr(nb, K->bs, K->nnzb, Km.rp, Km.ci, K->val, ar, s);
+        if (bits) {
+            std::string m = "malformed matrix:";
+            if (bits & 16) m += " non-finite-value";
+            if (bits & 32) m += " zero-diagonal";
+            if (bits & ~48) m += " pattern";
+            throw Error(SCR_E_INVALID, m);
+        }
+        // from here on a failure leaves the handle half-updated
+        h->broken = true;
+        HIPCHK(hipMemcpyAsync(Km.v, K->val, Km.nnzb * Km.br * Km.bc * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (h->kind == SCR_SYSTEM) {
+            split_values(Km, h->A, h->G, h->D, h->C, s);
+            schur_update(h->A, h->G, h->D, h->C, h->opts.schur_diag, h->dvec, h->Sh, ar, s);
+            if (coords) {
+                double* xyz = ar.make<double>(nb * 3);
+                HIPCHK(hipMemcpyAsync(xyz, coords, nb * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+                rigid_modes(nb, xyz, h->B, ar, s);
+                ar.free(xyz);
+            }
+            update_hierarchy(*h->hA, h->A.v, coords ? h->B : nullptr, ar, s);
+            update_hierarchy(*h->hS, h->Sh.v, nullptr, ar, s);
+            for (DSell<double>* M : {&h->Ks, &h->As, &h->Gs, &h->Ds, &h->Cs}) sell_free(*M, ar);
+            h->Ks = sell_from_bsr<double>(Km, ar, s);
+            h->As = sell_from_bsr<double>(h->A, ar, s);
+            h->Gs = sell_from_bsr<double>(h->G, ar, s);
+            h->Ds = sell_from_bsr<double>(h->D, ar, s);
+            h->Cs = sell_from_bsr<double>(h->C, ar, s);
+            if (h->Shs.nslices) {
+                sell_free(h->Shs, ar);
+                h->Shs = sell_from_bsr<double>(h->Sh, ar, s);
+            }
+        } else {
+            update_hierarchy(*h->hL, Km.v, nullptr, ar, s);
+            sell_free(h->Ls, ar);
+            h->Ls = sell_from_bsr<double>(Km, ar, s);
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        h->broken = false;
+        h->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return SCR_OK;
+    } catch (const Error& e) {
+        (void)hipStreamSynchronize(s);
+        return fail(e);
+    }
+}
+
 scr_status scr_handle_destroy(scr_handle* h) {
     if (!h) return SCR_OK;
     try {
@@ -404,6 +486,7 @@ scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_
     try {
         if (!h || !b || !x) throw Error(SCR_E_INVALID, "NULL argument");
         if (h->kind != SCR_SYSTEM) throw Error(SCR_E_INVALID, "scr_solve needs an SCR_SYSTEM handle");
+        if (h->broken) throw Error(SCR_E_INVALID, "handle left unusable by a failed amg_update");
         HIPCHK(hipSetDevice(h->ctx->device));
         scr_solve_opts o;
         if (opts) o = *opts;
@@ -447,6 +530,7 @@ scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const sc
     try {
         if (!h || !b || !x) throw Error(SCR_E_INVALID, "NULL argument");
         if (h->kind != MESH_SYSTEM) throw Error(SCR_E_INVALID, "mesh_motion_solve needs a MESH_SYSTEM handle");
+        if (h->broken) throw Error(SCR_E_INVALID, "handle left unusable by a failed amg_update");
         HIPCHK(hipSetDevice(h->ctx->device));
         scr_solve_opts o;
         if (opts) o = *opts;

@@ -91,6 +91,9 @@ struct LevelSetup {
     double* Dinv = nullptr;
     double* B = nullptr;
     double lam = 0.0;
+    // kept for the numeric re-setup: aggregate member lists and the pattern of A P (no values)
+    int32_t *mrp = nullptr, *mem = nullptr;
+    DBsr AP;
 };
 
 class Hierarchy {
@@ -98,6 +101,8 @@ class Hierarchy {
     virtual ~Hierarchy() = default;
     // y = V-cycle(x), zero initial guess; FP64 in and out (cast at the boundary in MIXED).
     virtual void vcycle(const double* x, double* y, hipStream_t s) = 0;
+    // rebuild the solve-phase copies (sliced ELL in T, D^-1, smoothing coefficients) from L
+    virtual void refresh(Arena& ar, hipStream_t s) = 0;
     std::vector<LevelSetup> L;
     double* cinv = nullptr;          // dense inverse of the coarsest matrix (FP64)
     int64_t ncoarse = 0;
@@ -109,6 +114,18 @@ class Hierarchy {
 // prof: the context profiler, or nullptr; when set, level-0 smoother steps are timed.
 std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
                                            hipStream_t s, Profiler* prof = nullptr);
+
+// Numeric re-setup for new level-0 values on the same pattern (and, if B0 is not NULL, a new
+// near-null space): aggregates and every pattern are kept, every value-dependent quantity of every
+// level is recomputed as in build_hierarchy.
+void update_hierarchy(Hierarchy& H, const double* vals0, const double* B0, Arena& ar, hipStream_t s);
+
+// new values of S^ = C - D d^-1 G into its existing pattern (the patterns of A, G, D, C unchanged)
+void schur_update(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, int mode, double* d, DBsr& S, Arena& ar,
+                  hipStream_t s);
+
+// values of the split of K into A, G, D, C (patterns already set up by split_blocks)
+void split_values(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, hipStream_t s);
 
 // rigid-body modes (6 columns) of nb nodes from coordinates, shifted by their mean
 void rigid_modes(int64_t nb, const double* xyz, double* B, Arena& ar, hipStream_t s);

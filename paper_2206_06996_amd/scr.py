@@ -23,7 +23,7 @@ SCR_FP64, SCR_MIXED = 0, 1
 SCR_SMOOTH_JACOBI, SCR_SMOOTH_CHEBYSHEV = 0, 1
 
 EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", "scr_ctx_destroy",
-            "scr_ctx_bytes_in_use", "amg_setup", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
+            "scr_ctx_bytes_in_use", "amg_setup", "amg_update", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
             "scr_handle_bytes", "scr_footprint_estimate", "scr_status_str", "scr_last_error", "scr_hier_levels",
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
             "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
@@ -101,6 +101,7 @@ def lib():
         L.scr_ctx_bytes_in_use.argtypes = [P]
         L.scr_ctx_bytes_in_use.restype = C.c_int64
         L.amg_setup.argtypes = [P, C.c_int, C.POINTER(ScrBsr), P, C.POINTER(AmgOpts), P, C.POINTER(P)]
+        L.amg_update.argtypes = [P, C.POINTER(ScrBsr), P, P]
         L.scr_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), P, C.POINTER(Stats)]
         L.mesh_motion_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), P, C.POINTER(Stats)]
         L.scr_handle_destroy.argtypes = [P]
@@ -125,7 +126,7 @@ def lib():
         L.srv_drain.argtypes = [P, C.POINTER(C.c_int)]
         L.srv_destroy.argtypes = [P]
         L.srv_destroy.restype = None
-        for f in ("amg_setup", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
+        for f in ("amg_setup", "amg_update", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
                   "scr_ctx_profile", "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait",
                   "srv_drain"):
@@ -261,6 +262,17 @@ def amg_setup(ctx: Context, kind: int, row_ptr, col_idx, val, coords=None, opts:
     _check(lib().amg_setup(ctx.ptr, kind, C.byref(K), cp, C.byref(opts) if opts else None, _stream(stream),
                            C.byref(h)))
     return Handle(h, kind, n)
+
+
+def amg_update(h: Handle, row_ptr, col_idx, val, coords=None, stream=None):
+    """Numeric re-setup of h for new values on the same pattern (and new coordinates, optional)."""
+    import torch
+    bs = 4 if h.kind == SCR_SYSTEM else 1
+    K = ScrBsr(n_brows=row_ptr.numel() - 1, bs=bs, nnzb=col_idx.numel(),
+               row_ptr=_dev(row_ptr, torch.int32, "row_ptr"), col_idx=_dev(col_idx, torch.int32, "col_idx"),
+               val=_dev(val, torch.float64, "val"))
+    cp = _dev(coords, torch.float64, "coords") if coords is not None else None
+    _check(lib().amg_update(h.ptr, C.byref(K), cp, _stream(stream)))
 
 
 def scr_solve(h: Handle, b, x, opts: SolveOpts | None = None, stream=None):

@@ -1,0 +1,260 @@
+"""Numeric re-setup (amg_update) on the GPU, through the C ABI, against the oracle's re-setup.
+
+Bars: with the same values the updated handle is bitwise the freshly set-up one (same kernels,
+same terms in the same order); when a full setup would pick the same aggregates (K -> 2K, or a
+power-of-two similarity on a two-level hierarchy) the updated hierarchy is bitwise the fresh GPU
+one; for a changed time step (aggregates kept, every value recomputed) the updated hierarchy
+matches the oracle's updated hierarchy with the bars of the setup parity tests (patterns and
+aggregates bit-exact, values within 1e-11) and FP64 solves take the oracle's outer iteration
+count; invalid updates are rejected with the handle left as it was."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.test_gpu_parity import _compare_hierarchy
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def scr():
+    import paper_2206_06996_amd.scr as m
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(scr):
+    c = scr.Context(0)
+    yield c
+    c.destroy()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+FIELDS = ("A.rp", "A.ci", "A.v", "agg", "P.rp", "P.ci", "P.v", "R.rp", "R.ci", "R.v", "strong", "dead", "Dinv", "B")
+
+
+def snapshot(h, which):
+    out = []
+    n = h.hier_levels(which)
+    for l in range(n):
+        fs = FIELDS if l + 1 < n else ("A.rp", "A.ci", "A.v", "Dinv", "B")
+        out.append({f: h.hier_level_copy(which, l, f) for f in fs} | {"info": h.hier_level_info(which, l)})
+    return out
+
+
+def same_snapshot(a, b):
+    assert len(a) == len(b)
+    for l, (x, y) in enumerate(zip(a, b)):
+        assert x.keys() == y.keys()
+        for f in x:
+            if f == "info":
+                assert x[f] == y[f], (l, x[f], y[f])
+            else:
+                assert np.array_equal(x[f], y[f]), (l, f)
+
+
+def setup(scr, ctx, s, val=None, **kw):
+    v = s.val if val is None else val
+    print(f"[gpu] amg_setup n_b={s.n_b} {kw}", flush=True)
+    return scr.amg_setup(ctx, scr.SCR_SYSTEM, dev(s.rp), dev(s.ci), dev(v.reshape(-1)), dev(s.xyz.reshape(-1)),
+                         scr.amg_opts(**kw))
+
+
+def update(scr, h, s, val, xyz=None):
+    print(f"[gpu] amg_update n_b={s.n_b}", flush=True)
+    scr.amg_update(h, dev(s.rp), dev(s.ci), dev(val.reshape(-1)), None if xyz is None else dev(xyz.reshape(-1)))
+
+
+def solve(scr, h, b, **kw):
+    x = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    rc, st = scr.scr_solve(h, dev(b), x, scr.solve_opts(**kw))
+    return host(x), rc, st
+
+
+def matrices(h):
+    return {n: h.matrix_copy(n) for n in ("A", "G", "D", "C", "Shat")}
+
+
+def test_update_with_the_same_values_is_bitwise_the_setup(scr, ctx, small_fsi):
+    s = small_fsi
+    h = setup(scr, ctx, s, coarse_max=60)
+    before = (snapshot(h, 0), snapshot(h, 1), matrices(h))
+    b = synth.rhs(2, 4 * s.n_b, s.mask)
+    x0, rc0, _ = solve(scr, h, b)
+    update(scr, h, s, s.val.copy(), s.xyz)
+    after = (snapshot(h, 0), snapshot(h, 1), matrices(h))
+    same_snapshot(before[0], after[0])
+    same_snapshot(before[1], after[1])
+    for n in before[2]:
+        for a, c in zip(before[2][n], after[2][n]):
+            assert np.array_equal(a, c), n
+    x1, rc1, _ = solve(scr, h, b)
+    assert rc0 == rc1 == 0 and np.array_equal(x0, x1)
+    h.destroy()
+
+
+def _node_scaling(nb, seed):
+    return np.exp2(np.random.default_rng(seed).integers(-3, 4, nb)).astype(np.float64)
+
+
+@pytest.mark.parametrize("case", ["similarity_two_level", "uniform_scaling"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_update_equals_a_fresh_setup_when_aggregates_coincide(scr, ctx, small_fsi, case, precision):
+    s = small_fsi
+    rows = np.repeat(np.arange(s.n_b), np.diff(s.rp))
+    if case == "similarity_two_level":
+        sc = _node_scaling(s.n_b, 3)
+        val2 = s.val * (sc[rows] * sc[s.ci])[:, None, None]
+        kw = dict(coarse_max=60, max_levels=2, precision=precision)
+    else:
+        val2 = 2.0 * s.val
+        kw = dict(coarse_max=60, precision=precision)
+    fresh = setup(scr, ctx, s, val2, **kw)
+    upd = setup(scr, ctx, s, **kw)
+    update(scr, upd, s, val2)
+    same_snapshot(snapshot(upd, 0), snapshot(fresh, 0))
+    same_snapshot(snapshot(upd, 1), snapshot(fresh, 1))
+    mu, mf = matrices(upd), matrices(fresh)
+    for n in mu:
+        for a, c in zip(mu[n], mf[n]):
+            assert np.array_equal(a, c), n
+    b = synth.rhs(5, 4 * s.n_b, s.mask)
+    xu, rcu, stu = solve(scr, upd, b)
+    xf, rcf, stf = solve(scr, fresh, b)
+    assert rcu == rcf == 0 and np.array_equal(xu, xf) and stu["outer_it"] == stf["outer_it"]
+    # and the oracle's re-setup agrees with the GPU one
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(**{k: v for k, v in kw.items() if k != "precision"}))
+    o.update(val2)
+    _compare_hierarchy(upd, 0, o.amgA)
+    _compare_hierarchy(upd, 1, o.amgS)
+    upd.destroy(); fresh.destroy()
+
+
+@pytest.fixture(scope="module")
+def dt_pair():
+    """cfg0 at dt = 1e-3 and at dt = 2e-3: the same pattern, every value of A and C changed."""
+    p = synth.cfg0_params()
+    s1 = synth.generate(p)
+    p.dt = 2.0e-3
+    s2 = synth.generate(p)
+    assert np.array_equal(s1.rp, s2.rp) and np.array_equal(s1.ci, s2.ci)
+    return s1, s2
+
+
+@pytest.mark.parametrize("with_coords", [False, True])
+def test_changed_time_step_matches_the_oracle_update(scr, ctx, dt_pair, with_coords):
+    s1, s2 = dt_pair
+    xyz2 = 2.0 * s1.xyz if with_coords else None      # a rescaled geometry: new rigid-body modes
+    h = setup(scr, ctx, s1)
+    o = oracle.Scr(s1.rp, s1.ci, s1.val, s1.xyz)
+    agg0 = [h.hier_level_copy(0, l, "agg") for l in range(h.hier_levels(0) - 1)]
+    update(scr, h, s1, s2.val, xyz2)
+    o.update(s2.val, xyz2)
+    for l, a in enumerate(agg0):
+        assert np.array_equal(h.hier_level_copy(0, l, "agg"), a)
+    _compare_hierarchy(h, 0, o.amgA)
+    _compare_hierarchy(h, 1, o.amgS)
+    for n, (rp, ci, v) in matrices(h).items():
+        orp, oci, ov = o.matrix(n)
+        assert np.array_equal(rp, orp) and np.array_equal(ci, oci), n
+        assert np.abs(v - ov).max() <= 1e-13 * np.abs(ov).max(), n
+    b = synth.rhs(7, 4 * s2.n_b, s2.mask)
+    xo, rco, sto = o.solve(b, oracle.solve_opts(tol=1e-8))
+    xg, rc, st = solve(scr, h, b)
+    print(f"[gpu]   outer gpu={st['outer_it']} oracle={sto['outer_it']}", flush=True)
+    assert rc == 0 and rco == 0
+    assert st["outer_it"] == sto["outer_it"]
+    rel = np.linalg.norm(b - oracle.bsr_spmv(s2.rp, s2.ci, s2.val, xg)) / np.linalg.norm(b)
+    assert rel <= 1e-8
+    xt, rct, _ = o.solve(b, oracle.solve_opts(tol=1e-12))
+    assert np.linalg.norm(xg - xt) <= 1e-6 * np.linalg.norm(xt)
+    h.destroy()
+
+
+def test_mixed_precision_update_solves_the_new_system(scr, ctx, dt_pair):
+    s1, s2 = dt_pair
+    h = setup(scr, ctx, s1, precision=scr.SCR_MIXED)
+    update(scr, h, s1, s2.val)
+    b = synth.rhs(8, 4 * s2.n_b, s2.mask)
+    xg, rc, st = solve(scr, h, b)
+    assert rc == 0
+    rel = np.linalg.norm(b - oracle.bsr_spmv(s2.rp, s2.ci, s2.val, xg)) / np.linalg.norm(b)
+    assert rel <= 1e-8
+    h.destroy()
+
+
+def test_simple_preconditioner_after_update(scr, ctx, dt_pair):
+    # the explicit S^ copy that SIMPLE uses is rebuilt by the update
+    s1, s2 = dt_pair
+    h = setup(scr, ctx, s1)
+    b = synth.rhs(9, 4 * s2.n_b, s2.mask)
+    solve(scr, h, b, precond=scr.SCR_PRECOND_SIMPLE)      # builds the S^ copy on the old values
+    update(scr, h, s1, s2.val)
+    o = oracle.Scr(s1.rp, s1.ci, s1.val, s1.xyz)
+    o.update(s2.val)
+    xg, rc, st = solve(scr, h, b, precond=scr.SCR_PRECOND_SIMPLE)
+    xo, rco, sto = o.solve(b, oracle.solve_opts(tol=1e-8, precond=1))
+    assert rc == 0 and rco == 0 and st["outer_it"] == sto["outer_it"]
+    h.destroy()
+
+
+def test_mesh_update_matches_the_oracle_update(scr, ctx, cfg0):
+    s = cfg0
+    rows = np.repeat(np.arange(s.n_phys), np.diff(s.Lrp))
+    sc = 1.0 + 0.5 * np.random.default_rng(4).uniform(size=s.n_phys)
+    v2 = s.Lval * np.sqrt(sc[rows] * sc[s.Lci])          # a congruence D L D: still SPD, every value changed
+    h = scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(s.Lrp), dev(s.Lci), dev(s.Lval))
+    m = oracle.Mesh(s.Lrp, s.Lci, s.Lval)
+    scr.amg_update(h, dev(s.Lrp), dev(s.Lci), dev(v2))
+    m.update(v2)
+    _compare_hierarchy(h, 2, m.amg)
+    b = synth.rhs(11, 3 * s.n_phys, np.repeat(s.Lmask, 3))
+    xo, rco, its, rel = m.solve(b, tol=1e-12)
+    x = torch.zeros(3 * s.n_phys, dtype=torch.float64, device="cuda")
+    rc, st = scr.mesh_motion_solve(h, dev(b), x, scr.solve_opts(tol=1e-10, max_it=500))
+    assert rc == 0
+    xg = host(x)
+    for c in range(3):
+        r = b[c::3] - oracle.bsr_spmv(s.Lrp, s.Lci, v2, xg[c::3])
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[c::3])
+    assert np.linalg.norm(xg - xo) <= 1e-7 * np.linalg.norm(xo)
+    h.destroy()
+
+
+def test_invalid_updates_leave_the_handle_unchanged(scr, ctx, small_fsi):
+    s = small_fsi
+    h = setup(scr, ctx, s, coarse_max=60)
+    b = synth.rhs(12, 4 * s.n_b, s.mask)
+    x0, _, _ = solve(scr, h, b)
+    ci = s.ci.copy()
+    r = 5
+    a, c = s.rp[r], s.rp[r + 1]
+    ci[a:c] = np.roll(ci[a:c], 1)                          # same counts, different pattern
+    v = s.val.reshape(-1)
+    with pytest.raises(scr.ScrError) as e:
+        scr.amg_update(h, dev(s.rp), dev(ci), dev(v))
+    assert e.value.status == scr.SCR_E_INVALID
+    with pytest.raises(scr.ScrError) as e:                 # wrong nnzb
+        scr.amg_update(h, dev(s.rp), dev(s.ci[:-1]), dev(v[:-16]))
+    assert e.value.status == scr.SCR_E_INVALID
+    bad = v.copy()
+    bad[100] = np.nan
+    with pytest.raises(scr.ScrError) as e:
+        scr.amg_update(h, dev(s.rp), dev(s.ci), dev(bad))
+    assert e.value.status == scr.SCR_E_INVALID
+    x1, rc, _ = solve(scr, h, b)
+    assert rc == 0 and np.array_equal(x0, x1)
+    h.destroy()
