@@ -58,8 +58,8 @@ def parse():
 
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-KERNEL_SOURCES = ["paper_2206_06996_amd/csrc/sparse.hip", "paper_2206_06996_amd/csrc/amg.hip",
-                  "paper_2206_06996_amd/csrc/common.h"]
+# the files that define the profiled kernel and its data layout
+KERNEL_SOURCES = ["paper_2206_06996_amd/csrc/sparse.hip", "paper_2206_06996_amd/csrc/common.h"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "smooth_a0_cfg1_pmc.json")
 
 
