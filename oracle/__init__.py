@@ -113,6 +113,8 @@ def lib():
         L.orc_amg_update.restype = C.c_int
         L.orc_scr_update.argtypes = [P, P, P]
         L.orc_scr_update.restype = C.c_int
+        L.orc_scr_set_outlets.argtypes = [P, C.c_int, P, P, P, P]
+        L.orc_scr_set_outlets.restype = C.c_int
         L.orc_mesh_update.argtypes = [P, P]
         L.orc_mesh_update.restype = C.c_int
         L.orc_mesh_create.argtypes = [C.c_int64, P, P, P, C.POINTER(AmgOpts), C.POINTER(P)]
@@ -288,6 +290,20 @@ class Scr:
         if getattr(self, "h", None):
             lib().orc_scr_free(self.h)
             self.h = None
+
+    def set_outlets(self, outlets, m):
+        """Outlet resistance coupling: outlets = [(block rows, a (n, 3)), ...], m = coefficients;
+        the solves' K and A gain sum_k m_k a_k a_k^T on the velocity dofs (empty list removes it)."""
+        n = len(outlets)
+        off = np.zeros(n + 1, np.int64)
+        for k, (blk, a) in enumerate(outlets):
+            off[k + 1] = off[k] + len(blk)
+        blk = np.ascontiguousarray(np.concatenate([b for b, _ in outlets]) if n else np.zeros(1), np.int32)
+        a = np.ascontiguousarray(np.concatenate([a for _, a in outlets]) if n else np.zeros((1, 3)), np.float64)
+        mm = np.ascontiguousarray(m if n else np.zeros(1), np.float64)
+        self._outlets = (off, blk, a, mm)
+        if lib().orc_scr_set_outlets(self.h, n, _p(off), _p(blk), _p(a), _p(mm)):
+            raise ValueError("invalid outlet data")
 
     def matrix(self, which):
         """which: 'A', 'G', 'D', 'C', 'Shat' -> (rp, ci, val)"""

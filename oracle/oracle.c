@@ -906,7 +906,24 @@ typedef struct {
     solve_opts so;
     scr_stats st;
     double *t1, *t2, *t3;   /* scratch */
+    /* outlet resistance coupling: outlet k adds m_k a_k a_k^T to the velocity block; its entries
+     * out_off[k] .. out_off[k+1]-1 name a block row and the 3 velocity components of a_k there */
+    int n_out;
+    int64_t* out_off; int32_t* out_blk; double *out_a, *out_m;
 } scr;
+
+/* yv += sum_k m_k a_k (a_k . xv) on velocity vectors (3 per block row), outlets in order, each
+ * dot product summed over its entries in order (Sec. 3.5, the linearised reduced outlet models) */
+static void add_outlets(const scr* s, const double* xv, double* yv) {
+    for (int k = 0; k < s->n_out; ++k) {
+        double dot = 0.0;
+        for (int64_t e = s->out_off[k]; e < s->out_off[k + 1]; ++e)
+            for (int i = 0; i < 3; ++i) dot += s->out_a[3 * e + i] * xv[3 * (int64_t)s->out_blk[e] + i];
+        double c = s->out_m[k] * dot;
+        for (int64_t e = s->out_off[k]; e < s->out_off[k + 1]; ++e)
+            for (int i = 0; i < 3; ++i) yv[3 * (int64_t)s->out_blk[e] + i] += c * s->out_a[3 * e + i];
+    }
+}
 
 static void op_K(void* c, const double* x, double* y) {
     /* split layout: x = [x_v (3nb); x_p (nb)] */
@@ -923,8 +940,12 @@ static void op_K(void* c, const double* x, double* y) {
         }
         y[3 * i] = acc[0]; y[3 * i + 1] = acc[1]; y[3 * i + 2] = acc[2]; y[3 * nb + i] = acc[3];
     }
+    add_outlets(s, x, y);
 }
-static void op_A(void* c, const double* x, double* y) { bsr_mv(((scr*)c)->A, x, y); }
+static void op_A(void* c, const double* x, double* y) {
+    bsr_mv(((scr*)c)->A, x, y);
+    add_outlets((scr*)c, x, y);
+}
 static void prec_A(void* c, const double* x, double* y) { scr* s = (scr*)c; s->st.vcycles_A++; orc_amg_vcycle(s->amgA, x, y); }
 static void prec_S(void* c, const double* x, double* y) { scr* s = (scr*)c; s->st.vcycles_S++; orc_amg_vcycle(s->amgS, x, y); }
 
@@ -1127,8 +1148,30 @@ int orc_scr_update(scr* s, const double* val, const double* xyz) {
     return amg_update(s->amgS, s->Sh->v, NULL);
 }
 
+/* Attach the outlet coupling (copied; n = 0 removes it).  The operators K and A of the solves
+ * include it; the split, S^ and both hierarchies are those of the sparse K (they are not rebuilt). */
+int orc_scr_set_outlets(scr* s, int n, const int64_t* off, const int32_t* blk, const double* a, const double* m) {
+    free(s->out_off); free(s->out_blk); free(s->out_a); free(s->out_m);
+    s->out_off = NULL; s->out_blk = NULL; s->out_a = NULL; s->out_m = NULL;
+    s->n_out = 0;
+    if (n <= 0) return 0;
+    int64_t ne = off[n];
+    for (int k = 0; k < n; ++k) if (off[k + 1] < off[k]) return -1;
+    for (int64_t e = 0; e < ne; ++e) if (blk[e] < 0 || blk[e] >= s->nb) return -1;
+    s->out_off = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+    s->out_blk = (int32_t*)malloc(sizeof(int32_t) * (ne > 0 ? ne : 1));
+    s->out_a = (double*)malloc(sizeof(double) * 3 * (ne > 0 ? ne : 1));
+    s->out_m = (double*)malloc(sizeof(double) * n);
+    memcpy(s->out_off, off, sizeof(int64_t) * (n + 1));
+    if (ne) { memcpy(s->out_blk, blk, sizeof(int32_t) * ne); memcpy(s->out_a, a, sizeof(double) * 3 * ne); }
+    memcpy(s->out_m, m, sizeof(double) * n);
+    s->n_out = n;
+    return 0;
+}
+
 void orc_scr_free(scr* s) {
     if (!s) return;
+    free(s->out_off); free(s->out_blk); free(s->out_a); free(s->out_m);
     bsr_free(s->K); bsr_free(s->A); bsr_free(s->G); bsr_free(s->D); bsr_free(s->C); bsr_free(s->Sh);
     free(s->diagA); orc_amg_free(s->amgA); orc_amg_free(s->amgS);
     free(s);

@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("rho_s", C.c_double), ("E_s", C.c_double), ("nu_s", C.c_double), ("dt", C.c_double),
                 ("rho_inf", C.c_double), ("terms", C.c_int), ("apply_bc", C.c_int),
                 ("vms_dt_coupling", C.c_int), ("box_solid", C.c_int), ("y_h", C.c_double),
-                ("y_rd", C.c_double), ("y_ld", C.c_double), ("y_th1", C.c_double), ("y_th2", C.c_double)]
+                ("y_rd", C.c_double), ("y_ld", C.c_double), ("y_th1", C.c_double), ("y_th2", C.c_double),
+                ("u_max", C.c_double)]
 
 
 def _load():
@@ -53,11 +54,12 @@ def _load():
         lib.synth_get_nodes.argtypes = [P, P, P, P]
         lib.synth_get_L.argtypes = [P, P, P, P, P, P]
         lib.synth_get_tets.argtypes = [P, P, P, P, P]
+        lib.synth_get_flow.argtypes = [P, P, P, P, P]
         lib.synth_free.argtypes = [P]
         lib.synth_rhs.argtypes = [C.c_uint64, C.c_int64, P, P]
-        lib.synth_element.argtypes = [P, C.POINTER(Params), C.c_int, P]
+        lib.synth_element.argtypes = [P, P, C.POINTER(Params), C.c_int, P]
         lib.synth_element.restype = C.c_double
-        lib.synth_tau.argtypes = [P, C.POINTER(Params), P, P]
+        lib.synth_tau.argtypes = [P, P, C.POINTER(Params), P, P]
         lib.synth_genalpha.argtypes = [C.c_double, P, P, P]
         _lib = lib
     return _lib
@@ -69,11 +71,12 @@ def _ptr(a: np.ndarray):
 
 def default_params(**kw) -> Params:
     """Physical constants of the fluid/solid workloads: rho=1.06, mu=0.04, dt=1e-3,
-    rho_inf=0.5; solid E=1e6, nu=0.45, rho_s=1.0 (cgs units as in the paper's Section 6)."""
+    rho_inf=0.5; solid E=1e6, nu=0.45, rho_s=1.0 (cgs units as in the paper's Section 6).
+    At rest (u_max = 0) unless an advective centreline speed u_max is given."""
     p = Params(mode=0, m_core=6, n_bl=0, n_wall=0, nz=40, R=1.0, L=5.0, wall_ratio=1.2,
                bl_ratio=0.6, rho_f=1.06, mu_f=0.04, rho_s=1.0, E_s=1.0e6, nu_s=0.45, dt=1.0e-3,
-               rho_inf=0.5, terms=31, apply_bc=1, vms_dt_coupling=0, box_solid=0, y_h=0.0, y_rd=0.7,
-               y_ld=5.0, y_th1=0.0, y_th2=0.0)
+               rho_inf=0.5, terms=63, apply_bc=1, vms_dt_coupling=0, box_solid=0, y_h=0.0, y_rd=0.7,
+               y_ld=5.0, y_th1=0.0, y_th2=0.0, u_max=0.0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -96,9 +99,9 @@ def generate(p: Params, tets: bool = False) -> System:
     if rc != 0:
         raise RuntimeError(f"synth_build failed ({rc})")
     try:
-        info = np.zeros(8, np.int64)
+        info = np.zeros(10, np.int64)
         lib.synth_info(h, _ptr(info))
-        n_phys, nb, nnzb, nt, nnzL, nif, S, nzn = (int(v) for v in info)
+        n_phys, nb, nnzb, nt, nnzL, nif, S, nzn, n_out, n_oe = (int(v) for v in info)
         rp = np.empty(nb + 1, np.int32); ci = np.empty(nnzb, np.int32)
         val = np.empty((nnzb, 4, 4), np.float64)
         lib.synth_get_K(h, _ptr(rp), _ptr(ci), _ptr(val))
@@ -107,9 +110,13 @@ def generate(p: Params, tets: bool = False) -> System:
         Lrp = np.empty(n_phys + 1, np.int32); Lci = np.empty(nnzL, np.int32)
         Lval = np.empty(nnzL); Lmask = np.empty(n_phys, np.uint8); Lxyz = np.empty((n_phys, 3))
         lib.synth_get_L(h, _ptr(Lrp), _ptr(Lci), _ptr(Lval), _ptr(Lmask), _ptr(Lxyz))
+        uadv = np.empty((nb, 3)); ooff = np.empty(n_out + 1, np.int64)
+        oblk = np.empty(max(n_oe, 1), np.int32); oa = np.empty((max(n_oe, 1), 3))
+        lib.synth_get_flow(h, _ptr(uadv), _ptr(ooff), _ptr(oblk), _ptr(oa))
+        outlets = [(oblk[ooff[k]:ooff[k + 1]].copy(), oa[ooff[k]:ooff[k + 1]].copy()) for k in range(n_out)]
         out = System(n_phys=n_phys, n_b=nb, nnzb=nnzb, n_tets=nt, n_iface=nif, section=S,
                      layers=nzn, rp=rp, ci=ci, val=val, xyz=xyz, mask=mask, kind=kind,
-                     Lrp=Lrp, Lci=Lci, Lval=Lval, Lmask=Lmask, Lxyz=Lxyz)
+                     Lrp=Lrp, Lci=Lci, Lval=Lval, Lmask=Lmask, Lxyz=Lxyz, uadv=uadv, outlets=outlets)
         if tets:
             tv = np.empty((nt, 4), np.int32); tp = np.empty((nt, 4), np.int32)
             ts = np.empty(nt, np.uint8); bop = np.empty(n_phys, np.int32)
@@ -129,19 +136,23 @@ def rhs(seed: int, n: int, mask: np.ndarray | None = None) -> np.ndarray:
     return out
 
 
-def element(x4: np.ndarray, p: Params, solid: bool = False):
+def element(x4: np.ndarray, p: Params, solid: bool = False, u4: np.ndarray | None = None):
+    """16x16 element matrix (index 4*a + c) of one tetrahedron; u4: advective velocity at its
+    4 vertices (4x3) or None (at rest)."""
     lib = _load()
     x = np.ascontiguousarray(x4, np.float64).reshape(12)
+    u = None if u4 is None else np.ascontiguousarray(u4, np.float64).reshape(12)
     Ke = np.empty((16, 16))
-    V = lib.synth_element(_ptr(x), C.byref(p), int(solid), _ptr(Ke))
+    V = lib.synth_element(_ptr(x), None if u is None else _ptr(u), C.byref(p), int(solid), _ptr(Ke))
     return Ke, V
 
 
-def tau(x4: np.ndarray, p: Params):
+def tau(x4: np.ndarray, p: Params, ub: np.ndarray | None = None):
     lib = _load()
     x = np.ascontiguousarray(x4, np.float64).reshape(12)
+    u = None if ub is None else np.ascontiguousarray(ub, np.float64).reshape(3)
     a = np.zeros(1); b = np.zeros(1)
-    lib.synth_tau(_ptr(x), C.byref(p), _ptr(a), _ptr(b))
+    lib.synth_tau(_ptr(x), None if u is None else _ptr(u), C.byref(p), _ptr(a), _ptr(b))
     return float(a[0]), float(b[0])
 
 

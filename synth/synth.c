@@ -14,7 +14,7 @@
  * (conforming, and no cap-shaped slivers at the shell corners).
  *
  * Physics of the entries (fully discrete tangent of the paper's Section 3, divided by
- * alpha_f*gamma*dt, evaluated at rest so every convective term vanishes):
+ * alpha_f*gamma*dt; at rest every convective term vanishes, see the advective state below):
  *   fluid (Sec. 3.2, VMS):  A = rho*c_t*M (x) I3 + mu*Dev + tau_C*graddiv,
  *                           G = -(V/4) dN_a/dx_i,  D = -G^T,  C = tau_M * stiffness
  *   solid (Sec. 3.1 with c_m = c_c = 0, Sec. 3.5 tangent):
@@ -23,6 +23,20 @@
  *   c_t = alpha_m/(alpha_f*gamma*dt); first-order generalized-alpha constants (Sec. 3.4).
  *   tau_M, tau_C from the element metric G = J^-T M J^-1 with the regular-simplex matrix M
  *   (Sec. 3.2, definition of the stabilisation parameters; the double sum over k,l).
+ * Advective state (u_max != 0; tube and box only): the fluid nodes carry the Poiseuille profile
+ * u = u_max (1 - r^2/R^2) e_z (r from the axis; box: R = half the narrower side, profile clipped
+ * at zero).  It is a steady solution with zero fine-scale residual, so the VMS terms that carry
+ * the state's v' or p' vanish, and the Oseen (frozen advection) tangent of Sec. 3.2 adds, per
+ * fluid element with centroid velocity ub and constant grad u:
+ *   A += rho N_a (ub.grad N_b) I + rho M_ab grad u                  (Galerkin convection, reaction)
+ *      + tau_M rho^2 (ub.grad N_a) (c_t N_b + ub.grad N_b) I        (fine-scale momentum, SUPG form)
+ *   G += tau_M rho (ub.grad N_a) dN_b/dx_i                          (v' through grad p)
+ *   D += tau_M rho dN_a/dx_j (ub.grad N_b)                          (continuity, v' through (grad v) u)
+ * with tau_M including ub.G.ub; element integrals by the centroid rule (exact for the mass-like
+ * and gradient-gradient parts).  A is then nonsymmetric.
+ * Outlets (tube and box): the outlet face z = z_max; per face triangle of a fluid element the
+ * vector a of the resistance coupling (Sec. 3.5: a_Ai = integral of N_A n_i over the outlet)
+ * gets area/3 * n at each vertex (n = +e_z); Dirichlet velocity dofs are zeroed.
  * Interface pressure duplication (Sec. 3.3): every node on the lumen/wall interface gets a
  * "virtual" block row right after it; solid elements use it for pressure, the physical
  * node for velocity; its velocity slots are identity rows.
@@ -57,7 +71,7 @@ typedef struct {
     double wall_ratio; /* outer wall radius / R */
     double bl_ratio;   /* boundary-layer gradation factor */
     double rho_f, mu_f, rho_s, E_s, nu_s, dt, rho_inf;
-    int terms;       /* bitmask: 1 mass, 2 dev, 4 graddiv, 8 G/D, 16 C; 31 = all */
+    int terms;       /* bitmask: 1 mass, 2 dev, 4 graddiv, 8 G/D, 16 C, 32 advection; 63 = all */
     int apply_bc;    /* 1: Dirichlet elimination; 0: natural boundaries everywhere */
     int vms_dt_coupling; /* 1: add c_t*rho*tau_M*(V/4)*dN_a/dx_j to D (fluid) */
     int box_solid;   /* box only: 1 = every element is solid */
@@ -65,6 +79,7 @@ typedef struct {
     double y_rd;     /* Y: daughter radius / parent radius */
     double y_ld;     /* Y: daughter length (parent length is L) */
     double y_th1, y_th2; /* Y: daughter angles from the z axis (radians), toward +x and -x */
+    double u_max;    /* centreline speed of the advective Poiseuille state (0 = at rest) */
 } synth_params;
 
 typedef struct {
@@ -78,6 +93,9 @@ typedef struct {
     uint8_t *mask;              /* 4 per block row, 1 = Dirichlet dof */
     int32_t *Lrp, *Lci; double *Lval; uint8_t *Lmask;
     int32_t *tv, *tp; uint8_t *tsolid;
+    double *uadv;               /* advective velocity per block row (3; zero off the fluid) */
+    int n_out;                  /* outlets; entries of outlet k are out_off[k] .. out_off[k+1]-1 */
+    int64_t *out_off; int32_t *out_blk; double *out_a;   /* block row and a (3) per entry */
 } synth_sys;
 
 /* ---- counter-based generator (Vigna's splitmix64 output function) ---- */
@@ -131,8 +149,8 @@ static double tet_grad(const double* x, double dN[4][3]) {
     return det;
 }
 
-/* tau_M and tau_C of the fluid VMS at zero velocity (Sec. 3.2). */
-static void fluid_tau(const double* x, const synth_params* p, double* tauM, double* tauC) {
+/* tau_M and tau_C of the fluid VMS (Sec. 3.2) for the advective velocity ub (NULL = at rest). */
+static void fluid_tau(const double* x, const synth_params* p, const double* ub, double* tauM, double* tauC) {
     double dN[4][3];
     tet_grad(x, dN);
     const double c = cbrt(2.0) / 2.0;
@@ -145,19 +163,24 @@ static void fluid_tau(const double* x, const synth_params* p, double* tauM, doub
                 for (int l = 0; l < 3; ++l) s += dN[k + 1][i] * M[k][l] * dN[l + 1][j];
             G[i][j] = s;
         }
-    double GG = 0.0, trG = 0.0;
+    double GG = 0.0, trG = 0.0, uGu = 0.0;
     for (int i = 0; i < 3; ++i) {
         trG += G[i][i];
-        for (int j = 0; j < 3; ++j) GG += G[i][j] * G[i][j];
+        for (int j = 0; j < 3; ++j) {
+            GG += G[i][j] * G[i][j];
+            if (ub) uGu += ub[i] * G[i][j] * ub[j];
+        }
     }
     const double CT = 4.0, CI = 36.0;
     double nu = p->mu_f / p->rho_f;
-    *tauM = 1.0 / p->rho_f / sqrt(CT / (p->dt * p->dt) + CI * nu * nu * GG);
+    *tauM = 1.0 / p->rho_f / sqrt(CT / (p->dt * p->dt) + uGu + CI * nu * nu * GG);
     *tauC = 1.0 / (*tauM * trG);
 }
 
-/* Element matrix, 16x16, index 4*a + c (c = 0,1,2 velocity, 3 pressure). Returns volume. */
-static double element_matrix(const double* x, const synth_params* p, int solid, double* Ke) {
+/* Element matrix, 16x16, index 4*a + c (c = 0,1,2 velocity, 3 pressure). u4: the advective
+ * velocity at the 4 vertices (12 values) or NULL (at rest); ignored for solid elements.
+ * Returns the volume. */
+static double element_matrix(const double* x, const double* u4, const synth_params* p, int solid, double* Ke) {
     double dN[4][3];
     double det = tet_grad(x, dN);
     double V = fabs(det) / 6.0;
@@ -166,8 +189,16 @@ static double element_matrix(const double* x, const synth_params* p, int solid, 
     double ct = am / (af * g * p->dt);
     memset(Ke, 0, sizeof(double) * 256);
     double rho, visc, gd = 0.0, tauM = 0.0, tauC = 0.0;
+    int conv = !solid && u4 != NULL && (p->terms & 32);
+    double ub[3] = {0.0, 0.0, 0.0}, gu[3][3] = {{0.0}};   /* centroid velocity, grad u (d u_i / d x_j) */
+    if (conv)
+        for (int i = 0; i < 3; ++i) {
+            ub[i] = 0.25 * (u4[i] + u4[3 + i] + u4[6 + i] + u4[9 + i]);
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 4; ++c) gu[i][j] += u4[3 * c + i] * dN[c][j];
+        }
     if (!solid) {
-        fluid_tau(x, p, &tauM, &tauC);
+        fluid_tau(x, p, conv ? ub : NULL, &tauM, &tauC);
         rho = p->rho_f; visc = p->mu_f; gd = tauC;
     } else {
         double mu_s = p->E_s / (2.0 * (1.0 + p->nu_s));
@@ -178,6 +209,8 @@ static double element_matrix(const double* x, const synth_params* p, int solid, 
         for (int b = 0; b < 4; ++b) {
             double Mab = V * (a == b ? 2.0 : 1.0) / 20.0;
             double Lab = V * (dN[a][0] * dN[b][0] + dN[a][1] * dN[b][1] + dN[a][2] * dN[b][2]);
+            double ua = ub[0] * dN[a][0] + ub[1] * dN[a][1] + ub[2] * dN[a][2];   /* ub . grad N_a */
+            double uB = ub[0] * dN[b][0] + ub[1] * dN[b][1] + ub[2] * dN[b][2];   /* ub . grad N_b */
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) {
                     double v = 0.0;
@@ -186,28 +219,39 @@ static double element_matrix(const double* x, const synth_params* p, int solid, 
                         v += visc * ((i == j ? Lab : 0.0) + V * dN[a][j] * dN[b][i]
                                      - (2.0 / 3.0) * V * dN[a][i] * dN[b][j]);
                     if (p->terms & 4) v += gd * V * dN[a][i] * dN[b][j];
+                    if (conv) {
+                        if (i == j) v += rho * (V / 4.0) * uB + tauM * rho * rho * ua * (ct * (V / 4.0) + V * uB);
+                        v += rho * Mab * gu[i][j];
+                    }
                     Ke[(4 * a + i) * 16 + 4 * b + j] = v;
                 }
-            if (p->terms & 8)
-                for (int i = 0; i < 3; ++i) {
-                    double gv = -(V / 4.0) * dN[a][i];      /* G[(a,i), b] */
-                    Ke[(4 * a + i) * 16 + 4 * b + 3] = gv;
-                    double dv = (V / 4.0) * dN[b][i];       /* D[a, (b,i)] = -G[(b,i), a] */
+            for (int i = 0; i < 3; ++i) {
+                double gv = 0.0, dv = 0.0;
+                if (p->terms & 8) {
+                    gv = -(V / 4.0) * dN[a][i];             /* G[(a,i), b] */
+                    dv = (V / 4.0) * dN[b][i];              /* D[a, (b,i)] = -G[(b,i), a] at rest */
                     if (!solid && p->vms_dt_coupling) dv += ct * rho * tauM * (V / 4.0) * dN[a][i];
-                    Ke[(4 * a + 3) * 16 + 4 * b + i] = dv;
                 }
+                if (conv) {
+                    gv += tauM * rho * V * ua * dN[b][i];
+                    dv += tauM * rho * V * dN[a][i] * uB;
+                }
+                Ke[(4 * a + i) * 16 + 4 * b + 3] = gv;
+                Ke[(4 * a + 3) * 16 + 4 * b + i] = dv;
+            }
             if (p->terms & 16)
                 Ke[(4 * a + 3) * 16 + 4 * b + 3] = solid ? (ct / kappa) * Mab : tauM * Lab;
         }
     return V;
 }
 
-/* Test hooks: element matrix and tau of one tetrahedron given its 4 vertices (12 doubles). */
-double synth_element(const double* x4, const synth_params* p, int solid, double* Ke) {
-    return element_matrix(x4, p, solid, Ke);
+/* Test hooks: element matrix and tau of one tetrahedron given its 4 vertices (12 doubles) and
+ * optionally the advective velocity at them (u4, 12 doubles, or NULL). */
+double synth_element(const double* x4, const double* u4, const synth_params* p, int solid, double* Ke) {
+    return element_matrix(x4, u4, p, solid, Ke);
 }
-void synth_tau(const double* x4, const synth_params* p, double* tauM, double* tauC) {
-    fluid_tau(x4, p, tauM, tauC);
+void synth_tau(const double* x4, const double* ub, const synth_params* p, double* tauM, double* tauC) {
+    fluid_tau(x4, p, ub, tauM, tauC);
 }
 
 /* ---- geometry helpers ---- */
@@ -446,6 +490,7 @@ void synth_free(synth_sys* s) {
     free(s->rp); free(s->ci); free(s->val); free(s->mask);
     free(s->Lrp); free(s->Lci); free(s->Lval); free(s->Lmask);
     free(s->tv); free(s->tp); free(s->tsolid);
+    free(s->uadv); free(s->out_off); free(s->out_blk); free(s->out_a);
     free(s);
 }
 
@@ -597,13 +642,32 @@ int synth_build(const synth_params* p, synth_sys** out) {
     s->ci = (int32_t*)malloc(sizeof(int32_t) * s->nnzb);
     for (int64_t b = 0; b < nb; ++b) memcpy(s->ci + s->rp[b], cols + b * ROWCAP, sizeof(int32_t) * cnt[b]);
     s->val = (double*)calloc((size_t)s->nnzb * 16, sizeof(double));
+    /* advective state: Poiseuille profile on the fluid block rows (tube and box) */
+    s->uadv = (double*)calloc(3 * (size_t)nb, sizeof(double));
+    int conv = p->u_max != 0.0 && p->mode != 2;
+    if (conv) {
+        double cx = 0.0, cy = 0.0, R = p->R;
+        if (p->mode == 1) {
+            double lx = (double)(s->S - 1) * p->R, ly = (double)(n_phys / ((int64_t)s->S * s->nzn) - 1) * p->R;
+            cx = 0.5 * lx; cy = 0.5 * ly; R = 0.5 * (lx < ly ? lx : ly);
+        }
+        for (int64_t b = 0; b < nb; ++b) {
+            if (s->node_kind[b] == 1 || s->node_kind[b] == 3) continue;
+            double dx = s->xyz[3 * b] - cx, dy = s->xyz[3 * b + 1] - cy;
+            double w = 1.0 - (dx * dx + dy * dy) / (R * R);
+            s->uadv[3 * b + 2] = w > 0.0 ? p->u_max * w : 0.0;
+        }
+    }
     /* assemble */
     double Ke[256];
     for (int64_t e = 0; e < s->n_tets; ++e) {
         const int32_t* va = s->tv + 4 * e; const int32_t* pa = s->tp + 4 * e;
-        double x[12];
-        for (int a = 0; a < 4; ++a) memcpy(x + 3 * a, s->xyz + 3 * va[a], 3 * sizeof(double));
-        element_matrix(x, p, s->tsolid[e], Ke);
+        double x[12], u4[12];
+        for (int a = 0; a < 4; ++a) {
+            memcpy(x + 3 * a, s->xyz + 3 * va[a], 3 * sizeof(double));
+            memcpy(u4 + 3 * a, s->uadv + 3 * va[a], 3 * sizeof(double));
+        }
+        element_matrix(x, conv ? u4 : NULL, p, s->tsolid[e], Ke);
         for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b) {
                 /* A part: (va[a], va[b]) [i][j]; G: (va[a], pa[b]) [i][3]; D: (pa[a], va[b]) [3][j]; C: (pa[a], pa[b]) [3][3] */
@@ -653,6 +717,43 @@ int synth_build(const synth_params* p, synth_sys** out) {
                         if ((i < 3 && s->node_kind[r] == 3) || (j < 3 && s->node_kind[c] == 3)) blk[4 * i + j] = 0.0;
                 if (c == r && s->node_kind[r] == 3) for (int i = 0; i < 3; ++i) blk[5 * i] = 1.0;
             }
+    }
+    /* outlet of the tube and box: faces of fluid elements on the plane z = z_max */
+    s->out_off = (int64_t*)calloc(2, sizeof(int64_t));
+    if (p->mode != 2) {
+        double zmax = -INFINITY;
+        for (int64_t n = 0; n < n_phys; ++n) if (s->xyz_phys[3 * n + 2] > zmax) zmax = s->xyz_phys[3 * n + 2];
+        double* acc = (double*)calloc(nb, sizeof(double));
+        static const int face[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+        for (int64_t e = 0; e < s->n_tets; ++e) {
+            if (s->tsolid[e]) continue;
+            const int32_t* va = s->tv + 4 * e;
+            for (int f = 0; f < 4; ++f) {
+                const double* q[3];
+                int on = 1;
+                for (int t = 0; t < 3; ++t) {
+                    q[t] = s->xyz + 3 * va[face[f][t]];
+                    on &= q[t][2] == zmax;
+                }
+                if (!on) continue;
+                double e1x = q[1][0] - q[0][0], e1y = q[1][1] - q[0][1];
+                double e2x = q[2][0] - q[0][0], e2y = q[2][1] - q[0][1];
+                double area = 0.5 * fabs(e1x * e2y - e1y * e2x);
+                for (int t = 0; t < 3; ++t) acc[va[face[f][t]]] += area / 3.0;
+            }
+        }
+        int64_t ne = 0;
+        for (int64_t b = 0; b < nb; ++b) if (acc[b] != 0.0 && !s->mask[4 * b + 2]) ++ne;
+        if (ne > 0) {
+            s->n_out = 1;
+            s->out_off[1] = ne;
+            s->out_blk = (int32_t*)malloc(sizeof(int32_t) * ne);
+            s->out_a = (double*)calloc(3 * (size_t)ne, sizeof(double));
+            int64_t t = 0;
+            for (int64_t b = 0; b < nb; ++b)
+                if (acc[b] != 0.0 && !s->mask[4 * b + 2]) { s->out_blk[t] = (int32_t)b; s->out_a[3 * t + 2] = acc[b]; ++t; }
+        }
+        free(acc);
     }
     /* mesh-motion Laplacian over physical nodes, element factor 1/V:  entries dN_a . dN_b */
     {
@@ -708,6 +809,16 @@ int synth_build(const synth_params* p, synth_sys** out) {
 void synth_info(const synth_sys* s, int64_t* info) {
     info[0] = s->n_phys; info[1] = s->n_b; info[2] = s->nnzb; info[3] = s->n_tets;
     info[4] = s->nnz_L; info[5] = s->n_iface; info[6] = s->S; info[7] = s->nzn;
+    info[8] = s->n_out; info[9] = s->out_off[s->n_out];
+}
+void synth_get_flow(const synth_sys* s, double* uadv, int64_t* out_off, int32_t* out_blk, double* out_a) {
+    memcpy(uadv, s->uadv, sizeof(double) * 3 * s->n_b);
+    memcpy(out_off, s->out_off, sizeof(int64_t) * (s->n_out + 1));
+    int64_t ne = s->out_off[s->n_out];
+    if (ne) {
+        memcpy(out_blk, s->out_blk, sizeof(int32_t) * ne);
+        memcpy(out_a, s->out_a, sizeof(double) * 3 * ne);
+    }
 }
 void synth_get_K(const synth_sys* s, int32_t* rp, int32_t* ci, double* val) {
     memcpy(rp, s->rp, sizeof(int32_t) * (s->n_b + 1));

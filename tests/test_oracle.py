@@ -574,3 +574,83 @@ def test_mesh_update_equals_a_fresh_setup_when_aggregates_coincide(cfg0):
     upd = oracle.Mesh(s.Lrp, s.Lci, s.Lval, ao)
     upd.update(v2)
     _same_hierarchy(upd.amg, fresh.amg)
+
+
+# ----------------------------------------------------------------------------- advection and outlets
+@pytest.fixture(scope="module")
+def flow_fsi():
+    """small_fsi with the advective Poiseuille state (u_max = 30): a nonsymmetric velocity block."""
+    kw = dict(mode=0, m_core=2, n_bl=1, n_wall=1, nz=8, R=1.0, L=2.0)
+    return synth.generate(synth.default_params(u_max=30.0, **kw))
+
+
+def _outlet_columns(s, outlets):
+    """the coupling vectors as dense interleaved 4n columns (velocity entries only)"""
+    cols = []
+    for blk, a in outlets:
+        v = np.zeros((s.n_b, 4))
+        v[blk, :3] = a
+        cols.append(v.reshape(-1))
+    return np.array(cols).T
+
+
+def _two_outlets(s):
+    blk, a = s.outlets[0]
+    h = len(blk) // 2
+    return [(blk[:h], a[:h]), (blk[h:], a[h:])], np.array([1.0e3, 4.0e3])
+
+
+def test_advective_system_solve_matches_dense_lu(flow_fsi):
+    s = flow_fsi
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz)
+    Kd = bsr_to_dense(s.rp, s.ci, s.val)
+    b = synth.rhs(3, 4 * s.n_b, s.mask)
+    x, rc, st = o.solve(b, oracle.solve_opts(tol=1e-11))
+    xl = oracle.dense_solve(Kd, b)
+    assert rc == 0 and np.linalg.norm(x - xl) <= 1e-10 * np.linalg.norm(xl)
+
+
+def test_outlet_coupling_solve_is_the_woodbury_update_of_the_plain_solve(flow_fsi):
+    # (K + U M U^T)^-1 b = y - Z (M^-1 + U^T Z)^-1 U^T y with y = K^-1 b, Z = K^-1 U: the plain
+    # system's dense LU only, so nothing of the oracle's operator enters the reference
+    s = flow_fsi
+    outlets, m = _two_outlets(s)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz)
+    o.set_outlets(outlets, m)
+    Kd = bsr_to_dense(s.rp, s.ci, s.val)
+    U = _outlet_columns(s, outlets)
+    b = synth.rhs(3, 4 * s.n_b, s.mask)
+    y = oracle.dense_solve(Kd, b)
+    Z = np.column_stack([oracle.dense_solve(Kd, U[:, k]) for k in range(U.shape[1])])
+    xw = y - Z @ np.linalg.solve(np.diag(1.0 / m) + U.T @ Z, U.T @ y)
+    x, rc, st = o.solve(b, oracle.solve_opts(tol=1e-11))
+    assert rc == 0 and np.linalg.norm(x - xw) <= 1e-9 * np.linalg.norm(xw)
+    assert np.linalg.norm(y - xw) > 1e-5 * np.linalg.norm(xw)         # the coupling matters here
+    # swapping the two resistances is a different system
+    o.set_outlets(outlets, m[::-1])
+    x2, _, _ = o.solve(b, oracle.solve_opts(tol=1e-11))
+    assert np.linalg.norm(x2 - xw) > 1e-6 * np.linalg.norm(xw)
+    # removing the coupling restores the plain solve
+    o.set_outlets([], [])
+    x0, rc0, _ = o.solve(b, oracle.solve_opts(tol=1e-11))
+    assert rc0 == 0 and np.linalg.norm(x0 - y) <= 1e-9 * np.linalg.norm(y)
+
+
+def test_algorithm2_with_outlets_uses_the_coupled_velocity_block(flow_fsi):
+    # S x = C x - D (A + sum_k m_k a_k a_k^T)^-1 G x with exact inner solves
+    s = flow_fsi
+    outlets, m = _two_outlets(s)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz)
+    o.set_outlets(outlets, m)
+    A, G, D, Cb, _, perm = _dense_blocks(s)
+    Uv = _outlet_columns(s, outlets)[perm][:3 * s.n_b]
+    Af = A + Uv @ np.diag(m) @ Uv.T
+    xp = np.random.default_rng(9).normal(size=s.n_b)
+    exact = Cb @ xp - D @ np.linalg.solve(Af, G @ xp)
+    y = o.apply("S", xp, oracle.solve_opts(tol_I=1e-14, max_it_I=400))
+    assert np.linalg.norm(y - exact) <= 1e-10 * np.linalg.norm(exact)
+    plain = Cb @ xp - D @ np.linalg.solve(A, G @ xp)
+    assert np.linalg.norm(plain - exact) > 1e-6 * np.linalg.norm(exact)
+    # the A and K operators
+    xv = np.random.default_rng(10).normal(size=3 * s.n_b)
+    assert np.allclose(o.apply("A", xv), Af @ xv, rtol=0, atol=1e-12 * np.abs(Af @ xv).max())

@@ -362,3 +362,125 @@ def test_y_mesh_laplacian(ysmall):
     full = nbr_dir == 0
     raw = np.asarray(Lf.sum(axis=1)).ravel()
     assert full.any() and np.abs(raw[full]).max() <= 1e-12 * abs(L).max()
+
+
+# ----------------------------------------------------------------------------- advective state and outlets
+def _bary_grad(x4):
+    """Gradients of the barycentric coordinates of a tetrahedron (rows), from the 4x4 system
+    [1 x y z] lambda = e (independent of the generator's Jacobian inverse)."""
+    T = np.hstack([np.ones((4, 1)), x4])
+    return np.linalg.inv(T)[1:].T            # (4, 3): grad lambda_a
+
+
+def test_reaction_term_alone_for_a_linear_field_with_zero_centroid_velocity():
+    # u(x) = B (x - centroid): the centroid velocity is zero, so tau_M and every advective term
+    # vanish except the reaction rho * M_ab * grad u with grad u = B (P1 is exact on linear fields)
+    rng = np.random.default_rng(21)
+    x = _random_tet(rng)
+    B = rng.normal(size=(3, 3))
+    u4 = (x - x.mean(0)) @ B.T
+    p = synth.default_params()
+    K0, V = synth.element(x, p, False)
+    K1, _ = synth.element(x, p, False, u4)
+    dK = (K1 - K0).reshape(4, 4, 4, 4)        # [a, c, b, d]
+    M = V * (np.ones((4, 4)) + np.eye(4)) / 20.0
+    expect = p.rho_f * M[:, None, :, None] * np.pad(B, ((0, 1), (0, 1)))[None, :, None, :]
+    assert np.abs(dK - expect).max() <= 1e-13 * np.abs(K1).max()
+
+
+def test_uniform_advection_terms_match_quadrature_of_the_weak_form():
+    # uniform u, only the advection bit: the element integrals of the Oseen VMS terms, evaluated
+    # by a degree-2 quadrature with independently computed shape functions
+    rng = np.random.default_rng(22)
+    x = _random_tet(rng)
+    u = rng.normal(size=3)
+    p = synth.default_params(terms=32)
+    Ke, V = synth.element(x, p, False, np.tile(u, (4, 1)))
+    tauM, _ = synth.tau(x, p, u)
+    am, af, g = synth.genalpha(p.rho_inf)
+    ct = am / (af * g * p.dt)
+    rho = p.rho_f
+    dN = _bary_grad(x)
+    a_, b_ = 0.5854101966249685, 0.1381966011250105
+    pts = [np.roll([a_, b_, b_, b_], k) for k in range(4)]            # barycentric points, weight V/4
+    ud = dN @ u                                                        # u . grad N_a
+    A = np.zeros((4, 4)); G = np.zeros((4, 3, 4)); D = np.zeros((4, 4, 3))
+    for lam in pts:
+        w = V / 4.0
+        A += w * (rho * np.outer(lam, ud) + tauM * rho * rho * np.outer(ud, ct * lam + ud))
+        G += w * tauM * rho * ud[:, None, None] * dN.T[None, :, :]
+        D += w * tauM * rho * dN[:, None, :] * ud[None, :, None]
+    K = Ke.reshape(4, 4, 4, 4)
+    scale = np.abs(Ke).max()
+    for i in range(3):
+        for j in range(3):
+            assert np.abs(K[:, i, :, j] - (A if i == j else 0.0)).max() <= 1e-12 * scale
+        assert np.abs(K[:, i, :, 3] - G[:, i, :]).max() <= 1e-12 * scale
+        assert np.abs(K[:, 3, :, i] - D[:, :, i]).max() <= 1e-12 * scale
+    assert np.abs(K[:, 3, :, 3]).max() == 0.0
+
+
+def test_tau_M_with_advection_and_no_viscosity():
+    # mu = 0: tau_M = rho^-1 (4/dt^2 + u.G.u)^-1/2; for a velocity field along one edge direction
+    # the metric term is positive and tau_M falls below dt/(2 rho)
+    p = synth.default_params(mu_f=0.0)
+    x = _random_tet(np.random.default_rng(23))
+    t0, _ = synth.tau(x, p, np.zeros(3))
+    assert t0 == pytest.approx(p.dt / (2 * p.rho_f), rel=1e-14)
+    u = 50.0 * (x[1] - x[0])
+    t1, _ = synth.tau(x, p, u)
+    uGu = (1.0 / (p.rho_f * t1)) ** 2 - 4.0 / p.dt ** 2
+    assert t1 < t0 and uGu > 0.0
+    t2, _ = synth.tau(x, p, 2.0 * u)                  # u.G.u is quadratic in u
+    assert (1.0 / (p.rho_f * t2)) ** 2 - 4.0 / p.dt ** 2 == pytest.approx(4.0 * uGu, rel=1e-9)
+
+
+def test_advective_state_and_nonsymmetric_velocity_block(small_fsi_flow):
+    import scipy.sparse as sp
+    s0, s1 = small_fsi_flow
+    assert np.array_equal(s0.rp, s1.rp) and np.array_equal(s0.ci, s1.ci)
+    fluid = np.isin(s1.kind, (0, 2))
+    r = np.hypot(s1.xyz[:, 0], s1.xyz[:, 1])
+    expect = np.where(fluid, 30.0 * np.clip(1.0 - r ** 2, 0.0, None), 0.0)
+    assert np.allclose(s1.uadv[:, 2], expect, rtol=0, atol=1e-12) and not s1.uadv[:, :2].any()
+    A = lambda s: bsr_to_dense(s.rp, s.ci, s.val[:, :3, :3])
+    A0, A1 = A(s0), A(s1)
+    assert np.abs(A0 - A0.T).max() <= 1e-13 * np.abs(A0).max()
+    assert np.abs(A1 - A1.T).max() > 1e-3 * np.abs(A1).max()
+    # rows and columns of purely solid nodes see no fluid element: unchanged
+    solid_rows = np.repeat(s1.kind == 1, 3)
+    assert np.array_equal(A0[solid_rows][:, solid_rows], A1[solid_rows][:, solid_rows])
+    # the advective state makes every fluid element's contribution differ, but Dirichlet rows stay
+    d = np.where(s1.mask)[0]
+    K1 = sp.csr_matrix(bsr_to_dense(s1.rp, s1.ci, s1.val))
+    assert np.all(K1[d].data == 1.0) and abs(K1[:, d]).sum() == d.size
+
+
+@pytest.fixture(scope="module")
+def small_fsi_flow():
+    kw = dict(mode=0, m_core=2, n_bl=1, n_wall=1, nz=8, R=1.0, L=2.0)
+    return synth.generate(synth.default_params(**kw)), synth.generate(synth.default_params(u_max=30.0, **kw))
+
+
+def test_outlet_vector_is_the_outlet_face_area_distribution():
+    # without Dirichlet elimination the weights are the P1 integrals of N_A over the outlet face:
+    # they sum to the area of the regular 8*m-gon that bounds the lumen, and sit on z = L only
+    kw = dict(mode=0, m_core=3, n_bl=1, n_wall=0, nz=4, R=1.0, L=2.0)
+    s = synth.generate(synth.default_params(apply_bc=0, **kw))
+    assert len(s.outlets) == 1
+    blk, a = s.outlets[0]
+    N = 8 * 4
+    assert a[:, 2].sum() == pytest.approx(0.5 * N * np.sin(2 * np.pi / N), rel=1e-13)
+    assert not a[:, :2].any() and np.all(a[:, 2] > 0)
+    assert np.all(s.xyz[blk, 2] == s.xyz[:, 2].max())
+    # each vertex of the regular triangulated disk gets a third of its incident triangle areas:
+    # the centre node of the section touches 8 triangles of the innermost shell
+    centre = np.where((np.hypot(s.xyz[blk, 0], s.xyz[blk, 1]) == 0.0))[0]
+    assert centre.size == 1
+    # with Dirichlet elimination the wall ring is dropped (no-slip) and the rest is unchanged
+    s2 = synth.generate(synth.default_params(apply_bc=1, **kw))
+    blk2, a2 = s2.outlets[0]
+    keep = np.isin(blk, blk2)
+    assert np.array_equal(blk[keep], blk2) and np.array_equal(a[keep], a2)
+    ring = np.hypot(s.xyz[blk[~keep], 0], s.xyz[blk[~keep], 1])
+    assert np.allclose(ring, 1.0, rtol=0, atol=1e-12) and ring.size == N
