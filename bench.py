@@ -38,6 +38,9 @@ def parse():
                     help="outer preconditioner: SCR (Algorithm 1), SIMPLE or SIMPLEC (Sec. 5.2.1)")
     ap.add_argument("--dt-sweep", action="store_true",
                     help="compare SCR and SIMPLE iterations and times on cfg1 at dt = 1e-5, 1e-4, 1e-3 (FP64)")
+    ap.add_argument("--flow", action="store_true",
+                    help="cfg1 with the advective Poiseuille state (u_max = 30 cm/s; nonsymmetric velocity block) "
+                         "and the outlet resistance coupling (m = 1000) attached in every step")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default=None,
                     help="default: both for cfg1, mixed for cfg4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -58,6 +61,8 @@ def parse():
 
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+FLOW_U_MAX = 30.0       # --flow: centreline speed of the advective state (cm/s)
+FLOW_M = 1000.0         # --flow: outlet resistance coefficient of the coupling
 # the files that define the profiled kernel and its data layout
 KERNEL_SOURCES = ["paper_2206_06996_amd/csrc/sparse.hip", "paper_2206_06996_amd/csrc/common.h"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "smooth_a0_cfg1_pmc.json")
@@ -364,11 +369,19 @@ def main():
     t0 = time.time()
     if args.precision is None:
         args.precision = "both" if args.workload == "cfg1" else "mixed"
-    s = synth.generate(synth.cfg1_params() if args.workload == "cfg1" else synth.cfg4_params())
+    prm = synth.cfg1_params() if args.workload == "cfg1" else synth.cfg4_params()
+    if args.flow:
+        if args.workload != "cfg1":
+            raise SystemExit("--flow runs on cfg1 only")
+        prm.u_max = FLOW_U_MAX
+    s = synth.generate(prm)
     log(f"[bench] {args.workload} generated: n_b={s.n_b} nnzb={s.nnzb} nodes={s.n_phys} ({time.time() - t0:.1f}s)", args)
     if args.workload == "cfg1":
         workload = ("cfg1 unified fluid+solid tube 41x41x179 (300,899 nodes, 323,811 block rows, "
                     "5,051,767 4x4 blocks) + mesh motion (300,899 x 3)")
+        if args.flow:
+            workload += (f"; advective Poiseuille state u_max = {FLOW_U_MAX:g} cm/s (Oseen VMS tangent, nonsymmetric A) "
+                         f"and the outlet resistance coupling m = {FLOW_M:g} over {len(s.outlets[0][0])} outlet nodes")
     else:
         workload = (f"cfg4 Y-bifurcation, voxel mesh (parent R=1, daughters 0.7 at seeded angles, wall 1.2x; "
                     f"{s.n_phys:,} nodes, {s.n_b:,} block rows, {s.nnzb:,} 4x4 blocks) + mesh motion ({s.n_phys:,} x 3)")
@@ -408,6 +421,8 @@ def main():
             torch.cuda.synchronize()
             ts = time.perf_counter()
             h = scr.amg_setup(ctx, scr.SCR_SYSTEM, rp, ci, val, xyz, ao)
+            if args.flow:
+                scr.set_outlets(h, s.outlets, [FLOW_M])
             t1 = time.perf_counter()
             rc, st = scr.scr_solve(h, B[i], x, so)
             t2 = time.perf_counter()
@@ -490,7 +505,7 @@ def main():
             out[prec]["smoother_l0_GBps"] = round(rr["prof"]["gbs"], 1)
     pr = r["prof"]
     if pr:
-        traffic = pmc_traffic() if (main_prec == "fp64" and args.workload == "cfg1") else None
+        traffic = pmc_traffic() if (main_prec == "fp64" and args.workload == "cfg1" and not args.flow) else None
         out["roofline"] = {"bound": "hbm", "achieved": round(pr["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(pr["gbs"] / HBM_PEAK_GBS, 4),
                            "traffic": None if traffic is None else round(traffic / (pr["avg_us"] * 1e-6) / 1e9, 1),
@@ -501,7 +516,8 @@ def main():
                            "alg_bytes_per_launch": int(pr["bytes_per_launch"])}
     else:
         out["roofline"] = None
-    out["cpu_baseline"] = None if (args.no_cpu_baseline or args.workload != "cfg1" or args.precond != "scr") else \
+    out["cpu_baseline"] = None if (args.no_cpu_baseline or args.workload != "cfg1" or args.precond != "scr"
+                                   or args.flow) else \
         cpu_baseline(s, None, BM_host, args)
     print(json.dumps(out))
 

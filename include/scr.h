@@ -155,6 +155,21 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
  * unusable: every later solve or update on it returns SCR_E_INVALID, destroy it. */
 scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, void* stream);
 
+/* Outlet resistance coupling (Sec. 3.5: the consistent linearisation of the reduced outlet models
+ * adds alpha_f gamma dt sum_k m_k a_k a_k^T to the velocity block, a_k holding the integrals of
+ * N_A n_i over outlet k; for a tangent scaled by 1/(alpha_f gamma dt) the coefficient is m_k).
+ * After this call the solves of h use K + sum_k m[k] [a_k; 0][a_k; 0]^T as the outer operator
+ * and A + sum_k m[k] a_k a_k^T wherever Algorithms 1 and 2 (and SIMPLE) apply or invert A; the
+ * split, S^ and both AMG hierarchies stay those of the sparse K (they are not rebuilt).
+ * off: host, n_out + 1 nondecreasing offsets from 0; outlet k owns entries off[k] .. off[k+1]-1.
+ * blk: device, off[n_out] block rows (each row at most once over all outlets); a: device,
+ * 3 * off[n_out] FP64, the velocity components of a_k at those rows; m: host, n_out FP64.
+ * All are copied.  n_out = 0 removes the coupling.  It survives amg_update.  Errors:
+ * SCR_E_INVALID (handle kind, offsets, rows out of range or repeated, non-finite values) with
+ * the previous coupling kept. */
+scr_status scr_set_outlets(scr_handle* h, int n_out, const int64_t* off /* host */, const int32_t* blk,
+                           const double* a, const double* m /* host */, void* stream);
+
 /* Solve K x = b (SCR_SYSTEM handle) by FGMRES(P_SCR) to ||b - K x|| <= tol ||b|| (true FP64
  * residual, checked at exit).  b, x: device, 4 * n_brows FP64, node-interleaved [vx vy vz p].
  * x is the initial guess if use_x0, else it is overwritten.  Returns SCR_OK, or

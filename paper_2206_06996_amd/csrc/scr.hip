@@ -33,19 +33,77 @@ struct scr_handle {
     scr_stats st{};
     scr_solve_opts so{};
     bool broken = false;                          // a failed amg_update left the hierarchies half-updated
+    // outlet coupling (scr_set_outlets): outlet k adds m_k a_k a_k^T to the velocity block; entry e
+    // of the concatenated list names block row out_blk[e], outlet out_id[e] and a_k there (3)
+    int n_out = 0;
+    int64_t n_oe = 0;
+    int32_t *out_blk = nullptr, *out_id = nullptr;
+    int64_t* out_off = nullptr;
+    double *out_a = nullptr, *out_m = nullptr, *out_s = nullptr;
 };
 
 namespace {
+
+// s_k = m_k * (a_k . x_v): one workgroup per outlet, its entries strided over the threads and the
+// partial sums added by a fixed LDS tree
+__global__ void __launch_bounds__(256) outlet_dot_k(const int64_t* __restrict__ off, const int32_t* __restrict__ blk,
+                                                    const double* __restrict__ a, const double* __restrict__ m,
+                                                    const double* __restrict__ x, double* __restrict__ sk) {
+    __shared__ double red[256];
+    const int k = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t e = off[k] + threadIdx.x; e < off[k + 1]; e += 256) {
+        const int64_t b = blk[e];
+        acc += a[3 * e] * x[3 * b] + a[3 * e + 1] * x[3 * b + 1] + a[3 * e + 2] * x[3 * b + 2];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sk[k] = m[k] * red[0];
+}
+// y_v += s_k a_k (block rows are distinct across all outlets, so entries never collide)
+__global__ void outlet_axpy_k(int64_t ne, const int32_t* __restrict__ blk, const int32_t* __restrict__ id,
+                              const double* __restrict__ a, const double* __restrict__ sk, double* __restrict__ y) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const double c = sk[id[e]];
+    const int64_t b = blk[e];
+    for (int i = 0; i < 3; ++i) y[3 * b + i] += c * a[3 * e + i];
+}
+
+// y_v += sum_k m_k a_k (a_k . x_v) on velocity vectors (node-interleaved, 3 per block row)
+void apply_outlets(const scr_handle* h, const double* xv, double* yv, hipStream_t s) {
+    if (h->n_out == 0) return;
+    outlet_dot_k<<<h->n_out, 256, 0, s>>>(h->out_off, h->out_blk, h->out_a, h->out_m, xv, h->out_s);
+    outlet_axpy_k<<<cdiv(h->n_oe, 256), 256, 0, s>>>(h->n_oe, h->out_blk, h->out_id, h->out_a, h->out_s, yv);
+    check_launch("outlets");
+}
 
 struct MatOp : Op {
     const DSell<double>* M;
     explicit MatOp(const DSell<double>* m) : M(m) {}
     void apply(const double* x, double* y, hipStream_t s) override { sell_mv<double>(*M, x, nullptr, y, 0, s); }
 };
+// K with the outlet coupling, on split vectors (the velocity part leads)
 struct KOp : Op {
-    const DSell<double>* K;
-    explicit KOp(const DSell<double>* k) : K(k) {}
-    void apply(const double* x, double* y, hipStream_t s) override { sell_mv_split4(*K, x, nullptr, y, 0, s); }
+    const scr_handle* h;
+    explicit KOp(const scr_handle* hh) : h(hh) {}
+    void apply(const double* x, double* y, hipStream_t s) override {
+        sell_mv_split4(h->Ks, x, nullptr, y, 0, s);
+        apply_outlets(h, x, y, s);
+    }
+};
+// the velocity block A with the outlet coupling
+struct AOp : Op {
+    const scr_handle* h;
+    explicit AOp(const scr_handle* hh) : h(hh) {}
+    void apply(const double* x, double* y, hipStream_t s) override {
+        sell_mv<double>(h->As, x, nullptr, y, 0, s);
+        apply_outlets(h, x, y, s);
+    }
 };
 struct VOp : Op {
     Hierarchy* H;
@@ -63,7 +121,7 @@ struct SchurOp : Op {
     explicit SchurOp(scr_handle* hh) : h(hh) {}
     void apply(const double* xp, double* y, hipStream_t s) override {
         sell_mv<double>(h->Gs, xp, nullptr, h->xbar, 0, s);
-        MatOp aop(&h->As);
+        AOp aop(h);
         VOp pa(h->hA.get(), &h->st.vcycles_A);
         KStat k = h->gA->solve(aop, pa, h->xbar, h->xtil, h->so.tol_I, h->so.max_it_I, false, false, s);
         h->st.calls_I++;
@@ -83,7 +141,7 @@ struct ScrPrec : Op {
         const double* rp = r + 3 * n;
         double* yv = y;
         double* yp = y + 3 * n;
-        MatOp aop(&h->As);
+        AOp aop(h);
         VOp pa(h->hA.get(), &h->st.vcycles_A);
         KStat k = h->gA->solve(aop, pa, rv, h->yhat, h->so.tol_A, h->so.max_it_A, false, false, s);
         h->st.calls_A++;
@@ -120,7 +178,7 @@ struct SimplePrec : Op {
         const double* rp = r + 3 * n;
         double* yv = y;
         double* yp = y + 3 * n;
-        MatOp aop(&h->As);
+        AOp aop(h);
         VOp pa(h->hA.get(), &h->st.vcycles_A);
         KStat k = h->gA->solve(aop, pa, rv, h->yhat, h->so.tol_A, h->so.max_it_A, false, false, s);
         h->st.calls_A++;
@@ -462,6 +520,76 @@ scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, voi
     }
 }
 
+scr_status scr_set_outlets(scr_handle* h, int n_out, const int64_t* off, const int32_t* blk, const double* a,
+                           const double* m, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!h) throw Error(SCR_E_INVALID, "NULL handle");
+        if (h->kind != SCR_SYSTEM) throw Error(SCR_E_INVALID, "outlets belong to an SCR_SYSTEM handle");
+        if (n_out < 0) throw Error(SCR_E_INVALID, "n_out < 0");
+        if (n_out > 0 && (!off || !m)) throw Error(SCR_E_INVALID, "NULL off or m");
+        HIPCHK(hipSetDevice(h->ctx->device));
+        Arena& ar = *h->ar;
+        int64_t ne = n_out > 0 ? off[n_out] : 0;
+        if (n_out > 0) {
+            if (off[0] != 0) throw Error(SCR_E_INVALID, "off[0] != 0");
+            for (int k = 0; k < n_out; ++k)
+                if (off[k + 1] < off[k]) throw Error(SCR_E_INVALID, "off is not nondecreasing");
+            for (int k = 0; k < n_out; ++k)
+                if (!std::isfinite(m[k])) throw Error(SCR_E_INVALID, "non-finite coefficient");
+            if (ne > 0 && (!blk || !a)) throw Error(SCR_E_INVALID, "NULL blk or a");
+        }
+        // validate the (small) entry lists on the host before anything is replaced
+        std::vector<int32_t> hb(ne);
+        std::vector<double> ha(3 * ne);
+        if (ne > 0) {
+            HIPCHK(hipMemcpyAsync(hb.data(), blk, ne * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(ha.data(), a, 3 * ne * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            std::vector<uint8_t> seen(h->nb, 0);
+            for (int64_t e = 0; e < ne; ++e) {
+                if (hb[e] < 0 || hb[e] >= h->nb) throw Error(SCR_E_INVALID, "outlet block row out of range");
+                if (seen[hb[e]]) throw Error(SCR_E_INVALID, "a block row appears twice in the outlet lists");
+                seen[hb[e]] = 1;
+            }
+            for (double v : ha)
+                if (!std::isfinite(v)) throw Error(SCR_E_INVALID, "non-finite outlet vector");
+        }
+        for (void* p : {(void*)h->out_blk, (void*)h->out_id, (void*)h->out_off, (void*)h->out_a, (void*)h->out_m,
+                        (void*)h->out_s})
+            ar.free(p);
+        h->out_blk = h->out_id = nullptr;
+        h->out_off = nullptr;
+        h->out_a = h->out_m = h->out_s = nullptr;
+        h->n_out = 0;
+        h->n_oe = 0;
+        if (n_out == 0) return SCR_OK;
+        std::vector<int32_t> hid(ne);
+        for (int k = 0; k < n_out; ++k)
+            for (int64_t e = off[k]; e < off[k + 1]; ++e) hid[e] = k;
+        h->out_off = ar.make<int64_t>(n_out + 1);
+        h->out_m = ar.make<double>(n_out);
+        h->out_s = ar.make<double>(n_out);
+        h->out_blk = ar.make<int32_t>(ne > 0 ? ne : 1);
+        h->out_id = ar.make<int32_t>(ne > 0 ? ne : 1);
+        h->out_a = ar.make<double>(3 * (ne > 0 ? ne : 1));
+        HIPCHK(hipMemcpyAsync(h->out_off, off, (n_out + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->out_m, m, n_out * sizeof(double), hipMemcpyHostToDevice, s));
+        if (ne > 0) {
+            HIPCHK(hipMemcpyAsync(h->out_blk, hb.data(), ne * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(h->out_id, hid.data(), ne * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(h->out_a, ha.data(), 3 * ne * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        h->n_out = n_out;
+        h->n_oe = ne;
+        return SCR_OK;
+    } catch (const Error& e) {
+        (void)hipStreamSynchronize(s);
+        return fail(e);
+    }
+}
+
 scr_status scr_handle_destroy(scr_handle* h) {
     if (!h) return SCR_OK;
     try {
@@ -500,7 +628,7 @@ scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_
         const int64_t nb = h->nb;
         interleaved_to_split(nb, b, h->bs, s);
         if (o.use_x0) interleaved_to_split(nb, x, h->xs, s);
-        KOp kop(&h->Ks);
+        KOp kop(h);
         ScrPrec prec_scr(h);
         SimplePrec prec_simple(h);
         if (o.precond == SCR_PRECOND_SIMPLE) ensure_simple(h, s);
@@ -691,8 +819,8 @@ scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const sc
         if ((op <= 9 || op == 12 || op == 13) != scr)
             throw Error(SCR_E_INVALID, "operator not available on this handle kind");
         switch (op) {
-            case 0: sell_mv_split4(h->Ks, x, nullptr, y, 0, s); break;
-            case 1: sell_mv<double>(h->As, x, nullptr, y, 0, s); break;
+            case 0: { KOp k(h); k.apply(x, y, s); break; }
+            case 1: { AOp a(h); a.apply(x, y, s); break; }
             case 2: h->hA->vcycle(x, y, s); break;
             case 3: h->hS->vcycle(x, y, s); break;
             case 4: { SchurOp so(h); so.apply(x, y, s); break; }

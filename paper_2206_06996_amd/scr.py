@@ -23,7 +23,7 @@ SCR_FP64, SCR_MIXED = 0, 1
 SCR_SMOOTH_JACOBI, SCR_SMOOTH_CHEBYSHEV = 0, 1
 
 EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", "scr_ctx_destroy",
-            "scr_ctx_bytes_in_use", "amg_setup", "amg_update", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
+            "scr_ctx_bytes_in_use", "amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
             "scr_handle_bytes", "scr_footprint_estimate", "scr_status_str", "scr_last_error", "scr_hier_levels",
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
             "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
@@ -102,6 +102,7 @@ def lib():
         L.scr_ctx_bytes_in_use.restype = C.c_int64
         L.amg_setup.argtypes = [P, C.c_int, C.POINTER(ScrBsr), P, C.POINTER(AmgOpts), P, C.POINTER(P)]
         L.amg_update.argtypes = [P, C.POINTER(ScrBsr), P, P]
+        L.scr_set_outlets.argtypes = [P, C.c_int, P, P, P, P, P]
         L.scr_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), P, C.POINTER(Stats)]
         L.mesh_motion_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), P, C.POINTER(Stats)]
         L.scr_handle_destroy.argtypes = [P]
@@ -126,7 +127,7 @@ def lib():
         L.srv_drain.argtypes = [P, C.POINTER(C.c_int)]
         L.srv_destroy.argtypes = [P]
         L.srv_destroy.restype = None
-        for f in ("amg_setup", "amg_update", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
+        for f in ("amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
                   "scr_ctx_profile", "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait",
                   "srv_drain"):
@@ -273,6 +274,25 @@ def amg_update(h: Handle, row_ptr, col_idx, val, coords=None, stream=None):
                val=_dev(val, torch.float64, "val"))
     cp = _dev(coords, torch.float64, "coords") if coords is not None else None
     _check(lib().amg_update(h.ptr, C.byref(K), cp, _stream(stream)))
+
+
+def set_outlets(h: Handle, outlets, m, stream=None):
+    """Outlet resistance coupling: outlets = [(block rows, a (n, 3)), ...] (numpy arrays), m =
+    one coefficient per outlet; an empty list removes the coupling."""
+    import torch
+    n = len(outlets)
+    off = np.zeros(n + 1, np.int64)
+    for k, (blk, _) in enumerate(outlets):
+        off[k + 1] = off[k] + len(blk)
+    mm = np.ascontiguousarray(np.asarray(m, np.float64).reshape(-1)[:n] if n else np.zeros(1))
+    blk = a = None
+    if n:
+        blk = torch.from_numpy(np.ascontiguousarray(np.concatenate([np.asarray(b) for b, _ in outlets]), np.int32)).to("cuda")
+        a = torch.from_numpy(np.ascontiguousarray(np.concatenate([np.asarray(v).reshape(-1) for _, v in outlets]),
+                                                  np.float64)).to("cuda")
+    _check(lib().scr_set_outlets(h.ptr, n, off.ctypes.data_as(P), None if blk is None else _dev(blk, torch.int32, "blk"),
+                                 None if a is None else _dev(a, torch.float64, "a"), mm.ctypes.data_as(P),
+                                 _stream(stream)))
 
 
 def scr_solve(h: Handle, b, x, opts: SolveOpts | None = None, stream=None):
