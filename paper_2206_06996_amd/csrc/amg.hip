@@ -85,6 +85,7 @@ void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, 
 // ====================================================================== generic SpGEMM (one wave per row)
 constexpr int HS_MAX = 8192;       // largest LDS hash table per row
 constexpr int HMAX = HS_MAX / 2;   // unique columns allowed per row
+constexpr int HS_COUNT = 2048;     // hash table of the counting pass (retried with HS_MAX on overflow)
 
 // returns 1 if newly inserted (table of hs slots, hs a power of two, never more than half full)
 __device__ __forceinline__ int hash_insert(int* t, int hs, int key) {
@@ -297,29 +298,42 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
     C.rp = ar.make<int32_t>(X.nr + 1);
     int32_t* cnt = ar.make<int32_t>(X.nr + 1);
     int* flags = ar.make<int>(3);      // [overflow, max candidate bound, max output row length]
-    HIPCHK(hipMemsetAsync(flags, 0, 3 * sizeof(int), s));
+    zero_dev(flags, 3 * sizeof(int), s);
     if (X.nr > 0) spg_bound_k<<<cdiv(X.nr, 256), 256, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, flags + 1);
     int hflags[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    // hash table of the counting pass: twice the candidate bound, but at most HS_COUNT slots (the
+    // unique columns of a row are far fewer than its candidates); a row that overflows it makes
+    // the pass run again with the largest table.  The result does not depend on the table size.
     int need = 2 * (hflags[1] < HMAX ? hflags[1] : HMAX) + 2;
     int hs = 64;
-    while (hs < need && hs < HS_MAX) hs <<= 1;
-    size_t lds = (size_t)(hs + hs / 2 + WAVE) * sizeof(int);
-    if (X.nr > 0)
-        spg_symbolic<0><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr, flags);
-    check_launch("spg_count");
-    C.nnzb = scan_i32(cnt, C.rp, X.nr, ar, s);
+    while (hs < need && hs < HS_COUNT) hs <<= 1;
     int hf[3] = {0, 0, 0};
-    HIPCHK(hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hf[0]) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
+    for (;;) {
+        size_t lds = (size_t)(hs + hs / 2 + WAVE) * sizeof(int);
+        if (X.nr > 0)
+            spg_symbolic<0><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr,
+                                                    flags);
+        check_launch("spg_count");
+        HIPCHK(hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!hf[0]) break;
+        if (hs >= HS_MAX) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
+        hs = HS_MAX;
+        zero_dev(flags, sizeof(int), s);
+    }
+    C.nnzb = scan_i32(cnt, C.rp, X.nr, ar, s);
     const int wmax = hf[2];
     ar.free(cnt);
     C.ci = ar.make<int32_t>(C.nnzb > 0 ? C.nnzb : 1);
     C.v = ar.make<double>((C.nnzb > 0 ? C.nnzb : 1) * C.br * C.bc);
+    // the filling pass knows the widest row exactly
+    int hs1 = 64;
+    while (hs1 < 2 * wmax + 2) hs1 <<= 1;
+    size_t lds1 = (size_t)(hs1 + hs1 / 2 + WAVE) * sizeof(int);
     if (X.nr > 0)
-        spg_symbolic<1><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, flags);
+        spg_symbolic<1><<<X.nr, WAVE, lds1, s>>>(X.nr, hs1, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, flags);
     check_launch("spg_fill");
     ar.free(flags);
     spgemm_numeric_run(X, Y, C, wmax, s);
@@ -335,7 +349,7 @@ __global__ void rowlen_max_k(int64_t nr, const int32_t* __restrict__ rp, int* __
 // numeric phase only, into the existing pattern of C (same terms and order as a full product)
 static void spgemm_numeric(const DBsr& X, const DBsr& Y, DBsr& C, Arena& ar, hipStream_t s) {
     int* d = ar.make<int>(1);
-    HIPCHK(hipMemsetAsync(d, 0, sizeof(int), s));
+    zero_dev(d, sizeof(int), s);
     if (C.nr > 0) rowlen_max_k<<<cdiv(C.nr, 256), 256, 0, s>>>(C.nr, C.rp, d);
     int wmax = 0;
     HIPCHK(hipMemcpyAsync(&wmax, d, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -812,11 +826,11 @@ static DBsr transpose(const DBsr& M, Arena& ar, hipStream_t s) {
     DBsr T;
     T.nr = M.nc; T.nc = M.nr; T.br = M.bc; T.bc = M.br; T.nnzb = M.nnzb;
     int32_t* cnt = ar.make<int32_t>(M.nc + 1);
-    HIPCHK(hipMemsetAsync(cnt, 0, (M.nc + 1) * sizeof(int32_t), s));
+    zero_dev(cnt, (M.nc + 1) * sizeof(int32_t), s);
     if (M.nnzb) tr_count_k<<<cdiv(M.nnzb, 256), 256, 0, s>>>(M.nnzb, M.ci, cnt);
     T.rp = ar.make<int32_t>(M.nc + 1);
     scan_i32(cnt, T.rp, M.nc, ar, s);
-    HIPCHK(hipMemsetAsync(cnt, 0, (M.nc + 1) * sizeof(int32_t), s));
+    zero_dev(cnt, (M.nc + 1) * sizeof(int32_t), s);
     int32_t* tci = ar.make<int32_t>(M.nnzb + 1);
     int32_t* src = ar.make<int32_t>(M.nnzb + 1);
     if (M.nr) tr_fill_k<<<cdiv(M.nr, 256), 256, 0, s>>>(M.nr, M.rp, M.ci, T.rp, cnt, tci, src);
@@ -999,8 +1013,8 @@ static void level_diag(LevelSetup& L, int l, int* err, unsigned long long* lamd,
     const int64_t nr = L.A.nr;
     const int64_t g = cdiv(nr, 256);
     const int b = L.b;
-    HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
-    HIPCHK(hipMemsetAsync(lamd, 0, sizeof(unsigned long long), s));
+    zero_dev(err, sizeof(int), s);
+    zero_dev(lamd, sizeof(unsigned long long), s);
     if (g) {
         if (b == 1) dinv_lambda_k<1><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
         else if (b == 3) dinv_lambda_k<3><<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.Dinv, lamd, err);
@@ -1028,14 +1042,14 @@ static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
     if (H.cinv) { ar.free(H.cinv); H.cinv = nullptr; }
     double* M0 = ar.make<double>(nc * nc + 1);
     double* M1 = ar.make<double>(nc * nc + 1);
-    HIPCHK(hipMemsetAsync(M0, 0, nc * nc * sizeof(double), s));
+    zero_dev(M0, nc * nc * sizeof(double), s);
     if (C.A.nr) densify_k<<<cdiv(C.A.nr, 256), 256, 0, s>>>(C.A.nr, C.b, C.A.rp, C.A.ci, C.A.v, M0, nc);
     for (int64_t kp = 0; kp < nc; ++kp) {
         gj_step_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc, kp, M0, M1);
         std::swap(M0, M1);
     }
     check_launch("coarse inverse");
-    HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+    zero_dev(err, sizeof(int), s);
     if (nc) finite_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc * nc, M0, err);
     int he = 0;
     HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1059,12 +1073,12 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
     {
         LevelSetup l0;
         l0.A = bsr_alloc(A0.nr, A0.nc, A0.br, A0.bc, A0.nnzb, ar);
-        HIPCHK(hipMemcpyAsync(l0.A.rp, A0.rp, (A0.nr + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(l0.A.ci, A0.ci, A0.nnzb * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(l0.A.v, A0.v, A0.nnzb * A0.br * A0.bc * sizeof(double), hipMemcpyDeviceToDevice, s));
+        copy_dev(l0.A.rp, A0.rp, (A0.nr + 1) * sizeof(int32_t), s);
+        copy_dev(l0.A.ci, A0.ci, A0.nnzb * sizeof(int32_t), s);
+        copy_dev(l0.A.v, A0.v, A0.nnzb * A0.br * A0.bc * sizeof(double), s);
         l0.b = A0.br; l0.k = k;
         l0.B = ar.make<double>(A0.nr * A0.br * k);
-        HIPCHK(hipMemcpyAsync(l0.B, B0, A0.nr * A0.br * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+        copy_dev(l0.B, B0, A0.nr * A0.br * k * sizeof(double), s);
         H->L.push_back(l0);
     }
     for (int l = 0;; ++l) {
@@ -1096,7 +1110,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         mis_init_k<<<g, 256, 0, s>>>(nr, iso, o.seed, l, st);
         for (int round = 0;; ++round) {
             if (round > 100000) throw Error(SCR_E_HIP, "MIS-2 did not terminate");
-            HIPCHK(hipMemsetAsync(und, 0, sizeof(int), s));
+            zero_dev(und, sizeof(int), s);
             mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1);
             mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2);
             mis_decide_k<<<g, 256, 0, s>>>(nr, st, m2, und);
@@ -1117,7 +1131,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         uint8_t* step1 = ar.make<uint8_t>(nr);
         agg_roots_k<<<g, 256, 0, s>>>(nr, st, rid, L.agg);
         agg_dist1_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, iso, st, rid, L.agg, step1);
-        HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+        zero_dev(err, sizeof(int), s);
         agg_dist2_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, iso, step1, o.seed, l, L.agg, err);
         check_launch("aggregate");
         HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1133,22 +1147,22 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         const int kk = L.k;
         // members of each aggregate, ascending
         int32_t* mcnt = ar.make<int32_t>(na + 1);
-        HIPCHK(hipMemsetAsync(mcnt, 0, (na + 1) * sizeof(int32_t), s));
+        zero_dev(mcnt, (na + 1) * sizeof(int32_t), s);
         agg_count_k<<<g, 256, 0, s>>>(nr, L.agg, mcnt);
         int32_t* mrp = ar.make<int32_t>(na + 1);
         int64_t nmem = scan_i32(mcnt, mrp, na, ar, s);
-        HIPCHK(hipMemsetAsync(mcnt, 0, (na + 1) * sizeof(int32_t), s));
+        zero_dev(mcnt, (na + 1) * sizeof(int32_t), s);
         int32_t* mem = ar.make<int32_t>(nmem + 1);
         agg_fill_k<<<g, 256, 0, s>>>(nr, L.agg, mrp, mcnt, mem);
         agg_sort_k<<<cdiv(na, 64), 64, 0, s>>>(na, mrp, mem);
         // tentative prolongator and coarse near-null space
         double* Q = ar.make<double>(nr * b * kk);
-        HIPCHK(hipMemsetAsync(Q, 0, nr * b * kk * sizeof(double), s));
+        zero_dev(Q, nr * b * kk * sizeof(double), s);
         LevelSetup N;
         N.b = kk; N.k = kk;
         N.B = ar.make<double>(na * kk * kk);
         L.dead = ar.make<uint8_t>(na * kk);
-        HIPCHK(hipMemsetAsync(L.dead, 0, na * kk, s));
+        zero_dev(L.dead, na * kk, s);
         tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, kk, mrp, mem, L.B, Q, N.B, L.dead);
         check_launch("tentative");
         ar.free(mcnt);
@@ -1203,8 +1217,8 @@ void update_hierarchy(Hierarchy& H, const double* vals0, const double* B0, Arena
     int* err = ar.make<int>(1);
     unsigned long long* lamd = ar.make<unsigned long long>(1);
     LevelSetup& L0 = H.L[0];
-    HIPCHK(hipMemcpyAsync(L0.A.v, vals0, L0.A.nnzb * L0.b * L0.b * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (B0) HIPCHK(hipMemcpyAsync(L0.B, B0, L0.A.nr * L0.b * L0.k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    copy_dev(L0.A.v, vals0, L0.A.nnzb * L0.b * L0.b * sizeof(double), s);
+    if (B0) copy_dev(L0.B, B0, L0.A.nr * L0.b * L0.k * sizeof(double), s);
     for (size_t l = 0; l < H.L.size(); ++l) {
         LevelSetup& L = H.L[l];
         level_diag(L, (int)l, err, lamd, s);
@@ -1215,8 +1229,8 @@ void update_hierarchy(Hierarchy& H, const double* vals0, const double* B0, Arena
         const int64_t g = cdiv(nr, 256);
         // tentative prolongator, coarse near-null space and dead dofs from the kept aggregates
         double* Q = ar.make<double>(nr * b * kk);
-        HIPCHK(hipMemsetAsync(Q, 0, nr * b * kk * sizeof(double), s));
-        HIPCHK(hipMemsetAsync(L.dead, 0, na * kk, s));
+        zero_dev(Q, nr * b * kk * sizeof(double), s);
+        zero_dev(L.dead, na * kk, s);
         tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, kk, L.mrp, L.mem, L.B, Q, N.B, L.dead);
         check_launch("tentative");
         DBsr Pt;

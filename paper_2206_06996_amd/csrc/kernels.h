@@ -10,6 +10,9 @@ namespace scr {
 int64_t scan_i32(const int32_t* in, int32_t* out, int64_t n, Arena& ar, hipStream_t s);
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+// device-to-device copy and zero fill of `bytes` bytes by kernels (no runtime blit)
+void copy_dev(void* dst, const void* src, size_t bytes, hipStream_t s);
+void zero_dev(void* p, size_t bytes, hipStream_t s);
 template <typename T> void fill(T* p, T v, int64_t n, hipStream_t s);
 void cast_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 void cast_f2d(const float* a, double* b, int64_t n, hipStream_t s);

@@ -24,7 +24,7 @@ void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_
     check_launch("axpby");
 }
 void copy_d(int64_t n, const double* x, double* y, hipStream_t s) {
-    if (n > 0) HIPCHK(hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (n > 0) copy_dev(y, x, n * sizeof(double), s);
 }
 
 __global__ void i2s_k(int64_t nb, const double* __restrict__ a, double* __restrict__ sv) {
@@ -70,7 +70,7 @@ void Reducer::init(int64_t n_, Arena& ar, hipStream_t s) {
     partials = ar.make<double>((size_t)grid * RMAXJ);
     counter = ar.make<unsigned>(1);
     out = ar.make<double>(RMAXJ);
-    HIPCHK(hipMemsetAsync(counter, 0, sizeof(unsigned), s));
+    zero_dev(counter, sizeof(unsigned), s);
 }
 
 template <int J>
@@ -383,7 +383,7 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
     double* part = red_.partials;
     GLay L{m};
     double bn = device_norm(b, n, red_, slot_, s);
-    if (!use_x0 || bn == 0.0) HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    if (!use_x0 || bn == 0.0) zero_dev(x, n * sizeof(double), s);
     if (bn == 0.0) {
         st.converged = true;
         return st;
@@ -525,7 +525,7 @@ KStat Pcg::solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit
     const int G = red_.grid;
     double* part = red_.partials;
     int64_t nblk = cdiv(n, 256);
-    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    zero_dev(x, n * sizeof(double), s);
     double bn = device_norm(b, n, red_, slot_, s);
     if (bn == 0.0) { st.converged = true; return st; }
     if (!std::isfinite(bn)) throw Error(SCR_E_BREAKDOWN, "non-finite right-hand side");

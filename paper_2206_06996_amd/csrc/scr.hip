@@ -394,9 +394,9 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         Km.rp = ar.make<int32_t>(nb + 1);
         Km.ci = ar.make<int32_t>(K->nnzb);
         Km.v = ar.make<double>(K->nnzb * K->bs * K->bs);
-        HIPCHK(hipMemcpyAsync(Km.rp, K->row_ptr, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(Km.ci, K->col_idx, K->nnzb * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(Km.v, K->val, K->nnzb * K->bs * K->bs * sizeof(double), hipMemcpyDeviceToDevice, s));
+        copy_dev(Km.rp, K->row_ptr, (nb + 1) * sizeof(int32_t), s);
+        copy_dev(Km.ci, K->col_idx, K->nnzb * sizeof(int32_t), s);
+        copy_dev(Km.v, K->val, K->nnzb * K->bs * K->bs * sizeof(double), s);
         if (kind == SCR_SYSTEM) {
             split_blocks(Km, h->A, h->G, h->D, h->C, ar, s);
             if (o.schur_diag != SCR_DIAG_A && o.schur_diag != SCR_DIAG_ABSROWSUM)
@@ -404,7 +404,7 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
             h->dvec = ar.make<double>(3 * nb);
             h->Sh = schur_approx(h->A, h->G, h->D, h->C, o.schur_diag, h->dvec, ar, s);
             double* xyz = ar.make<double>(nb * 3);
-            HIPCHK(hipMemcpyAsync(xyz, coords, nb * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            copy_dev(xyz, coords, nb * 3 * sizeof(double), s);
             h->B = ar.make<double>(nb * 18);
             rigid_modes(nb, xyz, h->B, ar, s);
             ar.free(xyz);
@@ -465,7 +465,7 @@ scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, voi
         const int64_t nb = h->nb;
         // the pattern must be the stored one: row_ptr first (bounds for the col_idx compare)
         int* flag = ar.make<int>(1);
-        HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
+        zero_dev(flag, sizeof(int), s);
         pattern_diff_k<<<cdiv(nb + 1, 256), 256, 0, s>>>(nb, K->row_ptr, K->col_idx, Km.rp, Km.ci, flag);
         check_launch("pattern_diff");
         int hf = 0;
@@ -483,13 +483,13 @@ scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, voi
         }
         // from here on a failure leaves the handle half-updated
         h->broken = true;
-        HIPCHK(hipMemcpyAsync(Km.v, K->val, Km.nnzb * Km.br * Km.bc * sizeof(double), hipMemcpyDeviceToDevice, s));
+        copy_dev(Km.v, K->val, Km.nnzb * Km.br * Km.bc * sizeof(double), s);
         if (h->kind == SCR_SYSTEM) {
             split_values(Km, h->A, h->G, h->D, h->C, s);
             schur_update(h->A, h->G, h->D, h->C, h->opts.schur_diag, h->dvec, h->Sh, ar, s);
             if (coords) {
                 double* xyz = ar.make<double>(nb * 3);
-                HIPCHK(hipMemcpyAsync(xyz, coords, nb * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+                copy_dev(xyz, coords, nb * 3 * sizeof(double), s);
                 rigid_modes(nb, xyz, h->B, ar, s);
                 ar.free(xyz);
             }

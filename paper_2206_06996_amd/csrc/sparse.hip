@@ -82,7 +82,7 @@ __global__ void scan_tiles(const int32_t* __restrict__ in, int64_t n, const int6
 int64_t scan_i32(const int32_t* in, int32_t* out, int64_t n, Arena& ar, hipStream_t s) {
     int64_t nt = cdiv(n, SCAN_TILE);
     if (nt == 0) {
-        HIPCHK(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+        zero_dev(out, sizeof(int32_t), s);
         return 0;
     }
     int64_t* sums = ar.make<int64_t>(nt + 1);
@@ -113,6 +113,40 @@ template void fill<double>(double*, double, int64_t, hipStream_t);
 template void fill<float>(float*, float, int64_t, hipStream_t);
 template void fill<int64_t>(int64_t*, int64_t, int64_t, hipStream_t);
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { fill<int32_t>(p, v, n, s); }
+
+// Device copies and zero fills by kernels (8-byte words when both ends and the size allow it,
+// else bytes): the runtime's blit copy and fill leave a long idle gap behind them on the stream.
+template <typename W>
+__global__ void copy_words_k(int64_t n, const W* __restrict__ x, W* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+template <typename W>
+__global__ void zero_words_k(int64_t n, W* __restrict__ p) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+static unsigned word_grid(int64_t n) { return (unsigned)std::min<int64_t>(cdiv(n, 256), 16384); }
+void copy_dev(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    if ((((uintptr_t)dst | (uintptr_t)src | bytes) & 7) == 0) {
+        int64_t n = (int64_t)(bytes / 8);
+        copy_words_k<uint64_t><<<word_grid(n), 256, 0, s>>>(n, (const uint64_t*)src, (uint64_t*)dst);
+    } else {
+        copy_words_k<uint8_t><<<word_grid((int64_t)bytes), 256, 0, s>>>((int64_t)bytes, (const uint8_t*)src, (uint8_t*)dst);
+    }
+    check_launch("copy_dev");
+}
+void zero_dev(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    if ((((uintptr_t)p | bytes) & 7) == 0) {
+        int64_t n = (int64_t)(bytes / 8);
+        zero_words_k<uint64_t><<<word_grid(n), 256, 0, s>>>(n, (uint64_t*)p);
+    } else {
+        zero_words_k<uint8_t><<<word_grid((int64_t)bytes), 256, 0, s>>>((int64_t)bytes, (uint8_t*)p);
+    }
+    check_launch("zero_dev");
+}
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) { fill<uint8_t>(p, v, n, s); }
 
 __global__ void cast_d2f_k(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
@@ -406,21 +440,34 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
         }
     };
     r[0] = r[1] = r[2] = 0;
-    for (; t + U <= o1; t += U) {
-        int64_t c[U];
-        T vv[U][E], xx[U][BC];
+    // software-pipelined: the column indices of a step are loaded one step ahead, so each step
+    // issues its x gathers, the next step's indices and its values together and waits once
+    int64_t c[U];
+    if (t + U <= o1) {
 #pragma unroll
         for (int u = 0; u < U; ++u) c[u] = ci[(t + u) * WAVE + lane];
+    }
+    for (; t + U <= o1; t += U) {
+        T vv[U][E], xx[U][BC];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < BC; ++k) xx[u][k] = x[c[u] * BC + k];
+        int64_t cn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t q = t + U + u < o1 ? t + U + u : o1 - 1;     // stays inside the slice
+            cn[u] = ci[q * WAVE + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);     // keep the gathers and indices ahead of the values
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int e = 0; e < E; ++e) vv[u][e] = ld(v + ((t + u) * E + e) * WAVE + lane);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int k = 0; k < BC; ++k) xx[u][k] = x[c[u] * BC + k];
-#pragma unroll
         for (int u = 0; u < U; ++u) fma_block(vv[u], xx[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = cn[u];
     }
     if (U > 1 && t < o1) {
         int64_t c = ci[t * WAVE + lane];
@@ -808,7 +855,7 @@ __global__ void validate_k(int64_t nr, int bs, int64_t nnzb, const int32_t* __re
 int validate_bsr(int64_t nr, int bs, int64_t nnzb, const int32_t* rp, const int32_t* ci, const double* v, Arena& ar,
                  hipStream_t s) {
     int* flags = ar.make<int>(1);
-    HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), s));
+    zero_dev(flags, sizeof(int), s);
     if (nr > 0) validate_k<<<cdiv(nr, 256), 256, 0, s>>>(nr, bs, nnzb, rp, ci, v, flags);
     check_launch("validate");
     int h = 0;
