@@ -333,11 +333,26 @@ __device__ __forceinline__ T sell_row_dot(int64_t o0, int64_t o1, int lane, int 
     constexpr int U = Unroll<BC>::U;
     T acc = 0;
     int64_t t = o0;
-    for (; t + U <= o1; t += U) {
-        int64_t c[U];
+    // software-pipelined as the block-row-lane loop: column indices one step ahead, x gathers and
+    // the next indices issued before the values, one memory round trip per step
+    int32_t c[U];     // int32 until used, so that no sign extension waits for the load
+    if (t + U <= o1) {
 #pragma unroll
         for (int u = 0; u < U; ++u) c[u] = ci[(t + u) * RPS + cl];
-        T vv[U][BC];
+    }
+    for (; t + U <= o1; t += U) {
+        T xx[U][BC], vv[U][BC];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < BC; ++k) xx[u][k] = xat((int64_t)c[u], k);
+        int32_t cn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t q = t + U + u < o1 ? t + U + u : o1 - 1;     // stays inside the slice
+            cn[u] = ci[q * RPS + cl];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -345,7 +360,9 @@ __device__ __forceinline__ T sell_row_dot(int64_t o0, int64_t o1, int lane, int 
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < BC; ++k) acc += vv[u][k] * xat(c[u], k);
+            for (int k = 0; k < BC; ++k) acc += vv[u][k] * xx[u][k];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = cn[u];
     }
     for (; t < o1; ++t) {
         int64_t c = ci[t * RPS + cl];
@@ -442,7 +459,7 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
     r[0] = r[1] = r[2] = 0;
     // software-pipelined: the column indices of a step are loaded one step ahead, so each step
     // issues its x gathers, the next step's indices and its values together and waits once
-    int64_t c[U];
+    int32_t c[U];     // int32 until used, so that no sign extension waits for the load
     if (t + U <= o1) {
 #pragma unroll
         for (int u = 0; u < U; ++u) c[u] = ci[(t + u) * WAVE + lane];
@@ -452,8 +469,8 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int k = 0; k < BC; ++k) xx[u][k] = x[c[u] * BC + k];
-        int64_t cn[U];
+            for (int k = 0; k < BC; ++k) xx[u][k] = x[(int64_t)c[u] * BC + k];
+        int32_t cn[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int64_t q = t + U + u < o1 ? t + U + u : o1 - 1;     // stays inside the slice
