@@ -864,16 +864,89 @@ __global__ void densify_k(int64_t nr, int b, const int32_t* __restrict__ rp, con
         for (int r = 0; r < b; ++r)
             for (int c = 0; c < b; ++c) M[(i * b + r) * n + (int64_t)ci[q] * b + c] = v[((int64_t)q * b + r) * b + c];
 }
-// one Gauss-Jordan exchange step on pivot k (src -> dst); after all n steps dst = A^-1 (SPD A)
-__global__ void gj_step_k(int64_t n, int64_t k, const double* __restrict__ src, double* __restrict__ dst) {
+// Gauss-Jordan exchange steps over all pivots in order turn A into A^-1 (no pivoting: the
+// coarsest Galerkin matrices here have nonsingular leading blocks; a zero or non-finite pivot
+// shows up as a non-finite entry, checked afterwards).
+// A panel of GJ_P consecutive pivots K = [k0, k0 + np) at once, by the block form of the exchange
+// step (equal in exact arithmetic to the np single steps in order): with W = M_KK^-1,
+//   out_KK = W,  out_KR = W M_KR,  out_RK = -M_RK W,  out_RR = M_RR - M_RK W M_KR.
+constexpr int GJ_P = 32;
+// W by single exchange steps in LDS (every workgroup, redundantly), then T = M_RK W for the
+// workgroup's rows (T is n x GJ_P); workgroup 0 also stores W
+__global__ void __launch_bounds__(256) gj_panel_t_k(int64_t n, int64_t k0, int np, const double* __restrict__ src,
+                                                    double* __restrict__ T, double* __restrict__ Wout) {
+    __shared__ double W[GJ_P][GJ_P + 1];
+    constexpr int PER = GJ_P * GJ_P / 256;     // entries of W per thread (compile-time: registers)
+    {
+        double w0[PER];     // all loads issued before the first is used (clamped, branch-free indices)
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            int e = threadIdx.x + 256 * c;
+            int ee = e < np * np ? e : 0;
+            w0[c] = src[(k0 + ee / np) * n + k0 + ee % np];
+        }
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            int e = threadIdx.x + 256 * c;
+            if (e < np * np) W[e / np][e % np] = w0[c];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < np; ++k) {
+        const double ip = 1.0 / W[k][k];
+        double upd[PER];
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            int e = threadIdx.x + 256 * c;
+            upd[c] = 0.0;
+            if (e < np * np) {
+                int i = e / np, j = e % np;
+                if (i == k) upd[c] = (j == k) ? ip : W[k][j] * ip;
+                else if (j == k) upd[c] = -W[i][k] * ip;
+                else upd[c] = W[i][j] - W[i][k] * W[k][j] * ip;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+            int e = threadIdx.x + 256 * c;
+            if (e < np * np) W[e / np][e % np] = upd[c];
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0)
+        for (int e = threadIdx.x; e < np * np; e += 256) Wout[e] = W[e / np][e % np];
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double r[GJ_P];     // the row's panel entries, loaded once (clamped, branch-free indices)
+#pragma unroll
+    for (int l = 0; l < GJ_P; ++l) r[l] = src[i * n + k0 + (l < np ? l : np - 1)];
+    for (int c = 0; c < np; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < GJ_P; ++l)
+            if (l < np) t += r[l] * W[l][c];
+        T[i * GJ_P + c] = t;
+    }
+}
+__global__ void gj_panel_apply_k(int64_t n, int64_t k0, int np, const double* __restrict__ src,
+                                 const double* __restrict__ T, const double* __restrict__ W, double* __restrict__ dst) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * n) return;
     int64_t i = idx / n, j = idx % n;
-    double p = src[k * n + k];
+    bool iK = i >= k0 && i < k0 + np, jK = j >= k0 && j < k0 + np;
     double out;
-    if (i == k) out = (j == k) ? 1.0 / p : src[k * n + j] / p;
-    else if (j == k) out = -src[i * n + k] / p;
-    else out = src[i * n + j] - src[i * n + k] * src[k * n + j] / p;
+    if (iK && jK) {
+        out = W[(i - k0) * np + (j - k0)];
+    } else if (iK) {
+        out = 0.0;
+        for (int l = 0; l < np; ++l) out += W[(i - k0) * np + l] * src[(k0 + l) * n + j];
+    } else if (jK) {
+        out = -T[i * GJ_P + (j - k0)];
+    } else {
+        out = src[idx];
+        for (int l = 0; l < np; ++l) out -= T[i * GJ_P + l] * src[(k0 + l) * n + j];
+    }
     dst[idx] = out;
 }
 __global__ void finite_k(int64_t n, const double* __restrict__ a, int* __restrict__ err) {
@@ -1044,11 +1117,17 @@ static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
     double* M1 = ar.make<double>(nc * nc + 1);
     zero_dev(M0, nc * nc * sizeof(double), s);
     if (C.A.nr) densify_k<<<cdiv(C.A.nr, 256), 256, 0, s>>>(C.A.nr, C.b, C.A.rp, C.A.ci, C.A.v, M0, nc);
-    for (int64_t kp = 0; kp < nc; ++kp) {
-        gj_step_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc, kp, M0, M1);
+    double* T = ar.make<double>(nc * GJ_P + 1);
+    double* W = ar.make<double>(GJ_P * GJ_P);
+    for (int64_t k0 = 0; k0 < nc; k0 += GJ_P) {
+        int np = (int)std::min<int64_t>(GJ_P, nc - k0);
+        gj_panel_t_k<<<cdiv(nc, 256), 256, 0, s>>>(nc, k0, np, M0, T, W);
+        gj_panel_apply_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc, k0, np, M0, T, W, M1);
         std::swap(M0, M1);
     }
     check_launch("coarse inverse");
+    ar.free(T);
+    ar.free(W);
     zero_dev(err, sizeof(int), s);
     if (nc) finite_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc * nc, M0, err);
     int he = 0;
