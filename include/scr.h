@@ -73,7 +73,11 @@ typedef struct {
 /* Smoothed-aggregation AMG options (the paper uses BoomerAMG, Sec. 5.2 table of settings;
  * these are the SA replacements).  Defaults from scr_default_amg_opts. */
 typedef struct {
-    int precision;             /* SCR_FP64: hierarchy and V-cycle in FP64; SCR_MIXED: FP32 */
+    int precision;             /* SCR_FP64: everything in FP64.  SCR_MIXED: hierarchy values and
+                                  V-cycles in FP32 (coarsest solve FP64), and Algorithm 2's inner A
+                                  solve on FP32 vectors with the FP32 level-0 copy of A (dot products
+                                  accumulated in FP64); the outer FGMRES, K, the A- and S-level solves
+                                  of Algorithm 1 and every true residual stay FP64 */
     double theta;              /* strength threshold at level 0 (halved per level), 0.08 */
     int smoother;              /* scr_smoother, default Chebyshev */
     int cheb_degree;           /* 2 */

@@ -1055,6 +1055,16 @@ class HierT : public Hierarchy {
         smooth(l, q, b, q.w, x, s);
     }
 
+    void vcycle_f(const float* x, float* y, hipStream_t s) override {
+        if (!std::is_same<T, float>::value) throw Error(SCR_E_INVALID, "FP32 V-cycle on an FP64 hierarchy");
+        ++vcycles;
+        cycle(0, (const T*)x, (T*)y, s);
+    }
+    const DSell<float>* level0_f() const override {
+        if (!std::is_same<T, float>::value || S.size() < 2) return nullptr;
+        return (const DSell<float>*)&S[0].A;
+    }
+
     void vcycle(const double* x, double* y, hipStream_t s) override {
         ++vcycles;
         int64_t n = n0();

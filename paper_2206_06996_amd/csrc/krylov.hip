@@ -68,9 +68,7 @@ void Reducer::init(int64_t n_, Arena& ar, hipStream_t s) {
     int64_t g = cdiv(n, 4 * RTPB);
     grid = (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
     partials = ar.make<double>((size_t)grid * RMAXJ);
-    counter = ar.make<unsigned>(1);
     out = ar.make<double>(RMAXJ);
-    zero_dev(counter, sizeof(unsigned), s);
 }
 
 template <int J>
@@ -124,12 +122,20 @@ __device__ __forceinline__ void final_sums(const double* __restrict__ partials, 
     __syncthreads();
 }
 
-// ------------------------------------------------------------------ plain dot
-__global__ void __launch_bounds__(RTPB) dot_part_k(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+// ------------------------------------------------------------------ plain dot (FP64 accumulation)
+template <typename T>
+__global__ void __launch_bounds__(RTPB) dot_part_k(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
                                                    double* __restrict__ partials) {
     double acc[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) acc[0] += x[i] * y[i];
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB)
+        acc[0] += (double)x[i] * (double)y[i];
     block_partials<1>(acc, 1, partials);
+}
+// y = a x + b y in FP64, rounded to T
+template <typename T>
+__global__ void axpby_t_k(int64_t n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
 }
 template <int J>
 __global__ void __launch_bounds__(RTPB) sum_k(const double* __restrict__ partials, int nblk, int jn, double* __restrict__ out) {
@@ -169,13 +175,16 @@ __global__ void __launch_bounds__(RTPB) sum_pub_k(const double* __restrict__ par
     if (threadIdx.x == 0) publish(hslot, out, 1, seq);
 }
 
-double device_norm(const double* x, int64_t n, Reducer& red, StatusSlot& slot, hipStream_t s) {
+template <typename T>
+double device_norm(const T* x, int64_t n, Reducer& red, StatusSlot& slot, hipStream_t s) {
     dot_part_k<<<red.grid, RTPB, 0, s>>>(n, x, x, red.partials);
     sum_pub_k<<<1, RTPB, 0, s>>>(red.partials, red.grid, red.out, slot.d, slot.next());
     check_launch("dot");
     slot.wait(s);
     return std::sqrt(slot.h[0]);
 }
+template double device_norm<double>(const double*, int64_t, Reducer&, StatusSlot&, hipStream_t);
+template double device_norm<float>(const float*, int64_t, Reducer&, StatusSlot&, hipStream_t);
 
 // ------------------------------------------------------------------ GMRES kernels
 // state layout (doubles): H[(m+1)*m] | cs[m] | sn[m] | g[m+1] | y[m] | h1[64] | h2[64] | scal[8]
@@ -213,16 +222,17 @@ __global__ void __launch_bounds__(RTPB) gm_init_fin_k(const double* __restrict__
     }
 }
 
-__global__ void scale_by_k(int64_t n, double* __restrict__ v, const double* __restrict__ s) {
+template <typename T>
+__global__ void scale_by_k(int64_t n, T* __restrict__ v, const double* __restrict__ s) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double f = *s;
-    if (i < n) v[i] *= f;
+    if (i < n) v[i] = (T)((double)v[i] * f);
 }
 
 // partials of V_i . w  (i < jn)
-template <int J>
-__global__ void __launch_bounds__(RTPB) mdot_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
-                                               const double* __restrict__ w, double* __restrict__ partials) {
+template <int J, typename T>
+__global__ void __launch_bounds__(RTPB) mdot_k(int64_t n, int jn, const T* __restrict__ V, int64_t ld,
+                                               const T* __restrict__ w, double* __restrict__ partials) {
     double acc[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) acc[j] = 0.0;
@@ -230,15 +240,15 @@ __global__ void __launch_bounds__(RTPB) mdot_k(int64_t n, int jn, const double* 
         double we = w[e];
 #pragma unroll
         for (int j = 0; j < J; ++j)
-            if (j < jn) acc[j] += V[j * ld + e] * we;
+            if (j < jn) acc[j] += (double)V[j * ld + e] * we;
     }
     block_partials<J>(acc, jn, partials);
 }
 
 // w -= sum_i h_i V_i ;  partials of V_i . w
-template <int J>
-__global__ void __launch_bounds__(RTPB) upd_dot_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
-                                                  double* __restrict__ w, const double* __restrict__ h,
+template <int J, typename T>
+__global__ void __launch_bounds__(RTPB) upd_dot_k(int64_t n, int jn, const T* __restrict__ V, int64_t ld,
+                                                  T* __restrict__ w, const double* __restrict__ h,
                                                   double* __restrict__ partials) {
     __shared__ double hs[J];
     for (int j = threadIdx.x; j < jn; j += RTPB) hs[j] = h[j];
@@ -255,18 +265,19 @@ __global__ void __launch_bounds__(RTPB) upd_dot_k(int64_t n, int jn, const doubl
                 v[j] = V[j * ld + e];
                 we -= hs[j] * v[j];
             }
-        w[e] = we;
+        const T wr = (T)we;     // the stored value enters the dot products
+        w[e] = wr;
 #pragma unroll
         for (int j = 0; j < J; ++j)
-            if (j < jn) acc[j] += v[j] * we;
+            if (j < jn) acc[j] += v[j] * (double)wr;
     }
     block_partials<J>(acc, jn, partials);
 }
 
 // w -= sum_i h2_i V_i ; partials of ||w||^2
-template <int J>
-__global__ void __launch_bounds__(RTPB) upd_norm_k(int64_t n, int jn, const double* __restrict__ V, int64_t ld,
-                                                   double* __restrict__ w, const double* __restrict__ h2,
+template <int J, typename T>
+__global__ void __launch_bounds__(RTPB) upd_norm_k(int64_t n, int jn, const T* __restrict__ V, int64_t ld,
+                                                   T* __restrict__ w, const double* __restrict__ h2,
                                                    double* __restrict__ partials) {
     __shared__ double hs[J];
     for (int t = threadIdx.x; t < jn; t += RTPB) hs[t] = h2[t];
@@ -276,9 +287,10 @@ __global__ void __launch_bounds__(RTPB) upd_norm_k(int64_t n, int jn, const doub
         double we = w[e];
 #pragma unroll
         for (int t = 0; t < J; ++t)
-            if (t < jn) we -= hs[t] * V[t * ld + e];
-        w[e] = we;
-        acc[0] += we * we;
+            if (t < jn) we -= hs[t] * (double)V[t * ld + e];
+        const T wr = (T)we;
+        w[e] = wr;
+        acc[0] += (double)wr * (double)wr;
     }
     block_partials<1>(acc, 1, partials);
 }
@@ -336,16 +348,17 @@ __global__ void ysolve_k(double* __restrict__ st, int m, int j) {
 }
 
 // x += sum_i y_i Z_i
-__global__ void __launch_bounds__(RTPB) maxpy_k(int64_t n, int jn, const double* __restrict__ Z, int64_t ld,
-                                                const double* __restrict__ y, double* __restrict__ x) {
+template <typename T>
+__global__ void __launch_bounds__(RTPB) maxpy_k(int64_t n, int jn, const T* __restrict__ Z, int64_t ld,
+                                                const double* __restrict__ y, T* __restrict__ x) {
     __shared__ double ys[RMAXJ];
     for (int j = threadIdx.x; j < jn; j += RTPB) ys[j] = y[j];
     __syncthreads();
     int64_t e = (int64_t)blockIdx.x * RTPB + threadIdx.x;
     if (e >= n) return;
     double xe = x[e];
-    for (int j = 0; j < jn; ++j) xe += ys[j] * Z[j * ld + e];
-    x[e] = xe;
+    for (int j = 0; j < jn; ++j) xe += ys[j] * (double)Z[j * ld + e];
+    x[e] = (T)xe;
 }
 
 #define JDISPATCH(jn, KERNEL, ...)                                         \
@@ -357,10 +370,11 @@ __global__ void __launch_bounds__(RTPB) maxpy_k(int64_t n, int jn, const double*
         else KERNEL<64>__VA_ARGS__;                                        \
     } while (0)
 
-Gmres::Gmres(int64_t n, int m, Arena& ar, hipStream_t s) : n_(n), m_(m), ar_(&ar) {
+template <typename T>
+GmresT<T>::GmresT(int64_t n, int m, Arena& ar, hipStream_t s) : n_(n), m_(m), ar_(&ar) {
     if (m < 1 || m > 63) throw Error(SCR_E_INVALID, "restart length must be in [1, 63]");
-    V_ = ar.make<double>((size_t)(m + 1) * n);
-    Z_ = ar.make<double>((size_t)m * n);
+    V_ = ar.make<T>((size_t)(m + 1) * n);
+    Z_ = ar.make<T>((size_t)m * n);
     GLay L{m};
     st_ = ar.make<double>(L.size());
     red_.init(n, ar, s);
@@ -368,14 +382,16 @@ Gmres::Gmres(int64_t n, int m, Arena& ar, hipStream_t s) : n_(n), m_(m), ar_(&ar
     slot_.d = PinnedPool::device_ptr(slot_.h);
     slot_.h[15] = 0.0;
 }
-Gmres::~Gmres() {
+template <typename T>
+GmresT<T>::~GmresT() {
     if (slot_.h) ar_->ctx()->pinned.put(slot_.h);
     ar_->free(V_); ar_->free(Z_); ar_->free(st_);
     red_.release(*ar_);
 }
 
-KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool use_x0, bool check_true,
-                   hipStream_t s) {
+template <typename T>
+KStat GmresT<T>::solve(OpT<T>& A, OpT<T>& M, const T* b, T* x, double tol, int maxit, bool use_x0, bool check_true,
+                       hipStream_t s) {
     KStat st;
     const int64_t n = n_;
     const int m = m_;
@@ -383,7 +399,7 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
     double* part = red_.partials;
     GLay L{m};
     double bn = device_norm(b, n, red_, slot_, s);
-    if (!use_x0 || bn == 0.0) zero_dev(x, n * sizeof(double), s);
+    if (!use_x0 || bn == 0.0) zero_dev(x, n * sizeof(T), s);
     if (bn == 0.0) {
         st.converged = true;
         return st;
@@ -393,15 +409,15 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
     double est = INFINITY;
     int64_t nblk = cdiv(n, 256);
     for (;;) {
-        double* V0 = V_;
+        T* V0 = V_;
         if (first && !use_x0) {
-            copy_d(n, b, V0, s);
+            copy_dev(V0, b, n * sizeof(T), s);
         } else {
             A.apply(x, V0, s);
-            axpby(n, 1.0, b, -1.0, V0, s);
+            axpby_t_k<T><<<nblk, 256, 0, s>>>(n, 1.0, b, -1.0, V0);
         }
         first = false;
-        dot_part_k<<<G, RTPB, 0, s>>>(n, V0, V0, part);
+        dot_part_k<T><<<G, RTPB, 0, s>>>(n, V0, V0, part);
         gm_init_fin_k<<<1, RTPB, 0, s>>>(part, G, st_, m, slot_.d, slot_.next());
         check_launch("gm_init");
         slot_.wait(s);
@@ -415,9 +431,9 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
         scale_by_k<<<nblk, 256, 0, s>>>(n, V0, st_ + L.scal() + S_INV);
         int j = 0;
         while (j < m) {
-            double* Vj = V_ + (int64_t)j * n;
-            double* Zj = Z_ + (int64_t)j * n;
-            double* w = V_ + (int64_t)(j + 1) * n;
+            T* Vj = V_ + (int64_t)j * n;
+            T* Zj = Z_ + (int64_t)j * n;
+            T* w = V_ + (int64_t)(j + 1) * n;
             M.apply(Vj, Zj, s);
             A.apply(Zj, w, s);
             int jn = j + 1;
@@ -449,6 +465,9 @@ KStat Gmres::solve(Op& A, Op& M, const double* b, double* x, double tol, int max
     }
     return st;
 }
+
+template class GmresT<double>;
+template class GmresT<float>;
 
 // ------------------------------------------------------------------ CG kernels
 enum { C_RZ = 0, C_ALPHA = 1, C_BETA = 2, C_RN2 = 3, C_PQ = 4 };

@@ -26,6 +26,9 @@ struct scr_handle {
     double* dvec = nullptr;                       // the diagonal d used in S^ (3n)
     std::unique_ptr<Hierarchy> hA, hS, hL;
     std::unique_ptr<Gmres> gOuter, gA, gS;
+    // mixed precision: Algorithm 2's inner A solve on FP32 vectors (FP32 A of the hierarchy)
+    std::unique_ptr<GmresT<float>> gA32;
+    float *xbar32 = nullptr, *xtil32 = nullptr;
     std::unique_ptr<Pcg> cg;
     int restart = 0, restart_inner = 0;
     double *bs = nullptr, *xs = nullptr, *yhat = nullptr, *tv = nullptr, *tp = nullptr, *xbar = nullptr,
@@ -46,15 +49,16 @@ namespace {
 
 // s_k = m_k * (a_k . x_v): one workgroup per outlet, its entries strided over the threads and the
 // partial sums added by a fixed LDS tree
+template <typename T>
 __global__ void __launch_bounds__(256) outlet_dot_k(const int64_t* __restrict__ off, const int32_t* __restrict__ blk,
                                                     const double* __restrict__ a, const double* __restrict__ m,
-                                                    const double* __restrict__ x, double* __restrict__ sk) {
+                                                    const T* __restrict__ x, double* __restrict__ sk) {
     __shared__ double red[256];
     const int k = blockIdx.x;
     double acc = 0.0;
     for (int64_t e = off[k] + threadIdx.x; e < off[k + 1]; e += 256) {
         const int64_t b = blk[e];
-        acc += a[3 * e] * x[3 * b] + a[3 * e + 1] * x[3 * b + 1] + a[3 * e + 2] * x[3 * b + 2];
+        acc += a[3 * e] * (double)x[3 * b] + a[3 * e + 1] * (double)x[3 * b + 1] + a[3 * e + 2] * (double)x[3 * b + 2];
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -65,20 +69,22 @@ __global__ void __launch_bounds__(256) outlet_dot_k(const int64_t* __restrict__ 
     if (threadIdx.x == 0) sk[k] = m[k] * red[0];
 }
 // y_v += s_k a_k (block rows are distinct across all outlets, so entries never collide)
+template <typename T>
 __global__ void outlet_axpy_k(int64_t ne, const int32_t* __restrict__ blk, const int32_t* __restrict__ id,
-                              const double* __restrict__ a, const double* __restrict__ sk, double* __restrict__ y) {
+                              const double* __restrict__ a, const double* __restrict__ sk, T* __restrict__ y) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     const double c = sk[id[e]];
     const int64_t b = blk[e];
-    for (int i = 0; i < 3; ++i) y[3 * b + i] += c * a[3 * e + i];
+    for (int i = 0; i < 3; ++i) y[3 * b + i] = (T)((double)y[3 * b + i] + c * a[3 * e + i]);
 }
 
 // y_v += sum_k m_k a_k (a_k . x_v) on velocity vectors (node-interleaved, 3 per block row)
-void apply_outlets(const scr_handle* h, const double* xv, double* yv, hipStream_t s) {
+template <typename T>
+void apply_outlets(const scr_handle* h, const T* xv, T* yv, hipStream_t s) {
     if (h->n_out == 0) return;
-    outlet_dot_k<<<h->n_out, 256, 0, s>>>(h->out_off, h->out_blk, h->out_a, h->out_m, xv, h->out_s);
-    outlet_axpy_k<<<cdiv(h->n_oe, 256), 256, 0, s>>>(h->n_oe, h->out_blk, h->out_id, h->out_a, h->out_s, yv);
+    outlet_dot_k<T><<<h->n_out, 256, 0, s>>>(h->out_off, h->out_blk, h->out_a, h->out_m, xv, h->out_s);
+    outlet_axpy_k<T><<<cdiv(h->n_oe, 256), 256, 0, s>>>(h->n_oe, h->out_blk, h->out_id, h->out_a, h->out_s, yv);
     check_launch("outlets");
 }
 
@@ -105,6 +111,24 @@ struct AOp : Op {
         apply_outlets(h, x, y, s);
     }
 };
+// the same on FP32 vectors, with the FP32 copy of A that level 0 of the mixed hierarchy holds
+struct AOp32 : OpT<float> {
+    const scr_handle* h;
+    explicit AOp32(const scr_handle* hh) : h(hh) {}
+    void apply(const float* x, float* y, hipStream_t s) override {
+        sell_mv<float>(*h->hA->level0_f(), x, nullptr, y, 0, s);
+        apply_outlets(h, x, y, s);
+    }
+};
+struct VOp32 : OpT<float> {
+    Hierarchy* H;
+    int64_t* count;
+    VOp32(Hierarchy* hh, int64_t* c) : H(hh), count(c) {}
+    void apply(const float* x, float* y, hipStream_t s) override {
+        H->vcycle_f(x, y, s);
+        ++*count;
+    }
+};
 struct VOp : Op {
     Hierarchy* H;
     int64_t* count;
@@ -121,9 +145,20 @@ struct SchurOp : Op {
     explicit SchurOp(scr_handle* hh) : h(hh) {}
     void apply(const double* xp, double* y, hipStream_t s) override {
         sell_mv<double>(h->Gs, xp, nullptr, h->xbar, 0, s);
-        AOp aop(h);
-        VOp pa(h->hA.get(), &h->st.vcycles_A);
-        KStat k = h->gA->solve(aop, pa, h->xbar, h->xtil, h->so.tol_I, h->so.max_it_I, false, false, s);
+        KStat k;
+        if (h->gA32) {
+            // mixed precision: the inner solve to delta_I on FP32 vectors, FP32 A and V-cycle
+            const int64_t n3 = 3 * h->nb;
+            cast_d2f(h->xbar, h->xbar32, n3, s);
+            AOp32 aop(h);
+            VOp32 pa(h->hA.get(), &h->st.vcycles_A);
+            k = h->gA32->solve(aop, pa, h->xbar32, h->xtil32, h->so.tol_I, h->so.max_it_I, false, false, s);
+            cast_f2d(h->xtil32, h->xtil, n3, s);
+        } else {
+            AOp aop(h);
+            VOp pa(h->hA.get(), &h->st.vcycles_A);
+            k = h->gA->solve(aop, pa, h->xbar, h->xtil, h->so.tol_I, h->so.max_it_I, false, false, s);
+        }
         h->st.calls_I++;
         h->st.its_I += k.iters;
         sell_mv<double>(h->Cs, xp, nullptr, y, 0, s);
@@ -217,7 +252,14 @@ void ensure_workspaces(scr_handle* h, const scr_solve_opts& o, hipStream_t s) {
         if (!h->gA || h->restart_inner != o.restart_inner) {
             h->gA.reset(new Gmres(3 * h->nb, o.restart_inner, *h->ar, s));
             h->gS.reset(new Gmres(h->nb, o.restart_inner, *h->ar, s));
+            h->gA32.reset();
+            if (h->opts.precision == SCR_MIXED && h->hA->level0_f())
+                h->gA32.reset(new GmresT<float>(3 * h->nb, o.restart_inner, *h->ar, s));
             h->restart_inner = o.restart_inner;
+        }
+        if (h->gA32 && !h->xbar32) {
+            h->xbar32 = h->ar->make<float>(3 * h->nb);
+            h->xtil32 = h->ar->make<float>(3 * h->nb);
         }
     } else if (!h->cg) {
         h->cg.reset(new Pcg(h->nb, *h->ar, s));
@@ -441,7 +483,7 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         return SCR_OK;
     } catch (const Error& e) {
         if (h) {
-            h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->cg.reset();
+            h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->gA32.reset(); h->cg.reset();
             (void)hipStreamSynchronize(s);
             h->ar.reset();
             (void)hipStreamSynchronize(s);
@@ -594,7 +636,7 @@ scr_status scr_handle_destroy(scr_handle* h) {
     if (!h) return SCR_OK;
     try {
         hipStream_t s = h->ar ? h->ar->stream() : nullptr;
-        h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->cg.reset();
+        h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->gA32.reset(); h->cg.reset();
         h->hA.reset(); h->hS.reset(); h->hL.reset();
         h->ar.reset();
         (void)hipStreamSynchronize(s);

@@ -6,11 +6,14 @@
 
 namespace scr {
 
-// A linear operator or preconditioner on FP64 device vectors.
-struct Op {
-    virtual void apply(const double* x, double* y, hipStream_t s) = 0;
-    virtual ~Op() = default;
+// A linear operator or preconditioner on device vectors of T (FP64, or FP32 for the mixed
+// precision inner solves).
+template <typename T>
+struct OpT {
+    virtual void apply(const T* x, T* y, hipStream_t s) = 0;
+    virtual ~OpT() = default;
 };
+using Op = OpT<double>;
 
 struct KStat {
     int64_t iters = 0;
@@ -18,18 +21,17 @@ struct KStat {
     bool converged = false;
 };
 
-// Deterministic FP64 reductions: a fixed grid per vector length, per-block partials summed in
-// block order by the last block to finish.
+// Deterministic FP64 reductions: a fixed grid per vector length, per-block partials summed in a
+// fixed order by a one-block kernel.
 struct Reducer {
     int64_t n = 0;
     int grid = 0;
     double* partials = nullptr;      // grid * 64
-    unsigned* counter = nullptr;
     double* out = nullptr;           // 64 results
     void init(int64_t n_, Arena& ar, hipStream_t s);
     void release(Arena& ar) {
-        ar.free(partials); ar.free(counter); ar.free(out);
-        partials = nullptr; counter = nullptr; out = nullptr;
+        ar.free(partials); ar.free(out);
+        partials = nullptr; out = nullptr;
     }
 };
 
@@ -44,13 +46,15 @@ struct StatusSlot {
 };
 
 // Right-preconditioned flexible GMRES(m) (Saad 1993) with CGS2 Arnoldi; the Hessenberg matrix,
-// Givens rotations and least-squares solve stay in device memory; the host reads one residual
-// estimate per iteration.
-class Gmres {
+// Givens rotations and least-squares solve stay in device memory (FP64); the host reads one
+// residual estimate per iteration.  The Krylov vectors are T; every dot product and vector update
+// is computed in FP64 and rounded to T when stored.
+template <typename T>
+class GmresT {
    public:
-    Gmres(int64_t n, int m, Arena& ar, hipStream_t s);
-    ~Gmres();
-    KStat solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool use_x0, bool check_true,
+    GmresT(int64_t n, int m, Arena& ar, hipStream_t s);
+    ~GmresT();
+    KStat solve(OpT<T>& A, OpT<T>& M, const T* b, T* x, double tol, int maxit, bool use_x0, bool check_true,
                 hipStream_t s);
     int64_t n() const { return n_; }
 
@@ -58,10 +62,12 @@ class Gmres {
     int64_t n_;
     int m_;
     Arena* ar_;
-    double *V_, *Z_, *st_;
+    T *V_, *Z_;
+    double* st_;
     Reducer red_;
     StatusSlot slot_;
 };
+using Gmres = GmresT<double>;
 
 // Preconditioned CG, or flexible CG with the Polak-Ribiere beta (Notay 2000).
 class Pcg {
@@ -78,7 +84,8 @@ class Pcg {
     StatusSlot slot_;
 };
 
-double device_norm(const double* x, int64_t n, Reducer& red, StatusSlot& slot, hipStream_t s);
+template <typename T>
+double device_norm(const T* x, int64_t n, Reducer& red, StatusSlot& slot, hipStream_t s);
 
 // ---------------------------------------------------------------- AMG (amg.hip)
 struct LevelSetup {
@@ -103,6 +110,10 @@ class Hierarchy {
     virtual void vcycle(const double* x, double* y, hipStream_t s) = 0;
     // rebuild the solve-phase copies (sliced ELL in T, D^-1, smoothing coefficients) from L
     virtual void refresh(Arena& ar, hipStream_t s) = 0;
+    // FP32 hierarchies: the V-cycle on FP32 vectors (no conversions), and the FP32 sliced-ELL copy
+    // of the level-0 matrix (nullptr when the hierarchy is FP64 or has a single level)
+    virtual void vcycle_f(const float* x, float* y, hipStream_t s) = 0;
+    virtual const DSell<float>* level0_f() const = 0;
     std::vector<LevelSetup> L;
     double* cinv = nullptr;          // dense inverse of the coarsest matrix (FP64)
     int64_t ncoarse = 0;
