@@ -85,7 +85,7 @@ void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, 
 // ====================================================================== generic SpGEMM (one wave per row)
 constexpr int HS_MAX = 8192;       // largest LDS hash table per row
 constexpr int HMAX = HS_MAX / 2;   // unique columns allowed per row
-constexpr int HS_COUNT = 2048;     // hash table of the counting pass (retried with HS_MAX on overflow)
+constexpr int HS_COUNT = 2048;     // first hash table of the counting pass (x4 on each overflow)
 
 // returns 1 if newly inserted (table of hs slots, hs a power of two, never more than half full)
 __device__ __forceinline__ int hash_insert(int* t, int hs, int key) {
@@ -131,18 +131,44 @@ __global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const i
     for (int t = lane; t < hs; t += WAVE) table[t] = -1;
     if (lane == 0) nuniq = 0;
     __syncthreads();
-    for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) {
-        int32_t k = xci[q];
-        for (int32_t t = yrp[k] + lane; t < yrp[k + 1]; t += WAVE) {
+    // The candidates (X entry q, Y entry t) of up to 64 X entries at a time are spread over all
+    // lanes: lane l holds the Y row of X entry q0 + l, an inclusive prefix of their lengths maps a
+    // candidate number to its (l, t) by a binary search over the prefix (every lane takes part in
+    // the shuffles).  Only a set is built here, so the order of insertion does not matter.
+    const int32_t x0 = xrp[i], x1 = xrp[i + 1];
+    for (int32_t q0 = x0; q0 < x1; q0 += WAVE) {
+        int st = 0, len = 0;
+        if (q0 + lane < x1) {
+            int32_t k = xci[q0 + lane];
+            st = yrp[k];
+            len = yrp[k + 1] - st;
+        }
+        int incl = len;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            int v = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += v;
+        }
+        const int total = __shfl(incl, WAVE - 1, WAVE);
+        for (int base = 0; base < total; base += WAVE) {
             if (nuniq >= hmax) break;
-            int c = yci[t];
-            if (hash_insert(table, hs, c)) {
-                int pos = atomicAdd(&nuniq, 1);
-                if (pos < hmax + WAVE) list[pos] = c;
+            const int cidx = base + lane;
+            int l = 0;     // number of lanes whose inclusive prefix is <= cidx
+            for (int step = WAVE / 2; step > 0; step >>= 1) {
+                int v = __shfl(incl, l + step - 1, WAVE);
+                if (v <= cidx) l += step;
+            }
+            const int stl = __shfl(st, l, WAVE);
+            const int excl = __shfl(incl, l, WAVE) - __shfl(len, l, WAVE);
+            if (cidx < total) {
+                int c = yci[stl + (cidx - excl)];
+                if (hash_insert(table, hs, c)) {
+                    int pos = atomicAdd(&nuniq, 1);
+                    if (pos < hmax + WAVE) list[pos] = c;
+                }
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
     int w = nuniq;
     if (w >= hmax) {
         if (lane == 0) atomicOr(overflow, 1);
@@ -305,7 +331,8 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
     HIPCHK(hipStreamSynchronize(s));
     // hash table of the counting pass: twice the candidate bound, but at most HS_COUNT slots (the
     // unique columns of a row are far fewer than its candidates); a row that overflows it makes
-    // the pass run again with the largest table.  The result does not depend on the table size.
+    // the pass run again with a table four times larger.  The result does not depend on the table
+    // size.
     int need = 2 * (hflags[1] < HMAX ? hflags[1] : HMAX) + 2;
     int hs = 64;
     while (hs < need && hs < HS_COUNT) hs <<= 1;
@@ -320,7 +347,7 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
         HIPCHK(hipStreamSynchronize(s));
         if (!hf[0]) break;
         if (hs >= HS_MAX) throw Error(SCR_E_INVALID, "Galerkin product row wider than " + std::to_string(HMAX) + " blocks");
-        hs = HS_MAX;
+        hs = std::min(4 * hs, HS_MAX);
         zero_dev(flags, sizeof(int), s);
     }
     C.nnzb = scan_i32(cnt, C.rp, X.nr, ar, s);
