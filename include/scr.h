@@ -245,7 +245,9 @@ scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const sc
  * free up, and their kernels overlap on the device.  A request whose footprint alone exceeds the
  * budget is rejected (SCR_E_OOM), never queued forever.  Each request builds its hierarchies
  * once (amg_setup) and reuses them for its n_rhs successive corrections (the multi-corrector
- * loop of Sec. 3.5 with a frozen tangent), and for its mesh-motion solves when L is given.
+ * loop of Sec. 3.5), and for its mesh-motion solves when L is given.  The tangent is frozen
+ * unless the request gives new values for a correction: then the hierarchies are re-set up
+ * numerically (amg_update) before that correction's solve.
  * All device arrays of a request are borrowed until srv_wait/srv_poll reports it done. */
 typedef struct scr_server scr_server;
 
@@ -258,6 +260,10 @@ typedef struct {
     const scr_bsr* L;              /* optional mesh Laplacian (NULL = none) */
     const double* const* bm;       /* n_rhs device pointers (n_L x 3 each), if L */
     double* const* xm;             /* n_rhs device pointers (outputs), if L */
+    const double* const* vals;     /* NULL (frozen tangent), or n_rhs device pointers: vals[c]
+                                      (c >= 1; NULL keeps the previous values) are the K values of
+                                      correction c on K's pattern (nnzb * 16 each); vals[0] is
+                                      ignored (K.val is the first correction's matrix) */
 } scr_request;
 
 typedef struct {
@@ -265,7 +271,7 @@ typedef struct {
     int64_t n_solves;
     double latency_ms;             /* submit -> last correction done */
     double queue_ms;               /* submit -> admission */
-    double setup_ms, solve_ms;     /* summed over the request */
+    double setup_ms, solve_ms;     /* summed over the request (setup_ms includes re-setups) */
     int64_t footprint;             /* admission estimate (bytes) */
     int64_t device_bytes;          /* measured peak of the request's handle(s) */
     scr_stats last;                /* stats of the last SCR solve */

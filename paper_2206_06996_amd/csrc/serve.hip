@@ -5,7 +5,8 @@
 // fits next to the requests already running; requests that arrive meanwhile wait in order and
 // start as soon as a finishing request releases its slot and memory.  Kernels of different
 // requests overlap on the device through the slots' streams.  Each request builds its
-// hierarchies once and reuses them for all of its successive corrections.
+// hierarchies once and reuses them for all of its successive corrections, re-set up numerically
+// when a correction brings new matrix values.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -23,7 +24,7 @@ struct Job {
     int64_t id = 0;
     scr_bsr K{};
     const double* coords = nullptr;
-    std::vector<const double*> b, bm;
+    std::vector<const double*> b, bm, vals;
     std::vector<double*> x, xm;
     bool has_L = false;
     scr_bsr L{};
@@ -69,6 +70,18 @@ void run_job(scr_server* S, Job* j, hipStream_t st) {
         r.device_bytes = scr_handle_bytes(h) + (hm ? scr_handle_bytes(hm) : 0);
         auto t1 = Clock::now();
         for (size_t c = 0; c < j->b.size(); ++c) {
+            if (c > 0 && !j->vals.empty() && j->vals[c]) {
+                // a new tangent for this correction: numeric re-setup on the same pattern
+                auto tu = Clock::now();
+                scr_bsr Kc = j->K;
+                Kc.val = j->vals[c];
+                scr_status ru = amg_update(h, &Kc, nullptr, st);
+                r.setup_ms += std::chrono::duration<double, std::milli>(Clock::now() - tu).count();
+                if (ru != SCR_OK) {
+                    r.status = ru;
+                    break;
+                }
+            }
             scr_stats stt{};
             scr_status rs = scr_solve(h, j->b[c], j->x[c], &S->solve, st, &stt);
             r.last = stt;
@@ -181,6 +194,7 @@ scr_status srv_submit(scr_server* S, const scr_request* r, int64_t* id) {
         j->b.push_back(r->b[c]);
         j->x.push_back(r->x[c]);
         if (r->L) { j->bm.push_back(r->bm[c]); j->xm.push_back(r->xm[c]); }
+        if (r->vals) j->vals.push_back(r->vals[c]);
     }
     if (r->L) { j->has_L = true; j->L = *r->L; }
     j->footprint = scr_footprint_estimate(SCR_SYSTEM, r->K.n_brows, r->K.nnzb, &S->amg, &S->solve);

@@ -73,7 +73,7 @@ class Stats(C.Structure):
 
 class ScrRequest(C.Structure):
     _fields_ = [("K", ScrBsr), ("coords", P), ("n_rhs", C.c_int), ("b", C.POINTER(P)), ("x", C.POINTER(P)),
-                ("L", C.POINTER(ScrBsr)), ("bm", C.POINTER(P)), ("xm", C.POINTER(P))]
+                ("L", C.POINTER(ScrBsr)), ("bm", C.POINTER(P)), ("xm", C.POINTER(P)), ("vals", C.POINTER(P))]
 
 
 class SrvResult(C.Structure):
@@ -349,9 +349,11 @@ class Server:
         _check(lib().srv_create(ctx.ptr, max_slots, hbm_budget, C.byref(amg) if amg else None,
                                 C.byref(solve) if solve else None, C.byref(self.ptr)))
 
-    def submit(self, K, coords, bs, xs, L=None, bms=None, xms=None) -> int:
+    def submit(self, K, coords, bs, xs, L=None, bms=None, xms=None, vals=None) -> int:
         """K = (row_ptr, col_idx, val) tensors of the 4x4 system; bs/xs lists of RHS/output tensors;
-        L = (row_ptr, col_idx, val) of the mesh Laplacian with bms/xms lists (optional)."""
+        L = (row_ptr, col_idx, val) of the mesh Laplacian with bms/xms lists (optional); vals = a
+        list with one entry per correction: None (keep the previous tangent) or the K values of
+        that correction on K's pattern (the first entry is ignored)."""
         import torch
         n = len(bs)
         barr = (P * n)(*[_dev(b, torch.float64, "b") for b in bs])
@@ -364,6 +366,11 @@ class Server:
             xmarr = (P * n)(*[_dev(x, torch.float64, "xm") for x in xms])
             req.L = C.pointer(Lb); req.bm = bmarr; req.xm = xmarr
             keep += [L, bms, xms, Lb, bmarr, xmarr]
+        if vals is not None:
+            varr = (P * n)(*[None if (v is None or c == 0) else _dev(v, torch.float64, "vals")
+                             for c, v in enumerate(vals)])
+            req.vals = varr
+            keep += [vals, varr]
         rid = C.c_int64()
         _check(lib().srv_submit(self.ptr, C.byref(req), C.byref(rid)))
         self._keep[rid.value] = keep

@@ -134,3 +134,43 @@ def test_failing_request_is_isolated(scr, systems):
     srv.destroy()
     assert ctx.bytes_in_use() == 0
     ctx.destroy()
+
+
+def test_new_tangent_per_correction_matches_sequential_re_setups(scr):
+    # three corrections whose tangents change (dt = 1e-3, 2e-3, 4e-3 on one mesh): the server's
+    # numeric re-setups give bitwise what setup -> solve -> amg_update -> solve on one handle gives
+    p = synth.cfg0_params()
+    mats = []
+    for dt in (1e-3, 2e-3, 4e-3):
+        p.dt = dt
+        mats.append(synth.generate(p))
+    s0 = mats[0]
+    assert all(np.array_equal(m.rp, s0.rp) and np.array_equal(m.ci, s0.ci) for m in mats)
+    K = (dev(s0.rp), dev(s0.ci), dev(s0.val.reshape(-1)))
+    coords = dev(s0.xyz.reshape(-1))
+    bs = [dev(synth.rhs(700 + c, 4 * s0.n_b, s0.mask)) for c in range(3)]
+    ctx = scr.Context(0)
+    h = scr.amg_setup(ctx, scr.SCR_SYSTEM, *K, coords)
+    ref = []
+    for c in range(3):
+        if c:
+            scr.amg_update(h, K[0], K[1], dev(mats[c].val.reshape(-1)))
+        x = torch.zeros_like(bs[c])
+        rc, _ = scr.scr_solve(h, bs[c], x)
+        assert rc == 0
+        ref.append(x.cpu().numpy())
+    h.destroy()
+    srv = scr.Server(ctx, max_slots=2)
+    xs = [torch.full_like(b, np.nan) for b in bs]
+    xf = [torch.full_like(b, np.nan) for b in bs]
+    i_new = srv.submit(K, coords, bs, xs, vals=[None] + [dev(m.val.reshape(-1)) for m in mats[1:]])
+    i_frozen = srv.submit(K, coords, bs, xf)
+    rn, rf = srv.wait(i_new), srv.wait(i_frozen)
+    assert rn["status"] == 0 and rf["status"] == 0 and rn["n_solves"] == 3
+    for c in range(3):
+        assert np.array_equal(xs[c].cpu().numpy(), ref[c])
+    assert np.array_equal(xf[0].cpu().numpy(), ref[0])
+    assert not np.array_equal(xf[2].cpu().numpy(), ref[2])      # the frozen tangent is another system
+    srv.destroy()
+    assert ctx.bytes_in_use() == 0
+    ctx.destroy()
