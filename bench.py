@@ -9,7 +9,9 @@ One step = one Newton corrector's linear work on the GPU:
                             built once before the timed region, as the paper's Sec. 5.2.2 does)
 Inputs are resident in HBM before the timed region.  Each step uses its own seeded RHS.
 Outside the timed region the line also reports the numeric re-setup (amg_update: new values on
-the same pattern, aggregates kept) as resetup_ms beside the full setup_ms.
+the same pattern, aggregates kept) as resetup_ms beside the full setup_ms, and the device assembly
+of the tangent matrix from the tetrahedra (scr_assemble_tangent, at the workload's advective state)
+as "assembly".
 """
 from __future__ import annotations
 
@@ -374,7 +376,7 @@ def main():
         if args.workload != "cfg1":
             raise SystemExit("--flow runs on cfg1 only")
         prm.u_max = FLOW_U_MAX
-    s = synth.generate(prm)
+    s = synth.generate(prm, tets=True)
     log(f"[bench] {args.workload} generated: n_b={s.n_b} nnzb={s.nnzb} nodes={s.n_phys} ({time.time() - t0:.1f}s)", args)
     if args.workload == "cfg1":
         workload = ("cfg1 unified fluid+solid tube 41x41x179 (300,899 nodes, 323,811 block rows, "
@@ -462,6 +464,24 @@ def main():
                 prof = dict(launches=n, avg_us=1e3 * ms / n, bytes_per_launch=by / n, gbs=(by / n) / (ms / n * 1e-3) / 1e9)
         results[prec] = dict(lat=lat, setup=setup_ms, solve=solve_ms, mesh=mesh_ms, destroy=destroy_ms, stats=stats, prof=prof,
                              region=region, update=upd_ms)
+    # device tangent assembly (outside the timed region): the same matrix from the tetrahedra
+    asm_a = scr.scr_assembler_create(ctx, dev(s.tv), dev(s.tp), dev(s.tsolid), rp, ci, xyz, dev(s.mask),
+                                     scr.tangent_params(**{k: getattr(prm, k) for k in (
+                                         "rho_f", "mu_f", "rho_s", "E_s", "nu_s", "dt", "rho_inf", "terms",
+                                         "vms_dt_coupling")}))
+    u_adv = dev(s.uadv) if prm.u_max else None
+    kval = torch.empty_like(val)
+    asm_ms = []
+    for _ in range(4):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        scr.scr_assemble_tangent(asm_a, u_adv, kval)
+        asm_ms.append((time.perf_counter() - ta) * 1e3)
+    asm_a.destroy()
+    kdiff = float((kval - val).abs().max() / val.abs().max())
+    del kval
+    log(f"[bench] tangent assembly: {' '.join(f'{v:.2f}' for v in asm_ms)} ms, max |K_gpu - K| / max |K| = {kdiff:.1e}",
+        args)
     main_prec = "fp64" if "fp64" in results else precisions[0]
     r = results[main_prec]
     total = r["region"]
@@ -503,6 +523,8 @@ def main():
         if rr["prof"]:
             out[prec]["smoother_l0_avg_us"] = round(rr["prof"]["avg_us"], 2)
             out[prec]["smoother_l0_GBps"] = round(rr["prof"]["gbs"], 1)
+    out["assembly"] = {"ms": round(float(np.median(asm_ms[1:])), 3), "n_tets": int(s.n_tets),
+                       "advective": bool(prm.u_max), "max_rel_diff_vs_input": kdiff}
     pr = r["prof"]
     if pr:
         traffic = pmc_traffic() if (main_prec == "fp64" and args.workload == "cfg1" and not args.flow) else None

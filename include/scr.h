@@ -189,6 +189,62 @@ scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const sc
 scr_status scr_handle_destroy(scr_handle* h);
 int64_t scr_handle_bytes(const scr_handle* h);
 
+/* Device assembly of the corrector tangent matrix K (Sec. 3.5: the consistent linearisation of
+ * the semi-discrete unified-continuum equations of Sec. 3.1 (solid, c_m = c_c = 0) and Sec. 3.2
+ * (fluid, residual-based VMS), with the first-order generalized-alpha constants of Sec. 3.4,
+ * divided by alpha_f gamma dt) on P1 tetrahedra, element integrals by the one-point centroid
+ * rule, fluid convection in the Oseen form about a given advective velocity u.  Per element with
+ * volume V, local vertices a, b, M_ab = V (1 + delta_ab) / 20, L_ab = V grad N_a . grad N_b,
+ * c_t = alpha_m / (alpha_f gamma dt), u_b the centroid velocity and ub.dN = u_b . grad N:
+ *   A_ab,ij = delta_ij rho c_t M_ab + visc (delta_ij L_ab + V dN_a,j dN_b,i - 2/3 V dN_a,i dN_b,j)
+ *             + tau_C V dN_a,i dN_b,j                                          (fluid only)
+ *             + delta_ij [rho V/4 ub.dN_b + tau_M rho^2 ub.dN_a (c_t V/4 + V ub.dN_b)]
+ *             + rho M_ab (grad u)_ij                                          (fluid, u given)
+ *   G_ab,i  = -V/4 dN_a,i + tau_M rho V ub.dN_a dN_b,i
+ *   D_ab,j  =  V/4 dN_b,j + tau_M rho V dN_a,j ub.dN_b  [+ c_t rho tau_M V/4 dN_a,j]
+ *   C_ab    =  tau_M L_ab (fluid),  (c_t / kappa) M_ab (solid)
+ * with visc = mu_f (fluid), (alpha_f gamma dt / alpha_m) mu_s (solid), mu_s = E/(2(1+nu)),
+ * kappa = E/(3(1-2nu)), and tau_M, tau_C of Sec. 3.2 from the element metric J^-T M J^-1 (M the
+ * regular-simplex matrix with 2^(1/3)/2 scaling, C_T = 4, C_I = 36, the u_b.G.u_b term with u).
+ * The A and G rows of vertex a go to block row tv[a], its D and C row to tp[a]; the columns of
+ * vertex b are tv[b] (A, D) and tp[b] (G, C).  tp differs from tv on the fluid/solid interface,
+ * where solid elements take their pressure from a duplicated block row (Sec. 3.3).  Dirichlet
+ * dofs (mask) are eliminated: their rows and columns are zeroed and the diagonal set to 1.
+ * Every entry is the sum of its element contributions in ascending element order, so the result
+ * is bitwise reproducible. */
+typedef struct {
+    double rho_f, mu_f;         /* fluid density and dynamic viscosity */
+    double rho_s, E_s, nu_s;    /* solid density, Young's modulus, Poisson's ratio */
+    double dt;                  /* time step */
+    double rho_inf;             /* generalized-alpha spectral radius at infinity, in [0, 1] */
+    int32_t terms;              /* terms assembled: 1 mass, 2 viscous/elastic, 4 grad-div, 8 G and D,
+                                   16 C, 32 convection; 63 = all */
+    int32_t vms_dt_coupling;    /* 1: include the bracketed c_t term of D (fluid) */
+} scr_tangent_params;
+
+typedef struct scr_assembler scr_assembler;
+
+/* Validate and copy a mesh and a block pattern, and build the per-row incidence lists.
+ * tv, tp: device, n_tets x 4 int32 (velocity and pressure block row of each vertex); solid:
+ * device, n_tets bytes (nonzero = solid element); row_ptr (n_brows + 1), col_idx: the 4x4 block
+ * pattern of K (device; columns strictly ascending per row); coords: device, n_brows x 3 FP64
+ * (the coordinates of the velocity rows are used); mask: device, 4 * n_brows bytes (1 = Dirichlet
+ * dof).  All are copied.  Errors: SCR_E_INVALID for bad sizes or constants, a malformed pattern,
+ * vertex rows out of range, a degenerate element, or an element coupling two rows the pattern
+ * does not hold; SCR_E_OOM; SCR_E_HIP. */
+scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv, const int32_t* tp,
+                                const uint8_t* solid, int64_t n_brows, const int32_t* row_ptr,
+                                const int32_t* col_idx, const double* coords, const uint8_t* mask,
+                                const scr_tangent_params* params /* host */, void* stream,
+                                scr_assembler** out /* host */);
+/* Assemble K into val (device, 16 * nnzb FP64, row-major 4x4 blocks in the pattern's order; every
+ * value is overwritten).  u: device, n_brows x 3 FP64 advective velocity at the velocity rows, or
+ * NULL for the tangent at rest (no convection terms; tau without the u.G.u term).  Non-finite u
+ * gives non-finite values (amg_setup and amg_update reject them).  Returns after completion. */
+scr_status scr_assemble_tangent(scr_assembler* a, const double* u, double* val, void* stream);
+int64_t scr_assembler_nnzb(const scr_assembler* a);
+scr_status scr_assembler_destroy(scr_assembler* a);
+
 /* Opt-in kernel timing (roofline measurement).  After scr_ctx_profile(ctx, kernel), every launch
  * of that kernel family on handles created from ctx afterwards is bracketed by HIP events on the
  * stream it runs on; scr_ctx_profile_read returns the number of launches, their summed duration

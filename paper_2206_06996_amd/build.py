@@ -26,6 +26,7 @@ SOURCES = {
     "amg.hip": ["-ffp-contract=off"],
     "scr.hip": [],
     "serve.hip": [],
+    "assemble.hip": [],
 }
 
 

@@ -1,0 +1,449 @@
+// assemble.hip -- device assembly of the corrector tangent matrix on P1 tetrahedra (Sec. 3.1,
+// 3.2 and 3.5: the linearised unified-continuum VMS tangent, divided by alpha_f gamma dt) into a
+// fixed 4x4 block pattern.
+//
+// One thread per block row.  The row's incident (element, local vertex) pairs are kept sorted by
+// element, so every entry is the sum of its element contributions in ascending element order:
+// the result does not depend on scheduling (no atomics in the value pass).  Each thread recomputes
+// the geometry, tau and the advective quantities of each incident element (an element is seen by
+// at most eight rows: four velocity and four pressure rows, which coincide off the interface).
+#include <climits>
+#include <cmath>
+#include <memory>
+
+#include "common.h"
+#include "kernels.h"
+
+struct scr_assembler {
+    scr::Ctx* ctx = nullptr;
+    std::unique_ptr<scr::Arena> ar;
+    int64_t n_tets = 0, nb = 0, nnzb = 0, n_inc = 0;
+    int32_t *tv = nullptr, *tp = nullptr, *rp = nullptr, *ci = nullptr, *inc_off = nullptr;
+    int64_t* inc = nullptr;       // per block row, sorted: ((4 e + a) << 2) | role
+    uint8_t *solid = nullptr, *mask = nullptr;
+    double* xyz = nullptr;
+    scr_tangent_params p{};
+};
+
+namespace scr {
+namespace {
+
+// constants of one assembly (Sec. 3.4: first-order generalized-alpha; Sec. 3.1: solid moduli)
+struct TanPrm {
+    double rho_f, mu_f, rho_s, ct, visc_s, kappa, dt;
+    int terms, dtc;
+};
+
+TanPrm tan_prm(const scr_tangent_params& p) {
+    const double am = 0.5 * (3.0 - p.rho_inf) / (1.0 + p.rho_inf);
+    const double af = 1.0 / (1.0 + p.rho_inf), g = 1.0 / (1.0 + p.rho_inf);
+    TanPrm t;
+    t.rho_f = p.rho_f; t.mu_f = p.mu_f; t.rho_s = p.rho_s; t.dt = p.dt;
+    t.ct = am / (af * g * p.dt);
+    t.visc_s = (af * g * p.dt / am) * (p.E_s / (2.0 * (1.0 + p.nu_s)));
+    t.kappa = p.E_s / (3.0 * (1.0 - 2.0 * p.nu_s));
+    t.terms = p.terms;
+    t.dtc = p.vms_dt_coupling;
+    return t;
+}
+
+// Shape-function gradients of a tetrahedron: with the edge vectors e_k = x_k - x_0 (k = 1..3) and
+// det = e_1 . (e_2 x e_3), grad N_1 = (e_2 x e_3)/det, grad N_2 = (e_3 x e_1)/det,
+// grad N_3 = (e_1 x e_2)/det (the rows of the inverse Jacobian), grad N_0 = -(sum of the others).
+// Returns det (six times the signed volume).
+__device__ __forceinline__ double tet_shape(const double (&x)[4][3], double (&dN)[4][3]) {
+    double e[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) e[k][i] = x[k + 1][i] - x[0][i];
+    double c[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double* u = e[(k + 1) % 3];
+        const double* w = e[(k + 2) % 3];
+        c[k][0] = u[1] * w[2] - u[2] * w[1];
+        c[k][1] = u[2] * w[0] - u[0] * w[2];
+        c[k][2] = u[0] * w[1] - u[1] * w[0];
+    }
+    const double det = e[0][0] * c[0][0] + e[0][1] * c[0][1] + e[0][2] * c[0][2];
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        dN[1][i] = c[0][i] * inv;
+        dN[2][i] = c[1][i] * inv;
+        dN[3][i] = c[2][i] * inv;
+        dN[0][i] = -(dN[1][i] + dN[2][i] + dN[3][i]);
+    }
+    return det;
+}
+
+// tau_M and tau_C of the fluid VMS (Sec. 3.2) from the element metric G = J^-T M J^-1, M the
+// regular-simplex matrix (2^(1/3)/2 times [2 1 1; 1 2 1; 1 1 2]), C_T = 4, C_I = 36; ub is the
+// advective velocity at the centroid (zero at rest).
+__device__ __forceinline__ void fluid_tau(const double (&dN)[4][3], const double (&ub)[3], const TanPrm& P,
+                                          double& tauM, double& tauC) {
+    const double c = 0.6299605249474366;   // 2^(1/3) / 2
+    double G[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            // sum_kl dN_k,i M_kl dN_l,j with M = c (I + 1 1^T)
+            const double s1 = dN[1][i] + dN[2][i] + dN[3][i];
+            const double s2 = dN[1][j] + dN[2][j] + dN[3][j];
+            G[i][j] = c * (dN[1][i] * dN[1][j] + dN[2][i] * dN[2][j] + dN[3][i] * dN[3][j] + s1 * s2);
+        }
+    double GG = 0.0, trG = 0.0, uGu = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        trG += G[i][i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            GG += G[i][j] * G[i][j];
+            uGu += ub[i] * G[i][j] * ub[j];
+        }
+    }
+    const double nu = P.mu_f / P.rho_f;
+    tauM = 1.0 / (P.rho_f * sqrt(4.0 / (P.dt * P.dt) + uGu + 36.0 * nu * nu * GG));
+    tauC = 1.0 / (tauM * trG);
+}
+
+// position of column c in the sorted columns ci[lo, hi), or -1
+__device__ __forceinline__ int32_t find_col(const int32_t* __restrict__ ci, int32_t lo, int32_t hi, int32_t c) {
+    int32_t a = lo, b = hi;
+    while (a < b) {
+        const int32_t m = (a + b) >> 1;
+        if (ci[m] < c) a = m + 1;
+        else b = m;
+    }
+    return (a < hi && ci[a] == c) ? a : -1;
+}
+
+// ---------------------------------------------------------------- set-up kernels
+// rows whose pattern is malformed: columns out of range or not strictly ascending
+__global__ void pattern_check_k(int64_t nb, int64_t nnzb, const int32_t* __restrict__ rp,
+                                const int32_t* __restrict__ ci, int* __restrict__ err) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    const int32_t lo = rp[r], hi = rp[r + 1];
+    bool bad = lo < 0 || hi < lo || hi > nnzb;
+    for (int32_t q = lo; q < hi && !bad; ++q) bad = ci[q] < 0 || ci[q] >= nb || (q > lo && ci[q] <= ci[q - 1]);
+    if (bad) atomicOr(err, 1);
+}
+
+// per element: vertex rows in range, a nondegenerate finite geometry, and every block position the
+// element writes present in the pattern
+__global__ void element_check_k(int64_t nt, int64_t nb, const int32_t* __restrict__ tv, const int32_t* __restrict__ tp,
+                                const double* __restrict__ xyz, const int32_t* __restrict__ rp,
+                                const int32_t* __restrict__ ci, int* __restrict__ err) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nt) return;
+    int32_t va[4], pa[4];
+    for (int a = 0; a < 4; ++a) {
+        va[a] = tv[4 * e + a];
+        pa[a] = tp[4 * e + a];
+        if (va[a] < 0 || va[a] >= nb || pa[a] < 0 || pa[a] >= nb) {
+            atomicOr(err, 2);
+            return;
+        }
+    }
+    double x[4][3], dN[4][3];
+    for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i) x[a][i] = xyz[3 * (int64_t)va[a] + i];
+    const double det = tet_shape(x, dN);
+    if (!(det != 0.0) || !isfinite(det)) atomicOr(err, 4);
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            const int32_t rows[2] = {va[a], pa[a]}, cols[2] = {va[b], pa[b]};
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t)
+                    if (find_col(ci, rp[rows[s]], rp[rows[s] + 1], cols[t]) < 0) atomicOr(err, 8);
+        }
+}
+
+// incidence: element vertex (e, a) touches block row tv (velocity rows, role 1) and tp (pressure
+// row, role 2); they coincide (role 3) off the fluid/solid interface
+__global__ void inc_count_k(int64_t n4, const int32_t* __restrict__ tv, const int32_t* __restrict__ tp,
+                            int32_t* __restrict__ cnt) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n4) return;
+    const int32_t v = tv[t], p = tp[t];
+    atomicAdd(&cnt[v], 1);
+    if (p != v) atomicAdd(&cnt[p], 1);
+}
+__global__ void inc_fill_k(int64_t n4, const int32_t* __restrict__ tv, const int32_t* __restrict__ tp,
+                           int32_t* __restrict__ cur, int64_t* __restrict__ inc) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n4) return;
+    const int32_t v = tv[t], p = tp[t];
+    if (p == v) {
+        inc[atomicAdd(&cur[v], 1)] = (t << 2) | 3;
+    } else {
+        inc[atomicAdd(&cur[v], 1)] = (t << 2) | 1;
+        inc[atomicAdd(&cur[p], 1)] = (t << 2) | 2;
+    }
+}
+// each row's list in ascending key order (= element order): insertion sort, the lists are short
+__global__ void inc_sort_k(int64_t nb, const int32_t* __restrict__ off, int64_t* __restrict__ inc) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    const int32_t lo = off[r], hi = off[r + 1];
+    for (int32_t i = lo + 1; i < hi; ++i) {
+        const int64_t k = inc[i];
+        int32_t j = i - 1;
+        while (j >= lo && inc[j] > k) {
+            inc[j + 1] = inc[j];
+            --j;
+        }
+        inc[j + 1] = k;
+    }
+}
+
+// ---------------------------------------------------------------- the tangent
+// Element rows of local vertex a, per column vertex b (entries (i, j), i, j = 0..2 velocity, 3
+// pressure; V the volume, M_ab = V (1 + delta_ab)/20 the P1 mass, L_ab = V grad N_a . grad N_b):
+//   A_ij = delta_ij rho c_t M_ab                                                  (mass, bit 1)
+//        + visc (delta_ij L_ab + V dN_a,j dN_b,i - 2/3 V dN_a,i dN_b,j)          (bit 2)
+//        + tau_C V dN_a,i dN_b,j                          (fluid grad-div stabilisation, bit 4)
+//        + delta_ij [rho (V/4) ub.dN_b + tau_M rho^2 (ub.dN_a)(c_t V/4 + V ub.dN_b)]
+//        + rho M_ab grad u_ij                           (fluid convection, Oseen form, bit 32)
+//   G_i  = -(V/4) dN_a,i  [+ tau_M rho V (ub.dN_a) dN_b,i]                        (bit 8 [32])
+//   D_j  =  (V/4) dN_b,j  [+ c_t rho tau_M (V/4) dN_a,j]  [+ tau_M rho V dN_a,j (ub.dN_b)]
+//   C    =  tau_M L_ab (fluid),  (c_t/kappa) M_ab (solid)                          (bit 16)
+// visc = mu_f for fluid, (alpha_f gamma dt/alpha_m) mu_s for solid.  The A and G rows go to block
+// row tv[a] (role 1), the D and C row to tp[a] (role 2); columns tv[b] (A, D) and tp[b] (G, C).
+__global__ void __launch_bounds__(256) tangent_rows_k(int64_t nb, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ ci, const int32_t* __restrict__ ioff,
+                                                      const int64_t* __restrict__ inc, const int32_t* __restrict__ tv,
+                                                      const int32_t* __restrict__ tp, const uint8_t* __restrict__ solid,
+                                                      const double* __restrict__ xyz, const double* __restrict__ u,
+                                                      const uint8_t* __restrict__ mask, TanPrm P,
+                                                      double* __restrict__ val) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    const int32_t lo = rp[r], hi = rp[r + 1];
+    double* vr = val + (int64_t)lo * 16;
+    for (int64_t q = 0; q < (int64_t)(hi - lo) * 16; ++q) vr[q] = 0.0;
+    const bool t_mass = P.terms & 1, t_visc = P.terms & 2, t_gd = P.terms & 4, t_gdiv = P.terms & 8,
+               t_c = P.terms & 16;
+    for (int32_t k = ioff[r]; k < ioff[r + 1]; ++k) {
+        const int64_t key = inc[k];
+        const int64_t e = key >> 4;
+        const int a = (int)((key >> 2) & 3);
+        const int role = (int)(key & 3);
+        int32_t va[4], pa[4];
+        double x[4][3];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            va[b] = tv[4 * e + b];
+            pa[b] = tp[4 * e + b];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) x[b][i] = xyz[3 * (int64_t)va[b] + i];
+        }
+        double dN[4][3];
+        const double V = fabs(tet_shape(x, dN)) / 6.0;
+        const bool sol = solid[e] != 0;
+        const bool conv = !sol && u != nullptr && (P.terms & 32);
+        double ub[3] = {0.0, 0.0, 0.0}, gu[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        if (conv) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double ui = u[3 * (int64_t)va[b] + i];
+                    ub[i] += 0.25 * ui;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) gu[i][j] += ui * dN[b][j];
+                }
+        }
+        double tauM = 0.0, tauC = 0.0, rho, visc;
+        if (!sol) {
+            fluid_tau(dN, ub, P, tauM, tauC);
+            rho = P.rho_f;
+            visc = P.mu_f;
+        } else {
+            rho = P.rho_s;
+            visc = P.visc_s;
+        }
+        const double gd = sol ? 0.0 : tauC;
+        const double ua = ub[0] * dN[a][0] + ub[1] * dN[a][1] + ub[2] * dN[a][2];
+        for (int b = 0; b < 4; ++b) {
+            const double Mab = V * (a == b ? 2.0 : 1.0) / 20.0;
+            const double Lab = V * (dN[a][0] * dN[b][0] + dN[a][1] * dN[b][1] + dN[a][2] * dN[b][2]);
+            const double uB = ub[0] * dN[b][0] + ub[1] * dN[b][1] + ub[2] * dN[b][2];
+            double* bv = vr + (int64_t)(find_col(ci, lo, hi, va[b]) - lo) * 16;
+            double* bp = vr + (int64_t)(find_col(ci, lo, hi, pa[b]) - lo) * 16;
+            if (role & 1) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        double v = 0.0;
+                        if (t_mass && i == j) v += rho * P.ct * Mab;
+                        if (t_visc)
+                            v += visc * ((i == j ? Lab : 0.0) + V * dN[a][j] * dN[b][i] -
+                                         (2.0 / 3.0) * V * dN[a][i] * dN[b][j]);
+                        if (t_gd) v += gd * V * dN[a][i] * dN[b][j];
+                        if (conv) {
+                            if (i == j) v += rho * (V / 4.0) * uB + tauM * rho * rho * ua * (P.ct * (V / 4.0) + V * uB);
+                            v += rho * Mab * gu[i][j];
+                        }
+                        bv[4 * i + j] += v;
+                    }
+                    double g = t_gdiv ? -(V / 4.0) * dN[a][i] : 0.0;
+                    if (conv) g += tauM * rho * V * ua * dN[b][i];
+                    bp[4 * i + 3] += g;
+                }
+            }
+            if (role & 2) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double d = 0.0;
+                    if (t_gdiv) {
+                        d = (V / 4.0) * dN[b][j];
+                        if (!sol && P.dtc) d += P.ct * rho * tauM * (V / 4.0) * dN[a][j];
+                    }
+                    if (conv) d += tauM * rho * V * dN[a][j] * uB;
+                    bv[12 + j] += d;
+                }
+                if (t_c) bp[15] += sol ? (P.ct / P.kappa) * Mab : tauM * Lab;
+            }
+        }
+    }
+    // Dirichlet elimination: rows and columns of constrained dofs zeroed, unit diagonal
+    uint8_t mr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mr[i] = mask[4 * r + i];
+    for (int32_t q = lo; q < hi; ++q) {
+        const int32_t c = ci[q];
+        double* blk = val + (int64_t)q * 16;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint8_t mc = mask[4 * (int64_t)c + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (mr[i] || mc) blk[4 * i + j] = (c == r && i == j) ? 1.0 : 0.0;
+        }
+    }
+}
+
+scr_status asm_fail(const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+}
+
+}  // namespace
+}  // namespace scr
+
+using namespace scr;
+
+scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv, const int32_t* tp,
+                                const uint8_t* solid, int64_t n_brows, const int32_t* row_ptr,
+                                const int32_t* col_idx, const double* coords, const uint8_t* mask,
+                                const scr_tangent_params* params, void* stream, scr_assembler** out) {
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<scr_assembler> A;
+    try {
+        if (!ctx || !out || !params) throw Error(SCR_E_INVALID, "NULL ctx, out or params");
+        *out = nullptr;
+        if (n_tets < 1 || n_brows < 1) throw Error(SCR_E_INVALID, "n_tets and n_brows must be positive");
+        if (!tv || !tp || !solid || !row_ptr || !col_idx || !coords || !mask)
+            throw Error(SCR_E_INVALID, "NULL input array");
+        if (8 * n_tets > INT32_MAX) throw Error(SCR_E_INVALID, "too many elements (the incidence lists use 32-bit offsets)");
+        const scr_tangent_params& p = *params;
+        for (double v : {p.rho_f, p.mu_f, p.rho_s, p.E_s, p.dt})
+            if (!(v > 0.0) || !std::isfinite(v)) throw Error(SCR_E_INVALID, "physical constants must be positive");
+        if (!(p.nu_s > -1.0 && p.nu_s < 0.5)) throw Error(SCR_E_INVALID, "nu_s must lie in (-1, 0.5)");
+        if (!(p.rho_inf >= 0.0 && p.rho_inf <= 1.0)) throw Error(SCR_E_INVALID, "rho_inf must lie in [0, 1]");
+        if (p.terms < 0 || p.terms > 63) throw Error(SCR_E_INVALID, "terms must be a mask of bits 1..32");
+        HIPCHK(hipSetDevice(ctx->c.device));
+        A.reset(new scr_assembler());
+        A->ctx = &ctx->c;
+        A->ar.reset(new Arena(&ctx->c, s));
+        Arena& ar = *A->ar;
+        A->n_tets = n_tets;
+        A->nb = n_brows;
+        A->p = p;
+        int32_t ends[2];
+        HIPCHK(hipMemcpyAsync(&ends[0], row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&ends[1], row_ptr + n_brows, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (ends[0] != 0 || ends[1] < n_brows) throw Error(SCR_E_INVALID, "row_ptr must start at 0 and cover the diagonal");
+        A->nnzb = ends[1];
+        A->tv = ar.make<int32_t>(4 * n_tets);
+        A->tp = ar.make<int32_t>(4 * n_tets);
+        A->solid = ar.make<uint8_t>(n_tets);
+        A->rp = ar.make<int32_t>(n_brows + 1);
+        A->ci = ar.make<int32_t>(A->nnzb);
+        A->xyz = ar.make<double>(3 * n_brows);
+        A->mask = ar.make<uint8_t>(4 * n_brows);
+        copy_dev(A->tv, tv, 4 * n_tets * sizeof(int32_t), s);
+        copy_dev(A->tp, tp, 4 * n_tets * sizeof(int32_t), s);
+        copy_dev(A->solid, solid, n_tets, s);
+        copy_dev(A->rp, row_ptr, (n_brows + 1) * sizeof(int32_t), s);
+        copy_dev(A->ci, col_idx, A->nnzb * sizeof(int32_t), s);
+        copy_dev(A->xyz, coords, 3 * n_brows * sizeof(double), s);
+        copy_dev(A->mask, mask, 4 * n_brows, s);
+        int* err = ar.make<int>(1);
+        zero_dev(err, sizeof(int), s);
+        pattern_check_k<<<cdiv(n_brows, 256), 256, 0, s>>>(n_brows, A->nnzb, A->rp, A->ci, err);
+        check_launch("pattern_check");
+        int herr = 0;
+        HIPCHK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (herr) throw Error(SCR_E_INVALID, "malformed pattern (row_ptr decreasing, columns out of range or unsorted)");
+        element_check_k<<<cdiv(n_tets, 256), 256, 0, s>>>(n_tets, n_brows, A->tv, A->tp, A->xyz, A->rp, A->ci, err);
+        check_launch("element_check");
+        HIPCHK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (herr & 2) throw Error(SCR_E_INVALID, "element vertex row out of range");
+        if (herr & 4) throw Error(SCR_E_INVALID, "degenerate or non-finite element");
+        if (herr & 8) throw Error(SCR_E_INVALID, "an element couples two block rows the pattern does not hold");
+        // incidence lists
+        int32_t* cnt = ar.make<int32_t>(n_brows);
+        zero_dev(cnt, n_brows * sizeof(int32_t), s);
+        inc_count_k<<<cdiv(4 * n_tets, 256), 256, 0, s>>>(4 * n_tets, A->tv, A->tp, cnt);
+        check_launch("inc_count");
+        A->inc_off = ar.make<int32_t>(n_brows + 1);
+        A->n_inc = scan_i32(cnt, A->inc_off, n_brows, ar, s);
+        A->inc = ar.make<int64_t>(A->n_inc);
+        copy_dev(cnt, A->inc_off, n_brows * sizeof(int32_t), s);
+        inc_fill_k<<<cdiv(4 * n_tets, 256), 256, 0, s>>>(4 * n_tets, A->tv, A->tp, cnt, A->inc);
+        check_launch("inc_fill");
+        inc_sort_k<<<cdiv(n_brows, 256), 256, 0, s>>>(n_brows, A->inc_off, A->inc);
+        check_launch("inc_sort");
+        ar.free(cnt);
+        ar.free(err);
+        HIPCHK(hipStreamSynchronize(s));
+        *out = A.release();
+        return SCR_OK;
+    } catch (const Error& e) {
+        (void)hipStreamSynchronize(s);
+        return asm_fail(e);
+    }
+}
+
+scr_status scr_assemble_tangent(scr_assembler* A, const double* u, double* val, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!A || !val) throw Error(SCR_E_INVALID, "NULL assembler or val");
+        HIPCHK(hipSetDevice(A->ctx->device));
+        tangent_rows_k<<<cdiv(A->nb, 256), 256, 0, s>>>(A->nb, A->rp, A->ci, A->inc_off, A->inc, A->tv, A->tp,
+                                                         A->solid, A->xyz, u, A->mask, tan_prm(A->p), val);
+        check_launch("tangent_rows");
+        HIPCHK(hipStreamSynchronize(s));
+        return SCR_OK;
+    } catch (const Error& e) {
+        (void)hipStreamSynchronize(s);
+        return asm_fail(e);
+    }
+}
+
+int64_t scr_assembler_nnzb(const scr_assembler* A) { return A ? A->nnzb : 0; }
+
+scr_status scr_assembler_destroy(scr_assembler* A) {
+    if (!A) return SCR_OK;
+    delete A;   // the arena synchronises its stream and returns every block to the context cache
+    return SCR_OK;
+}

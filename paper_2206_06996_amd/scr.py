@@ -27,7 +27,8 @@ EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", 
             "scr_handle_bytes", "scr_footprint_estimate", "scr_status_str", "scr_last_error", "scr_hier_levels",
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
             "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
-            "srv_destroy"]
+            "srv_destroy", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_nnzb",
+            "scr_assembler_destroy"]
 SCR_PROF_OFF, SCR_PROF_SMOOTH_A0 = 0, 1
 
 
@@ -87,6 +88,13 @@ class SrvResult(C.Structure):
         return d
 
 
+class TangentParams(C.Structure):
+    """scr_tangent_params: physical constants of the tangent assembly."""
+    _fields_ = [("rho_f", C.c_double), ("mu_f", C.c_double), ("rho_s", C.c_double), ("E_s", C.c_double),
+                ("nu_s", C.c_double), ("dt", C.c_double), ("rho_inf", C.c_double), ("terms", C.c_int32),
+                ("vms_dt_coupling", C.c_int32)]
+
+
 def lib():
     """Load libscr.so (built by paper_2206_06996_amd.build); raise if it is missing."""
     global _lib
@@ -127,10 +135,16 @@ def lib():
         L.srv_drain.argtypes = [P, C.POINTER(C.c_int)]
         L.srv_destroy.argtypes = [P]
         L.srv_destroy.restype = None
+        L.scr_assembler_create.argtypes = [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P,
+                                           C.POINTER(TangentParams), P, C.POINTER(P)]
+        L.scr_assemble_tangent.argtypes = [P, P, P, P]
+        L.scr_assembler_nnzb.argtypes = [P]
+        L.scr_assembler_nnzb.restype = C.c_int64
+        L.scr_assembler_destroy.argtypes = [P]
         for f in ("amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
                   "scr_ctx_profile", "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait",
-                  "srv_drain"):
+                  "srv_drain", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -293,6 +307,57 @@ def set_outlets(h: Handle, outlets, m, stream=None):
     _check(lib().scr_set_outlets(h.ptr, n, off.ctypes.data_as(P), None if blk is None else _dev(blk, torch.int32, "blk"),
                                  None if a is None else _dev(a, torch.float64, "a"), mm.ctypes.data_as(P),
                                  _stream(stream)))
+
+
+def tangent_params(**kw) -> TangentParams:
+    """Defaults: every term, no c_t coupling in D; the physical constants must be given."""
+    t = TangentParams(terms=63, vms_dt_coupling=0)
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+class Assembler:
+    def __init__(self, ptr, n_brows, nnzb):
+        self.ptr, self.n_brows, self.nnzb = ptr, n_brows, nnzb
+
+    def destroy(self):
+        if self.ptr:
+            lib().scr_assembler_destroy(self.ptr)
+            self.ptr = P()
+
+
+def scr_assembler_create(ctx: Context, tv, tp, solid, row_ptr, col_idx, coords, mask, params: TangentParams,
+                         stream=None) -> Assembler:
+    """tv, tp: (n_tets, 4) int32; solid: n_tets uint8; row_ptr, col_idx: int32 pattern; coords:
+    (n_brows, 3) FP64; mask: 4 n_brows uint8 (all device tensors)."""
+    import torch
+    a = P()
+    n = row_ptr.numel() - 1
+    nt = tv.shape[0] if tv.dim() == 2 else -1
+    if tv.shape != (nt, 4) or tp.shape != (nt, 4) or solid.numel() != nt:
+        raise ValueError("tv and tp must be (n_tets, 4) and solid n_tets long")
+    if coords.numel() != 3 * n or mask.numel() != 4 * n:
+        raise ValueError("coords must hold 3 n_brows and mask 4 n_brows values")
+    if n < 1 or col_idx.numel() != int(row_ptr[-1].item()):
+        raise ValueError("col_idx must hold row_ptr[n_brows] entries")
+    _check(lib().scr_assembler_create(ctx.ptr, tv.shape[0], _dev(tv, torch.int32, "tv"), _dev(tp, torch.int32, "tp"),
+                                      _dev(solid, torch.uint8, "solid"), n, _dev(row_ptr, torch.int32, "row_ptr"),
+                                      _dev(col_idx, torch.int32, "col_idx"), _dev(coords, torch.float64, "coords"),
+                                      _dev(mask, torch.uint8, "mask"), C.byref(params), _stream(stream), C.byref(a)))
+    return Assembler(a, n, lib().scr_assembler_nnzb(a))
+
+
+def scr_assemble_tangent(a: Assembler, u, val, stream=None):
+    """val (16 nnzb FP64, device) = the tangent at the advective velocity u ((n_brows, 3) FP64
+    device tensor, or None for the tangent at rest)."""
+    import torch
+    if val.numel() != 16 * a.nnzb:
+        raise ValueError("val must hold 16 * nnzb values")
+    if u is not None and u.numel() != 3 * a.n_brows:
+        raise ValueError("u must hold 3 * n_brows values")
+    _check(lib().scr_assemble_tangent(a.ptr, None if u is None else _dev(u, torch.float64, "u"),
+                                      _dev(val, torch.float64, "val"), _stream(stream)))
 
 
 def scr_solve(h: Handle, b, x, opts: SolveOpts | None = None, stream=None):
