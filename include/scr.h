@@ -237,8 +237,8 @@ scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv,
                                 const int32_t* col_idx, const double* coords, const uint8_t* mask,
                                 const scr_tangent_params* params /* host */, void* stream,
                                 scr_assembler** out /* host */);
-/* Assemble K into val (device, 16 * nnzb FP64, row-major 4x4 blocks in the pattern's order; every
- * value is overwritten).  u: device, n_brows x 3 FP64 advective velocity at the velocity rows, or
+/* Assemble K into val (device, 16 * nnzb FP64, 16-byte aligned, row-major 4x4 blocks in the
+ * pattern's order; every value is overwritten).  u: device, n_brows x 3 FP64 advective velocity at the velocity rows, or
  * NULL for the tangent at rest (no convection terms; tau without the u.G.u term).  Non-finite u
  * gives non-finite values (amg_setup and amg_update reject them).  Returns after completion. */
 scr_status scr_assemble_tangent(scr_assembler* a, const double* u, double* val, void* stream);

@@ -2,11 +2,12 @@
 // 3.2 and 3.5: the linearised unified-continuum VMS tangent, divided by alpha_f gamma dt) into a
 // fixed 4x4 block pattern.
 //
-// One thread per block row.  The row's incident (element, local vertex) pairs are kept sorted by
-// element, so every entry is the sum of its element contributions in ascending element order:
-// the result does not depend on scheduling (no atomics in the value pass).  Each thread recomputes
-// the geometry, tau and the advective quantities of each incident element (an element is seen by
-// at most eight rows: four velocity and four pressure rows, which coincide off the interface).
+// One thread per stored 4x4 block.  Each block row keeps its incident (element, local vertex)
+// pairs sorted by element, so every entry is the sum of its element contributions in ascending
+// element order: the result does not depend on scheduling (no atomics in the value pass).  A
+// thread recomputes the geometry, tau and the advective quantities of each element that couples
+// its row and column (an element is seen by the 16 blocks of its vertex pairs, more on the
+// fluid/solid interface); the values are accumulated in registers and written once.
 #include <climits>
 #include <cmath>
 #include <memory>
@@ -20,6 +21,7 @@ struct scr_assembler {
     int64_t n_tets = 0, nb = 0, nnzb = 0, n_inc = 0;
     int32_t *tv = nullptr, *tp = nullptr, *rp = nullptr, *ci = nullptr, *inc_off = nullptr;
     int64_t* inc = nullptr;       // per block row, sorted: ((4 e + a) << 2) | role
+    int32_t* rowof = nullptr;     // block row of each stored block
     uint8_t *solid = nullptr, *mask = nullptr;
     double* xyz = nullptr;
     scr_tangent_params p{};
@@ -213,18 +215,23 @@ __global__ void inc_sort_k(int64_t nb, const int32_t* __restrict__ off, int64_t*
 //   C    =  tau_M L_ab (fluid),  (c_t/kappa) M_ab (solid)                          (bit 16)
 // visc = mu_f for fluid, (alpha_f gamma dt/alpha_m) mu_s for solid.  The A and G rows go to block
 // row tv[a] (role 1), the D and C row to tp[a] (role 2); columns tv[b] (A, D) and tp[b] (G, C).
-__global__ void __launch_bounds__(256) tangent_rows_k(int64_t nb, const int32_t* __restrict__ rp,
-                                                      const int32_t* __restrict__ ci, const int32_t* __restrict__ ioff,
-                                                      const int64_t* __restrict__ inc, const int32_t* __restrict__ tv,
-                                                      const int32_t* __restrict__ tp, const uint8_t* __restrict__ solid,
-                                                      const double* __restrict__ xyz, const double* __restrict__ u,
-                                                      const uint8_t* __restrict__ mask, TanPrm P,
-                                                      double* __restrict__ val) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nb) return;
-    const int32_t lo = rp[r], hi = rp[r + 1];
-    double* vr = val + (int64_t)lo * 16;
-    for (int64_t q = 0; q < (int64_t)(hi - lo) * 16; ++q) vr[q] = 0.0;
+// One thread per stored block (r, c): it walks row r's incidence list (ascending elements), skips
+// the elements that do not hold c as a velocity or pressure column, and accumulates the 16 entries
+// of the block in registers; each block is written once (consecutive threads write consecutive
+// blocks), then the Dirichlet elimination is applied to it.
+__global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int32_t* __restrict__ rowof,
+                                                        const int32_t* __restrict__ ci, const int32_t* __restrict__ ioff,
+                                                        const int64_t* __restrict__ inc, const int32_t* __restrict__ tv,
+                                                        const int32_t* __restrict__ tp, const uint8_t* __restrict__ solid,
+                                                        const double* __restrict__ xyz, const double* __restrict__ u,
+                                                        const uint8_t* __restrict__ mask, TanPrm P,
+                                                        double* __restrict__ val) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnzb) return;
+    const int32_t r = rowof[q], c = ci[q];
+    double acc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t] = 0.0;
     const bool t_mass = P.terms & 1, t_visc = P.terms & 2, t_gd = P.terms & 4, t_gdiv = P.terms & 8,
                t_c = P.terms & 16;
     for (int32_t k = ioff[r]; k < ioff[r + 1]; ++k) {
@@ -232,15 +239,22 @@ __global__ void __launch_bounds__(256) tangent_rows_k(int64_t nb, const int32_t*
         const int64_t e = key >> 4;
         const int a = (int)((key >> 2) & 3);
         const int role = (int)(key & 3);
-        int32_t va[4], pa[4];
-        double x[4][3];
+        typedef int I4 __attribute__((ext_vector_type(4)));
+        const I4 va = *reinterpret_cast<const I4*>(tv + 4 * e);
+        const I4 pa = *reinterpret_cast<const I4*>(tp + 4 * e);
+        // the column vertex b of c (velocity and pressure columns; at most one b each)
+        int bv = -1, bq = -1;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            va[b] = tv[4 * e + b];
-            pa[b] = tp[4 * e + b];
+            if (va[b] == c) bv = b;
+            if (pa[b] == c) bq = b;
+        }
+        if (bv < 0 && bq < 0) continue;
+        double x[4][3];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int i = 0; i < 3; ++i) x[b][i] = xyz[3 * (int64_t)va[b] + i];
-        }
         double dN[4][3];
         const double V = fabs(tet_shape(x, dN)) / 6.0;
         const bool sol = solid[e] != 0;
@@ -267,65 +281,88 @@ __global__ void __launch_bounds__(256) tangent_rows_k(int64_t nb, const int32_t*
             visc = P.visc_s;
         }
         const double gd = sol ? 0.0 : tauC;
-        const double ua = ub[0] * dN[a][0] + ub[1] * dN[a][1] + ub[2] * dN[a][2];
-        for (int b = 0; b < 4; ++b) {
-            const double Mab = V * (a == b ? 2.0 : 1.0) / 20.0;
-            const double Lab = V * (dN[a][0] * dN[b][0] + dN[a][1] * dN[b][1] + dN[a][2] * dN[b][2]);
-            const double uB = ub[0] * dN[b][0] + ub[1] * dN[b][1] + ub[2] * dN[b][2];
-            double* bv = vr + (int64_t)(find_col(ci, lo, hi, va[b]) - lo) * 16;
-            double* bp = vr + (int64_t)(find_col(ci, lo, hi, pa[b]) - lo) * 16;
+        double dNa[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dNa[i] = a == 0 ? dN[0][i] : a == 1 ? dN[1][i] : a == 2 ? dN[2][i] : dN[3][i];
+        const double ua = ub[0] * dNa[0] + ub[1] * dNa[1] + ub[2] * dNa[2];
+        if (bv >= 0) {
+            double dNb[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dNb[i] = bv == 0 ? dN[0][i] : bv == 1 ? dN[1][i] : bv == 2 ? dN[2][i] : dN[3][i];
+            const double Mab = V * (a == bv ? 2.0 : 1.0) / 20.0;
+            const double Lab = V * (dNa[0] * dNb[0] + dNa[1] * dNb[1] + dNa[2] * dNb[2]);
+            const double uB = ub[0] * dNb[0] + ub[1] * dNb[1] + ub[2] * dNb[2];
             if (role & 1) {
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
+                for (int i = 0; i < 3; ++i)
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
                         double v = 0.0;
                         if (t_mass && i == j) v += rho * P.ct * Mab;
                         if (t_visc)
-                            v += visc * ((i == j ? Lab : 0.0) + V * dN[a][j] * dN[b][i] -
-                                         (2.0 / 3.0) * V * dN[a][i] * dN[b][j]);
-                        if (t_gd) v += gd * V * dN[a][i] * dN[b][j];
+                            v += visc * ((i == j ? Lab : 0.0) + V * dNa[j] * dNb[i] - (2.0 / 3.0) * V * dNa[i] * dNb[j]);
+                        if (t_gd) v += gd * V * dNa[i] * dNb[j];
                         if (conv) {
                             if (i == j) v += rho * (V / 4.0) * uB + tauM * rho * rho * ua * (P.ct * (V / 4.0) + V * uB);
                             v += rho * Mab * gu[i][j];
                         }
-                        bv[4 * i + j] += v;
+                        acc[4 * i + j] += v;
                     }
-                    double g = t_gdiv ? -(V / 4.0) * dN[a][i] : 0.0;
-                    if (conv) g += tauM * rho * V * ua * dN[b][i];
-                    bp[4 * i + 3] += g;
-                }
             }
             if (role & 2) {
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     double d = 0.0;
                     if (t_gdiv) {
-                        d = (V / 4.0) * dN[b][j];
-                        if (!sol && P.dtc) d += P.ct * rho * tauM * (V / 4.0) * dN[a][j];
+                        d = (V / 4.0) * dNb[j];
+                        if (!sol && P.dtc) d += P.ct * rho * tauM * (V / 4.0) * dNa[j];
                     }
-                    if (conv) d += tauM * rho * V * dN[a][j] * uB;
-                    bv[12 + j] += d;
+                    if (conv) d += tauM * rho * V * dNa[j] * uB;
+                    acc[12 + j] += d;
                 }
-                if (t_c) bp[15] += sol ? (P.ct / P.kappa) * Mab : tauM * Lab;
+            }
+        }
+        if (bq >= 0) {
+            double dNb[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dNb[i] = bq == 0 ? dN[0][i] : bq == 1 ? dN[1][i] : bq == 2 ? dN[2][i] : dN[3][i];
+            if (role & 1) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    double g = t_gdiv ? -(V / 4.0) * dNa[i] : 0.0;
+                    if (conv) g += tauM * rho * V * ua * dNb[i];
+                    acc[4 * i + 3] += g;
+                }
+            }
+            if ((role & 2) && t_c) {
+                const double Mab = V * (a == bq ? 2.0 : 1.0) / 20.0;
+                const double Lab = V * (dNa[0] * dNb[0] + dNa[1] * dNb[1] + dNa[2] * dNb[2]);
+                acc[15] += sol ? (P.ct / P.kappa) * Mab : tauM * Lab;
             }
         }
     }
     // Dirichlet elimination: rows and columns of constrained dofs zeroed, unit diagonal
-    uint8_t mr[4];
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    D2* out = reinterpret_cast<D2*>(val + 16 * q);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) mr[i] = mask[4 * r + i];
-    for (int32_t q = lo; q < hi; ++q) {
-        const int32_t c = ci[q];
-        double* blk = val + (int64_t)q * 16;
+    for (int i = 0; i < 4; ++i) {
+        const uint8_t mr = mask[4 * (int64_t)r + i];
+        double w[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint8_t mc = mask[4 * (int64_t)c + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (mr[i] || mc) blk[4 * i + j] = (c == r && i == j) ? 1.0 : 0.0;
+            w[j] = (mr || mc) ? ((c == r && i == j) ? 1.0 : 0.0) : acc[4 * i + j];
         }
+        out[2 * i] = D2{w[0], w[1]};
+        out[2 * i + 1] = D2{w[2], w[3]};
     }
+}
+
+// block row of every stored block
+__global__ void row_of_k(int64_t nb, const int32_t* __restrict__ rp, int32_t* __restrict__ rowof) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    for (int32_t q = rp[r]; q < rp[r + 1]; ++q) rowof[q] = (int32_t)r;
 }
 
 scr_status asm_fail(const Error& e) {
@@ -413,6 +450,9 @@ scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv,
         check_launch("inc_fill");
         inc_sort_k<<<cdiv(n_brows, 256), 256, 0, s>>>(n_brows, A->inc_off, A->inc);
         check_launch("inc_sort");
+        A->rowof = ar.make<int32_t>(A->nnzb);
+        row_of_k<<<cdiv(n_brows, 256), 256, 0, s>>>(n_brows, A->rp, A->rowof);
+        check_launch("row_of");
         ar.free(cnt);
         ar.free(err);
         HIPCHK(hipStreamSynchronize(s));
@@ -428,10 +468,11 @@ scr_status scr_assemble_tangent(scr_assembler* A, const double* u, double* val, 
     hipStream_t s = (hipStream_t)stream;
     try {
         if (!A || !val) throw Error(SCR_E_INVALID, "NULL assembler or val");
+        if (reinterpret_cast<uintptr_t>(val) % 16 != 0) throw Error(SCR_E_INVALID, "val must be 16-byte aligned");
         HIPCHK(hipSetDevice(A->ctx->device));
-        tangent_rows_k<<<cdiv(A->nb, 256), 256, 0, s>>>(A->nb, A->rp, A->ci, A->inc_off, A->inc, A->tv, A->tp,
-                                                         A->solid, A->xyz, u, A->mask, tan_prm(A->p), val);
-        check_launch("tangent_rows");
+        tangent_blocks_k<<<cdiv(A->nnzb, 256), 256, 0, s>>>(A->nnzb, A->rowof, A->ci, A->inc_off, A->inc, A->tv, A->tp,
+                                                             A->solid, A->xyz, u, A->mask, tan_prm(A->p), val);
+        check_launch("tangent_blocks");
         HIPCHK(hipStreamSynchronize(s));
         return SCR_OK;
     } catch (const Error& e) {
