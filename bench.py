@@ -91,7 +91,7 @@ def pmc_traffic():
 
 
 COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
-SMOOTH_KERNEL = "smooth_rl3_k<double, true, false, false>"
+SMOOTH_KERNEL = "smooth_rl3_k<double, true, true, false>"
 
 
 def _pmc_rows(d, counter):

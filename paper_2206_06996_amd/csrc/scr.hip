@@ -293,7 +293,7 @@ void scr_default_amg_opts(scr_amg_opts* o) {
     o->precision = SCR_FP64;
     o->theta = 0.08;
     o->smoother = SCR_SMOOTH_CHEBYSHEV;
-    o->cheb_degree = 2;
+    o->cheb_degree = 5;
     o->cheb_ratio = 30.0;
     o->jacobi_sweeps = 2;
     o->coarse_max = 1024;

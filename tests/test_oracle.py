@@ -217,18 +217,29 @@ def _dense_level(h, l):
     return A, Dinv, i["lam"]
 
 
-def test_chebyshev_smoother_error_is_the_chebyshev_polynomial():
+def _cheb_error(Z, sigma, k):
+    """T_k(Z) / T_k(sigma) by the three-term recurrence T_{j+1} = 2 z T_j - T_{j-1}."""
+    I = np.eye(Z.shape[0])
+    Tm, T = I, Z
+    tm, t = 1.0, sigma
+    for _ in range(k - 1):
+        Tm, T = T, 2 * Z @ T - Tm
+        tm, t = t, 2 * sigma * t - tm
+    return T / t
+
+
+@pytest.mark.parametrize("degree", [2, 5])
+def test_chebyshev_smoother_error_is_the_chebyshev_polynomial(degree):
     rp, ci, val, _ = _laplacian_box(4, 4, 3)
     n = rp.size - 1
-    h = oracle.Amg(rp, ci, val, np.ones((n, 1)), oracle.amg_opts(coarse_max=10, theta=0.05))
+    h = oracle.Amg(rp, ci, val, np.ones((n, 1)), oracle.amg_opts(coarse_max=10, theta=0.05, cheb_degree=degree))
     A, Dinv, lam = _dense_level(h, 0)
     lmax, lmin = lam, lam / 30
     theta, delta = (lmax + lmin) / 2, (lmax - lmin) / 2
     Y = Dinv @ A
     I = np.eye(n)
     Z = (theta * I - Y) / delta
-    T2 = 2 * Z @ Z - I
-    E = T2 / (2 * (theta / delta) ** 2 - 1)          # T_2(Z) / T_2(sigma)
+    E = _cheb_error(Z, theta / delta, degree)
     rng = np.random.default_rng(2)
     b = rng.normal(size=n)
     x = h.smooth(0, b)
@@ -270,7 +281,7 @@ def test_vcycle_is_symmetric_and_matches_two_grid_formula(scr_small, smoother, s
         lmax, lmin = lam, lam / 30
         th, de = (lmax + lmin) / 2, (lmax - lmin) / 2
         Z = (th * I - Dinv @ A) / de
-        E = (2 * Z @ Z - I) / (2 * (th / de) ** 2 - 1)
+        E = _cheb_error(Z, th / de, oracle.amg_opts().cheb_degree)
     else:
         Ej = I - 4 / (3 * lam) * Dinv @ A
         E = Ej @ Ej
