@@ -98,14 +98,41 @@ __device__ __forceinline__ int hash_insert(int* t, int hs, int key) {
     }
 }
 
+// Maximum over a 256-thread workgroup, folded into *out by one atomic (every thread must call it).
+// A same-address atomic per row serialises at one L2 channel: 324k of them cost about 3.5 ms.
+template <typename T>
+__device__ __forceinline__ void block_max_to(T v, T* out) {
+    __shared__ T red[256 / WAVE];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, WAVE);
+        v = w > v ? w : v;
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T m = red[0];
+        for (int w = 1; w < 256 / WAVE; ++w) m = red[w] > m ? red[w] : m;
+        atomicMax(out, m);
+    }
+}
+
 // upper bound of the candidates of each row of X*Y (sum of the lengths of the Y rows it meets)
-__global__ void spg_bound_k(int64_t nr, const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci,
-                            const int32_t* __restrict__ yrp, int* __restrict__ maxub) {
+__global__ void __launch_bounds__(256) spg_bound_k(int64_t nr, const int32_t* __restrict__ xrp,
+                                                   const int32_t* __restrict__ xci, const int32_t* __restrict__ yrp,
+                                                   int* __restrict__ maxub) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr) return;
     int64_t ub = 0;
-    for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) ub += yrp[xci[q] + 1] - yrp[xci[q]];
-    atomicMax(maxub, (int)(ub < (1 << 30) ? ub : (1 << 30)));
+    if (i < nr)
+        for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) ub += yrp[xci[q] + 1] - yrp[xci[q]];
+    block_max_to((int)(ub < (1 << 30) ? ub : (1 << 30)), maxub);
+}
+
+// largest of n counts (one atomic per workgroup)
+__global__ void __launch_bounds__(256) max_i32_k(int64_t n, const int32_t* __restrict__ a, int* __restrict__ out) {
+    int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = a[i] > m ? a[i] : m;
+    block_max_to(m, out);
 }
 
 // count (phase 0) or emit sorted (phase 1) the structural pattern of row i of X*Y.
@@ -175,10 +202,7 @@ __global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const i
         return;
     }
     if (PHASE == 0) {
-        if (lane == 0) {
-            cnt[i] = w;
-            atomicMax(overflow + 2, w);
-        }
+        if (lane == 0) cnt[i] = w;
         return;
     }
     // rank sort of the unique columns
@@ -350,7 +374,12 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
         hs = std::min(4 * hs, HS_MAX);
         zero_dev(flags, sizeof(int), s);
     }
+    // widest output row (flags[2] is still zero: the counting pass does not touch it)
+    if (X.nr > 0) max_i32_k<<<(unsigned)std::min<int64_t>(cdiv(X.nr, 256), 1024), 256, 0, s>>>(X.nr, cnt, flags + 2);
+    check_launch("max_i32");
+    HIPCHK(hipMemcpyAsync(&hf[2], flags + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     C.nnzb = scan_i32(cnt, C.rp, X.nr, ar, s);
+    HIPCHK(hipStreamSynchronize(s));
     const int wmax = hf[2];
     ar.free(cnt);
     C.ci = ar.make<int32_t>(C.nnzb > 0 ? C.nnzb : 1);
@@ -368,9 +397,9 @@ static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& 
 }
 
 // max row length of a pattern
-__global__ void rowlen_max_k(int64_t nr, const int32_t* __restrict__ rp, int* __restrict__ out) {
+__global__ void __launch_bounds__(256) rowlen_max_k(int64_t nr, const int32_t* __restrict__ rp, int* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nr) atomicMax(out, rp[i + 1] - rp[i]);
+    block_max_to(i < nr ? rp[i + 1] - rp[i] : 0, out);
 }
 
 // numeric phase only, into the existing pattern of C (same terms and order as a full product)
@@ -758,32 +787,35 @@ __device__ bool invert_small(const double* __restrict__ a, double* __restrict__ 
 }
 
 template <int B>
-__global__ void dinv_lambda_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                              const double* __restrict__ v, double* __restrict__ Dinv, unsigned long long* __restrict__ lam,
-                              int* __restrict__ err) {
+__global__ void __launch_bounds__(256) dinv_lambda_k(int64_t nr, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                     double* __restrict__ Dinv, unsigned long long* __restrict__ lam,
+                                                     int* __restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr) return;
-    int32_t q = find_col(ci, rp[i], rp[i + 1], (int32_t)i);
-    double Di[B * B];
-    if (q < 0 || !invert_small<B>(v + (int64_t)q * B * B, Di)) {
-        atomicOr(err, 1);
-        return;
-    }
-    for (int e = 0; e < B * B; ++e) Dinv[i * B * B + e] = Di[e];
-    double rs[B];
-    for (int r = 0; r < B; ++r) rs[r] = 0.0;
-    for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
-        const double* blk = v + (int64_t)t * B * B;
-        for (int r = 0; r < B; ++r)
-            for (int c = 0; c < B; ++c) {
-                double sum = 0.0;
-                for (int l = 0; l < B; ++l) sum += Di[r * B + l] * blk[l * B + c];
-                rs[r] += fabs(sum);
+    double m = 0.0;     // max absolute row sum of D^-1 A over the block row (0 for idle threads)
+    if (i < nr) {
+        int32_t q = find_col(ci, rp[i], rp[i + 1], (int32_t)i);
+        double Di[B * B];
+        if (q < 0 || !invert_small<B>(v + (int64_t)q * B * B, Di)) {
+            atomicOr(err, 1);
+        } else {
+            for (int e = 0; e < B * B; ++e) Dinv[i * B * B + e] = Di[e];
+            double rs[B];
+            for (int r = 0; r < B; ++r) rs[r] = 0.0;
+            for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
+                const double* blk = v + (int64_t)t * B * B;
+                for (int r = 0; r < B; ++r)
+                    for (int c = 0; c < B; ++c) {
+                        double sum = 0.0;
+                        for (int l = 0; l < B; ++l) sum += Di[r * B + l] * blk[l * B + c];
+                        rs[r] += fabs(sum);
+                    }
             }
+            for (int r = 0; r < B; ++r) m = rs[r] > m ? rs[r] : m;
+        }
     }
-    double m = 0.0;
-    for (int r = 0; r < B; ++r) m = rs[r] > m ? rs[r] : m;
-    atomicMax(lam, (unsigned long long)__double_as_longlong(m));
+    // nonnegative doubles order as their bit patterns
+    block_max_to((unsigned long long)__double_as_longlong(m), lam);
 }
 
 // P = -omega D^-1 (A P_tent) + P_tent  (rows of AP_t are those of P)
