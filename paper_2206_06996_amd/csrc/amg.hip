@@ -562,6 +562,23 @@ __global__ void fdiag_k(int64_t nr, int bb, const int32_t* __restrict__ rp, cons
     int32_t q = find_col(ci, rp[i], rp[i + 1], (int32_t)i);
     fd[i] = q >= 0 ? block_f(v + (int64_t)q * bb, bb) : 0.0;
 }
+// strength of the coupling at entry q = (i, j) of row i, symmetrised with (j, i)
+__device__ __forceinline__ uint8_t strong_entry(int64_t i, int32_t q, int bb, const int32_t* __restrict__ rp,
+                                                const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                const double* __restrict__ fd, double th4) {
+    int32_t j = ci[q];
+    if (j == i) return 0;
+    double fij = block_f(v + (int64_t)q * bb, bb);
+    bool s1 = (fij * fij) >= ((th4 * fd[i]) * fd[j]);
+    bool s2 = false;
+    int32_t t = find_col(ci, rp[j], rp[j + 1], (int32_t)i);
+    if (t >= 0) {
+        double fji = block_f(v + (int64_t)t * bb, bb);
+        s2 = (fji * fji) >= ((th4 * fd[j]) * fd[i]);
+    }
+    return (s1 || s2) ? 1 : 0;
+}
+
 __global__ void strength_k(int64_t nr, int bb, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                            const double* __restrict__ v, const double* __restrict__ fd, double th4,
                            uint8_t* __restrict__ flags, uint8_t* __restrict__ iso) {
@@ -569,23 +586,29 @@ __global__ void strength_k(int64_t nr, int bb, const int32_t* __restrict__ rp, c
     if (i >= nr) return;
     uint8_t any = 0;
     for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
-        int32_t j = ci[q];
-        uint8_t f = 0;
-        if (j != i) {
-            double fij = block_f(v + (int64_t)q * bb, bb);
-            bool s1 = (fij * fij) >= ((th4 * fd[i]) * fd[j]);
-            bool s2 = false;
-            int32_t t = find_col(ci, rp[j], rp[j + 1], (int32_t)i);
-            if (t >= 0) {
-                double fji = block_f(v + (int64_t)t * bb, bb);
-                s2 = (fji * fji) >= ((th4 * fd[j]) * fd[i]);
-            }
-            f = (s1 || s2) ? 1 : 0;
-        }
+        const uint8_t f = strong_entry(i, q, bb, rp, ci, v, fd, th4);
         flags[q] = f;
         any |= f;
     }
     iso[i] = any ? 0 : 1;
+}
+
+// the same with one wavefront per row, lanes over its entries (levels with long rows)
+__global__ void __launch_bounds__(256) strength_wave_k(int64_t nr, int bb, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                       const double* __restrict__ fd, double th4,
+                                                       uint8_t* __restrict__ flags, uint8_t* __restrict__ iso) {
+    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (i >= nr) return;
+    int any = 0;
+    for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += WAVE) {
+        const uint8_t f = strong_entry(i, q, bb, rp, ci, v, fd, th4);
+        flags[q] = f;
+        any |= f;
+    }
+    const uint64_t b = __ballot(any);
+    if (lane == 0) iso[i] = b ? 0 : 1;
 }
 
 // state word: top 2 bits = 0 out/isolated, 1 undecided, 2 in; low 62 bits = priority
@@ -608,15 +631,44 @@ __global__ void mis_max_k(int64_t nr, const int32_t* __restrict__ rp, const int3
         }
     out[i] = m;
 }
-__global__ void mis_decide_k(int64_t nr, uint64_t* __restrict__ st, const uint64_t* __restrict__ m2, int* __restrict__ und) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// the same with one wavefront per row (levels with long rows)
+__global__ void __launch_bounds__(256) mis_max_wave_k(int64_t nr, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ ci, const uint8_t* __restrict__ flags,
+                                                      const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
     if (i >= nr) return;
-    uint64_t s = st[i];
-    if ((s >> 62) != 1) return;
-    uint64_t m = m2[i];
-    if ((m >> 62) == 2) st[i] = s & KEYMASK;               // an IN node within distance 2
-    else if (m == s) st[i] = ST_IN | (s & KEYMASK);        // largest undecided priority within distance 2
-    else atomicAdd(und, 1);
+    uint64_t m = 0;
+    for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += WAVE)
+        if (flags[q]) {
+            uint64_t v = in[ci[q]];
+            m = v > m ? v : m;
+        }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        uint64_t w = __shfl_xor(m, o, WAVE);
+        m = w > m ? w : m;
+    }
+    if (lane == 0) {
+        const uint64_t self = in[i];
+        out[i] = self > m ? self : m;
+    }
+}
+// *und becomes nonzero if a node stays undecided (one atomic per workgroup at most)
+__global__ void __launch_bounds__(256) mis_decide_k(int64_t nr, uint64_t* __restrict__ st,
+                                                    const uint64_t* __restrict__ m2, int* __restrict__ und) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int left = 0;
+    if (i < nr) {
+        uint64_t s = st[i];
+        if ((s >> 62) == 1) {
+            uint64_t m = m2[i];
+            if ((m >> 62) == 2) st[i] = s & KEYMASK;               // an IN node within distance 2
+            else if (m == s) st[i] = ST_IN | (s & KEYMASK);        // largest undecided priority within distance 2
+            else left = 1;
+        }
+    }
+    if (__syncthreads_or(left) && threadIdx.x == 0) atomicOr(und, 1);
 }
 
 __global__ void root_flag_k(int64_t nr, const uint64_t* __restrict__ st, int32_t* __restrict__ isroot) {
@@ -1247,7 +1299,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         fdiag_k<<<g, 256, 0, s>>>(nr, bb, L.A.rp, L.A.ci, L.A.v, fd);
         double theta = std::ldexp(o.theta, -l);
         double th4 = ((theta * theta) * theta) * theta;
-        strength_k<<<g, 256, 0, s>>>(nr, bb, L.A.rp, L.A.ci, L.A.v, fd, th4, L.strong, iso);
+        // rows of 16 or more entries on average: one wavefront per row (same flags)
+        const bool wide = L.A.nnzb >= 16 * nr;
+        if (wide) strength_wave_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, bb, L.A.rp, L.A.ci, L.A.v, fd, th4, L.strong, iso);
+        else strength_k<<<g, 256, 0, s>>>(nr, bb, L.A.rp, L.A.ci, L.A.v, fd, th4, L.strong, iso);
         check_launch("strength");
         ar.free(fd);
         // MIS-2 rounds
@@ -1259,8 +1314,13 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         for (int round = 0;; ++round) {
             if (round > 100000) throw Error(SCR_E_HIP, "MIS-2 did not terminate");
             zero_dev(und, sizeof(int), s);
-            mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1);
-            mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2);
+            if (wide) {
+                mis_max_wave_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1);
+                mis_max_wave_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2);
+            } else {
+                mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1);
+                mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2);
+            }
             mis_decide_k<<<g, 256, 0, s>>>(nr, st, m2, und);
             check_launch("mis2");
             int hu = 0;
