@@ -794,6 +794,91 @@ __global__ void tentative_k(int64_t na, int b, int k, const int32_t* __restrict_
     }
 }
 
+// The same factorisation with one wavefront per aggregate and the aggregate's rows of Q in LDS
+// (rows in member order, k columns).  Every sum is taken by lane 0 in that row order, so the
+// rounding is that of tentative_k; the element-wise updates run on all lanes.
+__global__ void __launch_bounds__(WAVE) tentative_lds_k(int64_t na, int b, int k, const int32_t* __restrict__ mrp,
+                                                        const int32_t* __restrict__ mem, const double* __restrict__ B,
+                                                        double* __restrict__ Q, double* __restrict__ Bc,
+                                                        uint8_t* __restrict__ dead) {
+    extern __shared__ double q[];
+    __shared__ double bc[2];
+    __shared__ double rk[64];      // R of the aggregate (k <= 8)
+    __shared__ uint8_t dl[8];
+    const int64_t a = blockIdx.x;
+    if (a >= na) return;
+    const int lane = threadIdx.x;
+    const int32_t lo = mrp[a], hi = mrp[a + 1];
+    const int nrow = (hi - lo) * b;
+    for (int e = lane; e < nrow * k; e += WAVE) {
+        const int rr = e / k, c = e - rr * k;
+        const int t = rr / b, r = rr - t * b;
+        q[e] = B[((int64_t)mem[lo + t] * b + r) * k + c];
+    }
+    for (int e = lane; e < k * k; e += WAVE) rk[e] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        double nb = 0.0;
+        if (lane == 0) {
+            for (int rr = 0; rr < nrow; ++rr) nb += q[rr * k + j] * q[rr * k + j];
+            nb = sqrt(nb);
+        }
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < j; ++i) {
+                if (dl[i]) continue;           // written and synchronised when column i finished
+                if (lane == 0) {
+                    double c = 0.0;
+                    for (int rr = 0; rr < nrow; ++rr) c += q[rr * k + i] * q[rr * k + j];
+                    bc[0] = c;
+                    rk[i * k + j] += c;
+                }
+                __syncthreads();
+                const double c = bc[0];
+                for (int rr = lane; rr < nrow; rr += WAVE) q[rr * k + j] -= c * q[rr * k + i];
+                __syncthreads();
+            }
+        if (lane == 0) {
+            double nv = 0.0;
+            for (int rr = 0; rr < nrow; ++rr) nv += q[rr * k + j] * q[rr * k + j];
+            nv = sqrt(nv);
+            const bool isdead = (nb == 0.0) || (nv <= 1e-10 * nb);
+            dl[j] = isdead ? 1 : 0;
+            dead[a * k + j] = isdead ? 1 : 0;
+            rk[j * k + j] = isdead ? 0.0 : nv;
+            bc[1] = nv;
+        }
+        __syncthreads();
+        const double nv = bc[1];
+        const bool isdead = dl[j] != 0;
+        for (int rr = lane; rr < nrow; rr += WAVE) q[rr * k + j] = isdead ? 0.0 : q[rr * k + j] / nv;
+        __syncthreads();
+    }
+    for (int e = lane; e < nrow * k; e += WAVE) {
+        const int rr = e / k, c = e - rr * k;
+        const int t = rr / b, r = rr - t * b;
+        Q[((int64_t)mem[lo + t] * b + r) * k + c] = q[e];
+    }
+    for (int e = lane; e < k * k; e += WAVE) Bc[a * k * k + e] = rk[e];
+}
+
+// tentative prolongator of all aggregates: the LDS form when the largest aggregate fits
+static void tentative_run(int64_t na, int b, int k, const int32_t* mrp, const int32_t* mem, const double* B,
+                          double* Q, double* Bc, uint8_t* dead, Arena& ar, hipStream_t s) {
+    if (na <= 0) return;
+    int* mx = ar.make<int>(1);
+    zero_dev(mx, sizeof(int), s);
+    rowlen_max_k<<<cdiv(na, 256), 256, 0, s>>>(na, mrp, mx);
+    check_launch("agg_max");
+    int hm = 0;
+    HIPCHK(hipMemcpyAsync(&hm, mx, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ar.free(mx);
+    const size_t lds = (size_t)hm * b * k * sizeof(double);
+    if (k <= 8 && lds <= 48 * 1024) tentative_lds_k<<<(unsigned)na, WAVE, lds, s>>>(na, b, k, mrp, mem, B, Q, Bc, dead);
+    else tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, k, mrp, mem, B, Q, Bc, dead);
+    check_launch("tentative");
+}
+
 // P_tent as BSR: one b x k block per aggregated row
 __global__ void ptent_cnt_k(int64_t nr, const int32_t* __restrict__ agg, int32_t* __restrict__ cnt) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1371,8 +1456,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         N.B = ar.make<double>(na * kk * kk);
         L.dead = ar.make<uint8_t>(na * kk);
         zero_dev(L.dead, na * kk, s);
-        tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, kk, mrp, mem, L.B, Q, N.B, L.dead);
-        check_launch("tentative");
+        tentative_run(na, b, kk, mrp, mem, L.B, Q, N.B, L.dead, ar, s);
         ar.free(mcnt);
         L.mrp = mrp;
         L.mem = mem;
@@ -1439,8 +1523,7 @@ void update_hierarchy(Hierarchy& H, const double* vals0, const double* B0, Arena
         double* Q = ar.make<double>(nr * b * kk);
         zero_dev(Q, nr * b * kk * sizeof(double), s);
         zero_dev(L.dead, na * kk, s);
-        tentative_k<<<cdiv(na, 64), 64, 0, s>>>(na, b, kk, L.mrp, L.mem, L.B, Q, N.B, L.dead);
-        check_launch("tentative");
+        tentative_run(na, b, kk, L.mrp, L.mem, L.B, Q, N.B, L.dead, ar, s);
         DBsr Pt;
         Pt.nr = nr; Pt.nc = na; Pt.br = b; Pt.bc = kk;
         Pt.rp = ar.make<int32_t>(nr + 1);
