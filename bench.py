@@ -33,8 +33,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cfg1", "cfg4"], default="cfg1",
-                    help="cfg1: unified tube (300,899 nodes, FP64 headline); cfg4: Y-bifurcation (about 4.0M nodes, "
+    ap.add_argument("--workload", choices=["cfg1", "cfg2", "cfg4"], default="cfg1",
+                    help="cfg1: unified tube (300,899 nodes, FP64 headline); cfg2: the same tube refined (1,456,866 "
+                         "nodes, FP64 and mixed); cfg4: Y-bifurcation (about 4.0M nodes, "
                          "mixed headline)")
     ap.add_argument("--precond", choices=["scr", "simple", "simplec"], default="scr",
                     help="outer preconditioner: SCR (Algorithm 1), SIMPLE or SIMPLEC (Sec. 5.2.1)")
@@ -44,7 +45,7 @@ def parse():
                     help="cfg1 with the advective Poiseuille state (u_max = 30 cm/s; nonsymmetric velocity block) "
                          "and the outlet resistance coupling (m = 1000) attached in every step")
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default=None,
-                    help="default: both for cfg1, mixed for cfg4")
+                    help="default: both for cfg1 and cfg2, mixed for cfg4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -370,8 +371,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     t0 = time.time()
     if args.precision is None:
-        args.precision = "both" if args.workload == "cfg1" else "mixed"
-    prm = synth.cfg1_params() if args.workload == "cfg1" else synth.cfg4_params()
+        args.precision = "mixed" if args.workload == "cfg4" else "both"
+    prm = {"cfg1": synth.cfg1_params, "cfg2": synth.cfg2_params, "cfg4": synth.cfg4_params}[args.workload]()
     if args.flow:
         if args.workload != "cfg1":
             raise SystemExit("--flow runs on cfg1 only")
@@ -384,6 +385,9 @@ def main():
         if args.flow:
             workload += (f"; advective Poiseuille state u_max = {FLOW_U_MAX:g} cm/s (Oseen VMS tangent, nonsymmetric A) "
                          f"and the outlet resistance coupling m = {FLOW_M:g} over {len(s.outlets[0][0])} outlet nodes")
+    elif args.workload == "cfg2":
+        workload = (f"cfg2 unified fluid+solid tube refined, 69x69x306 ({s.n_phys:,} nodes, {s.n_b:,} block rows, "
+                    f"{s.nnzb:,} 4x4 blocks) + mesh motion ({s.n_phys:,} x 3)")
     else:
         workload = (f"cfg4 Y-bifurcation, voxel mesh (parent R=1, daughters 0.7 at seeded angles, wall 1.2x; "
                     f"{s.n_phys:,} nodes, {s.n_b:,} block rows, {s.nnzb:,} 4x4 blocks) + mesh motion ({s.n_phys:,} x 3)")
@@ -406,6 +410,7 @@ def main():
         del src, dst
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     results = {}
+    x_last = {}
     for prec in precisions:
         p = scr.SCR_MIXED if prec == "mixed" else scr.SCR_FP64
         ao = scr.amg_opts(precision=p, schur_diag=1 if args.precond == "simplec" else 0)
@@ -445,6 +450,7 @@ def main():
                 args)
         torch.cuda.synchronize()
         region = time.perf_counter() - region
+        x_last[prec] = x.clone()       # solution of the last step's right-hand side (same in both precisions)
         # numeric re-setup (outside the timed region): new values on the same pattern, aggregates kept
         h = scr.amg_setup(ctx, scr.SCR_SYSTEM, rp, ci, val, xyz, ao)
         upd_ms = []
@@ -523,6 +529,12 @@ def main():
         if rr["prof"]:
             out[prec]["smoother_l0_avg_us"] = round(rr["prof"]["avg_us"], 2)
             out[prec]["smoother_l0_GBps"] = round(rr["prof"]["gbs"], 1)
+    if "fp64" in x_last and "mixed" in x_last:
+        # velocity and pressure apart: the solution norm is dominated by the pressure
+        xd, xm_ = x_last["fp64"].view(-1, 4), x_last["mixed"].view(-1, 4)
+        out["mixed_vs_fp64_rel_diff"] = {
+            "velocity": float((xm_[:, :3] - xd[:, :3]).norm() / xd[:, :3].norm()),
+            "pressure": float((xm_[:, 3] - xd[:, 3]).norm() / xd[:, 3].norm())}
     out["assembly"] = {"ms": round(float(np.median(asm_ms[1:])), 3), "n_tets": int(s.n_tets),
                        "advective": bool(prm.u_max), "max_rel_diff_vs_input": kdiff}
     pr = r["prof"]
