@@ -243,6 +243,7 @@ scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv,
  * gives non-finite values (amg_setup and amg_update reject them).  Returns after completion. */
 scr_status scr_assemble_tangent(scr_assembler* a, const double* u, double* val, void* stream);
 int64_t scr_assembler_nnzb(const scr_assembler* a);
+int64_t scr_assembler_nbrows(const scr_assembler* a);
 scr_status scr_assembler_destroy(scr_assembler* a);
 
 /* Opt-in kernel timing (roofline measurement).  After scr_ctx_profile(ctx, kernel), every launch
@@ -302,7 +303,8 @@ scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const sc
  * budget is rejected (SCR_E_OOM), never queued forever.  Each request builds its hierarchies
  * once (amg_setup) and reuses them for its n_rhs successive corrections (the multi-corrector
  * loop of Sec. 3.5), and for its mesh-motion solves when L is given.  The tangent is frozen
- * unless the request gives new values for a correction: then the hierarchies are re-set up
+ * unless the request gives new values for a correction, or a new advective velocity with an
+ * assembler (the tangent is then assembled on the device): the hierarchies are re-set up
  * numerically (amg_update) before that correction's solve.
  * All device arrays of a request are borrowed until srv_wait/srv_poll reports it done. */
 typedef struct scr_server scr_server;
@@ -320,6 +322,17 @@ typedef struct {
                                       (c >= 1; NULL keeps the previous values) are the K values of
                                       correction c on K's pattern (nnzb * 16 each); vals[0] is
                                       ignored (K.val is the first correction's matrix) */
+    scr_assembler* tangent;        /* NULL, or an assembler created on K's pattern (same n_brows and
+                                      nnzb): the tangents are then assembled on the device at the
+                                      advective velocities u, and vals is not read.  The first
+                                      correction's matrix is the tangent at u[0] (NULL = at rest)
+                                      and K.val is not read; for c >= 1 a non-NULL u[c] gives a new
+                                      tangent, assembled and re-set up numerically before that
+                                      correction's solve (NULL keeps the previous one).  The values
+                                      live in a buffer of 16 nnzb FP64 that the request holds while
+                                      it runs (counted in its footprint).  One assembler may serve
+                                      requests that run concurrently. */
+    const double* const* u;        /* n_rhs device pointers (n_brows x 3 each, or NULL), if tangent */
 } scr_request;
 
 typedef struct {

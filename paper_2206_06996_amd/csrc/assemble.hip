@@ -482,6 +482,7 @@ scr_status scr_assemble_tangent(scr_assembler* A, const double* u, double* val, 
 }
 
 int64_t scr_assembler_nnzb(const scr_assembler* A) { return A ? A->nnzb : 0; }
+int64_t scr_assembler_nbrows(const scr_assembler* A) { return A ? A->nb : 0; }
 
 scr_status scr_assembler_destroy(scr_assembler* A) {
     if (!A) return SCR_OK;

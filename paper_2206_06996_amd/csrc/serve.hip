@@ -6,7 +6,8 @@
 // start as soon as a finishing request releases its slot and memory.  Kernels of different
 // requests overlap on the device through the slots' streams.  Each request builds its
 // hierarchies once and reuses them for all of its successive corrections, re-set up numerically
-// when a correction brings new matrix values.
+// when a correction brings new matrix values (given, or assembled on the device from the
+// request's mesh at a new advective velocity).
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -24,7 +25,8 @@ struct Job {
     int64_t id = 0;
     scr_bsr K{};
     const double* coords = nullptr;
-    std::vector<const double*> b, bm, vals;
+    std::vector<const double*> b, bm, vals, u;
+    scr_assembler* tangent = nullptr;   // tangents assembled on the device at u[c]
     std::vector<double*> x, xm;
     bool has_L = false;
     scr_bsr L{};
@@ -60,8 +62,21 @@ void run_job(scr_server* S, Job* j, hipStream_t st) {
     r.status = SCR_OK;
     scr_handle* h = nullptr;
     scr_handle* hm = nullptr;
+    double* kval = nullptr;            // assembled tangent values (16 nnzb), if j->tangent
     auto t0 = Clock::now();
-    scr_status rc = amg_setup(S->ctx, SCR_SYSTEM, &j->K, j->coords, &S->amg, st, &h);
+    scr_bsr K0 = j->K;
+    scr_status rc = SCR_OK;
+    if (j->tangent) {
+        if (hipMallocAsync(reinterpret_cast<void**>(&kval), (size_t)j->K.nnzb * 16 * sizeof(double), st) != hipSuccess) {
+            (void)hipGetLastError();
+            kval = nullptr;
+            rc = SCR_E_OOM;
+        } else {
+            rc = scr_assemble_tangent(j->tangent, j->u.empty() ? nullptr : j->u[0], kval, st);
+            K0.val = kval;
+        }
+    }
+    if (rc == SCR_OK) rc = amg_setup(S->ctx, SCR_SYSTEM, &K0, j->coords, &S->amg, st, &h);
     if (rc == SCR_OK && j->has_L) rc = amg_setup(S->ctx, MESH_SYSTEM, &j->L, nullptr, &S->amg, st, &hm);
     r.setup_ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
     if (rc != SCR_OK) {
@@ -70,12 +85,22 @@ void run_job(scr_server* S, Job* j, hipStream_t st) {
         r.device_bytes = scr_handle_bytes(h) + (hm ? scr_handle_bytes(hm) : 0);
         auto t1 = Clock::now();
         for (size_t c = 0; c < j->b.size(); ++c) {
-            if (c > 0 && !j->vals.empty() && j->vals[c]) {
+            const double* newval = nullptr;
+            auto tu = Clock::now();
+            scr_status ru = SCR_OK;
+            if (c > 0 && j->tangent && !j->u.empty() && j->u[c]) {
+                ru = scr_assemble_tangent(j->tangent, j->u[c], kval, st);
+                newval = kval;
+            } else if (c > 0 && !j->tangent && !j->vals.empty() && j->vals[c]) {
+                newval = j->vals[c];
+            }
+            if (ru == SCR_OK && newval) {
                 // a new tangent for this correction: numeric re-setup on the same pattern
-                auto tu = Clock::now();
                 scr_bsr Kc = j->K;
-                Kc.val = j->vals[c];
-                scr_status ru = amg_update(h, &Kc, nullptr, st);
+                Kc.val = newval;
+                ru = amg_update(h, &Kc, nullptr, st);
+            }
+            if (newval || ru != SCR_OK) {
                 r.setup_ms += std::chrono::duration<double, std::milli>(Clock::now() - tu).count();
                 if (ru != SCR_OK) {
                     r.status = ru;
@@ -101,6 +126,10 @@ void run_job(scr_server* S, Job* j, hipStream_t st) {
     }
     if (h) scr_handle_destroy(h);
     if (hm) scr_handle_destroy(hm);
+    if (kval) {
+        (void)hipFreeAsync(kval, st);
+        (void)hipStreamSynchronize(st);
+    }
 }
 
 void worker(scr_server* S, int slot) {
@@ -187,18 +216,26 @@ scr_status srv_submit(scr_server* S, const scr_request* r, int64_t* id) {
         scr::set_last_error("srv_submit: mesh right-hand sides and outputs are required with L");
         return SCR_E_INVALID;
     }
+    if (r->tangent && (scr_assembler_nnzb(r->tangent) != r->K.nnzb ||
+                       scr_assembler_nbrows(r->tangent) != r->K.n_brows)) {
+        scr::set_last_error("srv_submit: the assembler was not created on K's pattern");
+        return SCR_E_INVALID;
+    }
     auto* j = new Job();
     j->K = r->K;
+    j->tangent = r->tangent;
     j->coords = r->coords;
     for (int c = 0; c < r->n_rhs; ++c) {
         j->b.push_back(r->b[c]);
         j->x.push_back(r->x[c]);
         if (r->L) { j->bm.push_back(r->bm[c]); j->xm.push_back(r->xm[c]); }
         if (r->vals) j->vals.push_back(r->vals[c]);
+        if (r->tangent && r->u) j->u.push_back(r->u[c]);
     }
     if (r->L) { j->has_L = true; j->L = *r->L; }
     j->footprint = scr_footprint_estimate(SCR_SYSTEM, r->K.n_brows, r->K.nnzb, &S->amg, &S->solve);
     if (r->L) j->footprint += scr_footprint_estimate(MESH_SYSTEM, r->L->n_brows, r->L->nnzb, &S->amg, &S->solve);
+    if (r->tangent) j->footprint += r->K.nnzb * 16 * (int64_t)sizeof(double);
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->budget > 0 && j->footprint > S->budget) {
         delete j;

@@ -28,7 +28,7 @@ EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", 
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
             "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
             "srv_destroy", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_nnzb",
-            "scr_assembler_destroy"]
+            "scr_assembler_nbrows", "scr_assembler_destroy"]
 SCR_PROF_OFF, SCR_PROF_SMOOTH_A0 = 0, 1
 
 
@@ -74,7 +74,8 @@ class Stats(C.Structure):
 
 class ScrRequest(C.Structure):
     _fields_ = [("K", ScrBsr), ("coords", P), ("n_rhs", C.c_int), ("b", C.POINTER(P)), ("x", C.POINTER(P)),
-                ("L", C.POINTER(ScrBsr)), ("bm", C.POINTER(P)), ("xm", C.POINTER(P)), ("vals", C.POINTER(P))]
+                ("L", C.POINTER(ScrBsr)), ("bm", C.POINTER(P)), ("xm", C.POINTER(P)), ("vals", C.POINTER(P)),
+                ("tangent", P), ("u", C.POINTER(P))]
 
 
 class SrvResult(C.Structure):
@@ -140,6 +141,8 @@ def lib():
         L.scr_assemble_tangent.argtypes = [P, P, P, P]
         L.scr_assembler_nnzb.argtypes = [P]
         L.scr_assembler_nnzb.restype = C.c_int64
+        L.scr_assembler_nbrows.argtypes = [P]
+        L.scr_assembler_nbrows.restype = C.c_int64
         L.scr_assembler_destroy.argtypes = [P]
         for f in ("amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
@@ -414,11 +417,13 @@ class Server:
         _check(lib().srv_create(ctx.ptr, max_slots, hbm_budget, C.byref(amg) if amg else None,
                                 C.byref(solve) if solve else None, C.byref(self.ptr)))
 
-    def submit(self, K, coords, bs, xs, L=None, bms=None, xms=None, vals=None) -> int:
+    def submit(self, K, coords, bs, xs, L=None, bms=None, xms=None, vals=None, tangent=None, us=None) -> int:
         """K = (row_ptr, col_idx, val) tensors of the 4x4 system; bs/xs lists of RHS/output tensors;
         L = (row_ptr, col_idx, val) of the mesh Laplacian with bms/xms lists (optional); vals = a
         list with one entry per correction: None (keep the previous tangent) or the K values of
-        that correction on K's pattern (the first entry is ignored)."""
+        that correction on K's pattern (the first entry is ignored).  tangent = an Assembler on K's
+        pattern with us = one advective velocity per correction (a (n_brows, 3) tensor or None):
+        the tangents are then assembled on the device (the first at us[0], None = at rest)."""
         import torch
         n = len(bs)
         barr = (P * n)(*[_dev(b, torch.float64, "b") for b in bs])
@@ -436,6 +441,16 @@ class Server:
                              for c, v in enumerate(vals)])
             req.vals = varr
             keep += [vals, varr]
+        if tangent is not None:
+            req.tangent = tangent.ptr
+            keep.append(tangent)
+            if us is not None:
+                for u in us:
+                    if u is not None and u.numel() != 3 * tangent.n_brows:
+                        raise ValueError("each u must hold 3 * n_brows values")
+                uarr = (P * n)(*[None if u is None else _dev(u, torch.float64, "u") for u in us])
+                req.u = uarr
+                keep += [us, uarr]
         rid = C.c_int64()
         _check(lib().srv_submit(self.ptr, C.byref(req), C.byref(rid)))
         self._keep[rid.value] = keep

@@ -174,3 +174,54 @@ def test_new_tangent_per_correction_matches_sequential_re_setups(scr):
     srv.destroy()
     assert ctx.bytes_in_use() == 0
     ctx.destroy()
+
+
+def test_tangents_assembled_per_correction_match_sequential(scr):
+    # three corrections at advective states 0, u and 2u (tangents assembled on the device from the
+    # mesh): the server gives bitwise what assemble -> setup -> solve -> assemble -> amg_update ->
+    # solve on one handle gives; a request with a frozen tangent runs beside it
+    from oracle import assembly as asm
+    p = synth.default_params(mode=0, m_core=2, n_bl=1, n_wall=1, nz=8, R=1.0, L=2.0, u_max=20.0)
+    s = synth.generate(p, tets=True)
+    ctx = scr.Context(0)
+    a = scr.scr_assembler_create(ctx, dev(s.tv), dev(s.tp), dev(s.tsolid), dev(s.rp), dev(s.ci),
+                                 dev(s.xyz.reshape(-1)), dev(s.mask), scr.tangent_params(**asm.params_of(p)))
+    us = [None, dev(s.uadv), dev(2.0 * s.uadv)]
+    K = (dev(s.rp), dev(s.ci), dev(s.val.reshape(-1)))
+    coords = dev(s.xyz.reshape(-1))
+    bs = [dev(synth.rhs(800 + c, 4 * s.n_b, s.mask)) for c in range(3)]
+    ref, h = [], None
+    for c in range(3):
+        val = torch.empty(16 * a.nnzb, dtype=torch.float64, device="cuda")
+        scr.scr_assemble_tangent(a, us[c], val)
+        if c == 0:
+            h = scr.amg_setup(ctx, scr.SCR_SYSTEM, K[0], K[1], val, coords)
+        else:
+            scr.amg_update(h, K[0], K[1], val)
+        x = torch.zeros_like(bs[c])
+        rc, _ = scr.scr_solve(h, bs[c], x)
+        assert rc == 0
+        ref.append(x.cpu().numpy())
+    h.destroy()
+    srv = scr.Server(ctx, max_slots=2)
+    xs = [torch.full_like(b, np.nan) for b in bs]
+    xf = [torch.full_like(b, np.nan) for b in bs]
+    i_asm = srv.submit(K, coords, bs, xs, tangent=a, us=us)
+    i_frozen = srv.submit(K, coords, bs, xf)
+    ra, rf = srv.wait(i_asm), srv.wait(i_frozen)
+    assert ra["status"] == 0 and rf["status"] == 0 and ra["n_solves"] == 3
+    for c in range(3):
+        assert np.array_equal(xs[c].cpu().numpy(), ref[c])
+    assert not np.array_equal(xf[2].cpu().numpy(), ref[2])      # the frozen tangent is another system
+    # an assembler on another pattern is rejected at submission
+    p2 = synth.default_params(mode=0, m_core=2, n_bl=1, n_wall=1, nz=6, R=1.0, L=2.0)
+    s2 = synth.generate(p2, tets=True)
+    a2 = scr.scr_assembler_create(ctx, dev(s2.tv), dev(s2.tp), dev(s2.tsolid), dev(s2.rp), dev(s2.ci),
+                                  dev(s2.xyz.reshape(-1)), dev(s2.mask), scr.tangent_params(**asm.params_of(p2)))
+    with pytest.raises(scr.ScrError) as e:
+        srv.submit(K, coords, bs, xs, tangent=a2)
+    assert e.value.status == scr.SCR_E_INVALID
+    srv.destroy()
+    a.destroy(); a2.destroy()
+    assert ctx.bytes_in_use() == 0
+    ctx.destroy()
