@@ -200,8 +200,9 @@ int64_t scr_handle_bytes(const scr_handle* h);
  *             + tau_C V dN_a,i dN_b,j                                          (fluid only)
  *             + delta_ij [rho V/4 ub.dN_b + tau_M rho^2 ub.dN_a (c_t V/4 + V ub.dN_b)]
  *             + rho M_ab (grad u)_ij                                          (fluid, u given)
- *   G_ab,i  = -V/4 dN_a,i + tau_M rho V ub.dN_a dN_b,i
- *   D_ab,j  =  V/4 dN_b,j + tau_M rho V dN_a,j ub.dN_b  [+ c_t rho tau_M V/4 dN_a,j]
+ *   G_ab,i  = -V/4 dN_a,i  + tau_M rho V ub.dN_a dN_b,i                      (2nd: fluid, u given)
+ *   D_ab,j  =  V/4 dN_b,j  + tau_M rho V dN_a,j ub.dN_b  [+ c_t rho tau_M V/4 dN_a,j]
+ *                                             (2nd: fluid, u given; bracket: fluid, vms_dt_coupling)
  *   C_ab    =  tau_M L_ab (fluid),  (c_t / kappa) M_ab (solid)
  * with visc = mu_f (fluid), (alpha_f gamma dt / alpha_m) mu_s (solid), mu_s = E/(2(1+nu)),
  * kappa = E/(3(1-2nu)), and tau_M, tau_C of Sec. 3.2 from the element metric J^-T M J^-1 (M the
@@ -244,6 +245,8 @@ scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv,
 scr_status scr_assemble_tangent(scr_assembler* a, const double* u, double* val, void* stream);
 int64_t scr_assembler_nnzb(const scr_assembler* a);
 int64_t scr_assembler_nbrows(const scr_assembler* a);
+/* Release the assembler's device memory.  Every assembly that uses it, on any stream or in a
+ * server request, must have finished. */
 scr_status scr_assembler_destroy(scr_assembler* a);
 
 /* Opt-in kernel timing (roofline measurement).  After scr_ctx_profile(ctx, kernel), every launch
