@@ -1214,11 +1214,13 @@ class HierT : public Hierarchy {
     }
 
     // algorithmic bytes of one smoother step with a matrix product: every stored block (values
-    // and column index) once, x once, the right-hand side, D^-1, the output and d as used
+    // and column index) once, x once, the right-hand side, the output, d as used, and D^-1 where
+    // the kernel reads it (the FP32 block-row-lane kernels solve with the diagonal block they stream)
     double step_bytes(const LS& q, bool rd, bool wd) const {
         const double b = q.A.br, t = sizeof(T);
         double rows = (double)q.A.nr;
-        return (double)q.A.nnzb * (b * b * t + 4.0) + rows * (b * t * 3.0 + b * b * t + (rd ? b * t : 0.0) + (wd ? b * t : 0.0));
+        const double dinv = (q.A.rowlane && sizeof(T) == 4) ? 0.0 : b * b * t;
+        return (double)q.A.nnzb * (b * b * t + 4.0) + rows * (b * t * 3.0 + dinv + (rd ? b * t : 0.0) + (wd ? b * t : 0.0));
     }
 
     // smoothing sweeps from xin (nullptr = zero) into dst
