@@ -90,6 +90,8 @@ typedef struct {
     int schur_diag;            /* SCR_SYSTEM: the diagonal d in S^ = C - D d^-1 G (Sec. 5.2.1):
                                   SCR_DIAG_A (default) the diagonal of A; SCR_DIAG_ABSROWSUM the sums
                                   of the absolute values of A's rows (the SIMPLEC lumping) */
+    int schur_cheb_degree;     /* SCR_SYSTEM: Chebyshev degree of AMG(S^), 8 (0 = cheb_degree) */
+    double schur_cheb_ratio;   /* SCR_SYSTEM: Chebyshev interval ratio of AMG(S^), 100 (0 = cheb_ratio) */
 } scr_amg_opts;
 
 /* Krylov options.  Defaults: tol 1e-8 (outer), tol_A = tol_S = tol_I = 1e-3 and 200

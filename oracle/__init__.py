@@ -33,7 +33,7 @@ class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("smoother", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("jacobi_sweeps", C.c_int), ("coarse_max", C.c_int),
                 ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
-                ("schur_diag", C.c_int)]
+                ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -57,7 +57,8 @@ def amg_opts(**kw) -> AmgOpts:
     """Defaults: theta=0.08 (halved per level), Chebyshev degree 2 on [lam/30, lam], coarse
     solve below 1024 unknowns, at most 10 levels, stop if coarsening is slower than 0.8."""
     o = AmgOpts(theta=0.08, smoother=1, cheb_degree=5, cheb_ratio=30.0, jacobi_sweeps=2,
-                coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0)
+                coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0,
+                schur_cheb_degree=8, schur_cheb_ratio=100.0)
     for k, v in kw.items():
         setattr(o, k, v)
     return o

@@ -224,6 +224,8 @@ typedef struct {
     uint64_t seed;
     int schur_diag;      /* SCR system setup: diagonal used in S^ = C - D d^-1 G:
                             0 the diagonal of A (SCR, SIMPLE), 1 absolute row sums of A (SIMPLEC) */
+    int schur_cheb_degree;     /* SCR system: Chebyshev degree of AMG(S^) (0 = cheb_degree) */
+    double schur_cheb_ratio;   /* SCR system: Chebyshev interval ratio of AMG(S^) (0 = cheb_ratio) */
 } amg_opts;
 
 #define MAXLEV 16
@@ -1120,7 +1122,10 @@ int orc_scr_create(int64_t nb, const int32_t* rp, const int32_t* ci, const doubl
     free(B);
     double* ones = (double*)malloc(sizeof(double) * nb);
     for (int64_t i = 0; i < nb; ++i) ones[i] = 1.0;
-    s->amgS = amg_build(s->Sh, ones, 1, ao);
+    amg_opts oS = *ao;
+    if (ao->schur_cheb_degree > 0) oS.cheb_degree = ao->schur_cheb_degree;
+    if (ao->schur_cheb_ratio > 0) oS.cheb_ratio = ao->schur_cheb_ratio;
+    s->amgS = amg_build(s->Sh, ones, 1, &oS);
     free(ones);
     *out = s;
     if (!s->amgA || !s->amgS) return -1;

@@ -294,6 +294,8 @@ void scr_default_amg_opts(scr_amg_opts* o) {
     o->theta = 0.08;
     o->smoother = SCR_SMOOTH_CHEBYSHEV;
     o->cheb_degree = 5;
+    o->schur_cheb_degree = 8;
+    o->schur_cheb_ratio = 100.0;
     o->cheb_ratio = 30.0;
     o->jacobi_sweeps = 2;
     o->coarse_max = 1024;
@@ -408,7 +410,8 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         const scr_amg_opts& o = h->opts;
         if (o.precision != SCR_FP64 && o.precision != SCR_MIXED) throw Error(SCR_E_INVALID, "precision");
         if (!(o.theta > 0) || o.coarse_max < 1 || o.max_levels < 1 || o.cheb_degree < 1 || o.jacobi_sweeps < 1 ||
-            !(o.cheb_ratio > 1) || !(o.max_coarse_ratio > 0))
+            !(o.cheb_ratio > 1) || !(o.max_coarse_ratio > 0) || o.schur_cheb_degree < 0 ||
+            !(o.schur_cheb_ratio == 0.0 || o.schur_cheb_ratio > 1))
             throw Error(SCR_E_INVALID, "AMG options out of range");
         h->ar.reset(new Arena(&ctx->c, s));
         Arena& ar = *h->ar;
@@ -454,7 +457,12 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
             h->hA = build_hierarchy(h->A, h->B, 6, o, ar, s, pa);
             double* ones = ar.make<double>(nb);
             fill<double>(ones, 1.0, nb, s);
-            h->hS = build_hierarchy(h->Sh, ones, 1, o, ar, s);
+            // AMG(S^) with its own Chebyshev settings: its V-cycles are cheap (scalar, small), and
+            // each Schur iteration saved also saves an inner A solve of Algorithm 2
+            scr_amg_opts oS = o;
+            if (o.schur_cheb_degree > 0) oS.cheb_degree = o.schur_cheb_degree;
+            if (o.schur_cheb_ratio > 0) oS.cheb_ratio = o.schur_cheb_ratio;
+            h->hS = build_hierarchy(h->Sh, ones, 1, oS, ar, s);
             ar.free(ones);
             h->Ks = sell_from_bsr<double>(Km, ar, s);
             h->As = sell_from_bsr<double>(h->A, ar, s);
