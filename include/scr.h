@@ -80,7 +80,7 @@ typedef struct {
                                   of Algorithm 1 and every true residual stay FP64 */
     double theta;              /* strength threshold at level 0 (halved per level), 0.08 */
     int smoother;              /* scr_smoother, default Chebyshev */
-    int cheb_degree;           /* 5 */
+    int cheb_degree;           /* 4 */
     double cheb_ratio;         /* lower end of the Chebyshev interval = lambda_hat / ratio, 30 */
     int jacobi_sweeps;         /* 2 */
     int coarse_max;            /* direct solve once a level has <= coarse_max unknowns, 1024 */

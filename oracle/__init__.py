@@ -56,7 +56,7 @@ class ScrStats(C.Structure):
 def amg_opts(**kw) -> AmgOpts:
     """Defaults: theta=0.08 (halved per level), Chebyshev degree 2 on [lam/30, lam], coarse
     solve below 1024 unknowns, at most 10 levels, stop if coarsening is slower than 0.8."""
-    o = AmgOpts(theta=0.08, smoother=1, cheb_degree=5, cheb_ratio=30.0, jacobi_sweeps=2,
+    o = AmgOpts(theta=0.08, smoother=1, cheb_degree=4, cheb_ratio=30.0, jacobi_sweeps=2,
                 coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0,
                 schur_cheb_degree=8, schur_cheb_ratio=100.0)
     for k, v in kw.items():

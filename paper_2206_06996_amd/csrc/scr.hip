@@ -293,7 +293,7 @@ void scr_default_amg_opts(scr_amg_opts* o) {
     o->precision = SCR_FP64;
     o->theta = 0.08;
     o->smoother = SCR_SMOOTH_CHEBYSHEV;
-    o->cheb_degree = 5;
+    o->cheb_degree = 4;
     o->schur_cheb_degree = 8;
     o->schur_cheb_ratio = 100.0;
     o->cheb_ratio = 30.0;
