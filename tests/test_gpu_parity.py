@@ -138,6 +138,32 @@ def test_vcycle_parity_fp64(scr, ctx, small_fsi, smoother):
     h.destroy()
 
 
+@pytest.mark.parametrize("deg,ratio", [(3, 30.0), (0, 0.0)])
+def test_schur_smoother_options_parity(scr, ctx, small_fsi, deg, ratio):
+    # AMG(S^) with its own Chebyshev setting (0 = the setting of AMG(A)) on both sides
+    s = small_fsi
+    kw = dict(coarse_max=60, schur_cheb_degree=deg, schur_cheb_ratio=ratio)
+    h = gpu_setup(scr, ctx, s, **kw)
+    o = orc_setup(s, **kw)
+    od = orc_setup(s, coarse_max=60)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, s.n_b)
+    y = torch.empty(s.n_b, dtype=torch.float64, device="cuda")
+    scr.scr_apply(h, "VS", dev(x), y)
+    yo, yd = o.apply("VS", x), od.apply("VS", x)
+    assert np.linalg.norm(host(y) - yo) <= 1e-10 * np.linalg.norm(yo)
+    assert np.linalg.norm(yo - yd) > 1e-6 * np.linalg.norm(yd)      # the option changes the cycle
+    h.destroy()
+
+
+def test_invalid_schur_smoother_options_rejected(scr, ctx, small_fsi):
+    for kw in (dict(schur_cheb_degree=-1), dict(schur_cheb_ratio=0.5)):
+        with pytest.raises(scr.ScrError) as e:
+            gpu_setup(scr, ctx, small_fsi, **kw)
+        assert e.value.status == scr.SCR_E_INVALID
+    assert ctx.bytes_in_use() == 0
+
+
 def test_vcycle_mixed_is_close_to_fp64(scr, ctx, small_fsi):
     s = small_fsi
     h = gpu_setup(scr, ctx, s, coarse_max=60, precision=scr.SCR_MIXED)
