@@ -166,3 +166,15 @@ def test_rows_subset_matches_full_assembly():
     for r in rows:
         sl = slice(s.rp[r], s.rp[r + 1])
         assert np.array_equal(part[sl], full[sl])
+
+
+def test_generalized_alpha_constants_special_cases():
+    # rho_inf = 1: no high-frequency damping, alpha_m = alpha_f = gamma = 1/2 (trapezoidal rule);
+    # rho_inf = 0: alpha_m = 3/2, alpha_f = gamma = 1; in general gamma = 1/(1 + rho_inf) and the
+    # scheme keeps second order (gamma = 1/2 + alpha_m - alpha_f)
+    assert asm.genalpha(1.0) == (0.5, 0.5, 0.5)
+    assert asm.genalpha(0.0) == (1.5, 1.0, 1.0)
+    for r in (0.2, 0.5, 0.8):
+        am, af, g = asm.genalpha(r)
+        assert abs(g - 1.0 / (1.0 + r)) < 1e-15 and abs(af - 1.0 / (1.0 + r)) < 1e-15
+        assert abs(am - (3.0 - r) / (2.0 * (1.0 + r))) < 1e-15
