@@ -665,3 +665,117 @@ def test_algorithm2_with_outlets_uses_the_coupled_velocity_block(flow_fsi):
     # the A and K operators
     xv = np.random.default_rng(10).normal(size=3 * s.n_b)
     assert np.allclose(o.apply("A", xv), Af @ xv, rtol=0, atol=1e-12 * np.abs(Af @ xv).max())
+
+
+# ----------------------------------------------------------------------------- near-null space of AMG(A)
+def _p1_gradients(x4):
+    """Gradients of the four P1 shape functions of a tetrahedron (rows), from J^-1."""
+    J = (x4[1:] - x4[0]).T                       # columns x_a - x_0, a = 1..3
+    G = np.linalg.inv(J)                         # row a - 1 of J^-1 is grad N_a, a = 1..3
+    return np.vstack([-G.sum(0), G])
+
+
+def _rigid_mode_errors(s, B):
+    """For each column of the velocity near-null space B ((3 n_b) x 6), the largest symmetric
+    gradient of its P1 interpolant over the mesh's elements, relative to the largest gradient;
+    and the constant skew part (the rotation vector) of each column's gradient."""
+    sym = np.zeros(B.shape[1]); skew = np.zeros((B.shape[1], 3)); gmax = np.zeros(B.shape[1])
+    for e in range(s.n_tets):
+        rows = s.tv[e]
+        dN = _p1_gradients(s.xyz[rows])
+        for c in range(B.shape[1]):
+            u = B[:, c].reshape(-1, 3)[rows]     # nodal velocities of the element (4 x 3)
+            grad = u.T @ dN                      # du_i/dx_j
+            sym[c] = max(sym[c], np.abs(grad + grad.T).max() / 2)
+            gmax[c] = max(gmax[c], np.abs(grad).max())
+            w = (grad - grad.T) / 2
+            skew[c] = (w[2, 1], w[0, 2], w[1, 0])
+    return sym, gmax, skew
+
+
+@pytest.mark.parametrize("which", ["small_fsi", "cfg0"])
+def test_near_null_space_of_A_is_the_six_rigid_motions(which, request):
+    # Sec. 5.2.1 preconditions A with AMG(A); its near-null space must be the rigid motions that
+    # the deviatoric operator annihilates: three translations (zero gradient, value e_c) and
+    # three rotations (zero symmetric gradient, constant skew gradient about z, x, y).
+    s = request.getfixturevalue(which)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz)
+    B = o.amgA.get(0, "B")
+    assert B.shape == (3 * s.n_b, 6)
+    sym, gmax, skew = _rigid_mode_errors(s, B)
+    assert np.all(sym <= 1e-12 * np.maximum(gmax, 1.0)), sym
+    for c in range(3):
+        assert gmax[c] <= 1e-12
+        assert np.array_equal(B[:, c].reshape(-1, 3), np.tile(np.eye(3)[c], (s.n_b, 1)))
+    for c, axis in zip(range(3, 6), (2, 0, 1)):
+        assert np.allclose(skew[c], np.eye(3)[axis], atol=1e-12)
+    # the six columns are independent on the mesh
+    assert np.linalg.matrix_rank(B) == 6
+
+
+def test_near_null_space_check_catches_a_flipped_rotation_sign(small_fsi):
+    # the check above is sensitive: one sign flipped in a rotation column breaks it
+    s = small_fsi
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz)
+    B = o.amgA.get(0, "B").copy()
+    Bv = B.reshape(-1, 3, 6)
+    Bv[:, 1, 3] = -Bv[:, 1, 3]                   # u = (-y, x, 0) becomes (-y, -x, 0)
+    sym, gmax, _ = _rigid_mode_errors(s, Bv.reshape(-1, 6))
+    assert sym[3] > 0.5 and np.all(sym[[0, 1, 2, 4, 5]] <= 1e-12 * np.maximum(gmax[[0, 1, 2, 4, 5]], 1.0))
+
+
+def test_deviatoric_and_graddiv_operators_annihilate_the_near_null_space(small_fsi):
+    # the generator's viscous/elastic (deviatoric) and grad-div terms alone, with natural
+    # boundaries, have the oracle's six near-null vectors in their kernel on every velocity row
+    # of a physical node (the rows of virtual interface nodes are identity rows)
+    p = synth.default_params(mode=0, m_core=2, n_bl=1, n_wall=1, nz=8, R=1.0, L=2.0, terms=2 | 4, apply_bc=0)
+    s = synth.generate(p, tets=True)
+    assert s.n_b == small_fsi.n_b and np.array_equal(s.xyz, small_fsi.xyz)
+    o = oracle.Scr(small_fsi.rp, small_fsi.ci, small_fsi.val, small_fsi.xyz)
+    B = o.amgA.get(0, "B")
+    A = s.val[:, :3, :3]
+    AB = np.stack([oracle.bsr_spmv(s.rp, s.ci, A, B[:, c]) for c in range(6)], axis=1)
+    phys = np.repeat(s.kind != 3, 3)
+    scale = np.abs(A).max() * np.abs(B).max() * 15
+    assert np.abs(AB[phys]).max() <= 1e-12 * scale
+    # the full velocity block (mass included) does not annihilate them: the check has teeth
+    Af = small_fsi.val[:, :3, :3]
+    ABf = oracle.bsr_spmv(small_fsi.rp, small_fsi.ci, Af, B[:, 0])
+    assert np.abs(ABf[phys]).max() > 1e-3 * scale
+
+
+# ----------------------------------------------------------------------------- block strength
+def _scaled_block(rng, b, f):
+    """A random b x b block whose squared Frobenius norm is exactly f (to rounding)."""
+    M = rng.normal(size=(b, b))
+    return M * np.sqrt(f / (M * M).sum())
+
+
+@pytest.mark.parametrize("b", [3, 6])
+def test_block_strength_flips_at_the_frobenius_threshold(b):
+    # strong iff f_ij^2 >= theta^4 f_ii f_jj with f the squared Frobenius norm of the block,
+    # symmetrised by OR; blocks placed a relative 1e-6 above and below the threshold flip the
+    # flag, whichever of (i, j) and (j, i) carries the coupling
+    rng = np.random.default_rng(b)
+    theta = 0.08
+    fii, fjj = 3.7, 0.45
+    thr = np.sqrt(theta ** 4 * fii * fjj)            # f_ij at the threshold
+    rp = np.array([0, 2, 4], np.int32); ci = np.array([0, 1, 0, 1], np.int32)
+    for side in (0, 1):                               # coupling in block (0,1) or in (1,0)
+        for rel, expect in ((1 + 1e-6, 1), (1 - 1e-6, 0)):
+            val = np.zeros((4, b, b))
+            val[0] = _scaled_block(rng, b, fii)
+            val[3] = _scaled_block(rng, b, fjj)
+            val[1 + side] = _scaled_block(rng, b, rel * thr)
+            val[2 - side] = _scaled_block(rng, b, 1e-3 * thr)   # the other direction is weak
+            flags, iso = oracle.strength(rp, ci, val, theta)
+            assert flags.tolist() == [0, expect, expect, 0], (side, rel, flags)
+            assert iso.tolist() == [1 - expect, 1 - expect]
+    # a norm other than the squared Frobenius norm would move the flip point: the max-abs entry
+    # of a block scaled to the Frobenius threshold is well below it
+    val = np.zeros((4, b, b))
+    val[0] = _scaled_block(rng, b, fii); val[3] = _scaled_block(rng, b, fjj)
+    val[1] = _scaled_block(rng, b, 1.001 * thr); val[2] = val[1].T
+    assert (val[1] ** 2).max() < 0.9 * thr
+    flags, _ = oracle.strength(rp, ci, val, theta)
+    assert flags.tolist() == [0, 1, 1, 0]
