@@ -21,12 +21,22 @@
  *     the matrix-free Schur action (Appendix B, Algorithm 2);
  *   - preconditioned (and flexible) CG for the mesh-motion Laplacian (Sec. 5.2.2).
  * The parameters of SA-AMG are not in the paper (it uses BoomerAMG); they are inputs here.
+ *
+ * Threads (OpenMP) only split loops whose iterations are independent (rows of a product, entries
+ * of a vector update, aggregates); every dot product sums fixed chunks of DOT_CHUNK entries in
+ * order and then the chunk sums in order.  Every result is therefore the same for any thread
+ * count, bit for bit.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* loops shorter than this run on one thread (thread start-up would dominate) */
+#define PAR_MIN 4096
+/* dot products: partial sums over fixed chunks of this many entries, then over the chunks */
+#define DOT_CHUNK 4096
 
 /* ------------------------------------------------------------------ sparse block matrix */
 typedef struct {
@@ -53,6 +63,7 @@ static void bsr_free(bsr* M) {
 /* y = M x */
 static void bsr_mv(const bsr* M, const double* x, double* y) {
     int br = M->br, bc = M->bc;
+#pragma omp parallel for schedule(static) if (M->nr > PAR_MIN)
     for (int64_t i = 0; i < M->nr; ++i) {
         double acc[8] = {0};
         for (int32_t q = M->rp[i]; q < M->rp[i + 1]; ++q) {
@@ -79,55 +90,70 @@ static int cmp_i32(const void* a, const void* b) {
     return (x > y) - (x < y);
 }
 
-/* C = X * Y with the structural pattern (no numerical dropping), columns sorted. */
+/* C = X * Y with the structural pattern (no numerical dropping), columns sorted.  Each row of C
+ * is computed on its own (a row's terms are accumulated in the order of X's row, then of Y's
+ * rows), so the rows are split over threads, each with its own column marks. */
 static bsr* spgemm(const bsr* X, const bsr* Y) {
     int m = X->br, n = X->bc, p = Y->bc;
     int64_t nr = X->nr, nc = Y->nc;
-    int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (nc > 0 ? nc : 1));
-    for (int64_t c = 0; c < nc; ++c) mark[c] = -1;
     int32_t* rp = (int32_t*)calloc(nr + 1, sizeof(int32_t));
-    int64_t cap = 1024, nnz = 0;
-    int32_t* ci = (int32_t*)malloc(sizeof(int32_t) * cap);
-    for (int64_t i = 0; i < nr; ++i) {
-        int64_t start = nnz;
-        for (int32_t q = X->rp[i]; q < X->rp[i + 1]; ++q) {
-            int32_t k = X->ci[q];
-            for (int32_t t = Y->rp[k]; t < Y->rp[k + 1]; ++t) {
-                int32_t c = Y->ci[t];
-                if (mark[c] != (int32_t)i) {
-                    mark[c] = (int32_t)i;
-                    if (nnz == cap) { cap *= 2; ci = (int32_t*)realloc(ci, sizeof(int32_t) * cap); }
-                    ci[nnz++] = c;
+    /* pass 1: row lengths */
+#pragma omp parallel if (nr > PAR_MIN)
+    {
+        int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (nc > 0 ? nc : 1));
+        for (int64_t c = 0; c < nc; ++c) mark[c] = -1;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nr; ++i) {
+            int32_t cnt = 0;
+            for (int32_t q = X->rp[i]; q < X->rp[i + 1]; ++q) {
+                int32_t k = X->ci[q];
+                for (int32_t t = Y->rp[k]; t < Y->rp[k + 1]; ++t)
+                    if (mark[Y->ci[t]] != (int32_t)i) { mark[Y->ci[t]] = (int32_t)i; ++cnt; }
+            }
+            rp[i + 1] = cnt;
+        }
+        free(mark);
+    }
+    for (int64_t i = 0; i < nr; ++i) rp[i + 1] += rp[i];
+    bsr* Cm = bsr_new(nr, nc, m, p, rp[nr]);
+    memcpy(Cm->rp, rp, sizeof(int32_t) * (nr + 1));
+    free(rp);
+    /* pass 2: sorted columns; pass 3: values through a column -> position map */
+#pragma omp parallel if (nr > PAR_MIN)
+    {
+        int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (nc > 0 ? nc : 1));
+        for (int64_t c = 0; c < nc; ++c) mark[c] = -1;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nr; ++i) {
+            int32_t nz = Cm->rp[i];
+            for (int32_t q = X->rp[i]; q < X->rp[i + 1]; ++q) {
+                int32_t k = X->ci[q];
+                for (int32_t t = Y->rp[k]; t < Y->rp[k + 1]; ++t)
+                    if (mark[Y->ci[t]] != (int32_t)i) { mark[Y->ci[t]] = (int32_t)i; Cm->ci[nz++] = Y->ci[t]; }
+            }
+            qsort(Cm->ci + Cm->rp[i], Cm->rp[i + 1] - Cm->rp[i], sizeof(int32_t), cmp_i32);
+        }
+        for (int64_t c = 0; c < nc; ++c) mark[c] = -1;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < nr; ++i) {
+            for (int32_t q = Cm->rp[i]; q < Cm->rp[i + 1]; ++q) mark[Cm->ci[q]] = q;
+            for (int32_t q = X->rp[i]; q < X->rp[i + 1]; ++q) {
+                int32_t k = X->ci[q];
+                const double* xb = X->v + (int64_t)q * m * n;
+                for (int32_t t = Y->rp[k]; t < Y->rp[k + 1]; ++t) {
+                    const double* yb = Y->v + (int64_t)t * n * p;
+                    double* cb = Cm->v + (int64_t)mark[Y->ci[t]] * m * p;
+                    for (int r = 0; r < m; ++r)
+                        for (int c = 0; c < p; ++c) {
+                            double s = 0.0;
+                            for (int l = 0; l < n; ++l) s += xb[r * n + l] * yb[l * p + c];
+                            cb[r * p + c] += s;
+                        }
                 }
             }
         }
-        qsort(ci + start, nnz - start, sizeof(int32_t), cmp_i32);
-        rp[i + 1] = (int32_t)nnz;
+        free(mark);
     }
-    bsr* Cm = bsr_new(nr, nc, m, p, nnz);
-    memcpy(Cm->rp, rp, sizeof(int32_t) * (nr + 1));
-    memcpy(Cm->ci, ci, sizeof(int32_t) * nnz);
-    free(rp); free(ci);
-    /* numeric: position map per row */
-    for (int64_t c = 0; c < nc; ++c) mark[c] = -1;
-    for (int64_t i = 0; i < nr; ++i) {
-        for (int32_t q = Cm->rp[i]; q < Cm->rp[i + 1]; ++q) mark[Cm->ci[q]] = q;
-        for (int32_t q = X->rp[i]; q < X->rp[i + 1]; ++q) {
-            int32_t k = X->ci[q];
-            const double* xb = X->v + (int64_t)q * m * n;
-            for (int32_t t = Y->rp[k]; t < Y->rp[k + 1]; ++t) {
-                const double* yb = Y->v + (int64_t)t * n * p;
-                double* cb = Cm->v + (int64_t)mark[Y->ci[t]] * m * p;
-                for (int r = 0; r < m; ++r)
-                    for (int c = 0; c < p; ++c) {
-                        double s = 0.0;
-                        for (int l = 0; l < n; ++l) s += xb[r * n + l] * yb[l * p + c];
-                        cb[r * p + c] += s;
-                    }
-            }
-        }
-    }
-    free(mark);
     return Cm;
 }
 
@@ -165,6 +191,7 @@ static int lu_factor(int64_t n, double* A, int64_t* piv) {
         if (best == 0.0) return -1;
         if (pr != k)
             for (int64_t j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[pr * n + j]; A[pr * n + j] = t; }
+#pragma omp parallel for schedule(static) if (n - k > 256)
         for (int64_t i = k + 1; i < n; ++i) {
             double l = A[i * n + k] / A[k * n + k];
             A[i * n + k] = l;
@@ -263,11 +290,13 @@ void orc_strength(int64_t nr, int b, const int32_t* rp, const int32_t* ci, const
     bsr M = {nr, nr, b, b, rp[nr], (int32_t*)rp, (int32_t*)ci, (double*)val};
     int bb = b * b;
     double* fd = (double*)malloc(sizeof(double) * nr);
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN)
     for (int64_t i = 0; i < nr; ++i) {
         int32_t q = find_in_row(&M, i, (int32_t)i);
         fd[i] = q >= 0 ? block_f(val + (int64_t)q * bb, bb) : 0.0;
     }
     double th4 = ((theta * theta) * theta) * theta;
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN)
     for (int64_t i = 0; i < nr; ++i) {
         iso[i] = 1;
         for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
@@ -342,13 +371,16 @@ int64_t orc_aggregate(int64_t nr, const int32_t* rp, const int32_t* ci, const ui
     int64_t na = 0;
     for (int64_t i = 0; i < nr; ++i) agg[i] = root[i] ? (int32_t)na++ : -1;
     uint8_t* step1 = (uint8_t*)calloc(nr > 0 ? nr : 1, 1);
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN)
     for (int64_t i = 0; i < nr; ++i) {
         if (iso[i] || root[i]) continue;
         for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
             if (flags[q] && root[ci[q]]) { agg[i] = agg[ci[q]]; step1[i] = 1; break; }
     }
+    int lost = 0;
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN) reduction(| : lost)
     for (int64_t i = 0; i < nr; ++i) {
-        if (iso[i] || agg[i] >= 0) continue;
+        if (iso[i] || agg[i] >= 0 || step1[i]) continue;
         uint64_t best = 0; int32_t bj = -1;
         for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
             int32_t j = ci[q];
@@ -356,11 +388,11 @@ int64_t orc_aggregate(int64_t nr, const int32_t* rp, const int32_t* ci, const ui
             uint64_t kj = orc_mis_key(seed, level, j);
             if (bj < 0 || kj > best) { best = kj; bj = j; }
         }
-        if (bj < 0) { free(step1); return -1; }   /* cannot happen for a maximal set */
-        agg[i] = agg[bj];
+        if (bj < 0) { lost = 1; continue; }      /* cannot happen for a maximal set */
+        agg[i] = agg[bj];                          /* bj joined in the previous step: final */
     }
     free(step1);
-    return na;
+    return lost ? -1 : na;
 }
 
 /* Tentative prolongator by Gram-Schmidt (two modified-GS passes) of the near-null space
@@ -378,6 +410,7 @@ static void tentative(int64_t nr, int b, int k, const int32_t* agg, int64_t na, 
     for (int64_t i = 0; i < nr; ++i) if (agg[i] >= 0) mem[fill[agg[i]]++] = (int32_t)i;
     memset(Q, 0, sizeof(double) * nr * b * k);
     memset(Bc, 0, sizeof(double) * na * k * k);
+#pragma omp parallel for schedule(dynamic, 64) if (na > 256)
     for (int64_t a = 0; a < na; ++a) {
         int64_t nn = cnt[a + 1] - cnt[a];
         int64_t rows = nn * b;
@@ -430,10 +463,11 @@ static int level_diag(level* L) {
     int b = L->b, bb = b * b;
     L->Dinv = (double*)malloc(sizeof(double) * A->nr * bb);
     double lam = 0.0;
+    int bad = 0;
+#pragma omp parallel for schedule(static) if (A->nr > PAR_MIN) reduction(max : lam) reduction(| : bad)
     for (int64_t i = 0; i < A->nr; ++i) {
         int32_t q = find_in_row(A, i, (int32_t)i);
-        if (q < 0) return -1;
-        if (small_inverse(b, A->v + (int64_t)q * bb, L->Dinv + i * bb)) return -1;
+        if (q < 0 || small_inverse(b, A->v + (int64_t)q * bb, L->Dinv + i * bb)) { bad = 1; continue; }
         double rs[8] = {0};
         for (int32_t t = A->rp[i]; t < A->rp[i + 1]; ++t) {
             const double* blk = A->v + (int64_t)t * bb;
@@ -446,6 +480,7 @@ static int level_diag(level* L) {
         }
         for (int r = 0; r < b; ++r) if (rs[r] > lam) lam = rs[r];
     }
+    if (bad) return -1;
     L->lam = lam;
     return 0;
 }
@@ -480,6 +515,7 @@ static bsr* smooth_prolongator(const level* L, const double* Q) {
     memcpy(P->rp, rp, sizeof(int32_t) * (nr + 1));
     memcpy(P->ci, ci, sizeof(int32_t) * nnz);
     free(rp); free(ci);
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN)
     for (int64_t i = 0; i < nr; ++i) {
         if (L->agg[i] < 0) continue;
         const double* Di = L->Dinv + i * bb;
@@ -635,6 +671,7 @@ static void smooth(const amg* h, int l, const double* b, double* x, int zero_ini
     int bs = L->b, bb = bs * bs;
     if (zero_init) memset(x, 0, sizeof(double) * n);
     #define DINV_APPLY(src, dst) do { \
+        _Pragma("omp parallel for schedule(static) if (n > PAR_MIN)") \
         for (int64_t i_ = 0; i_ < L->A->nr; ++i_) \
             for (int r_ = 0; r_ < bs; ++r_) { double s_ = 0.0; \
                 for (int c_ = 0; c_ < bs; ++c_) s_ += L->Dinv[i_ * bb + r_ * bs + c_] * (src)[i_ * bs + c_]; \
@@ -643,8 +680,10 @@ static void smooth(const amg* h, int l, const double* b, double* x, int zero_ini
         double w = 4.0 / (3.0 * L->lam);
         for (int s = 0; s < h->o.jacobi_sweeps; ++s) {
             bsr_mv(L->A, x, r);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
             for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
             DINV_APPLY(r, z);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
             for (int64_t i = 0; i < n; ++i) x[i] += w * z[i];
         }
     } else {
@@ -652,14 +691,18 @@ static void smooth(const amg* h, int l, const double* b, double* x, int zero_ini
         double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
         double sigma = theta / delta, rho_prev = 1.0 / sigma;
         bsr_mv(L->A, x, r);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
         for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
         DINV_APPLY(r, z);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
         for (int64_t i = 0; i < n; ++i) { d[i] = z[i] / theta; x[i] += d[i]; }
         for (int s = 1; s < h->o.cheb_degree; ++s) {
             bsr_mv(L->A, x, r);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
             for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
             DINV_APPLY(r, z);
             double rho = 1.0 / (2.0 * sigma - rho_prev);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
             for (int64_t i = 0; i < n; ++i) { d[i] = rho * rho_prev * d[i] + (2.0 * rho / delta) * z[i]; x[i] += d[i]; }
             rho_prev = rho;
         }
@@ -680,6 +723,7 @@ static void vcycle_rec(amg* h, int l, const double* b, double* x) {
     double* z = (double*)malloc(sizeof(double) * n);
     smooth(h, l, b, x, 1, r, d, z);
     bsr_mv(L->A, x, r);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
     int64_t nc = L->R->nr * L->R->br;
     double* bc = (double*)malloc(sizeof(double) * nc);
@@ -687,6 +731,7 @@ static void vcycle_rec(amg* h, int l, const double* b, double* x) {
     bsr_mv(L->R, r, bc);
     vcycle_rec(h, l + 1, bc, xc);
     bsr_mv(L->P, xc, z);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
     for (int64_t i = 0; i < n; ++i) x[i] += z[i];
     smooth(h, l, b, x, 0, r, d, z);
     free(r); free(d); free(z); free(bc); free(xc);
@@ -756,9 +801,26 @@ int orc_amg_level_get(const amg* h, int l, int field, void* dst) {
 /* ------------------------------------------------------------------ Krylov */
 typedef void (*op_fn)(void* ctx, const double* x, double* y);
 
+/* sum_i a_i b_i: each chunk of DOT_CHUNK entries summed in order, then the chunk sums in order
+ * (the same result on any number of threads) */
 static double dot(int64_t n, const double* a, const double* b) {
+    int64_t nch = (n + DOT_CHUNK - 1) / DOT_CHUNK;
+    if (nch <= 1) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+        return s;
+    }
+    double* part = (double*)malloc(sizeof(double) * nch);
+#pragma omp parallel for schedule(static) if (nch > 8)
+    for (int64_t c = 0; c < nch; ++c) {
+        int64_t e = (c + 1) * DOT_CHUNK < n ? (c + 1) * DOT_CHUNK : n;
+        double s = 0.0;
+        for (int64_t i = c * DOT_CHUNK; i < e; ++i) s += a[i] * b[i];
+        part[c] = s;
+    }
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    for (int64_t c = 0; c < nch; ++c) s += part[c];
+    free(part);
     return s;
 }
 
@@ -786,13 +848,18 @@ static kstat fgmres(int64_t n, op_fn op, void* oc, op_fn prec, void* pc, const d
     for (;;) {
         /* r = b - op(x) */
         if (first && !use_x0) memcpy(V, b, sizeof(double) * n);
-        else { op(oc, x, w); for (int64_t i = 0; i < n; ++i) V[i] = b[i] - w[i]; }
+        else {
+            op(oc, x, w);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
+            for (int64_t i = 0; i < n; ++i) V[i] = b[i] - w[i];
+        }
         first = 0;
         double beta = sqrt(dot(n, V, V));
         st.rel_res = beta / bn;
         if (beta <= tol * bn) { st.converged = 1; break; }
         if (!check_true && est <= tol * bn) { st.converged = 1; break; }
         if (st.iters >= maxit) break;
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
         for (int64_t i = 0; i < n; ++i) V[i] /= beta;
         memset(g, 0, sizeof(double) * (m + 1));
         g[0] = beta;
@@ -803,6 +870,7 @@ static kstat fgmres(int64_t n, op_fn op, void* oc, op_fn prec, void* pc, const d
             for (int i = 0; i <= j; ++i) {
                 double hij = dot(n, w, V + (int64_t)i * n);
                 H[i * m + j] = hij;
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
                 for (int64_t e = 0; e < n; ++e) w[e] -= hij * V[(int64_t)i * n + e];
             }
             double hn = sqrt(dot(n, w, w));
@@ -824,6 +892,7 @@ static kstat fgmres(int64_t n, op_fn op, void* oc, op_fn prec, void* pc, const d
             ++j;
             est = fabs(g[j]);
             if (hn == 0.0) break;           /* happy breakdown */
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
             for (int64_t e = 0; e < n; ++e) V[(int64_t)j * n + e] = w[e] / hn;
             if (est <= tol * bn || st.iters >= maxit) break;
         }
@@ -833,6 +902,7 @@ static kstat fgmres(int64_t n, op_fn op, void* oc, op_fn prec, void* pc, const d
             y[i] = s / H[i * m + i];
         }
         for (int i = 0; i < j; ++i)
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
             for (int64_t e = 0; e < n; ++e) x[e] += y[i] * Z[(int64_t)i * n + e];
         st.rel_res = est / bn;
         if (!check_true && (est <= tol * bn || st.iters >= maxit)) { st.converged = est <= tol * bn; break; }
@@ -861,6 +931,7 @@ static kstat pcg(int64_t n, op_fn op, void* oc, op_fn prec, void* pc, const doub
         op(oc, p, q);
         double alpha = rz / dot(n, p, q);
         memcpy(rold, r, sizeof(double) * n);
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
         for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
         st.iters++;
         double rn = sqrt(dot(n, r, r));
@@ -871,11 +942,12 @@ static kstat pcg(int64_t n, op_fn op, void* oc, op_fn prec, void* pc, const doub
         double rz_new = dot(n, r, z);
         double beta;
         if (flexible) {
-            double s = 0.0;
-            for (int64_t i = 0; i < n; ++i) s += z[i] * (r[i] - rold[i]);
-            beta = s / rz;
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
+            for (int64_t i = 0; i < n; ++i) rold[i] = r[i] - rold[i];
+            beta = dot(n, z, rold) / rz;        /* z . (r_new - r_old) */
         } else beta = rz_new / rz;
         rz = rz_new;
+#pragma omp parallel for schedule(static) if (n > PAR_MIN)
         for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     }
     free(r); free(z); free(p); free(q); free(rold);
@@ -931,6 +1003,7 @@ static void op_K(void* c, const double* x, double* y) {
     /* split layout: x = [x_v (3nb); x_p (nb)] */
     scr* s = (scr*)c;
     int64_t nb = s->nb;
+#pragma omp parallel for schedule(static) if (nb > PAR_MIN)
     for (int64_t i = 0; i < nb; ++i) {
         double acc[4] = {0};
         for (int32_t q = s->K->rp[i]; q < s->K->rp[i + 1]; ++q) {
