@@ -48,7 +48,7 @@ typedef enum {
 } scr_status;
 
 typedef enum { SCR_SYSTEM = 0, MESH_SYSTEM = 1 } scr_kind;
-typedef enum { SCR_FP64 = 0, SCR_MIXED = 1 } scr_precision;
+typedef enum { SCR_FP64 = 0, SCR_MIXED = 1, SCR_MIXED_FP32_INNER = 2 } scr_precision;
 typedef enum { SCR_SMOOTH_JACOBI = 0, SCR_SMOOTH_CHEBYSHEV = 1 } scr_smoother;
 
 /* diagonal used in S^ (scr_amg_opts.schur_diag) */
@@ -73,11 +73,16 @@ typedef struct {
 /* Smoothed-aggregation AMG options (the paper uses BoomerAMG, Sec. 5.2 table of settings;
  * these are the SA replacements).  Defaults from scr_default_amg_opts. */
 typedef struct {
-    int precision;             /* SCR_FP64: everything in FP64.  SCR_MIXED: hierarchy values and
-                                  V-cycles in FP32 (coarsest solve FP64), and Algorithm 2's inner A
-                                  solve on FP32 vectors with the FP32 level-0 copy of A (dot products
-                                  accumulated in FP64); the outer FGMRES, K, the A- and S-level solves
-                                  of Algorithm 1 and every true residual stay FP64 */
+    int precision;             /* SCR_FP64: everything in FP64.  SCR_MIXED: the AMG hierarchy values
+                                  and the whole V-cycle in FP32 (cast at its entry and exit; the
+                                  coarsest solve FP64); every Krylov level (the outer FGMRES, the A-
+                                  and S-level solves of Algorithm 1, Algorithm 2's inner A solve), its
+                                  Arnoldi process and Hessenberg least squares, the products with K,
+                                  A, G, D, C and every true residual stay FP64.
+                                  SCR_MIXED_FP32_INNER: as SCR_MIXED, and in addition Algorithm 2's
+                                  inner A solve (GMRES to tol_I) runs on FP32 vectors with the FP32
+                                  level-0 copy of A (dot products and updates accumulated in FP64,
+                                  rounded on store; Hessenberg least squares FP64) */
     double theta;              /* strength threshold at level 0 (halved per level), 0.08 */
     int smoother;              /* scr_smoother, default Chebyshev */
     int cheb_degree;           /* 4 */
@@ -102,7 +107,7 @@ typedef struct {
     int max_it, max_it_A, max_it_S, max_it_I;
     int restart, restart_inner;
     int use_x0;                /* 1: x holds the initial guess on entry */
-    int flexible_cg;           /* mesh solve: 1 = flexible CG (Notay), 0 = PCG; MIXED forces 1 */
+    int flexible_cg;           /* mesh solve: 1 = flexible CG (Notay), 0 = PCG; an FP32 hierarchy forces 1 */
     int precond;               /* scr_solve: SCR_PRECOND_SCR (default, Appendix B Algorithm 1) or
                                   SCR_PRECOND_SIMPLE (Sec. 5.2.1: S^ in place of S, d^-1 in the upper
                                   factor; SIMPLEC when the handle was set up with SCR_DIAG_ABSROWSUM) */
@@ -176,20 +181,37 @@ scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, voi
 scr_status scr_set_outlets(scr_handle* h, int n_out, const int64_t* off /* host */, const int32_t* blk,
                            const double* a, const double* m /* host */, void* stream);
 
-/* Solve K x = b (SCR_SYSTEM handle) by FGMRES(P_SCR) to ||b - K x|| <= tol ||b|| (true FP64
- * residual, checked at exit).  b, x: device, 4 * n_brows FP64, node-interleaved [vx vy vz p].
- * x is the initial guess if use_x0, else it is overwritten.  Returns SCR_OK, or
- * SCR_NOT_CONVERGED with x = last iterate; stats (host, may be NULL) are filled either way. */
+/* Solve the corrector system K x = b of Sec. 3.5 (SCR_SYSTEM handle) by right-preconditioned
+ * flexible GMRES with the Schur-complement-reduction preconditioner of Sec. 5.2.1 (the inverse of
+ * the block LDU factorisation of [A G; D C]), applied by Appendix B, Algorithm 1 (its step 2
+ * read as r_p <- r_p - D y^_v), with the Schur action of Algorithm 2 (or, with
+ * scr_solve_opts.precond = SCR_PRECOND_SIMPLE, the SIMPLE/SIMPLEC preconditioners of Sec. 5.2.1),
+ * to ||b - K x|| <= tol ||b|| (true FP64 residual, checked at exit).
+ * b, x: device, 4 * n_brows FP64, node-interleaved [vx vy vz p]; b is not modified; x is
+ * caller-allocated and is the initial guess if use_x0, else it is overwritten.  Returns SCR_OK,
+ * or SCR_NOT_CONVERGED with x = last iterate; stats (host, may be NULL) are filled either way.
+ * Errors: SCR_E_INVALID (NULL pointers, a MESH_SYSTEM handle, options out of range, a handle
+ * left unusable by amg_update), SCR_E_BREAKDOWN (non-finite values in a Krylov recurrence),
+ * SCR_E_OOM and SCR_E_HIP (workspace allocation on first use, runtime errors). */
 scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts /* host */,
                      void* stream, scr_stats* stats /* host */);
 
-/* Solve L X = B (MESH_SYSTEM handle) for three right-hand sides by CG + AMG(L), each column to
- * ||B_c - L X_c|| <= tol ||B_c||.  b, x: device, n_brows x 3 FP64 interleaved [ux uy uz]. */
+/* Solve the mesh-motion system of Sec. 2.2.2 (harmonic extension of the wall displacement into
+ * the fluid domain, the same scalar Laplacian L for the x, y and z components; MESH_SYSTEM
+ * handle) by CG preconditioned with AMG(L) as in Sec. 5.2.2: L X = B for the three columns at
+ * once, each column stopping at ||B_c - L X_c|| <= tol ||B_c||, max_it iterations.  PCG for an
+ * FP64 hierarchy, flexible CG (Notay) for an FP32 one or with flexible_cg.
+ * b, x: device, n_brows x 3 FP64 interleaved [ux uy uz]; b is not modified; x is overwritten.
+ * Returns SCR_OK or SCR_NOT_CONVERGED (stats.mesh_its / mesh_rel per column).  Errors as for
+ * scr_solve. */
 scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts /* host */,
                              void* stream, scr_stats* stats /* host */);
 
 scr_status scr_handle_destroy(scr_handle* h);
+/* Device memory the handle holds now, and the most it ever held (setup temporaries included);
+ * bytes as counted against the context budget. */
 int64_t scr_handle_bytes(const scr_handle* h);
+int64_t scr_handle_peak_bytes(const scr_handle* h);
 
 /* Device assembly of the corrector tangent matrix K (Sec. 3.5: the consistent linearisation of
  * the semi-discrete unified-continuum equations of Sec. 3.1 (solid, c_m = c_c = 0) and Sec. 3.2
@@ -262,8 +284,10 @@ scr_status scr_ctx_profile(scr_ctx* ctx, int kernel);
 scr_status scr_ctx_profile_read(scr_ctx* ctx, int64_t* launches /* host */, double* total_ms /* host */,
                                 double* bytes /* host */);
 
-/* Upper bound of the device memory a handle of this size will hold (host-side model, used
- * for admission control). */
+/* Upper bound of the device memory a handle of this size will hold at its peak
+ * (scr_handle_peak_bytes: setup temporaries, hierarchies, Krylov workspaces), from a host-side
+ * model of the sizes; used for admission control and checked against the measured peak by the
+ * tests on the tube workloads. */
 int64_t scr_footprint_estimate(int kind, int64_t n_brows, int64_t nnzb, const scr_amg_opts* amg,
                                const scr_solve_opts* solve);
 

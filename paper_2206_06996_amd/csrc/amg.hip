@@ -1060,9 +1060,11 @@ __global__ void densify_k(int64_t nr, int b, const int32_t* __restrict__ rp, con
         for (int r = 0; r < b; ++r)
             for (int c = 0; c < b; ++c) M[(i * b + r) * n + (int64_t)ci[q] * b + c] = v[((int64_t)q * b + r) * b + c];
 }
-// Gauss-Jordan exchange steps over all pivots in order turn A into A^-1 (no pivoting: the
-// coarsest Galerkin matrices here have nonsingular leading blocks; a zero or non-finite pivot
-// shows up as a non-finite entry, checked afterwards).
+// Gauss-Jordan exchange steps over all pivots in order turn A into A^-1.  This fast form takes
+// the pivots in order without interchanges; the result is checked afterwards (the backward error
+// of one solve with it, coarse_check_*) and recomputed with row interchanges (partial pivoting,
+// gjp_*) when a small or zero leading pivot spoilt it: the coarsest operators are not SPD in
+// general (the advective velocity block is nonsymmetric).
 // A panel of GJ_P consecutive pivots K = [k0, k0 + np) at once, by the block form of the exchange
 // step (equal in exact arithmetic to the np single steps in order): with W = M_KK^-1,
 //   out_KK = W,  out_KR = W M_KR,  out_RK = -M_RK W,  out_RR = M_RR - M_RK W M_KR.
@@ -1148,6 +1150,131 @@ __global__ void gj_panel_apply_k(int64_t n, int64_t k0, int np, const double* __
 __global__ void finite_k(int64_t n, const double* __restrict__ a, int* __restrict__ err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && !isfinite(a[i])) atomicOr(err, 1);
+}
+
+// ---- accuracy check of an explicit inverse X of A: y = X v for a fixed v, then the normwise
+// backward error eta = ||A y - v||_inf / (||A||_inf ||y||_inf + ||v||_inf) (about n * 1e-16 for
+// a stable inverse; a spoilt pivot makes it large or non-finite)
+__device__ __forceinline__ double check_vec(int64_t i) { return 1.0 + (double)((i * 7919) % 13) / 13.0; }
+__global__ void __launch_bounds__(256) coarse_check_y_k(int64_t n, const double* __restrict__ X, double* __restrict__ y) {
+    int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (row >= n) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    double acc = 0.0;
+    for (int64_t c = lane; c < n; c += WAVE) acc += X[row * n + c] * check_vec(c);
+    acc = wave_sum(acc);
+    if (lane == 0) y[row] = acc;
+}
+// per row: |(A y)_i - v_i| and the absolute row sum of A
+__global__ void __launch_bounds__(256) coarse_check_r_k(int64_t n, const double* __restrict__ A, const double* __restrict__ y,
+                                                        double* __restrict__ rr, double* __restrict__ ra) {
+    int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (row >= n) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    double acc = 0.0, abs_sum = 0.0;
+    for (int64_t c = lane; c < n; c += WAVE) {
+        acc += A[row * n + c] * y[c];
+        abs_sum += fabs(A[row * n + c]);
+    }
+    acc = wave_sum(acc);
+    abs_sum = wave_sum(abs_sum);
+    if (lane == 0) {
+        rr[row] = fabs(acc - check_vec(row));
+        ra[row] = abs_sum;
+    }
+}
+// one workgroup: eta into *eta (NaN propagates: fmax would drop it, so non-finite values are flagged)
+__global__ void __launch_bounds__(256) coarse_check_eta_k(int64_t n, const double* __restrict__ rr,
+                                                          const double* __restrict__ ra, const double* __restrict__ y,
+                                                          double* __restrict__ eta) {
+    __shared__ double red[3][256];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    double m[3] = {0.0, 0.0, 0.0};
+    int nf = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double a = rr[i], b = ra[i], c = fabs(y[i]);
+        if (!isfinite(a) || !isfinite(b) || !isfinite(c)) nf = 1;
+        m[0] = a > m[0] ? a : m[0];
+        m[1] = b > m[1] ? b : m[1];
+        m[2] = c > m[2] ? c : m[2];
+    }
+    if (nf) atomicOr(&bad, 1);
+    for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = m[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *eta = bad ? INFINITY : red[0][0] / (red[1][0] * red[2][0] + 2.0);
+}
+
+// ---- Gauss-Jordan with partial pivoting (the fallback): step k picks the row p >= k with the
+// largest |M_pk| (the smallest such p on ties), swaps rows k and p of the current matrix and
+// applies the exchange step at (k, k); at the end the column interchanges are undone in reverse
+// order (the inverse of the row-permuted matrix is A^-1 P^-1).
+__global__ void __launch_bounds__(256) gjp_pivot_k(int64_t n, int64_t k, double* __restrict__ M, int32_t* __restrict__ perm,
+                                                   int* __restrict__ err) {
+    __shared__ double bv[256];
+    __shared__ int64_t bi[256];
+    double best = -1.0;
+    int64_t arg = n;
+    for (int64_t i = k + threadIdx.x; i < n; i += 256) {
+        const double v = fabs(M[i * n + k]);
+        if (v > best) { best = v; arg = i; }     // ascending i per thread: the first largest
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = arg;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double v = bv[threadIdx.x + o];
+            const int64_t a = bi[threadIdx.x + o];
+            if (v > bv[threadIdx.x] || (v == bv[threadIdx.x] && a < bi[threadIdx.x])) {
+                bv[threadIdx.x] = v;
+                bi[threadIdx.x] = a;
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t p = bi[0];
+    if (threadIdx.x == 0) {
+        perm[k] = (int32_t)(p < n ? p : k);
+        if (!(bv[0] > 0.0) || !isfinite(bv[0])) atomicOr(err, 1);
+    }
+    if (p >= n || p == k) return;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double a = M[k * n + j];
+        M[k * n + j] = M[p * n + j];
+        M[p * n + j] = a;
+    }
+}
+__global__ void gjp_exchange_k(int64_t n, int64_t k, const double* __restrict__ src, double* __restrict__ dst) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    const int64_t i = idx / n, j = idx % n;
+    const double ip = 1.0 / src[k * n + k];
+    double out;
+    if (i == k) out = (j == k) ? ip : src[k * n + j] * ip;
+    else if (j == k) out = -src[i * n + k] * ip;
+    else out = src[idx] - src[i * n + k] * src[k * n + j] * ip;
+    dst[idx] = out;
+}
+// undo the interchanges on the columns: row i applies swap (k, perm[k]) for k = n-1 .. 0
+__global__ void gjp_unpermute_k(int64_t n, const int32_t* __restrict__ perm, double* __restrict__ M) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* row = M + i * n;
+    for (int64_t k = n - 1; k >= 0; --k) {
+        const int64_t p = perm[k];
+        if (p != k) {
+            const double a = row[k];
+            row[k] = row[p];
+            row[p] = a;
+        }
+    }
 }
 
 // ====================================================================== hierarchy with solve-phase data in T
@@ -1314,17 +1441,40 @@ static void level_diag(LevelSetup& L, int l, int* err, unsigned long long* lamd,
     L.lam = lam;
 }
 
-// coarsest level: explicit inverse by Gauss-Jordan exchange steps (the matrix is SPD)
+// backward error of the explicit inverse X of the dense A (one check solve; synchronises)
+static double coarse_check(int64_t nc, const double* A, const double* X, Arena& ar, hipStream_t s) {
+    double* y = ar.make<double>(nc);
+    double* rr = ar.make<double>(nc);
+    double* ra = ar.make<double>(nc);
+    double* eta = ar.make<double>(1);
+    coarse_check_y_k<<<cdiv(nc, 4), 256, 0, s>>>(nc, X, y);
+    coarse_check_r_k<<<cdiv(nc, 4), 256, 0, s>>>(nc, A, y, rr, ra);
+    coarse_check_eta_k<<<1, 256, 0, s>>>(nc, rr, ra, y, eta);
+    check_launch("coarse check");
+    double he = 0.0;
+    HIPCHK(hipMemcpyAsync(&he, eta, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ar.free(y); ar.free(rr); ar.free(ra); ar.free(eta);
+    return he;
+}
+
+// largest accepted backward error of the fast inverse (a stable inverse gives about n * 1e-16)
+constexpr double COARSE_ETA_MAX = 1e-10;
+
+// coarsest level: explicit inverse by Gauss-Jordan exchange steps, in order (fast panels), or
+// with partial pivoting when the fast inverse fails its check.  H.coarse_pivoted records which.
 static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
     LevelSetup& C = H.L.back();
     int64_t nc = C.A.nr * C.b;
     H.ncoarse = nc;
     if (nc > 8192) throw Error(SCR_E_INVALID, "coarsest AMG level too large for a direct solve (" + std::to_string(nc) + ")");
     if (H.cinv) { ar.free(H.cinv); H.cinv = nullptr; }
+    double* A = ar.make<double>(nc * nc + 1);      // the dense coarsest matrix, kept for the check
     double* M0 = ar.make<double>(nc * nc + 1);
     double* M1 = ar.make<double>(nc * nc + 1);
-    zero_dev(M0, nc * nc * sizeof(double), s);
-    if (C.A.nr) densify_k<<<cdiv(C.A.nr, 256), 256, 0, s>>>(C.A.nr, C.b, C.A.rp, C.A.ci, C.A.v, M0, nc);
+    zero_dev(A, nc * nc * sizeof(double), s);
+    if (C.A.nr) densify_k<<<cdiv(C.A.nr, 256), 256, 0, s>>>(C.A.nr, C.b, C.A.rp, C.A.ci, C.A.v, A, nc);
+    copy_dev(M0, A, nc * nc * sizeof(double), s);
     double* T = ar.make<double>(nc * GJ_P + 1);
     double* W = ar.make<double>(GJ_P * GJ_P);
     for (int64_t k0 = 0; k0 < nc; k0 += GJ_P) {
@@ -1336,6 +1486,28 @@ static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
     check_launch("coarse inverse");
     ar.free(T);
     ar.free(W);
+    H.coarse_eta = nc ? coarse_check(nc, A, M0, ar, s) : 0.0;
+    H.coarse_pivoted = false;
+    if (!(H.coarse_eta <= COARSE_ETA_MAX)) {
+        // partial pivoting, one exchange step per pivot
+        int32_t* perm = ar.make<int32_t>(nc);
+        zero_dev(err, sizeof(int), s);
+        copy_dev(M0, A, nc * nc * sizeof(double), s);
+        for (int64_t k = 0; k < nc; ++k) {
+            gjp_pivot_k<<<1, 256, 0, s>>>(nc, k, M0, perm, err);
+            gjp_exchange_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc, k, M0, M1);
+            std::swap(M0, M1);
+        }
+        gjp_unpermute_k<<<cdiv(nc, 256), 256, 0, s>>>(nc, perm, M0);
+        check_launch("coarse inverse (pivoted)");
+        int he = 0;
+        HIPCHK(hipMemcpyAsync(&he, err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ar.free(perm);
+        if (he) throw Error(SCR_E_INVALID, "coarsest AMG matrix is singular");
+        H.coarse_eta = coarse_check(nc, A, M0, ar, s);
+        H.coarse_pivoted = true;
+    }
     zero_dev(err, sizeof(int), s);
     if (nc) finite_k<<<cdiv(nc * nc, 256), 256, 0, s>>>(nc * nc, M0, err);
     int he = 0;
@@ -1343,6 +1515,7 @@ static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     if (he) throw Error(SCR_E_INVALID, "coarsest AMG matrix is singular");
     ar.free(M1);
+    ar.free(A);
     H.cinv = M0;
 }
 
@@ -1351,7 +1524,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
     std::unique_ptr<Hierarchy> H;
     HierT<double>* hd = nullptr;
     HierT<float>* hf = nullptr;
-    if (o.precision == SCR_MIXED) { hf = new HierT<float>(); hf->prof = prof; H.reset(hf); }
+    if (o.precision != SCR_FP64) { hf = new HierT<float>(); hf->prof = prof; H.reset(hf); }
     else { hd = new HierT<double>(); hd->prof = prof; H.reset(hd); }
     H->opts = o;
     int* err = ar.make<int>(1);

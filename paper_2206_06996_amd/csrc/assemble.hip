@@ -365,10 +365,7 @@ __global__ void row_of_k(int64_t nb, const int32_t* __restrict__ rp, int32_t* __
     for (int32_t q = rp[r]; q < rp[r + 1]; ++q) rowof[q] = (int32_t)r;
 }
 
-scr_status asm_fail(const Error& e) {
-    set_last_error(e.what());
-    return e.code;
-}
+scr_status asm_fail(const std::exception& e) { return status_of(e); }
 
 }  // namespace
 }  // namespace scr
@@ -458,7 +455,7 @@ scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv,
         HIPCHK(hipStreamSynchronize(s));
         *out = A.release();
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         (void)hipStreamSynchronize(s);
         return asm_fail(e);
     }
@@ -475,7 +472,7 @@ scr_status scr_assemble_tangent(scr_assembler* A, const double* u, double* val, 
         check_launch("tangent_blocks");
         HIPCHK(hipStreamSynchronize(s));
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         (void)hipStreamSynchronize(s);
         return asm_fail(e);
     }

@@ -9,6 +9,7 @@
 #include <iterator>
 #include <map>
 #include <mutex>
+#include <new>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -26,6 +27,16 @@ struct Error : std::runtime_error {
 };
 
 void set_last_error(const std::string& m);
+
+// The status an exception maps to at the C boundary (its message becomes the thread's last error):
+// the library's own errors carry their status, a failed host allocation is SCR_E_OOM, anything else
+// SCR_E_HIP.
+inline scr_status status_of(const std::exception& e) {
+    set_last_error(e.what());
+    if (const Error* se = dynamic_cast<const Error*>(&e)) return se->code;
+    if (dynamic_cast<const std::bad_alloc*>(&e)) return SCR_E_OOM;
+    return SCR_E_HIP;
+}
 
 #define HIPCHK(expr)                                                                              \
     do {                                                                                          \
@@ -54,7 +65,10 @@ struct Profiler {
         std::lock_guard<std::mutex> g(mu);
         if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(SCR_E_HIP, "hipEventCreate failed");
+        }
         return e;
     }
     void push(hipEvent_t a, hipEvent_t b, double by) {
@@ -88,8 +102,10 @@ struct PinnedPool {
         std::lock_guard<std::mutex> g(mu);
         if (free_.empty()) {
             void* c = nullptr;
-            if (hipHostMalloc(&c, 64 * 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
-                throw std::runtime_error("hipHostMalloc failed");
+            if (hipHostMalloc(&c, 64 * 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(SCR_E_OOM, "hipHostMalloc of the Krylov status slots failed");
+            }
             std::memset(c, 0, 64 * 16 * sizeof(double));
             chunks.push_back(c);
             for (int i = 0; i < 64; ++i) free_.push_back(static_cast<double*>(c) + 16 * i);
@@ -101,7 +117,10 @@ struct PinnedPool {
     // device address of a slot
     static double* device_ptr(double* h) {
         void* d = nullptr;
-        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) throw std::runtime_error("hipHostGetDevicePointer failed");
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(SCR_E_HIP, "hipHostGetDevicePointer failed");
+        }
         return static_cast<double*>(d);
     }
     void put(double* p) {
@@ -210,6 +229,7 @@ class Arena {
         }
         ctx_->in_use += (int64_t)bytes;
         bytes_ += (int64_t)bytes;
+        if (bytes_ > peak_) peak_ = bytes_;
         live_.push_back({p, bytes});
         return p;
     }
@@ -240,6 +260,7 @@ class Arena {
         bytes_ = 0;
     }
     int64_t bytes() const { return bytes_; }
+    int64_t peak() const { return peak_; }
     hipStream_t stream() const { return stream_; }
     Ctx* ctx() const { return ctx_; }
 
@@ -250,6 +271,7 @@ class Arena {
     std::vector<A> live_;
     std::multimap<size_t, void*> spare_;
     int64_t bytes_ = 0;
+    int64_t peak_ = 0;     // largest bytes_ ever held
 };
 
 // ---------------------------------------------------------------- matrices

@@ -26,7 +26,7 @@ struct scr_handle {
     double* dvec = nullptr;                       // the diagonal d used in S^ (3n)
     std::unique_ptr<Hierarchy> hA, hS, hL;
     std::unique_ptr<Gmres> gOuter, gA, gS;
-    // mixed precision: Algorithm 2's inner A solve on FP32 vectors (FP32 A of the hierarchy)
+    // SCR_MIXED_FP32_INNER: Algorithm 2's inner A solve on FP32 vectors (FP32 A of the hierarchy)
     std::unique_ptr<GmresT<float>> gA32;
     float *xbar32 = nullptr, *xtil32 = nullptr;
     std::unique_ptr<Pcg> cg;
@@ -147,7 +147,7 @@ struct SchurOp : Op {
         sell_mv<double>(h->Gs, xp, nullptr, h->xbar, 0, s);
         KStat k;
         if (h->gA32) {
-            // mixed precision: the inner solve to delta_I on FP32 vectors, FP32 A and V-cycle
+            // SCR_MIXED_FP32_INNER: the inner solve to delta_I on FP32 vectors, FP32 A and V-cycle
             const int64_t n3 = 3 * h->nb;
             cast_d2f(h->xbar, h->xbar32, n3, s);
             AOp32 aop(h);
@@ -234,10 +234,7 @@ void ensure_simple(scr_handle* h, hipStream_t s) {
     if (h->Shs.nslices == 0 && h->Sh.nr > 0) h->Shs = sell_from_bsr<double>(h->Sh, *h->ar, s);
 }
 
-scr_status fail(const Error& e) {
-    set_last_error(e.what());
-    return e.code;
-}
+scr_status fail(const std::exception& e) { return status_of(e); }
 
 void ensure_workspaces(scr_handle* h, const scr_solve_opts& o, hipStream_t s) {
     if (o.restart < 1 || o.restart > 63 || o.restart_inner < 1 || o.restart_inner > 63)
@@ -253,7 +250,7 @@ void ensure_workspaces(scr_handle* h, const scr_solve_opts& o, hipStream_t s) {
             h->gA.reset(new Gmres(3 * h->nb, o.restart_inner, *h->ar, s));
             h->gS.reset(new Gmres(h->nb, o.restart_inner, *h->ar, s));
             h->gA32.reset();
-            if (h->opts.precision == SCR_MIXED && h->hA->level0_f())
+            if (h->opts.precision == SCR_MIXED_FP32_INNER && h->hA->level0_f())
                 h->gA32.reset(new GmresT<float>(3 * h->nb, o.restart_inner, *h->ar, s));
             h->restart_inner = o.restart_inner;
         }
@@ -354,7 +351,7 @@ scr_status scr_ctx_create(int device, int64_t hbm_budget, scr_ctx** out) {
         c->c.cu_count = p.multiProcessorCount;
         *out = c;
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         return fail(e);
     }
 }
@@ -408,7 +405,8 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         if (opts) h->opts = *opts;
         else scr_default_amg_opts(&h->opts);
         const scr_amg_opts& o = h->opts;
-        if (o.precision != SCR_FP64 && o.precision != SCR_MIXED) throw Error(SCR_E_INVALID, "precision");
+        if (o.precision != SCR_FP64 && o.precision != SCR_MIXED && o.precision != SCR_MIXED_FP32_INNER)
+            throw Error(SCR_E_INVALID, "precision");
         if (!(o.theta > 0) || o.coarse_max < 1 || o.max_levels < 1 || o.cheb_degree < 1 || o.jacobi_sweeps < 1 ||
             !(o.cheb_ratio > 1) || !(o.max_coarse_ratio > 0) || o.schur_cheb_degree < 0 ||
             !(o.schur_cheb_ratio == 0.0 || o.schur_cheb_ratio > 1))
@@ -489,7 +487,7 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         h->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = h.release();
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         if (h) {
             h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->gA32.reset(); h->cg.reset();
             (void)hipStreamSynchronize(s);
@@ -564,7 +562,7 @@ scr_status amg_update(scr_handle* h, const scr_bsr* K, const double* coords, voi
         h->broken = false;
         h->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         (void)hipStreamSynchronize(s);
         return fail(e);
     }
@@ -634,7 +632,7 @@ scr_status scr_set_outlets(scr_handle* h, int n_out, const int64_t* off, const i
         h->n_out = n_out;
         h->n_oe = ne;
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         (void)hipStreamSynchronize(s);
         return fail(e);
     }
@@ -650,12 +648,13 @@ scr_status scr_handle_destroy(scr_handle* h) {
         (void)hipStreamSynchronize(s);
         delete h;
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         return fail(e);
     }
 }
 
 int64_t scr_handle_bytes(const scr_handle* h) { return (h && h->ar) ? h->ar->bytes() : 0; }
+int64_t scr_handle_peak_bytes(const scr_handle* h) { return (h && h->ar) ? h->ar->peak() : 0; }
 
 scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts, void* stream,
                      scr_stats* stats) {
@@ -694,7 +693,7 @@ scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_
         h->st.device_bytes = h->ar->bytes();
         if (stats) *stats = h->st;
         return k.converged ? SCR_OK : SCR_NOT_CONVERGED;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         (void)hipStreamSynchronize(s);
         if (stats && h) *stats = h->st;
         return fail(e);
@@ -721,7 +720,7 @@ scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const sc
         const int64_t n = h->nb;
         MatOp lop(&h->Ls);
         VOp pl(h->hL.get(), &h->st.vcycles_L);
-        bool flexible = o.flexible_cg || h->opts.precision == SCR_MIXED;
+        bool flexible = o.flexible_cg || h->opts.precision != SCR_FP64;
         bool ok = true;
         for (int c = 0; c < 3; ++c) {
             gather_col3(n, b, c, h->col_b, s);
@@ -739,7 +738,7 @@ scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const sc
         h->st.device_bytes = h->ar->bytes();
         if (stats) *stats = h->st;
         return ok ? SCR_OK : SCR_NOT_CONVERGED;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         (void)hipStreamSynchronize(s);
         if (stats && h) *stats = h->st;
         return fail(e);
@@ -752,7 +751,7 @@ int64_t scr_footprint_estimate(int kind, int64_t n_brows, int64_t nnzb, const sc
     if (solve) so = *solve;
     else scr_default_solve_opts(&so);
     const double pad = 1.15;     // sliced-ELL padding
-    const double amgf = (amg && amg->precision == SCR_MIXED) ? 0.5 : 1.0;
+    const double amgf = (amg && amg->precision != SCR_FP64) ? 0.5 : 1.0;
     double bytes;
     if (kind == SCR_SYSTEM) {
         double perblk = 132.0 + (76.0 + 28.0 + 28.0 + 12.0)          // K and its split (FP64 + indices)
@@ -781,7 +780,7 @@ scr_status scr_hier_levels(scr_handle* h, int which, int* nlev) {
         if (!h || !nlev) throw Error(SCR_E_INVALID, "NULL argument");
         *nlev = (int)which_hier(h, which)->L.size();
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         return fail(e);
     }
 }
@@ -796,7 +795,7 @@ scr_status scr_hier_level_info(scr_handle* h, int which, int level, int64_t* inf
         info[5] = L.P.nnzb; info[6] = L.R.nnzb; info[7] = H->ncoarse;
         *lam = L.lam;
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         return fail(e);
     }
 }
@@ -830,7 +829,7 @@ scr_status scr_hier_level_copy(scr_handle* h, int which, int level, int field, v
         if (!src) throw Error(SCR_E_INVALID, "field not present on this level");
         if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         return fail(e);
     }
 }
@@ -849,7 +848,7 @@ scr_status scr_matrix_copy(scr_handle* h, int which, int field, void* dst, int64
         else if (field == 1) HIPCHK(hipMemcpy(dst, M->ci, M->nnzb * sizeof(int32_t), hipMemcpyDeviceToHost));
         else HIPCHK(hipMemcpy(dst, M->v, M->nnzb * M->br * M->bc * sizeof(double), hipMemcpyDeviceToHost));
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         return fail(e);
     }
 }
@@ -893,7 +892,7 @@ scr_status scr_apply(scr_handle* h, int op, const double* x, double* y, const sc
         }
         HIPCHK(hipStreamSynchronize(s));
         return SCR_OK;
-    } catch (const Error& e) {
+    } catch (const std::exception& e) {
         (void)hipStreamSynchronize(s);
         return fail(e);
     }

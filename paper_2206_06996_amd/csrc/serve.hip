@@ -63,6 +63,7 @@ void run_job(scr_server* S, Job* j, hipStream_t st) {
     scr_handle* h = nullptr;
     scr_handle* hm = nullptr;
     double* kval = nullptr;            // assembled tangent values (16 nnzb), if j->tangent
+    const int64_t kbytes = j->K.nnzb * 16 * (int64_t)sizeof(double);
     auto t0 = Clock::now();
     scr_bsr K0 = j->K;
     scr_status rc = SCR_OK;
@@ -82,7 +83,7 @@ void run_job(scr_server* S, Job* j, hipStream_t st) {
     if (rc != SCR_OK) {
         r.status = rc;
     } else {
-        r.device_bytes = scr_handle_bytes(h) + (hm ? scr_handle_bytes(hm) : 0);
+        r.device_bytes = scr_handle_peak_bytes(h) + (hm ? scr_handle_peak_bytes(hm) : 0) + (kval ? kbytes : 0);
         auto t1 = Clock::now();
         for (size_t c = 0; c < j->b.size(); ++c) {
             const double* newval = nullptr;
@@ -119,7 +120,7 @@ void run_job(scr_server* S, Job* j, hipStream_t st) {
                 if (rm != SCR_OK && (r.status == SCR_OK || rm < 0)) r.status = rm;
                 if (rm < 0) break;
             }
-            int64_t by = scr_handle_bytes(h) + (hm ? scr_handle_bytes(hm) : 0);
+            int64_t by = scr_handle_peak_bytes(h) + (hm ? scr_handle_peak_bytes(hm) : 0) + (kval ? kbytes : 0);
             if (by > r.device_bytes) r.device_bytes = by;
         }
         r.solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - t1).count();
@@ -139,14 +140,13 @@ void worker(scr_server* S, int slot) {
         Job* j = nullptr;
         {
             std::unique_lock<std::mutex> lk(S->mu);
+            // the budget holds on the way out too: srv_destroy lets the queue drain, in order
             S->cv_work.wait(lk, [&] {
-                if (S->stop) return true;
-                if (S->queue.empty()) return false;
+                if (S->queue.empty()) return S->stop;
                 Job* h = S->queue.front();
                 return S->reserved + h->footprint <= S->budget || S->active == 0 || S->budget <= 0;
             });
-            if (S->stop && S->queue.empty()) return;
-            if (S->queue.empty()) continue;
+            if (S->queue.empty()) return;     // stop requested and nothing left
             j = S->queue.front();
             S->queue.pop_front();
             S->reserved += j->footprint;

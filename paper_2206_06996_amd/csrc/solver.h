@@ -117,6 +117,8 @@ class Hierarchy {
     std::vector<LevelSetup> L;
     double* cinv = nullptr;          // dense inverse of the coarsest matrix (FP64)
     int64_t ncoarse = 0;
+    double coarse_eta = 0.0;         // backward error of one solve with cinv (accuracy check)
+    bool coarse_pivoted = false;     // cinv came from the partial-pivoting fallback
     scr_amg_opts opts{};
     int64_t vcycles = 0;
     int64_t n0() const { return L.empty() ? 0 : L[0].A.nr * L[0].b; }

@@ -19,11 +19,11 @@ P = C.c_void_p
 SCR_OK, SCR_NOT_CONVERGED = 0, 1
 SCR_E_INVALID, SCR_E_OOM, SCR_E_HIP, SCR_E_BREAKDOWN, SCR_E_UNIMPLEMENTED, SCR_E_NO_DEVICE = -1, -2, -3, -4, -5, -6
 SCR_SYSTEM, MESH_SYSTEM = 0, 1
-SCR_FP64, SCR_MIXED = 0, 1
+SCR_FP64, SCR_MIXED, SCR_MIXED_FP32_INNER = 0, 1, 2
 SCR_SMOOTH_JACOBI, SCR_SMOOTH_CHEBYSHEV = 0, 1
 
 EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", "scr_ctx_destroy",
-            "scr_ctx_bytes_in_use", "amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
+            "scr_ctx_bytes_in_use", "scr_handle_peak_bytes", "amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
             "scr_handle_bytes", "scr_footprint_estimate", "scr_status_str", "scr_last_error", "scr_hier_levels",
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
             "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
@@ -117,6 +117,8 @@ def lib():
         L.scr_handle_destroy.argtypes = [P]
         L.scr_handle_bytes.argtypes = [P]
         L.scr_handle_bytes.restype = C.c_int64
+        L.scr_handle_peak_bytes.argtypes = [P]
+        L.scr_handle_peak_bytes.restype = C.c_int64
         L.scr_footprint_estimate.argtypes = [C.c_int, C.c_int64, C.c_int64, C.POINTER(AmgOpts), C.POINTER(SolveOpts)]
         L.scr_footprint_estimate.restype = C.c_int64
         L.scr_status_str.argtypes = [C.c_int]
@@ -225,6 +227,9 @@ class Handle:
 
     def bytes(self) -> int:
         return lib().scr_handle_bytes(self.ptr)
+
+    def peak_bytes(self) -> int:
+        return lib().scr_handle_peak_bytes(self.ptr)
 
     # ---- inspection
     def hier_levels(self, which: int) -> int:

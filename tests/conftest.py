@@ -53,3 +53,20 @@ def split_perm(nb):
     """Permutation taking interleaved [vx vy vz p] per node to split [v (3nb); p (nb)]."""
     v = np.arange(4 * nb).reshape(nb, 4)
     return np.concatenate([v[:, :3].reshape(-1), v[:, 3]])
+
+
+def field_errors(x, xref):
+    """Relative errors of the velocity and the pressure parts of node-interleaved [vx vy vz p]
+    vectors, each against its own norm (the pressure dominates the norm of the whole vector)."""
+    x4 = np.asarray(x).reshape(-1, 4)
+    r4 = np.asarray(xref).reshape(-1, 4)
+    ev = np.linalg.norm(x4[:, :3] - r4[:, :3]) / np.linalg.norm(r4[:, :3])
+    ep = np.linalg.norm(x4[:, 3] - r4[:, 3]) / np.linalg.norm(r4[:, 3])
+    return float(ev), float(ep)
+
+
+def assert_fields(x, xref, tol, what=""):
+    """Velocity and pressure each within tol of their own reference norms (printed first)."""
+    ev, ep = field_errors(x, xref)
+    print(f"[fields] {what} velocity err {ev:.2e}, pressure err {ep:.2e} (tol {tol:.0e})", flush=True)
+    assert ev <= tol and ep <= tol, (what, ev, ep)

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.conftest import bsr_to_dense
+from tests.conftest import assert_fields, bsr_to_dense
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -85,7 +85,7 @@ def test_all_dirichlet_velocity_block(scr, ctx, tiny):
     rc, st = scr.scr_solve(h, dev(b), x, scr.solve_opts(tol=1e-12))
     xl = np.linalg.solve(bsr_to_dense(s.rp, s.ci, val), b)
     assert rc == 0 and st["outer_it"] <= 2
-    assert np.linalg.norm(x.cpu().numpy() - xl) <= 1e-10 * np.linalg.norm(xl)
+    assert_fields(x.cpu().numpy(), xl, 1e-10, "all-Dirichlet velocity")
     h.destroy()
 
 
@@ -101,3 +101,42 @@ def test_all_dirichlet_mesh_laplacian(scr, ctx, tiny):
     assert rc == 0 and max(st["mesh_its"]) <= 1
     assert np.allclose(x.cpu().numpy(), b, rtol=0, atol=1e-14)
     h.destroy()
+
+
+def _dense_csr(M):
+    n = M.shape[0]
+    rp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    ci = np.tile(np.arange(n, dtype=np.int32), n)
+    return rp, ci, np.ascontiguousarray(M.reshape(-1))
+
+
+@pytest.mark.parametrize("case", ["tiny_leading_pivot", "zero_leading_block", "spd"])
+def test_coarse_direct_solve_pivots_when_needed(scr, ctx, case):
+    # a matrix no larger than coarse_max gives a one-level hierarchy whose V-cycle is the coarsest
+    # direct solve; nonsymmetric operators with a tiny or a zero leading pivot (the fast in-order
+    # inverse is spoilt there and the partial-pivoting fallback takes over) and an SPD one (the fast
+    # inverse passes its check) must all match dense LU
+    import oracle
+    rng = np.random.default_rng(17)
+    n = 200
+    M = rng.normal(size=(n, n)) + 20.0 * np.eye(n)
+    if case == "tiny_leading_pivot":
+        M[0, 0] = 1e-13
+    elif case == "zero_leading_block":
+        M[:2, :2] = np.array([[1e-300, 3.0], [2.0, 1e-300]])   # diagonal nonzero (validated), pivots ~0
+    else:
+        M = M @ M.T
+    rp, ci, v = _dense_csr(M)
+    for precision in (0, 1):
+        h = scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(rp), dev(ci), dev(v), None,
+                          scr.amg_opts(precision=precision, coarse_max=1024))
+        assert h.hier_levels(2) == 1
+        b = rng.uniform(-1, 1, n)
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        scr.scr_apply(h, "VL", dev(b), y)
+        xl = oracle.dense_solve(M, b)
+        err = np.linalg.norm(y.cpu().numpy() - xl) / np.linalg.norm(xl)
+        print(f"[gpu] coarse {case} precision={precision}: error vs dense LU {err:.2e}", flush=True)
+        # the FP32 V-cycle rounds its input and output to FP32 around the FP64 inverse
+        assert err <= (1e-11 if precision == 0 else 1e-6)
+        h.destroy()

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from tests.conftest import bsr_to_dense, split_perm
+from tests.conftest import assert_fields, bsr_to_dense, split_perm
 
 pytestmark = pytest.mark.gpu
 
@@ -212,7 +212,7 @@ def cfg0_reference(cfg0):
     return refs
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_cfg0_solve_parity(scr, ctx, cfg0, cfg0_reference, precision):
     h = gpu_setup(scr, ctx, cfg0, precision=precision)
     for seed, (b, xo) in cfg0_reference.items():
@@ -221,13 +221,12 @@ def test_cfg0_solve_parity(scr, ctx, cfg0, cfg0_reference, precision):
         rc, st = scr.scr_solve(h, dev(b), x)
         xg = host(x)
         rel = np.linalg.norm(b - oracle.bsr_spmv(cfg0.rp, cfg0.ci, cfg0.val, xg)) / np.linalg.norm(b)
-        err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-        print(f"[gpu]   rc={rc} outer={st['outer_it']} rel={rel:.3e} err={err:.3e} its_A={st['its_A']} "
+        print(f"[gpu]   rc={rc} outer={st['outer_it']} rel={rel:.3e} its_A={st['its_A']} "
               f"its_S={st['its_S']} its_I={st['its_I']} t={st['t_solve_ms']:.1f}ms", flush=True)
         assert rc == 0 and st["converged"] == 1
         assert rel <= 1e-8
         assert st["rel_res_true"] == pytest.approx(rel, rel=1e-3)
-        assert err <= 1e-6
+        assert_fields(xg, xo, 1e-6, f"cfg0 seed {seed} precision {precision}")
     h.destroy()
 
 
@@ -240,7 +239,7 @@ def test_fsi_solve_matches_dense_lu(scr, ctx, tiny, small_fsi):
         x = torch.zeros(4 * s.n_b, dtype=torch.float64, device="cuda")
         rc, st = scr.scr_solve(h, dev(b), x, scr.solve_opts(tol=1e-11))
         assert rc == 0
-        assert np.linalg.norm(host(x) - xl) <= 1e-9 * np.linalg.norm(xl)
+        assert_fields(host(x), xl, 1e-9, f"dense LU n_b={s.n_b}")
         h.destroy()
 
 

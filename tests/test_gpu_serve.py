@@ -1,10 +1,12 @@
 """Serving (continuous batching) on the GPU: every request's results are the same alone and in the
-mix (bitwise: the kernels are deterministic and requests share no state), admission respects the
-device-memory budget, oversize requests are rejected, and a failing request does not disturb the
-others."""
+mix (bitwise: the kernels are deterministic and requests share no state) and solve their systems
+(true residuals recomputed by the oracle's SpMV), every request's measured device-memory peak stays
+within its admission footprint, admission respects the device-memory budget, oversize requests are
+rejected, and a failing request does not disturb the others."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -38,7 +40,7 @@ def _systems():
             L=(dev(s.Lrp), dev(s.Lci), dev(s.Lval)),
             b=[dev(synth.rhs(100 * k + c, 4 * s.n_b, s.mask)) for c in range(nrhs)],
             bm=[dev(synth.rhs(100 * k + 50 + c, 3 * s.n_phys, np.repeat(s.Lmask, 3))) for c in range(nrhs)],
-            nb=s.n_b, nphys=s.n_phys))
+            nb=s.n_b, nphys=s.n_phys, sys=s))
     return out
 
 
@@ -84,6 +86,21 @@ def test_results_identical_alone_and_in_the_mix(scr, systems):
             assert np.array_equal(x.cpu().numpy(), ref)
         for x, ref in zip(xms, xma):
             assert np.array_equal(x.cpu().numpy(), ref)
+        # the served results solve their systems (the oracle's SpMV), and the request's measured peak
+        # of device memory stays within the footprint it was admitted with
+        sd = systems[k % len(systems)]
+        s = sd["sys"]
+        for x, b in zip(xs, sd["b"]):
+            bh = b.cpu().numpy()
+            r = bh - oracle.bsr_spmv(s.rp, s.ci, s.val, x.cpu().numpy())
+            assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(bh), k
+        for x, b in zip(xms, sd["bm"]):
+            xh, bh = x.cpu().numpy(), b.cpu().numpy()
+            for c in range(3):
+                rc_ = bh[c::3] - oracle.bsr_spmv(s.Lrp, s.Lci, s.Lval, xh[c::3])
+                assert np.linalg.norm(rc_) <= 1e-8 * max(np.linalg.norm(bh[c::3]), 1e-300), (k, c)
+        print(f"[gpu] request {k}: n_b={sd['nb']} peak {r['device_bytes']} footprint {r['footprint']}", flush=True)
+        assert 0 < r["device_bytes"] <= r["footprint"], (k, r["device_bytes"], r["footprint"])
     assert max_active >= 2                     # requests really overlapped
     srv.destroy()
     assert ctx.bytes_in_use() == 0

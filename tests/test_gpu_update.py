@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import synth
+from tests.conftest import assert_fields
 from tests.test_gpu_parity import _compare_hierarchy
 
 pytestmark = pytest.mark.gpu
@@ -180,19 +181,24 @@ def test_changed_time_step_matches_the_oracle_update(scr, ctx, dt_pair, with_coo
     rel = np.linalg.norm(b - oracle.bsr_spmv(s2.rp, s2.ci, s2.val, xg)) / np.linalg.norm(b)
     assert rel <= 1e-8
     xt, rct, _ = o.solve(b, oracle.solve_opts(tol=1e-12))
-    assert np.linalg.norm(xg - xt) <= 1e-6 * np.linalg.norm(xt)
+    assert_fields(xg, xt, 1e-6, "after amg_update")
     h.destroy()
 
 
-def test_mixed_precision_update_solves_the_new_system(scr, ctx, dt_pair):
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_precision_update_solves_the_new_system(scr, ctx, dt_pair, precision):
     s1, s2 = dt_pair
-    h = setup(scr, ctx, s1, precision=scr.SCR_MIXED)
+    h = setup(scr, ctx, s1, precision=precision)
     update(scr, h, s1, s2.val)
     b = synth.rhs(8, 4 * s2.n_b, s2.mask)
     xg, rc, st = solve(scr, h, b)
     assert rc == 0
     rel = np.linalg.norm(b - oracle.bsr_spmv(s2.rp, s2.ci, s2.val, xg)) / np.linalg.norm(b)
     assert rel <= 1e-8
+    o = oracle.Scr(s1.rp, s1.ci, s1.val, s1.xyz)
+    o.update(s2.val)
+    xt, rct, _ = o.solve(b, oracle.solve_opts(tol=1e-12))
+    assert_fields(xg, xt, 1e-6, f"mixed ({precision}) after amg_update")
     h.destroy()
 
 
