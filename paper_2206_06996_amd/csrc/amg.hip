@@ -1286,6 +1286,8 @@ class HierT : public Hierarchy {
         DBsrT<T> R;
         T* Dinv = nullptr;
         T *b = nullptr, *x = nullptr, *w = nullptr, *t1 = nullptr, *t2 = nullptr, *d = nullptr, *r = nullptr;
+        // the same vectors for three interleaved columns (scalar hierarchies built with `three`)
+        T *b3 = nullptr, *x3 = nullptr, *w3 = nullptr, *t13 = nullptr, *t23 = nullptr, *d3 = nullptr, *r3 = nullptr;
         std::vector<double> c1, c2;    // smoothing-step coefficients
         bool cheb = false;
     };
@@ -1301,6 +1303,7 @@ class HierT : public Hierarchy {
             LS& q = S[l];
             int64_t n = ls.A.nr * ls.b;
             q.b = a.make<T>(n); q.x = a.make<T>(n);
+            if (three) { q.b3 = a.make<T>(3 * n); q.x3 = a.make<T>(3 * n); }
             if (l + 1 == L.size()) continue;
             q.A = sell_from_bsr<T>(ls.A, a, s);
             q.P = sell_from_bsr<T>(ls.P, a, s);
@@ -1310,6 +1313,10 @@ class HierT : public Hierarchy {
             if (std::is_same<T, double>::value) copy_d(bb, ls.Dinv, (double*)q.Dinv, s);
             else cast_d2f(ls.Dinv, (float*)q.Dinv, bb, s);
             q.w = a.make<T>(n); q.t1 = a.make<T>(n); q.t2 = a.make<T>(n); q.d = a.make<T>(n); q.r = a.make<T>(n);
+            if (three) {
+                q.w3 = a.make<T>(3 * n); q.t13 = a.make<T>(3 * n); q.t23 = a.make<T>(3 * n);
+                q.d3 = a.make<T>(3 * n); q.r3 = a.make<T>(3 * n);
+            }
             // smoothing coefficients: step t computes dn = c1[t] d + c2[t] Dinv (b - A x)
             if (opts.smoother == SCR_SMOOTH_CHEBYSHEV) {
                 q.cheb = true;
@@ -1335,6 +1342,7 @@ class HierT : public Hierarchy {
             sell_free(q.P, a);
             a.free(q.R.v);
             for (T* p : {q.Dinv, q.b, q.x, q.w, q.t1, q.t2, q.d, q.r}) a.free(p);
+            for (T* p : {q.b3, q.x3, q.w3, q.t13, q.t23, q.d3, q.r3}) a.free(p);
         }
         S.clear();
         prepare(a, s);
@@ -1378,6 +1386,44 @@ class HierT : public Hierarchy {
         cycle(l + 1, S[l + 1].b, S[l + 1].x, s);
         sell_mv<T>(q.P, S[l + 1].x, nullptr, q.w, 2, s);
         smooth(l, q, b, q.w, x, s);
+    }
+
+    // the V-cycle on three interleaved columns: every kernel passes over its matrix once for all
+    // three, and each column's result is bitwise the one-column V-cycle's
+    void smooth3(LS& q, const T* b, const T* xin, T* dst, hipStream_t s) {
+        int ns = (int)q.c1.size();
+        const T* cur = xin;
+        for (int t = 0; t < ns; ++t) {
+            T* out = (t == ns - 1) ? dst : ((t % 2 == 0) ? q.t13 : q.t23);
+            bool rd = q.cheb && t > 0, wd = q.cheb && t + 1 < ns, zero = cur == nullptr;
+            smooth_step3<T>(q.A, q.Dinv, b, cur, q.d3, out, q.c1[t], q.c2[t], rd, wd, zero, s);
+            cur = out;
+        }
+    }
+    void cycle3(size_t l, const T* b, T* x, hipStream_t s) {
+        if (l + 1 == S.size()) {
+            dense_mv3<T>(ncoarse, cinv, b, x, s);
+            return;
+        }
+        LS& q = S[l];
+        smooth3(q, b, nullptr, q.w3, s);
+        sell_mv3<T>(q.A, q.w3, b, q.r3, 1, s);
+        bsrt_mv3<T>(q.R, q.r3, S[l + 1].b3, s);
+        cycle3(l + 1, S[l + 1].b3, S[l + 1].x3, s);
+        sell_mv3<T>(q.P, S[l + 1].x3, nullptr, q.w3, 2, s);
+        smooth3(q, b, q.w3, x, s);
+    }
+    void vcycle3(const double* x, double* y, hipStream_t s) override {
+        if (!three) throw Error(SCR_E_INVALID, "three-column V-cycle on a hierarchy built without it");
+        vcycles += 3;
+        int64_t n = n0();
+        if (std::is_same<T, double>::value) {
+            cycle3(0, (const T*)x, (T*)y, s);
+        } else {
+            cast_d2f(x, (float*)S[0].b3, 3 * n, s);
+            cycle3(0, S[0].b3, S[0].x3, s);
+            cast_f2d((const float*)S[0].x3, y, 3 * n, s);
+        }
     }
 
     void vcycle_f(const float* x, float* y, hipStream_t s) override {
@@ -1520,13 +1566,15 @@ static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
 }
 
 std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
-                                           hipStream_t s, Profiler* prof) {
+                                           hipStream_t s, Profiler* prof, bool three) {
+    if (three && A0.br != 1) throw Error(SCR_E_INVALID, "three-column V-cycles need a scalar matrix");
     std::unique_ptr<Hierarchy> H;
     HierT<double>* hd = nullptr;
     HierT<float>* hf = nullptr;
     if (o.precision != SCR_FP64) { hf = new HierT<float>(); hf->prof = prof; H.reset(hf); }
     else { hd = new HierT<double>(); hd->prof = prof; H.reset(hd); }
     H->opts = o;
+    H->three = three;
     int* err = ar.make<int>(1);
     unsigned long long* lamd = ar.make<unsigned long long>(1);
     // level 0: copy of A0 and B0

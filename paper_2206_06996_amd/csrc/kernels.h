@@ -47,6 +47,14 @@ void smooth_step(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* 
                  hipEvent_t e1 = nullptr);
 // x = M b for a dense row-major n x n FP64 matrix M (coarsest-level inverse)
 template <typename T> void dense_mv(int64_t n, const double* M, const T* b, T* x, hipStream_t s);
+// The same four operations for 1x1 matrices on three node-interleaved columns (entry 3 i + c), one
+// pass over the matrix; per column bitwise the one-column result
+template <typename T> void sell_mv3(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStream_t s);
+template <typename T> void bsrt_mv3(const DBsrT<T>& R, const T* x, T* y, hipStream_t s);
+template <typename T>
+void smooth_step3(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, double c1, double c2,
+                  bool read_d, bool write_d, bool zero_in, hipStream_t s);
+template <typename T> void dense_mv3(int64_t n, const double* M, const T* b, T* x, hipStream_t s);
 // validate a square BSR (device); returns error bits (synchronises)
 int validate_bsr(int64_t nr, int bs, int64_t nnzb, const int32_t* rp, const int32_t* ci, const double* v,
                  Arena& ar, hipStream_t s);
@@ -56,7 +64,5 @@ void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_
 void copy_d(int64_t n, const double* x, double* y, hipStream_t s);
 void interleaved_to_split(int64_t nb, const double* a, double* sv, hipStream_t s);
 void split_to_interleaved(int64_t nb, const double* sv, double* a, hipStream_t s);
-void gather_col3(int64_t n, const double* a, int c, double* y, hipStream_t s);
-void scatter_col3(int64_t n, const double* y, int c, double* a, hipStream_t s);
 
 }  // namespace scr

@@ -1,6 +1,6 @@
 // krylov.hip -- FP64 vector kernels, deterministic reductions and the Krylov drivers:
 // flexible GMRES with classical Gram-Schmidt applied twice (CGS2) and device-resident Givens
-// rotations, and (flexible) preconditioned CG.  Every reduction uses a grid fixed by the
+// rotations, and (flexible) preconditioned CG on three interleaved columns.  Every reduction uses a grid fixed by the
 // vector length and sums per-block partials in block order, so results are bitwise
 // reproducible run to run.
 #include <immintrin.h>
@@ -47,21 +47,6 @@ void split_to_interleaved(int64_t nb, const double* sv, double* a, hipStream_t s
     if (nb > 0) s2i_k<<<cdiv(nb, 256), 256, 0, s>>>(nb, sv, a);
     check_launch("s2i");
 }
-__global__ void gcol_k(int64_t n, const double* __restrict__ a, int c, double* __restrict__ y) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = a[3 * i + c];
-}
-__global__ void scol_k(int64_t n, const double* __restrict__ y, int c, double* __restrict__ a) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[3 * i + c] = y[i];
-}
-void gather_col3(int64_t n, const double* a, int c, double* y, hipStream_t s) {
-    if (n > 0) gcol_k<<<cdiv(n, 256), 256, 0, s>>>(n, a, c, y);
-}
-void scatter_col3(int64_t n, const double* y, int c, double* a, hipStream_t s) {
-    if (n > 0) scol_k<<<cdiv(n, 256), 256, 0, s>>>(n, y, c, a);
-}
-
 // ------------------------------------------------------------------ reduction machinery
 void Reducer::init(int64_t n_, Arena& ar, hipStream_t s) {
     n = n_;
@@ -469,112 +454,165 @@ KStat GmresT<T>::solve(OpT<T>& A, OpT<T>& M, const T* b, T* x, double tol, int m
 template class GmresT<double>;
 template class GmresT<float>;
 
-// ------------------------------------------------------------------ CG kernels
-enum { C_RZ = 0, C_ALPHA = 1, C_BETA = 2, C_RN2 = 3, C_PQ = 4 };
+// ------------------------------------------------------------------ CG on three columns
+// Per-column state (doubles): RZ[3] | ALPHA[3] | BETA[3] | PQ[3] | DONE[3] | RN2[3] | spare
+enum { C3_RZ = 0, C3_ALPHA = 3, C3_BETA = 6, C3_PQ = 9, C3_DONE = 12, C3_RN2 = 15, C3_SIZE = 32 };
 
-// st[ALPHA] = st[RZ] / (p . q)  (from the partials of p . q)
-__global__ void __launch_bounds__(RTPB) cg_alpha_fin_k(const double* __restrict__ partials, int nblk, double* __restrict__ st) {
-    final_sums<1>(partials, nblk, 1, st + C_PQ);
-    if (threadIdx.x == 0) st[C_ALPHA] = st[C_RZ] / st[C_PQ];
+// the reduction grid of a vector length (as Reducer::init)
+static int reduce_grid(int64_t n) {
+    int64_t g = cdiv(n, 4 * RTPB);
+    return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }
 
-// (rold = r;) x += alpha p; r -= alpha q; partials of r . r
-__global__ void __launch_bounds__(RTPB) cg_update_k(int64_t n, double* __restrict__ x, const double* __restrict__ p,
-                                                    double* __restrict__ r, const double* __restrict__ q,
-                                                    double* __restrict__ rold, const double* __restrict__ st,
+// partials of x_c . y_c per column (the element order of dot_part_k, per column)
+__global__ void __launch_bounds__(RTPB) dot3_part_k(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
                                                     double* __restrict__ partials) {
-    double alpha = st[C_ALPHA];
-    double acc[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) {
-        double ri = r[i];
-        if (rold) rold[i] = ri;
-        x[i] += alpha * p[i];
-        ri -= alpha * q[i];
-        r[i] = ri;
-        acc[0] += ri * ri;
-    }
-    block_partials<1>(acc, 1, partials);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += x[3 * i + c] * y[3 * i + c];
+    block_partials<3>(acc, 3, partials);
+}
+__global__ void __launch_bounds__(RTPB) sum3_pub_k(const double* __restrict__ partials, int nblk, double* __restrict__ out,
+                                                   double* __restrict__ hslot, double seq) {
+    final_sums<3>(partials, nblk, 3, out);
+    if (threadIdx.x == 0) publish(hslot, out, 3, seq);
+}
+// ALPHA_c = RZ_c / PQ_c for the columns still running
+__global__ void __launch_bounds__(RTPB) cg3_alpha_fin_k(const double* __restrict__ partials, int nblk, double* __restrict__ st) {
+    final_sums<3>(partials, nblk, 3, st + C3_PQ);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) st[C3_ALPHA + c] = st[C3_DONE + c] != 0.0 ? 0.0 : st[C3_RZ + c] / st[C3_PQ + c];
+}
+// per running column: (rold = r;) x += alpha p; r -= alpha q; partials of r . r
+__global__ void __launch_bounds__(RTPB) cg3_update_k(int64_t n, double* __restrict__ x, const double* __restrict__ p,
+                                                     double* __restrict__ r, const double* __restrict__ q,
+                                                     double* __restrict__ rold, const double* __restrict__ st,
+                                                     double* __restrict__ partials) {
+    double alpha[3];
+    bool run[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { alpha[c] = st[C3_ALPHA + c]; run[c] = st[C3_DONE + c] == 0.0; }
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (!run[c]) continue;
+            const int64_t o = 3 * i + c;
+            double ri = r[o];
+            if (rold) rold[o] = ri;
+            x[o] += alpha[c] * p[o];
+            ri -= alpha[c] * q[o];
+            r[o] = ri;
+            acc[c] += ri * ri;
+        }
+    block_partials<3>(acc, 3, partials);
+}
+// partials of r_c . z_c and (flexible) z_c . (r_c - rold_c)
+__global__ void __launch_bounds__(RTPB) cg3_rz_k(int64_t n, const double* __restrict__ r, const double* __restrict__ z,
+                                                 const double* __restrict__ rold, double* __restrict__ partials) {
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double zi = z[3 * i + c], ri = r[3 * i + c];
+            acc[c] += ri * zi;
+            if (rold) acc[3 + c] += zi * (ri - rold[3 * i + c]);
+        }
+    block_partials<6>(acc, 6, partials);
+}
+// BETA_c = (flex ? num_c : rz_new_c) / RZ_c; RZ_c = rz_new_c   (init: only RZ)
+__global__ void __launch_bounds__(RTPB) cg3_beta_fin_k(const double* __restrict__ partials, int nblk, int flexible,
+                                                       int init, double* __restrict__ st) {
+    __shared__ double res[6];
+    final_sums<6>(partials, nblk, 6, res);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) {
+            if (st[C3_DONE + c] != 0.0) continue;
+            if (!init) st[C3_BETA + c] = (flexible ? res[3 + c] : res[c]) / st[C3_RZ + c];
+            st[C3_RZ + c] = res[c];
+        }
+}
+__global__ void cg3_p_k(int64_t n3, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ st) {
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n3) return;
+    const int c = (int)(o % 3);
+    p[o] = st[C3_DONE + c] != 0.0 ? 0.0 : z[o] + st[C3_BETA + c] * p[o];
+}
+__global__ void cg3_set_done_k(double* __restrict__ st, double d0, double d1, double d2) {
+    if (threadIdx.x == 0) { st[C3_DONE] = d0; st[C3_DONE + 1] = d1; st[C3_DONE + 2] = d2; }
+}
+__global__ void cg3_init_k(double* __restrict__ st) {
+    for (int e = threadIdx.x; e < C3_SIZE; e += blockDim.x) st[e] = 0.0;
 }
 
-// partials of r . z and (flexible) z . (r - rold)
-__global__ void __launch_bounds__(RTPB) cg_rz_k(int64_t n, const double* __restrict__ r, const double* __restrict__ z,
-                                                const double* __restrict__ rold, double* __restrict__ partials) {
-    double acc[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * RTPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RTPB) {
-        double zi = z[i], ri = r[i];
-        acc[0] += ri * zi;
-        if (rold) acc[1] += zi * (ri - rold[i]);
-    }
-    block_partials<2>(acc, 2, partials);
-}
-// beta = (flex ? num : rz_new) / rz; rz = rz_new   (init: only rz = rz_new)
-__global__ void __launch_bounds__(RTPB) cg_beta_fin_k(const double* __restrict__ partials, int nblk, int flexible,
-                                                      int init, double* __restrict__ st) {
-    __shared__ double res[2];
-    final_sums<2>(partials, nblk, 2, res);
-    if (threadIdx.x == 0) {
-        if (!init) st[C_BETA] = (flexible ? res[1] : res[0]) / st[C_RZ];
-        st[C_RZ] = res[0];
-    }
+int64_t Pcg3::workspace_doubles(int64_t n) {
+    return 15 * n + C3_SIZE + (int64_t)reduce_grid(n) * RMAXJ + RMAXJ;
 }
 
-__global__ void cg_p_k(int64_t n, double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ st) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double beta = st[C_BETA];
-    if (i < n) p[i] = z[i] + beta * p[i];
+Pcg3::Pcg3(int64_t n, double* ws, StatusSlot* slot) : n_(n), grid_(reduce_grid(n)), slot_(slot) {
+    r_ = ws; z_ = r_ + 3 * n; p_ = z_ + 3 * n; q_ = p_ + 3 * n; rold_ = q_ + 3 * n;
+    st_ = rold_ + 3 * n;
+    part_ = st_ + C3_SIZE;
+    out_ = part_ + (int64_t)grid_ * RMAXJ;
 }
 
-Pcg::Pcg(int64_t n, Arena& ar, hipStream_t s) : n_(n), ar_(&ar) {
-    r_ = ar.make<double>(n); z_ = ar.make<double>(n); p_ = ar.make<double>(n);
-    q_ = ar.make<double>(n); rold_ = ar.make<double>(n); st_ = ar.make<double>(8);
-    red_.init(n, ar, s);
-    slot_.h = ar.ctx()->pinned.get();
-    slot_.d = PinnedPool::device_ptr(slot_.h);
-    slot_.h[15] = 0.0;
-}
-Pcg::~Pcg() {
-    if (slot_.h) ar_->ctx()->pinned.put(slot_.h);
-    ar_->free(r_); ar_->free(z_); ar_->free(p_); ar_->free(q_); ar_->free(rold_); ar_->free(st_);
-    red_.release(*ar_);
-}
-
-KStat Pcg::solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool flexible, hipStream_t s) {
-    KStat st;
+Pcg3::Result Pcg3::solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool flexible,
+                         hipStream_t s) {
+    Result res;
     const int64_t n = n_;
-    const int G = red_.grid;
-    double* part = red_.partials;
-    int64_t nblk = cdiv(n, 256);
-    zero_dev(x, n * sizeof(double), s);
-    double bn = device_norm(b, n, red_, slot_, s);
-    if (bn == 0.0) { st.converged = true; return st; }
-    if (!std::isfinite(bn)) throw Error(SCR_E_BREAKDOWN, "non-finite right-hand side");
-    copy_d(n, b, r_, s);
+    const int G = grid_;
+    const int64_t nblk3 = cdiv(3 * n, 256);
+    cg3_init_k<<<1, 64, 0, s>>>(st_);
+    zero_dev(x, 3 * n * sizeof(double), s);
+    dot3_part_k<<<G, RTPB, 0, s>>>(n, b, b, part_);
+    sum3_pub_k<<<1, RTPB, 0, s>>>(part_, G, out_, slot_->d, slot_->next());
+    check_launch("cg3 norm");
+    slot_->wait(s);
+    double bn[3];
+    bool done[3];
+    for (int c = 0; c < 3; ++c) {
+        bn[c] = std::sqrt(slot_->h[c]);
+        if (!std::isfinite(bn[c])) throw Error(SCR_E_BREAKDOWN, "non-finite right-hand side");
+        done[c] = bn[c] == 0.0;
+        res.converged[c] = done[c];
+    }
+    if (done[0] && done[1] && done[2]) return res;
+    cg3_set_done_k<<<1, 64, 0, s>>>(st_, done[0] ? 1.0 : 0.0, done[1] ? 1.0 : 0.0, done[2] ? 1.0 : 0.0);
+    copy_d(3 * n, b, r_, s);
     M.apply(r_, z_, s);
-    copy_d(n, z_, p_, s);
-    cg_rz_k<<<G, RTPB, 0, s>>>(n, r_, z_, nullptr, part);
-    cg_beta_fin_k<<<1, RTPB, 0, s>>>(part, G, 0, 1, st_);
+    copy_d(3 * n, z_, p_, s);
+    cg3_rz_k<<<G, RTPB, 0, s>>>(n, r_, z_, nullptr, part_);
+    cg3_beta_fin_k<<<1, RTPB, 0, s>>>(part_, G, 0, 1, st_);
     double* rold = flexible ? rold_ : nullptr;
     for (;;) {
         A.apply(p_, q_, s);
-        dot_part_k<<<G, RTPB, 0, s>>>(n, p_, q_, part);
-        cg_alpha_fin_k<<<1, RTPB, 0, s>>>(part, G, st_);
-        cg_update_k<<<G, RTPB, 0, s>>>(n, x, p_, r_, q_, rold, st_, part);
-        sum_pub_k<<<1, RTPB, 0, s>>>(part, G, st_ + C_RN2, slot_.d, slot_.next());
-        check_launch("cg");
-        slot_.wait(s);
-        ++st.iters;
-        double rn = std::sqrt(slot_.h[0]);
-        if (!std::isfinite(rn)) throw Error(SCR_E_BREAKDOWN, "non-finite residual in CG");
-        st.rel_res = rn / bn;
-        if (rn <= tol * bn) { st.converged = true; break; }
-        if (st.iters >= maxit) break;
+        dot3_part_k<<<G, RTPB, 0, s>>>(n, p_, q_, part_);
+        cg3_alpha_fin_k<<<1, RTPB, 0, s>>>(part_, G, st_);
+        cg3_update_k<<<G, RTPB, 0, s>>>(n, x, p_, r_, q_, rold, st_, part_);
+        sum3_pub_k<<<1, RTPB, 0, s>>>(part_, G, st_ + C3_RN2, slot_->d, slot_->next());
+        check_launch("cg3");
+        slot_->wait(s);
+        bool changed = false;
+        for (int c = 0; c < 3; ++c) {
+            if (done[c]) continue;
+            ++res.iters[c];
+            const double rn = std::sqrt(slot_->h[c]);
+            if (!std::isfinite(rn)) throw Error(SCR_E_BREAKDOWN, "non-finite residual in CG");
+            res.rel[c] = rn / bn[c];
+            if (rn <= tol * bn[c]) { res.converged[c] = true; done[c] = true; changed = true; }
+            else if (res.iters[c] >= maxit) { done[c] = true; changed = true; }
+        }
+        if (done[0] && done[1] && done[2]) break;
+        if (changed)
+            cg3_set_done_k<<<1, 64, 0, s>>>(st_, done[0] ? 1.0 : 0.0, done[1] ? 1.0 : 0.0, done[2] ? 1.0 : 0.0);
         M.apply(r_, z_, s);
-        cg_rz_k<<<G, RTPB, 0, s>>>(n, r_, z_, rold, part);
-        cg_beta_fin_k<<<1, RTPB, 0, s>>>(part, G, flexible ? 1 : 0, 0, st_);
-        cg_p_k<<<nblk, 256, 0, s>>>(n, p_, z_, st_);
-        check_launch("cg");
+        cg3_rz_k<<<G, RTPB, 0, s>>>(n, r_, z_, rold, part_);
+        cg3_beta_fin_k<<<1, RTPB, 0, s>>>(part_, G, flexible ? 1 : 0, 0, st_);
+        cg3_p_k<<<nblk3, 256, 0, s>>>(3 * n, p_, z_, st_);
+        check_launch("cg3");
     }
-    return st;
+    return res;
 }
 
 }  // namespace scr

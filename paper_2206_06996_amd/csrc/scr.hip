@@ -29,10 +29,12 @@ struct scr_handle {
     // SCR_MIXED_FP32_INNER: Algorithm 2's inner A solve on FP32 vectors (FP32 A of the hierarchy)
     std::unique_ptr<GmresT<float>> gA32;
     float *xbar32 = nullptr, *xtil32 = nullptr;
-    std::unique_ptr<Pcg> cg;
     int restart = 0, restart_inner = 0;
     double *bs = nullptr, *xs = nullptr, *yhat = nullptr, *tv = nullptr, *tp = nullptr, *xbar = nullptr,
-           *xtil = nullptr, *col_b = nullptr, *col_x = nullptr;
+           *xtil = nullptr;
+    // mesh motion: the three-column CG's workspace (allocated on the first solve) and its status slot
+    double* mws = nullptr;
+    StatusSlot mslot;
     scr_stats st{};
     scr_solve_opts so{};
     bool broken = false;                          // a failed amg_update left the hierarchies half-updated
@@ -92,6 +94,17 @@ struct MatOp : Op {
     const DSell<double>* M;
     explicit MatOp(const DSell<double>* m) : M(m) {}
     void apply(const double* x, double* y, hipStream_t s) override { sell_mv<double>(*M, x, nullptr, y, 0, s); }
+};
+// the scalar mesh Laplacian and AMG(L) on three node-interleaved columns
+struct MatOp3 : Op {
+    const DSell<double>* M;
+    explicit MatOp3(const DSell<double>* m) : M(m) {}
+    void apply(const double* x, double* y, hipStream_t s) override { sell_mv3<double>(*M, x, nullptr, y, 0, s); }
+};
+struct VOp3 : Op {
+    Hierarchy* H;
+    explicit VOp3(Hierarchy* h) : H(h) {}
+    void apply(const double* x, double* y, hipStream_t s) override { H->vcycle3(x, y, s); }
 };
 // K with the outlet coupling, on split vectors (the velocity part leads)
 struct KOp : Op {
@@ -258,9 +271,31 @@ void ensure_workspaces(scr_handle* h, const scr_solve_opts& o, hipStream_t s) {
             h->xbar32 = h->ar->make<float>(3 * h->nb);
             h->xtil32 = h->ar->make<float>(3 * h->nb);
         }
-    } else if (!h->cg) {
-        h->cg.reset(new Pcg(h->nb, *h->ar, s));
+    } else if (!h->mws) {
+        h->mws = h->ar->make<double>(Pcg3::workspace_doubles(h->nb));
     }
+}
+
+// The mesh-motion solve of Sec. 5.2.2 on the three interleaved columns: CG (flexible CG for an FP32
+// hierarchy or on request) with one product with L and one V-cycle of AMG(L) per iteration for all
+// three columns; ws holds Pcg3::workspace_doubles(n) doubles.  Fills the handle's stats.
+bool mesh_solve_run(scr_handle* h, const double* b, double* x, const scr_solve_opts& o, double* ws, hipStream_t s) {
+    MatOp3 lop(&h->Ls);
+    VOp3 pl(h->hL.get());
+    const bool flexible = o.flexible_cg || h->opts.precision != SCR_FP64;
+    const int64_t v0 = h->hL->vcycles;
+    Pcg3 cg(h->nb, ws, &h->mslot);
+    Pcg3::Result k = cg.solve(lop, pl, b, x, o.tol, o.max_it, flexible, s);
+    bool ok = true;
+    for (int c = 0; c < 3; ++c) {
+        h->st.mesh_its[c] = k.iters[c];
+        h->st.mesh_rel[c] = k.rel[c];
+        ok &= k.converged[c];
+        if (k.iters[c] > h->st.outer_it) h->st.outer_it = (int)k.iters[c];
+        if (k.rel[c] > h->st.rel_res_true) h->st.rel_res_true = k.rel[c];
+    }
+    h->st.vcycles_L = h->hL->vcycles - v0;
+    return ok;
 }
 
 // flag = 1 if the pattern (rp, ci) differs from the stored one (rp already known to be in range)
@@ -477,11 +512,12 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         } else {
             double* ones = ar.make<double>(nb);
             fill<double>(ones, 1.0, nb, s);
-            h->hL = build_hierarchy(Km, ones, 1, o, ar, s);
+            h->hL = build_hierarchy(Km, ones, 1, o, ar, s, nullptr, true);
             ar.free(ones);
             h->Ls = sell_from_bsr<double>(Km, ar, s);
-            h->col_b = ar.make<double>(nb);
-            h->col_x = ar.make<double>(nb);
+            h->mslot.h = ctx->c.pinned.get();
+            h->mslot.d = PinnedPool::device_ptr(h->mslot.h);
+            h->mslot.h[15] = 0.0;
         }
         HIPCHK(hipStreamSynchronize(s));
         h->st.t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -489,8 +525,9 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         return SCR_OK;
     } catch (const std::exception& e) {
         if (h) {
-            h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->gA32.reset(); h->cg.reset();
+            h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->gA32.reset();
             (void)hipStreamSynchronize(s);
+            if (h->mslot.h) h->ctx->pinned.put(h->mslot.h);
             h->ar.reset();
             (void)hipStreamSynchronize(s);
         }
@@ -642,8 +679,10 @@ scr_status scr_handle_destroy(scr_handle* h) {
     if (!h) return SCR_OK;
     try {
         hipStream_t s = h->ar ? h->ar->stream() : nullptr;
-        h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->gA32.reset(); h->cg.reset();
+        h->gOuter.reset(); h->gA.reset(); h->gS.reset(); h->gA32.reset();
         h->hA.reset(); h->hS.reset(); h->hL.reset();
+        (void)hipStreamSynchronize(s);
+        if (h->mslot.h) h->ctx->pinned.put(h->mslot.h);
         h->ar.reset();
         (void)hipStreamSynchronize(s);
         delete h;
@@ -717,21 +756,7 @@ scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const sc
         double setup_ms = h->st.t_setup_ms;
         h->st = scr_stats{};
         h->st.t_setup_ms = setup_ms;
-        const int64_t n = h->nb;
-        MatOp lop(&h->Ls);
-        VOp pl(h->hL.get(), &h->st.vcycles_L);
-        bool flexible = o.flexible_cg || h->opts.precision != SCR_FP64;
-        bool ok = true;
-        for (int c = 0; c < 3; ++c) {
-            gather_col3(n, b, c, h->col_b, s);
-            KStat k = h->cg->solve(lop, pl, h->col_b, h->col_x, o.tol, o.max_it, flexible, s);
-            scatter_col3(n, h->col_x, c, x, s);
-            h->st.mesh_its[c] = k.iters;
-            h->st.mesh_rel[c] = k.rel_res;
-            ok &= k.converged;
-            if (k.iters > h->st.outer_it) h->st.outer_it = (int)k.iters;
-            if (k.rel_res > h->st.rel_res_true) h->st.rel_res_true = k.rel_res;
-        }
+        bool ok = mesh_solve_run(h, b, x, o, h->mws, s);
         HIPCHK(hipStreamSynchronize(s));
         h->st.converged = ok ? 1 : 0;
         h->st.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -762,8 +787,12 @@ int64_t scr_footprint_estimate(int kind, int64_t n_brows, int64_t nnzb, const sc
                                          1.0 * (2 * so.restart_inner + 1) + 24.0);
         bytes = perblk * nnzb + hier + krylov + 64.0 * 1024 * 1024 + 8.0 * 1024 * 1024 * 2;
     } else {
+        // L and its solve copy; the hierarchy (values in FP64 for setup, T for the V-cycle); one- and
+        // three-column level vectors (28 per level, the levels adding up to about 1.1 n); the CG
+        // workspace (15 n)
         double hier = nnzb * 12.0 * 3.0 * (1.0 + amgf);
-        bytes = nnzb * 12.0 * (1.0 + pad) + hier + 8.0 * n_brows * 12.0 + 16.0 * 1024 * 1024;
+        double vecs = 8.0 * n_brows * (1.1 * 28.0 * (amgf < 1.0 ? 0.5 : 1.0) + 1.1 * 2.0 + 15.0 + 12.0);
+        bytes = nnzb * 12.0 * (1.0 + pad) + hier + vecs + 16.0 * 1024 * 1024;
     }
     return (int64_t)bytes;
 }

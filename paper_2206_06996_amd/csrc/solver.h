@@ -69,19 +69,30 @@ class GmresT {
 };
 using Gmres = GmresT<double>;
 
-// Preconditioned CG, or flexible CG with the Polak-Ribiere beta (Notay 2000).
-class Pcg {
+// Preconditioned CG, or flexible CG with the Polak-Ribiere beta (Notay 2000), on three
+// node-interleaved columns at once (the mesh-motion system of Sec. 5.2.2: one Laplacian for x, y
+// and z): one product with L and one V-cycle of AMG(L) per iteration for all three, each column
+// with its own recurrence scalars and its own stopping test.  Per column the arithmetic and the
+// reduction order are those of a one-column CG with the same grid.
+// The workspace (Pcg3::workspace_doubles(n) doubles) and the status slot are the caller's (the
+// slot's sequence number must persist from one solve to the next).
+class Pcg3 {
    public:
-    Pcg(int64_t n, Arena& ar, hipStream_t s);
-    ~Pcg();
-    KStat solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool flexible, hipStream_t s);
+    static int64_t workspace_doubles(int64_t n);
+    Pcg3(int64_t n, double* ws, StatusSlot* slot);
+    struct Result {
+        int64_t iters[3] = {0, 0, 0};
+        double rel[3] = {0.0, 0.0, 0.0};
+        bool converged[3] = {false, false, false};
+    };
+    // x (3n, interleaved) is overwritten; A and M act on interleaved three-column vectors
+    Result solve(Op& A, Op& M, const double* b, double* x, double tol, int maxit, bool flexible, hipStream_t s);
 
    private:
     int64_t n_;
-    Arena* ar_;
-    double *r_, *z_, *p_, *q_, *rold_, *st_;
-    Reducer red_;
-    StatusSlot slot_;
+    int grid_;
+    double *r_, *z_, *p_, *q_, *rold_, *st_, *part_, *out_;
+    StatusSlot* slot_;
 };
 
 template <typename T>
@@ -113,6 +124,10 @@ class Hierarchy {
     // FP32 hierarchies: the V-cycle on FP32 vectors (no conversions), and the FP32 sliced-ELL copy
     // of the level-0 matrix (nullptr when the hierarchy is FP64 or has a single level)
     virtual void vcycle_f(const float* x, float* y, hipStream_t s) = 0;
+    // scalar hierarchies built with `three`: the V-cycle on three node-interleaved columns (the mesh
+    // Laplacian acts on x, y and z alike), FP64 in and out; counts three V-cycles
+    virtual void vcycle3(const double* x, double* y, hipStream_t s) = 0;
+    bool three = false;
     virtual const DSell<float>* level0_f() const = 0;
     std::vector<LevelSetup> L;
     double* cinv = nullptr;          // dense inverse of the coarsest matrix (FP64)
@@ -126,7 +141,7 @@ class Hierarchy {
 
 // prof: the context profiler, or nullptr; when set, level-0 smoother steps are timed.
 std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
-                                           hipStream_t s, Profiler* prof = nullptr);
+                                           hipStream_t s, Profiler* prof = nullptr, bool three = false);
 
 // Numeric re-setup for new level-0 values on the same pattern (and, if B0 is not NULL, a new
 // near-null space): aggregates and every pattern are kept, every value-dependent quantity of every

@@ -880,6 +880,262 @@ template void smooth_step<double>(const DSell<double>&, const double*, const dou
 template void smooth_step<float>(const DSell<float>&, const float*, const float*, const float*, float*, float*,
                                  double, double, bool, bool, bool, hipStream_t, hipEvent_t, hipEvent_t);
 
+// ---------------------------------------------------------------- three interleaved columns (1x1 blocks)
+// The scalar mesh Laplacian acts on x, y and z alike (Sec. 5.2.2): its products, smoother steps,
+// restriction and coarse solve take the three columns of node-interleaved vectors (entry 3 i + c)
+// in one pass over the matrix.  Per column every sum is taken in the order of the one-column
+// kernels above (same slot order, same slice split, same lane tree), so each column's result is
+// bitwise that of the one-column kernel.
+
+// the three-column form of sell_row_dot for 1x1 blocks: the slot's column index and value are
+// loaded once and the three x entries of the column gathered together; each column accumulates in
+// the slot order of the one-column loop (the same unroll, the same terms)
+template <typename T>
+__device__ __forceinline__ void sell_row_dot3(int64_t o0, int64_t o1, int lane, const int32_t* __restrict__ ci,
+                                              const T* __restrict__ v, const T* __restrict__ x, T (&acc)[3]) {
+    constexpr int U = Unroll<1>::U;
+    acc[0] = acc[1] = acc[2] = 0;
+    int64_t t = o0;
+    int32_t c[U];
+    if (t + U <= o1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = ci[(t + u) * WAVE + lane];
+    }
+    for (; t + U <= o1; t += U) {
+        T xx[U][3], vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xx[u][k] = x[3 * (int64_t)c[u] + k];
+        int32_t cn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t q = t + U + u < o1 ? t + U + u : o1 - 1;     // stays inside the slice
+            cn[u] = ci[q * WAVE + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u] = v[(t + u) * WAVE + lane];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k] += vv[u] * xx[u][k];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = cn[u];
+    }
+    for (; t < o1; ++t) {
+        int64_t cc = ci[t * WAVE + lane];
+        T vv = v[t * WAVE + lane];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += vv * x[3 * cc + k];
+    }
+}
+template <typename T, int MODE, int WPS>
+__global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) sell_mv3_k(int64_t nslices, const int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
+                                                  const T* __restrict__ v, const T* __restrict__ x,
+                                                  const T* __restrict__ b, T* __restrict__ y) {
+    int wv = threadIdx.x / WAVE;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * SliceGroup<WPS>::SPB + wv / WPS;
+    int lane = threadIdx.x & (WAVE - 1);
+    bool live = sl < nslices;
+    T acc[3] = {0, 0, 0};
+    if (live) {
+        int64_t a, e;
+        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        sell_row_dot3<T>(a, e, lane, ci, v, x, acc);
+    }
+    if (WPS > 1) {
+        __shared__ T red[SliceGroup<WPS>::SPB * WPS][3][WAVE];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) red[wv][c][lane] = acc[c];
+        __syncthreads();
+        if (wv % WPS != 0) return;
+        for (int w = 1; w < WPS; ++w)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += red[wv + w][c][lane];
+    }
+    if (!live) return;
+    int64_t i = rowid[sl * WAVE + lane];
+    if (i < 0) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int64_t o = 3 * i + c;
+        if (MODE == 0) y[o] = acc[c];
+        else if (MODE == 1) y[o] = b[o] - acc[c];
+        else if (MODE == 2) y[o] += acc[c];
+        else y[o] -= acc[c];
+    }
+}
+
+template <typename T>
+void sell_mv3(const DSell<T>& A, const T* x, const T* b, T* y, int mode, hipStream_t s) {
+    if (A.br != 1 || A.bc != 1 || A.rowlane) throw Error(SCR_E_UNIMPLEMENTED, "sell_mv3: 1x1 blocks only");
+    if (A.nslices == 0) return;
+    int wps = waves_per_slice(A);
+#define MV3(W)                                                                                                  \
+    {                                                                                                           \
+        constexpr int W_ = W;                                                                                   \
+        dim3 g((unsigned)cdiv(A.nslices, SliceGroup<W_>::SPB)), th(SliceGroup<W_>::THREADS);                    \
+        switch (mode) {                                                                                         \
+            case 0: sell_mv3_k<T, 0, W_><<<g, th, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+            case 1: sell_mv3_k<T, 1, W_><<<g, th, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+            case 2: sell_mv3_k<T, 2, W_><<<g, th, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+            default: sell_mv3_k<T, 3, W_><<<g, th, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, x, b, y); break; \
+        }                                                                                                       \
+    }
+    if (wps == 1) MV3(1)
+    else if (wps == 2) MV3(2)
+    else if (wps == 4) MV3(4)
+    else if (wps == 8) MV3(8)
+    else MV3(16)
+#undef MV3
+    check_launch("sell_mv3");
+}
+template void sell_mv3<double>(const DSell<double>&, const double*, const double*, double*, int, hipStream_t);
+template void sell_mv3<float>(const DSell<float>&, const float*, const float*, float*, int, hipStream_t);
+
+// y = R x for 1x1 R (rows of R are long; one row per wavefront, the lane tree of bsrt_mv_k)
+template <typename T>
+__global__ void __launch_bounds__(256) bsrt_mv3_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                  const T* __restrict__ v, const T* __restrict__ x, T* __restrict__ y) {
+    int64_t row = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x / WAVE);
+    if (row >= nr) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    T acc[3] = {0, 0, 0};
+    int64_t q0 = rp[row], len = rp[row + 1] - q0;
+    for (int64_t j = lane; j < len; j += WAVE) {
+        int64_t c = ci[q0 + j];
+        const T vv = v[q0 + j];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += vv * x[3 * c + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T sum = wave_sum(acc[k]);
+        if (lane == 0) y[3 * row + k] = sum;
+    }
+}
+template <typename T>
+void bsrt_mv3(const DBsrT<T>& R, const T* x, T* y, hipStream_t s) {
+    if (R.br != 1 || R.bc != 1) throw Error(SCR_E_UNIMPLEMENTED, "bsrt_mv3: 1x1 blocks only");
+    int64_t nblk = cdiv(R.nr, 4);
+    if (nblk == 0) return;
+    bsrt_mv3_k<T><<<nblk, 256, 0, s>>>(R.nr, R.rp, R.ci, R.v, x, y);
+    check_launch("bsrt_mv3");
+}
+template void bsrt_mv3<double>(const DBsrT<double>&, const double*, double*, hipStream_t);
+template void bsrt_mv3<float>(const DBsrT<float>&, const float*, float*, hipStream_t);
+
+// one smoothing step on three columns (1x1 blocks): as smooth_k with B = 1, per column
+template <typename T, bool RD, bool WD, bool ZERO, int WPS>
+__global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) smooth3_k(int64_t nslices, const int32_t* __restrict__ off,
+                                                 const int32_t* __restrict__ rowid, const int32_t* __restrict__ ci,
+                                                 const T* __restrict__ v, const T* __restrict__ Dinv,
+                                                 const T* __restrict__ b, const T* __restrict__ xin, T* __restrict__ d,
+                                                 T* __restrict__ xout, T c1, T c2) {
+    int wv = threadIdx.x / WAVE;
+    int64_t sl = xcd_tile(blockIdx.x, gridDim.x) * SliceGroup<WPS>::SPB + wv / WPS;
+    bool live = sl < nslices;
+    int lane = threadIdx.x & (WAVE - 1);
+    T acc[3] = {0, 0, 0};
+    if (!ZERO && live) {
+        int64_t a, e;
+        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        sell_row_dot3<T>(a, e, lane, ci, v, xin, acc);
+    }
+    if (WPS > 1) {
+        __shared__ T red[SliceGroup<WPS>::SPB * WPS][3][WAVE];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) red[wv][c][lane] = acc[c];
+        __syncthreads();
+        if (wv % WPS != 0) return;
+        for (int w = 1; w < WPS; ++w)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += red[wv + w][c][lane];
+    }
+    if (!live) return;
+    int64_t i = rowid[sl * WAVE + lane];
+    if (i < 0) return;
+    const T di = Dinv[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int64_t o = 3 * i + c;
+        const T res = b[o] - acc[c];
+        T z = 0;
+        z += di * res;
+        T dn = c2 * z;
+        if (RD) dn += c1 * d[o];
+        if (WD) d[o] = dn;
+        xout[o] = ZERO ? dn : xin[o] + dn;
+    }
+}
+
+template <typename T>
+void smooth_step3(const DSell<T>& A, const T* Dinv, const T* b, const T* xin, T* d, T* xout, double c1, double c2,
+                  bool read_d, bool write_d, bool zero_in, hipStream_t s) {
+    if (A.br != 1 || A.bc != 1 || A.rowlane) throw Error(SCR_E_UNIMPLEMENTED, "smooth_step3: 1x1 blocks only");
+    if (A.nslices == 0) return;
+    const T C1 = (T)c1, C2 = (T)c2;
+    int wps = zero_in ? 1 : waves_per_slice(A);
+#define S3W(RD, WD, Z, W)                                                                                        \
+    do {                                                                                                         \
+        dim3 g((unsigned)cdiv(A.nslices, SliceGroup<W>::SPB)), th(SliceGroup<W>::THREADS);                        \
+        smooth3_k<T, RD, WD, Z, W><<<g, th, 0, s>>>(A.nslices, A.off, A.rowid, A.ci, A.v, Dinv, b, xin, d, xout,  \
+                                                   C1, C2);                                                      \
+    } while (0)
+#define S3(RD, WD, Z)                                                                                            \
+    do {                                                                                                         \
+        if (wps == 16) S3W(RD, WD, Z, 16);                                                                       \
+        else if (wps == 8) S3W(RD, WD, Z, 8);                                                                    \
+        else if (wps == 4) S3W(RD, WD, Z, 4);                                                                    \
+        else if (wps == 2) S3W(RD, WD, Z, 2);                                                                    \
+        else S3W(RD, WD, Z, 1);                                                                                  \
+    } while (0)
+    if (zero_in) {
+        if (write_d) S3W(false, true, true, 1); else S3W(false, false, true, 1);
+    } else if (read_d) {
+        if (write_d) S3(true, true, false); else S3(true, false, false);
+    } else {
+        if (write_d) S3(false, true, false); else S3(false, false, false);
+    }
+#undef S3
+#undef S3W
+    check_launch("smooth_step3");
+}
+template void smooth_step3<double>(const DSell<double>&, const double*, const double*, const double*, double*,
+                                   double*, double, double, bool, bool, bool, hipStream_t);
+template void smooth_step3<float>(const DSell<float>&, const float*, const float*, const float*, float*, float*,
+                                  double, double, bool, bool, bool, hipStream_t);
+
+// x = M b on three columns (the lane tree of dense_mv_k, per column)
+template <typename T>
+__global__ void __launch_bounds__(256) dense_mv3_k(int64_t n, const double* __restrict__ M, const T* __restrict__ b,
+                                                   T* __restrict__ x) {
+    int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (row >= n) return;
+    int lane = threadIdx.x & (WAVE - 1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t c = lane; c < n; c += WAVE) {
+        const double m = M[row * n + c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] += m * (double)b[3 * c + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double sum = wave_sum(acc[k]);
+        if (lane == 0) x[3 * row + k] = (T)sum;
+    }
+}
+template <typename T>
+void dense_mv3(int64_t n, const double* M, const T* b, T* x, hipStream_t s) {
+    if (n <= 0) return;
+    dense_mv3_k<T><<<cdiv(n, 4), 256, 0, s>>>(n, M, b, x);
+    check_launch("dense_mv3");
+}
+template void dense_mv3<double>(int64_t, const double*, const double*, double*, hipStream_t);
+template void dense_mv3<float>(int64_t, const double*, const float*, float*, hipStream_t);
+
 // ---------------------------------------------------------------- coarsest level: x = M b (M = A_c^-1, FP64)
 template <typename T>
 __global__ void __launch_bounds__(256) dense_mv_k(int64_t n, const double* __restrict__ M, const T* __restrict__ b,

@@ -146,7 +146,8 @@ def lib():
         L.scr_assembler_nbrows.argtypes = [P]
         L.scr_assembler_nbrows.restype = C.c_int64
         L.scr_assembler_destroy.argtypes = [P]
-        for f in ("amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy", "scr_ctx_create",
+        for f in ("amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve",
+                  "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
                   "scr_ctx_profile", "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait",
                   "srv_drain", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_destroy"):

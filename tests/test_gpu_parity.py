@@ -306,3 +306,30 @@ def test_determinism(scr, ctx, cfg0):
         h.destroy()
     assert np.array_equal(aggs[0], aggs[1])
     assert np.array_equal(xs[0], xs[1])
+
+
+def test_mesh_columns_are_independent(scr, ctx, cfg0):
+    # the three columns share each pass over L and AMG(L) but nothing else: each column of a
+    # three-column solve is bitwise the solve of that column alone (the others zero, so finished
+    # at once), with the same iteration count; a zero column stays zero
+    s = cfg0
+    for precision in (0, 1):
+        h = scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(s.Lrp), dev(s.Lci), dev(s.Lval), None,
+                          scr.amg_opts(precision=precision))
+        b = synth.rhs(31, 3 * s.n_phys, np.repeat(s.Lmask, 3))
+        x = torch.zeros(3 * s.n_phys, dtype=torch.float64, device="cuda")
+        rc, st = scr.mesh_motion_solve(h, dev(b), x, scr.solve_opts(tol=1e-10, max_it=500))
+        assert rc == 0
+        xg = host(x)
+        for c in range(3):
+            bc = np.zeros_like(b)
+            bc[c::3] = b[c::3]
+            xc = torch.full((3 * s.n_phys,), np.nan, dtype=torch.float64, device="cuda")
+            rc1, st1 = scr.mesh_motion_solve(h, dev(bc), xc, scr.solve_opts(tol=1e-10, max_it=500))
+            xch = host(xc)
+            assert rc1 == 0 and st1["mesh_its"][c] == st["mesh_its"][c]
+            assert np.array_equal(xch[c::3], xg[c::3]), (precision, c)
+            for o in range(3):
+                if o != c:
+                    assert not xch[o::3].any() and st1["mesh_its"][o] == 0
+        h.destroy()

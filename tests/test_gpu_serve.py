@@ -92,8 +92,8 @@ def test_results_identical_alone_and_in_the_mix(scr, systems):
         s = sd["sys"]
         for x, b in zip(xs, sd["b"]):
             bh = b.cpu().numpy()
-            r = bh - oracle.bsr_spmv(s.rp, s.ci, s.val, x.cpu().numpy())
-            assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(bh), k
+            res = bh - oracle.bsr_spmv(s.rp, s.ci, s.val, x.cpu().numpy())
+            assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(bh), k
         for x, b in zip(xms, sd["bm"]):
             xh, bh = x.cpu().numpy(), b.cpu().numpy()
             for c in range(3):
