@@ -89,6 +89,7 @@ def lib():
         L.orc_strength.argtypes = [C.c_int64, C.c_int, P, P, P, C.c_double, P, P]
         L.orc_mis_key.argtypes = [C.c_uint64, C.c_int, C.c_int64]
         L.orc_mis_key.restype = C.c_uint64
+        L.orc_num_threads.restype = C.c_int
         L.orc_mis2.argtypes = [C.c_int64, P, P, P, P, C.c_uint64, C.c_int, P]
         L.orc_aggregate.argtypes = [C.c_int64, P, P, P, P, P, C.c_uint64, C.c_int, P]
         L.orc_aggregate.restype = C.c_int64
@@ -169,6 +170,11 @@ def strength(rp, ci, val, theta):
     flags = np.empty(ci.size, np.uint8); iso = np.empty(nr, np.uint8)
     lib().orc_strength(nr, b, _p(rp), _p(ci), _p(val), theta, _p(flags), _p(iso))
     return flags, iso
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(lib().orc_num_threads())
 
 
 def mis_key(seed, level, i):

@@ -28,6 +28,7 @@
  * count, bit for bit.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -37,6 +38,9 @@
 #define PAR_MIN 4096
 /* dot products: partial sums over fixed chunks of this many entries, then over the chunks */
 #define DOT_CHUNK 4096
+
+/* threads the parallel loops use (OMP_NUM_THREADS, else every core) */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ sparse block matrix */
 typedef struct {
