@@ -207,6 +207,18 @@ scr_status scr_solve(scr_handle* h, const double* b, double* x, const scr_solve_
 scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts /* host */,
                              void* stream, scr_stats* stats /* host */);
 
+/* mesh_motion_solve without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same solve, the
+ * same kernels and the bitwise same result, with the CG workspace (15 n + O(1) doubles) in a
+ * static device array of 256 MiB that each GPU holds from the first context on it until the
+ * process ends, instead of the handle's memory.  Everything else it uses (L, AMG(L), the level
+ * vectors, the status slot) was allocated by amg_setup.  Limit: meshes of up to about 2.2M nodes;
+ * larger ones return SCR_E_INVALID.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other threads, other streams) race and must be serialised by the caller.
+ * Other arguments, results and errors as mesh_motion_solve. */
+scr_status mesh_motion_solve_noalloc(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts /* host */,
+                                     void* stream, scr_stats* stats /* host */);
+
 scr_status scr_handle_destroy(scr_handle* h);
 /* Device memory the handle holds now, and the most it ever held (setup temporaries included);
  * bytes as counted against the context budget. */

@@ -13,6 +13,35 @@ static thread_local std::string g_last_error;
 void set_last_error(const std::string& m) { g_last_error = m; }
 }  // namespace scr
 
+// Device scratch of mesh_motion_solve_noalloc (the three-column CG's workspace), one copy per GPU,
+// held until the process ends.  Host code uses only the per-device address from
+// hipGetSymbolAddress (noalloc_scratch), never this name.
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = int64_t(32) << 20;     // 256 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// the address of this device's copy of `scratch`; the device must be current.  Taken once per
+// device (at context creation).
+double* noalloc_scratch(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) throw Error(SCR_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw Error(SCR_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace
+
 struct scr_handle {
     Ctx* ctx = nullptr;
     int kind = SCR_SYSTEM;
@@ -380,6 +409,7 @@ scr_status scr_ctx_create(int device, int64_t hbm_budget, scr_ctx** out) {
             uint64_t thr = UINT64_MAX;
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
         }
+        (void)noalloc_scratch(device);     // this device's scratch address, once (device is current)
         auto* c = new scr_ctx();
         c->c.device = device;
         c->c.budget = hbm_budget;
@@ -757,6 +787,42 @@ scr_status mesh_motion_solve(scr_handle* h, const double* b, double* x, const sc
         h->st = scr_stats{};
         h->st.t_setup_ms = setup_ms;
         bool ok = mesh_solve_run(h, b, x, o, h->mws, s);
+        HIPCHK(hipStreamSynchronize(s));
+        h->st.converged = ok ? 1 : 0;
+        h->st.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        h->st.device_bytes = h->ar->bytes();
+        if (stats) *stats = h->st;
+        return ok ? SCR_OK : SCR_NOT_CONVERGED;
+    } catch (const std::exception& e) {
+        (void)hipStreamSynchronize(s);
+        if (stats && h) *stats = h->st;
+        return fail(e);
+    }
+}
+
+scr_status mesh_motion_solve_noalloc(scr_handle* h, const double* b, double* x, const scr_solve_opts* opts,
+                                     void* stream, scr_stats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (!h || !b || !x) throw Error(SCR_E_INVALID, "NULL argument");
+        if (h->kind != MESH_SYSTEM) throw Error(SCR_E_INVALID, "mesh_motion_solve_noalloc needs a MESH_SYSTEM handle");
+        if (h->broken) throw Error(SCR_E_INVALID, "handle left unusable by a failed amg_update");
+        const int64_t need = Pcg3::workspace_doubles(h->nb);
+        if (need > NOALLOC_SCRATCH_DOUBLES)
+            throw Error(SCR_E_INVALID, "mesh of " + std::to_string(h->nb) + " nodes needs " +
+                                           std::to_string(need * 8) + " bytes of scratch; the static scratch holds " +
+                                           std::to_string(NOALLOC_SCRATCH_DOUBLES * 8));
+        HIPCHK(hipSetDevice(h->ctx->device));
+        double* ws = noalloc_scratch(h->ctx->device);
+        scr_solve_opts o;
+        if (opts) o = *opts;
+        else scr_default_solve_opts(&o);
+        check_opts(o);
+        double setup_ms = h->st.t_setup_ms;
+        h->st = scr_stats{};
+        h->st.t_setup_ms = setup_ms;
+        bool ok = mesh_solve_run(h, b, x, o, ws, s);
         HIPCHK(hipStreamSynchronize(s));
         h->st.converged = ok ? 1 : 0;
         h->st.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -23,7 +23,7 @@ SCR_FP64, SCR_MIXED, SCR_MIXED_FP32_INNER = 0, 1, 2
 SCR_SMOOTH_JACOBI, SCR_SMOOTH_CHEBYSHEV = 0, 1
 
 EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", "scr_ctx_destroy",
-            "scr_ctx_bytes_in_use", "scr_handle_peak_bytes", "amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
+            "scr_ctx_bytes_in_use", "scr_handle_peak_bytes", "mesh_motion_solve_noalloc", "amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
             "scr_handle_bytes", "scr_footprint_estimate", "scr_status_str", "scr_last_error", "scr_hier_levels",
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
             "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
@@ -114,6 +114,7 @@ def lib():
         L.scr_set_outlets.argtypes = [P, C.c_int, P, P, P, P, P]
         L.scr_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), P, C.POINTER(Stats)]
         L.mesh_motion_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), P, C.POINTER(Stats)]
+        L.mesh_motion_solve_noalloc.argtypes = [P, P, P, C.POINTER(SolveOpts), P, C.POINTER(Stats)]
         L.scr_handle_destroy.argtypes = [P]
         L.scr_handle_bytes.argtypes = [P]
         L.scr_handle_bytes.restype = C.c_int64
@@ -147,7 +148,7 @@ def lib():
         L.scr_assembler_nbrows.restype = C.c_int64
         L.scr_assembler_destroy.argtypes = [P]
         for f in ("amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve",
-                  "scr_handle_destroy", "scr_ctx_create",
+                  "mesh_motion_solve_noalloc", "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
                   "scr_ctx_profile", "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait",
                   "srv_drain", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_destroy"):
@@ -383,6 +384,16 @@ def mesh_motion_solve(h: Handle, b, x, opts: SolveOpts | None = None, stream=Non
     st = Stats()
     rc = _check(lib().mesh_motion_solve(h.ptr, _dev(b, torch.float64, "b"), _dev(x, torch.float64, "x"),
                                         C.byref(opts) if opts else None, _stream(stream), C.byref(st)),
+                allow=(SCR_OK, SCR_NOT_CONVERGED))
+    return rc, st.as_dict()
+
+
+def mesh_motion_solve_noalloc(h: Handle, b, x, opts: SolveOpts | None = None, stream=None):
+    """mesh_motion_solve with the CG workspace in the library's static device scratch."""
+    import torch
+    st = Stats()
+    rc = _check(lib().mesh_motion_solve_noalloc(h.ptr, _dev(b, torch.float64, "b"), _dev(x, torch.float64, "x"),
+                                                C.byref(opts) if opts else None, _stream(stream), C.byref(st)),
                 allow=(SCR_OK, SCR_NOT_CONVERGED))
     return rc, st.as_dict()
 
