@@ -232,6 +232,17 @@ __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restr
     }
 }
 
+// Block-row lanes: the E = 3*bc values of slot t.  FP32: entry e of lane l at (t*E + e)*64 + l.  FP64:
+// the entries in pairs (e, e+1) stored next to each other per lane, so that a lane reads two of
+// them with one 16-byte load (a wavefront 1 KB per load instruction), and an odd last entry as a
+// plain 64-wide vector after the pairs.
+__host__ __device__ __forceinline__ int64_t rl_vidx(int64_t t, int e, int lane, int E, bool paired) {
+    if (!paired) return (t * E + e) * WAVE + lane;
+    const int64_t base = t * E * WAVE;
+    if (e < (E & ~1)) return base + (e >> 1) * 2 * WAVE + lane * 2 + (e & 1);
+    return base + (int64_t)(E - 1) * WAVE + lane;
+}
+
 // block-row lanes: one thread per (slice, lane) = block row; all br*bc entries of each slot
 template <typename T>
 __global__ void sell_fill_rowlane(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -253,7 +264,7 @@ __global__ void sell_fill_rowlane(const int32_t* __restrict__ rp, const int32_t*
         int64_t q = lo + (t - o0);
         bool real = i >= 0 && q < hi;
         sci[t * WAVE + lane] = real ? ci[q] : pad;
-        for (int e = 0; e < nb2; ++e) sv[(t * nb2 + e) * WAVE + lane] = real ? (T)v[q * nb2 + e] : (T)0;
+        for (int e = 0; e < nb2; ++e) sv[rl_vidx(t, e, lane, nb2, sizeof(T) == 8)] = real ? (T)v[q * nb2 + e] : (T)0;
     }
 }
 
@@ -476,9 +487,22 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
                                              const T* __restrict__ v, const T* __restrict__ x, T r[3],
                                              int32_t irow = -1, T* dg = nullptr) {
     constexpr int U = BC == 3 ? 2 : 1, E = 3 * BC;
-    auto ld = [](const T* p) -> T {
-        if (sizeof(T) == 8) return __builtin_nontemporal_load(p);
-        return *p;
+    // the E values of slot tt (layout of rl_vidx): FP64 in 16-byte pairs, nontemporal
+    auto load_slot = [&](int64_t tt, T (&vv)[E]) {
+        if constexpr (sizeof(T) == 8) {
+            typedef T V2 __attribute__((ext_vector_type(2)));
+            const T* base = v + tt * E * WAVE;
+#pragma unroll
+            for (int k = 0; k < E / 2; ++k) {
+                const V2 w = __builtin_nontemporal_load(reinterpret_cast<const V2*>(base + k * 2 * WAVE) + lane);
+                vv[2 * k] = w.x;
+                vv[2 * k + 1] = w.y;
+            }
+            if constexpr (E % 2 == 1) vv[E - 1] = __builtin_nontemporal_load(base + (E - 1) * WAVE + lane);
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) vv[e] = v[(tt * E + e) * WAVE + lane];
+        }
     };
     auto fma_block = [&](const T* vv, const T* xx) {
 #pragma unroll
@@ -513,9 +537,7 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
         }
         __builtin_amdgcn_sched_barrier(0);     // keep the gathers and indices ahead of the values
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int e = 0; e < E; ++e) vv[u][e] = ld(v + ((t + u) * E + e) * WAVE + lane);
+        for (int u = 0; u < U; ++u) load_slot(t + u, vv[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) fma_block(vv[u], xx[u]);
         if constexpr (CAP) {
@@ -533,8 +555,7 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
     if (U > 1 && t < o1) {
         int64_t c = ci[t * WAVE + lane];
         T vv[E], xx[BC];
-#pragma unroll
-        for (int e = 0; e < E; ++e) vv[e] = ld(v + (t * E + e) * WAVE + lane);
+        load_slot(t, vv);
 #pragma unroll
         for (int k = 0; k < BC; ++k) xx[k] = x[c * BC + k];
         fma_block(vv, xx);
