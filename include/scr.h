@@ -285,6 +285,87 @@ int64_t scr_assembler_nbrows(const scr_assembler* a);
  * server request, must have finished. */
 scr_status scr_assembler_destroy(scr_assembler* a);
 
+/* ---------------------------------------------------------------- time integration
+ * The segregated predictor multi-corrector algorithm of Sec. 3.5 with the first-order
+ * generalized-alpha method of Sec. 3.4 (same-Y predictor; alpha_m, alpha_f, gamma from the
+ * assembler's rho_inf), run on the device for the linear(ised) unified continuum on a fixed mesh:
+ * the fluid VMS at rest of Sec. 3.2 (the tangent of scr_assemble_tangent without convection), the
+ * small-strain solid of Sec. 3.1 in velocity form with its kinematic equation u_dot = v, the
+ * interface pressure duplication of Sec. 3.3, and the mesh motion by harmonic extension of the
+ * solid displacement (Sec. 2.2.2; Dirichlet data: the solid displacement on mesh nodes whose
+ * velocity row touches a solid element, zero on the other Dirichlet nodes).  The residual of the
+ * balance equations is R = K_rate (v_dot - f, p_dot) + K_state (v, p) + K_disp (u_solid, 0) at
+ * the intermediate states (f: the body force per unit mass), with the operators the same element
+ * integrals give
+ * (the corrector tangent divided by alpha_f gamma dt is c_t K_rate + K_state + K_disp / c_t).
+ * One step, from the state at t_n:
+ *   predictor  y_{n+1} = y_n, y_dot_{n+1} = ((gamma-1)/gamma) y_dot_n (every field);
+ *   corrector l = 1, 2, ...: (1-2) du_dot_s = (alpha_f gamma dt/alpha_m) dv_dot_s - R_k/alpha_m,
+ *     u_dot_s += du_dot_s, u_s += gamma dt du_dot_s on the solid rows, with dv_dot_s the previous
+ *     corrector's velocity-rate increment and R_k = u_dot_s(alpha_m) - v(alpha_f) at the iterate
+ *     before that increment was applied (at l = 1: zero and the predictor's R_k);
+ *     (3-4) the mesh displacement from mesh_motion_solve and the mesh velocity
+ *     v_hat = (u_hat_{n+1} - u_hat_n)/(gamma dt) + ((gamma-1)/gamma) v_hat_n; (7) the residual; (8)
+ *     stop when ||R|| <= tol_R ||R_(1)|| or ||R|| <= tol_A; (9) scr_solve of the corrector system
+ *     for (dv_dot, dp_dot); (10) v_dot += dv_dot, v += gamma dt dv_dot, p_dot += dp_dot,
+ *     p += gamma dt dp_dot.
+ * Dirichlet dofs (the assembler's mask) keep zero increments and zero residual.  The reduced
+ * outlet models (steps 5-6) and the update of the geometry by the mesh motion are not part of this
+ * model.  A step with a new dt re-assembles the operators and re-sets the hierarchies up
+ * numerically (amg_update: aggregates and patterns kept). */
+typedef struct {
+    int32_t max_correctors;    /* l_max, 10 */
+    double tol_R;              /* relative stopping tolerance of step 8, 1e-6 */
+    double tol_A;              /* absolute stopping tolerance of step 8, 1e-14 */
+    double mesh_tol;           /* tolerance of the mesh-motion solves, 1e-10 */
+} scr_corrector_opts;
+
+typedef struct {
+    int32_t correctors;        /* corrector iterations (the last one only tested the residual) */
+    int32_t converged;
+    double res0, res;          /* ||R|| at the first corrector and at the last test */
+    int64_t linear_its;        /* outer FGMRES iterations over the step's corrector solves */
+    int64_t mesh_its;          /* mesh CG iterations (largest column) summed over the correctors */
+    int32_t resetups;          /* 1 if the step re-assembled and re-set up for a new dt */
+    double t_ms;
+} scr_step_stats;
+
+typedef enum {
+    SCR_STATE_Y = 0,           /* (v, p): 4 per block row, node-interleaved */
+    SCR_STATE_YDOT = 1,        /* (v_dot, p_dot): 4 per block row */
+    SCR_STATE_U_SOLID = 2,     /* solid displacement: 3 per block row (zero off solid rows) */
+    SCR_STATE_UDOT_SOLID = 3,  /* its rate */
+    SCR_STATE_U_MESH = 4,      /* mesh displacement: 3 per mesh node */
+    SCR_STATE_V_MESH = 5       /* mesh velocity: 3 per mesh node */
+} scr_state_field;
+
+typedef struct scr_stepper scr_stepper;
+
+void scr_default_corrector_opts(scr_corrector_opts* o);   /* o: host */
+
+/* a: the assembler of the system (its pattern, mesh, materials, mask and rho_inf; its dt is
+ * replaced by each step's); L: the mesh Laplacian of Sec. 2.2.2 with its Dirichlet nodes eliminated
+ * (as for MESH_SYSTEM); L_full: device, nnzb(L) values of the same Laplacian before the elimination
+ * (for the lifting of the Dirichlet data); mesh_mask: device, n_L bytes (1 = Dirichlet mesh node);
+ * blk_of_phys: device, n_L int32, the velocity block row of each mesh node; solid_rows: device,
+ * n_brows bytes (1 = the velocity row touches a solid element); coords: device, n_brows x 3;
+ * dt0: the first time step size.  All are copied; the state starts at rest.  The hierarchies are
+ * built here (amg_opts, solve_opts for every corrector solve; NULL = defaults). */
+scr_status scr_stepper_create(scr_ctx* ctx, scr_assembler* a, const scr_bsr* L, const double* L_full,
+                              const uint8_t* mesh_mask, const int32_t* blk_of_phys, const uint8_t* solid_rows,
+                              const double* coords, double dt0, const scr_amg_opts* amg /* host */,
+                              const scr_solve_opts* solve /* host */, const scr_corrector_opts* copts /* host */,
+                              void* stream, scr_stepper** out /* host */);
+/* Copy a field of the state at t_n (set = 0: into dst; set = 1: from dst). */
+scr_status scr_stepper_state(scr_stepper* s, int field, double* dst, int set, void* stream);
+/* One time step of size dt.  f: device, n_brows x 3 body force per unit mass at t_n + alpha_f dt
+ * (zero on Dirichlet dofs is not required), or NULL.  Returns SCR_OK, or SCR_NOT_CONVERGED when
+ * max_correctors did not meet the stopping test (the state is advanced either way); stats (host,
+ * may be NULL).  Errors: SCR_E_INVALID, SCR_E_BREAKDOWN, SCR_E_OOM, SCR_E_HIP, or a failed solve's
+ * status. */
+scr_status scr_step(scr_stepper* s, double dt, const double* f, void* stream, scr_step_stats* stats /* host */);
+scr_status scr_stepper_destroy(scr_stepper* s);
+
 /* Opt-in kernel timing (roofline measurement).  After scr_ctx_profile(ctx, kernel), every launch
  * of that kernel family on handles created from ctx afterwards is bracketed by HIP events on the
  * stream it runs on; scr_ctx_profile_read returns the number of launches, their summed duration

@@ -24,15 +24,29 @@ rule):
   its pressure row at ``tp`` (they differ on the fluid/solid interface, Sec. 3.3), then the
   symmetric elimination of Dirichlet dofs (rows and columns zeroed, unit diagonal).
 
+The same routine also yields the three parts of the linear(ised) semi-discrete residual that the
+predictor multi-corrector of Sec. 3.5 evaluates at the intermediate states, with no advection
+(``form``): "rate" acts on the rates (v_dot, p_dot): rho M in both media, the fine-scale rate term
+of the continuity row when it is enabled, and the solid pressure mass M / kappa; "state" acts on
+(v, p): the fluid viscous and grad-div terms, the pressure gradient / divergence pair and the
+fluid pressure stabilisation; "disp" acts on the solid displacement: the deviatoric elastic
+stiffness with the plain modulus mu_s.  Their Dirichlet rows and columns are zero (no unit
+diagonal).  Differentiating the residual at the intermediate states with respect to the velocity
+rate, with the solid displacement rate tied to it by the kinematic equation, gives
+tangent = c_t rate + state + disp / c_t.
+
 Pinned in ``tests/test_assembly_oracle.py`` by patch tests on a uniform box (linear fields),
 lumped-mass and lumped-volume identities, D = -G^T at rest, and agreement with the independently
-written element integrals of the input generator (themselves pinned in ``tests/test_synth.py``).
+written element integrals of the input generator (themselves pinned in ``tests/test_synth.py``);
+the residual parts in ``tests/test_corrector_oracle.py`` (lumped masses, rigid motions, the
+identity above at two step sizes, the medium each term lives in).
 """
 from __future__ import annotations
 
 import numpy as np
 
 MASS, VISC, GRADDIV, GD, CPP, CONV = 1, 2, 4, 8, 16, 32
+FORMS = ("tangent", "rate", "state", "disp")
 
 
 def genalpha(rho_inf: float):
@@ -66,9 +80,24 @@ def stabilisation(dN: np.ndarray, ub: np.ndarray, rho: float, mu: float, dt: flo
     return tauM, tauC
 
 
-def element_matrices(X, solid, U, prm: dict) -> np.ndarray:
+def _coefficients(form: str, ct: float, mu_f: float, visc_s: float, mu_s: float, kappa: float):
+    """Weight of each term in one assembled form: (mass, fluid viscosity, solid elastic modulus,
+    grad-div, G/D pair, fine-scale rate term, fluid pressure stabilisation, solid pressure mass)."""
+    if form == "tangent":
+        return dict(mass=ct, visc_f=mu_f, visc_s=visc_s, graddiv=1.0, gd=1.0, dtc=ct, cpp_f=1.0, cpp_s=ct / kappa)
+    if form == "rate":
+        return dict(mass=1.0, visc_f=0.0, visc_s=0.0, graddiv=0.0, gd=0.0, dtc=1.0, cpp_f=0.0, cpp_s=1.0 / kappa)
+    if form == "state":
+        return dict(mass=0.0, visc_f=mu_f, visc_s=0.0, graddiv=1.0, gd=1.0, dtc=0.0, cpp_f=1.0, cpp_s=0.0)
+    if form == "disp":
+        return dict(mass=0.0, visc_f=0.0, visc_s=mu_s, graddiv=0.0, gd=0.0, dtc=0.0, cpp_f=0.0, cpp_s=0.0)
+    raise ValueError(f"unknown form {form!r}")
+
+
+def element_matrices(X, solid, U, prm: dict, form: str = "tangent") -> np.ndarray:
     """Element tangents Ke[e, a, i, b, j] (i, j = 0..2 velocity, 3 pressure) of Sec. 3.5 divided by
-    alpha_f gamma dt.  X: (ne, 4, 3); solid: (ne,) bool; U: (ne, 4, 3) advective velocity at the
+    alpha_f gamma dt, or one residual part (``form``, see the module docstring; advection only in
+    the tangent).  X: (ne, 4, 3); solid: (ne,) bool; U: (ne, 4, 3) advective velocity at the
     vertices or None (at rest); prm: rho_f, mu_f, rho_s, E_s, nu_s, dt, rho_inf, terms,
     vms_dt_coupling."""
     ne = X.shape[0]
@@ -78,9 +107,10 @@ def element_matrices(X, solid, U, prm: dict) -> np.ndarray:
     ct = am / (af * gam * dt)
     mu_s = prm["E_s"] / (2.0 * (1.0 + prm["nu_s"]))
     kappa = prm["E_s"] / (3.0 * (1.0 - 2.0 * prm["nu_s"]))
+    w = _coefficients(form, ct, prm["mu_f"], (af * gam * dt / am) * mu_s, mu_s, kappa)
     dN, V = shape_gradients(X)
     fluid = ~solid
-    conv = (terms & CONV) != 0 and U is not None
+    conv = (terms & CONV) != 0 and U is not None and form == "tangent"
     ub = np.zeros((ne, 3))
     gu = np.zeros((ne, 3, 3))                                    # gu[e, i, j] = d u_i / d x_j
     if conv:
@@ -90,7 +120,7 @@ def element_matrices(X, solid, U, prm: dict) -> np.ndarray:
     tauM = np.where(fluid, tauM, 0.0)
     tauC = np.where(fluid, tauC, 0.0)
     rho = np.where(fluid, prm["rho_f"], prm["rho_s"])
-    visc = np.where(fluid, prm["mu_f"], (af * gam * dt / am) * mu_s)
+    visc = np.where(fluid, w["visc_f"], w["visc_s"])
 
     I3 = np.eye(3)
     Mab = V[:, None, None] * (np.ones((4, 4)) + np.eye(4))[None] / 20.0           # P1 mass matrix
@@ -99,14 +129,14 @@ def element_matrices(X, solid, U, prm: dict) -> np.ndarray:
     Ke = np.zeros((ne, 4, 4, 4, 4))
     Avv = np.zeros((ne, 4, 3, 4, 3))
     if terms & MASS:
-        Avv += (rho * ct)[:, None, None, None, None] * np.einsum("eab,ij->eaibj", Mab, I3)
+        Avv += (rho * w["mass"])[:, None, None, None, None] * np.einsum("eab,ij->eaibj", Mab, I3)
     if terms & VISC:
         Avv += visc[:, None, None, None, None] * (
             np.einsum("eab,ij->eaibj", Lab, I3)
             + V[:, None, None, None, None] * np.einsum("eaj,ebi->eaibj", dN, dN)
             - (2.0 / 3.0) * V[:, None, None, None, None] * np.einsum("eai,ebj->eaibj", dN, dN))
     if terms & GRADDIV:
-        Avv += (tauC * V)[:, None, None, None, None] * np.einsum("eai,ebj->eaibj", dN, dN)
+        Avv += (w["graddiv"] * tauC * V)[:, None, None, None, None] * np.einsum("eai,ebj->eaibj", dN, dN)
     if conv:
         # Galerkin convection rho w . (ub . grad) v and reaction rho w . (grad u) v
         # (N_a at the centroid is 1/4 for every a)
@@ -120,10 +150,10 @@ def element_matrices(X, solid, U, prm: dict) -> np.ndarray:
     Ke[:, :, :3, :, :3] = Avv
     if terms & GD:
         # -(p, div w) and (q, div v) with p, v at the centroid: V/4 per vertex value
-        Ke[:, :, :3, :, 3] = -(V / 4.0)[:, None, None, None] * dN[:, :, :, None]
-        Ke[:, :, 3, :, :3] = (V / 4.0)[:, None, None, None] * dN[:, None, :, :]
+        Ke[:, :, :3, :, 3] = -(w["gd"] * V / 4.0)[:, None, None, None] * dN[:, :, :, None]
+        Ke[:, :, 3, :, :3] = (w["gd"] * V / 4.0)[:, None, None, None] * dN[:, None, :, :]
         if prm.get("vms_dt_coupling", 0):
-            Ke[:, :, 3, :, :3] += (ct * rho * tauM * V / 4.0)[:, None, None, None] * dN[:, :, None, :]
+            Ke[:, :, 3, :, :3] += (w["dtc"] * rho * tauM * V / 4.0)[:, None, None, None] * dN[:, :, None, :]
     if conv:
         # grad p through v' in the momentum row: (ub . grad w) tau_M rho grad p
         Ke[:, :, :3, :, 3] += (tauM * rho * V)[:, None, None, None] * ua[:, :, None, None] * \
@@ -131,8 +161,8 @@ def element_matrices(X, solid, U, prm: dict) -> np.ndarray:
         # (grad q) . tau_M rho (ub . grad) v in the continuity row
         Ke[:, :, 3, :, :3] += (tauM * rho * V)[:, None, None, None] * dN[:, :, None, :] * ua[:, None, :, None]
     if terms & CPP:
-        Ke[:, :, 3, :, 3] = np.where(fluid[:, None, None], tauM[:, None, None] * Lab,
-                                     (ct / kappa) * Mab)
+        Ke[:, :, 3, :, 3] = np.where(fluid[:, None, None], w["cpp_f"] * tauM[:, None, None] * Lab,
+                                     w["cpp_s"] * Mab)
     return Ke
 
 
@@ -147,10 +177,12 @@ def _positions(rp, ci, rows, cols):
     return q
 
 
-def tangent(tv, tp, tsolid, xyz, rp, ci, mask, prm: dict, u=None, rows=None, chunk: int = 100_000):
+def tangent(tv, tp, tsolid, xyz, rp, ci, mask, prm: dict, u=None, rows=None, chunk: int = 100_000,
+            form: str = "tangent"):
     """Assembled tangent values (nnzb, 4, 4) on the pattern (rp, ci), Dirichlet dofs (mask, 4 per
     block row) eliminated.  u: (n_b, 3) advective velocity or None.  rows: optional block rows;
-    then only the elements touching them are assembled and only those rows are exact."""
+    then only the elements touching them are assembled and only those rows are exact.  form: one
+    of FORMS; the residual parts keep zero Dirichlet rows and columns."""
     tv = np.asarray(tv); tp = np.asarray(tp)
     solid = np.asarray(tsolid).astype(bool)
     nb = rp.size - 1
@@ -164,7 +196,7 @@ def tangent(tv, tp, tsolid, xyz, rp, ci, mask, prm: dict, u=None, rows=None, chu
         e = elems[s:s + chunk]
         X = xyz[tv[e]]
         U = None if u is None else u[tv[e]]
-        Ke = element_matrices(X, solid[e], U, prm)
+        Ke = element_matrices(X, solid[e], U, prm, form)
         for a in range(4):
             for b in range(4):
                 q = _positions(rp, ci, tv[e, a], tv[e, b])
@@ -180,6 +212,8 @@ def tangent(tv, tp, tsolid, xyz, rp, ci, mask, prm: dict, u=None, rows=None, chu
     rowof = np.repeat(np.arange(nb), np.diff(rp))
     kill = m[rowof][:, :, None] | m[ci][:, None, :]
     val[kill] = 0.0
+    if form != "tangent":
+        return val
     diag = np.nonzero(rowof == ci)[0]
     for i in range(4):
         d = diag[m[rowof[diag], i]]

@@ -27,6 +27,7 @@ SOURCES = {
     "scr.hip": [],
     "serve.hip": [],
     "assemble.hip": [],
+    "corrector.hip": [],
 }
 
 

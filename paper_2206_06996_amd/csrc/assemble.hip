@@ -30,22 +30,55 @@ struct scr_assembler {
 namespace scr {
 namespace {
 
-// constants of one assembly (Sec. 3.4: first-order generalized-alpha; Sec. 3.1: solid moduli)
+// constants of one assembly (Sec. 3.4: first-order generalized-alpha; Sec. 3.1: solid moduli) and
+// the coefficient of each term in the assembled form (FORM_TANGENT: the corrector tangent divided
+// by alpha_f gamma dt; the other forms are the parts of the linear(ised) semi-discrete residual that
+// act on the rates, on the state and on the solid displacement, see OperatorForm)
 struct TanPrm {
     double rho_f, mu_f, rho_s, ct, visc_s, kappa, dt;
     int terms, dtc;
+    double c_mass;          // times rho M (both media)
+    double c_visc_f;        // fluid viscous coefficient (mu_f or 0)
+    double c_visc_s;        // solid elastic coefficient
+    double c_gd;            // times tau_C grad-div (fluid)
+    double c_gdiv;          // G and D (1 or 0)
+    double c_dtc;           // the fine-scale rate term of D (fluid, with vms_dt_coupling)
+    double c_cf;            // times tau_M L (fluid pressure block)
+    double c_cs;            // times M (solid pressure block)
+    int conv;               // Oseen convection terms allowed
+    int unit_diag;          // Dirichlet dofs: unit diagonal (the tangent) or zero rows (residual parts)
 };
 
-TanPrm tan_prm(const scr_tangent_params& p) {
+TanPrm tan_prm(const scr_tangent_params& p, int form = FORM_TANGENT) {
     const double am = 0.5 * (3.0 - p.rho_inf) / (1.0 + p.rho_inf);
     const double af = 1.0 / (1.0 + p.rho_inf), g = 1.0 / (1.0 + p.rho_inf);
     TanPrm t;
     t.rho_f = p.rho_f; t.mu_f = p.mu_f; t.rho_s = p.rho_s; t.dt = p.dt;
     t.ct = am / (af * g * p.dt);
-    t.visc_s = (af * g * p.dt / am) * (p.E_s / (2.0 * (1.0 + p.nu_s)));
+    const double mu_s = p.E_s / (2.0 * (1.0 + p.nu_s));
+    t.visc_s = (af * g * p.dt / am) * mu_s;
     t.kappa = p.E_s / (3.0 * (1.0 - 2.0 * p.nu_s));
     t.terms = p.terms;
     t.dtc = p.vms_dt_coupling;
+    t.c_mass = t.c_visc_f = t.c_visc_s = t.c_gd = t.c_gdiv = t.c_dtc = t.c_cf = t.c_cs = 0.0;
+    t.conv = 0;
+    t.unit_diag = 0;
+    switch (form) {
+        case FORM_TANGENT:
+            t.c_mass = t.ct; t.c_visc_f = t.mu_f; t.c_visc_s = t.visc_s; t.c_gd = 1.0; t.c_gdiv = 1.0;
+            t.c_dtc = t.ct; t.c_cf = 1.0; t.c_cs = t.ct / t.kappa; t.conv = 1; t.unit_diag = 1;
+            break;
+        case FORM_RATE:       // acts on (v_dot, p_dot): rho M, the solid pressure mass M / kappa
+            t.c_mass = 1.0; t.c_dtc = 1.0; t.c_cs = 1.0 / t.kappa;
+            break;
+        case FORM_STATE:      // acts on (v, p): fluid viscous and grad-div, G and D, tau_M L
+            t.c_visc_f = t.mu_f; t.c_gd = 1.0; t.c_gdiv = 1.0; t.c_cf = 1.0;
+            break;
+        case FORM_DISP:       // acts on the solid displacement: the deviatoric elastic stiffness
+            t.c_visc_s = mu_s;
+            break;
+        default: throw Error(SCR_E_INVALID, "unknown operator form");
+    }
     return t;
 }
 
@@ -232,7 +265,7 @@ __global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int3
     double acc[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc[t] = 0.0;
-    const bool t_mass = P.terms & 1, t_visc = P.terms & 2, t_gd = P.terms & 4, t_gdiv = P.terms & 8,
+    const bool t_mass = P.terms & 1, t_visc = P.terms & 2, t_gd = P.terms & 4, t_gdiv = (P.terms & 8) && P.c_gdiv != 0.0,
                t_c = P.terms & 16;
     for (int32_t k = ioff[r]; k < ioff[r + 1]; ++k) {
         const int64_t key = inc[k];
@@ -258,7 +291,7 @@ __global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int3
         double dN[4][3];
         const double V = fabs(tet_shape(x, dN)) / 6.0;
         const bool sol = solid[e] != 0;
-        const bool conv = !sol && u != nullptr && (P.terms & 32);
+        const bool conv = !sol && u != nullptr && (P.terms & 32) && P.conv;
         double ub[3] = {0.0, 0.0, 0.0}, gu[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
         if (conv) {
 #pragma unroll
@@ -275,12 +308,12 @@ __global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int3
         if (!sol) {
             fluid_tau(dN, ub, P, tauM, tauC);
             rho = P.rho_f;
-            visc = P.mu_f;
+            visc = P.c_visc_f;
         } else {
             rho = P.rho_s;
-            visc = P.visc_s;
+            visc = P.c_visc_s;
         }
-        const double gd = sol ? 0.0 : tauC;
+        const double gd = sol ? 0.0 : P.c_gd * tauC;
         double dNa[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) dNa[i] = a == 0 ? dN[0][i] : a == 1 ? dN[1][i] : a == 2 ? dN[2][i] : dN[3][i];
@@ -298,7 +331,7 @@ __global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int3
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
                         double v = 0.0;
-                        if (t_mass && i == j) v += rho * P.ct * Mab;
+                        if (t_mass && i == j) v += rho * P.c_mass * Mab;
                         if (t_visc)
                             v += visc * ((i == j ? Lab : 0.0) + V * dNa[j] * dNb[i] - (2.0 / 3.0) * V * dNa[i] * dNb[j]);
                         if (t_gd) v += gd * V * dNa[i] * dNb[j];
@@ -313,9 +346,9 @@ __global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int3
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     double d = 0.0;
-                    if (t_gdiv) {
-                        d = (V / 4.0) * dNb[j];
-                        if (!sol && P.dtc) d += P.ct * rho * tauM * (V / 4.0) * dNa[j];
+                    if (P.terms & 8) {
+                        if (t_gdiv) d = (V / 4.0) * dNb[j];
+                        if (!sol && P.dtc) d += P.c_dtc * rho * tauM * (V / 4.0) * dNa[j];
                     }
                     if (conv) d += tauM * rho * V * dNa[j] * uB;
                     acc[12 + j] += d;
@@ -337,7 +370,7 @@ __global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int3
             if ((role & 2) && t_c) {
                 const double Mab = V * (a == bq ? 2.0 : 1.0) / 20.0;
                 const double Lab = V * (dNa[0] * dNb[0] + dNa[1] * dNb[1] + dNa[2] * dNb[2]);
-                acc[15] += sol ? (P.ct / P.kappa) * Mab : tauM * Lab;
+                acc[15] += sol ? P.c_cs * Mab : P.c_cf * tauM * Lab;
             }
         }
     }
@@ -351,7 +384,7 @@ __global__ void __launch_bounds__(256) tangent_blocks_k(int64_t nnzb, const int3
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint8_t mc = mask[4 * (int64_t)c + j];
-            w[j] = (mr || mc) ? ((c == r && i == j) ? 1.0 : 0.0) : acc[4 * i + j];
+            w[j] = (mr || mc) ? ((c == r && i == j && P.unit_diag) ? 1.0 : 0.0) : acc[4 * i + j];
         }
         out[2 * i] = D2{w[0], w[1]};
         out[2 * i + 1] = D2{w[2], w[3]};
@@ -460,6 +493,26 @@ scr_status scr_assembler_create(scr_ctx* ctx, int64_t n_tets, const int32_t* tv,
         return asm_fail(e);
     }
 }
+
+namespace scr {
+void assemble_form(scr_assembler* A, int form, double dt, const double* u, double* val, hipStream_t s) {
+    if (!A || !val) throw Error(SCR_E_INVALID, "NULL assembler or val");
+    if (!(dt > 0.0) || !std::isfinite(dt)) throw Error(SCR_E_INVALID, "dt must be positive");
+    if (reinterpret_cast<uintptr_t>(val) % 16 != 0) throw Error(SCR_E_INVALID, "val must be 16-byte aligned");
+    scr_tangent_params p = A->p;
+    p.dt = dt;
+    const TanPrm P = tan_prm(p, form);
+    tangent_blocks_k<<<cdiv(A->nnzb, 256), 256, 0, s>>>(A->nnzb, A->rowof, A->ci, A->inc_off, A->inc, A->tv, A->tp,
+                                                         A->solid, A->xyz, form == FORM_TANGENT ? u : nullptr,
+                                                         A->mask, P, val);
+    check_launch("tangent_blocks");
+}
+double asmb_rho_inf(const scr_assembler* A) { return A->p.rho_inf; }
+void asmb_pattern(const scr_assembler* A, int32_t* rp, int32_t* ci, hipStream_t s) {
+    copy_dev(rp, A->rp, (A->nb + 1) * sizeof(int32_t), s);
+    copy_dev(ci, A->ci, A->nnzb * sizeof(int32_t), s);
+}
+}  // namespace scr
 
 scr_status scr_assemble_tangent(scr_assembler* A, const double* u, double* val, void* stream) {
     hipStream_t s = (hipStream_t)stream;

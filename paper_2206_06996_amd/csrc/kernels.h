@@ -59,6 +59,21 @@ template <typename T> void dense_mv3(int64_t n, const double* M, const T* b, T* 
 int validate_bsr(int64_t nr, int bs, int64_t nnzb, const int32_t* rp, const int32_t* ci, const double* v,
                  Arena& ar, hipStream_t s);
 
+// ---------------------------------------------------------------- operator forms (assemble.hip)
+// The linear(ised) semi-discrete residual of the unified continuum (Sec. 3.1, 3.2 at rest, 3.5) is
+//   R = K_rate (v_dot, p_dot) + K_state (v, p) + K_disp (u_solid, 0) - rho M (f, 0),
+// evaluated at the generalized-alpha intermediate states, and the corrector tangent divided by
+// alpha_f gamma dt is c_t K_rate + K_state + K_disp / c_t (c_t = alpha_m / (alpha_f gamma dt)).
+// FORM_TANGENT assembles the latter (what scr_assemble_tangent gives); the three parts have the
+// rows and columns of Dirichlet dofs zeroed (zero diagonal).
+enum OperatorForm { FORM_TANGENT = 0, FORM_RATE = 1, FORM_STATE = 2, FORM_DISP = 3 };
+// values of one form on the assembler's pattern at time step dt (its other constants unchanged);
+// u: advective velocity (n_brows x 3) for FORM_TANGENT, or NULL
+void assemble_form(scr_assembler* a, int form, double dt, const double* u, double* val, hipStream_t s);
+// the assembler's generalized-alpha spectral radius, and a copy of its block pattern (device)
+double asmb_rho_inf(const scr_assembler* a);
+void asmb_pattern(const scr_assembler* a, int32_t* rp, int32_t* ci, hipStream_t s);
+
 // ---------------------------------------------------------------- vectors (krylov.hip)
 void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);   // y = a x + b y
 void copy_d(int64_t n, const double* x, double* y, hipStream_t s);

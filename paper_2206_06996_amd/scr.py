@@ -28,7 +28,8 @@ EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", 
             "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply", "scr_ctx_profile",
             "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_drain",
             "srv_destroy", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_nnzb",
-            "scr_assembler_nbrows", "scr_assembler_destroy"]
+            "scr_assembler_nbrows", "scr_assembler_destroy", "scr_default_corrector_opts", "scr_stepper_create",
+            "scr_stepper_state", "scr_step", "scr_stepper_destroy"]
 SCR_PROF_OFF, SCR_PROF_SMOOTH_A0 = 0, 1
 
 
@@ -96,6 +97,22 @@ class TangentParams(C.Structure):
                 ("vms_dt_coupling", C.c_int32)]
 
 
+class CorrectorOpts(C.Structure):
+    _fields_ = [("max_correctors", C.c_int32), ("tol_R", C.c_double), ("tol_A", C.c_double),
+                ("mesh_tol", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("correctors", C.c_int32), ("converged", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
+                ("linear_its", C.c_int64), ("mesh_its", C.c_int64), ("resetups", C.c_int32), ("t_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SCR_STATE = {"y": 0, "ydot": 1, "u_solid": 2, "udot_solid": 3, "u_mesh": 4, "v_mesh": 5}
+
+
 def lib():
     """Load libscr.so (built by paper_2206_06996_amd.build); raise if it is missing."""
     global _lib
@@ -147,11 +164,19 @@ def lib():
         L.scr_assembler_nbrows.argtypes = [P]
         L.scr_assembler_nbrows.restype = C.c_int64
         L.scr_assembler_destroy.argtypes = [P]
+        L.scr_default_corrector_opts.argtypes = [C.POINTER(CorrectorOpts)]
+        L.scr_default_corrector_opts.restype = None
+        L.scr_stepper_create.argtypes = [P, P, C.POINTER(ScrBsr), P, P, P, P, P, C.c_double, C.POINTER(AmgOpts),
+                                         C.POINTER(SolveOpts), C.POINTER(CorrectorOpts), P, C.POINTER(P)]
+        L.scr_stepper_state.argtypes = [P, C.c_int, P, C.c_int, P]
+        L.scr_step.argtypes = [P, C.c_double, P, P, C.POINTER(StepStats)]
+        L.scr_stepper_destroy.argtypes = [P]
         for f in ("amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve",
                   "mesh_motion_solve_noalloc", "scr_handle_destroy", "scr_ctx_create",
                   "scr_hier_levels", "scr_hier_level_info", "scr_hier_level_copy", "scr_matrix_copy", "scr_apply",
                   "scr_ctx_profile", "scr_ctx_profile_read", "srv_create", "srv_submit", "srv_poll", "srv_wait",
-                  "srv_drain", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_destroy"):
+                  "srv_drain", "scr_assembler_create", "scr_assemble_tangent", "scr_assembler_destroy",
+                  "scr_stepper_create", "scr_stepper_state", "scr_step", "scr_stepper_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -368,6 +393,81 @@ def scr_assemble_tangent(a: Assembler, u, val, stream=None):
         raise ValueError("u must hold 3 * n_brows values")
     _check(lib().scr_assemble_tangent(a.ptr, None if u is None else _dev(u, torch.float64, "u"),
                                       _dev(val, torch.float64, "val"), _stream(stream)))
+
+
+def corrector_opts(**kw) -> CorrectorOpts:
+    o = CorrectorOpts()
+    lib().scr_default_corrector_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Stepper:
+    """The predictor multi-corrector time stepper (scr_stepper_*)."""
+
+    def __init__(self, ptr, n_brows, n_mesh):
+        self.ptr, self.n_brows, self.n_mesh = ptr, n_brows, n_mesh
+
+    def _size(self, field):
+        return 4 * self.n_brows if field < 2 else 3 * self.n_brows if field < 4 else 3 * self.n_mesh
+
+    def state(self, field: str, out=None, stream=None):
+        """Copy a field of the state at t_n into out (a new FP64 device tensor if None)."""
+        import torch
+        f = SCR_STATE[field]
+        if out is None:
+            out = torch.empty(self._size(f), dtype=torch.float64, device="cuda")
+        if out.numel() != self._size(f):
+            raise ValueError(f"{field} holds {self._size(f)} values")
+        _check(lib().scr_stepper_state(self.ptr, f, _dev(out, torch.float64, field), 0, _stream(stream)))
+        return out
+
+    def set_state(self, field: str, src, stream=None):
+        import torch
+        f = SCR_STATE[field]
+        if src.numel() != self._size(f):
+            raise ValueError(f"{field} holds {self._size(f)} values")
+        _check(lib().scr_stepper_state(self.ptr, f, _dev(src, torch.float64, field), 1, _stream(stream)))
+
+    def step(self, dt: float, f=None, stream=None):
+        """One time step; returns (status, stats dict)."""
+        import torch
+        if f is not None and f.numel() != 3 * self.n_brows:
+            raise ValueError("f must hold 3 * n_brows values")
+        st = StepStats()
+        rc = _check(lib().scr_step(self.ptr, float(dt), None if f is None else _dev(f, torch.float64, "f"),
+                                   _stream(stream), C.byref(st)), allow=(SCR_OK, SCR_NOT_CONVERGED))
+        return rc, st.as_dict()
+
+    def destroy(self):
+        if self.ptr:
+            lib().scr_stepper_destroy(self.ptr)
+            self.ptr = P()
+
+
+def scr_stepper_create(ctx: Context, a: Assembler, L_row_ptr, L_col_idx, L_val, L_full, mesh_mask, blk_of_phys,
+                       solid_rows, coords, dt0: float, amg: AmgOpts | None = None, solve: SolveOpts | None = None,
+                       copts: CorrectorOpts | None = None, stream=None) -> Stepper:
+    """L_*: the eliminated mesh Laplacian (CSR, device); L_full: its values before the elimination;
+    mesh_mask: n_L uint8; blk_of_phys: n_L int32; solid_rows: n_brows uint8; coords: n_brows x 3."""
+    import torch
+    nL = L_row_ptr.numel() - 1
+    if L_val.numel() != L_col_idx.numel() or L_full.numel() != L_col_idx.numel():
+        raise ValueError("L_val and L_full must hold nnz(L) values")
+    if mesh_mask.numel() != nL or blk_of_phys.numel() != nL:
+        raise ValueError("mesh_mask and blk_of_phys must hold n_L entries")
+    if solid_rows.numel() != a.n_brows or coords.numel() != 3 * a.n_brows:
+        raise ValueError("solid_rows must hold n_brows and coords 3 n_brows entries")
+    Lb = _bsr(L_row_ptr, L_col_idx, L_val, 1)
+    s = P()
+    _check(lib().scr_stepper_create(ctx.ptr, a.ptr, C.byref(Lb), _dev(L_full, torch.float64, "L_full"),
+                                    _dev(mesh_mask, torch.uint8, "mesh_mask"),
+                                    _dev(blk_of_phys, torch.int32, "blk_of_phys"),
+                                    _dev(solid_rows, torch.uint8, "solid_rows"), _dev(coords, torch.float64, "coords"),
+                                    float(dt0), C.byref(amg) if amg else None, C.byref(solve) if solve else None,
+                                    C.byref(copts) if copts else None, _stream(stream), C.byref(s)))
+    return Stepper(s, a.n_brows, nL)
 
 
 def scr_solve(h: Handle, b, x, opts: SolveOpts | None = None, stream=None):
