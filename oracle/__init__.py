@@ -35,7 +35,9 @@ class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("smoother", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("jacobi_sweeps", C.c_int), ("coarse_max", C.c_int),
                 ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
-                ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double)]
+                ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double),
+                ("amg_type", C.c_int), ("cl_theta", C.c_double), ("trunc", C.c_double), ("pmax", C.c_int),
+                ("hmis_domain", C.c_int), ("gs_domain", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -56,11 +58,15 @@ class ScrStats(C.Structure):
 
 
 def amg_opts(**kw) -> AmgOpts:
-    """Defaults: theta=0.08 (halved per level), Chebyshev degree 2 on [lam/30, lam], coarse
-    solve below 1024 unknowns, at most 10 levels, stop if coarsening is slower than 0.8."""
+    """Defaults: smoothed aggregation with theta=0.08 (halved per level), Chebyshev degree 4 on
+    [lam/30, lam], coarse solve below 1024 unknowns, at most 10 levels, stop if coarsening is
+    slower than 0.8.  amg_type=1: classical AMG with the paper's settings (strength 0.5, HMIS on
+    domains of 256 rows, extended+i truncated at 0.3 with at most 5 entries, hybrid Gauss-Seidel on
+    domains of 64 rows)."""
     o = AmgOpts(theta=0.08, smoother=1, cheb_degree=4, cheb_ratio=30.0, jacobi_sweeps=2,
                 coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0,
-                schur_cheb_degree=8, schur_cheb_ratio=100.0)
+                schur_cheb_degree=8, schur_cheb_ratio=100.0, amg_type=0, cl_theta=0.5, trunc=0.3, pmax=5,
+                hmis_domain=256, gs_domain=64)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -132,6 +138,14 @@ def lib():
         L.orc_gmres.restype = C.c_int
         L.orc_cg.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_double, C.c_int, C.c_int, P, P]
         L.orc_cg.restype = C.c_int
+        L.orc_cl_strength.argtypes = [C.c_int64, P, P, P, P, C.c_double, P]
+        L.orc_cl_hmis.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_uint64, C.c_int, P, P]
+        L.orc_cl_hmis.restype = C.c_int
+        L.orc_cl_extpi.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_double, C.c_int, P, P, P]
+        L.orc_cl_extpi.restype = C.c_int64
+        L.orc_cl_gs.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int, P, P, P]
+        L.orc_cl_uniform.argtypes = [C.c_uint64, C.c_int, C.c_int64]
+        L.orc_cl_uniform.restype = C.c_double
         _lib = L
     return _lib
 
@@ -196,11 +210,56 @@ def aggregate(rp, ci, flags, iso, root, seed, level):
     return int(na), agg
 
 
+def cl_strength(rp, ci, val, func, theta=0.5):
+    """Classical strength flags (one per stored entry) of a scalar CSR matrix."""
+    rp = _c(rp, np.int32); ci = _c(ci, np.int32); val = _c(val, np.float64); func = _c(func, np.uint8)
+    S = np.empty(ci.size, np.uint8)
+    lib().orc_cl_strength(rp.size - 1, _p(rp), _p(ci), _p(val), _p(func), theta, _p(S))
+    return S
+
+
+def cl_hmis(rp, ci, S, domain=256, seed=0, level=0):
+    """HMIS C/F split: (cf, first) with 1 = C, -1 = F (first: the domain-wise first pass)."""
+    rp = _c(rp, np.int32); ci = _c(ci, np.int32); S = _c(S, np.uint8)
+    nr = rp.size - 1
+    cf = np.empty(nr, np.int8); first = np.empty(nr, np.int8)
+    if lib().orc_cl_hmis(nr, _p(rp), _p(ci), _p(S), domain, seed, level, _p(cf), _p(first)):
+        raise ValueError("pattern is not structurally symmetric")
+    return cf, first
+
+
+def cl_uniform(seed, level, i):
+    return float(lib().orc_cl_uniform(seed, level, i))
+
+
+def cl_extpi(rp, ci, val, func, S, cf, trunc=0.3, pmax=5):
+    """Extended+i interpolation of a C/F split: (P.rp, P.ci, P.v), columns = coarse indices."""
+    rp = _c(rp, np.int32); ci = _c(ci, np.int32); val = _c(val, np.float64); func = _c(func, np.uint8)
+    S = _c(S, np.uint8); cf = _c(cf, np.int8)
+    nr = rp.size - 1
+    prp = np.empty(nr + 1, np.int32)
+    nnz = lib().orc_cl_extpi(nr, _p(rp), _p(ci), _p(val), _p(func), _p(S), _p(cf), trunc, pmax, _p(prp), None, None)
+    pci = np.empty(nnz, np.int32); pv = np.empty(nnz)
+    lib().orc_cl_extpi(nr, _p(rp), _p(ci), _p(val), _p(func), _p(S), _p(cf), trunc, pmax, _p(prp), _p(pci), _p(pv))
+    return prp, pci, pv
+
+
+def cl_gs(rp, ci, val, b, x_old=None, domain=64, backward=False):
+    """One hybrid Gauss-Seidel sweep from x_old (None = zero)."""
+    rp = _c(rp, np.int32); ci = _c(ci, np.int32); val = _c(val, np.float64); b = _c(b, np.float64)
+    x = np.zeros_like(b)
+    xo = None if x_old is None else _c(x_old, np.float64)
+    lib().orc_cl_gs(rp.size - 1, _p(rp), _p(ci), _p(val), domain, int(backward), _p(b),
+                    None if xo is None else _p(xo), _p(x))
+    return x
+
+
 class Hierarchy:
     """Read access to one AMG hierarchy (owned by an Amg, Scr or Mesh object)."""
 
     FIELDS = {"A.rp": 0, "A.ci": 1, "A.v": 2, "agg": 3, "P.rp": 4, "P.ci": 5, "P.v": 6,
-              "R.rp": 7, "R.ci": 8, "R.v": 9, "strong": 10, "dead": 11, "Dinv": 12, "B": 13, "Q": 14}
+              "R.rp": 7, "R.ci": 8, "R.v": 9, "strong": 10, "dead": 11, "Dinv": 12, "B": 13, "Q": 14,
+              "func": 15}
 
     def __init__(self, h, owner):
         self.h = h
@@ -227,7 +286,7 @@ class Hierarchy:
                   8: ((i["nnzR"],), np.int32), 9: ((i["nnzR"], i["k"], i["b"]), np.float64),
                   10: ((i["nnzA"],), np.uint8), 11: ((i["nagg"] * i["k"],), np.uint8),
                   12: ((i["nr"], i["b"], i["b"]), np.float64), 13: ((i["nr"] * i["b"], i["k"]), np.float64),
-                  14: ((i["nr"] * i["b"], i["k"]), np.float64)}
+                  14: ((i["nr"] * i["b"], i["k"]), np.float64), 15: ((i["nr"],), np.uint8)}
         shape, dt = shapes[f]
         out = np.empty(shape, dt)
         if lib().orc_amg_level_get(self.h, l, f, _p(out)) != 0:

@@ -257,6 +257,12 @@ typedef struct {
                             0 the diagonal of A (SCR, SIMPLE), 1 absolute row sums of A (SIMPLEC) */
     int schur_cheb_degree;     /* SCR system: Chebyshev degree of AMG(S^) (0 = cheb_degree) */
     double schur_cheb_ratio;   /* SCR system: Chebyshev interval ratio of AMG(S^) (0 = cheb_ratio) */
+    int amg_type;        /* 0 smoothed aggregation, 1 classical (the paper's settings) */
+    double cl_theta;     /* classical strength threshold, 0.5 */
+    double trunc;        /* interpolation truncation factor, 0.3 */
+    int pmax;            /* interpolation entries per row, 5 */
+    int hmis_domain;     /* rows per HMIS domain */
+    int gs_domain;       /* rows per hybrid Gauss-Seidel domain */
 } amg_opts;
 
 #define MAXLEV 16
@@ -271,6 +277,7 @@ typedef struct {
     double* B;           /* near-null space: (nr*b) x k row-major */
     uint8_t* dead;       /* per coarse dof (n_agg*k) */
     double* Q;           /* tentative prolongator (nr*b) x k row-major */
+    uint8_t* func;       /* classical: function (unknown) of each scalar row */
 } level;
 
 typedef struct {
@@ -458,7 +465,7 @@ static void tentative(int64_t nr, int b, int k, const int32_t* agg, int64_t na, 
 
 static void level_free(level* L) {
     bsr_free(L->A); bsr_free(L->P); bsr_free(L->R);
-    free(L->agg); free(L->strong); free(L->Dinv); free(L->B); free(L->dead); free(L->Q);
+    free(L->agg); free(L->strong); free(L->Dinv); free(L->B); free(L->dead); free(L->Q); free(L->func);
 }
 
 /* D^-1 (block diagonal inverse) and lambda_hat = max abs row sum of D^-1 A */
@@ -607,12 +614,480 @@ static int coarse_factor(amg* h) {
     return lu_factor(nc, h->LU, h->piv);
 }
 
+/* ------------------------------------------------------------------ classical AMG
+ * The paper's preconditioner settings (Sec. 5.2, table of AMG settings): classical strength with
+ * threshold 0.5, HMIS coarsening, extended+i interpolation truncated at 0.3 with at most 5
+ * entries per row, hybrid Gauss-Seidel smoothing, V-cycle.  Restated here:
+ *
+ * Strength (scalar rows; "functions" f(i) give the unknown approach for systems: only couplings
+ * between unknowns of the same function count).  With s = sign(a_ii) (+1 for a_ii = 0) and
+ * m_i = max over j != i, f(j) = f(i) of -s a_ij, row i depends strongly on j iff m_i > 0 and
+ * -s a_ij >= theta m_i.  S_i: the points i depends on; S^T_i: the points that depend on i.
+ *
+ * HMIS (De Sterck, Yang and Heys): rows are cut into domains of `dom` consecutive rows (the
+ * processor domains of a distributed run).  In each domain, the first pass of Ruge-Stueben
+ * coarsening on the strength graph restricted to the domain: measure lambda_i = number of domain
+ * points depending on i; points with no dependency either way inside the domain are F; then
+ * repeatedly the undecided point of largest measure (lowest index on ties) becomes C, the
+ * undecided domain points depending on it become F, the undecided domain points it depends on
+ * lose one unit of measure, and for each new F point the undecided domain points it depends on
+ * gain one.  The C points of this pass whose strong connections (both directions) all stay in
+ * their domain start PMIS over the whole graph: measure w_i = |S^T_i| + u_i with u_i uniform in
+ * [0, 1) from splitmix64 of (seed, level, i); every other point with |S^T_i| = 0 is F and the
+ * rest undecided; then repeatedly every undecided point depending on a C point of the previous
+ * round becomes F, and every undecided point whose w beats that of every undecided strong
+ * neighbour (either direction; ties to the lower index) becomes C.
+ *
+ * Extended+i interpolation (De Sterck, Falgout, Nolting and Yang).  For an F point i: C^_i = the
+ * C points of S_i and the C points of S_k for every F point k of S_i.  For such a k, with
+ * a'_kl = a_kl where a_kl and a_kk have opposite signs (else 0), den_k = sum of a'_kl over
+ * l in C^_i and l = i.  Then, running over row i (same function, j != i, ascending columns):
+ * a_ij for j in C^_i goes to num_j; for a strong F neighbour k with den_k != 0 the terms
+ * a_ik a'_kl / den_k (row k ascending, l in C^_i or l = i) go to num_l, or to the diagonal when
+ * l = i; every other coupling (weak, or den_k = 0) is added to the diagonal a~_ii, which starts at
+ * a_ii.  w_ij = -num_j / a~_ii.  Truncation: entries below trunc * max |w| are dropped, then all
+ * but the pmax largest in magnitude (ties to the lower column), and the kept entries are scaled
+ * so that the row keeps its sum.  C points interpolate themselves with weight 1.
+ *
+ * Hybrid Gauss-Seidel (Baker, Falgout, Kolev and Yang): Gauss-Seidel inside domains of `gs_dom`
+ * consecutive rows, Jacobi between them: x_i = (b_i - sum_{j != i} a_ij x~_j) / a_ii with x~_j
+ * the new value for j earlier in the same domain (forward sweep: j < i; backward: j > i) and the
+ * previous iterate otherwise.  V-cycle: one forward sweep from zero, coarse-grid correction, one
+ * backward sweep (a symmetric cycle for symmetric A).
+ */
+static int opposite(double a, double d) { return (a > 0.0 && d < 0.0) || (a < 0.0 && d > 0.0); }
+
+void orc_cl_strength(int64_t nr, const int32_t* rp, const int32_t* ci, const double* val, const uint8_t* func,
+                     double theta, uint8_t* S) {
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN)
+    for (int64_t i = 0; i < nr; ++i) {
+        double aii = 0.0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (ci[q] == i) aii = val[q];
+        double sg = aii < 0.0 ? -1.0 : 1.0;
+        int have = 0;
+        double m = 0.0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            int32_t j = ci[q];
+            if (j == i || func[j] != func[i]) continue;
+            double v = -sg * val[q];
+            if (!have || v > m) { m = v; have = 1; }
+        }
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            int32_t j = ci[q];
+            S[q] = 0;
+            if (j == i || func[j] != func[i] || !have || !(m > 0.0)) continue;
+            S[q] = (uint8_t)(-sg * val[q] >= theta * m);
+        }
+    }
+}
+
+/* position of (j, i) for every stored (i, j); -1 if the pattern lacks it */
+static int32_t* transpose_map(int64_t nr, const int32_t* rp, const int32_t* ci) {
+    int32_t* t = (int32_t*)malloc(sizeof(int32_t) * (rp[nr] > 0 ? rp[nr] : 1));
+    bsr M = {nr, nr, 1, 1, rp[nr], (int32_t*)rp, (int32_t*)ci, NULL};
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN)
+    for (int64_t i = 0; i < nr; ++i)
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) t[q] = find_in_row(&M, ci[q], (int32_t)i);
+    return t;
+}
+
+double orc_cl_uniform(uint64_t seed, int level, int64_t i) {
+    uint64_t h = sm64(seed ^ ((uint64_t)level << 56) ^ ((uint64_t)i * 0x9E6C63D0676A9A99ULL));
+    return (double)(h >> 11) * 0x1.0p-53;
+}
+
+/* cf[i] = 1 (C) or -1 (F); first[i] = the first pass's decision (1 C, -1 F).  Returns 0, or -1
+ * if the pattern is not structurally symmetric. */
+int orc_cl_hmis(int64_t nr, const int32_t* rp, const int32_t* ci, const uint8_t* S, int dom, uint64_t seed,
+                int level, int8_t* cf, int8_t* first) {
+    int32_t* tm = transpose_map(nr, rp, ci);
+    for (int64_t q = 0; q < rp[nr]; ++q)
+        if (tm[q] < 0) { free(tm); return -1; }
+    /* ST[q] for q = (i, j): j depends on i */
+    uint8_t* ST = (uint8_t*)malloc(rp[nr] > 0 ? rp[nr] : 1);
+    for (int64_t q = 0; q < rp[nr]; ++q) ST[q] = S[tm[q]];
+    free(tm);
+    int32_t* lam = (int32_t*)malloc(sizeof(int32_t) * (nr > 0 ? nr : 1));
+    int8_t* st = (int8_t*)malloc(nr > 0 ? nr : 1);              /* 0 undecided, 1 C, 2 F */
+    int32_t* newf = (int32_t*)malloc(sizeof(int32_t) * (nr > 0 ? nr : 1));
+    for (int64_t d0 = 0; d0 < nr; d0 += dom) {
+        int64_t d1 = d0 + dom < nr ? d0 + dom : nr;
+        for (int64_t i = d0; i < d1; ++i) {
+            int32_t l = 0, dep = 0;
+            for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+                int32_t j = ci[q];
+                if (j < d0 || j >= d1) continue;
+                l += ST[q];
+                dep += S[q];
+            }
+            lam[i] = l;
+            st[i] = (l == 0 && dep == 0) ? 2 : 0;
+        }
+        for (;;) {
+            int64_t c = -1;
+            for (int64_t i = d0; i < d1; ++i)
+                if (st[i] == 0 && (c < 0 || lam[i] > lam[c])) c = i;
+            if (c < 0) break;
+            st[c] = 1;
+            int64_t nf = 0;
+            for (int32_t q = rp[c]; q < rp[c + 1]; ++q) {
+                int32_t j = ci[q];
+                if (j >= d0 && j < d1 && st[j] == 0 && ST[q]) { st[j] = 2; newf[nf++] = j; }
+            }
+            for (int32_t q = rp[c]; q < rp[c + 1]; ++q) {
+                int32_t j = ci[q];
+                if (j >= d0 && j < d1 && st[j] == 0 && S[q]) lam[j] -= 1;
+            }
+            for (int64_t t = 0; t < nf; ++t) {
+                int32_t j = newf[t];
+                for (int32_t q = rp[j]; q < rp[j + 1]; ++q) {
+                    int32_t k = ci[q];
+                    if (k >= d0 && k < d1 && st[k] == 0 && S[q]) lam[k] += 1;
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < nr; ++i) first[i] = st[i] == 1 ? 1 : -1;
+    /* PMIS, started from the interior C points of the first pass */
+    double* w = (double*)malloc(sizeof(double) * (nr > 0 ? nr : 1));
+    uint8_t* isnew = (uint8_t*)malloc(nr > 0 ? nr : 1);
+    int8_t* nx = (int8_t*)malloc(nr > 0 ? nr : 1);
+    for (int64_t i = 0; i < nr; ++i) {
+        int64_t dm = i / dom;
+        int interior = 1;
+        int32_t nst = 0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            nst += ST[q];
+            if ((S[q] || ST[q]) && ci[q] / dom != dm) interior = 0;
+        }
+        w[i] = (double)nst + orc_cl_uniform(seed, level, i);
+        if (first[i] == 1 && interior) st[i] = 1;
+        else st[i] = nst == 0 ? 2 : 0;
+        isnew[i] = st[i] == 1;
+    }
+    for (;;) {
+        for (int64_t i = 0; i < nr; ++i) {
+            nx[i] = st[i];
+            if (st[i] != 0) continue;
+            for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+                if (S[q] && isnew[ci[q]]) { nx[i] = 2; break; }
+        }
+        int64_t und = 0;
+        for (int64_t i = 0; i < nr; ++i) { st[i] = nx[i]; und += st[i] == 0; isnew[i] = 0; }
+        if (und == 0) break;
+        for (int64_t i = 0; i < nr; ++i) {
+            if (st[i] != 0) continue;
+            int best = 1;
+            for (int32_t q = rp[i]; q < rp[i + 1] && best; ++q) {
+                int32_t j = ci[q];
+                if (j == i || st[j] != 0 || !(S[q] || ST[q])) continue;
+                if (!(w[i] > w[j] || (w[i] == w[j] && i < j))) best = 0;
+            }
+            if (best) isnew[i] = 1;
+        }
+        for (int64_t i = 0; i < nr; ++i)
+            if (isnew[i]) st[i] = 1;
+    }
+    for (int64_t i = 0; i < nr; ++i) cf[i] = st[i] == 1 ? 1 : -1;
+    free(ST); free(lam); free(st); free(newf); free(w); free(isnew); free(nx);
+    return 0;
+}
+
+static int cmp_i32_asc(const void* a, const void* b) {
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+static int64_t find_sorted(const int32_t* v, int64_t n, int32_t key) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (v[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && v[lo] == key) ? lo : -1;
+}
+
+/* One row of extended+i interpolation (F point i).  hat: sorted C^_i (fine indices), m entries;
+ * w: m weights out.  Returns 0, or 1 if the modified diagonal is zero (empty row). */
+static int extpi_row(const int32_t* rp, const int32_t* ci, const double* val, const uint8_t* func, const uint8_t* S,
+                     const int32_t* cidx, int64_t i, const int32_t* hat, int64_t m, double* w) {
+    double diag = 0.0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+        if (ci[q] == i) diag = val[q];
+    for (int64_t t = 0; t < m; ++t) w[t] = 0.0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        int32_t n = ci[q];
+        if (n == i || func[n] != func[i]) continue;
+        int64_t p = find_sorted(hat, m, n);
+        if (p >= 0) { w[p] = w[p] + val[q]; continue; }
+        if (S[q] && cidx[n] < 0) {
+            double ann = 0.0, den = 0.0;
+            for (int32_t r = rp[n]; r < rp[n + 1]; ++r)
+                if (ci[r] == n) ann = val[r];
+            for (int32_t r = rp[n]; r < rp[n + 1]; ++r) {
+                int32_t l = ci[r];
+                if ((l == i || find_sorted(hat, m, l) >= 0) && opposite(val[r], ann)) den = den + val[r];
+            }
+            if (den == 0.0) { diag = diag + val[q]; continue; }
+            for (int32_t r = rp[n]; r < rp[n + 1]; ++r) {
+                int32_t l = ci[r];
+                if (!opposite(val[r], ann)) continue;
+                double t = (val[q] * val[r]) / den;
+                if (l == i) diag = diag + t;
+                else {
+                    int64_t pl = find_sorted(hat, m, l);
+                    if (pl >= 0) w[pl] = w[pl] + t;
+                }
+            }
+            continue;
+        }
+        diag = diag + val[q];
+    }
+    if (diag == 0.0) return 1;
+    for (int64_t t = 0; t < m; ++t) w[t] = -w[t] / diag;
+    return 0;
+}
+
+typedef struct { double a; int32_t c; } wcol;
+static int cmp_wcol(const void* x, const void* y) {
+    const wcol* p = (const wcol*)x;
+    const wcol* q = (const wcol*)y;
+    if (p->a != q->a) return p->a > q->a ? -1 : 1;
+    return (p->c > q->c) - (p->c < q->c);
+}
+
+/* Truncation of one row (columns ascending): keep |w| >= trunc * max |w| (and w != 0), then the
+ * pmax largest, then scale the kept entries to the row's original sum.  Compacts in place and
+ * returns the kept count. */
+static int64_t truncate_row(int32_t* col, double* w, int64_t m, double trunc, int pmax) {
+    double mx = 0.0, all = 0.0;
+    for (int64_t t = 0; t < m; ++t) {
+        all = all + w[t];
+        if (fabs(w[t]) > mx) mx = fabs(w[t]);
+    }
+    int64_t k = 0;
+    for (int64_t t = 0; t < m; ++t)
+        if (w[t] != 0.0 && fabs(w[t]) >= trunc * mx) { col[k] = col[t]; w[k] = w[t]; ++k; }
+    if (pmax > 0 && k > pmax) {
+        wcol* tmp = (wcol*)malloc(sizeof(wcol) * k);
+        for (int64_t t = 0; t < k; ++t) { tmp[t].a = fabs(w[t]); tmp[t].c = col[t]; }
+        qsort(tmp, k, sizeof(wcol), cmp_wcol);
+        /* keep the first pmax of the magnitude order, in ascending columns */
+        int32_t* keep = (int32_t*)malloc(sizeof(int32_t) * pmax);
+        for (int t = 0; t < pmax; ++t) keep[t] = tmp[t].c;
+        qsort(keep, pmax, sizeof(int32_t), cmp_i32_asc);
+        int64_t k2 = 0;
+        for (int64_t t = 0; t < k; ++t)
+            if (find_sorted(keep, pmax, col[t]) >= 0) { col[k2] = col[t]; w[k2] = w[t]; ++k2; }
+        k = k2;
+        free(tmp); free(keep);
+    }
+    double kept = 0.0;
+    for (int64_t t = 0; t < k; ++t) kept = kept + w[t];
+    if (kept != 0.0) {
+        double sc = all / kept;
+        for (int64_t t = 0; t < k; ++t) w[t] = w[t] * sc;
+    }
+    return k;
+}
+
+/* Extended+i interpolation P (nr x nc, 1x1 blocks) from the C/F split (cidx: coarse index or -1). */
+static bsr* extpi(int64_t nr, int64_t nc, const int32_t* rp, const int32_t* ci, const double* val, const uint8_t* func,
+                  const uint8_t* S, const int32_t* cidx, double trunc, int pmax) {
+    int32_t** rc = (int32_t**)calloc(nr > 0 ? nr : 1, sizeof(int32_t*));
+    double** rw = (double**)calloc(nr > 0 ? nr : 1, sizeof(double*));
+    int64_t* rn = (int64_t*)calloc(nr > 0 ? nr : 1, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 256) if (nr > PAR_MIN)
+    for (int64_t i = 0; i < nr; ++i) {
+        if (cidx[i] >= 0) {
+            rc[i] = (int32_t*)malloc(sizeof(int32_t)); rw[i] = (double*)malloc(sizeof(double));
+            rc[i][0] = cidx[i]; rw[i][0] = 1.0; rn[i] = 1;
+            continue;
+        }
+        int64_t cap = 0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            if (!S[q]) continue;
+            int32_t j = ci[q];
+            if (cidx[j] >= 0) ++cap;
+            else cap += rp[j + 1] - rp[j];
+        }
+        int32_t* hat = (int32_t*)malloc(sizeof(int32_t) * (cap > 0 ? cap : 1));
+        int64_t m = 0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            if (!S[q]) continue;
+            int32_t j = ci[q];
+            if (cidx[j] >= 0) { hat[m++] = j; continue; }
+            for (int32_t r = rp[j]; r < rp[j + 1]; ++r)
+                if (S[r] && cidx[ci[r]] >= 0) hat[m++] = ci[r];
+        }
+        qsort(hat, m, sizeof(int32_t), cmp_i32_asc);
+        int64_t u = 0;
+        for (int64_t t = 0; t < m; ++t)
+            if (u == 0 || hat[t] != hat[u - 1]) hat[u++] = hat[t];
+        m = u;
+        double* w = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
+        if (m == 0 || extpi_row(rp, ci, val, func, S, cidx, i, hat, m, w)) m = 0;
+        for (int64_t t = 0; t < m; ++t) hat[t] = cidx[hat[t]];
+        rn[i] = truncate_row(hat, w, m, trunc, pmax);
+        rc[i] = hat; rw[i] = w;
+    }
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < nr; ++i) nnz += rn[i];
+    bsr* P = bsr_new(nr, nc, 1, 1, nnz);
+    for (int64_t i = 0; i < nr; ++i) {
+        P->rp[i + 1] = P->rp[i] + (int32_t)rn[i];
+        memcpy(P->ci + P->rp[i], rc[i], sizeof(int32_t) * rn[i]);
+        memcpy(P->v + P->rp[i], rw[i], sizeof(double) * rn[i]);
+        free(rc[i]); free(rw[i]);
+    }
+    free(rc); free(rw); free(rn);
+    return P;
+}
+
+/* test entry: P of a given split; prp (nr + 1) always, pci/pv (nnz) when not NULL; returns nnz */
+int64_t orc_cl_extpi(int64_t nr, const int32_t* rp, const int32_t* ci, const double* val, const uint8_t* func,
+                     const uint8_t* S, const int8_t* cf, double trunc, int pmax, int32_t* prp, int32_t* pci,
+                     double* pv) {
+    int32_t* cidx = (int32_t*)malloc(sizeof(int32_t) * (nr > 0 ? nr : 1));
+    int64_t nc = 0;
+    for (int64_t i = 0; i < nr; ++i) cidx[i] = cf[i] == 1 ? (int32_t)nc++ : -1;
+    bsr* P = extpi(nr, nc, rp, ci, val, func, S, cidx, trunc, pmax);
+    memcpy(prp, P->rp, sizeof(int32_t) * (nr + 1));
+    if (pci) memcpy(pci, P->ci, sizeof(int32_t) * P->nnzb);
+    if (pv) memcpy(pv, P->v, sizeof(double) * P->nnzb);
+    int64_t nnz = P->nnzb;
+    bsr_free(P); free(cidx);
+    return nnz;
+}
+
+/* One hybrid Gauss-Seidel sweep (x out; xold the previous iterate, NULL = zero). */
+static void hybrid_gs(const bsr* A, const double* Dinv, int dom, int backward, const double* b, const double* xold,
+                      double* x) {
+    int64_t nr = A->nr;
+    int64_t nd = (nr + dom - 1) / dom;
+#pragma omp parallel for schedule(static) if (nr > PAR_MIN)
+    for (int64_t d = 0; d < nd; ++d) {
+        int64_t lo = d * dom, hi = lo + dom < nr ? lo + dom : nr;
+        for (int64_t t = 0; t < hi - lo; ++t) {
+            int64_t i = backward ? hi - 1 - t : lo + t;
+            double s = 0.0;
+            for (int32_t q = A->rp[i]; q < A->rp[i + 1]; ++q) {
+                int64_t j = A->ci[q];
+                if (j == i) continue;
+                int fresh = j >= lo && j < hi && (backward ? j > i : j < i);
+                double xj = fresh ? x[j] : (xold ? xold[j] : 0.0);
+                s = s + A->v[q] * xj;
+            }
+            x[i] = (b[i] - s) * Dinv[i];
+        }
+    }
+}
+
+void orc_cl_gs(int64_t nr, const int32_t* rp, const int32_t* ci, const double* val, int dom, int backward,
+               const double* b, const double* xold, double* x) {
+    bsr A = {nr, nr, 1, 1, rp[nr], (int32_t*)rp, (int32_t*)ci, (double*)val};
+    double* Dinv = (double*)malloc(sizeof(double) * (nr > 0 ? nr : 1));
+    for (int64_t i = 0; i < nr; ++i) {
+        Dinv[i] = 0.0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (ci[q] == i) Dinv[i] = 1.0 / val[q];
+    }
+    hybrid_gs(&A, Dinv, dom, backward, b, xold, x);
+    free(Dinv);
+}
+
+/* the scalar matrix of a b x b BSR matrix (row b*i + r, columns in order) and the function of
+ * each scalar row (r) */
+static bsr* to_scalar(const bsr* A, uint8_t** func) {
+    int b = A->br;
+    bsr* S = bsr_new(A->nr * b, A->nc * b, 1, 1, A->nnzb * b * b);
+    *func = (uint8_t*)malloc(A->nr * b > 0 ? A->nr * b : 1);
+    int64_t p = 0;
+    for (int64_t i = 0; i < A->nr; ++i)
+        for (int r = 0; r < b; ++r) {
+            int64_t row = i * b + r;
+            (*func)[row] = (uint8_t)r;
+            for (int32_t q = A->rp[i]; q < A->rp[i + 1]; ++q)
+                for (int c = 0; c < b; ++c) {
+                    S->ci[p] = A->ci[q] * b + c;
+                    S->v[p] = A->v[(int64_t)q * b * b + r * b + c];
+                    ++p;
+                }
+            S->rp[row + 1] = (int32_t)p;
+        }
+    return S;
+}
+
+static amg* amg_build_classical(const bsr* A0, const amg_opts* o) {
+    amg* h = (amg*)calloc(1, sizeof(amg));
+    h->o = *o;
+    level* L = &h->L[0];
+    L->A = to_scalar(A0, &L->func);
+    L->b = 1; L->k = 1;
+    int l = 0;
+    int64_t maxn = 0;
+    for (;;) {
+        L = &h->L[l];
+        int64_t n = L->A->nr;
+        if (n > maxn) maxn = n;
+        if (n <= o->coarse_max || l + 1 >= o->max_levels || l + 1 >= MAXLEV) break;
+        L->strong = (uint8_t*)malloc(L->A->nnzb > 0 ? L->A->nnzb : 1);
+        orc_cl_strength(n, L->A->rp, L->A->ci, L->A->v, L->func, o->cl_theta, L->strong);
+        int8_t* cf = (int8_t*)malloc(n > 0 ? n : 1);
+        int8_t* first = (int8_t*)malloc(n > 0 ? n : 1);
+        if (orc_cl_hmis(n, L->A->rp, L->A->ci, L->strong, o->hmis_domain, o->seed, l, cf, first)) {
+            free(cf); free(first); orc_amg_free(h); return NULL;
+        }
+        free(first);
+        L->agg = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+        int64_t nc = 0;
+        for (int64_t i = 0; i < n; ++i) L->agg[i] = cf[i] == 1 ? (int32_t)nc++ : -1;
+        free(cf);
+        if (nc <= 0 || (double)nc > o->max_coarse_ratio * (double)n) {
+            free(L->agg); L->agg = NULL; free(L->strong); L->strong = NULL;
+            break;
+        }
+        L->n_agg = nc;
+        L->P = extpi(n, nc, L->A->rp, L->A->ci, L->A->v, L->func, L->strong, L->agg, o->trunc, o->pmax);
+        L->R = transpose(L->P);
+        bsr* AP = spgemm(L->A, L->P);
+        level* N = &h->L[l + 1];
+        N->A = spgemm(L->R, AP);
+        bsr_free(AP);
+        N->b = 1; N->k = 1;
+        N->func = (uint8_t*)malloc(nc > 0 ? nc : 1);
+        for (int64_t i = 0; i < n; ++i)
+            if (L->agg[i] >= 0) N->func[L->agg[i]] = L->func[i];
+        ++l;
+    }
+    h->nlev = l + 1;
+    for (int t = 0; t + 1 < h->nlev; ++t)
+        if (level_diag(&h->L[t])) { orc_amg_free(h); return NULL; }
+    if (coarse_factor(h)) { orc_amg_free(h); return NULL; }
+    h->work = (double*)malloc(sizeof(double) * 6 * (maxn + 8));
+    return h;
+}
+
 /* Numeric re-setup (a reuse of the hierarchy when the matrix values change and its pattern does
  * not): level 0 takes the new values (and, if B0 is not NULL, a new near-null space); the
  * strength flags, MIS-2 roots and aggregates of every level are kept; every value-dependent
  * quantity is recomputed level by level exactly as in a full setup. */
 static int amg_update(amg* h, const double* vals0, const double* B0) {
     level* L0 = &h->L[0];
+    if (h->o.amg_type == 1) {
+        /* classical: the splitting and the interpolation depend on the values; set up again */
+        bsr A = *L0->A;
+        A.v = (double*)vals0;
+        amg* h2 = amg_build_classical(&A, &h->o);
+        if (!h2) return -1;
+        int64_t vc = h->vcycles;
+        for (int l = 0; l < h->nlev; ++l) level_free(&h->L[l]);
+        free(h->LU); free(h->piv); free(h->work);
+        *h = *h2;
+        h->vcycles = vc;
+        free(h2);
+        return 0;
+    }
     memcpy(L0->A->v, vals0, sizeof(double) * L0->A->nnzb * L0->b * L0->b);
     if (B0) memcpy(L0->B, B0, sizeof(double) * L0->A->nr * L0->b * L0->k);
     for (int l = 0; l + 1 < h->nlev; ++l)
@@ -625,6 +1100,7 @@ int orc_amg_update(amg* h, const double* vals0, const double* B0) { return amg_u
 /* Build the hierarchy for the square b x b BSR matrix A0 with near-null space B0 ((nr*b) x k).
  * A0 is copied.  Returns NULL on failure. */
 static amg* amg_build(const bsr* A0, const double* B0, int k, const amg_opts* o) {
+    if (o->amg_type == 1) return amg_build_classical(A0, o);
     amg* h = (amg*)calloc(1, sizeof(amg));
     h->o = *o;
     level* L = &h->L[0];
@@ -725,7 +1201,8 @@ static void vcycle_rec(amg* h, int l, const double* b, double* x) {
     double* r = (double*)malloc(sizeof(double) * n);
     double* d = (double*)malloc(sizeof(double) * n);
     double* z = (double*)malloc(sizeof(double) * n);
-    smooth(h, l, b, x, 1, r, d, z);
+    if (h->o.amg_type == 1) hybrid_gs(L->A, L->Dinv, h->o.gs_domain, 0, b, NULL, x);
+    else smooth(h, l, b, x, 1, r, d, z);
     bsr_mv(L->A, x, r);
 #pragma omp parallel for schedule(static) if (n > PAR_MIN)
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
@@ -737,7 +1214,12 @@ static void vcycle_rec(amg* h, int l, const double* b, double* x) {
     bsr_mv(L->P, xc, z);
 #pragma omp parallel for schedule(static) if (n > PAR_MIN)
     for (int64_t i = 0; i < n; ++i) x[i] += z[i];
-    smooth(h, l, b, x, 0, r, d, z);
+    if (h->o.amg_type == 1) {
+        memcpy(d, x, sizeof(double) * n);
+        hybrid_gs(L->A, L->Dinv, h->o.gs_domain, 1, b, d, x);
+    } else {
+        smooth(h, l, b, x, 0, r, d, z);
+    }
     free(r); free(d); free(z); free(bc); free(xc);
 }
 
@@ -753,7 +1235,13 @@ void orc_amg_smooth(amg* h, int l, const double* b, double* x, int zero_init) {
     double* r = (double*)malloc(sizeof(double) * n);
     double* d = (double*)malloc(sizeof(double) * n);
     double* z = (double*)malloc(sizeof(double) * n);
-    smooth(h, l, b, x, zero_init, r, d, z);
+    if (h->o.amg_type == 1) {
+        /* classical: the V-cycle's sweeps (forward from zero, or backward from x) */
+        if (zero_init) hybrid_gs(h->L[l].A, h->L[l].Dinv, h->o.gs_domain, 0, b, NULL, x);
+        else { memcpy(d, x, sizeof(double) * n); hybrid_gs(h->L[l].A, h->L[l].Dinv, h->o.gs_domain, 1, b, d, x); }
+    } else {
+        smooth(h, l, b, x, zero_init, r, d, z);
+    }
     free(r); free(d); free(z);
 }
 
@@ -777,7 +1265,8 @@ void orc_amg_level_info(const amg* h, int l, int64_t* info, double* lam) {
     *lam = L->lam;
 }
 
-/* field: 0 A.rp 1 A.ci 2 A.v 3 agg 4 P.rp 5 P.ci 6 P.v 7 R.rp 8 R.ci 9 R.v 10 strong 11 dead 12 Dinv 13 B 14 Q */
+/* field: 0 A.rp 1 A.ci 2 A.v 3 agg (classical: coarse index or -1) 4 P.rp 5 P.ci 6 P.v 7 R.rp
+ * 8 R.ci 9 R.v 10 strong 11 dead 12 Dinv 13 B 14 Q 15 func (classical) */
 int orc_amg_level_get(const amg* h, int l, int field, void* dst) {
     const level* L = &h->L[l];
     const bsr* M = NULL;
@@ -795,8 +1284,9 @@ int orc_amg_level_get(const amg* h, int l, int field, void* dst) {
         case 10: if (!L->strong) return -1; memcpy(dst, L->strong, L->A->nnzb); break;
         case 11: if (!L->dead) return -1; memcpy(dst, L->dead, L->n_agg * L->k); break;
         case 12: if (!L->Dinv) return -1; memcpy(dst, L->Dinv, sizeof(double) * L->A->nr * L->b * L->b); break;
-        case 13: memcpy(dst, L->B, sizeof(double) * L->A->nr * L->b * L->k); break;
+        case 13: if (!L->B) return -1; memcpy(dst, L->B, sizeof(double) * L->A->nr * L->b * L->k); break;
         case 14: if (!L->Q) return -1; memcpy(dst, L->Q, sizeof(double) * L->A->nr * L->b * L->k); break;
+        case 15: if (!L->func) return -1; memcpy(dst, L->func, L->A->nr); break;
         default: return -1;
     }
     return 0;
