@@ -50,6 +50,9 @@ typedef enum {
 typedef enum { SCR_SYSTEM = 0, MESH_SYSTEM = 1 } scr_kind;
 typedef enum { SCR_FP64 = 0, SCR_MIXED = 1, SCR_MIXED_FP32_INNER = 2 } scr_precision;
 typedef enum { SCR_SMOOTH_JACOBI = 0, SCR_SMOOTH_CHEBYSHEV = 1 } scr_smoother;
+/* AMG kind (amg_type): smoothed aggregation (default), or classical AMG with the settings of the
+ * paper's table in Sec. 5.2 (see scr_amg_opts) */
+typedef enum { SCR_AMG_SA = 0, SCR_AMG_CLASSICAL = 1 } scr_amg_type;
 
 /* diagonal used in S^ (scr_amg_opts.schur_diag) */
 typedef enum { SCR_DIAG_A = 0, SCR_DIAG_ABSROWSUM = 1 } scr_schur_diag;
@@ -97,6 +100,25 @@ typedef struct {
                                   of the absolute values of A's rows (the SIMPLEC lumping) */
     int schur_cheb_degree;     /* SCR_SYSTEM: Chebyshev degree of AMG(S^), 8 (0 = cheb_degree) */
     double schur_cheb_ratio;   /* SCR_SYSTEM: Chebyshev interval ratio of AMG(S^), 100 (0 = cheb_ratio) */
+    int amg_type;              /* SCR_AMG_SA (default) or SCR_AMG_CLASSICAL: the BoomerAMG settings of
+                                  Sec. 5.2's table on the device.  Strength: row i depends on j (same
+                                  function, i.e. the same velocity component for A's 3x3 blocks) when
+                                  -s a_ij >= cl_theta max_k (-s a_ik), s = sign(a_ii).  HMIS: the
+                                  Ruge-Stueben first pass inside domains of 256 consecutive rows (one
+                                  workgroup each), then PMIS over the whole graph started from the
+                                  first pass's C points whose strong connections stay in their domain
+                                  (random part from splitmix64 of seed, level, row).  Extended+i
+                                  interpolation truncated at trunc and to pmax entries per row (row
+                                  sums kept).  Smoother: one hybrid Gauss-Seidel sweep before (forward)
+                                  and after (backward) the coarse correction, Gauss-Seidel inside
+                                  domains of 64 rows (one wavefront each), Jacobi between them.
+                                  Galerkin coarse operators, direct coarsest solve.  FP64 only; the
+                                  near-null space, theta, the smoother and Chebyshev fields are not
+                                  used; amg_update sets the hierarchy up again.  Aggressive
+                                  coarsening (the table's last row) is not implemented. */
+    double cl_theta;           /* classical strength threshold, 0.5 */
+    double trunc;              /* interpolation truncation factor, 0.3 */
+    int pmax;                  /* interpolation entries per row, 5 (1..16) */
 } scr_amg_opts;
 
 /* Krylov options.  Defaults: tol 1e-8 (outer), tol_A = tol_S = tol_I = 1e-3 and 200
@@ -390,12 +412,15 @@ const char* scr_last_error(void);
 /* ---------------------------------------------------------------- inspection / components
  * Hierarchies: which = 0 AMG(A), 1 AMG(S^), 2 AMG(L).  Fields of a level (copied to host):
  *   0 A.row_ptr (int32, nr+1)   1 A.col_idx (int32, nnzb)   2 A.val (FP64, nnzb*b*b)
- *   3 aggregate of each block row (int32, nr; -1 = isolated)
+ *   3 aggregate of each block row (int32, nr; -1 = isolated); classical: the coarse index of each
+ *     C point, -1 on F points
  *   4 P.row_ptr  5 P.col_idx  6 P.val (FP64, b x k blocks)
  *   7 R.row_ptr  8 R.col_idx  9 R.val (FP64, k x b blocks)
  *   10 strong flag per stored block of A (uint8)   11 dead coarse dof flags (uint8, nagg*k)
  *   12 D^-1 blocks (FP64, nr*b*b)   13 near-null space B (FP64, nr*b x k)
- * info = [nr, b, k, nnzb(A), nagg, nnzb(P), nnzb(R), n_coarsest]; lam = lambda_hat. */
+ *   15 classical: the function of each scalar row (uint8, nr)
+ * info = [nr, b, k, nnzb(A), nagg, nnzb(P), nnzb(R), n_coarsest]; lam = lambda_hat.  Classical
+ * hierarchies are scalar (b = k = 1, level 0 the scalar rows of the blocks); nagg = C points. */
 scr_status scr_hier_levels(scr_handle* h, int which, int* nlev /* host */);
 scr_status scr_hier_level_info(scr_handle* h, int which, int level, int64_t* info /* host, 8 */,
                                double* lam /* host */);

@@ -24,6 +24,7 @@ SOURCES = {
     "sparse.hip": [],
     "krylov.hip": [],
     "amg.hip": ["-ffp-contract=off"],
+    "classical.hip": ["-ffp-contract=off"],
     "scr.hip": [],
     "serve.hip": [],
     "assemble.hip": [],

@@ -39,7 +39,7 @@ __device__ __forceinline__ uint64_t mis_key(uint64_t seed, int level, int64_t i)
     return ((h >> 34) << 32) | (uint64_t)(uint32_t)i;
 }
 
-static DBsr bsr_alloc(int64_t nr, int64_t nc, int br, int bc, int64_t nnzb, Arena& ar) {
+DBsr bsr_alloc(int64_t nr, int64_t nc, int br, int bc, int64_t nnzb, Arena& ar) {
     DBsr M;
     M.nr = nr; M.nc = nc; M.br = br; M.bc = bc; M.nnzb = nnzb;
     M.rp = ar.make<int32_t>(nr + 1);
@@ -47,7 +47,7 @@ static DBsr bsr_alloc(int64_t nr, int64_t nc, int br, int bc, int64_t nnzb, Aren
     M.v = ar.make<double>((nnzb > 0 ? nnzb : 1) * br * bc);
     return M;
 }
-static void bsr_release(DBsr& M, Arena& ar) {
+void bsr_release(DBsr& M, Arena& ar) {
     ar.free(M.rp); ar.free(M.ci); ar.free(M.v);
     M = DBsr();
 }
@@ -342,7 +342,7 @@ static void spgemm_numeric_run(const DBsr& X, const DBsr& Y, DBsr& C, int wmax, 
     check_launch("spg_numeric");
 }
 
-static DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hipStream_t s) {
+DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hipStream_t s) {
     DBsr C;
     C.nr = X.nr; C.nc = Y.nc; C.br = X.br; C.bc = Y.bc;
     C.rp = ar.make<int32_t>(X.nr + 1);
@@ -1018,7 +1018,7 @@ __global__ void row_of_k(int64_t nr, const int32_t* __restrict__ rp, int32_t* __
     for (int32_t q = rp[i]; q < rp[i + 1]; ++q) rowof[q] = (int32_t)i;
 }
 
-static DBsr transpose(const DBsr& M, Arena& ar, hipStream_t s) {
+DBsr transpose(const DBsr& M, Arena& ar, hipStream_t s) {
     DBsr T;
     T.nr = M.nc; T.nc = M.nr; T.br = M.bc; T.bc = M.br; T.nnzb = M.nnzb;
     int32_t* cnt = ar.make<int32_t>(M.nc + 1);
@@ -1463,7 +1463,7 @@ static int64_t read_i32(const int32_t* p, hipStream_t s) {
 }
 
 // D^-1 (into L.Dinv) and lambda_hat = max abs row sum of D^-1 A (into L.lam)
-static void level_diag(LevelSetup& L, int l, int* err, unsigned long long* lamd, hipStream_t s) {
+void level_diag(LevelSetup& L, int l, int* err, unsigned long long* lamd, hipStream_t s) {
     const int64_t nr = L.A.nr;
     const int64_t g = cdiv(nr, 256);
     const int b = L.b;
@@ -1509,7 +1509,7 @@ constexpr double COARSE_ETA_MAX = 1e-10;
 
 // coarsest level: explicit inverse by Gauss-Jordan exchange steps, in order (fast panels), or
 // with partial pivoting when the fast inverse fails its check.  H.coarse_pivoted records which.
-static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
+void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
     LevelSetup& C = H.L.back();
     int64_t nc = C.A.nr * C.b;
     H.ncoarse = nc;
@@ -1568,6 +1568,7 @@ static void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s) {
 std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int k, const scr_amg_opts& o, Arena& ar,
                                            hipStream_t s, Profiler* prof, bool three) {
     if (three && A0.br != 1) throw Error(SCR_E_INVALID, "three-column V-cycles need a scalar matrix");
+    if (o.amg_type == SCR_AMG_CLASSICAL) return build_classical(A0, o, ar, s, three);
     std::unique_ptr<Hierarchy> H;
     HierT<double>* hd = nullptr;
     HierT<float>* hf = nullptr;
@@ -1729,6 +1730,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
 }
 
 void update_hierarchy(Hierarchy& H, const double* vals0, const double* B0, Arena& ar, hipStream_t s) {
+    if (H.opts.amg_type == SCR_AMG_CLASSICAL) {
+        update_classical(H, vals0, ar, s);
+        return;
+    }
     int* err = ar.make<int>(1);
     unsigned long long* lamd = ar.make<unsigned long long>(1);
     LevelSetup& L0 = H.L[0];

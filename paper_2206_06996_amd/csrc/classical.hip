@@ -1,0 +1,728 @@
+// classical.hip -- classical AMG on the device with the settings of the paper's table of
+// BoomerAMG options (Sec. 5.2): classical strength (threshold 0.5), HMIS coarsening, extended+i
+// interpolation truncated at 0.3 with at most 5 entries per row, hybrid Gauss-Seidel smoothing,
+// V-cycle with Galerkin coarse operators and a direct coarsest solve.
+//
+// Mapping to the chip.  HMIS's per-processor first pass (Ruge-Stueben) runs with one workgroup
+// per domain of 256 consecutive rows: the measures and states live in LDS, each step picks the
+// domain's largest measure by a workgroup reduction, and the C/F updates are LDS integer atomics
+// (order-free, so the result is that of the sequential pass).  The PMIS rounds and extended+i are
+// row-parallel.  Hybrid Gauss-Seidel gives each wavefront a domain of 64 rows: the rows are swept
+// in order, the lanes split each row's entries, and a row's new value stays in the register of
+// the lane that owns it, where the later rows of the domain read it by a cross-lane permute.
+// Interpolation weights, their truncation and the Galerkin products are evaluated in the
+// definitions' order without fused multiply-adds (this file is built with -ffp-contract=off), so
+// every level's split, pattern and values are those of a sequential evaluation.
+#include <algorithm>
+#include <memory>
+
+#include "solver.h"
+
+namespace scr {
+namespace {
+
+constexpr int HMIS_DOM = 256;      // rows per HMIS domain (one workgroup)
+constexpr int GS_DOM = 64;         // rows per hybrid Gauss-Seidel domain (one wavefront)
+constexpr int8_t ST_U = 0, ST_C = 1, ST_F = 2, ST_NEWF = 3;
+
+// ------------------------------------------------------------------ set-up kernels
+// scalar rows of a b x b block matrix: row b i + r holds, block by block, the entries of row r
+__global__ void to_scalar_k(int64_t nb, int b, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const double* __restrict__ v, int32_t* __restrict__ srp, int32_t* __restrict__ sci,
+                            double* __restrict__ sv, uint8_t* __restrict__ func) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int32_t q0 = rp[i], len = rp[i + 1] - q0;
+    for (int r = 0; r < b; ++r) {
+        const int64_t row = (int64_t)b * i + r;
+        int64_t p = (int64_t)b * b * q0 + (int64_t)r * b * len;
+        srp[row] = (int32_t)p;
+        func[row] = (uint8_t)r;
+        for (int32_t q = q0; q < q0 + len; ++q)
+            for (int c = 0; c < b; ++c) {
+                sci[p] = ci[q] * b + c;
+                sv[p] = v[(int64_t)q * b * b + r * b + c];
+                ++p;
+            }
+    }
+    if (i == nb - 1) srp[(int64_t)b * nb] = (int32_t)((int64_t)b * b * rp[nb]);
+}
+
+__device__ __forceinline__ int32_t find_sorted_dev(const int32_t* __restrict__ v, int32_t lo, int32_t hi, int32_t key) {
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (v[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// tmap[q] = position of (j, i) for q = (i, j); err if the pattern is not structurally symmetric
+__global__ void tmap_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       int32_t* __restrict__ tmap, int* __restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int32_t j = ci[q];
+        const int32_t t = find_sorted_dev(ci, rp[j], rp[j + 1], (int32_t)i);
+        if (t < rp[j + 1] && ci[t] == i) tmap[q] = t;
+        else { tmap[q] = -1; *err = 1; }
+    }
+}
+
+// classical strength within a function: -s a_ij >= theta max_k(-s a_ik), s = sign(a_ii)
+__global__ void cl_strength_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              const double* __restrict__ v, const uint8_t* __restrict__ func, double theta,
+                              uint8_t* __restrict__ S) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    double aii = 0.0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+        if (ci[q] == i) aii = v[q];
+    const double sg = aii < 0.0 ? -1.0 : 1.0;
+    bool have = false;
+    double m = 0.0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int32_t j = ci[q];
+        if (j == i || func[j] != func[i]) continue;
+        const double x = -sg * v[q];
+        if (!have || x > m) { m = x; have = true; }
+    }
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int32_t j = ci[q];
+        uint8_t f = 0;
+        if (j != i && func[j] == func[i] && have && m > 0.0) f = (uint8_t)(-sg * v[q] >= theta * m);
+        S[q] = f;
+    }
+}
+
+// Ruge-Stueben first pass inside one domain of HMIS_DOM rows per workgroup (writes first[i]:
+// 1 = C, -1 = F).  One C point per step: the undecided point of largest measure, lowest row on ties.
+__global__ void __launch_bounds__(HMIS_DOM) hmis_first_k(int64_t nr, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci, const uint8_t* __restrict__ S,
+                                                         const int32_t* __restrict__ tmap, int8_t* __restrict__ first) {
+    __shared__ int lam[HMIS_DOM];
+    __shared__ int8_t st[HMIS_DOM];
+    __shared__ long long red[HMIS_DOM / WAVE];
+    const int t = threadIdx.x;
+    const int64_t d0 = (int64_t)blockIdx.x * HMIS_DOM;
+    const int64_t d1 = d0 + HMIS_DOM < nr ? d0 + HMIS_DOM : nr;
+    const int64_t i = d0 + t;
+    const bool live = i < d1;
+    if (live) {
+        int l = 0, dep = 0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            const int64_t j = ci[q];
+            if (j < d0 || j >= d1) continue;
+            l += S[tmap[q]];
+            dep += S[q];
+        }
+        lam[t] = l;
+        st[t] = (l == 0 && dep == 0) ? ST_F : ST_U;
+    } else {
+        lam[t] = 0;
+        st[t] = ST_F;
+    }
+    __syncthreads();
+    for (;;) {
+        // key: measure (biased positive) then 255 - t, so the maximum is the largest measure, lowest t
+        long long key = st[t] == ST_U ? (((long long)lam[t] + (1LL << 30)) << 8) | (long long)(HMIS_DOM - 1 - t) : -1;
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) {
+            long long w = __shfl_xor(key, o, WAVE);
+            key = w > key ? w : key;
+        }
+        if ((t & (WAVE - 1)) == 0) red[t / WAVE] = key;
+        __syncthreads();
+        long long best = red[0];
+        for (int w = 1; w < HMIS_DOM / WAVE; ++w) best = red[w] > best ? red[w] : best;
+        __syncthreads();
+        if (best < 0) break;
+        const int c = HMIS_DOM - 1 - (int)(best & 0xFF);
+        const int64_t cr = d0 + c;
+        if (t == c) st[c] = ST_C;
+        __syncthreads();
+        // the domain's undecided points that depend on c become F
+        for (int32_t q = rp[cr] + t; q < rp[cr + 1]; q += HMIS_DOM) {
+            const int64_t j = ci[q];
+            if (j >= d0 && j < d1 && st[j - d0] == ST_U && S[tmap[q]]) st[j - d0] = ST_NEWF;
+        }
+        __syncthreads();
+        // the undecided points c depends on lose one unit of measure
+        for (int32_t q = rp[cr] + t; q < rp[cr + 1]; q += HMIS_DOM) {
+            const int64_t j = ci[q];
+            if (j >= d0 && j < d1 && st[j - d0] == ST_U && S[q]) atomicSub(&lam[j - d0], 1);
+        }
+        // the undecided points each new F point depends on gain one
+        if (live && st[t] == ST_NEWF)
+            for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+                const int64_t k = ci[q];
+                if (k >= d0 && k < d1 && st[k - d0] == ST_U && S[q]) atomicAdd(&lam[k - d0], 1);
+            }
+        __syncthreads();
+        if (st[t] == ST_NEWF) st[t] = ST_F;
+        __syncthreads();
+    }
+    if (live) first[i] = st[t] == ST_C ? 1 : -1;
+}
+
+__device__ __forceinline__ uint64_t splitmix(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+
+// PMIS start: measure |S^T_i| + u_i; C for first-pass C points whose strong connections stay in
+// their domain; F for points that influence nobody; the rest undecided
+__global__ void pmis_init_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const uint8_t* __restrict__ S, const int32_t* __restrict__ tmap,
+                            const int8_t* __restrict__ first, uint64_t seed, int level, double* __restrict__ w,
+                            int8_t* __restrict__ st, uint8_t* __restrict__ isnew) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    const int64_t dm = i / HMIS_DOM;
+    bool interior = true;
+    int nst = 0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const uint8_t sT = S[tmap[q]];
+        nst += sT;
+        if ((S[q] || sT) && (int64_t)ci[q] / HMIS_DOM != dm) interior = false;
+    }
+    const uint64_t h = splitmix(seed ^ ((uint64_t)level << 56) ^ ((uint64_t)i * 0x9E6C63D0676A9A99ULL));
+    w[i] = (double)nst + (double)(h >> 11) * 0x1.0p-53;
+    int8_t s;
+    if (first[i] == 1 && interior) s = ST_C;
+    else s = nst == 0 ? ST_F : ST_U;
+    st[i] = s;
+    isnew[i] = s == ST_C;
+}
+
+// undecided points that depend on a C point of the previous round become F; counts the undecided
+__global__ void pmis_f_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                         const uint8_t* __restrict__ S, const uint8_t* __restrict__ isnew, const int8_t* __restrict__ st,
+                         int8_t* __restrict__ out, int* __restrict__ und) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int u = 0;
+    if (i < nr) {
+        int8_t s = st[i];
+        if (s == ST_U)
+            for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+                if (S[q] && isnew[ci[q]]) { s = ST_F; break; }
+        out[i] = s;
+        u = s == ST_U;
+    }
+    // one atomic per wavefront
+    for (int o = WAVE / 2; o > 0; o >>= 1) u += __shfl_xor(u, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && u) atomicAdd(und, u);
+}
+
+// undecided points whose measure beats every undecided strong neighbour's (either direction)
+__global__ void pmis_c_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                         const uint8_t* __restrict__ S, const int32_t* __restrict__ tmap, const double* __restrict__ w,
+                         const int8_t* __restrict__ st, uint8_t* __restrict__ isnew) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    bool best = st[i] == ST_U;
+    for (int32_t q = rp[i]; q < rp[i + 1] && best; ++q) {
+        const int64_t j = ci[q];
+        if (j == i || st[j] != ST_U || !(S[q] || S[tmap[q]])) continue;
+        if (!(w[i] > w[j] || (w[i] == w[j] && i < j))) best = false;
+    }
+    isnew[i] = best;
+}
+
+__global__ void pmis_apply_k(int64_t nr, const uint8_t* __restrict__ isnew, int8_t* __restrict__ st) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr && isnew[i]) st[i] = ST_C;
+}
+
+__global__ void cflag_k(int64_t nr, const int8_t* __restrict__ st, int32_t* __restrict__ f) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) f[i] = st[i] == ST_C;
+}
+
+__global__ void cidx_k(int64_t nr, const int8_t* __restrict__ st, const int32_t* __restrict__ rank,
+                       int32_t* __restrict__ cidx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) cidx[i] = st[i] == ST_C ? rank[i] : -1;
+}
+
+__global__ void coarse_func_k(int64_t nr, const int32_t* __restrict__ cidx, const uint8_t* __restrict__ func,
+                              uint8_t* __restrict__ fc) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr && cidx[i] >= 0) fc[cidx[i]] = func[i];
+}
+
+// upper bound of |C^_i| (1 for C points)
+__global__ void extpi_cap_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const uint8_t* __restrict__ S, const int32_t* __restrict__ cidx, int32_t* __restrict__ cap) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    if (cidx[i] >= 0) { cap[i] = 1; return; }
+    int64_t c = 0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        if (!S[q]) continue;
+        const int32_t j = ci[q];
+        c += cidx[j] >= 0 ? 1 : rp[j + 1] - rp[j];
+    }
+    cap[i] = (int32_t)(c < (1 << 30) ? c : (1 << 30));
+}
+
+__device__ __forceinline__ bool opposite(double a, double d) { return (a > 0.0 && d < 0.0) || (a < 0.0 && d > 0.0); }
+
+__device__ void heap_sift(int32_t* a, int64_t n, int64_t r) {
+    for (;;) {
+        int64_t c = 2 * r + 1;
+        if (c >= n) return;
+        if (c + 1 < n && a[c + 1] > a[c]) ++c;
+        if (a[r] >= a[c]) return;
+        int32_t t = a[r]; a[r] = a[c]; a[c] = t;
+        r = c;
+    }
+}
+__device__ void heap_sort(int32_t* a, int64_t n) {
+    for (int64_t r = n / 2 - 1; r >= 0; --r) heap_sift(a, n, r);
+    for (int64_t e = n - 1; e > 0; --e) {
+        int32_t t = a[0]; a[0] = a[e]; a[e] = t;
+        heap_sift(a, e, 0);
+    }
+}
+__device__ __forceinline__ int64_t in_hat(const int32_t* hat, int64_t m, int32_t key) {
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (hat[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < m && hat[lo] == key) ? lo : -1;
+}
+
+// extended+i row i into its scratch segment [off_i, off_i + cap_i): the kept coarse columns
+// (ascending) and weights at its front, their count in cnt[i]
+__global__ void extpi_row_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const double* __restrict__ v, const uint8_t* __restrict__ func,
+                            const uint8_t* __restrict__ S, const int32_t* __restrict__ cidx,
+                            const int32_t* __restrict__ off, double trunc, int pmax, int32_t* __restrict__ hcol,
+                            double* __restrict__ hw, int32_t* __restrict__ cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int32_t* hat = hcol + off[i];
+    double* w = hw + off[i];
+    if (cidx[i] >= 0) {
+        hat[0] = cidx[i];
+        w[0] = 1.0;
+        cnt[i] = 1;
+        return;
+    }
+    // C^_i: strong C neighbours and the strong C neighbours of strong F neighbours (sorted, unique)
+    int64_t m = 0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        if (!S[q]) continue;
+        const int32_t j = ci[q];
+        if (cidx[j] >= 0) { hat[m++] = j; continue; }
+        for (int32_t r = rp[j]; r < rp[j + 1]; ++r)
+            if (S[r] && cidx[ci[r]] >= 0) hat[m++] = ci[r];
+    }
+    heap_sort(hat, m);
+    int64_t u = 0;
+    for (int64_t t = 0; t < m; ++t)
+        if (u == 0 || hat[t] != hat[u - 1]) hat[u++] = hat[t];
+    m = u;
+    double diag = 0.0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+        if (ci[q] == i) diag = v[q];
+    for (int64_t t = 0; t < m; ++t) w[t] = 0.0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int32_t n = ci[q];
+        if (n == i || func[n] != func[i]) continue;
+        const int64_t p = in_hat(hat, m, n);
+        if (p >= 0) { w[p] = w[p] + v[q]; continue; }
+        if (S[q] && cidx[n] < 0) {
+            double ann = 0.0, den = 0.0;
+            for (int32_t r = rp[n]; r < rp[n + 1]; ++r)
+                if (ci[r] == n) ann = v[r];
+            for (int32_t r = rp[n]; r < rp[n + 1]; ++r) {
+                const int32_t l = ci[r];
+                if ((l == i || in_hat(hat, m, l) >= 0) && opposite(v[r], ann)) den = den + v[r];
+            }
+            if (den == 0.0) { diag = diag + v[q]; continue; }
+            for (int32_t r = rp[n]; r < rp[n + 1]; ++r) {
+                const int32_t l = ci[r];
+                if (!opposite(v[r], ann)) continue;
+                const double x = (v[q] * v[r]) / den;
+                if (l == i) diag = diag + x;
+                else {
+                    const int64_t pl = in_hat(hat, m, l);
+                    if (pl >= 0) w[pl] = w[pl] + x;
+                }
+            }
+            continue;
+        }
+        diag = diag + v[q];
+    }
+    if (m == 0 || diag == 0.0) { cnt[i] = 0; return; }
+    for (int64_t t = 0; t < m; ++t) w[t] = -w[t] / diag;
+    // truncation: relative to the largest magnitude, then the pmax largest, then the row sum
+    double mx = 0.0, all = 0.0;
+    for (int64_t t = 0; t < m; ++t) {
+        all = all + w[t];
+        if (fabs(w[t]) > mx) mx = fabs(w[t]);
+    }
+    int64_t k = 0;
+    for (int64_t t = 0; t < m; ++t)
+        if (w[t] != 0.0 && fabs(w[t]) >= trunc * mx) { hat[k] = hat[t]; w[k] = w[t]; ++k; }
+    if (k > pmax) {
+        // the pmax largest magnitudes, lower column first on ties: mark them by negating the column
+        for (int s = 0; s < pmax; ++s) {
+            int64_t b = -1;
+            for (int64_t t = 0; t < k; ++t) {
+                if (hat[t] < 0) continue;
+                if (b < 0 || fabs(w[t]) > fabs(w[b])) b = t;
+            }
+            hat[b] = -1 - hat[b];
+        }
+        int64_t k2 = 0;
+        for (int64_t t = 0; t < k; ++t)
+            if (hat[t] < 0) { hat[k2] = -1 - hat[t]; w[k2] = w[t]; ++k2; }
+        k = k2;
+    }
+    double kept = 0.0;
+    for (int64_t t = 0; t < k; ++t) kept = kept + w[t];
+    if (kept != 0.0) {
+        const double sc = all / kept;
+        for (int64_t t = 0; t < k; ++t) w[t] = w[t] * sc;
+    }
+    for (int64_t t = 0; t < k; ++t) hat[t] = cidx[hat[t]];
+    cnt[i] = (int32_t)k;
+}
+
+__global__ void extpi_fill_k(int64_t nr, const int32_t* __restrict__ off, const int32_t* __restrict__ hcol,
+                             const double* __restrict__ hw, const int32_t* __restrict__ prp, int32_t* __restrict__ pci,
+                             double* __restrict__ pv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    const int32_t n = prp[i + 1] - prp[i];
+    for (int32_t t = 0; t < n; ++t) {
+        pci[prp[i] + t] = hcol[off[i] + t];
+        pv[prp[i] + t] = hw[off[i] + t];
+    }
+}
+
+// ------------------------------------------------------------------ hybrid Gauss-Seidel
+// One sweep: x_i = (b_i - sum_{j != i} a_ij x~_j) / a_ii, x~_j new for rows of the same domain
+// already swept (forward: j < i; backward: j > i), else the previous iterate xold (nullptr: 0).
+// NC node-interleaved columns (entry NC i + c).  One wavefront per domain of GS_DOM rows.
+template <int NC, bool BWD>
+__global__ void __launch_bounds__(256) hgs_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                             const double* __restrict__ v, const double* __restrict__ dinv,
+                                             const double* __restrict__ b, const double* __restrict__ xold,
+                                             double* __restrict__ x) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * (256 / WAVE) + threadIdx.x / WAVE;
+    const int64_t lo = d * GS_DOM;
+    if (lo >= nr) return;
+    const int64_t hi = lo + GS_DOM < nr ? lo + GS_DOM : nr;
+    double xn[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xn[c] = 0.0;
+    for (int64_t t = 0; t < hi - lo; ++t) {
+        const int64_t i = BWD ? hi - 1 - t : lo + t;
+        double acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        const int32_t q0 = rp[i], q1 = rp[i + 1];
+        for (int32_t base = q0; base < q1; base += WAVE) {
+            const int32_t q = base + lane;
+            const bool valid = q < q1;
+            const int64_t j = valid ? ci[q] : i;
+            const double a = valid ? v[q] : 0.0;
+            const bool in_dom = j >= lo && j < hi;
+            const bool fresh = in_dom && (BWD ? j > i : j < i);
+            const int src = in_dom ? (int)(j - lo) : 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double xf = __shfl(xn[c], src, WAVE);
+                const double xo = (!fresh && valid && xold != nullptr) ? xold[NC * j + c] : 0.0;
+                if (valid && j != i) acc[c] += a * (fresh ? xf : xo);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double sum = wave_sum(acc[c]);
+            const double xi = (b[NC * i + c] - sum) * dinv[i];
+            if (lane == (int)(i - lo)) {
+                xn[c] = xi;
+                x[NC * i + c] = xi;
+            }
+        }
+    }
+}
+
+template <int NC>
+void hgs(const DBsr& A, const double* Dinv, const double* b, const double* xold, double* x, bool backward, hipStream_t s) {
+    const int64_t nd = cdiv(A.nr, GS_DOM);
+    const unsigned g = (unsigned)cdiv(nd, 256 / WAVE);
+    if (!g) return;
+    if (backward) hgs_k<NC, true><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, b, xold, x);
+    else hgs_k<NC, false><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, b, xold, x);
+    check_launch("hybrid_gs");
+}
+
+// ------------------------------------------------------------------ hierarchy
+class ClassicalHier : public Hierarchy {
+   public:
+    struct LS {
+        DSell<double> A, P;
+        DBsrT<double> R;
+        double *b = nullptr, *x = nullptr, *w = nullptr, *r = nullptr;
+        double *b3 = nullptr, *x3 = nullptr, *w3 = nullptr, *r3 = nullptr;
+    };
+    std::vector<LS> S;
+    DBsr pattern0;                   // the block pattern of A0 (no values), for amg_update
+
+    void prepare(Arena& a, hipStream_t s) {
+        S.resize(L.size());
+        for (size_t l = 0; l < L.size(); ++l) {
+            LevelSetup& ls = L[l];
+            LS& q = S[l];
+            const int64_t n = ls.A.nr;
+            q.b = a.make<double>(n); q.x = a.make<double>(n);
+            if (three) { q.b3 = a.make<double>(3 * n); q.x3 = a.make<double>(3 * n); }
+            if (l + 1 == L.size()) continue;
+            q.A = sell_from_bsr<double>(ls.A, a, s);
+            q.P = sell_from_bsr<double>(ls.P, a, s);
+            q.R = bsrt_from_bsr<double>(ls.R, a, s);
+            q.w = a.make<double>(n); q.r = a.make<double>(n);
+            if (three) { q.w3 = a.make<double>(3 * n); q.r3 = a.make<double>(3 * n); }
+        }
+    }
+    void release_solve(Arena& a) {
+        for (auto& q : S) {
+            sell_free(q.A, a);
+            sell_free(q.P, a);
+            a.free(q.R.v);
+            for (double* p : {q.b, q.x, q.w, q.r, q.b3, q.x3, q.w3, q.r3}) a.free(p);
+        }
+        S.clear();
+    }
+    void refresh(Arena& a, hipStream_t s) override {
+        release_solve(a);
+        prepare(a, s);
+    }
+    void cycle(size_t l, const double* b, double* x, hipStream_t s) {
+        if (l + 1 == S.size()) {
+            dense_mv<double>(ncoarse, cinv, b, x, s);
+            return;
+        }
+        LS& q = S[l];
+        const LevelSetup& ls = L[l];
+        hgs<1>(ls.A, ls.Dinv, b, nullptr, q.w, false, s);
+        sell_mv<double>(q.A, q.w, b, q.r, 1, s);
+        bsrt_mv<double>(q.R, q.r, S[l + 1].b, s);
+        cycle(l + 1, S[l + 1].b, S[l + 1].x, s);
+        sell_mv<double>(q.P, S[l + 1].x, nullptr, q.w, 2, s);
+        hgs<1>(ls.A, ls.Dinv, b, q.w, x, true, s);
+    }
+    void cycle3(size_t l, const double* b, double* x, hipStream_t s) {
+        if (l + 1 == S.size()) {
+            dense_mv3<double>(ncoarse, cinv, b, x, s);
+            return;
+        }
+        LS& q = S[l];
+        const LevelSetup& ls = L[l];
+        hgs<3>(ls.A, ls.Dinv, b, nullptr, q.w3, false, s);
+        sell_mv3<double>(q.A, q.w3, b, q.r3, 1, s);
+        bsrt_mv3<double>(q.R, q.r3, S[l + 1].b3, s);
+        cycle3(l + 1, S[l + 1].b3, S[l + 1].x3, s);
+        sell_mv3<double>(q.P, S[l + 1].x3, nullptr, q.w3, 2, s);
+        hgs<3>(ls.A, ls.Dinv, b, q.w3, x, true, s);
+    }
+    void vcycle(const double* x, double* y, hipStream_t s) override {
+        ++vcycles;
+        cycle(0, x, y, s);
+    }
+    void vcycle3(const double* x, double* y, hipStream_t s) override {
+        if (!three) throw Error(SCR_E_INVALID, "three-column V-cycle on a hierarchy built without it");
+        vcycles += 3;
+        cycle3(0, x, y, s);
+    }
+    void vcycle_f(const float*, float*, hipStream_t) override {
+        throw Error(SCR_E_INVALID, "classical AMG runs in FP64 only");
+    }
+    const DSell<float>* level0_f() const override { return nullptr; }
+};
+
+int read_flag(const int* p, hipStream_t s) {
+    int v = 0;
+    HIPCHK(hipMemcpyAsync(&v, p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return v;
+}
+
+// C/F split of level L (strength flags set): HMIS; returns the number of C points, coarse
+// indices in L.agg
+int64_t hmis_split(LevelSetup& L, const int32_t* tmap, uint64_t seed, int level, int* err, Arena& ar, hipStream_t s) {
+    const int64_t nr = L.A.nr;
+    const unsigned g = (unsigned)cdiv(nr, 256);
+    int8_t* first = ar.make<int8_t>(nr);
+    hmis_first_k<<<(unsigned)cdiv(nr, HMIS_DOM), HMIS_DOM, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, tmap, first);
+    check_launch("hmis first pass");
+    double* w = ar.make<double>(nr);
+    int8_t* st = ar.make<int8_t>(nr);
+    int8_t* st2 = ar.make<int8_t>(nr);
+    uint8_t* isnew = ar.make<uint8_t>(nr);
+    pmis_init_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, tmap, first, seed, level, w, st, isnew);
+    check_launch("pmis init");
+    for (int round = 0;; ++round) {
+        if (round > 100000) throw Error(SCR_E_HIP, "PMIS did not terminate");
+        zero_dev(err, sizeof(int), s);
+        pmis_f_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, isnew, st, st2, err);
+        check_launch("pmis f");
+        std::swap(st, st2);
+        if (read_flag(err, s) == 0) break;
+        pmis_c_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, tmap, w, st, isnew);
+        pmis_apply_k<<<g, 256, 0, s>>>(nr, isnew, st);
+        check_launch("pmis c");
+    }
+    int32_t* f = ar.make<int32_t>(nr + 1);
+    int32_t* rank = ar.make<int32_t>(nr + 1);
+    cflag_k<<<g, 256, 0, s>>>(nr, st, f);
+    const int64_t nc = scan_i32(f, rank, nr, ar, s);
+    L.agg = ar.make<int32_t>(nr);
+    cidx_k<<<g, 256, 0, s>>>(nr, st, rank, L.agg);
+    check_launch("coarse index");
+    ar.free(f); ar.free(rank); ar.free(first); ar.free(w); ar.free(st); ar.free(st2); ar.free(isnew);
+    return nc;
+}
+
+// extended+i interpolation of level L into L.P
+void extpi(LevelSetup& L, int64_t nc, const scr_amg_opts& o, Arena& ar, hipStream_t s) {
+    const int64_t nr = L.A.nr;
+    const unsigned g = (unsigned)cdiv(nr, 256);
+    int32_t* cap = ar.make<int32_t>(nr + 1);
+    int32_t* off = ar.make<int32_t>(nr + 1);
+    extpi_cap_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, L.agg, cap);
+    check_launch("extpi cap");
+    const int64_t total = scan_i32(cap, off, nr, ar, s);
+    if (total >= (1LL << 31)) throw Error(SCR_E_OOM, "interpolation candidates exceed 2^31");
+    int32_t* hcol = ar.make<int32_t>(total + 1);
+    double* hw = ar.make<double>(total + 1);
+    int32_t* cnt = ar.make<int32_t>(nr + 1);
+    extpi_row_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.func, L.strong, L.agg, off, o.trunc, o.pmax, hcol, hw,
+                                  cnt);
+    check_launch("extpi rows");
+    DBsr P;
+    P.nr = nr; P.nc = nc; P.br = 1; P.bc = 1;
+    P.rp = ar.make<int32_t>(nr + 1);
+    P.nnzb = scan_i32(cnt, P.rp, nr, ar, s);
+    P.ci = ar.make<int32_t>(P.nnzb + 1);
+    P.v = ar.make<double>(P.nnzb + 1);
+    extpi_fill_k<<<g, 256, 0, s>>>(nr, off, hcol, hw, P.rp, P.ci, P.v);
+    check_launch("extpi fill");
+    ar.free(cap); ar.free(off); ar.free(hcol); ar.free(hw); ar.free(cnt);
+    L.P = P;
+}
+
+// every level of the classical hierarchy into H (H.L empty on entry; level 0 from A0)
+void setup_levels(ClassicalHier& H, const DBsr& A0, const scr_amg_opts& o, Arena& ar, hipStream_t s) {
+    int* err = ar.make<int>(1);
+    unsigned long long* lamd = ar.make<unsigned long long>(1);
+    {
+        LevelSetup l0;
+        const int b = A0.br;
+        const int64_t n = A0.nr * b;
+        l0.A = bsr_alloc(n, A0.nc * b, 1, 1, A0.nnzb * b * b, ar);
+        l0.b = 1; l0.k = 1;
+        l0.func = ar.make<uint8_t>(n > 0 ? n : 1);
+        if (A0.nr) to_scalar_k<<<(unsigned)cdiv(A0.nr, 256), 256, 0, s>>>(A0.nr, b, A0.rp, A0.ci, A0.v, l0.A.rp, l0.A.ci,
+                                                                          l0.A.v, l0.func);
+        else zero_dev(l0.A.rp, sizeof(int32_t), s);
+        check_launch("to_scalar");
+        H.L.push_back(l0);
+    }
+    for (int l = 0;; ++l) {
+        LevelSetup& L = H.L[l];
+        const int64_t nr = L.A.nr;
+        const unsigned g = (unsigned)cdiv(nr, 256);
+        L.Dinv = ar.make<double>(nr > 0 ? nr : 1);
+        level_diag(L, l, err, lamd, s);
+        if (nr <= o.coarse_max || l + 1 >= o.max_levels || l + 1 >= 16) break;
+        int32_t* tmap = ar.make<int32_t>(L.A.nnzb + 1);
+        zero_dev(err, sizeof(int), s);
+        tmap_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, tmap, err);
+        check_launch("transpose map");
+        if (read_flag(err, s)) throw Error(SCR_E_INVALID, "classical AMG needs a structurally symmetric matrix");
+        L.strong = ar.make<uint8_t>(L.A.nnzb + 1);
+        cl_strength_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.func, o.cl_theta, L.strong);
+        check_launch("classical strength");
+        const int64_t nc = hmis_split(L, tmap, o.seed, l, err, ar, s);
+        ar.free(tmap);
+        if (nc <= 0 || (double)nc > o.max_coarse_ratio * (double)nr) {
+            ar.free(L.agg); L.agg = nullptr;
+            ar.free(L.strong); L.strong = nullptr;
+            break;
+        }
+        L.nagg = nc;
+        extpi(L, nc, o, ar, s);
+        L.R = transpose(L.P, ar, s);
+        DBsr AP = spgemm(L.A, L.P, nullptr, ar, s);
+        LevelSetup N;
+        N.A = spgemm(L.R, AP, nullptr, ar, s);
+        bsr_release(AP, ar);
+        N.b = 1; N.k = 1;
+        N.func = ar.make<uint8_t>(nc);
+        coarse_func_k<<<g, 256, 0, s>>>(nr, L.agg, L.func, N.func);
+        check_launch("coarse functions");
+        H.L.push_back(N);   // invalidates L
+    }
+    coarse_inverse(H, err, ar, s);
+    ar.free(err);
+    ar.free(lamd);
+}
+
+void release_levels(ClassicalHier& H, Arena& ar) {
+    H.release_solve(ar);
+    for (LevelSetup& L : H.L) {
+        bsr_release(L.A, ar);
+        bsr_release(L.P, ar);
+        bsr_release(L.R, ar);
+        for (void* p : {(void*)L.agg, (void*)L.strong, (void*)L.Dinv, (void*)L.func}) ar.free(p);
+    }
+    H.L.clear();
+    if (H.cinv) { ar.free(H.cinv); H.cinv = nullptr; }
+}
+
+}  // namespace
+
+std::unique_ptr<Hierarchy> build_classical(const DBsr& A0, const scr_amg_opts& o, Arena& ar, hipStream_t s, bool three) {
+    if (A0.br != A0.bc || A0.br < 1 || A0.br > 6) throw Error(SCR_E_INVALID, "classical AMG: square blocks up to 6x6");
+    if (three && A0.br != 1) throw Error(SCR_E_INVALID, "three-column V-cycles need a scalar matrix");
+    std::unique_ptr<ClassicalHier> H(new ClassicalHier());
+    H->opts = o;
+    H->three = three;
+    DBsr& p0 = H->pattern0;
+    p0.nr = A0.nr; p0.nc = A0.nc; p0.br = A0.br; p0.bc = A0.bc; p0.nnzb = A0.nnzb;
+    p0.rp = ar.make<int32_t>(A0.nr + 1);
+    p0.ci = ar.make<int32_t>(A0.nnzb + 1);
+    copy_dev(p0.rp, A0.rp, (A0.nr + 1) * sizeof(int32_t), s);
+    copy_dev(p0.ci, A0.ci, A0.nnzb * sizeof(int32_t), s);
+    setup_levels(*H, A0, o, ar, s);
+    H->prepare(ar, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return std::unique_ptr<Hierarchy>(H.release());
+}
+
+void update_classical(Hierarchy& Hb, const double* vals0, Arena& ar, hipStream_t s) {
+    ClassicalHier& H = static_cast<ClassicalHier&>(Hb);
+    // the splitting and the interpolation depend on the values: set the hierarchy up again on
+    // the kept block pattern of level 0
+    release_levels(H, ar);
+    DBsr A0 = H.pattern0;
+    A0.v = const_cast<double*>(vals0);
+    setup_levels(H, A0, H.opts, ar, s);
+    H.prepare(ar, s);
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+}  // namespace scr

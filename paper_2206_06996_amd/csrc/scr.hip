@@ -364,6 +364,10 @@ void scr_default_amg_opts(scr_amg_opts* o) {
     o->max_coarse_ratio = 0.8;
     o->seed = 0;
     o->schur_diag = SCR_DIAG_A;
+    o->amg_type = SCR_AMG_SA;
+    o->cl_theta = 0.5;
+    o->trunc = 0.3;
+    o->pmax = 5;
 }
 
 void scr_default_solve_opts(scr_solve_opts* o) {
@@ -476,6 +480,11 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
             !(o.cheb_ratio > 1) || !(o.max_coarse_ratio > 0) || o.schur_cheb_degree < 0 ||
             !(o.schur_cheb_ratio == 0.0 || o.schur_cheb_ratio > 1))
             throw Error(SCR_E_INVALID, "AMG options out of range");
+        if (o.amg_type != SCR_AMG_SA && o.amg_type != SCR_AMG_CLASSICAL) throw Error(SCR_E_INVALID, "amg_type");
+        if (o.amg_type == SCR_AMG_CLASSICAL &&
+            (o.precision != SCR_FP64 || !(o.cl_theta > 0 && o.cl_theta <= 1) || !(o.trunc >= 0 && o.trunc < 1) ||
+             o.pmax < 1 || o.pmax > 16))
+            throw Error(SCR_E_INVALID, "classical AMG: FP64 only, 0 < cl_theta <= 1, 0 <= trunc < 1, 1 <= pmax <= 16");
         h->ar.reset(new Arena(&ctx->c, s));
         Arena& ar = *h->ar;
         const int64_t nb = K->n_brows;
@@ -919,6 +928,7 @@ scr_status scr_hier_level_copy(scr_handle* h, int which, int level, int field, v
             case 11: src = L.dead; bytes = L.nagg * L.k; break;
             case 12: src = L.Dinv; bytes = L.A.nr * L.b * L.b * sizeof(double); break;
             case 13: src = L.B; bytes = L.A.nr * L.b * L.k * sizeof(double); break;
+            case 15: src = L.func; bytes = L.A.nr; break;
             default: throw Error(SCR_E_INVALID, "unknown field");
         }
         if (!src) throw Error(SCR_E_INVALID, "field not present on this level");

@@ -108,6 +108,7 @@ struct LevelSetup {
     uint8_t* dead = nullptr;
     double* Dinv = nullptr;
     double* B = nullptr;
+    uint8_t* func = nullptr;         // classical AMG: the function (unknown) of each scalar row
     double lam = 0.0;
     // kept for the numeric re-setup: aggregate member lists and the pattern of A P (no values)
     int32_t *mrp = nullptr, *mem = nullptr;
@@ -154,6 +155,24 @@ void schur_update(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, in
 
 // values of the split of K into A, G, D, C (patterns already set up by split_blocks)
 void split_values(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, hipStream_t s);
+
+// classical AMG (classical.hip): the hierarchy of Sec. 5.2's settings for A0 (scalar, or b x b
+// blocks taken as b functions), and its set-up again for new level-0 values
+std::unique_ptr<Hierarchy> build_classical(const DBsr& A0, const scr_amg_opts& o, Arena& ar, hipStream_t s,
+                                           bool three);
+void update_classical(Hierarchy& H, const double* vals0, Arena& ar, hipStream_t s);
+
+// building blocks shared by the two AMG set-ups (amg.hip)
+DBsr bsr_alloc(int64_t nr, int64_t nc, int br, int bc, int64_t nnzb, Arena& ar);
+void bsr_release(DBsr& M, Arena& ar);
+// C = X Y on the structural pattern (rows with rowmask[i] == 0 left empty when rowmask is given);
+// each entry sums its products in the order of X's row
+DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hipStream_t s);
+DBsr transpose(const DBsr& M, Arena& ar, hipStream_t s);
+// D^-1 and lambda_hat of a level (err, lamd: one-element device scratch)
+void level_diag(LevelSetup& L, int l, int* err, unsigned long long* lamd, hipStream_t s);
+// explicit inverse of the coarsest level into H.cinv (fast, with a pivoted fallback)
+void coarse_inverse(Hierarchy& H, int* err, Arena& ar, hipStream_t s);
 
 // rigid-body modes (6 columns) of nb nodes from coordinates, shifted by their mean
 void rigid_modes(int64_t nb, const double* xyz, double* B, Arena& ar, hipStream_t s);

@@ -21,6 +21,7 @@ SCR_E_INVALID, SCR_E_OOM, SCR_E_HIP, SCR_E_BREAKDOWN, SCR_E_UNIMPLEMENTED, SCR_E
 SCR_SYSTEM, MESH_SYSTEM = 0, 1
 SCR_FP64, SCR_MIXED, SCR_MIXED_FP32_INNER = 0, 1, 2
 SCR_SMOOTH_JACOBI, SCR_SMOOTH_CHEBYSHEV = 0, 1
+SCR_AMG_SA, SCR_AMG_CLASSICAL = 0, 1
 
 EXPORTED = ["scr_default_amg_opts", "scr_default_solve_opts", "scr_ctx_create", "scr_ctx_destroy",
             "scr_ctx_bytes_in_use", "scr_handle_peak_bytes", "mesh_motion_solve_noalloc", "amg_setup", "amg_update", "scr_set_outlets", "scr_solve", "mesh_motion_solve", "scr_handle_destroy",
@@ -48,7 +49,8 @@ class AmgOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("theta", C.c_double), ("smoother", C.c_int), ("cheb_degree", C.c_int),
                 ("cheb_ratio", C.c_double), ("jacobi_sweeps", C.c_int), ("coarse_max", C.c_int),
                 ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
-                ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double)]
+                ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double),
+                ("amg_type", C.c_int), ("cl_theta", C.c_double), ("trunc", C.c_double), ("pmax", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -272,7 +274,7 @@ class Handle:
         return dict(nr=nr, b=b, k=k, nnzA=nnzA, nagg=nagg, nnzP=nnzP, nnzR=nnzR, ncoarse=ncoarse, lam=lam.value)
 
     FIELDS = {"A.rp": 0, "A.ci": 1, "A.v": 2, "agg": 3, "P.rp": 4, "P.ci": 5, "P.v": 6, "R.rp": 7, "R.ci": 8,
-              "R.v": 9, "strong": 10, "dead": 11, "Dinv": 12, "B": 13}
+              "R.v": 9, "strong": 10, "dead": 11, "Dinv": 12, "B": 13, "func": 15}
 
     def hier_level_copy(self, which: int, level: int, field: str) -> np.ndarray:
         i = self.hier_level_info(which, level)
@@ -283,7 +285,8 @@ class Handle:
                   6: ((i["nnzP"], i["b"], i["k"]), np.float64), 7: ((i["nagg"] + 1,), np.int32),
                   8: ((i["nnzR"],), np.int32), 9: ((i["nnzR"], i["k"], i["b"]), np.float64),
                   10: ((i["nnzA"],), np.uint8), 11: ((i["nagg"] * i["k"],), np.uint8),
-                  12: ((i["nr"], i["b"], i["b"]), np.float64), 13: ((i["nr"] * i["b"], i["k"]), np.float64)}
+                  12: ((i["nr"], i["b"], i["b"]), np.float64), 13: ((i["nr"] * i["b"], i["k"]), np.float64),
+                  15: ((i["nr"],), np.uint8)}
         shape, dt = shapes[f]
         out = np.empty(shape, dt)
         _check(lib().scr_hier_level_copy(self.ptr, which, level, f, out.ctypes.data_as(P)))

@@ -1,0 +1,168 @@
+"""GPU parity of the classical AMG (amg_type = SCR_AMG_CLASSICAL: the BoomerAMG settings of the
+paper's table in Sec. 5.2) with the oracle's (oracle.c, amg_type = 1), through the C ABI.
+
+Bars: every level's strength flags, C/F split (coarse indices), functions and the patterns of A,
+P and R bit-exact, and the values of P and of every coarse A bit-exact too (both sides evaluate
+the interpolation and the Galerkin sums in the same order without fused multiply-adds); one
+V-cycle within 1e-12 (the hybrid Gauss-Seidel sweeps sum each row in a different order); SCR and
+mesh solves with the FP64 iteration counts of the oracle, per-field errors within 1e-6 of the
+oracle's solution at 1e-12; amg_update equal to a fresh set-up on the new values.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.conftest import assert_fields
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def scr():
+    import paper_2206_06996_amd.scr as m
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(scr):
+    c = scr.Context(0)
+    yield c
+    c.destroy()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _gpu_scr(scr, ctx, s, val=None, **kw):
+    print(f"[gpu] classical amg_setup SCR n_b={s.n_b} {kw}", flush=True)
+    v = s.val if val is None else val
+    return scr.amg_setup(ctx, scr.SCR_SYSTEM, dev(s.rp), dev(s.ci), dev(v.reshape(-1)), dev(s.xyz.reshape(-1)),
+                         scr.amg_opts(amg_type=scr.SCR_AMG_CLASSICAL, **kw))
+
+
+def _gpu_mesh(scr, ctx, s, **kw):
+    print(f"[gpu] classical amg_setup MESH n={s.n_phys} {kw}", flush=True)
+    return scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(s.Lrp), dev(s.Lci), dev(s.Lval), None,
+                         scr.amg_opts(amg_type=scr.SCR_AMG_CLASSICAL, **kw))
+
+
+def _same(hg, which, ho):
+    ng = hg.hier_levels(which)
+    assert ng == ho.nlevels
+    for l in range(ng):
+        ig, io = hg.hier_level_info(which, l), ho.info(l)
+        for k in ("nr", "b", "k", "nnzA", "nagg", "nnzP", "nnzR", "ncoarse"):
+            assert ig[k] == io[k], (which, l, k, ig[k], io[k])
+        fields = ["A.rp", "A.ci", "A.v", "func"]
+        if l + 1 < ng:
+            fields += ["strong", "agg", "P.rp", "P.ci", "P.v", "R.rp", "R.ci", "R.v"]
+        for f in fields:
+            g, o = hg.hier_level_copy(which, l, f), ho.get(l, f)
+            assert np.array_equal(g.reshape(o.shape), o), (which, l, f)
+        if l + 1 < ng:
+            g, o = hg.hier_level_copy(which, l, "Dinv"), ho.get(l, "Dinv")
+            assert np.abs(g.reshape(o.shape) - o).max() <= 1e-15 * np.abs(o).max(), (which, l, "Dinv")
+    print(f"[gpu]   hierarchy {which}: {ng} levels, rows {[hg.hier_level_info(which, l)['nr'] for l in range(ng)]} "
+          f"bit-exact", flush=True)
+
+
+@pytest.mark.parametrize("case", ["small_fsi", "cfg0"])
+def test_scr_hierarchies_bit_exact(scr, ctx, case, small_fsi, cfg0):
+    s = {"small_fsi": small_fsi, "cfg0": cfg0}[case]
+    kw = dict(coarse_max=60) if case == "small_fsi" else {}
+    h = _gpu_scr(scr, ctx, s, **kw)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(amg_type=1, **kw))
+    _same(h, 0, o.amgA)
+    _same(h, 1, o.amgS)
+    h.destroy()
+
+
+@pytest.mark.parametrize("coarse_max", [64, 1024])
+def test_mesh_hierarchy_bit_exact_and_vcycle(scr, ctx, cfg0, coarse_max):
+    s = cfg0
+    h = _gpu_mesh(scr, ctx, s, coarse_max=coarse_max)
+    o = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, coarse_max=coarse_max))
+    _same(h, 2, o.amg)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1, 1, s.n_phys)
+    y = torch.empty(s.n_phys, dtype=torch.float64, device="cuda")
+    scr.scr_apply(h, "VL", dev(x), y)
+    ref = o.amg.vcycle(x)
+    err = np.linalg.norm(host(y) - ref) / np.linalg.norm(ref)
+    print(f"[gpu]   mesh V-cycle rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+    h.destroy()
+
+
+def test_vcycle_parity_scr(scr, ctx, small_fsi):
+    s = small_fsi
+    h = _gpu_scr(scr, ctx, s, coarse_max=60)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(amg_type=1, coarse_max=60))
+    rng = np.random.default_rng(4)
+    for op, n, hier in (("VA", 3 * s.n_b, o.amgA), ("VS", s.n_b, o.amgS)):
+        x = rng.uniform(-1, 1, n)
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        scr.scr_apply(h, op, dev(x), y)
+        ref = hier.vcycle(x)
+        err = np.linalg.norm(host(y) - ref) / np.linalg.norm(ref)
+        print(f"[gpu]   {op} rel err {err:.2e}", flush=True)
+        assert err <= 1e-12, op
+    h.destroy()
+
+
+def test_scr_and_mesh_solves_match_oracle(scr, ctx, cfg0):
+    s = cfg0
+    b = synth.rhs(21, 4 * s.n_b, s.mask)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(amg_type=1))
+    xo, rco, sto = o.solve(b, oracle.solve_opts(tol=1e-8))
+    xt, _, _ = o.solve(b, oracle.solve_opts(tol=1e-12, max_it=400))
+    h = _gpu_scr(scr, ctx, s)
+    x = torch.zeros(4 * s.n_b, dtype=torch.float64, device="cuda")
+    rc, st = scr.scr_solve(h, dev(b), x)
+    print(f"[gpu]   classical SCR: rc={rc} {({k: st[k] for k in ('outer_it', 'its_A', 'its_S', 'its_I')})} "
+          f"oracle {({k: sto[k] for k in ('outer_it', 'its_A', 'its_S', 'its_I')})}", flush=True)
+    assert rc == 0 and rco == 0
+    for k in ("outer_it", "its_A", "its_S", "its_I"):
+        assert st[k] == sto[k], k
+    assert_fields(host(x), xt, 1e-6, "classical SCR vs oracle at 1e-12")
+    h.destroy()
+    # mesh: three columns in one CG, each column's count equal to the oracle's
+    bm = synth.rhs(22, 3 * s.n_phys, np.repeat(s.Lmask, 3))
+    om = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1))
+    xmo, rcmo, itso, _ = om.solve(bm, tol=1e-10)
+    hm = _gpu_mesh(scr, ctx, s)
+    xm = torch.zeros(3 * s.n_phys, dtype=torch.float64, device="cuda")
+    rcm, stm = scr.mesh_motion_solve(hm, dev(bm), xm, scr.solve_opts(tol=1e-10))
+    print(f"[gpu]   classical mesh: rc={rcm} its={stm['mesh_its']} oracle {list(itso)}", flush=True)
+    assert rcm == 0 and list(stm["mesh_its"]) == list(itso)
+    err = np.linalg.norm(host(xm) - xmo) / np.linalg.norm(xmo)
+    assert err <= 1e-8
+    hm.destroy()
+
+
+def test_update_equals_fresh_setup_and_options(scr, ctx, small_fsi):
+    s = small_fsi
+    h = _gpu_scr(scr, ctx, s, coarse_max=60)
+    val2 = s.val.copy()
+    rng = np.random.default_rng(5)
+    val2[:, :3, :3] *= rng.uniform(0.5, 2.0, (val2.shape[0], 1, 1))
+    val2[:, :3, :3] = 0.5 * (val2[:, :3, :3] + val2[:, :3, :3].transpose(0, 2, 1))
+    scr.amg_update(h, dev(s.rp), dev(s.ci), dev(val2.reshape(-1)))
+    o2 = oracle.Scr(s.rp, s.ci, val2, s.xyz, oracle.amg_opts(amg_type=1, coarse_max=60))
+    _same(h, 0, o2.amgA)
+    _same(h, 1, o2.amgS)
+    h.destroy()
+    # classical is FP64 only; option ranges are checked
+    for kw in (dict(precision=1), dict(pmax=0), dict(pmax=17), dict(cl_theta=0.0), dict(trunc=1.0)):
+        with pytest.raises(scr.ScrError):
+            _gpu_scr(scr, ctx, s, **kw)
