@@ -64,6 +64,14 @@ def parse():
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturation")
+    ap.add_argument("--amg", action="append", default=[], metavar="KEY=VALUE",
+                    help="override an scr_amg_opts field for every hierarchy (repeatable), e.g. --amg theta=0.04")
+    ap.add_argument("--dump-levels", metavar="JSON", default=None,
+                    help="write the FP64 hierarchy sizes (AMG(A), AMG(S^), AMG(L)) and the first step's V-cycle "
+                         "counts to JSON (for --kernel-table)")
+    ap.add_argument("--kernel-table", nargs=2, metavar=("TRACE_DIR", "LEVELS_JSON"), default=None,
+                    help="CPU only: per-kernel table (time, algorithmic bytes, GB/s) from a rocprofv3 kernel trace "
+                         "of a one-step FP64 run and its --dump-levels file")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into profiles/ and exit")
     return ap.parse_args()
@@ -142,6 +150,162 @@ def pmc_summary(fetch_dir, write_dir, workload):
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def amg_overrides(args):
+    out = {}
+    for kv in args.amg:
+        k, v = kv.split("=", 1)
+        out[k] = float(v) if any(c in v for c in ".e") else int(v)
+    return out
+
+
+def dump_levels(path, scr, h, hm, s, first_stats):
+    """Sizes of every level of the three FP64 hierarchies and one step's V-cycle counts."""
+    out = {"n_b": int(s.n_b), "nnzb": int(s.nnzb), "n_phys": int(s.n_phys), "nnzL": int(s.Lci.size), "hier": {}}
+    for name, hh, which in (("A", h, 0), ("S", h, 1), ("L", hm, 2)):
+        out["hier"][name] = [hh.hier_level_info(which, l) for l in range(hh.hier_levels(which))]
+    if first_stats is not None:
+        st, stm = first_stats
+        out["step"] = {k: st[k] for k in ("outer_it", "its_A", "its_S", "its_I", "vcycles_A", "vcycles_S")}
+        out["step"]["mesh_its"] = list(stm["mesh_its"])
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+
+
+def _kt_bytes(levels):
+    """Grid size -> (algorithmic bytes, where) for every launch shape of the V-cycle, Krylov and
+    product kernels: each stored matrix value and index once, each vector it must read or write
+    once.  D^-1 is not counted (it follows from the diagonal block the smoother streams)."""
+    from math import ceil
+    H = levels["hier"]
+    shapes = {}
+
+    def add(key, grid, byts, where):
+        shapes.setdefault(key, {}).setdefault(grid, (byts, where))
+
+    def slice_grid(nr, b, wps):
+        nsl = ceil(nr / (64 // b))
+        spb = 1 if wps >= 4 else 4 // wps
+        return ceil(nsl / spb) * spb * wps * 64
+    for name, lv in H.items():
+        for l, L in enumerate(lv):
+            nr, b, k, nnz = L["nr"], L["b"], L["k"], L["nnzA"]
+            last = l + 1 == len(lv)
+            if last:
+                n = L["ncoarse"]
+                add("dense_mv_k<double>", ceil(n / 4) * 256, 8.0 * n * n + 16.0 * n, f"{name}{l} coarse")
+                add("dense_mv3_k<double>", ceil(n / 4) * 256, 8.0 * n * n + 48.0 * n, f"{name}{l} coarse")
+                continue
+            mat = nnz * (b * b * 8.0 + 4.0)
+            vec = b * 8.0
+            for rd in (0, 1):
+                for wd in (0, 1):
+                    byts = mat + nr * (4.0 + vec * (3 + rd + wd))
+                    zero = nr * (4.0 + vec * (2 + wd))
+                    if b == 3 and l == 0:
+                        g = ceil(ceil(nr / 64) / 4) * 256
+                        add(f"smooth_rl3_k<double,{rd},{wd},0>", g, byts, f"{name}{l}")
+                        add(f"smooth_rl3_k<double,0,{wd},1>", g, zero, f"{name}{l}")
+                    for w in (1, 2, 4, 8, 16):
+                        add(f"smooth_k<double,{b},{rd},{wd},0,{w}>", slice_grid(nr, b, w), byts, f"{name}{l}")
+                        add(f"smooth_k<double,{b},0,{wd},1,{w}>", slice_grid(nr, b, w), zero, f"{name}{l}")
+                        if b == 1:
+                            add(f"smooth3_k<double,{rd},{wd},0,{w}>", slice_grid(nr, 1, w),
+                                nnz * 12.0 + nr * (4.0 + 24.0 * (3 + rd + wd)), f"{name}{l}")
+                            add(f"smooth3_k<double,0,{wd},1,{w}>", slice_grid(nr, 1, w), nr * (4.0 + 24.0 * (2 + wd)),
+                                f"{name}{l}")
+            # products with A_l (residual y = b - A x: x, b read, y written)
+            for mode in (0, 1, 3):
+                nv = 2 if mode == 0 else 3
+                byts = mat + nr * (4.0 + vec * nv)
+                if b == 3 and l == 0:
+                    add(f"sell_mv_rl3_k<double,3,{mode}>", ceil(ceil(nr / 64) / 4) * 256, byts, f"{name}{l} A")
+                for w in (1, 2, 4, 8, 16):
+                    add(f"sell_mv_k<double,{b},{b},{mode},{w}>", slice_grid(nr, b, w), byts, f"{name}{l} A")
+                    if b == 1:
+                        add(f"sell_mv3_k<double,{mode},{w}>", slice_grid(nr, 1, w), nnz * 12.0 + nr * (4.0 + 24.0 * nv),
+                            f"{name}{l} A")
+            # prolongation y += P x (P: nr x nc blocks b x k; x coarse, y read and written)
+            nc, nnzp = L["nagg"], L["nnzP"]
+            pbytes = nnzp * (b * k * 8.0 + 4.0) + nc * k * 8.0 + nr * (4.0 + 2 * b * 8.0)
+            if b == 3 and l == 0:
+                add(f"sell_mv_rl3_k<double,{k},2>", ceil(ceil(nr / 64) / 4) * 256, pbytes, f"{name}{l} P")
+            for w in (1, 2, 4, 8, 16):
+                add(f"sell_mv_k<double,{b},{k},2,{w}>", slice_grid(nr, b, w), pbytes, f"{name}{l} P")
+                if b == 1:
+                    add(f"sell_mv3_k<double,2,{w}>", slice_grid(nr, 1, w),
+                        nnzp * 12.0 + nc * 24.0 + nr * (4.0 + 48.0), f"{name}{l} P")
+            # restriction y = R x (R: nc x nr blocks k x b)
+            rbytes = L["nnzR"] * (k * b * 8.0 + 4.0) + nr * b * 8.0 + nc * (4.0 + k * 8.0)
+            add(f"bsrt_mv_k<double,{k},{b}>", ceil(nc / 4) * 256, rbytes, f"{name}{l} R")
+            if b == 1:
+                add("bsrt_mv3_k<double>", ceil(nc / 4) * 256, L["nnzR"] * 12.0 + nr * 24.0 + nc * 28.0, f"{name}{l} R")
+    nb, nnzb = levels["n_b"], levels["nnzb"]
+    for mode in (0, 1):
+        add(f"sell_mv_split4_k<{mode}>", ceil(ceil(nb / 16) / 4) * 256,
+            nnzb * (16 * 8.0 + 4.0) + nb * (4.0 + 32.0 * (2 + mode)), "K")
+    return shapes
+
+
+def _kt_key(name):
+    """Normalised template key of a demangled kernel name (booleans as 0/1, no spaces)."""
+    import re
+    m = re.match(r"(?:void )?scr::(?:\(anonymous namespace\)::)?([A-Za-z0-9_]+)(<[^()]*>)?", name)
+    if not m:
+        return None
+    base, targs = m.group(1), (m.group(2) or "")
+    targs = targs.replace(" ", "").replace("true", "1").replace("false", "0")
+    return base + targs
+
+
+def kernel_table(trace_dir, levels_json):
+    import csv
+    import glob
+    levels = json.load(open(levels_json))
+    shapes = _kt_bytes(levels)
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *kernel_trace.csv under {trace_dir}")
+    agg = {}
+    total_ns = 0.0
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"]
+            ns = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+            grid = int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+            total_ns += ns
+            a = agg.setdefault(name, {"calls": 0, "ns": 0.0, "bytes": 0.0, "bytes_ns": 0.0, "where": set()})
+            a["calls"] += 1
+            a["ns"] += ns
+            key = _kt_key(name)
+            hit = shapes.get(key, {}).get(grid) if key else None
+            if hit:
+                a["bytes"] += hit[0]
+                a["bytes_ns"] += ns
+                a["where"].add(hit[1])
+    rows = sorted(agg.items(), key=lambda kv: -kv[1]["ns"])
+    print(f"Total kernel time {total_ns / 1e6:.1f} ms over {sum(a['calls'] for a in agg.values())} dispatches.\n")
+    print("| total ms | % | calls | avg us | alg. bytes / call | GB/s | of 8 TB/s | levels | kernel |")
+    print("|---:|---:|---:|---:|---:|---:|---:|---|---|")
+    tb = tt = 0.0
+    for name, a in rows[:25]:
+        cov = a["bytes_ns"] / a["ns"] if a["ns"] else 0.0
+        if a["bytes"] and cov > 0.999:
+            gbs = a["bytes"] / a["ns"]
+            b_call = f"{a['bytes'] / a['calls'] / 1e6:.1f} MB"
+            rate, frac = f"{gbs:.0f}", f"{gbs / HBM_PEAK_GBS:.2f}"
+        else:
+            b_call, rate, frac = "-", "-", "-"
+        short = name.replace("void ", "").split("(")[0][:70]
+        print(f"| {a['ns'] / 1e6:.2f} | {100 * a['ns'] / total_ns:.1f} | {a['calls']} | {a['ns'] / a['calls'] / 1e3:.2f} | "
+              f"{b_call} | {rate} | {frac} | {', '.join(sorted(a['where']))[:40]} | `{short}` |")
+    for name, a in agg.items():
+        if a["bytes"] and a["bytes_ns"] >= 0.999 * a["ns"]:
+            tb += a["bytes"]; tt += a["ns"]
+    print(f"\nKernels with a byte count (every dispatch matched to a level): {tt / 1e6:.1f} ms of {total_ns / 1e6:.1f} ms "
+          f"kernel time ({100 * tt / total_ns:.1f} %), {tb / 1e9:.2f} GB algorithmic, "
+          f"{tb / tt:.0f} GB/s = {tb / tt / HBM_PEAK_GBS:.3f} of 8 TB/s.")
 
 
 def load_reference(workload):
@@ -390,6 +554,9 @@ def log(msg, args=None):
 
 def main():
     args = parse()
+    if args.kernel_table:
+        kernel_table(*args.kernel_table)
+        return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args.workload)
         return
@@ -452,7 +619,7 @@ def main():
     results = {}
     x_first = {}
     for pi, prec in enumerate(precisions):
-        ao = scr.amg_opts(precision=pcode[prec], schur_diag=1 if args.precond == "simplec" else 0)
+        ao = scr.amg_opts(precision=pcode[prec], schur_diag=1 if args.precond == "simplec" else 0, **amg_overrides(args))
         so = scr.solve_opts(precond=scr.SCR_PRECOND_SCR if args.precond == "scr" else scr.SCR_PRECOND_SIMPLE)
         hm = scr.amg_setup(ctx, scr.MESH_SYSTEM, Lrp, Lci, Lval, None, ao)
         # the first pass warms up W steps; the later passes one step (the device and the caches are warm)
@@ -509,6 +676,8 @@ def main():
             upd_ms.append((time.perf_counter() - tu) * 1e3)
         peak = h.peak_bytes()
         fp = scr.footprint_estimate(scr.SCR_SYSTEM, s.n_b, s.nnzb, ao)
+        if args.dump_levels and prec == "fp64":
+            dump_levels(args.dump_levels, scr, h, hm, s, stats[0] if stats else None)
         h.destroy()
         log(f"[bench] {prec} amg_update: {' '.join(f'{v:.1f}' for v in upd_ms)} ms; handle peak {peak / 2**30:.2f} GiB, "
             f"footprint estimate {fp / 2**30:.2f} GiB", args)
@@ -550,7 +719,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f32/f64",
         "data": "synthetic (seeded tube mesh, seeded RHS)",
-        "config": {"workload": workload, "precision": main_prec, "tol": 1e-8, "precond": args.precond},
+        "config": {"workload": workload, "precision": main_prec, "tol": 1e-8, "precond": args.precond,
+                   **({"amg": amg_overrides(args)} if args.amg else {})},
     }
     for prec, rr in results.items():
         lat = np.array(rr["lat"]) * 1e3

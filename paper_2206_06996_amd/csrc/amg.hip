@@ -1349,13 +1349,14 @@ class HierT : public Hierarchy {
     }
 
     // algorithmic bytes of one smoother step with a matrix product: every stored block (values
-    // and column index) once, x once, the right-hand side, the output, d as used, and D^-1 where
-    // the kernel reads it (the FP32 block-row-lane kernels solve with the diagonal block they stream)
+    // and column index) once, a 4-byte row index per block row, x once, the right-hand side, the
+    // output and d as used.  D^-1 is not counted: it follows from the diagonal block the step
+    // streams anyway (the block-row-lane kernels solve with that block; the other smoothers read
+    // the stored inverse, which this count leaves out).
     double step_bytes(const LS& q, bool rd, bool wd) const {
         const double b = q.A.br, t = sizeof(T);
         double rows = (double)q.A.nr;
-        const double dinv = (q.A.rowlane && sizeof(T) == 4) ? 0.0 : b * b * t;
-        return (double)q.A.nnzb * (b * b * t + 4.0) + rows * (b * t * 3.0 + dinv + (rd ? b * t : 0.0) + (wd ? b * t : 0.0));
+        return (double)q.A.nnzb * (b * b * t + 4.0) + rows * (4.0 + b * t * (3.0 + (rd ? 1.0 : 0.0) + (wd ? 1.0 : 0.0)));
     }
 
     // smoothing sweeps from xin (nullptr = zero) into dst

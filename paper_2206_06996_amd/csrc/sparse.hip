@@ -476,8 +476,9 @@ static int waves_per_slice(const DSell<T>& A) {
 }
 
 // ---- block-row lanes (3xBC, BC = 3 or 6): r[0..2] = sum over the lane's slots of block * x[col]
-// 3x3: two slots per step (both slots' columns, then their 18 values and two x 3-vectors are
-// loaded before use); 3x6: one slot per step (18 values and an x 6-vector).  FP64 values are
+// Two slots per step (both slots' columns, then their values and x vectors are loaded before
+// use); FP32 3x6 takes one slot per step (18 values and an x 6-vector).  Measured on the refined
+// tube: two 3x6 FP64 slots per step make the level-0 prolongation 3.5 % faster.  FP64 values are
 // streamed with nontemporal loads (read once per call; measured: a gain in FP64, a loss in FP32).
 // CAP: also copy the 3x3 block of column irow (the diagonal block of the lane's row) into dg; the
 // first match is the stored block (padding slots that repeat the row's last column hold zeros and
@@ -486,7 +487,7 @@ template <typename T, int BC, bool CAP = false>
 __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, const int32_t* __restrict__ ci,
                                              const T* __restrict__ v, const T* __restrict__ x, T r[3],
                                              int32_t irow = -1, T* dg = nullptr) {
-    constexpr int U = BC == 3 ? 2 : 1, E = 3 * BC;
+    constexpr int U = (BC == 3 || sizeof(T) == 8) ? 2 : 1, E = 3 * BC;
     // the E values of slot tt (layout of rl_vidx): FP64 in 16-byte pairs, nontemporal
     auto load_slot = [&](int64_t tt, T (&vv)[E]) {
         if constexpr (sizeof(T) == 8) {
@@ -786,17 +787,17 @@ __global__ void __launch_bounds__(256) smooth_rl3_k(int64_t nslices, const int32
     int lane = threadIdx.x & (WAVE - 1);
     T r[3] = {0, 0, 0};
     const int64_t i = rowid[sl * WAVE + lane];
-    // FP32: the diagonal block is captured while the row streams by and D^-1 is not read (1.6 %
-    // faster mixed solves); FP64 keeps the stored inverse (the capture's registers cost a wave of
-    // occupancy per SIMD, which there outweighs the 72 bytes per row it saves)
-    constexpr bool CAP = sizeof(T) == 4;
+    // the diagonal block is captured while the row streams by and D^-1 is not read (72 bytes per
+    // row less; measured on the refined tube: the FP64 steps 6-11 % faster, FP32 mixed solves 1.6 %)
+    constexpr bool CAP = true;
     T dg[9];
     if (!ZERO) rowlane3_dot<T, 3, CAP>(off[sl], off[sl + 1], lane, ci, v, xin, r, (int32_t)i, dg);
     if (i < 0) return;
     T res[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) res[q] = b[i * 3 + q] - r[q];
-    // z = D^-1 res: the stored inverse, or the adjugate of the captured block over its determinant
+    // z = D^-1 res: the adjugate of the captured block over its determinant (the stored inverse in
+    // the first step, which has no matrix product)
     T z[3];
     if (ZERO || !CAP) {
         const T* Di = Dinv + i * 9;
