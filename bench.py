@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--load", type=float, default=0.8, help="Poisson arrival rate as a fraction of saturation")
+    ap.add_argument("--stepper", action="store_true",
+                    help="time steps of the device predictor multi-corrector (scr_step) on --workload cfg1/cfg2: "
+                         "seeded body force, --steps steps of dt = 1e-3 then one of 5e-4 (a numeric re-setup)")
     ap.add_argument("--amg", action="append", default=[], metavar="KEY=VALUE",
                     help="override an scr_amg_opts field for every hierarchy (repeatable), e.g. --amg theta=0.04")
     ap.add_argument("--dump-levels", metavar="JSON", default=None,
@@ -550,6 +553,59 @@ def dt_sweep(args):
                       "rows": rows}))
 
 
+def stepper_bench(args):
+    """Time steps of the segregated predictor multi-corrector (Sec. 3.5) on the device: each step
+    assembles the residual at the intermediate states, solves the corrector systems (scr_solve) and
+    the mesh motion (three-column CG), and updates every field; a new dt also re-assembles the four
+    operator forms and re-sets the hierarchies up numerically."""
+    import torch
+    import synth
+    import paper_2206_06996_amd.scr as scr
+    prec = {"fp64": scr.SCR_FP64, "mixed": scr.SCR_MIXED}.get(args.precision or "fp64", scr.SCR_FP64)
+    prm = {"cfg1": synth.cfg1_params, "cfg2": synth.cfg2_params}[args.workload]()
+    s = synth.generate(prm, tets=True)
+    free = synth.cfg1_params() if args.workload == "cfg1" else synth.cfg2_params()
+    free.apply_bc = 0
+    Lfull = synth.generate(free).Lval
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    solid = np.zeros(s.n_b, np.uint8)
+    solid[s.tv[s.tsolid.astype(bool)].reshape(-1)] = 1
+    ctx = scr.Context(0)
+    a = scr.scr_assembler_create(ctx, dev(s.tv), dev(s.tp), dev(s.tsolid), dev(s.rp), dev(s.ci), dev(s.xyz),
+                                 dev(s.mask), scr.tangent_params(**{k: getattr(prm, k) for k in (
+                                     "rho_f", "mu_f", "rho_s", "E_s", "nu_s", "dt", "rho_inf", "terms",
+                                     "vms_dt_coupling")}))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = scr.scr_stepper_create(ctx, a, dev(s.Lrp), dev(s.Lci), dev(s.Lval), dev(Lfull), dev(s.Lmask),
+                                dev(s.blk_of_phys), dev(solid), dev(s.xyz.reshape(-1)), 1e-3,
+                                amg=scr.amg_opts(precision=prec, **amg_overrides(args)))
+    create_ms = 1e3 * (time.perf_counter() - t0)
+    rows = []
+    dts = [1e-3] * max(args.steps, 1) + [5e-4]
+    for n, dt in enumerate(dts):
+        f = dev(synth.rhs(3000 + n, 3 * s.n_b))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc, gs = st.step(dt, f)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t1)
+        row = dict(step=n, dt=dt, rc=rc, ms=round(ms, 1), **{k: gs[k] for k in (
+            "correctors", "converged", "linear_its", "mesh_its", "resetups")}, res_ratio=gs["res"] / gs["res0"])
+        log(f"[stepper] {row}", args)
+        rows.append(row)
+    st.destroy()
+    a.destroy()
+    ctx.destroy()
+    plain = [r["ms"] for r in rows if not r["resetups"]]
+    print(json.dumps({"metric": "predictor multi-corrector time steps per second (device scr_step)",
+                      "value": round(1e3 / float(np.median(plain)), 4), "unit": "steps/s",
+                      "config": {"workload": f"{args.workload} tube ({s.n_b:,} block rows, {s.n_tets:,} tetrahedra) "
+                                             f"+ mesh motion ({s.n_phys:,} nodes)",
+                                 "precision": args.precision or "fp64", "dt": "1e-3, then 5e-4"},
+                      "create_ms": round(create_ms, 1), "rows": rows}))
+
+
 def log(msg, args=None):
     if not (args and args.quiet):
         print(msg, file=sys.stderr, flush=True)
@@ -572,6 +628,9 @@ def main():
         return
     if args.dt_sweep:
         dt_sweep(args)
+        return
+    if args.stepper:
+        stepper_bench(args)
         return
     import torch
     import synth
