@@ -37,7 +37,7 @@ class AmgOpts(C.Structure):
                 ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
                 ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double),
                 ("amg_type", C.c_int), ("cl_theta", C.c_double), ("trunc", C.c_double), ("pmax", C.c_int),
-                ("hmis_domain", C.c_int), ("gs_domain", C.c_int)]
+                ("hmis_domain", C.c_int), ("gs_domain", C.c_int), ("agg_levels", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -61,12 +61,12 @@ def amg_opts(**kw) -> AmgOpts:
     """Defaults: smoothed aggregation with theta=0.08 (halved per level), Chebyshev degree 4 on
     [lam/30, lam], coarse solve below 1024 unknowns, at most 10 levels, stop if coarsening is
     slower than 0.8.  amg_type=1: classical AMG with the paper's settings (strength 0.5, HMIS on
-    domains of 256 rows, extended+i truncated at 0.3 with at most 5 entries, hybrid Gauss-Seidel on
-    domains of 64 rows)."""
+    domains of 256 rows, aggressive two-stage coarsening on the first two levels, extended+i truncated
+    at 0.3 with at most 5 entries, hybrid Gauss-Seidel on domains of 64 rows)."""
     o = AmgOpts(theta=0.08, smoother=1, cheb_degree=4, cheb_ratio=30.0, jacobi_sweeps=2,
                 coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0,
                 schur_cheb_degree=8, schur_cheb_ratio=100.0, amg_type=0, cl_theta=0.5, trunc=0.3, pmax=5,
-                hmis_domain=256, gs_domain=64)
+                hmis_domain=256, gs_domain=64, agg_levels=2)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -144,6 +144,8 @@ def lib():
         L.orc_cl_extpi.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_double, C.c_int, P, P, P]
         L.orc_cl_extpi.restype = C.c_int64
         L.orc_cl_gs.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int, P, P, P]
+        L.orc_cl_second_stage.argtypes = [C.c_int64, P, P, P, P, P, P, P]
+        L.orc_cl_second_stage.restype = C.c_int64
         L.orc_cl_uniform.argtypes = [C.c_uint64, C.c_int, C.c_int64]
         L.orc_cl_uniform.restype = C.c_double
         _lib = L
@@ -226,6 +228,18 @@ def cl_hmis(rp, ci, S, domain=256, seed=0, level=0):
     if lib().orc_cl_hmis(nr, _p(rp), _p(ci), _p(S), domain, seed, level, _p(cf), _p(first)):
         raise ValueError("pattern is not structurally symmetric")
     return cf, first
+
+
+def cl_second_stage(rp, ci, S, cf):
+    """The second-stage graph of aggressive coarsening on the C points of cf: (rp, ci, edge flags)
+    in the numbering of the C points."""
+    rp = _c(rp, np.int32); ci = _c(ci, np.int32); S = _c(S, np.uint8); cf = _c(cf, np.int8)
+    n1 = int((cf == 1).sum())
+    grp = np.empty(n1 + 1, np.int32)
+    nnz = lib().orc_cl_second_stage(rp.size - 1, _p(rp), _p(ci), _p(S), _p(cf), _p(grp), None, None)
+    gci = np.empty(nnz, np.int32); gS = np.empty(nnz, np.uint8)
+    lib().orc_cl_second_stage(rp.size - 1, _p(rp), _p(ci), _p(S), _p(cf), _p(grp), _p(gci), _p(gS))
+    return grp, gci, gS
 
 
 def cl_uniform(seed, level, i):

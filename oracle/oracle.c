@@ -263,6 +263,7 @@ typedef struct {
     int pmax;            /* interpolation entries per row, 5 */
     int hmis_domain;     /* rows per HMIS domain */
     int gs_domain;       /* rows per hybrid Gauss-Seidel domain */
+    int agg_levels;      /* classical: levels coarsened aggressively (two stages), 2 */
 } amg_opts;
 
 #define MAXLEV 16
@@ -649,6 +650,13 @@ static int coarse_factor(amg* h) {
  * but the pmax largest in magnitude (ties to the lower column), and the kept entries are scaled
  * so that the row keeps its sum.  C points interpolate themselves with weight 1.
  *
+ * Aggressive coarsening (the first agg_levels levels): HMIS on S gives first-stage C points; HMIS
+ * again, on the graph in which C point i depends on C point j when a path of one or two strong
+ * dependencies leads from i to j, keeps a subset of them as the level's C points.  Interpolation in
+ * two stages of extended+i: P1 from the fine points onto the first-stage C points (on A), P2 from
+ * those onto the kept ones (on A1 = P1^T A P1 with its own strength), P = P1 P2, each truncated as
+ * above.
+ *
  * Hybrid Gauss-Seidel (Baker, Falgout, Kolev and Yang): Gauss-Seidel inside domains of `gs_dom`
  * consecutive rows, Jacobi between them: x_i = (b_i - sum_{j != i} a_ij x~_j) / a_ii with x~_j
  * the new value for j earlier in the same domain (forward sweep: j < i; backward: j > i) and the
@@ -1018,6 +1026,170 @@ static bsr* to_scalar(const bsr* A, uint8_t** func) {
     return S;
 }
 
+/* Aggressive coarsening, second stage: the graph on the first-stage C points (c1[i] = index among
+ * them, -1 for F points) in which C point i depends on C point j when j is reached from i by a
+ * path of one or two strong dependencies (S_i, or S_k for k in S_i).  Returned as a structurally
+ * symmetric pattern (the union of the edges and their reverses, columns ascending) with a flag per
+ * entry for the edges themselves. */
+static void second_stage_graph(int64_t n, const int32_t* rp, const int32_t* ci, const uint8_t* S, const int32_t* c1,
+                               int64_t n1, int32_t** grp, int32_t** gci, uint8_t** gS) {
+    int32_t** out = (int32_t**)calloc(n1 > 0 ? n1 : 1, sizeof(int32_t*));
+    int64_t* no = (int64_t*)calloc(n1 > 0 ? n1 : 1, sizeof(int64_t));
+    int64_t* nin = (int64_t*)calloc(n1 > 0 ? n1 : 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        if (c1[i] < 0) continue;
+        int64_t cap = 0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (S[q]) cap += 1 + (rp[ci[q] + 1] - rp[ci[q]]);
+        int32_t* e = (int32_t*)malloc(sizeof(int32_t) * (cap > 0 ? cap : 1));
+        int64_t m = 0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            if (!S[q]) continue;
+            int32_t k = ci[q];
+            if (c1[k] >= 0 && k != i) e[m++] = c1[k];
+            for (int32_t r = rp[k]; r < rp[k + 1]; ++r)
+                if (S[r] && c1[ci[r]] >= 0 && ci[r] != i) e[m++] = c1[ci[r]];
+        }
+        qsort(e, m, sizeof(int32_t), cmp_i32_asc);
+        int64_t u = 0;
+        for (int64_t t2 = 0; t2 < m; ++t2)
+            if (u == 0 || e[t2] != e[u - 1]) e[u++] = e[t2];
+        out[c1[i]] = e;
+        no[c1[i]] = u;
+    }
+    for (int64_t a = 0; a < n1; ++a)
+        for (int64_t t2 = 0; t2 < no[a]; ++t2) nin[out[a][t2]]++;
+    int32_t** in = (int32_t**)calloc(n1 > 0 ? n1 : 1, sizeof(int32_t*));
+    for (int64_t a = 0; a < n1; ++a) { in[a] = (int32_t*)malloc(sizeof(int32_t) * (nin[a] > 0 ? nin[a] : 1)); nin[a] = 0; }
+    for (int64_t a = 0; a < n1; ++a)
+        for (int64_t t2 = 0; t2 < no[a]; ++t2) { int32_t b = out[a][t2]; in[b][nin[b]++] = (int32_t)a; }
+    int32_t* rp2 = (int32_t*)calloc(n1 + 1, sizeof(int32_t));
+    int64_t tot = 0;
+    for (int64_t a = 0; a < n1; ++a) tot += no[a] + nin[a];
+    int32_t* ci2 = (int32_t*)malloc(sizeof(int32_t) * (tot > 0 ? tot : 1));
+    uint8_t* f2 = (uint8_t*)malloc(tot > 0 ? tot : 1);
+    int64_t p = 0;
+    for (int64_t a = 0; a < n1; ++a) {
+        /* merge the sorted out-list with the (ascending) in-list */
+        int64_t x = 0, y = 0;
+        while (x < no[a] || y < nin[a]) {
+            int32_t cx = x < no[a] ? out[a][x] : INT32_MAX, cy = y < nin[a] ? in[a][y] : INT32_MAX;
+            int32_t c = cx < cy ? cx : cy;
+            ci2[p] = c;
+            f2[p] = cx == c;
+            if (cx == c) ++x;
+            if (cy == c) ++y;
+            ++p;
+        }
+        rp2[a + 1] = (int32_t)p;
+        free(out[a]); free(in[a]);
+    }
+    free(out); free(in); free(no); free(nin);
+    *grp = rp2; *gci = ci2; *gS = f2;
+}
+
+/* Drop and rescale the entries of every row of P as for one interpolation row. */
+static bsr* truncate_matrix(const bsr* P, double trunc, int pmax) {
+    int32_t* col = (int32_t*)malloc(sizeof(int32_t) * (P->nnzb > 0 ? P->nnzb : 1));
+    double* w = (double*)malloc(sizeof(double) * (P->nnzb > 0 ? P->nnzb : 1));
+    int64_t* cnt = (int64_t*)calloc(P->nr > 0 ? P->nr : 1, sizeof(int64_t));
+    memcpy(col, P->ci, sizeof(int32_t) * P->nnzb);
+    memcpy(w, P->v, sizeof(double) * P->nnzb);
+    for (int64_t i = 0; i < P->nr; ++i)
+        cnt[i] = truncate_row(col + P->rp[i], w + P->rp[i], P->rp[i + 1] - P->rp[i], trunc, pmax);
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < P->nr; ++i) nnz += cnt[i];
+    bsr* T = bsr_new(P->nr, P->nc, 1, 1, nnz);
+    for (int64_t i = 0; i < P->nr; ++i) {
+        T->rp[i + 1] = T->rp[i] + (int32_t)cnt[i];
+        memcpy(T->ci + T->rp[i], col + P->rp[i], sizeof(int32_t) * cnt[i]);
+        memcpy(T->v + T->rp[i], w + P->rp[i], sizeof(double) * cnt[i]);
+    }
+    free(col); free(w); free(cnt);
+    return T;
+}
+
+/* One aggressive level: HMIS on S (first stage), HMIS on the second-stage graph of its C points,
+ * P = truncation of P1 P2 with P1 = extended+i of A onto the first-stage C points and P2 =
+ * extended+i of A1 = P1^T A P1 onto the second-stage C points.  Writes L->agg (coarse index of
+ * the final C points, -1 elsewhere) and L->P; returns the number of coarse points, or -1. */
+static int64_t aggressive_level(level* L, const amg_opts* o, int l) {
+    const bsr* A = L->A;
+    int64_t n = A->nr;
+    int8_t* cf = (int8_t*)malloc(n > 0 ? n : 1);
+    int8_t* first = (int8_t*)malloc(n > 0 ? n : 1);
+    if (orc_cl_hmis(n, A->rp, A->ci, L->strong, o->hmis_domain, o->seed, l, cf, first)) { free(cf); free(first); return -1; }
+    int32_t* c1 = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int64_t n1 = 0;
+    for (int64_t i = 0; i < n; ++i) c1[i] = cf[i] == 1 ? (int32_t)n1++ : -1;
+    int32_t *grp, *gci;
+    uint8_t* gS;
+    second_stage_graph(n, A->rp, A->ci, L->strong, c1, n1, &grp, &gci, &gS);
+    int8_t* cf2 = (int8_t*)malloc(n1 > 0 ? n1 : 1);
+    int8_t* first2 = (int8_t*)malloc(n1 > 0 ? n1 : 1);
+    int rc = orc_cl_hmis(n1, grp, gci, gS, o->hmis_domain, o->seed, l + 32, cf2, first2);
+    free(grp); free(gci); free(gS); free(first2); free(cf); free(first);
+    if (rc) { free(c1); free(cf2); return -1; }
+    int32_t* c2 = (int32_t*)malloc(sizeof(int32_t) * (n1 > 0 ? n1 : 1));
+    int64_t n2 = 0;
+    for (int64_t a = 0; a < n1; ++a) c2[a] = cf2[a] == 1 ? (int32_t)n2++ : -1;
+    free(cf2);
+    L->agg = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) L->agg[i] = c1[i] >= 0 ? c2[c1[i]] : -1;
+    if (n2 <= 0) { free(c1); free(c2); return n2; }
+    bsr* P1 = extpi(n, n1, A->rp, A->ci, A->v, L->func, L->strong, c1, o->trunc, o->pmax);
+    bsr* R1 = transpose(P1);
+    bsr* AP1 = spgemm(A, P1);
+    bsr* A1 = spgemm(R1, AP1);
+    bsr_free(R1); bsr_free(AP1);
+    uint8_t* f1 = (uint8_t*)malloc(n1 > 0 ? n1 : 1);
+    for (int64_t i = 0; i < n; ++i)
+        if (c1[i] >= 0) f1[c1[i]] = L->func[i];
+    uint8_t* S1 = (uint8_t*)malloc(A1->nnzb > 0 ? A1->nnzb : 1);
+    orc_cl_strength(n1, A1->rp, A1->ci, A1->v, f1, o->cl_theta, S1);
+    bsr* P2 = extpi(n1, n2, A1->rp, A1->ci, A1->v, f1, S1, c2, o->trunc, o->pmax);
+    bsr* P12 = spgemm(P1, P2);
+    L->P = truncate_matrix(P12, o->trunc, o->pmax);
+    bsr_free(P1); bsr_free(A1); bsr_free(P2); bsr_free(P12);
+    free(S1); free(f1); free(c1); free(c2);
+    return n2;
+}
+
+/* One standard level: HMIS on S and extended+i onto its C points.  Writes L->agg and L->P (P only
+ * when there are C points); returns the number of coarse points, or -1. */
+static int64_t standard_level(level* L, const amg_opts* o, int l) {
+    const bsr* A = L->A;
+    int64_t n = A->nr;
+    int8_t* cf = (int8_t*)malloc(n > 0 ? n : 1);
+    int8_t* first = (int8_t*)malloc(n > 0 ? n : 1);
+    if (orc_cl_hmis(n, A->rp, A->ci, L->strong, o->hmis_domain, o->seed, l, cf, first)) { free(cf); free(first); return -1; }
+    free(first);
+    L->agg = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; ++i) L->agg[i] = cf[i] == 1 ? (int32_t)nc++ : -1;
+    free(cf);
+    if (nc > 0) L->P = extpi(n, nc, A->rp, A->ci, A->v, L->func, L->strong, L->agg, o->trunc, o->pmax);
+    return nc;
+}
+
+/* test entry: the second-stage graph of a split (cf: 1 C, -1 F); grp (n1 + 1) always, gci/gS
+ * (entries) when not NULL; returns the number of entries */
+int64_t orc_cl_second_stage(int64_t n, const int32_t* rp, const int32_t* ci, const uint8_t* S, const int8_t* cf,
+                            int32_t* grp, int32_t* gci, uint8_t* gS) {
+    int32_t* c1 = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int64_t n1 = 0;
+    for (int64_t i = 0; i < n; ++i) c1[i] = cf[i] == 1 ? (int32_t)n1++ : -1;
+    int32_t *r2, *c2;
+    uint8_t* f2;
+    second_stage_graph(n, rp, ci, S, c1, n1, &r2, &c2, &f2);
+    memcpy(grp, r2, sizeof(int32_t) * (n1 + 1));
+    if (gci) memcpy(gci, c2, sizeof(int32_t) * r2[n1]);
+    if (gS) memcpy(gS, f2, r2[n1]);
+    int64_t nnz = r2[n1];
+    free(r2); free(c2); free(f2); free(c1);
+    return nnz;
+}
+
 static amg* amg_build_classical(const bsr* A0, const amg_opts* o) {
     amg* h = (amg*)calloc(1, sizeof(amg));
     h->o = *o;
@@ -1033,22 +1205,14 @@ static amg* amg_build_classical(const bsr* A0, const amg_opts* o) {
         if (n <= o->coarse_max || l + 1 >= o->max_levels || l + 1 >= MAXLEV) break;
         L->strong = (uint8_t*)malloc(L->A->nnzb > 0 ? L->A->nnzb : 1);
         orc_cl_strength(n, L->A->rp, L->A->ci, L->A->v, L->func, o->cl_theta, L->strong);
-        int8_t* cf = (int8_t*)malloc(n > 0 ? n : 1);
-        int8_t* first = (int8_t*)malloc(n > 0 ? n : 1);
-        if (orc_cl_hmis(n, L->A->rp, L->A->ci, L->strong, o->hmis_domain, o->seed, l, cf, first)) {
-            free(cf); free(first); orc_amg_free(h); return NULL;
-        }
-        free(first);
-        L->agg = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
-        int64_t nc = 0;
-        for (int64_t i = 0; i < n; ++i) L->agg[i] = cf[i] == 1 ? (int32_t)nc++ : -1;
-        free(cf);
-        if (nc <= 0 || (double)nc > o->max_coarse_ratio * (double)n) {
+        int64_t nc = l < o->agg_levels ? aggressive_level(L, o, l) : standard_level(L, o, l);
+        if (nc < 0) { orc_amg_free(h); return NULL; }
+        if (nc == 0 || (double)nc > o->max_coarse_ratio * (double)n) {
             free(L->agg); L->agg = NULL; free(L->strong); L->strong = NULL;
+            bsr_free(L->P); L->P = NULL;
             break;
         }
         L->n_agg = nc;
-        L->P = extpi(n, nc, L->A->rp, L->A->ci, L->A->v, L->func, L->strong, L->agg, o->trunc, o->pmax);
         L->R = transpose(L->P);
         bsr* AP = spgemm(L->A, L->P);
         level* N = &h->L[l + 1];

@@ -12,6 +12,9 @@ paper's table in Sec. 5.2), against results fixed by the definitions and textboo
   two F points in a row (the distance-two case, weights 2/3 and 1/3); rows of interpolation sum to
   one where the matrix's rows sum to zero (also after truncation); truncation and the five-entry
   cap on a star with known weights;
+* aggressive coarsening: the second-stage graph equals the brute-force paths of length one or two
+  among the C points (boolean matrix products); on the 1-D Laplacian two stages keep every fourth
+  point and the two-stage interpolation is linear between them;
 * hybrid Gauss-Seidel: one domain is Gauss-Seidel (triangular solves), one-row domains are Jacobi,
   general domains are block triangular solves with the previous iterate outside the block;
 * the hierarchy: A_{l+1} = P^T A_l P in dense arithmetic, C rows of P the identity, the symmetry
@@ -201,6 +204,81 @@ def test_truncation_and_cap_on_a_star():
     P = _P(A, cf, trunc=0.3, pmax=3, theta=0.05)
     kept = np.zeros(c.size, bool); kept[[0, 2, 5]] = True
     assert np.allclose(P[0], np.where(kept, c / c[kept].sum(), 0.0), rtol=1e-15, atol=0)
+
+
+# ------------------------------------------------------------------------------ aggressive coarsening
+@pytest.mark.parametrize("which", ["lap2d", "mesh"])
+def test_second_stage_graph_is_paths_of_length_two(which):
+    if which == "lap2d":
+        A = _lap2d(10, 0.3)
+    else:
+        s = synth.generate(synth.cfg0_params())
+        A = _csr(sp.csr_matrix((s.Lval, s.Lci, s.Lrp)))
+    S = _strength(A)
+    cf, _ = oracle.cl_hmis(A.indptr, A.indices, S, domain=64)
+    grp, gci, gS = oracle.cl_second_stage(A.indptr, A.indices, S, cf)
+    D = sp.csr_matrix((S.astype(np.int64), A.indices, A.indptr), shape=A.shape)
+    D.eliminate_zeros()
+    C = np.nonzero(cf > 0)[0]
+    reach = (D + D @ D).tocsr()[C][:, C].toarray() > 0     # paths of one or two strong dependencies
+    E = reach.copy()
+    np.fill_diagonal(E, False)
+    n1 = C.size
+    G = np.zeros((n1, n1), bool)
+    F = np.zeros((n1, n1), bool)
+    rows = np.repeat(np.arange(n1), np.diff(grp))
+    G[rows, gci] = True
+    F[rows, gci] = gS.astype(bool)
+    assert np.array_equal(F, E)                      # the edges
+    assert np.array_equal(G, E | E.T)                # the symmetric pattern
+    assert all(np.all(np.diff(gci[grp[i]:grp[i + 1]]) > 0) for i in range(n1))
+
+
+def test_aggressive_1d_keeps_every_fourth_point_and_interpolates_linearly():
+    n = 31
+    A = _lap1d(n)
+    B = np.ones((n, 1))
+    h = oracle.Amg(A.indptr, A.indices, A.data, B,
+                   oracle.amg_opts(amg_type=1, agg_levels=1, coarse_max=4, hmis_domain=1 << 20, trunc=0.0, pmax=0))
+    agg = h.get(0, "agg")
+    C = np.nonzero(agg >= 0)[0]
+    assert np.array_equal(C, np.arange(3, n, 4))
+    i = h.info(0)
+    P = sp.csr_matrix((h.get(0, "P.v").ravel(), h.get(0, "P.ci"), h.get(0, "P.rp")), shape=(n, i["nagg"])).toarray()
+    x = np.arange(1, n + 1, dtype=float)           # node positions; zero Dirichlet values at 0 and n + 1
+    lin = np.interp(x, np.concatenate([[0.0], x[C], [n + 1.0]]), np.concatenate([[0.0], x[C], [0.0]]))
+    assert np.allclose(P @ x[C], lin, rtol=0, atol=1e-13)
+    # the default truncation keeps the same rows here (weights 3/4 and 1/4 pass 0.3 of the largest)
+    h2 = oracle.Amg(A.indptr, A.indices, A.data, B,
+                    oracle.amg_opts(amg_type=1, agg_levels=1, coarse_max=4, hmis_domain=1 << 20))
+    P2 = sp.csr_matrix((h2.get(0, "P.v").ravel(), h2.get(0, "P.ci"), h2.get(0, "P.rp")), shape=(n, i["nagg"])).toarray()
+    assert np.allclose(P2, P, rtol=0, atol=1e-14)
+
+
+def test_aggressive_levels_coarsen_faster_and_keep_galerkin():
+    s = synth.generate(synth.cfg0_params())
+    h0 = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, agg_levels=0, coarse_max=64)).amg
+    m2 = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, agg_levels=2, coarse_max=64))
+    h2 = m2.amg
+    r0 = [h0.info(l)["nr"] for l in range(h0.nlevels)]
+    r2 = [h2.info(l)["nr"] for l in range(h2.nlevels)]
+    assert r2[1] < r0[1] / 2 and r2[2] < r0[2]
+    op0 = sum(h0.info(l)["nnzA"] for l in range(h0.nlevels))
+    op2 = sum(h2.info(l)["nnzA"] for l in range(h2.nlevels))
+    assert op2 < op0                                   # lower operator complexity
+    for l in range(2):
+        i = h2.info(l)
+        A = sp.csr_matrix((h2.get(l, "A.v").ravel(), h2.get(l, "A.ci"), h2.get(l, "A.rp")), shape=(i["nr"],) * 2)
+        P = sp.csr_matrix((h2.get(l, "P.v").ravel(), h2.get(l, "P.ci"), h2.get(l, "P.rp")), shape=(i["nr"], i["nagg"]))
+        j = h2.info(l + 1)
+        Ac = sp.csr_matrix((h2.get(l + 1, "A.v").ravel(), h2.get(l + 1, "A.ci"), h2.get(l + 1, "A.rp")),
+                           shape=(j["nr"],) * 2).toarray()
+        ref = P.toarray().T @ A.toarray() @ P.toarray()
+        assert np.abs(Ac - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert (np.diff(P.indptr) <= 5).all()
+    b = synth.rhs(2, 3 * s.n_phys, np.repeat(s.Lmask, 3))
+    x, rc, its, rel = m2.solve(b, tol=1e-10)
+    assert rc == 0 and its.max() <= 40
 
 
 # ------------------------------------------------------------------------------ hybrid GS
