@@ -114,11 +114,17 @@ typedef struct {
                                   domains of 64 rows (one wavefront each), Jacobi between them.
                                   Galerkin coarse operators, direct coarsest solve.  FP64 only; the
                                   near-null space, theta, the smoother and Chebyshev fields are not
-                                  used; amg_update sets the hierarchy up again.  Aggressive
-                                  coarsening (the table's last row) is not implemented. */
+                                  used; amg_update sets the hierarchy up again.  The first
+                                  agg_levels levels coarsen aggressively (two stages): HMIS gives
+                                  first-stage C points; a second HMIS runs on the graph that joins
+                                  two of them when one reaches the other through one or two strong
+                                  dependencies; P is the truncated product P1 P2 of the extended+i
+                                  interpolation P1 onto the first-stage C points and the extended+i
+                                  interpolation P2 of P1^T A P1 onto the second-stage ones. */
     double cl_theta;           /* classical strength threshold, 0.5 */
     double trunc;              /* interpolation truncation factor, 0.3 */
     int pmax;                  /* interpolation entries per row, 5 (1..16) */
+    int agg_levels;            /* classical: levels coarsened aggressively, 2 (0 = none; <= 16) */
 } scr_amg_opts;
 
 /* Krylov options.  Defaults: tol 1e-8 (outer), tol_A = tol_S = tol_I = 1e-3 and 200

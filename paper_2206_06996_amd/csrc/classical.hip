@@ -266,7 +266,7 @@ __global__ void extpi_cap_k(int64_t nr, const int32_t* __restrict__ rp, const in
         const int32_t j = ci[q];
         c += cidx[j] >= 0 ? 1 : rp[j + 1] - rp[j];
     }
-    cap[i] = (int32_t)(c < (1 << 30) ? c : (1 << 30));
+    cap[i] = (int32_t)(c < INT32_MAX ? c : INT32_MAX);
 }
 
 __device__ __forceinline__ bool opposite(double a, double d) { return (a > 0.0 && d < 0.0) || (a < 0.0 && d > 0.0); }
@@ -296,6 +296,43 @@ __device__ __forceinline__ int64_t in_hat(const int32_t* hat, int64_t m, int32_t
         else hi = mid;
     }
     return (lo < m && hat[lo] == key) ? lo : -1;
+}
+
+// Truncation of one interpolation row (columns ascending, non-negative): entries below trunc times
+// the largest magnitude dropped (and exact zeros), then all but the pmax largest (lower column on
+// ties), then the kept entries scaled to the row's original sum.  Compacts in place; returns the
+// kept count.  The sums run in column order, as in the definition.
+__device__ int64_t truncate_seg(int32_t* col, double* w, int64_t m, double trunc, int pmax) {
+    double mx = 0.0, all = 0.0;
+    for (int64_t t = 0; t < m; ++t) {
+        all = all + w[t];
+        if (fabs(w[t]) > mx) mx = fabs(w[t]);
+    }
+    int64_t k = 0;
+    for (int64_t t = 0; t < m; ++t)
+        if (w[t] != 0.0 && fabs(w[t]) >= trunc * mx) { col[k] = col[t]; w[k] = w[t]; ++k; }
+    if (k > pmax) {
+        // the pmax largest magnitudes, lower column first on ties: mark them by negating the column
+        for (int s = 0; s < pmax; ++s) {
+            int64_t b = -1;
+            for (int64_t t = 0; t < k; ++t) {
+                if (col[t] < 0) continue;
+                if (b < 0 || fabs(w[t]) > fabs(w[b])) b = t;
+            }
+            col[b] = -1 - col[b];
+        }
+        int64_t k2 = 0;
+        for (int64_t t = 0; t < k; ++t)
+            if (col[t] < 0) { col[k2] = -1 - col[t]; w[k2] = w[t]; ++k2; }
+        k = k2;
+    }
+    double kept = 0.0;
+    for (int64_t t = 0; t < k; ++t) kept = kept + w[t];
+    if (kept != 0.0) {
+        const double sc = all / kept;
+        for (int64_t t = 0; t < k; ++t) w[t] = w[t] * sc;
+    }
+    return k;
 }
 
 // extended+i row i into its scratch segment [off_i, off_i + cap_i): the kept coarse columns
@@ -363,36 +400,7 @@ __global__ void extpi_row_k(int64_t nr, const int32_t* __restrict__ rp, const in
     }
     if (m == 0 || diag == 0.0) { cnt[i] = 0; return; }
     for (int64_t t = 0; t < m; ++t) w[t] = -w[t] / diag;
-    // truncation: relative to the largest magnitude, then the pmax largest, then the row sum
-    double mx = 0.0, all = 0.0;
-    for (int64_t t = 0; t < m; ++t) {
-        all = all + w[t];
-        if (fabs(w[t]) > mx) mx = fabs(w[t]);
-    }
-    int64_t k = 0;
-    for (int64_t t = 0; t < m; ++t)
-        if (w[t] != 0.0 && fabs(w[t]) >= trunc * mx) { hat[k] = hat[t]; w[k] = w[t]; ++k; }
-    if (k > pmax) {
-        // the pmax largest magnitudes, lower column first on ties: mark them by negating the column
-        for (int s = 0; s < pmax; ++s) {
-            int64_t b = -1;
-            for (int64_t t = 0; t < k; ++t) {
-                if (hat[t] < 0) continue;
-                if (b < 0 || fabs(w[t]) > fabs(w[b])) b = t;
-            }
-            hat[b] = -1 - hat[b];
-        }
-        int64_t k2 = 0;
-        for (int64_t t = 0; t < k; ++t)
-            if (hat[t] < 0) { hat[k2] = -1 - hat[t]; w[k2] = w[t]; ++k2; }
-        k = k2;
-    }
-    double kept = 0.0;
-    for (int64_t t = 0; t < k; ++t) kept = kept + w[t];
-    if (kept != 0.0) {
-        const double sc = all / kept;
-        for (int64_t t = 0; t < k; ++t) w[t] = w[t] * sc;
-    }
+    const int64_t k = truncate_seg(hat, w, m, trunc, pmax);
     for (int64_t t = 0; t < k; ++t) hat[t] = cidx[hat[t]];
     cnt[i] = (int32_t)k;
 }
@@ -407,6 +415,107 @@ __global__ void extpi_fill_k(int64_t nr, const int32_t* __restrict__ off, const 
         pci[prp[i] + t] = hcol[off[i] + t];
         pv[prp[i] + t] = hw[off[i] + t];
     }
+}
+
+// truncation of every row of a product P = P1 P2 in place (kept entries at the front of each row)
+__global__ void trunc_rows_k(int64_t nr, const int32_t* __restrict__ rp, int32_t* __restrict__ ci,
+                             double* __restrict__ v, double trunc, int pmax, int32_t* __restrict__ cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    cnt[i] = (int32_t)truncate_seg(ci + rp[i], v + rp[i], rp[i + 1] - rp[i], trunc, pmax);
+}
+
+// ---- aggressive coarsening: the second-stage graph on the first-stage C points
+__global__ void fine_of_k(int64_t nr, const int32_t* __restrict__ c1, int32_t* __restrict__ fine_of) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr && c1[i] >= 0) fine_of[c1[i]] = (int32_t)i;
+}
+// upper bound of the out-edges of C point a: one per strong dependency and its row
+__global__ void ss_cap_k(int64_t n1, const int32_t* __restrict__ fine_of, const int32_t* __restrict__ rp,
+                         const int32_t* __restrict__ ci, const uint8_t* __restrict__ S, int32_t* __restrict__ cap) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n1) return;
+    const int64_t i = fine_of[a];
+    int64_t c = 0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+        if (S[q]) c += 1 + (rp[ci[q] + 1] - rp[ci[q]]);
+    cap[a] = (int32_t)(c < INT32_MAX ? c : INT32_MAX);
+}
+// the out-edges of a (C points reached by one or two strong dependencies), sorted and unique
+__global__ void ss_out_k(int64_t n1, const int32_t* __restrict__ fine_of, const int32_t* __restrict__ rp,
+                         const int32_t* __restrict__ ci, const uint8_t* __restrict__ S, const int32_t* __restrict__ c1,
+                         const int32_t* __restrict__ off, int32_t* __restrict__ buf, int32_t* __restrict__ no) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n1) return;
+    const int64_t i = fine_of[a];
+    int32_t* e = buf + off[a];
+    int64_t m = 0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        if (!S[q]) continue;
+        const int32_t k = ci[q];
+        if (c1[k] >= 0 && k != i) e[m++] = c1[k];
+        for (int32_t r = rp[k]; r < rp[k + 1]; ++r)
+            if (S[r] && c1[ci[r]] >= 0 && ci[r] != i) e[m++] = c1[ci[r]];
+    }
+    heap_sort(e, m);
+    int64_t u = 0;
+    for (int64_t t = 0; t < m; ++t)
+        if (u == 0 || e[t] != e[u - 1]) e[u++] = e[t];
+    no[a] = (int32_t)u;
+}
+__global__ void ss_indeg_k(int64_t n1, const int32_t* __restrict__ off, const int32_t* __restrict__ buf,
+                           const int32_t* __restrict__ no, int32_t* __restrict__ nin) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n1) return;
+    for (int32_t t = 0; t < no[a]; ++t) atomicAdd(&nin[buf[off[a] + t]], 1);
+}
+__global__ void ss_in_fill_k(int64_t n1, const int32_t* __restrict__ off, const int32_t* __restrict__ buf,
+                             const int32_t* __restrict__ no, const int32_t* __restrict__ inoff, int32_t* __restrict__ cur,
+                             int32_t* __restrict__ inbuf) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n1) return;
+    for (int32_t t = 0; t < no[a]; ++t) {
+        const int32_t b = buf[off[a] + t];
+        inbuf[inoff[b] + atomicAdd(&cur[b], 1)] = (int32_t)a;
+    }
+}
+// the in-lists sorted (their fill order came from atomics)
+__global__ void ss_in_sort_k(int64_t n1, const int32_t* __restrict__ inoff, const int32_t* __restrict__ nin,
+                             int32_t* __restrict__ inbuf) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n1) heap_sort(inbuf + inoff[b], nin[b]);
+}
+// row a of the symmetric pattern: the merge of its out- and in-lists, flag = out-edge
+// (FILL = false: count only)
+template <bool FILL>
+__global__ void ss_merge_k(int64_t n1, const int32_t* __restrict__ off, const int32_t* __restrict__ buf,
+                           const int32_t* __restrict__ no, const int32_t* __restrict__ inoff,
+                           const int32_t* __restrict__ inbuf, const int32_t* __restrict__ nin,
+                           const int32_t* __restrict__ rp2, int32_t* __restrict__ ci2, uint8_t* __restrict__ f2,
+                           int32_t* __restrict__ cnt) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n1) return;
+    const int32_t* o = buf + off[a];
+    const int32_t* in = inbuf + inoff[a];
+    int32_t x = 0, y = 0, p = 0;
+    while (x < no[a] || y < nin[a]) {
+        const int32_t cx = x < no[a] ? o[x] : INT32_MAX, cy = y < nin[a] ? in[y] : INT32_MAX;
+        const int32_t c = cx < cy ? cx : cy;
+        if (FILL) {
+            ci2[rp2[a] + p] = c;
+            f2[rp2[a] + p] = cx == c;
+        }
+        if (cx == c) ++x;
+        if (cy == c) ++y;
+        ++p;
+    }
+    if (!FILL) cnt[a] = p;
+}
+// coarse index of the level: the second-stage index of the first-stage C points that stayed C
+__global__ void agg_compose_k(int64_t nr, const int32_t* __restrict__ c1, const int32_t* __restrict__ c2,
+                              int32_t* __restrict__ agg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) agg[i] = c1[i] >= 0 ? c2[c1[i]] : -1;
 }
 
 // ------------------------------------------------------------------ hybrid Gauss-Seidel
@@ -560,57 +669,69 @@ int read_flag(const int* p, hipStream_t s) {
     return v;
 }
 
-// C/F split of level L (strength flags set): HMIS; returns the number of C points, coarse
-// indices in L.agg
-int64_t hmis_split(LevelSetup& L, const int32_t* tmap, uint64_t seed, int level, int* err, Arena& ar, hipStream_t s) {
-    const int64_t nr = L.A.nr;
-    const unsigned g = (unsigned)cdiv(nr, 256);
-    int8_t* first = ar.make<int8_t>(nr);
-    hmis_first_k<<<(unsigned)cdiv(nr, HMIS_DOM), HMIS_DOM, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, tmap, first);
-    check_launch("hmis first pass");
-    double* w = ar.make<double>(nr);
-    int8_t* st = ar.make<int8_t>(nr);
-    int8_t* st2 = ar.make<int8_t>(nr);
-    uint8_t* isnew = ar.make<uint8_t>(nr);
-    pmis_init_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, tmap, first, seed, level, w, st, isnew);
-    check_launch("pmis init");
-    for (int round = 0;; ++round) {
-        if (round > 100000) throw Error(SCR_E_HIP, "PMIS did not terminate");
-        zero_dev(err, sizeof(int), s);
-        pmis_f_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, isnew, st, st2, err);
-        check_launch("pmis f");
-        std::swap(st, st2);
-        if (read_flag(err, s) == 0) break;
-        pmis_c_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, tmap, w, st, isnew);
-        pmis_apply_k<<<g, 256, 0, s>>>(nr, isnew, st);
-        check_launch("pmis c");
+// transpose map of a structurally symmetric pattern (throws otherwise)
+int32_t* transpose_map(int64_t nr, const int32_t* rp, const int32_t* ci, int64_t nnz, int* err, Arena& ar, hipStream_t s) {
+    int32_t* tmap = ar.make<int32_t>(nnz + 1);
+    zero_dev(err, sizeof(int), s);
+    if (nr) tmap_k<<<(unsigned)cdiv(nr, 256), 256, 0, s>>>(nr, rp, ci, tmap, err);
+    check_launch("transpose map");
+    if (read_flag(err, s)) throw Error(SCR_E_INVALID, "classical AMG needs a structurally symmetric matrix");
+    return tmap;
+}
+
+// HMIS C/F split of the graph (rp, ci, S) with its transpose map: returns the number of C points
+// and their indices in *cidx (allocated; -1 on F points)
+int64_t hmis(int64_t nr, const int32_t* rp, const int32_t* ci, const uint8_t* S, const int32_t* tmap, uint64_t seed,
+             int level, int* err, Arena& ar, hipStream_t s, int32_t** cidx) {
+    const unsigned g = (unsigned)cdiv(nr > 0 ? nr : 1, 256);
+    int8_t* first = ar.make<int8_t>(nr + 1);
+    double* w = ar.make<double>(nr + 1);
+    int8_t* st = ar.make<int8_t>(nr + 1);
+    int8_t* st2 = ar.make<int8_t>(nr + 1);
+    uint8_t* isnew = ar.make<uint8_t>(nr + 1);
+    if (nr) {
+        hmis_first_k<<<(unsigned)cdiv(nr, HMIS_DOM), HMIS_DOM, 0, s>>>(nr, rp, ci, S, tmap, first);
+        check_launch("hmis first pass");
+        pmis_init_k<<<g, 256, 0, s>>>(nr, rp, ci, S, tmap, first, seed, level, w, st, isnew);
+        check_launch("pmis init");
+        for (int round = 0;; ++round) {
+            if (round > 100000) throw Error(SCR_E_HIP, "PMIS did not terminate");
+            zero_dev(err, sizeof(int), s);
+            pmis_f_k<<<g, 256, 0, s>>>(nr, rp, ci, S, isnew, st, st2, err);
+            check_launch("pmis f");
+            std::swap(st, st2);
+            if (read_flag(err, s) == 0) break;
+            pmis_c_k<<<g, 256, 0, s>>>(nr, rp, ci, S, tmap, w, st, isnew);
+            pmis_apply_k<<<g, 256, 0, s>>>(nr, isnew, st);
+            check_launch("pmis c");
+        }
     }
     int32_t* f = ar.make<int32_t>(nr + 1);
     int32_t* rank = ar.make<int32_t>(nr + 1);
-    cflag_k<<<g, 256, 0, s>>>(nr, st, f);
+    if (nr) cflag_k<<<g, 256, 0, s>>>(nr, st, f);
     const int64_t nc = scan_i32(f, rank, nr, ar, s);
-    L.agg = ar.make<int32_t>(nr);
-    cidx_k<<<g, 256, 0, s>>>(nr, st, rank, L.agg);
+    *cidx = ar.make<int32_t>(nr + 1);
+    if (nr) cidx_k<<<g, 256, 0, s>>>(nr, st, rank, *cidx);
     check_launch("coarse index");
     ar.free(f); ar.free(rank); ar.free(first); ar.free(w); ar.free(st); ar.free(st2); ar.free(isnew);
     return nc;
 }
 
-// extended+i interpolation of level L into L.P
-void extpi(LevelSetup& L, int64_t nc, const scr_amg_opts& o, Arena& ar, hipStream_t s) {
-    const int64_t nr = L.A.nr;
-    const unsigned g = (unsigned)cdiv(nr, 256);
+// extended+i interpolation (nr x nc, 1x1) of (A, func, S) onto the C points of cidx
+DBsr extpi(const DBsr& A, const uint8_t* func, const uint8_t* S, const int32_t* cidx, int64_t nc,
+           const scr_amg_opts& o, Arena& ar, hipStream_t s) {
+    const int64_t nr = A.nr;
+    const unsigned g = (unsigned)cdiv(nr > 0 ? nr : 1, 256);
     int32_t* cap = ar.make<int32_t>(nr + 1);
     int32_t* off = ar.make<int32_t>(nr + 1);
-    extpi_cap_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, L.agg, cap);
+    if (nr) extpi_cap_k<<<g, 256, 0, s>>>(nr, A.rp, A.ci, S, cidx, cap);
     check_launch("extpi cap");
     const int64_t total = scan_i32(cap, off, nr, ar, s);
-    if (total >= (1LL << 31)) throw Error(SCR_E_OOM, "interpolation candidates exceed 2^31");
+    if (total >= INT32_MAX) throw Error(SCR_E_OOM, "interpolation candidates exceed 2^31");
     int32_t* hcol = ar.make<int32_t>(total + 1);
     double* hw = ar.make<double>(total + 1);
     int32_t* cnt = ar.make<int32_t>(nr + 1);
-    extpi_row_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.func, L.strong, L.agg, off, o.trunc, o.pmax, hcol, hw,
-                                  cnt);
+    if (nr) extpi_row_k<<<g, 256, 0, s>>>(nr, A.rp, A.ci, A.v, func, S, cidx, off, o.trunc, o.pmax, hcol, hw, cnt);
     check_launch("extpi rows");
     DBsr P;
     P.nr = nr; P.nc = nc; P.br = 1; P.bc = 1;
@@ -618,10 +739,124 @@ void extpi(LevelSetup& L, int64_t nc, const scr_amg_opts& o, Arena& ar, hipStrea
     P.nnzb = scan_i32(cnt, P.rp, nr, ar, s);
     P.ci = ar.make<int32_t>(P.nnzb + 1);
     P.v = ar.make<double>(P.nnzb + 1);
-    extpi_fill_k<<<g, 256, 0, s>>>(nr, off, hcol, hw, P.rp, P.ci, P.v);
+    if (nr) extpi_fill_k<<<g, 256, 0, s>>>(nr, off, hcol, hw, P.rp, P.ci, P.v);
     check_launch("extpi fill");
     ar.free(cap); ar.free(off); ar.free(hcol); ar.free(hw); ar.free(cnt);
-    L.P = P;
+    return P;
+}
+
+// the rows of P truncated as one interpolation row each, into a new matrix (P released)
+DBsr truncate_matrix(DBsr& P, const scr_amg_opts& o, Arena& ar, hipStream_t s) {
+    const int64_t nr = P.nr;
+    const unsigned g = (unsigned)cdiv(nr > 0 ? nr : 1, 256);
+    int32_t* cnt = ar.make<int32_t>(nr + 1);
+    if (nr) trunc_rows_k<<<g, 256, 0, s>>>(nr, P.rp, P.ci, P.v, o.trunc, o.pmax, cnt);
+    check_launch("truncate rows");
+    DBsr T;
+    T.nr = nr; T.nc = P.nc; T.br = 1; T.bc = 1;
+    T.rp = ar.make<int32_t>(nr + 1);
+    T.nnzb = scan_i32(cnt, T.rp, nr, ar, s);
+    T.ci = ar.make<int32_t>(T.nnzb + 1);
+    T.v = ar.make<double>(T.nnzb + 1);
+    if (nr) extpi_fill_k<<<g, 256, 0, s>>>(nr, P.rp, P.ci, P.v, T.rp, T.ci, T.v);
+    check_launch("truncate fill");
+    ar.free(cnt);
+    bsr_release(P, ar);
+    return T;
+}
+
+// One standard level: HMIS on S and extended+i onto its C points (L.agg, L.P); returns the number
+// of coarse points
+int64_t standard_level(LevelSetup& L, const int32_t* tmap, const scr_amg_opts& o, int l, int* err, Arena& ar,
+                       hipStream_t s) {
+    const int64_t nc = hmis(L.A.nr, L.A.rp, L.A.ci, L.strong, tmap, o.seed, l, err, ar, s, &L.agg);
+    if (nc > 0) L.P = extpi(L.A, L.func, L.strong, L.agg, nc, o, ar, s);
+    return nc;
+}
+
+// One aggressive level: HMIS on S (first stage), HMIS on the second-stage graph of its C points,
+// P = truncation of P1 P2 (P1: extended+i of A onto the first-stage C points; P2: extended+i of
+// A1 = P1^T A P1 onto the kept ones)
+int64_t aggressive_level(LevelSetup& L, const int32_t* tmap, const scr_amg_opts& o, int l, int* err, Arena& ar,
+                         hipStream_t s) {
+    const int64_t nr = L.A.nr;
+    const unsigned g = (unsigned)cdiv(nr > 0 ? nr : 1, 256);
+    int32_t* c1 = nullptr;
+    const int64_t n1 = hmis(nr, L.A.rp, L.A.ci, L.strong, tmap, o.seed, l, err, ar, s, &c1);
+    const unsigned g1 = (unsigned)cdiv(n1 > 0 ? n1 : 1, 256);
+    // the second-stage graph (symmetric pattern, flags on the edges)
+    int32_t* fine_of = ar.make<int32_t>(n1 + 1);
+    int32_t* cap = ar.make<int32_t>(n1 + 1);
+    int32_t* off = ar.make<int32_t>(n1 + 1);
+    if (nr) fine_of_k<<<g, 256, 0, s>>>(nr, c1, fine_of);
+    if (n1) ss_cap_k<<<g1, 256, 0, s>>>(n1, fine_of, L.A.rp, L.A.ci, L.strong, cap);
+    check_launch("second stage cap");
+    const int64_t tot = scan_i32(cap, off, n1, ar, s);
+    if (tot >= INT32_MAX) throw Error(SCR_E_OOM, "second-stage candidates exceed 2^31");
+    int32_t* buf = ar.make<int32_t>(tot + 1);
+    int32_t* no = ar.make<int32_t>(n1 + 1);
+    int32_t* nin = ar.make<int32_t>(n1 + 1);
+    zero_dev(nin, (n1 + 1) * sizeof(int32_t), s);
+    if (n1) {
+        ss_out_k<<<g1, 256, 0, s>>>(n1, fine_of, L.A.rp, L.A.ci, L.strong, c1, off, buf, no);
+        ss_indeg_k<<<g1, 256, 0, s>>>(n1, off, buf, no, nin);
+    }
+    check_launch("second stage out-edges");
+    int32_t* inoff = ar.make<int32_t>(n1 + 1);
+    const int64_t tin = scan_i32(nin, inoff, n1, ar, s);
+    int32_t* inbuf = ar.make<int32_t>(tin + 1);
+    int32_t* cur = ar.make<int32_t>(n1 + 1);
+    zero_dev(cur, (n1 + 1) * sizeof(int32_t), s);
+    int32_t* cnt = ar.make<int32_t>(n1 + 1);
+    if (n1) {
+        ss_in_fill_k<<<g1, 256, 0, s>>>(n1, off, buf, no, inoff, cur, inbuf);
+        ss_in_sort_k<<<g1, 256, 0, s>>>(n1, inoff, nin, inbuf);
+        ss_merge_k<false><<<g1, 256, 0, s>>>(n1, off, buf, no, inoff, inbuf, nin, nullptr, nullptr, nullptr, cnt);
+    }
+    check_launch("second stage in-edges");
+    DBsr G;
+    G.nr = G.nc = n1; G.br = G.bc = 1;
+    G.rp = ar.make<int32_t>(n1 + 1);
+    G.nnzb = scan_i32(cnt, G.rp, n1, ar, s);
+    if (G.nnzb >= INT32_MAX) throw Error(SCR_E_OOM, "second-stage graph exceeds 2^31 entries");
+    G.ci = ar.make<int32_t>(G.nnzb + 1);
+    uint8_t* gS = ar.make<uint8_t>(G.nnzb + 1);
+    if (n1) ss_merge_k<true><<<g1, 256, 0, s>>>(n1, off, buf, no, inoff, inbuf, nin, G.rp, G.ci, gS, nullptr);
+    check_launch("second stage pattern");
+    for (void* p : {(void*)cap, (void*)off, (void*)buf, (void*)no, (void*)nin, (void*)inoff, (void*)inbuf, (void*)cur,
+                    (void*)cnt, (void*)fine_of})
+        ar.free(p);
+    int32_t* gmap = transpose_map(n1, G.rp, G.ci, G.nnzb, err, ar, s);
+    int32_t* c2 = nullptr;
+    const int64_t n2 = hmis(n1, G.rp, G.ci, gS, gmap, o.seed, l + 32, err, ar, s, &c2);
+    ar.free(gmap); ar.free(gS); ar.free(G.rp); ar.free(G.ci);
+    L.agg = ar.make<int32_t>(nr + 1);
+    if (nr) agg_compose_k<<<g, 256, 0, s>>>(nr, c1, c2, L.agg);
+    check_launch("aggressive coarse index");
+    if (n2 > 0) {
+        DBsr P1 = extpi(L.A, L.func, L.strong, c1, n1, o, ar, s);
+        DBsr R1 = transpose(P1, ar, s);
+        DBsr AP1 = spgemm(L.A, P1, nullptr, ar, s);
+        DBsr A1 = spgemm(R1, AP1, nullptr, ar, s);
+        bsr_release(R1, ar);
+        bsr_release(AP1, ar);
+        uint8_t* f1 = ar.make<uint8_t>(n1 + 1);
+        if (nr) coarse_func_k<<<g, 256, 0, s>>>(nr, c1, L.func, f1);
+        uint8_t* S1 = ar.make<uint8_t>(A1.nnzb + 1);
+        if (n1) cl_strength_k<<<g1, 256, 0, s>>>(n1, A1.rp, A1.ci, A1.v, f1, o.cl_theta, S1);
+        check_launch("first-stage coarse strength");
+        DBsr P2 = extpi(A1, f1, S1, c2, n2, o, ar, s);
+        DBsr P12 = spgemm(P1, P2, nullptr, ar, s);
+        L.P = truncate_matrix(P12, o, ar, s);
+        bsr_release(P1, ar);
+        bsr_release(P2, ar);
+        bsr_release(A1, ar);
+        ar.free(f1);
+        ar.free(S1);
+    }
+    ar.free(c1);
+    ar.free(c2);
+    return n2;
 }
 
 // every level of the classical hierarchy into H (H.L empty on entry; level 0 from A0)
@@ -648,23 +883,20 @@ void setup_levels(ClassicalHier& H, const DBsr& A0, const scr_amg_opts& o, Arena
         L.Dinv = ar.make<double>(nr > 0 ? nr : 1);
         level_diag(L, l, err, lamd, s);
         if (nr <= o.coarse_max || l + 1 >= o.max_levels || l + 1 >= 16) break;
-        int32_t* tmap = ar.make<int32_t>(L.A.nnzb + 1);
-        zero_dev(err, sizeof(int), s);
-        tmap_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, tmap, err);
-        check_launch("transpose map");
-        if (read_flag(err, s)) throw Error(SCR_E_INVALID, "classical AMG needs a structurally symmetric matrix");
+        int32_t* tmap = transpose_map(nr, L.A.rp, L.A.ci, L.A.nnzb, err, ar, s);
         L.strong = ar.make<uint8_t>(L.A.nnzb + 1);
         cl_strength_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.func, o.cl_theta, L.strong);
         check_launch("classical strength");
-        const int64_t nc = hmis_split(L, tmap, o.seed, l, err, ar, s);
+        const int64_t nc = l < o.agg_levels ? aggressive_level(L, tmap, o, l, err, ar, s)
+                                            : standard_level(L, tmap, o, l, err, ar, s);
         ar.free(tmap);
         if (nc <= 0 || (double)nc > o.max_coarse_ratio * (double)nr) {
             ar.free(L.agg); L.agg = nullptr;
             ar.free(L.strong); L.strong = nullptr;
+            bsr_release(L.P, ar);
             break;
         }
         L.nagg = nc;
-        extpi(L, nc, o, ar, s);
         L.R = transpose(L.P, ar, s);
         DBsr AP = spgemm(L.A, L.P, nullptr, ar, s);
         LevelSetup N;

@@ -50,7 +50,8 @@ class AmgOpts(C.Structure):
                 ("cheb_ratio", C.c_double), ("jacobi_sweeps", C.c_int), ("coarse_max", C.c_int),
                 ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
                 ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double),
-                ("amg_type", C.c_int), ("cl_theta", C.c_double), ("trunc", C.c_double), ("pmax", C.c_int)]
+                ("amg_type", C.c_int), ("cl_theta", C.c_double), ("trunc", C.c_double), ("pmax", C.c_int),
+                ("agg_levels", C.c_int)]
 
 
 class SolveOpts(C.Structure):

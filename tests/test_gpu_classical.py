@@ -2,7 +2,8 @@
 paper's table in Sec. 5.2) with the oracle's (oracle.c, amg_type = 1), through the C ABI.
 
 Bars: every level's strength flags, C/F split (coarse indices), functions and the patterns of A,
-P and R bit-exact, and the values of P and of every coarse A bit-exact too (both sides evaluate
+P and R bit-exact (the first two levels coarsened aggressively by default, with cases of
+none and of every level aggressive), and the values of P and of every coarse A bit-exact too (both sides evaluate
 the interpolation and the Galerkin sums in the same order without fused multiply-adds); one
 V-cycle within 1e-12 (the hybrid Gauss-Seidel sweeps sum each row in a different order); SCR and
 mesh solves with the FP64 iteration counts of the oracle, per-field errors within 1e-6 of the
@@ -76,10 +77,11 @@ def _same(hg, which, ho):
           f"bit-exact", flush=True)
 
 
-@pytest.mark.parametrize("case", ["small_fsi", "cfg0"])
-def test_scr_hierarchies_bit_exact(scr, ctx, case, small_fsi, cfg0):
+@pytest.mark.parametrize("case,agg", [("small_fsi", 2), ("small_fsi", 0), ("cfg0", 2), ("cfg0", 0)])
+def test_scr_hierarchies_bit_exact(scr, ctx, case, agg, small_fsi, cfg0):
     s = {"small_fsi": small_fsi, "cfg0": cfg0}[case]
     kw = dict(coarse_max=60) if case == "small_fsi" else {}
+    kw["agg_levels"] = agg
     h = _gpu_scr(scr, ctx, s, **kw)
     o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(amg_type=1, **kw))
     _same(h, 0, o.amgA)
@@ -87,11 +89,11 @@ def test_scr_hierarchies_bit_exact(scr, ctx, case, small_fsi, cfg0):
     h.destroy()
 
 
-@pytest.mark.parametrize("coarse_max", [64, 1024])
-def test_mesh_hierarchy_bit_exact_and_vcycle(scr, ctx, cfg0, coarse_max):
+@pytest.mark.parametrize("coarse_max,agg", [(64, 2), (1024, 2), (64, 0), (64, 1), (8, 16)])
+def test_mesh_hierarchy_bit_exact_and_vcycle(scr, ctx, cfg0, coarse_max, agg):
     s = cfg0
-    h = _gpu_mesh(scr, ctx, s, coarse_max=coarse_max)
-    o = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, coarse_max=coarse_max))
+    h = _gpu_mesh(scr, ctx, s, coarse_max=coarse_max, agg_levels=agg)
+    o = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, coarse_max=coarse_max, agg_levels=agg))
     _same(h, 2, o.amg)
     rng = np.random.default_rng(2)
     x = rng.uniform(-1, 1, s.n_phys)
@@ -163,6 +165,7 @@ def test_update_equals_fresh_setup_and_options(scr, ctx, small_fsi):
     _same(h, 1, o2.amgS)
     h.destroy()
     # classical is FP64 only; option ranges are checked
-    for kw in (dict(precision=1), dict(pmax=0), dict(pmax=17), dict(cl_theta=0.0), dict(trunc=1.0)):
+    for kw in (dict(precision=1), dict(pmax=0), dict(pmax=17), dict(cl_theta=0.0), dict(trunc=1.0),
+               dict(agg_levels=-1), dict(agg_levels=17)):
         with pytest.raises(scr.ScrError):
             _gpu_scr(scr, ctx, s, **kw)
