@@ -37,7 +37,8 @@ class AmgOpts(C.Structure):
                 ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
                 ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double),
                 ("amg_type", C.c_int), ("cl_theta", C.c_double), ("trunc", C.c_double), ("pmax", C.c_int),
-                ("hmis_domain", C.c_int), ("gs_domain", C.c_int), ("agg_levels", C.c_int)]
+                ("hmis_domain", C.c_int), ("gs_domain", C.c_int), ("agg_levels", C.c_int),
+                ("l1_gs", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -66,7 +67,7 @@ def amg_opts(**kw) -> AmgOpts:
     o = AmgOpts(theta=0.08, smoother=1, cheb_degree=4, cheb_ratio=30.0, jacobi_sweeps=2,
                 coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0,
                 schur_cheb_degree=8, schur_cheb_ratio=100.0, amg_type=0, cl_theta=0.5, trunc=0.3, pmax=5,
-                hmis_domain=256, gs_domain=64, agg_levels=2)
+                hmis_domain=256, gs_domain=64, agg_levels=2, l1_gs=1)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -143,7 +144,7 @@ def lib():
         L.orc_cl_hmis.restype = C.c_int
         L.orc_cl_extpi.argtypes = [C.c_int64, P, P, P, P, P, P, C.c_double, C.c_int, P, P, P]
         L.orc_cl_extpi.restype = C.c_int64
-        L.orc_cl_gs.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int, P, P, P]
+        L.orc_cl_gs.argtypes = [C.c_int64, P, P, P, C.c_int, C.c_int, C.c_int, P, P, P]
         L.orc_cl_second_stage.argtypes = [C.c_int64, P, P, P, P, P, P, P]
         L.orc_cl_second_stage.restype = C.c_int64
         L.orc_cl_uniform.argtypes = [C.c_uint64, C.c_int, C.c_int64]
@@ -258,12 +259,12 @@ def cl_extpi(rp, ci, val, func, S, cf, trunc=0.3, pmax=5):
     return prp, pci, pv
 
 
-def cl_gs(rp, ci, val, b, x_old=None, domain=64, backward=False):
-    """One hybrid Gauss-Seidel sweep from x_old (None = zero)."""
+def cl_gs(rp, ci, val, b, x_old=None, domain=64, backward=False, l1=False):
+    """One hybrid Gauss-Seidel sweep from x_old (None = zero); l1: the l1 form."""
     rp = _c(rp, np.int32); ci = _c(ci, np.int32); val = _c(val, np.float64); b = _c(b, np.float64)
     x = np.zeros_like(b)
     xo = None if x_old is None else _c(x_old, np.float64)
-    lib().orc_cl_gs(rp.size - 1, _p(rp), _p(ci), _p(val), domain, int(backward), _p(b),
+    lib().orc_cl_gs(rp.size - 1, _p(rp), _p(ci), _p(val), domain, int(backward), int(l1), _p(b),
                     None if xo is None else _p(xo), _p(x))
     return x
 

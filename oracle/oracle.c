@@ -264,6 +264,7 @@ typedef struct {
     int hmis_domain;     /* rows per HMIS domain */
     int gs_domain;       /* rows per hybrid Gauss-Seidel domain */
     int agg_levels;      /* classical: levels coarsened aggressively (two stages), 2 */
+    int l1_gs;           /* classical: 1 the l1 hybrid Gauss-Seidel, 0 the plain one */
 } amg_opts;
 
 #define MAXLEV 16
@@ -279,6 +280,7 @@ typedef struct {
     uint8_t* dead;       /* per coarse dof (n_agg*k) */
     double* Q;           /* tentative prolongator (nr*b) x k row-major */
     uint8_t* func;       /* classical: function (unknown) of each scalar row */
+    double* ell;         /* classical, l1 smoother: sign(a_ii) sum of |a_ij| outside i's domain */
 } level;
 
 typedef struct {
@@ -467,6 +469,7 @@ static void tentative(int64_t nr, int b, int k, const int32_t* agg, int64_t na, 
 static void level_free(level* L) {
     bsr_free(L->A); bsr_free(L->P); bsr_free(L->R);
     free(L->agg); free(L->strong); free(L->Dinv); free(L->B); free(L->dead); free(L->Q); free(L->func);
+    free(L->ell);
 }
 
 /* D^-1 (block diagonal inverse) and lambda_hat = max abs row sum of D^-1 A */
@@ -660,8 +663,13 @@ static int coarse_factor(amg* h) {
  * Hybrid Gauss-Seidel (Baker, Falgout, Kolev and Yang): Gauss-Seidel inside domains of `gs_dom`
  * consecutive rows, Jacobi between them: x_i = (b_i - sum_{j != i} a_ij x~_j) / a_ii with x~_j
  * the new value for j earlier in the same domain (forward sweep: j < i; backward: j > i) and the
- * previous iterate otherwise.  V-cycle: one forward sweep from zero, coarse-grid correction, one
- * backward sweep (a symmetric cycle for symmetric A).
+ * previous iterate otherwise.  The l1 form of the same paper adds to the splitting's diagonal
+ * d_i = s sum |a_ij| over the columns j outside i's domain (s = sign(a_ii)): the sweep is
+ * x = x_old + M^-1 (b - A x_old) with M = (a_ii + d_i) on the diagonal and the in-domain lower
+ * (forward) or upper (backward) part of A, that is x_i = (b_i - sum_{j != i} a_ij x~_j + d_i x_old_i)
+ * / (a_ii + d_i); for symmetric positive definite A it converges whatever the domains, where the
+ * plain sweep may diverge once D^-1 A has eigenvalues above 2.  V-cycle: one forward sweep from
+ * zero, coarse-grid correction, one backward sweep (a symmetric cycle for symmetric A).
  */
 static int opposite(double a, double d) { return (a > 0.0 && d < 0.0) || (a < 0.0 && d > 0.0); }
 
@@ -969,8 +977,8 @@ int64_t orc_cl_extpi(int64_t nr, const int32_t* rp, const int32_t* ci, const dou
 }
 
 /* One hybrid Gauss-Seidel sweep (x out; xold the previous iterate, NULL = zero). */
-static void hybrid_gs(const bsr* A, const double* Dinv, int dom, int backward, const double* b, const double* xold,
-                      double* x) {
+static void hybrid_gs(const bsr* A, const double* Dinv, const double* ell, int dom, int backward, const double* b,
+                      const double* xold, double* x) {
     int64_t nr = A->nr;
     int64_t nd = (nr + dom - 1) / dom;
 #pragma omp parallel for schedule(static) if (nr > PAR_MIN)
@@ -986,22 +994,45 @@ static void hybrid_gs(const bsr* A, const double* Dinv, int dom, int backward, c
                 double xj = fresh ? x[j] : (xold ? xold[j] : 0.0);
                 s = s + A->v[q] * xj;
             }
-            x[i] = (b[i] - s) * Dinv[i];
+            double t = b[i] - s;
+            if (ell && xold) t = t + ell[i] * xold[i];
+            x[i] = t * Dinv[i];
         }
     }
 }
 
-void orc_cl_gs(int64_t nr, const int32_t* rp, const int32_t* ci, const double* val, int dom, int backward,
+/* The l1 term of every row (ell) and the inverse of the l1 diagonal a_ii + ell_i (Dinv). */
+static void l1_diag(const bsr* A, int dom, double* ell, double* Dinv) {
+    for (int64_t i = 0; i < A->nr; ++i) {
+        double aii = 0.0, e = 0.0;
+        for (int32_t q = A->rp[i]; q < A->rp[i + 1]; ++q) {
+            int64_t j = A->ci[q];
+            if (j == i) aii = A->v[q];
+            else if (j / dom != i / dom) e = e + fabs(A->v[q]);
+        }
+        ell[i] = aii < 0.0 ? -e : e;
+        Dinv[i] = 1.0 / (aii + ell[i]);
+    }
+}
+
+/* test entry: one hybrid Gauss-Seidel sweep (l1 form when l1 != 0) */
+void orc_cl_gs(int64_t nr, const int32_t* rp, const int32_t* ci, const double* val, int dom, int backward, int l1,
                const double* b, const double* xold, double* x) {
     bsr A = {nr, nr, 1, 1, rp[nr], (int32_t*)rp, (int32_t*)ci, (double*)val};
     double* Dinv = (double*)malloc(sizeof(double) * (nr > 0 ? nr : 1));
-    for (int64_t i = 0; i < nr; ++i) {
-        Dinv[i] = 0.0;
-        for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
-            if (ci[q] == i) Dinv[i] = 1.0 / val[q];
+    double* ell = (double*)malloc(sizeof(double) * (nr > 0 ? nr : 1));
+    if (l1) {
+        l1_diag(&A, dom, ell, Dinv);
+    } else {
+        for (int64_t i = 0; i < nr; ++i) {
+            Dinv[i] = 0.0;
+            for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+                if (ci[q] == i) Dinv[i] = 1.0 / val[q];
+        }
     }
-    hybrid_gs(&A, Dinv, dom, backward, b, xold, x);
+    hybrid_gs(&A, Dinv, l1 ? ell : NULL, dom, backward, b, xold, x);
     free(Dinv);
+    free(ell);
 }
 
 /* the scalar matrix of a b x b BSR matrix (row b*i + r, columns in order) and the function of
@@ -1225,8 +1256,13 @@ static amg* amg_build_classical(const bsr* A0, const amg_opts* o) {
         ++l;
     }
     h->nlev = l + 1;
-    for (int t = 0; t + 1 < h->nlev; ++t)
+    for (int t = 0; t + 1 < h->nlev; ++t) {
         if (level_diag(&h->L[t])) { orc_amg_free(h); return NULL; }
+        if (o->l1_gs) {
+            h->L[t].ell = (double*)malloc(sizeof(double) * (h->L[t].A->nr > 0 ? h->L[t].A->nr : 1));
+            l1_diag(h->L[t].A, o->gs_domain, h->L[t].ell, h->L[t].Dinv);
+        }
+    }
     if (coarse_factor(h)) { orc_amg_free(h); return NULL; }
     h->work = (double*)malloc(sizeof(double) * 6 * (maxn + 8));
     return h;
@@ -1365,7 +1401,7 @@ static void vcycle_rec(amg* h, int l, const double* b, double* x) {
     double* r = (double*)malloc(sizeof(double) * n);
     double* d = (double*)malloc(sizeof(double) * n);
     double* z = (double*)malloc(sizeof(double) * n);
-    if (h->o.amg_type == 1) hybrid_gs(L->A, L->Dinv, h->o.gs_domain, 0, b, NULL, x);
+    if (h->o.amg_type == 1) hybrid_gs(L->A, L->Dinv, L->ell, h->o.gs_domain, 0, b, NULL, x);
     else smooth(h, l, b, x, 1, r, d, z);
     bsr_mv(L->A, x, r);
 #pragma omp parallel for schedule(static) if (n > PAR_MIN)
@@ -1380,7 +1416,7 @@ static void vcycle_rec(amg* h, int l, const double* b, double* x) {
     for (int64_t i = 0; i < n; ++i) x[i] += z[i];
     if (h->o.amg_type == 1) {
         memcpy(d, x, sizeof(double) * n);
-        hybrid_gs(L->A, L->Dinv, h->o.gs_domain, 1, b, d, x);
+        hybrid_gs(L->A, L->Dinv, L->ell, h->o.gs_domain, 1, b, d, x);
     } else {
         smooth(h, l, b, x, 0, r, d, z);
     }
@@ -1401,8 +1437,8 @@ void orc_amg_smooth(amg* h, int l, const double* b, double* x, int zero_init) {
     double* z = (double*)malloc(sizeof(double) * n);
     if (h->o.amg_type == 1) {
         /* classical: the V-cycle's sweeps (forward from zero, or backward from x) */
-        if (zero_init) hybrid_gs(h->L[l].A, h->L[l].Dinv, h->o.gs_domain, 0, b, NULL, x);
-        else { memcpy(d, x, sizeof(double) * n); hybrid_gs(h->L[l].A, h->L[l].Dinv, h->o.gs_domain, 1, b, d, x); }
+        if (zero_init) hybrid_gs(h->L[l].A, h->L[l].Dinv, h->L[l].ell, h->o.gs_domain, 0, b, NULL, x);
+        else { memcpy(d, x, sizeof(double) * n); hybrid_gs(h->L[l].A, h->L[l].Dinv, h->L[l].ell, h->o.gs_domain, 1, b, d, x); }
     } else {
         smooth(h, l, b, x, zero_init, r, d, z);
     }

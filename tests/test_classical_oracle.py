@@ -314,6 +314,89 @@ def test_hybrid_gauss_seidel_special_cases():
                        sla.solve_triangular(D + Lo, b, lower=True), rtol=1e-13, atol=1e-13)
 
 
+def _ell(Ad, dom):
+    """The l1 term of every row by its definition: s_i times the sum of |a_ij| over the columns of
+    other domains."""
+    n = Ad.shape[0]
+    e = np.array([sum(abs(Ad[i, j]) for j in range(n) if j // dom != i // dom) for i in range(n)])
+    return np.sign(np.diag(Ad)) * e
+
+
+def test_l1_hybrid_gauss_seidel_special_cases():
+    rng = np.random.default_rng(1)
+    A = _csr(_lap2d(9) + sp.diags(rng.uniform(0.1, 1.0, 81)))
+    Ad = A.toarray()
+    b = rng.standard_normal(81)
+    x0 = rng.standard_normal(81)
+    # one domain: no coupling leaves it, the l1 sweep is the plain one
+    for backward in (False, True):
+        assert np.array_equal(oracle.cl_gs(A.indptr, A.indices, A.data, b, x0, domain=1 << 20, backward=backward, l1=True),
+                              oracle.cl_gs(A.indptr, A.indices, A.data, b, x0, domain=1 << 20, backward=backward))
+    # one-row domains: l1 Jacobi, x0 + (b - A x0) / (a_ii + sum_{j != i} |a_ij|)
+    xj = oracle.cl_gs(A.indptr, A.indices, A.data, b, x0, domain=1, l1=True)
+    l1d = np.diag(Ad) + (np.abs(Ad).sum(1) - np.abs(np.diag(Ad)))
+    assert np.allclose(xj, x0 + (b - Ad @ x0) / l1d, rtol=1e-13, atol=1e-13)
+    # domains of 16: x0 + M^-1 (b - A x0), M = the in-domain triangle of A plus diag(ell)
+    ell = _ell(Ad, 16)
+    for backward in (False, True):
+        x = oracle.cl_gs(A.indptr, A.indices, A.data, b, x0, domain=16, backward=backward, l1=True)
+        M = np.zeros_like(Ad)
+        for lo in range(0, 81, 16):
+            hi = min(81, lo + 16)
+            blk = Ad[lo:hi, lo:hi]
+            M[lo:hi, lo:hi] = np.triu(blk) if backward else np.tril(blk)
+        M += np.diag(ell)
+        ref = x0 + sla.solve_triangular(M, b - Ad @ x0, lower=not backward)
+        assert np.allclose(x, ref, rtol=1e-12, atol=1e-12)
+    # zero previous iterate: the l1 terms only enter through the diagonal
+    M = np.tril(Ad) * (np.arange(81)[:, None] // 16 == np.arange(81)[None, :] // 16) + np.diag(ell)
+    assert np.allclose(oracle.cl_gs(A.indptr, A.indices, A.data, b, None, domain=16, l1=True),
+                       sla.solve_triangular(M, b, lower=True), rtol=1e-12, atol=1e-12)
+
+
+def test_l1_sweep_converges_where_the_plain_one_diverges():
+    # symmetric positive definite with positive couplings and D^-1 A reaching about 7: the plain
+    # hybrid sweep (Jacobi between domains) amplifies the energy norm of the error, the l1 sweep
+    # lowers it at every sweep (Baker, Falgout, Kolev and Yang)
+    rng = np.random.default_rng(3)
+    n = 512
+    rows = np.repeat(np.arange(n), 6)
+    S = sp.csr_matrix((rng.uniform(0.5, 1.0, n * 6), (rows, rng.integers(0, n, n * 6))), shape=(n, n))
+    A = _csr(S @ S.T + 0.01 * sp.identity(n))
+    x0 = rng.standard_normal(n)
+    zero = np.zeros(n)
+    for l1 in (False, True):
+        x, en = x0.copy(), [x0 @ (A @ x0)]
+        for k in range(12):
+            x = oracle.cl_gs(A.indptr, A.indices, A.data, zero, x, domain=16, backward=bool(k % 2), l1=l1)
+            en.append(x @ (A @ x))
+        ratios = np.array(en[1:]) / np.array(en[:-1])
+        if l1:
+            assert ratios.max() < 1.0, ratios
+        else:
+            assert en[-1] > 1e3 * en[0], ratios
+
+
+def test_hierarchy_uses_the_l1_diagonal():
+    s = synth.generate(synth.cfg0_params())
+    for l1 in (0, 1):
+        m = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, coarse_max=64, l1_gs=l1))
+        h = m.amg
+        for l in range(h.nlevels - 1):
+            n = h.info(l)["nr"]
+            A = sp.csr_matrix((h.get(l, "A.v").reshape(-1), h.get(l, "A.ci"), h.get(l, "A.rp")), shape=(n, n))
+            if n <= 2000:
+                Ad = A.toarray()
+                d = np.diag(Ad) + (_ell(Ad, 64) if l1 else 0.0)
+            else:
+                # the dense definition is slow at the finest level: the same sums over the entries
+                C = A.tocoo()
+                off = (C.row // 64 != C.col // 64) & (C.row != C.col) if l1 else np.zeros(C.nnz, bool)
+                e = np.bincount(C.row[off], np.abs(C.data[off]), minlength=n)
+                d = A.diagonal() + np.sign(A.diagonal()) * e
+            assert np.allclose(h.get(l, "Dinv").reshape(-1), 1.0 / d, rtol=1e-14, atol=0), (l1, l)
+
+
 # ------------------------------------------------------------------------------ hierarchy
 def test_hierarchy_galerkin_products_and_symmetric_cycle():
     s = synth.generate(synth.cfg0_params())
