@@ -111,7 +111,10 @@ typedef struct {
                                   interpolation truncated at trunc and to pmax entries per row (row
                                   sums kept).  Smoother: one hybrid Gauss-Seidel sweep before (forward)
                                   and after (backward) the coarse correction, Gauss-Seidel inside
-                                  domains of 64 rows (one wavefront each), Jacobi between them.
+                                  domains of 64 rows (one wavefront each), Jacobi between them; in
+                                  its l1 form (l1_gs) each row's diagonal gains the absolute values
+                                  of its couplings outside its domain, which keeps the sweep
+                                  convergent for any symmetric positive definite matrix.
                                   Galerkin coarse operators, direct coarsest solve.  FP64 only; the
                                   near-null space, theta, the smoother and Chebyshev fields are not
                                   used; amg_update sets the hierarchy up again.  The first
@@ -125,6 +128,7 @@ typedef struct {
     double trunc;              /* interpolation truncation factor, 0.3 */
     int pmax;                  /* interpolation entries per row, 5 (1..16) */
     int agg_levels;            /* classical: levels coarsened aggressively, 2 (0 = none; <= 16) */
+    int l1_gs;                 /* classical: 1 (default) the l1 hybrid Gauss-Seidel, 0 the plain one */
 } scr_amg_opts;
 
 /* Krylov options.  Defaults: tol 1e-8 (outer), tol_A = tol_S = tol_I = 1e-3 and 200

@@ -519,14 +519,31 @@ __global__ void agg_compose_k(int64_t nr, const int32_t* __restrict__ c1, const 
 }
 
 // ------------------------------------------------------------------ hybrid Gauss-Seidel
-// One sweep: x_i = (b_i - sum_{j != i} a_ij x~_j) / a_ii, x~_j new for rows of the same domain
-// already swept (forward: j < i; backward: j > i), else the previous iterate xold (nullptr: 0).
+// l1 form of the sweep's diagonal: ell_i = s sum |a_ij| over the columns outside row i's domain
+// of GS_DOM rows (s = sign(a_ii), column order), dinv_i = 1 / (a_ii + ell_i)
+__global__ void l1_diag_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ ell, double* __restrict__ dinv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    double aii = 0.0, e = 0.0;
+    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+        const int64_t j = ci[q];
+        if (j == i) aii = v[q];
+        else if (j / GS_DOM != i / GS_DOM) e = e + fabs(v[q]);
+    }
+    ell[i] = aii < 0.0 ? -e : e;
+    dinv[i] = 1.0 / (aii + ell[i]);
+}
+
+// One sweep: x_i = (b_i - sum_{j != i} a_ij x~_j + ell_i xold_i) dinv_i, x~_j new for rows of the
+// same domain already swept (forward: j < i; backward: j > i), else the previous iterate xold
+// (nullptr: 0); ell nullptr and dinv = 1 / a_ii for the plain sweep, the l1 terms otherwise.
 // NC node-interleaved columns (entry NC i + c).  One wavefront per domain of GS_DOM rows.
 template <int NC, bool BWD>
 __global__ void __launch_bounds__(256) hgs_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const double* __restrict__ v, const double* __restrict__ dinv,
-                                             const double* __restrict__ b, const double* __restrict__ xold,
-                                             double* __restrict__ x) {
+                                             const double* __restrict__ ell, const double* __restrict__ b,
+                                             const double* __restrict__ xold, double* __restrict__ x) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * (256 / WAVE) + threadIdx.x / WAVE;
     const int64_t lo = d * GS_DOM;
@@ -559,7 +576,9 @@ __global__ void __launch_bounds__(256) hgs_k(int64_t nr, const int32_t* __restri
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double sum = wave_sum(acc[c]);
-            const double xi = (b[NC * i + c] - sum) * dinv[i];
+            double ti = b[NC * i + c] - sum;
+            if (ell != nullptr && xold != nullptr) ti = ti + ell[i] * xold[NC * i + c];
+            const double xi = ti * dinv[i];
             if (lane == (int)(i - lo)) {
                 xn[c] = xi;
                 x[NC * i + c] = xi;
@@ -569,12 +588,13 @@ __global__ void __launch_bounds__(256) hgs_k(int64_t nr, const int32_t* __restri
 }
 
 template <int NC>
-void hgs(const DBsr& A, const double* Dinv, const double* b, const double* xold, double* x, bool backward, hipStream_t s) {
+void hgs(const DBsr& A, const double* Dinv, const double* ell, const double* b, const double* xold, double* x,
+         bool backward, hipStream_t s) {
     const int64_t nd = cdiv(A.nr, GS_DOM);
     const unsigned g = (unsigned)cdiv(nd, 256 / WAVE);
     if (!g) return;
-    if (backward) hgs_k<NC, true><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, b, xold, x);
-    else hgs_k<NC, false><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, b, xold, x);
+    if (backward) hgs_k<NC, true><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
+    else hgs_k<NC, false><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
     check_launch("hybrid_gs");
 }
 
@@ -626,12 +646,12 @@ class ClassicalHier : public Hierarchy {
         }
         LS& q = S[l];
         const LevelSetup& ls = L[l];
-        hgs<1>(ls.A, ls.Dinv, b, nullptr, q.w, false, s);
+        hgs<1>(ls.A, ls.Dinv, ls.ell, b, nullptr, q.w, false, s);
         sell_mv<double>(q.A, q.w, b, q.r, 1, s);
         bsrt_mv<double>(q.R, q.r, S[l + 1].b, s);
         cycle(l + 1, S[l + 1].b, S[l + 1].x, s);
         sell_mv<double>(q.P, S[l + 1].x, nullptr, q.w, 2, s);
-        hgs<1>(ls.A, ls.Dinv, b, q.w, x, true, s);
+        hgs<1>(ls.A, ls.Dinv, ls.ell, b, q.w, x, true, s);
     }
     void cycle3(size_t l, const double* b, double* x, hipStream_t s) {
         if (l + 1 == S.size()) {
@@ -640,12 +660,12 @@ class ClassicalHier : public Hierarchy {
         }
         LS& q = S[l];
         const LevelSetup& ls = L[l];
-        hgs<3>(ls.A, ls.Dinv, b, nullptr, q.w3, false, s);
+        hgs<3>(ls.A, ls.Dinv, ls.ell, b, nullptr, q.w3, false, s);
         sell_mv3<double>(q.A, q.w3, b, q.r3, 1, s);
         bsrt_mv3<double>(q.R, q.r3, S[l + 1].b3, s);
         cycle3(l + 1, S[l + 1].b3, S[l + 1].x3, s);
         sell_mv3<double>(q.P, S[l + 1].x3, nullptr, q.w3, 2, s);
-        hgs<3>(ls.A, ls.Dinv, b, q.w3, x, true, s);
+        hgs<3>(ls.A, ls.Dinv, ls.ell, b, q.w3, x, true, s);
     }
     void vcycle(const double* x, double* y, hipStream_t s) override {
         ++vcycles;
@@ -882,6 +902,11 @@ void setup_levels(ClassicalHier& H, const DBsr& A0, const scr_amg_opts& o, Arena
         const unsigned g = (unsigned)cdiv(nr, 256);
         L.Dinv = ar.make<double>(nr > 0 ? nr : 1);
         level_diag(L, l, err, lamd, s);
+        if (o.l1_gs) {
+            L.ell = ar.make<double>(nr > 0 ? nr : 1);
+            if (nr) l1_diag_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.A.v, L.ell, L.Dinv);
+            check_launch("l1 diagonal");
+        }
         if (nr <= o.coarse_max || l + 1 >= o.max_levels || l + 1 >= 16) break;
         int32_t* tmap = transpose_map(nr, L.A.rp, L.A.ci, L.A.nnzb, err, ar, s);
         L.strong = ar.make<uint8_t>(L.A.nnzb + 1);
@@ -919,7 +944,7 @@ void release_levels(ClassicalHier& H, Arena& ar) {
         bsr_release(L.A, ar);
         bsr_release(L.P, ar);
         bsr_release(L.R, ar);
-        for (void* p : {(void*)L.agg, (void*)L.strong, (void*)L.Dinv, (void*)L.func}) ar.free(p);
+        for (void* p : {(void*)L.agg, (void*)L.strong, (void*)L.Dinv, (void*)L.func, (void*)L.ell}) ar.free(p);
     }
     H.L.clear();
     if (H.cinv) { ar.free(H.cinv); H.cinv = nullptr; }

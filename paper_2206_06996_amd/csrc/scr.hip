@@ -369,6 +369,7 @@ void scr_default_amg_opts(scr_amg_opts* o) {
     o->trunc = 0.3;
     o->pmax = 5;
     o->agg_levels = 2;
+    o->l1_gs = 1;
 }
 
 void scr_default_solve_opts(scr_solve_opts* o) {
@@ -484,9 +485,10 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         if (o.amg_type != SCR_AMG_SA && o.amg_type != SCR_AMG_CLASSICAL) throw Error(SCR_E_INVALID, "amg_type");
         if (o.amg_type == SCR_AMG_CLASSICAL &&
             (o.precision != SCR_FP64 || !(o.cl_theta > 0 && o.cl_theta <= 1) || !(o.trunc >= 0 && o.trunc < 1) ||
-             o.pmax < 1 || o.pmax > 16 || o.agg_levels < 0 || o.agg_levels > 16))
+             o.pmax < 1 || o.pmax > 16 || o.agg_levels < 0 || o.agg_levels > 16 ||
+             (o.l1_gs != 0 && o.l1_gs != 1)))
             throw Error(SCR_E_INVALID,
-                        "classical AMG: FP64 only, 0 < cl_theta <= 1, 0 <= trunc < 1, 1 <= pmax <= 16, 0 <= agg_levels <= 16");
+                        "classical AMG: FP64 only, 0 < cl_theta <= 1, 0 <= trunc < 1, 1 <= pmax <= 16, 0 <= agg_levels <= 16, l1_gs 0 or 1");
         h->ar.reset(new Arena(&ctx->c, s));
         Arena& ar = *h->ar;
         const int64_t nb = K->n_brows;

@@ -109,6 +109,7 @@ struct LevelSetup {
     double* Dinv = nullptr;
     double* B = nullptr;
     uint8_t* func = nullptr;         // classical AMG: the function (unknown) of each scalar row
+    double* ell = nullptr;           // classical AMG, l1 smoother: the l1 term of each row's diagonal
     double lam = 0.0;
     // kept for the numeric re-setup: aggregate member lists and the pattern of A P (no values)
     int32_t *mrp = nullptr, *mem = nullptr;

@@ -51,7 +51,7 @@ class AmgOpts(C.Structure):
                 ("max_levels", C.c_int), ("max_coarse_ratio", C.c_double), ("seed", C.c_uint64),
                 ("schur_diag", C.c_int), ("schur_cheb_degree", C.c_int), ("schur_cheb_ratio", C.c_double),
                 ("amg_type", C.c_int), ("cl_theta", C.c_double), ("trunc", C.c_double), ("pmax", C.c_int),
-                ("agg_levels", C.c_int)]
+                ("agg_levels", C.c_int), ("l1_gs", C.c_int)]
 
 
 class SolveOpts(C.Structure):

@@ -3,7 +3,7 @@ paper's table in Sec. 5.2) with the oracle's (oracle.c, amg_type = 1), through t
 
 Bars: every level's strength flags, C/F split (coarse indices), functions and the patterns of A,
 P and R bit-exact (the first two levels coarsened aggressively by default, with cases of
-none and of every level aggressive), and the values of P and of every coarse A bit-exact too (both sides evaluate
+none and of every level aggressive; the l1 hybrid Gauss-Seidel by default, the plain one too), and the values of P and of every coarse A bit-exact too (both sides evaluate
 the interpolation and the Galerkin sums in the same order without fused multiply-adds); one
 V-cycle within 1e-12 (the hybrid Gauss-Seidel sweeps sum each row in a different order); SCR and
 mesh solves with the FP64 iteration counts of the oracle, per-field errors within 1e-6 of the
@@ -77,11 +77,12 @@ def _same(hg, which, ho):
           f"bit-exact", flush=True)
 
 
-@pytest.mark.parametrize("case,agg", [("small_fsi", 2), ("small_fsi", 0), ("cfg0", 2), ("cfg0", 0)])
-def test_scr_hierarchies_bit_exact(scr, ctx, case, agg, small_fsi, cfg0):
+@pytest.mark.parametrize("case,agg,l1", [("small_fsi", 2, 1), ("small_fsi", 0, 0), ("cfg0", 2, 1), ("cfg0", 0, 1)])
+def test_scr_hierarchies_bit_exact(scr, ctx, case, agg, l1, small_fsi, cfg0):
     s = {"small_fsi": small_fsi, "cfg0": cfg0}[case]
     kw = dict(coarse_max=60) if case == "small_fsi" else {}
     kw["agg_levels"] = agg
+    kw["l1_gs"] = l1
     h = _gpu_scr(scr, ctx, s, **kw)
     o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(amg_type=1, **kw))
     _same(h, 0, o.amgA)
@@ -89,11 +90,11 @@ def test_scr_hierarchies_bit_exact(scr, ctx, case, agg, small_fsi, cfg0):
     h.destroy()
 
 
-@pytest.mark.parametrize("coarse_max,agg", [(64, 2), (1024, 2), (64, 0), (64, 1), (8, 16)])
-def test_mesh_hierarchy_bit_exact_and_vcycle(scr, ctx, cfg0, coarse_max, agg):
+@pytest.mark.parametrize("coarse_max,agg,l1", [(64, 2, 1), (1024, 2, 1), (64, 0, 0), (64, 1, 1), (8, 16, 0)])
+def test_mesh_hierarchy_bit_exact_and_vcycle(scr, ctx, cfg0, coarse_max, agg, l1):
     s = cfg0
-    h = _gpu_mesh(scr, ctx, s, coarse_max=coarse_max, agg_levels=agg)
-    o = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, coarse_max=coarse_max, agg_levels=agg))
+    h = _gpu_mesh(scr, ctx, s, coarse_max=coarse_max, agg_levels=agg, l1_gs=l1)
+    o = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1, coarse_max=coarse_max, agg_levels=agg, l1_gs=l1))
     _same(h, 2, o.amg)
     rng = np.random.default_rng(2)
     x = rng.uniform(-1, 1, s.n_phys)
@@ -166,6 +167,6 @@ def test_update_equals_fresh_setup_and_options(scr, ctx, small_fsi):
     h.destroy()
     # classical is FP64 only; option ranges are checked
     for kw in (dict(precision=1), dict(pmax=0), dict(pmax=17), dict(cl_theta=0.0), dict(trunc=1.0),
-               dict(agg_levels=-1), dict(agg_levels=17)):
+               dict(agg_levels=-1), dict(agg_levels=17), dict(l1_gs=2)):
         with pytest.raises(scr.ScrError):
             _gpu_scr(scr, ctx, s, **kw)
