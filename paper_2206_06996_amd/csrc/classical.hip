@@ -538,52 +538,131 @@ __global__ void l1_diag_k(int64_t nr, const int32_t* __restrict__ rp, const int3
 // One sweep: x_i = (b_i - sum_{j != i} a_ij x~_j + ell_i xold_i) dinv_i, x~_j new for rows of the
 // same domain already swept (forward: j < i; backward: j > i), else the previous iterate xold
 // (nullptr: 0); ell nullptr and dinv = 1 / a_ii for the plain sweep, the l1 terms otherwise.
-// NC node-interleaved columns (entry NC i + c).  One wavefront per domain of GS_DOM rows.
+// NC node-interleaved columns (entry NC i + c).  One wavefront per domain of GS_DOM rows, in two
+// phases so that no load waits in the sweep's chain of dependencies:
+//  1. every row of the domain (8 lanes per row, 8 rows at a time, no dependency between rows): its
+//     sum over the couplings that take the previous iterate, and its couplings to rows earlier in
+//     the sweep (the fresh ones) into LDS as the strictly lower triangle in sweep order, packed by
+//     columns;
+//  2. over the sweep positions q: lane q forms its new value, it is broadcast, and every later
+//     position subtracts its coupling to it (the fresh part of each row's sum, in sweep order).
+constexpr int GS_TRI = GS_DOM * (GS_DOM - 1) / 2;
+constexpr int GS_WPB = 2;           // wavefronts (domains) per workgroup
+constexpr int GS_U = 8;             // row entries per lane in flight in the first phase
+static_assert(GS_DOM == WAVE, "one lane per row of a domain");
+
+// slot of the coupling of sweep position p to position q < p (column-packed strict lower triangle)
+__device__ __forceinline__ int gs_tri(int p, int q) { return (GS_DOM - 1) * q - q * (q - 1) / 2 + (p - q - 1); }
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 template <int NC, bool BWD>
-__global__ void __launch_bounds__(256) hgs_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                             const double* __restrict__ v, const double* __restrict__ dinv,
-                                             const double* __restrict__ ell, const double* __restrict__ b,
-                                             const double* __restrict__ xold, double* __restrict__ x) {
+__global__ void __launch_bounds__(GS_WPB * WAVE) hgs_k(int64_t nr, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                     const double* __restrict__ dinv, const double* __restrict__ ell,
+                                                     const double* __restrict__ b, const double* __restrict__ xold,
+                                                     double* __restrict__ x) {
+    __shared__ double F[GS_WPB][GS_TRI];
+    const int wv = threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * (256 / WAVE) + threadIdx.x / WAVE;
+    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * GS_WPB + wv;
     const int64_t lo = d * GS_DOM;
-    if (lo >= nr) return;
-    const int64_t hi = lo + GS_DOM < nr ? lo + GS_DOM : nr;
-    double xn[NC];
+    const bool act = lo < nr;         // no early return: every wavefront reaches the barriers
+    const int64_t hi = act ? (lo + GS_DOM < nr ? lo + GS_DOM : nr) : lo;
+    const int n = (int)(hi - lo);
+    double* Fw = F[wv];
+    for (int e = lane; e < GS_TRI; e += WAVE) Fw[e] = 0.0;
+    __syncthreads();
+    // phase 1
+    const int grp = lane >> 3, gl = lane & 7;
+    // the row extent of sweep position `lane`, handed to the eight lanes of its group below
+    const int64_t il = BWD ? hi - 1 - lane : lo + lane;
+    const int32_t rs = lane < n ? rp[il] : 0, re = lane < n ? rp[il + 1] : 0;
+    double so[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) xn[c] = 0.0;
-    for (int64_t t = 0; t < hi - lo; ++t) {
-        const int64_t i = BWD ? hi - 1 - t : lo + t;
+    for (int c = 0; c < NC; ++c) so[c] = 0.0;
+    for (int k = 0; k < GS_DOM / 8; ++k) {
+        const int t = 8 * k + grp;     // this group's sweep position
+        const int32_t qs = __shfl(rs, t, WAVE), qe = __shfl(re, t, WAVE);
         double acc[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-        const int32_t q0 = rp[i], q1 = rp[i + 1];
-        for (int32_t base = q0; base < q1; base += WAVE) {
-            const int32_t q = base + lane;
-            const bool valid = q < q1;
-            const int64_t j = valid ? ci[q] : i;
-            const double a = valid ? v[q] : 0.0;
-            const bool in_dom = j >= lo && j < hi;
-            const bool fresh = in_dom && (BWD ? j > i : j < i);
-            const int src = in_dom ? (int)(j - lo) : 0;
+        if (t < n) {
+            const int64_t i = BWD ? hi - 1 - t : lo + t;
+            // GS_U entries per lane and step; every load of a step is issued before any is used (the
+            // index is clamped to the row's last entry, so the loads need no branch)
+            for (int32_t q = qs + gl; q < qe; q += 8 * GS_U) {
+                int32_t jj[GS_U];
+                double aa[GS_U];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double xf = __shfl(xn[c], src, WAVE);
-                const double xo = (!fresh && valid && xold != nullptr) ? xold[NC * j + c] : 0.0;
-                if (valid && j != i) acc[c] += a * (fresh ? xf : xo);
+                for (int u = 0; u < GS_U; ++u) {
+                    const int32_t qq = q + 8 * u < qe ? q + 8 * u : qe - 1;
+                    jj[u] = ci[qq];
+                    aa[u] = v[qq];
+                }
+                double xx[GS_U][NC];
+                bool old[GS_U], fresh[GS_U];
+                int pjs[GS_U];
+#pragma unroll
+                for (int u = 0; u < GS_U; ++u) {
+                    const bool real = q + 8 * u < qe;
+                    const int64_t j = jj[u];
+                    const bool in_dom = j >= lo && j < hi;
+                    pjs[u] = in_dom ? (BWD ? (int)(hi - 1 - j) : (int)(j - lo)) : 0;
+                    fresh[u] = real && in_dom && pjs[u] < t;
+                    old[u] = real && !fresh[u] && j != i;
+                    const int64_t jc = old[u] ? j : i;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) xx[u][c] = xold != nullptr ? xold[NC * jc + c] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < GS_U; ++u) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[c] += old[u] ? aa[u] * xx[u][c] : 0.0;
+                    if (fresh[u]) Fw[gs_tri(t, pjs[u])] = aa[u];
+                }
             }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double sum = wave_sum(acc[c]);
-            double ti = b[NC * i + c] - sum;
-            if (ell != nullptr && xold != nullptr) ti = ti + ell[i] * xold[NC * i + c];
-            const double xi = ti * dinv[i];
-            if (lane == (int)(i - lo)) {
-                xn[c] = xi;
-                x[NC * i + c] = xi;
-            }
+            double s = acc[c];
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) s += __shfl_xor(s, o, WAVE);
+            // lane 8k + g takes the sum of group g (held by its first lane)
+            const double mine = __shfl(s, 8 * (lane & 7), WAVE);
+            if ((lane >> 3) == k) so[c] = mine;
         }
+    }
+    // the row at sweep position `lane`
+    const bool own = lane < n;
+    const int64_t ip = BWD ? hi - 1 - lane : lo + lane;
+    const double dv = own ? dinv[ip] : 0.0;
+    const double ev = (own && ell != nullptr && xold != nullptr) ? ell[ip] : 0.0;
+    double r[NC], xn[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        r[c] = own ? b[NC * ip + c] - so[c] : 0.0;
+        if (own && ell != nullptr && xold != nullptr) r[c] = r[c] + ev * xold[NC * ip + c];
+        xn[c] = 0.0;
+    }
+    __syncthreads();
+    // phase 2
+    for (int q = 0; q < n; ++q) {
+        const double f = (lane > q && lane < n) ? Fw[gs_tri(lane, q)] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (lane == q) xn[c] = r[c] * dv;
+            const double xq = readlane_f64(xn[c], q);
+            r[c] = r[c] - f * xq;
+        }
+    }
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[NC * ip + c] = xn[c];
     }
 }
 
@@ -591,10 +670,10 @@ template <int NC>
 void hgs(const DBsr& A, const double* Dinv, const double* ell, const double* b, const double* xold, double* x,
          bool backward, hipStream_t s) {
     const int64_t nd = cdiv(A.nr, GS_DOM);
-    const unsigned g = (unsigned)cdiv(nd, 256 / WAVE);
+    const unsigned g = (unsigned)cdiv(nd, GS_WPB);
     if (!g) return;
-    if (backward) hgs_k<NC, true><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
-    else hgs_k<NC, false><<<g, 256, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
+    if (backward) hgs_k<NC, true><<<g, GS_WPB * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
+    else hgs_k<NC, false><<<g, GS_WPB * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
     check_launch("hybrid_gs");
 }
 
