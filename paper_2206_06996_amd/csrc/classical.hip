@@ -538,18 +538,21 @@ __global__ void l1_diag_k(int64_t nr, const int32_t* __restrict__ rp, const int3
 // One sweep: x_i = (b_i - sum_{j != i} a_ij x~_j + ell_i xold_i) dinv_i, x~_j new for rows of the
 // same domain already swept (forward: j < i; backward: j > i), else the previous iterate xold
 // (nullptr: 0); ell nullptr and dinv = 1 / a_ii for the plain sweep, the l1 terms otherwise.
-// NC node-interleaved columns (entry NC i + c).  One wavefront per domain of GS_DOM rows, in two
+// NC node-interleaved columns (entry NC i + c).  One workgroup per domain of GS_DOM rows, in two
 // phases so that no load waits in the sweep's chain of dependencies:
-//  1. every row of the domain (8 lanes per row, 8 rows at a time, no dependency between rows): its
-//     sum over the couplings that take the previous iterate, and its couplings to rows earlier in
-//     the sweep (the fresh ones) into LDS as the strictly lower triangle in sweep order, packed by
-//     columns;
-//  2. over the sweep positions q: lane q forms its new value, it is broadcast, and every later
-//     position subtracts its coupling to it (the fresh part of each row's sum, in sweep order).
+//  1. every row of the domain (GS_W wavefronts, 8 lanes per row, GS_RB rows per lane group and GS_U
+//     entries per lane in flight; no dependency between rows): its sum over the couplings that take
+//     the previous iterate, into LDS, and its couplings to rows earlier in the sweep (the fresh
+//     ones) into LDS as the strictly lower triangle in sweep order, packed by columns;
+//  2. the first wavefront, over the sweep positions q: lane q forms its new value, it is broadcast,
+//     and every later position subtracts its coupling to it (the fresh part of each row's sum, in
+//     sweep order).
 constexpr int GS_TRI = GS_DOM * (GS_DOM - 1) / 2;
-constexpr int GS_WPB = 2;           // wavefronts (domains) per workgroup
+constexpr int GS_W = 8;             // wavefronts per domain in the first phase
 constexpr int GS_U = 8;             // row entries per lane in flight in the first phase
-static_assert(GS_DOM == WAVE, "one lane per row of a domain");
+constexpr int GS_RB = 1;            // rows per lane group in flight in the first phase
+static_assert(GS_DOM == WAVE, "one lane per row of a domain in the second phase");
+static_assert(GS_W * 8 * GS_RB == GS_DOM, "the first phase covers the domain in one pass");
 
 // slot of the coupling of sweep position p to position q < p (column-packed strict lower triangle)
 __device__ __forceinline__ int gs_tri(int p, int q) { return (GS_DOM - 1) * q - q * (q - 1) / 2 + (p - q - 1); }
@@ -561,98 +564,105 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 }
 
 template <int NC, bool BWD>
-__global__ void __launch_bounds__(GS_WPB * WAVE) hgs_k(int64_t nr, const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ ci, const double* __restrict__ v,
-                                                     const double* __restrict__ dinv, const double* __restrict__ ell,
-                                                     const double* __restrict__ b, const double* __restrict__ xold,
-                                                     double* __restrict__ x) {
-    __shared__ double F[GS_WPB][GS_TRI];
+__global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                   const double* __restrict__ dinv, const double* __restrict__ ell,
+                                                   const double* __restrict__ b, const double* __restrict__ xold,
+                                                   double* __restrict__ x) {
+    __shared__ double F[GS_TRI];
+    __shared__ double so_sh[NC][GS_DOM];
     const int wv = threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t d = xcd_tile(blockIdx.x, gridDim.x) * GS_WPB + wv;
-    const int64_t lo = d * GS_DOM;
-    const bool act = lo < nr;         // no early return: every wavefront reaches the barriers
-    const int64_t hi = act ? (lo + GS_DOM < nr ? lo + GS_DOM : nr) : lo;
+    const int64_t lo = xcd_tile(blockIdx.x, gridDim.x) * GS_DOM;     // the grid covers the rows exactly
+    const int64_t hi = lo + GS_DOM < nr ? lo + GS_DOM : nr;
     const int n = (int)(hi - lo);
-    double* Fw = F[wv];
-    for (int e = lane; e < GS_TRI; e += WAVE) Fw[e] = 0.0;
+    for (int e = threadIdx.x; e < GS_TRI; e += GS_W * WAVE) F[e] = 0.0;
     __syncthreads();
-    // phase 1
+    // phase 1: wavefront wv takes positions 8 (GS_RB wv + r) + grp, r < GS_RB
     const int grp = lane >> 3, gl = lane & 7;
-    // the row extent of sweep position `lane`, handed to the eight lanes of its group below
     const int64_t il = BWD ? hi - 1 - lane : lo + lane;
     const int32_t rs = lane < n ? rp[il] : 0, re = lane < n ? rp[il + 1] : 0;
-    double so[NC];
+    int tt[GS_RB];
+    int32_t qs[GS_RB], qe[GS_RB];
+    int64_t ii[GS_RB];
+    int32_t len = 0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) so[c] = 0.0;
-    for (int k = 0; k < GS_DOM / 8; ++k) {
-        const int t = 8 * k + grp;     // this group's sweep position
-        const int32_t qs = __shfl(rs, t, WAVE), qe = __shfl(re, t, WAVE);
-        double acc[NC];
+    for (int r = 0; r < GS_RB; ++r) {
+        tt[r] = 8 * (GS_RB * wv + r) + grp;
+        qs[r] = __shfl(rs, tt[r], WAVE);
+        qe[r] = __shfl(re, tt[r], WAVE);
+        ii[r] = BWD ? hi - 1 - tt[r] : lo + tt[r];
+        len = qe[r] - qs[r] > len ? qe[r] - qs[r] : len;
+    }
+    double acc[GS_RB][NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-        if (t < n) {
-            const int64_t i = BWD ? hi - 1 - t : lo + t;
-            // GS_U entries per lane and step; every load of a step is issued before any is used (the
-            // index is clamped to the row's last entry, so the loads need no branch)
-            for (int32_t q = qs + gl; q < qe; q += 8 * GS_U) {
-                int32_t jj[GS_U];
-                double aa[GS_U];
+    for (int r = 0; r < GS_RB; ++r)
 #pragma unroll
-                for (int u = 0; u < GS_U; ++u) {
-                    const int32_t qq = q + 8 * u < qe ? q + 8 * u : qe - 1;
-                    jj[u] = ci[qq];
-                    aa[u] = v[qq];
-                }
-                double xx[GS_U][NC];
-                bool old[GS_U], fresh[GS_U];
-                int pjs[GS_U];
+        for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
+    // every load of a step is issued before any is used (the index is clamped to the row's last
+    // entry, or to entry 0 for a row with none, so that the loads need no branch)
+    for (int32_t o = gl; o < len; o += 8 * GS_U) {
+        int32_t jj[GS_RB][GS_U];
+        double aa[GS_RB][GS_U];
 #pragma unroll
-                for (int u = 0; u < GS_U; ++u) {
-                    const bool real = q + 8 * u < qe;
-                    const int64_t j = jj[u];
-                    const bool in_dom = j >= lo && j < hi;
-                    pjs[u] = in_dom ? (BWD ? (int)(hi - 1 - j) : (int)(j - lo)) : 0;
-                    fresh[u] = real && in_dom && pjs[u] < t;
-                    old[u] = real && !fresh[u] && j != i;
-                    const int64_t jc = old[u] ? j : i;
+        for (int r = 0; r < GS_RB; ++r)
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) xx[u][c] = xold != nullptr ? xold[NC * jc + c] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < GS_U; ++u) {
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) acc[c] += old[u] ? aa[u] * xx[u][c] : 0.0;
-                    if (fresh[u]) Fw[gs_tri(t, pjs[u])] = aa[u];
-                }
+            for (int u = 0; u < GS_U; ++u) {
+                const int32_t q = qs[r] + o + 8 * u;
+                const int32_t qq = q < qe[r] ? q : (qe[r] > qs[r] ? qe[r] - 1 : 0);
+                jj[r][u] = ci[qq];
+                aa[r][u] = v[qq];
             }
-        }
+        double xx[GS_RB][GS_U][NC];
+        bool old[GS_RB][GS_U], fresh[GS_RB][GS_U];
+        int pjs[GS_RB][GS_U];
+#pragma unroll
+        for (int r = 0; r < GS_RB; ++r)
+#pragma unroll
+            for (int u = 0; u < GS_U; ++u) {
+                const bool real = qs[r] + o + 8 * u < qe[r];
+                const int64_t j = jj[r][u];
+                const bool in_dom = j >= lo && j < hi;
+                pjs[r][u] = in_dom ? (BWD ? (int)(hi - 1 - j) : (int)(j - lo)) : 0;
+                fresh[r][u] = real && in_dom && pjs[r][u] < tt[r];
+                old[r][u] = real && !fresh[r][u] && j != ii[r];
+                const int64_t jc = old[r][u] ? j : lo;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) xx[r][u][c] = xold != nullptr ? xold[NC * jc + c] : 0.0;
+            }
+#pragma unroll
+        for (int r = 0; r < GS_RB; ++r)
+#pragma unroll
+            for (int u = 0; u < GS_U; ++u) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[r][c] += old[r][u] ? aa[r][u] * xx[r][u][c] : 0.0;
+                if (fresh[r][u]) F[gs_tri(tt[r], pjs[r][u])] = aa[r][u];
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < GS_RB; ++r)
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            double s = acc[c];
+            double s = acc[r][c];
 #pragma unroll
-            for (int o = 1; o < 8; o <<= 1) s += __shfl_xor(s, o, WAVE);
-            // lane 8k + g takes the sum of group g (held by its first lane)
-            const double mine = __shfl(s, 8 * (lane & 7), WAVE);
-            if ((lane >> 3) == k) so[c] = mine;
+            for (int w = 1; w < 8; w <<= 1) s += __shfl_xor(s, w, WAVE);
+            if (gl == 0) so_sh[c][tt[r]] = s;
         }
-    }
-    // the row at sweep position `lane`
+    __syncthreads();
+    if (wv != 0) return;
+    // phase 2 (first wavefront): the row at sweep position `lane`
     const bool own = lane < n;
-    const int64_t ip = BWD ? hi - 1 - lane : lo + lane;
-    const double dv = own ? dinv[ip] : 0.0;
-    const double ev = (own && ell != nullptr && xold != nullptr) ? ell[ip] : 0.0;
+    const double dv = own ? dinv[il] : 0.0;
+    const double ev = (own && ell != nullptr && xold != nullptr) ? ell[il] : 0.0;
     double r[NC], xn[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        r[c] = own ? b[NC * ip + c] - so[c] : 0.0;
-        if (own && ell != nullptr && xold != nullptr) r[c] = r[c] + ev * xold[NC * ip + c];
+        r[c] = own ? b[NC * il + c] - so_sh[c][lane] : 0.0;
+        if (own && ell != nullptr && xold != nullptr) r[c] = r[c] + ev * xold[NC * il + c];
         xn[c] = 0.0;
     }
-    __syncthreads();
-    // phase 2
     for (int q = 0; q < n; ++q) {
-        const double f = (lane > q && lane < n) ? Fw[gs_tri(lane, q)] : 0.0;
+        const double f = (lane > q && lane < n) ? F[gs_tri(lane, q)] : 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (lane == q) xn[c] = r[c] * dv;
@@ -662,18 +672,17 @@ __global__ void __launch_bounds__(GS_WPB * WAVE) hgs_k(int64_t nr, const int32_t
     }
     if (own) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) x[NC * ip + c] = xn[c];
+        for (int c = 0; c < NC; ++c) x[NC * il + c] = xn[c];
     }
 }
 
 template <int NC>
 void hgs(const DBsr& A, const double* Dinv, const double* ell, const double* b, const double* xold, double* x,
          bool backward, hipStream_t s) {
-    const int64_t nd = cdiv(A.nr, GS_DOM);
-    const unsigned g = (unsigned)cdiv(nd, GS_WPB);
+    const unsigned g = (unsigned)cdiv(A.nr, GS_DOM);     // one workgroup per domain
     if (!g) return;
-    if (backward) hgs_k<NC, true><<<g, GS_WPB * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
-    else hgs_k<NC, false><<<g, GS_WPB * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
+    if (backward) hgs_k<NC, true><<<g, GS_W * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
+    else hgs_k<NC, false><<<g, GS_W * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
     check_launch("hybrid_gs");
 }
 
