@@ -111,7 +111,7 @@ typedef struct {
                                   interpolation truncated at trunc and to pmax entries per row (row
                                   sums kept).  Smoother: one hybrid Gauss-Seidel sweep before (forward)
                                   and after (backward) the coarse correction, Gauss-Seidel inside
-                                  domains of 64 rows (one wavefront each), Jacobi between them; in
+                                  domains of 64 rows (one workgroup each), Jacobi between them; in
                                   its l1 form (l1_gs) each row's diagonal gains the absolute values
                                   of its couplings outside its domain, which keeps the sweep
                                   convergent for any symmetric positive definite matrix.

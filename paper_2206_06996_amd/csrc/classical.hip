@@ -1,15 +1,17 @@
 // classical.hip -- classical AMG on the device with the settings of the paper's table of
 // BoomerAMG options (Sec. 5.2): classical strength (threshold 0.5), HMIS coarsening, extended+i
-// interpolation truncated at 0.3 with at most 5 entries per row, hybrid Gauss-Seidel smoothing,
-// V-cycle with Galerkin coarse operators and a direct coarsest solve.
+// interpolation truncated at 0.3 with at most 5 entries per row, aggressive (two-stage) coarsening
+// on the first levels, hybrid Gauss-Seidel smoothing (l1 form by default), V-cycle with Galerkin
+// coarse operators and a direct coarsest solve.
 //
 // Mapping to the chip.  HMIS's per-processor first pass (Ruge-Stueben) runs with one workgroup
 // per domain of 256 consecutive rows: the measures and states live in LDS, each step picks the
 // domain's largest measure by a workgroup reduction, and the C/F updates are LDS integer atomics
 // (order-free, so the result is that of the sequential pass).  The PMIS rounds and extended+i are
-// row-parallel.  Hybrid Gauss-Seidel gives each wavefront a domain of 64 rows: the rows are swept
-// in order, the lanes split each row's entries, and a row's new value stays in the register of
-// the lane that owns it, where the later rows of the domain read it by a cross-lane permute.
+// row-parallel.  Hybrid Gauss-Seidel gives each workgroup a domain of 64 rows: its wavefronts
+// first gather, with no dependency between rows, every row's previous-iterate sum and its
+// couplings to earlier rows of the sweep into LDS; one wavefront then sweeps the domain with one
+// lane per row, each new value broadcast to the later lanes, so no global load sits in the chain.
 // Interpolation weights, their truncation and the Galerkin products are evaluated in the
 // definitions' order without fused multiply-adds (this file is built with -ffp-contract=off), so
 // every level's split, pattern and values are those of a sequential evaluation.
@@ -22,7 +24,7 @@ namespace scr {
 namespace {
 
 constexpr int HMIS_DOM = 256;      // rows per HMIS domain (one workgroup)
-constexpr int GS_DOM = 64;         // rows per hybrid Gauss-Seidel domain (one wavefront)
+constexpr int GS_DOM = 64;         // rows per hybrid Gauss-Seidel domain (one workgroup; one lane per row in its sequential phase)
 constexpr int8_t ST_U = 0, ST_C = 1, ST_F = 2, ST_NEWF = 3;
 
 // ------------------------------------------------------------------ set-up kernels
