@@ -170,3 +170,37 @@ def test_update_equals_fresh_setup_and_options(scr, ctx, small_fsi):
                dict(agg_levels=-1), dict(agg_levels=17), dict(l1_gs=2)):
         with pytest.raises(scr.ScrError):
             _gpu_scr(scr, ctx, s, **kw)
+
+
+def test_single_level_and_isolated_rows(scr, ctx, tiny):
+    """Degenerate hierarchies: a system no larger than coarse_max is one level (the direct solve),
+    and a matrix with no couplings (all rows isolated: no strong dependencies, no C points) stops
+    coarsening at level 0 whatever coarse_max says."""
+    from tests.conftest import bsr_to_dense
+    s = tiny
+    h = _gpu_scr(scr, ctx, s)
+    assert h.hier_levels(0) == 1 and h.hier_levels(1) == 1
+    b = synth.rhs(31, 4 * s.n_b, s.mask)
+    x = torch.zeros(4 * s.n_b, dtype=torch.float64, device="cuda")
+    # tol 1e-10: this system (condition number 2e9) has its rounding floor near 1.5e-12
+    rc, st = scr.scr_solve(h, dev(b), x, scr.solve_opts(tol=1e-10))
+    assert rc == 0
+    assert_fields(host(x), np.linalg.solve(bsr_to_dense(s.rp, s.ci, s.val), b), 1e-8, "classical one level")
+    x0 = torch.full_like(x, 3.0)
+    rc, st = scr.scr_solve(h, torch.zeros_like(x), x0)
+    assert rc == 0 and st["outer_it"] == 0 and not host(x0).any()
+    h.destroy()
+    n = s.n_phys
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    d = np.linspace(1.0, 2.0, n)
+    print(f"[gpu] classical amg_setup MESH diagonal n={n} coarse_max=8", flush=True)
+    hm = scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(rp), dev(ci), dev(d), None,
+                       scr.amg_opts(amg_type=scr.SCR_AMG_CLASSICAL, coarse_max=8))
+    assert hm.hier_levels(2) == 1
+    bm = synth.rhs(32, 3 * n, None)
+    xm = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    rc, st = scr.mesh_motion_solve(hm, dev(bm), xm)
+    assert rc == 0 and max(st["mesh_its"]) <= 1
+    assert np.allclose(host(xm), bm / np.repeat(d, 3), rtol=1e-14, atol=0)
+    hm.destroy()
