@@ -98,7 +98,9 @@ typedef struct {
     int schur_diag;            /* SCR_SYSTEM: the diagonal d in S^ = C - D d^-1 G (Sec. 5.2.1):
                                   SCR_DIAG_A (default) the diagonal of A; SCR_DIAG_ABSROWSUM the sums
                                   of the absolute values of A's rows (the SIMPLEC lumping) */
-    int schur_cheb_degree;     /* SCR_SYSTEM: Chebyshev degree of AMG(S^), 8 (0 = cheb_degree) */
+    int schur_cheb_degree;     /* SCR_SYSTEM: Chebyshev degree of AMG(S^); -1 (default): by the size of
+                                  S^ (8 up to 1,000,000 rows, 12 up to 3,000,000, 16 above);
+                                  0 = cheb_degree */
     double schur_cheb_ratio;   /* SCR_SYSTEM: Chebyshev interval ratio of AMG(S^), 100 (0 = cheb_ratio) */
     int amg_type;              /* SCR_AMG_SA (default) or SCR_AMG_CLASSICAL: the BoomerAMG settings of
                                   Sec. 5.2's table on the device.  Strength: row i depends on j (same

@@ -66,7 +66,7 @@ def amg_opts(**kw) -> AmgOpts:
     at 0.3 with at most 5 entries, hybrid Gauss-Seidel on domains of 64 rows)."""
     o = AmgOpts(theta=0.08, smoother=1, cheb_degree=4, cheb_ratio=30.0, jacobi_sweeps=2,
                 coarse_max=1024, max_levels=10, max_coarse_ratio=0.8, seed=0, schur_diag=0,
-                schur_cheb_degree=8, schur_cheb_ratio=100.0, amg_type=0, cl_theta=0.5, trunc=0.3, pmax=5,
+                schur_cheb_degree=-1, schur_cheb_ratio=100.0, amg_type=0, cl_theta=0.5, trunc=0.3, pmax=5,
                 hmis_domain=256, gs_domain=64, agg_levels=2, l1_gs=1)
     for k, v in kw.items():
         setattr(o, k, v)

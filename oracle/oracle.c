@@ -255,7 +255,8 @@ typedef struct {
     uint64_t seed;
     int schur_diag;      /* SCR system setup: diagonal used in S^ = C - D d^-1 G:
                             0 the diagonal of A (SCR, SIMPLE), 1 absolute row sums of A (SIMPLEC) */
-    int schur_cheb_degree;     /* SCR system: Chebyshev degree of AMG(S^) (0 = cheb_degree) */
+    int schur_cheb_degree;     /* SCR system: Chebyshev degree of AMG(S^) (0 = cheb_degree; -1 = by the
+                                  size of S^: 8 up to 1e6 rows, 12 up to 3e6, 16 above) */
     double schur_cheb_ratio;   /* SCR system: Chebyshev interval ratio of AMG(S^) (0 = cheb_ratio) */
     int amg_type;        /* 0 smoothed aggregation, 1 classical (the paper's settings) */
     double cl_theta;     /* classical strength threshold, 0.5 */
@@ -1890,7 +1891,9 @@ int orc_scr_create(int64_t nb, const int32_t* rp, const int32_t* ci, const doubl
     double* ones = (double*)malloc(sizeof(double) * nb);
     for (int64_t i = 0; i < nb; ++i) ones[i] = 1.0;
     amg_opts oS = *ao;
-    if (ao->schur_cheb_degree > 0) oS.cheb_degree = ao->schur_cheb_degree;
+    int sdeg = ao->schur_cheb_degree;
+    if (sdeg < 0) sdeg = nb <= 1000000 ? 8 : (nb <= 3000000 ? 12 : 16);
+    if (sdeg > 0) oS.cheb_degree = sdeg;
     if (ao->schur_cheb_ratio > 0) oS.cheb_ratio = ao->schur_cheb_ratio;
     s->amgS = amg_build(s->Sh, ones, 1, &oS);
     free(ones);

@@ -348,6 +348,11 @@ void check_opts(const scr_solve_opts& o) {
 
 }  // namespace
 
+// Chebyshev degree of AMG(S^) when the options leave it to the size of S^ (measured on the test
+// tubes and the Y: each Schur iteration saved also saves an inner A solve of Algorithm 2, which
+// pays for a stronger Schur smoother on the larger meshes, where the Schur counts grow)
+static int schur_degree_by_size(int64_t n) { return n <= 1000000 ? 8 : (n <= 3000000 ? 12 : 16); }
+
 extern "C" {
 
 void scr_default_amg_opts(scr_amg_opts* o) {
@@ -355,7 +360,7 @@ void scr_default_amg_opts(scr_amg_opts* o) {
     o->theta = 0.08;
     o->smoother = SCR_SMOOTH_CHEBYSHEV;
     o->cheb_degree = 4;
-    o->schur_cheb_degree = 8;
+    o->schur_cheb_degree = -1;
     o->schur_cheb_ratio = 100.0;
     o->cheb_ratio = 30.0;
     o->jacobi_sweeps = 2;
@@ -479,7 +484,7 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
         if (o.precision != SCR_FP64 && o.precision != SCR_MIXED && o.precision != SCR_MIXED_FP32_INNER)
             throw Error(SCR_E_INVALID, "precision");
         if (!(o.theta > 0) || o.coarse_max < 1 || o.max_levels < 1 || o.cheb_degree < 1 || o.jacobi_sweeps < 1 ||
-            !(o.cheb_ratio > 1) || !(o.max_coarse_ratio > 0) || o.schur_cheb_degree < 0 ||
+            !(o.cheb_ratio > 1) || !(o.max_coarse_ratio > 0) || o.schur_cheb_degree < -1 ||
             !(o.schur_cheb_ratio == 0.0 || o.schur_cheb_ratio > 1))
             throw Error(SCR_E_INVALID, "AMG options out of range");
         if (o.amg_type != SCR_AMG_SA && o.amg_type != SCR_AMG_CLASSICAL) throw Error(SCR_E_INVALID, "amg_type");
@@ -536,7 +541,8 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
             // AMG(S^) with its own Chebyshev settings: its V-cycles are cheap (scalar, small), and
             // each Schur iteration saved also saves an inner A solve of Algorithm 2
             scr_amg_opts oS = o;
-            if (o.schur_cheb_degree > 0) oS.cheb_degree = o.schur_cheb_degree;
+            const int sdeg = o.schur_cheb_degree >= 0 ? o.schur_cheb_degree : schur_degree_by_size(nb);
+            if (sdeg > 0) oS.cheb_degree = sdeg;
             if (o.schur_cheb_ratio > 0) oS.cheb_ratio = o.schur_cheb_ratio;
             h->hS = build_hierarchy(h->Sh, ones, 1, oS, ar, s);
             ar.free(ones);

@@ -32,7 +32,7 @@ def test_status_strings_and_defaults_without_gpu():
     L = scr.lib()
     assert L.scr_status_str(scr.SCR_E_INVALID) == b"invalid input"
     o = scr.amg_opts()
-    assert o.precision == scr.SCR_FP64 and o.smoother == scr.SCR_SMOOTH_CHEBYSHEV and o.cheb_degree == 4 and o.schur_cheb_degree == 8 and o.schur_cheb_ratio == 100.0
+    assert o.precision == scr.SCR_FP64 and o.smoother == scr.SCR_SMOOTH_CHEBYSHEV and o.cheb_degree == 4 and o.schur_cheb_degree == -1 and o.schur_cheb_ratio == 100.0
     so = scr.solve_opts()
     assert so.tol == 1e-8 and so.tol_A == so.tol_S == so.tol_I == 1e-3 and so.max_it == 200
     assert scr.footprint_estimate(scr.SCR_SYSTEM, 1000, 14000) > 14000 * 132

@@ -157,7 +157,7 @@ def test_schur_smoother_options_parity(scr, ctx, small_fsi, deg, ratio):
 
 
 def test_invalid_schur_smoother_options_rejected(scr, ctx, small_fsi):
-    for kw in (dict(schur_cheb_degree=-1), dict(schur_cheb_ratio=0.5)):
+    for kw in (dict(schur_cheb_degree=-2), dict(schur_cheb_ratio=0.5)):
         with pytest.raises(scr.ScrError) as e:
             gpu_setup(scr, ctx, small_fsi, **kw)
         assert e.value.status == scr.SCR_E_INVALID
