@@ -2,7 +2,8 @@
 the FP64 oracle of the predictor multi-corrector (oracle/corrector.py), through the C ABI.
 
 The oracle solves each corrector system and the mesh motion exactly (sparse LU); the device solves
-them iteratively (scr_solve to 1e-10, the mesh CG to 1e-12), so every field of the state is
+them iteratively (with smoothed-aggregation AMG in FP64 and mixed precision, and with the classical
+AMG option) (scr_solve to 1e-10, the mesh CG to 1e-12), so every field of the state is
 compared per field at 1e-7 relative to its own norm after every step.  The step count of
 correctors (2 for this linear model: one Newton step, then the test that passes), the re-setup on
 a change of dt and the state copies are checked as well.
@@ -49,15 +50,15 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def _pair(scr, ctx, tube, dt0, precision=0, max_correctors=10):
+def _pair(scr, ctx, tube, dt0, precision=0, max_correctors=10, amg_type=0):
     p, s, s_free = tube
-    print(f"[gpu] stepper n_b={s.n_b} n_L={s.n_phys} dt0={dt0} precision={precision}", flush=True)
+    print(f"[gpu] stepper n_b={s.n_b} n_L={s.n_phys} dt0={dt0} precision={precision} amg_type={amg_type}", flush=True)
     a = scr.scr_assembler_create(ctx, dev(s.tv), dev(s.tp), dev(s.tsolid), dev(s.rp), dev(s.ci), dev(s.xyz),
                                  dev(s.mask), scr.tangent_params(**asm.params_of(p)))
     solid = cor.solid_rows_of(s)
     st = scr.scr_stepper_create(ctx, a, dev(s.Lrp), dev(s.Lci), dev(s.Lval), dev(s_free.Lval), dev(s.Lmask),
                                 dev(s.blk_of_phys), dev(solid), dev(s.xyz.reshape(-1)), dt0,
-                                amg=scr.amg_opts(precision=precision), solve=scr.solve_opts(tol=1e-10),
+                                amg=scr.amg_opts(precision=precision, amg_type=amg_type), solve=scr.solve_opts(tol=1e-10),
                                 copts=scr.corrector_opts(mesh_tol=1e-12, max_correctors=max_correctors))
     orc = cor.Stepper(cor.assembled_operators(s, asm.params_of(p)), solid, cor.scalar_csr(s.Lrp, s.Lci, s_free.Lval),
                       s.Lmask, s.blk_of_phys, p.rho_inf, dt0, max_correctors=max_correctors)
@@ -81,10 +82,10 @@ def _compare(st, orc, tol, what):
     return worst
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_steps_match_oracle(scr, ctx, tube, precision):
+@pytest.mark.parametrize("precision,amg_type", [(0, 0), (1, 0), (0, 1)])
+def test_steps_match_oracle(scr, ctx, tube, precision, amg_type):
     p, s, _ = tube
-    a, st, orc = _pair(scr, ctx, tube, 1e-3, precision)
+    a, st, orc = _pair(scr, ctx, tube, 1e-3, precision, amg_type=amg_type)
     for n, dt in enumerate([1e-3, 1e-3, 5e-4, 5e-4]):
         f = synth.rhs(100 + n, 3 * s.n_b)
         rc, gs = st.step(dt, dev(f))
