@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--amg", action="append", default=[], metavar="KEY=VALUE",
                     help="override an scr_amg_opts field for every hierarchy (repeatable), e.g. --amg theta=0.04")
     ap.add_argument("--dump-levels", metavar="JSON", default=None,
-                    help="write the FP64 hierarchy sizes (AMG(A), AMG(S^), AMG(L)) and the first step's V-cycle "
+                    help="write the hierarchy sizes (AMG(A), AMG(S^), AMG(L)) and the first step's V-cycle "
                          "counts to JSON (for --kernel-table)")
     ap.add_argument("--kernel-table", nargs=2, metavar=("TRACE_DIR", "LEVELS_JSON"), default=None,
                     help="CPU only: per-kernel table (time, algorithmic bytes, GB/s) from a rocprofv3 kernel trace "
@@ -203,50 +203,51 @@ def _kt_bytes(levels):
                 add("dense_mv_k<double>", ceil(n / 4) * 256, 8.0 * n * n + 16.0 * n, f"{name}{l} coarse")
                 add("dense_mv3_k<double>", ceil(n / 4) * 256, 8.0 * n * n + 48.0 * n, f"{name}{l} coarse")
                 continue
-            mat = nnz * (b * b * 8.0 + 4.0)
-            vec = b * 8.0
-            for rd in (0, 1):
-                for wd in (0, 1):
-                    byts = mat + nr * (4.0 + vec * (3 + rd + wd))
-                    zero = nr * (4.0 + vec * (2 + wd))
+            for tn, tb in (("double", 8.0), ("float", 4.0)):     # FP64 and the mixed form's FP32 V-cycle
+                mat = nnz * (b * b * tb + 4.0)
+                vec = b * tb
+                for rd in (0, 1):
+                    for wd in (0, 1):
+                        byts = mat + nr * (4.0 + vec * (3 + rd + wd))
+                        zero = nr * (4.0 + vec * (2 + wd))
+                        if b == 3 and l == 0:
+                            g = ceil(ceil(nr / 64) / 4) * 256
+                            add(f"smooth_rl3_k<{tn},{rd},{wd},0>", g, byts, f"{name}{l}")
+                            add(f"smooth_rl3_k<{tn},0,{wd},1>", g, zero, f"{name}{l}")
+                        for w in (1, 2, 4, 8, 16):
+                            add(f"smooth_k<{tn},{b},{rd},{wd},0,{w}>", slice_grid(nr, b, w), byts, f"{name}{l}")
+                            add(f"smooth_k<{tn},{b},0,{wd},1,{w}>", slice_grid(nr, b, w), zero, f"{name}{l}")
+                            if b == 1:
+                                add(f"smooth3_k<{tn},{rd},{wd},0,{w}>", slice_grid(nr, 1, w),
+                                    nnz * (tb + 4.0) + nr * (4.0 + 3 * tb * (3 + rd + wd)), f"{name}{l}")
+                                add(f"smooth3_k<{tn},0,{wd},1,{w}>", slice_grid(nr, 1, w), nr * (4.0 + 3 * tb * (2 + wd)),
+                                    f"{name}{l}")
+                # products with A_l (residual y = b - A x: x, b read, y written)
+                for mode in (0, 1, 3):
+                    nv = 2 if mode == 0 else 3
+                    byts = mat + nr * (4.0 + vec * nv)
                     if b == 3 and l == 0:
-                        g = ceil(ceil(nr / 64) / 4) * 256
-                        add(f"smooth_rl3_k<double,{rd},{wd},0>", g, byts, f"{name}{l}")
-                        add(f"smooth_rl3_k<double,0,{wd},1>", g, zero, f"{name}{l}")
+                        add(f"sell_mv_rl3_k<{tn},3,{mode}>", ceil(ceil(nr / 64) / 4) * 256, byts, f"{name}{l} A")
                     for w in (1, 2, 4, 8, 16):
-                        add(f"smooth_k<double,{b},{rd},{wd},0,{w}>", slice_grid(nr, b, w), byts, f"{name}{l}")
-                        add(f"smooth_k<double,{b},0,{wd},1,{w}>", slice_grid(nr, b, w), zero, f"{name}{l}")
+                        add(f"sell_mv_k<{tn},{b},{b},{mode},{w}>", slice_grid(nr, b, w), byts, f"{name}{l} A")
                         if b == 1:
-                            add(f"smooth3_k<double,{rd},{wd},0,{w}>", slice_grid(nr, 1, w),
-                                nnz * 12.0 + nr * (4.0 + 24.0 * (3 + rd + wd)), f"{name}{l}")
-                            add(f"smooth3_k<double,0,{wd},1,{w}>", slice_grid(nr, 1, w), nr * (4.0 + 24.0 * (2 + wd)),
-                                f"{name}{l}")
-            # products with A_l (residual y = b - A x: x, b read, y written)
-            for mode in (0, 1, 3):
-                nv = 2 if mode == 0 else 3
-                byts = mat + nr * (4.0 + vec * nv)
+                            add(f"sell_mv3_k<{tn},{mode},{w}>", slice_grid(nr, 1, w), nnz * (tb + 4.0) + nr * (4.0 + 3 * tb * nv),
+                                f"{name}{l} A")
+                # prolongation y += P x (P: nr x nc blocks b x k; x coarse, y read and written)
+                nc, nnzp = L["nagg"], L["nnzP"]
+                pbytes = nnzp * (b * k * tb + 4.0) + nc * k * tb + nr * (4.0 + 2 * b * tb)
                 if b == 3 and l == 0:
-                    add(f"sell_mv_rl3_k<double,3,{mode}>", ceil(ceil(nr / 64) / 4) * 256, byts, f"{name}{l} A")
+                    add(f"sell_mv_rl3_k<{tn},{k},2>", ceil(ceil(nr / 64) / 4) * 256, pbytes, f"{name}{l} P")
                 for w in (1, 2, 4, 8, 16):
-                    add(f"sell_mv_k<double,{b},{b},{mode},{w}>", slice_grid(nr, b, w), byts, f"{name}{l} A")
+                    add(f"sell_mv_k<{tn},{b},{k},2,{w}>", slice_grid(nr, b, w), pbytes, f"{name}{l} P")
                     if b == 1:
-                        add(f"sell_mv3_k<double,{mode},{w}>", slice_grid(nr, 1, w), nnz * 12.0 + nr * (4.0 + 24.0 * nv),
-                            f"{name}{l} A")
-            # prolongation y += P x (P: nr x nc blocks b x k; x coarse, y read and written)
-            nc, nnzp = L["nagg"], L["nnzP"]
-            pbytes = nnzp * (b * k * 8.0 + 4.0) + nc * k * 8.0 + nr * (4.0 + 2 * b * 8.0)
-            if b == 3 and l == 0:
-                add(f"sell_mv_rl3_k<double,{k},2>", ceil(ceil(nr / 64) / 4) * 256, pbytes, f"{name}{l} P")
-            for w in (1, 2, 4, 8, 16):
-                add(f"sell_mv_k<double,{b},{k},2,{w}>", slice_grid(nr, b, w), pbytes, f"{name}{l} P")
+                        add(f"sell_mv3_k<{tn},2,{w}>", slice_grid(nr, 1, w),
+                            nnzp * (tb + 4.0) + nc * 3 * tb + nr * (4.0 + 6 * tb), f"{name}{l} P")
+                # restriction y = R x (R: nc x nr blocks k x b)
+                rbytes = L["nnzR"] * (k * b * tb + 4.0) + nr * b * tb + nc * (4.0 + k * tb)
+                add(f"bsrt_mv_k<{tn},{k},{b}>", ceil(nc / 4) * 256, rbytes, f"{name}{l} R")
                 if b == 1:
-                    add(f"sell_mv3_k<double,2,{w}>", slice_grid(nr, 1, w),
-                        nnzp * 12.0 + nc * 24.0 + nr * (4.0 + 48.0), f"{name}{l} P")
-            # restriction y = R x (R: nc x nr blocks k x b)
-            rbytes = L["nnzR"] * (k * b * 8.0 + 4.0) + nr * b * 8.0 + nc * (4.0 + k * 8.0)
-            add(f"bsrt_mv_k<double,{k},{b}>", ceil(nc / 4) * 256, rbytes, f"{name}{l} R")
-            if b == 1:
-                add("bsrt_mv3_k<double>", ceil(nc / 4) * 256, L["nnzR"] * 12.0 + nr * 24.0 + nc * 28.0, f"{name}{l} R")
+                    add(f"bsrt_mv3_k<{tn}>", ceil(nc / 4) * 256, L["nnzR"] * (tb + 4.0) + nr * 3 * tb + nc * (4.0 + 3 * tb), f"{name}{l} R")
     nb, nnzb = levels["n_b"], levels["nnzb"]
     for mode in (0, 1):
         add(f"sell_mv_split4_k<{mode}>", ceil(ceil(nb / 16) / 4) * 256,
@@ -746,7 +747,7 @@ def main():
             upd_ms.append((time.perf_counter() - tu) * 1e3)
         peak = h.peak_bytes()
         fp = scr.footprint_estimate(scr.SCR_SYSTEM, s.n_b, s.nnzb, ao)
-        if args.dump_levels and prec == "fp64":
+        if args.dump_levels and pi == 0:
             dump_levels(args.dump_levels, scr, h, hm, s, stats[0] if stats else None)
         h.destroy()
         log(f"[bench] {prec} amg_update: {' '.join(f'{v:.1f}' for v in upd_ms)} ms; handle peak {peak / 2**30:.2f} GiB, "
