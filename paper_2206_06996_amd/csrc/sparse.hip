@@ -232,15 +232,15 @@ __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restr
     }
 }
 
-// Block-row lanes: the E = 3*bc values of slot t.  FP32: entry e of lane l at (t*E + e)*64 + l.  FP64:
-// the entries in pairs (e, e+1) stored next to each other per lane, so that a lane reads two of
-// them with one 16-byte load (a wavefront 1 KB per load instruction), and an odd last entry as a
-// plain 64-wide vector after the pairs.
-__host__ __device__ __forceinline__ int64_t rl_vidx(int64_t t, int e, int lane, int E, bool paired) {
-    if (!paired) return (t * E + e) * WAVE + lane;
+// Block-row lanes: the E = 3*bc values of slot t, in groups of g entries stored next to each
+// other per lane (g = 2 for FP64, 4 for FP32), so that a lane reads a group with one 16-byte load
+// (a wavefront 1 KB per load instruction); the last E % g entries as plain 64-wide vectors after
+// the groups.
+__host__ __device__ __forceinline__ int64_t rl_vidx(int64_t t, int e, int lane, int E, int g) {
     const int64_t base = t * E * WAVE;
-    if (e < (E & ~1)) return base + (e >> 1) * 2 * WAVE + lane * 2 + (e & 1);
-    return base + (int64_t)(E - 1) * WAVE + lane;
+    const int full = E - E % g;
+    if (e < full) return base + (int64_t)(e / g) * g * WAVE + lane * g + (e % g);
+    return base + (int64_t)e * WAVE + lane;
 }
 
 // block-row lanes: one thread per (slice, lane) = block row; all br*bc entries of each slot
@@ -264,7 +264,8 @@ __global__ void sell_fill_rowlane(const int32_t* __restrict__ rp, const int32_t*
         int64_t q = lo + (t - o0);
         bool real = i >= 0 && q < hi;
         sci[t * WAVE + lane] = real ? ci[q] : pad;
-        for (int e = 0; e < nb2; ++e) sv[rl_vidx(t, e, lane, nb2, sizeof(T) == 8)] = real ? (T)v[q * nb2 + e] : (T)0;
+        for (int e = 0; e < nb2; ++e)
+            sv[rl_vidx(t, e, lane, nb2, sizeof(T) == 8 ? 2 : 4)] = real ? (T)v[q * nb2 + e] : (T)0;
     }
 }
 
@@ -488,7 +489,8 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
                                              const T* __restrict__ v, const T* __restrict__ x, T r[3],
                                              int32_t irow = -1, T* dg = nullptr) {
     constexpr int U = (BC == 3 || sizeof(T) == 8) ? 2 : 1, E = 3 * BC;
-    // the E values of slot tt (layout of rl_vidx): FP64 in 16-byte pairs, nontemporal
+    // the E values of slot tt (layout of rl_vidx): FP64 in 16-byte pairs, FP32 in 16-byte quads,
+    // nontemporal
     auto load_slot = [&](int64_t tt, T (&vv)[E]) {
         if constexpr (sizeof(T) == 8) {
             typedef T V2 __attribute__((ext_vector_type(2)));
@@ -501,8 +503,18 @@ __device__ __forceinline__ void rowlane3_dot(int64_t t, int64_t o1, int lane, co
             }
             if constexpr (E % 2 == 1) vv[E - 1] = __builtin_nontemporal_load(base + (E - 1) * WAVE + lane);
         } else {
+            typedef T V4 __attribute__((ext_vector_type(4)));
+            const T* base = v + tt * E * WAVE;
 #pragma unroll
-            for (int e = 0; e < E; ++e) vv[e] = v[(tt * E + e) * WAVE + lane];
+            for (int k = 0; k < E / 4; ++k) {
+                const V4 w = __builtin_nontemporal_load(reinterpret_cast<const V4*>(base + k * 4 * WAVE) + lane);
+                vv[4 * k] = w.x;
+                vv[4 * k + 1] = w.y;
+                vv[4 * k + 2] = w.z;
+                vv[4 * k + 3] = w.w;
+            }
+#pragma unroll
+            for (int e = E - E % 4; e < E; ++e) vv[e] = __builtin_nontemporal_load(base + e * WAVE + lane);
         }
     };
     auto fma_block = [&](const T* vv, const T* xx) {
