@@ -197,9 +197,12 @@ __global__ void sell_slice_len(const int32_t* __restrict__ rp, const int32_t* __
 // 6-wide FP64 block rows, whose values are stored in pairs (k, k+1) per lane so that a lane reads
 // two of them with one 16-byte load (measured: 6x6 FP64 smoother 33.6 -> 30.6 us per launch;
 // the same pairing for FP32, 8-byte loads, was slower, 17.5 -> 18.6 us).
-__host__ __device__ __forceinline__ bool sell_paired(int bc, int elem_bytes) { return bc == 6 && elem_bytes == 8; }
-__host__ __device__ __forceinline__ int64_t sell_vidx(int64_t t, int k, int lane, int bc, bool paired) {
-    if (paired) return ((t * 3 + (k >> 1)) * WAVE + lane) * 2 + (k & 1);
+// 6-wide FP32 rows: the first four values of a lane side by side (one 16-byte load), then the last
+// two (one 8-byte load).
+__host__ __device__ __forceinline__ bool sell_paired(int bc, int elem_bytes) { return bc == 6; }
+__host__ __device__ __forceinline__ int64_t sell_vidx(int64_t t, int k, int lane, int bc, bool paired, int elem_bytes) {
+    if (paired && elem_bytes == 8) return ((t * 3 + (k >> 1)) * WAVE + lane) * 2 + (k & 1);
+    if (paired) return t * 6 * WAVE + (k < 4 ? lane * 4 + k : 4 * WAVE + lane * 2 + (k - 4));
     return (t * bc + k) * WAVE + lane;
 }
 
@@ -228,7 +231,7 @@ __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restr
         bool real = valid && q < hi;
         if (colwriter) sci[t * rps + j] = real ? ci[q] : pad;
         for (int k = 0; k < bc; ++k)
-            sv[sell_vidx(t, k, lane, bc, paired)] = real ? (T)v[(q * br + r) * bc + k] : (T)0;
+            sv[sell_vidx(t, k, lane, bc, paired, (int)sizeof(T))] = real ? (T)v[(q * br + r) * bc + k] : (T)0;
     }
 }
 
@@ -360,6 +363,14 @@ __device__ __forceinline__ void sell_vals(const T* __restrict__ v, int64_t t, in
             vv[2 * kk] = w.x;
             vv[2 * kk + 1] = w.y;
         }
+    } else if constexpr (BC == 6) {
+        typedef T V4 __attribute__((ext_vector_type(4)));
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        const T* base = v + t * 6 * WAVE;
+        const V4 a = __builtin_nontemporal_load(reinterpret_cast<const V4*>(base) + lane);
+        const V2 c = __builtin_nontemporal_load(reinterpret_cast<const V2*>(base + 4 * WAVE) + lane);
+        vv[0] = a.x; vv[1] = a.y; vv[2] = a.z; vv[3] = a.w;
+        vv[4] = c.x; vv[5] = c.y;
     } else {
 #pragma unroll
         for (int k = 0; k < BC; ++k) vv[k] = ld_stream<BC>(v + (t * BC + k) * WAVE + lane);
