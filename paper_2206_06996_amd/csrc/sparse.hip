@@ -194,11 +194,10 @@ __global__ void sell_slice_len(const int32_t* __restrict__ rp, const int32_t* __
 }
 
 // Value k of slot t for lane `lane` in the scalar-row layout: k-major 64-wide vectors, except for
-// 6-wide FP64 block rows, whose values are stored in pairs (k, k+1) per lane so that a lane reads
-// two of them with one 16-byte load (measured: 6x6 FP64 smoother 33.6 -> 30.6 us per launch;
-// the same pairing for FP32, 8-byte loads, was slower, 17.5 -> 18.6 us).
-// 6-wide FP32 rows: the first four values of a lane side by side (one 16-byte load), then the last
-// two (one 8-byte load).
+// 6-wide block rows.  FP64: the values in pairs (k, k+1) per lane, so that a lane reads two of
+// them with one 16-byte load (measured: 6x6 FP64 smoother 33.6 -> 30.6 us per launch).  FP32: the
+// first four values of a lane side by side (one 16-byte load), then the last two (one 8-byte load);
+// pairs alone (three 8-byte loads) had been slower than six 4-byte loads, 17.5 -> 18.6 us.
 __host__ __device__ __forceinline__ bool sell_paired(int bc, int elem_bytes) { return bc == 6; }
 __host__ __device__ __forceinline__ int64_t sell_vidx(int64_t t, int k, int lane, int bc, bool paired, int elem_bytes) {
     if (paired && elem_bytes == 8) return ((t * 3 + (k >> 1)) * WAVE + lane) * 2 + (k & 1);
