@@ -180,7 +180,7 @@ __global__ void sell_rank_k(const int32_t* __restrict__ rp, int64_t nr, int64_t 
 }
 
 __global__ void sell_slice_len(const int32_t* __restrict__ rp, const int32_t* __restrict__ rowid, int rps,
-                               int64_t nslices, int32_t* __restrict__ len) {
+                               int64_t nslices, int grp, int32_t* __restrict__ len) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslices) return;
     int32_t m = 0;
@@ -190,7 +190,7 @@ __global__ void sell_slice_len(const int32_t* __restrict__ rp, const int32_t* __
         int32_t l = rp[i + 1] - rp[i];
         m = l > m ? l : m;
     }
-    len[s] = m;
+    len[s] = (m + grp - 1) / grp * grp;
 }
 
 // Value k of slot t for lane `lane` in the scalar-row layout: k-major 64-wide vectors, except for
@@ -205,10 +205,19 @@ __host__ __device__ __forceinline__ int64_t sell_vidx(int64_t t, int k, int lane
     return (t * bc + k) * WAVE + lane;
 }
 
+// 1x1 rows (one lane per row): slots grouped by four per lane, the column indices and the values of
+// slots 4g .. 4g+3 of a lane side by side, so that a lane reads four indices with one 16-byte load
+// and four values with one (FP32) or two (FP64); every slice holds a multiple of four slots.
+constexpr int SELL_G = 4;
+__host__ __device__ __forceinline__ int64_t sell_gpos(int64_t t, int lane) {
+    return ((t >> 2) * WAVE + lane) * SELL_G + (t & 3);
+}
+
 template <typename T>
 __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const double* __restrict__ v,
                           int br, int bc, int rps, const int32_t* __restrict__ rowid, const int32_t* __restrict__ off,
                           int32_t* __restrict__ sci, T* __restrict__ sv, int64_t nslices) {
+    const bool grouped = br == 1 && bc == 1;
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t s = g / WAVE;
     if (s >= nslices) return;
@@ -222,6 +231,25 @@ __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restr
     if (valid) {
         lo = rp[i]; hi = rp[i + 1];
         pad = hi > lo ? ci[hi - 1] : 0;
+    }
+    if (grouped) {
+        // whole groups of four slots (the slice's slot range is a multiple of four)
+        typedef int32_t I4 __attribute__((ext_vector_type(4)));
+        typedef T V4 __attribute__((ext_vector_type(4)));
+        for (int64_t t = o0; t < o1; t += SELL_G) {
+            I4 cc;
+            V4 vv;
+#pragma unroll
+            for (int u = 0; u < SELL_G; ++u) {
+                const int64_t q = lo + (t + u - o0);
+                const bool real = valid && q < hi;
+                cc[u] = real ? ci[q] : pad;
+                vv[u] = real ? (T)v[q] : (T)0;
+            }
+            *reinterpret_cast<I4*>(sci + sell_gpos(t, lane)) = cc;
+            *reinterpret_cast<V4*>(sv + sell_gpos(t, lane)) = vv;
+        }
+        return;
     }
     bool colwriter = j < rps && r == 0;
     const bool paired = sell_paired(bc, (int)sizeof(T));
@@ -284,7 +312,8 @@ DSell<T> sell_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
     int64_t win = (int64_t)(S.rowlane ? SELL_SIGMA_ROWLANE : SELL_SIGMA) * S.rps;
     sell_rank_k<<<cdiv(A.nr, 256), 256, 0, s>>>(A.rp, A.nr, win, S.rowid);
     int32_t* len = ar.make<int32_t>(S.nslices);
-    sell_slice_len<<<cdiv(S.nslices, 256), 256, 0, s>>>(A.rp, S.rowid, S.rps, S.nslices, len);
+    const int grp = (!S.rowlane && A.br == 1 && A.bc == 1) ? SELL_G : 1;
+    sell_slice_len<<<cdiv(S.nslices, 256), 256, 0, s>>>(A.rp, S.rowid, S.rps, S.nslices, grp, len);
     check_launch("sell_slice_len");
     S.off = ar.make<int32_t>(S.nslices + 1);
     S.slots = scan_i32(len, S.off, S.nslices, ar, s);
@@ -376,11 +405,74 @@ __device__ __forceinline__ void sell_vals(const T* __restrict__ v, int64_t t, in
     }
 }
 
+// the four column indices and the four values of slot group g of a lane (layout of sell_gpos)
+typedef int32_t SellI4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ SellI4 sell_gidx(const int32_t* __restrict__ ci, int64_t g, int lane) {
+    return *reinterpret_cast<const SellI4*>(ci + (g * WAVE + lane) * SELL_G);
+}
+template <typename T>
+__device__ __forceinline__ void sell_gvals(const T* __restrict__ v, int64_t g, int lane, T (&vv)[SELL_G]) {
+    const T* p = v + (g * WAVE + lane) * SELL_G;
+    if constexpr (sizeof(T) == 8) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        const V2 a = reinterpret_cast<const V2*>(p)[0], b = reinterpret_cast<const V2*>(p)[1];
+        vv[0] = a.x; vv[1] = a.y; vv[2] = b.x; vv[3] = b.y;
+    } else {
+        typedef T V4 __attribute__((ext_vector_type(4)));
+        const V4 a = *reinterpret_cast<const V4*>(p);
+        vv[0] = a.x; vv[1] = a.y; vv[2] = a.z; vv[3] = a.w;
+    }
+}
+
+// sell_row_dot for 1x1 rows in the grouped layout (o0, o1 multiples of four): two groups (eight
+// slots) per step, the indices one step ahead; the terms are added in slot order, as in the
+// one-slot-at-a-time loop
+template <typename T, typename XF>
+__device__ __forceinline__ T sell_row_dot_g(int64_t o0, int64_t o1, int lane, const int32_t* __restrict__ ci,
+                                            const T* __restrict__ v, XF xat) {
+    T acc = 0;
+    const int64_t g1 = o1 / SELL_G;
+    int64_t g = o0 / SELL_G;
+    SellI4 c[2];
+    if (g + 2 <= g1) {
+        c[0] = sell_gidx(ci, g, lane);
+        c[1] = sell_gidx(ci, g + 1, lane);
+    }
+    for (; g + 2 <= g1; g += 2) {
+        T xx[2][SELL_G], vv[2][SELL_G];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int j = 0; j < SELL_G; ++j) xx[u][j] = xat((int64_t)c[u][j], 0);
+        SellI4 cn[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) cn[u] = sell_gidx(ci, g + 2 + u < g1 ? g + 2 + u : g1 - 1, lane);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) sell_gvals<T>(v, g + u, lane, vv[u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int j = 0; j < SELL_G; ++j) acc += vv[u][j] * xx[u][j];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) c[u] = cn[u];
+    }
+    for (; g < g1; ++g) {
+        const SellI4 cc = sell_gidx(ci, g, lane);
+        T vv[SELL_G];
+        sell_gvals<T>(v, g, lane, vv);
+#pragma unroll
+        for (int j = 0; j < SELL_G; ++j) acc += vv[j] * xat((int64_t)cc[j], 0);
+    }
+    return acc;
+}
+
 // acc = sum over the lane's row segments of v . x[col*BC : col*BC+BC]; cl = the lane's block row
 // within the slice (column indices are stored once per block row, RPS per slot)
 template <typename T, int BC, int RPS, typename XF>
 __device__ __forceinline__ T sell_row_dot(int64_t o0, int64_t o1, int lane, int cl, const int32_t* __restrict__ ci,
                                           const T* __restrict__ v, XF xat) {
+    if constexpr (BC == 1 && RPS == WAVE) return sell_row_dot_g<T>(o0, o1, lane, ci, v, xat);
     constexpr int U = Unroll<BC>::U;
     T acc = 0;
     int64_t t = o0;
@@ -431,11 +523,12 @@ template <int WPS> struct SliceGroup {
     static constexpr int SPB = WPS >= 4 ? 1 : 4 / WPS;
     static constexpr int THREADS = SPB * WPS * 64;
 };
-template <int WPS>
+// (G = SELL_G for the grouped 1x1 layout: the chunks start at whole slot groups)
+template <int WPS, int G = 1>
 __device__ __forceinline__ void slice_part(int64_t o0, int64_t o1, int part, int64_t& a, int64_t& b) {
-    int64_t len = o1 - o0;
-    a = o0 + len * part / WPS;
-    b = o0 + len * (part + 1) / WPS;
+    int64_t len = (o1 - o0) / G;
+    a = o0 + G * (len * part / WPS);
+    b = o0 + G * (len * (part + 1) / WPS);
 }
 
 template <typename T, int BR, int BC, int MODE, int WPS>
@@ -453,7 +546,7 @@ __global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) sell_mv_k(int64_t ns
     T acc = 0;
     if (live) {
         int64_t a, e;
-        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        slice_part<WPS, (BR == 1 && BC == 1) ? SELL_G : 1>(off[sl], off[sl + 1], wv % WPS, a, e);
         acc = sell_row_dot<T, BC, RPS>(a, e, lane, cl, ci, v, xat);
     }
     if (WPS > 1) {
@@ -766,7 +859,7 @@ __global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) smooth_k(int64_t nsl
     if (!ZERO && live) {
         auto xat = [&](int64_t c, int k) { return xin[c * B + k]; };
         int64_t a, e;
-        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        slice_part<WPS, B == 1 ? SELL_G : 1>(off[sl], off[sl + 1], wv % WPS, a, e);
         acc = sell_row_dot<T, B, RPS>(a, e, lane, cl, ci, v, xat);
     }
     if (WPS > 1) {
@@ -937,41 +1030,45 @@ template void smooth_step<float>(const DSell<float>&, const float*, const float*
 template <typename T>
 __device__ __forceinline__ void sell_row_dot3(int64_t o0, int64_t o1, int lane, const int32_t* __restrict__ ci,
                                               const T* __restrict__ v, const T* __restrict__ x, T (&acc)[3]) {
-    constexpr int U = Unroll<1>::U;
     acc[0] = acc[1] = acc[2] = 0;
-    int64_t t = o0;
-    int32_t c[U];
-    if (t + U <= o1) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) c[u] = ci[(t + u) * WAVE + lane];
+    const int64_t g1 = o1 / SELL_G;
+    int64_t g = o0 / SELL_G;
+    SellI4 c[2];
+    if (g + 2 <= g1) {
+        c[0] = sell_gidx(ci, g, lane);
+        c[1] = sell_gidx(ci, g + 1, lane);
     }
-    for (; t + U <= o1; t += U) {
-        T xx[U][3], vv[U];
+    for (; g + 2 <= g1; g += 2) {
+        T xx[2][SELL_G][3], vv[2][SELL_G];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) xx[u][k] = x[3 * (int64_t)c[u] + k];
-        int32_t cn[U];
+            for (int j = 0; j < SELL_G; ++j)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            int64_t q = t + U + u < o1 ? t + U + u : o1 - 1;     // stays inside the slice
-            cn[u] = ci[q * WAVE + lane];
-        }
+                for (int k = 0; k < 3; ++k) xx[u][j][k] = x[3 * (int64_t)c[u][j] + k];
+        SellI4 cn[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) cn[u] = sell_gidx(ci, g + 2 + u < g1 ? g + 2 + u : g1 - 1, lane);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < U; ++u) vv[u] = v[(t + u) * WAVE + lane];
+        for (int u = 0; u < 2; ++u) sell_gvals<T>(v, g + u, lane, vv[u]);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) acc[k] += vv[u] * xx[u][k];
+            for (int j = 0; j < SELL_G; ++j)
 #pragma unroll
-        for (int u = 0; u < U; ++u) c[u] = cn[u];
+                for (int k = 0; k < 3; ++k) acc[k] += vv[u][j] * xx[u][j][k];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) c[u] = cn[u];
     }
-    for (; t < o1; ++t) {
-        int64_t cc = ci[t * WAVE + lane];
-        T vv = v[t * WAVE + lane];
+    for (; g < g1; ++g) {
+        const SellI4 cc = sell_gidx(ci, g, lane);
+        T vv[SELL_G];
+        sell_gvals<T>(v, g, lane, vv);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) acc[k] += vv * x[3 * cc + k];
+        for (int j = 0; j < SELL_G; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k] += vv[j] * x[3 * (int64_t)cc[j] + k];
     }
 }
 template <typename T, int MODE, int WPS>
@@ -986,7 +1083,7 @@ __global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) sell_mv3_k(int64_t n
     T acc[3] = {0, 0, 0};
     if (live) {
         int64_t a, e;
-        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        slice_part<WPS, SELL_G>(off[sl], off[sl + 1], wv % WPS, a, e);
         sell_row_dot3<T>(a, e, lane, ci, v, x, acc);
     }
     if (WPS > 1) {
@@ -1085,7 +1182,7 @@ __global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) smooth3_k(int64_t ns
     T acc[3] = {0, 0, 0};
     if (!ZERO && live) {
         int64_t a, e;
-        slice_part<WPS>(off[sl], off[sl + 1], wv % WPS, a, e);
+        slice_part<WPS, SELL_G>(off[sl], off[sl + 1], wv % WPS, a, e);
         sell_row_dot3<T>(a, e, lane, ci, v, xin, acc);
     }
     if (WPS > 1) {
