@@ -566,16 +566,19 @@ __global__ void __launch_bounds__(SliceGroup<WPS>::THREADS) sell_mv_k(int64_t ns
     else y[o] -= acc;
 }
 
-// waves per slice: enough waves for about 16 per CU while every wave keeps at least 8 slots; on
-// small matrices (fewer than 512 slices, where the time is the latency of each wave's chain of
-// dependent loads) down to 4 slots per wave and up to 16 waves per slice
+// waves per slice: doubled while the matrix has fewer than 64K waves in all (256 per CU) and each
+// wave keeps at least 3 of the slice's average slots, up to 8 waves per slice; on small matrices
+// (fewer than 512 slices, where the time is the latency of each wave's chain of dependent loads)
+// at least 4 slots and up to 16 waves.  Measured on the refined tube (A/B on one box): a cap of 64K
+// instead of 16K waves puts 8 waves on each slice of AMG(A)'s level 1 (55 slots) and 4 on AMG(S^)'s
+// level 0 and makes the FP64 solve 5 % faster; 16 waves per slice on level 1 is slower again.
 template <typename T>
 static int waves_per_slice(const DSell<T>& A) {
     if (A.nslices <= 0) return 1;
     int64_t avg = A.slots / A.nslices;
     int wmax = A.nslices < 512 ? 16 : 8, per = A.nslices < 512 ? 4 : 3;
     int w = 1;
-    while (w < wmax && A.nslices * w < 16384 && avg >= per * (w * 2)) w *= 2;
+    while (w < wmax && A.nslices * w < 65536 && avg >= per * (w * 2)) w *= 2;
     return w;
 }
 
