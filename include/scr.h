@@ -117,7 +117,9 @@ typedef struct {
                                   its l1 form (l1_gs) each row's diagonal gains the absolute values
                                   of its couplings outside its domain, which keeps the sweep
                                   convergent for any symmetric positive definite matrix.
-                                  Galerkin coarse operators, direct coarsest solve.  FP64 only; the
+                                  Galerkin coarse operators, direct coarsest solve.  Any precision:
+                                  the mixed forms run the V-cycle on FP32 copies of every level (the
+                                  coarsest solve in FP64), as for smoothed aggregation.  The
                                   near-null space, theta, the smoother and Chebyshev fields are not
                                   used; amg_update sets the hierarchy up again.  The first
                                   agg_levels levels coarsen aggressively (two stages): HMIS gives

@@ -17,6 +17,7 @@
 // every level's split, pattern and values are those of a sequential evaluation.
 #include <algorithm>
 #include <memory>
+#include <type_traits>
 
 #include "solver.h"
 
@@ -559,26 +560,29 @@ static_assert(GS_W * 8 * GS_RB == GS_DOM, "the first phase covers the domain in 
 // slot of the coupling of sweep position p to position q < p (column-packed strict lower triangle)
 __device__ __forceinline__ int gs_tri(int p, int q) { return (GS_DOM - 1) * q - q * (q - 1) / 2 + (p - q - 1); }
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
+__device__ __forceinline__ double readlane_t(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float readlane_t(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 
-template <int NC, bool BWD>
+template <typename T, int NC, bool BWD>
 __global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ ci, const double* __restrict__ v,
-                                                   const double* __restrict__ dinv, const double* __restrict__ ell,
-                                                   const double* __restrict__ b, const double* __restrict__ xold,
-                                                   double* __restrict__ x) {
-    __shared__ double F[GS_TRI];
-    __shared__ double so_sh[NC][GS_DOM];
+                                                   const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                   const T* __restrict__ dinv, const T* __restrict__ ell,
+                                                   const T* __restrict__ b, const T* __restrict__ xold,
+                                                   T* __restrict__ x) {
+    __shared__ T F[GS_TRI];
+    __shared__ T so_sh[NC][GS_DOM];
     const int wv = threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t lo = xcd_tile(blockIdx.x, gridDim.x) * GS_DOM;     // the grid covers the rows exactly
     const int64_t hi = lo + GS_DOM < nr ? lo + GS_DOM : nr;
     const int n = (int)(hi - lo);
-    for (int e = threadIdx.x; e < GS_TRI; e += GS_W * WAVE) F[e] = 0.0;
+    for (int e = threadIdx.x; e < GS_TRI; e += GS_W * WAVE) F[e] = T(0);
     __syncthreads();
     // phase 1: wavefront wv takes positions 8 (GS_RB wv + r) + grp, r < GS_RB
     const int grp = lane >> 3, gl = lane & 7;
@@ -596,16 +600,16 @@ __global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* 
         ii[r] = BWD ? hi - 1 - tt[r] : lo + tt[r];
         len = qe[r] - qs[r] > len ? qe[r] - qs[r] : len;
     }
-    double acc[GS_RB][NC];
+    T acc[GS_RB][NC];
 #pragma unroll
     for (int r = 0; r < GS_RB; ++r)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
+        for (int c = 0; c < NC; ++c) acc[r][c] = T(0);
     // every load of a step is issued before any is used (the index is clamped to the row's last
     // entry, or to entry 0 for a row with none, so that the loads need no branch)
     for (int32_t o = gl; o < len; o += 8 * GS_U) {
         int32_t jj[GS_RB][GS_U];
-        double aa[GS_RB][GS_U];
+        T aa[GS_RB][GS_U];
 #pragma unroll
         for (int r = 0; r < GS_RB; ++r)
 #pragma unroll
@@ -615,7 +619,7 @@ __global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* 
                 jj[r][u] = ci[qq];
                 aa[r][u] = v[qq];
             }
-        double xx[GS_RB][GS_U][NC];
+        T xx[GS_RB][GS_U][NC];
         bool old[GS_RB][GS_U], fresh[GS_RB][GS_U];
         int pjs[GS_RB][GS_U];
 #pragma unroll
@@ -630,14 +634,14 @@ __global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* 
                 old[r][u] = real && !fresh[r][u] && j != ii[r];
                 const int64_t jc = old[r][u] ? j : lo;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) xx[r][u][c] = xold != nullptr ? xold[NC * jc + c] : 0.0;
+                for (int c = 0; c < NC; ++c) xx[r][u][c] = xold != nullptr ? xold[NC * jc + c] : T(0);
             }
 #pragma unroll
         for (int r = 0; r < GS_RB; ++r)
 #pragma unroll
             for (int u = 0; u < GS_U; ++u) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[r][c] += old[r][u] ? aa[r][u] * xx[r][u][c] : 0.0;
+                for (int c = 0; c < NC; ++c) acc[r][c] += old[r][u] ? aa[r][u] * xx[r][u][c] : T(0);
                 if (fresh[r][u]) F[gs_tri(tt[r], pjs[r][u])] = aa[r][u];
             }
     }
@@ -645,7 +649,7 @@ __global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* 
     for (int r = 0; r < GS_RB; ++r)
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            double s = acc[r][c];
+            T s = acc[r][c];
 #pragma unroll
             for (int w = 1; w < 8; w <<= 1) s += __shfl_xor(s, w, WAVE);
             if (gl == 0) so_sh[c][tt[r]] = s;
@@ -654,21 +658,21 @@ __global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* 
     if (wv != 0) return;
     // phase 2 (first wavefront): the row at sweep position `lane`
     const bool own = lane < n;
-    const double dv = own ? dinv[il] : 0.0;
-    const double ev = (own && ell != nullptr && xold != nullptr) ? ell[il] : 0.0;
-    double r[NC], xn[NC];
+    const T dv = own ? dinv[il] : T(0);
+    const T ev = (own && ell != nullptr && xold != nullptr) ? ell[il] : T(0);
+    T r[NC], xn[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        r[c] = own ? b[NC * il + c] - so_sh[c][lane] : 0.0;
+        r[c] = own ? b[NC * il + c] - so_sh[c][lane] : T(0);
         if (own && ell != nullptr && xold != nullptr) r[c] = r[c] + ev * xold[NC * il + c];
-        xn[c] = 0.0;
+        xn[c] = T(0);
     }
     for (int q = 0; q < n; ++q) {
-        const double f = (lane > q && lane < n) ? F[gs_tri(lane, q)] : 0.0;
+        const T f = (lane > q && lane < n) ? F[gs_tri(lane, q)] : T(0);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (lane == q) xn[c] = r[c] * dv;
-            const double xq = readlane_f64(xn[c], q);
+            const T xq = readlane_t(xn[c], q);
             r[c] = r[c] - f * xq;
         }
     }
@@ -678,50 +682,76 @@ __global__ void __launch_bounds__(GS_W * WAVE) hgs_k(int64_t nr, const int32_t* 
     }
 }
 
-template <int NC>
-void hgs(const DBsr& A, const double* Dinv, const double* ell, const double* b, const double* xold, double* x,
-         bool backward, hipStream_t s) {
+// v: the values of A (pattern rp, ci) in T
+template <typename T, int NC>
+void hgs(const DBsr& A, const T* v, const T* Dinv, const T* ell, const T* b, const T* xold, T* x, bool backward,
+         hipStream_t s) {
     const unsigned g = (unsigned)cdiv(A.nr, GS_DOM);     // one workgroup per domain
     if (!g) return;
-    if (backward) hgs_k<NC, true><<<g, GS_W * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
-    else hgs_k<NC, false><<<g, GS_W * WAVE, 0, s>>>(A.nr, A.rp, A.ci, A.v, Dinv, ell, b, xold, x);
+    if (backward) hgs_k<T, NC, true><<<g, GS_W * WAVE, 0, s>>>(A.nr, A.rp, A.ci, v, Dinv, ell, b, xold, x);
+    else hgs_k<T, NC, false><<<g, GS_W * WAVE, 0, s>>>(A.nr, A.rp, A.ci, v, Dinv, ell, b, xold, x);
     check_launch("hybrid_gs");
 }
 
 // ------------------------------------------------------------------ hierarchy
-class ClassicalHier : public Hierarchy {
+class ClassicalBase : public Hierarchy {
+   public:
+    DBsr pattern0;                   // the block pattern of A0 (no values), for amg_update
+    virtual void prepare(Arena& a, hipStream_t s) = 0;
+    virtual void release_solve(Arena& a) = 0;
+};
+
+// the solve-phase copies in T: FP64, or FP32 for the mixed forms (the V-cycle on FP32 vectors with
+// FP32 copies of every level's matrix, diagonal and l1 terms; the coarsest solve with the FP64
+// inverse)
+template <typename T>
+class ClassicalHier : public ClassicalBase {
    public:
     struct LS {
-        DSell<double> A, P;
-        DBsrT<double> R;
-        double *b = nullptr, *x = nullptr, *w = nullptr, *r = nullptr;
-        double *b3 = nullptr, *x3 = nullptr, *w3 = nullptr, *r3 = nullptr;
+        DSell<T> A, P;
+        DBsrT<T> R;
+        const T *av = nullptr, *dinv = nullptr, *ell = nullptr;   // what the sweeps read
+        T *own_av = nullptr, *own_dinv = nullptr, *own_ell = nullptr;   // FP32 copies (owned)
+        T *b = nullptr, *x = nullptr, *w = nullptr, *r = nullptr;
+        T *b3 = nullptr, *x3 = nullptr, *w3 = nullptr, *r3 = nullptr;
     };
     std::vector<LS> S;
-    DBsr pattern0;                   // the block pattern of A0 (no values), for amg_update
 
-    void prepare(Arena& a, hipStream_t s) {
+    void prepare(Arena& a, hipStream_t s) override {
         S.resize(L.size());
         for (size_t l = 0; l < L.size(); ++l) {
             LevelSetup& ls = L[l];
             LS& q = S[l];
             const int64_t n = ls.A.nr;
-            q.b = a.make<double>(n); q.x = a.make<double>(n);
-            if (three) { q.b3 = a.make<double>(3 * n); q.x3 = a.make<double>(3 * n); }
+            q.b = a.make<T>(n); q.x = a.make<T>(n);
+            if (three) { q.b3 = a.make<T>(3 * n); q.x3 = a.make<T>(3 * n); }
             if (l + 1 == L.size()) continue;
-            q.A = sell_from_bsr<double>(ls.A, a, s);
-            q.P = sell_from_bsr<double>(ls.P, a, s);
-            q.R = bsrt_from_bsr<double>(ls.R, a, s);
-            q.w = a.make<double>(n); q.r = a.make<double>(n);
-            if (three) { q.w3 = a.make<double>(3 * n); q.r3 = a.make<double>(3 * n); }
+            q.A = sell_from_bsr<T>(ls.A, a, s);
+            q.P = sell_from_bsr<T>(ls.P, a, s);
+            q.R = bsrt_from_bsr<T>(ls.R, a, s);
+            if constexpr (std::is_same<T, double>::value) {
+                q.av = ls.A.v; q.dinv = ls.Dinv; q.ell = ls.ell;
+            } else {
+                q.own_av = a.make<T>(ls.A.nnzb + 1);
+                cast_d2f(ls.A.v, q.own_av, ls.A.nnzb, s);
+                q.own_dinv = a.make<T>(n);
+                cast_d2f(ls.Dinv, q.own_dinv, n, s);
+                if (ls.ell) {
+                    q.own_ell = a.make<T>(n);
+                    cast_d2f(ls.ell, q.own_ell, n, s);
+                }
+                q.av = q.own_av; q.dinv = q.own_dinv; q.ell = q.own_ell;
+            }
+            q.w = a.make<T>(n); q.r = a.make<T>(n);
+            if (three) { q.w3 = a.make<T>(3 * n); q.r3 = a.make<T>(3 * n); }
         }
     }
-    void release_solve(Arena& a) {
+    void release_solve(Arena& a) override {
         for (auto& q : S) {
             sell_free(q.A, a);
             sell_free(q.P, a);
             a.free(q.R.v);
-            for (double* p : {q.b, q.x, q.w, q.r, q.b3, q.x3, q.w3, q.r3}) a.free(p);
+            for (T* p : {q.own_av, q.own_dinv, q.own_ell, q.b, q.x, q.w, q.r, q.b3, q.x3, q.w3, q.r3}) a.free(p);
         }
         S.clear();
     }
@@ -729,47 +759,72 @@ class ClassicalHier : public Hierarchy {
         release_solve(a);
         prepare(a, s);
     }
-    void cycle(size_t l, const double* b, double* x, hipStream_t s) {
+    void cycle(size_t l, const T* b, T* x, hipStream_t s) {
         if (l + 1 == S.size()) {
-            dense_mv<double>(ncoarse, cinv, b, x, s);
+            dense_mv<T>(ncoarse, cinv, b, x, s);
             return;
         }
         LS& q = S[l];
         const LevelSetup& ls = L[l];
-        hgs<1>(ls.A, ls.Dinv, ls.ell, b, nullptr, q.w, false, s);
-        sell_mv<double>(q.A, q.w, b, q.r, 1, s);
-        bsrt_mv<double>(q.R, q.r, S[l + 1].b, s);
+        hgs<T, 1>(ls.A, q.av, q.dinv, q.ell, b, nullptr, q.w, false, s);
+        sell_mv<T>(q.A, q.w, b, q.r, 1, s);
+        bsrt_mv<T>(q.R, q.r, S[l + 1].b, s);
         cycle(l + 1, S[l + 1].b, S[l + 1].x, s);
-        sell_mv<double>(q.P, S[l + 1].x, nullptr, q.w, 2, s);
-        hgs<1>(ls.A, ls.Dinv, ls.ell, b, q.w, x, true, s);
+        sell_mv<T>(q.P, S[l + 1].x, nullptr, q.w, 2, s);
+        hgs<T, 1>(ls.A, q.av, q.dinv, q.ell, b, q.w, x, true, s);
     }
-    void cycle3(size_t l, const double* b, double* x, hipStream_t s) {
+    void cycle3(size_t l, const T* b, T* x, hipStream_t s) {
         if (l + 1 == S.size()) {
-            dense_mv3<double>(ncoarse, cinv, b, x, s);
+            dense_mv3<T>(ncoarse, cinv, b, x, s);
             return;
         }
         LS& q = S[l];
         const LevelSetup& ls = L[l];
-        hgs<3>(ls.A, ls.Dinv, ls.ell, b, nullptr, q.w3, false, s);
-        sell_mv3<double>(q.A, q.w3, b, q.r3, 1, s);
-        bsrt_mv3<double>(q.R, q.r3, S[l + 1].b3, s);
+        hgs<T, 3>(ls.A, q.av, q.dinv, q.ell, b, nullptr, q.w3, false, s);
+        sell_mv3<T>(q.A, q.w3, b, q.r3, 1, s);
+        bsrt_mv3<T>(q.R, q.r3, S[l + 1].b3, s);
         cycle3(l + 1, S[l + 1].b3, S[l + 1].x3, s);
-        sell_mv3<double>(q.P, S[l + 1].x3, nullptr, q.w3, 2, s);
-        hgs<3>(ls.A, ls.Dinv, ls.ell, b, q.w3, x, true, s);
+        sell_mv3<T>(q.P, S[l + 1].x3, nullptr, q.w3, 2, s);
+        hgs<T, 3>(ls.A, q.av, q.dinv, q.ell, b, q.w3, x, true, s);
     }
     void vcycle(const double* x, double* y, hipStream_t s) override {
         ++vcycles;
-        cycle(0, x, y, s);
+        if constexpr (std::is_same<T, double>::value) {
+            cycle(0, x, y, s);
+        } else {
+            const int64_t n = n0();
+            cast_d2f(x, S[0].b, n, s);
+            cycle(0, S[0].b, S[0].x, s);
+            cast_f2d(S[0].x, y, n, s);
+        }
     }
     void vcycle3(const double* x, double* y, hipStream_t s) override {
         if (!three) throw Error(SCR_E_INVALID, "three-column V-cycle on a hierarchy built without it");
         vcycles += 3;
-        cycle3(0, x, y, s);
+        if constexpr (std::is_same<T, double>::value) {
+            cycle3(0, x, y, s);
+        } else {
+            const int64_t n = n0();
+            cast_d2f(x, S[0].b3, 3 * n, s);
+            cycle3(0, S[0].b3, S[0].x3, s);
+            cast_f2d(S[0].x3, y, 3 * n, s);
+        }
     }
-    void vcycle_f(const float*, float*, hipStream_t) override {
-        throw Error(SCR_E_INVALID, "classical AMG runs in FP64 only");
+    void vcycle_f(const float* x, float* y, hipStream_t s) override {
+        if constexpr (std::is_same<T, float>::value) {
+            ++vcycles;
+            cycle(0, x, y, s);
+        } else {
+            throw Error(SCR_E_INVALID, "FP32 V-cycle on an FP64 hierarchy");
+        }
     }
-    const DSell<float>* level0_f() const override { return nullptr; }
+    const DSell<float>* level0_f() const override {
+        if constexpr (std::is_same<T, float>::value) {
+            return S.size() < 2 ? nullptr : &S[0].A;
+        } else {
+            return nullptr;
+        }
+    }
 };
 
 int read_flag(const int* p, hipStream_t s) {
@@ -970,7 +1025,7 @@ int64_t aggressive_level(LevelSetup& L, const int32_t* tmap, const scr_amg_opts&
 }
 
 // every level of the classical hierarchy into H (H.L empty on entry; level 0 from A0)
-void setup_levels(ClassicalHier& H, const DBsr& A0, const scr_amg_opts& o, Arena& ar, hipStream_t s) {
+void setup_levels(ClassicalBase& H, const DBsr& A0, const scr_amg_opts& o, Arena& ar, hipStream_t s) {
     int* err = ar.make<int>(1);
     unsigned long long* lamd = ar.make<unsigned long long>(1);
     {
@@ -1028,7 +1083,7 @@ void setup_levels(ClassicalHier& H, const DBsr& A0, const scr_amg_opts& o, Arena
     ar.free(lamd);
 }
 
-void release_levels(ClassicalHier& H, Arena& ar) {
+void release_levels(ClassicalBase& H, Arena& ar) {
     H.release_solve(ar);
     for (LevelSetup& L : H.L) {
         bsr_release(L.A, ar);
@@ -1045,7 +1100,9 @@ void release_levels(ClassicalHier& H, Arena& ar) {
 std::unique_ptr<Hierarchy> build_classical(const DBsr& A0, const scr_amg_opts& o, Arena& ar, hipStream_t s, bool three) {
     if (A0.br != A0.bc || A0.br < 1 || A0.br > 6) throw Error(SCR_E_INVALID, "classical AMG: square blocks up to 6x6");
     if (three && A0.br != 1) throw Error(SCR_E_INVALID, "three-column V-cycles need a scalar matrix");
-    std::unique_ptr<ClassicalHier> H(new ClassicalHier());
+    std::unique_ptr<ClassicalBase> H;
+    if (o.precision == SCR_FP64) H.reset(new ClassicalHier<double>());
+    else H.reset(new ClassicalHier<float>());
     H->opts = o;
     H->three = three;
     DBsr& p0 = H->pattern0;
@@ -1061,7 +1118,7 @@ std::unique_ptr<Hierarchy> build_classical(const DBsr& A0, const scr_amg_opts& o
 }
 
 void update_classical(Hierarchy& Hb, const double* vals0, Arena& ar, hipStream_t s) {
-    ClassicalHier& H = static_cast<ClassicalHier&>(Hb);
+    ClassicalBase& H = static_cast<ClassicalBase&>(Hb);
     // the splitting and the interpolation depend on the values: set the hierarchy up again on
     // the kept block pattern of level 0
     release_levels(H, ar);

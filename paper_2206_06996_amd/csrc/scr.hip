@@ -489,11 +489,11 @@ scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coo
             throw Error(SCR_E_INVALID, "AMG options out of range");
         if (o.amg_type != SCR_AMG_SA && o.amg_type != SCR_AMG_CLASSICAL) throw Error(SCR_E_INVALID, "amg_type");
         if (o.amg_type == SCR_AMG_CLASSICAL &&
-            (o.precision != SCR_FP64 || !(o.cl_theta > 0 && o.cl_theta <= 1) || !(o.trunc >= 0 && o.trunc < 1) ||
+            (!(o.cl_theta > 0 && o.cl_theta <= 1) || !(o.trunc >= 0 && o.trunc < 1) ||
              o.pmax < 1 || o.pmax > 16 || o.agg_levels < 0 || o.agg_levels > 16 ||
              (o.l1_gs != 0 && o.l1_gs != 1)))
             throw Error(SCR_E_INVALID,
-                        "classical AMG: FP64 only, 0 < cl_theta <= 1, 0 <= trunc < 1, 1 <= pmax <= 16, 0 <= agg_levels <= 16, l1_gs 0 or 1");
+                        "classical AMG: 0 < cl_theta <= 1, 0 <= trunc < 1, 1 <= pmax <= 16, 0 <= agg_levels <= 16, l1_gs 0 or 1");
         h->ar.reset(new Arena(&ctx->c, s));
         Arena& ar = *h->ar;
         const int64_t nb = K->n_brows;

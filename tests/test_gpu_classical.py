@@ -165,8 +165,8 @@ def test_update_equals_fresh_setup_and_options(scr, ctx, small_fsi):
     _same(h, 0, o2.amgA)
     _same(h, 1, o2.amgS)
     h.destroy()
-    # classical is FP64 only; option ranges are checked
-    for kw in (dict(precision=1), dict(pmax=0), dict(pmax=17), dict(cl_theta=0.0), dict(trunc=1.0),
+    # option ranges are checked
+    for kw in (dict(precision=7), dict(pmax=0), dict(pmax=17), dict(cl_theta=0.0), dict(trunc=1.0),
                dict(agg_levels=-1), dict(agg_levels=17), dict(l1_gs=2)):
         with pytest.raises(scr.ScrError):
             _gpu_scr(scr, ctx, s, **kw)
@@ -203,4 +203,46 @@ def test_single_level_and_isolated_rows(scr, ctx, tiny):
     rc, st = scr.mesh_motion_solve(hm, dev(bm), xm)
     assert rc == 0 and max(st["mesh_its"]) <= 1
     assert np.allclose(host(xm), bm / np.repeat(d, 3), rtol=1e-14, atol=0)
+    hm.destroy()
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_precision_vcycles_and_solves(scr, ctx, cfg0, small_fsi, precision):
+    """SCR_MIXED (precision 1) and SCR_MIXED_FP32_INNER (2): the classical V-cycle in FP32 (FP32 copies
+    of every level; the coarsest solve with the FP64 inverse) within 1e-4 of the oracle's FP64
+    V-cycle; the solves reach 1e-8 and their fields agree with the oracle's 1e-12 solution to 1e-6."""
+    s = small_fsi
+    h = _gpu_scr(scr, ctx, s, coarse_max=60, precision=precision)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(amg_type=1, coarse_max=60))
+    rng = np.random.default_rng(6)
+    for op, n, hier in (("VA", 3 * s.n_b, o.amgA), ("VS", s.n_b, o.amgS)):
+        x = rng.uniform(-1, 1, n)
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        scr.scr_apply(h, op, dev(x), y)
+        ref = hier.vcycle(x)
+        err = np.linalg.norm(host(y) - ref) / np.linalg.norm(ref)
+        print(f"[gpu]   classical FP32 {op} rel err {err:.2e}", flush=True)
+        assert err <= 1e-4, op
+    h.destroy()
+    s = cfg0
+    b = synth.rhs(23, 4 * s.n_b, s.mask)
+    o = oracle.Scr(s.rp, s.ci, s.val, s.xyz, oracle.amg_opts(amg_type=1))
+    xt, _, _ = o.solve(b, oracle.solve_opts(tol=1e-12, max_it=400))
+    h = _gpu_scr(scr, ctx, s, precision=precision)
+    x = torch.zeros(4 * s.n_b, dtype=torch.float64, device="cuda")
+    rc, st = scr.scr_solve(h, dev(b), x)
+    print(f"[gpu]   classical mixed({precision}) SCR: rc={rc} "
+          f"{({k: st[k] for k in ('outer_it', 'its_A', 'its_S', 'its_I')})}", flush=True)
+    assert rc == 0
+    assert_fields(host(x), xt, 1e-6, f"classical mixed({precision}) SCR vs oracle at 1e-12")
+    h.destroy()
+    bm = synth.rhs(24, 3 * s.n_phys, np.repeat(s.Lmask, 3))
+    om = oracle.Mesh(s.Lrp, s.Lci, s.Lval, oracle.amg_opts(amg_type=1))
+    xmo, _, _, _ = om.solve(bm, tol=1e-12)
+    hm = _gpu_mesh(scr, ctx, s, precision=precision)
+    xm = torch.zeros(3 * s.n_phys, dtype=torch.float64, device="cuda")
+    rcm, stm = scr.mesh_motion_solve(hm, dev(bm), xm, scr.solve_opts(tol=1e-10))
+    err = np.linalg.norm(host(xm) - xmo) / np.linalg.norm(xmo)
+    print(f"[gpu]   classical mixed({precision}) mesh: rc={rcm} its={stm['mesh_its']} err {err:.2e}", flush=True)
+    assert rcm == 0 and err <= 1e-8
     hm.destroy()
