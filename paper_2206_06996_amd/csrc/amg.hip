@@ -247,14 +247,21 @@ __global__ void __launch_bounds__(256) spg_numeric(int64_t nr, const int32_t* __
 }
 
 // numeric phase, one wave per output row: the row's output columns go into an LDS hash (column ->
-// position), then the products X_iq * Y_kt are pushed into LDS accumulators, q ascending (the
-// lanes of one step hold distinct columns of one row of Y, so no two lanes meet the same
-// accumulator).  Each accumulator receives the same terms in the same order as in the pull
-// kernel above, so the results are identical; the work is the candidate count instead of
-// (output entries) x (X row length) binary searches.
-// Dynamic LDS: hs keys, hs positions, then wmax * M * P doubles.
+// position).  The candidates (X entry q, Y entry t) of up to 64 X entries at a time are spread over
+// all lanes as in the symbolic phase, each lane forms its block product X_iq * Y_kt in registers,
+// and the products are added to their LDS accumulators in rounds: in each round the lowest pending
+// lane of every accumulator (an LDS atomic minimum over lane ids) adds its product.  Lanes hold
+// candidates in (q, t) order and a row of Y holds a column once, so every accumulator receives the
+// same terms in the same order (q ascending) as in the pull kernel above and the results are
+// identical; a round count is the largest number of candidates of one pass that meet one output
+// column, instead of one serial step per X entry.  Where the rows of Y of a chunk of 64 X entries
+// average SPG_STEP_LEN entries or more, the chunk instead takes one X entry per step with its row
+// of Y over the lanes (the same order again), which costs less than packing rows that already fill
+// the wave.
+// Dynamic LDS: hs keys, hs positions, wmax * M * P doubles, then wmax owner slots.
+constexpr int SPG_STEP_LEN = 32;
 template <int M, int N, int P>
-__global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, const int32_t* __restrict__ xrp,
+__global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, int wmax, const int32_t* __restrict__ xrp,
                                                         const int32_t* __restrict__ xci, const double* __restrict__ xv,
                                                         const int32_t* __restrict__ yrp, const int32_t* __restrict__ yci,
                                                         const double* __restrict__ yv, const int32_t* __restrict__ crp,
@@ -264,6 +271,7 @@ __global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, cons
     int* pos = smem + hs;
     double* acc = reinterpret_cast<double*>(smem + 2 * hs);
     constexpr int MP = M * P;
+    int* owner = reinterpret_cast<int*>(acc + (size_t)wmax * MP);
     int64_t i = blockIdx.x;
     if (i >= nr) return;
     int lane = threadIdx.x;
@@ -277,27 +285,88 @@ __global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, cons
         unsigned h = ((unsigned)c * 2654435761u) & (unsigned)(hs - 1);
         while (atomicCAS(&keys[h], -1, c) != -1) h = (h + 1) & (unsigned)(hs - 1);
         pos[h] = p;
+        owner[p] = WAVE;
         for (int e = 0; e < MP; ++e) acc[p * MP + e] = 0.0;
     }
     __syncthreads();
-    for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) {
-        int32_t k = xci[q];
-        const double* xb = xv + (int64_t)q * M * N;
-        for (int32_t t = yrp[k] + lane; t < yrp[k + 1]; t += WAVE) {
-            int c = yci[t];
-            unsigned h = ((unsigned)c * 2654435761u) & (unsigned)(hs - 1);
-            for (int g = 0; g < hs && keys[h] != c; ++g) h = (h + 1) & (unsigned)(hs - 1);
-            if (keys[h] != c) continue;       // not reached: every column met is in the pattern
-            double* a = acc + pos[h] * MP;
-            const double* yb = yv + (int64_t)t * N * P;
-            for (int r = 0; r < M; ++r)
-                for (int cc = 0; cc < P; ++cc) {
-                    double sum = 0.0;
-                    for (int l = 0; l < N; ++l) sum += xb[r * N + l] * yb[l * P + cc];
-                    a[r * P + cc] += sum;
-                }
+    const int32_t x0 = xrp[i], x1 = xrp[i + 1];
+    for (int32_t q0 = x0; q0 < x1; q0 += WAVE) {
+        int st = 0, len = 0;
+        if (q0 + lane < x1) {
+            int32_t k = xci[q0 + lane];
+            st = yrp[k];
+            len = yrp[k + 1] - st;
         }
-        __syncthreads();
+        int incl = len;
+        for (int o = 1; o < WAVE; o <<= 1) {
+            int v = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += v;
+        }
+        const int total = __shfl(incl, WAVE - 1, WAVE);
+        const int nq = x1 - q0 < WAVE ? x1 - q0 : WAVE;
+        if (total >= SPG_STEP_LEN * nq) {
+            // long rows of Y: one X entry per step, its row of Y over the lanes
+            for (int j = 0; j < nq; ++j) {
+                const int stj = __builtin_amdgcn_readlane(st, j);
+                const int enj = stj + __builtin_amdgcn_readlane(len, j);
+                const double* xb = xv + (int64_t)(q0 + j) * M * N;
+                for (int t = stj + lane; t < enj; t += WAVE) {
+                    const int c = yci[t];
+                    unsigned h = ((unsigned)c * 2654435761u) & (unsigned)(hs - 1);
+                    for (int g = 0; g < hs && keys[h] != c; ++g) h = (h + 1) & (unsigned)(hs - 1);
+                    if (keys[h] != c) continue;       // not reached: every column met is in the pattern
+                    double* a = acc + pos[h] * MP;
+                    const double* yb = yv + (int64_t)t * N * P;
+                    for (int r = 0; r < M; ++r)
+                        for (int cc = 0; cc < P; ++cc) {
+                            double sum = 0.0;
+                            for (int k = 0; k < N; ++k) sum += xb[r * N + k] * yb[k * P + cc];
+                            a[r * P + cc] += sum;
+                        }
+                }
+                __syncthreads();
+            }
+            continue;
+        }
+        for (int base = 0; base < total; base += WAVE) {
+            const int cidx = base + lane;
+            int l = 0;     // number of lanes whose inclusive prefix is <= cidx
+            for (int step = WAVE / 2; step > 0; step >>= 1) {
+                int v = __shfl(incl, l + step - 1, WAVE);
+                if (v <= cidx) l += step;
+            }
+            const int stl = __shfl(st, l, WAVE);
+            const int excl = __shfl(incl, l, WAVE) - __shfl(len, l, WAVE);
+            bool todo = false;
+            int p = 0;
+            double prod[MP];
+            if (cidx < total) {
+                const int32_t t = stl + (cidx - excl);
+                const int c = yci[t];
+                unsigned h = ((unsigned)c * 2654435761u) & (unsigned)(hs - 1);
+                for (int g = 0; g < hs && keys[h] != c; ++g) h = (h + 1) & (unsigned)(hs - 1);
+                todo = keys[h] == c;       // always: every column met is in the pattern
+                p = pos[h];
+                const double* xb = xv + (int64_t)(q0 + l) * M * N;
+                const double* yb = yv + (int64_t)t * N * P;
+                for (int r = 0; r < M; ++r)
+                    for (int cc = 0; cc < P; ++cc) {
+                        double sum = 0.0;
+                        for (int k = 0; k < N; ++k) sum += xb[r * N + k] * yb[k * P + cc];
+                        prod[r * P + cc] = sum;
+                    }
+            }
+            while (__ballot(todo)) {
+                if (todo) atomicMin(&owner[p], lane);
+                __syncthreads();
+                if (todo && owner[p] == lane) {
+                    for (int e = 0; e < MP; ++e) acc[p * MP + e] += prod[e];
+                    owner[p] = WAVE;
+                    todo = false;
+                }
+                __syncthreads();
+            }
+        }
     }
     for (int p = lane; p < w; p += WAVE)
         for (int e = 0; e < MP; ++e) cv[(int64_t)(c0 + p) * MP + e] = acc[p * MP + e];
@@ -310,10 +379,10 @@ static void spgemm_numeric_run(const DBsr& X, const DBsr& Y, DBsr& C, int wmax, 
     int key = X.br * 100 + X.bc * 10 + Y.bc;
     int hsn = 64;
     while (hsn < 2 * wmax) hsn <<= 1;
-    size_t lds_n = (size_t)2 * hsn * sizeof(int) + (size_t)wmax * C.br * C.bc * sizeof(double);
+    size_t lds_n = (size_t)2 * hsn * sizeof(int) + (size_t)wmax * (C.br * C.bc * sizeof(double) + sizeof(int));
     if (X.nr > 0 && lds_n <= 64 * 1024) {
 #define SPL(m, n, p)                                                                                          \
-    spg_numeric_lds<m, n, p><<<X.nr, WAVE, lds_n, s>>>(X.nr, hsn, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, \
+    spg_numeric_lds<m, n, p><<<X.nr, WAVE, lds_n, s>>>(X.nr, hsn, wmax, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, \
                                                        C.v)
         switch (key) {
             case 111: SPL(1, 1, 1); break;
