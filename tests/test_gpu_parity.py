@@ -123,6 +123,80 @@ def test_hierarchy_parity_bit_exact_patterns(scr, ctx, case, small_fsi, cfg0):
     h.destroy()
 
 
+def _product_in_x_order(X, Y, C):
+    """Values of X Y (block CSR triples, Y and C given by pattern + values / pattern) on C's pattern,
+    every output block accumulated over X's row in stored order, each block product formed term by
+    term from zero.  This is the order the library's Galerkin product is defined to follow, and the
+    library is built without floating-point contraction, so its values must match bit for bit."""
+    (xrp, xci, xv), (yrp, yci, yv), (crp, cci) = X, Y, C
+    M, N = xv.shape[1:]
+    P = yv.shape[2]
+    nr = len(xrp) - 1
+    ncols = int(max(cci.max(initial=0), yci.max(initial=0))) + 1
+    keyc = np.repeat(np.arange(nr, dtype=np.int64), np.diff(crp)) * ncols + cci
+    cv = np.zeros((len(cci), M, P))
+    xlen = np.diff(xrp)
+    for j in range(int(xlen.max(initial=0))):
+        rows = np.nonzero(xlen > j)[0]
+        q = xrp[rows] + j
+        k = xci[q]
+        ylen = (yrp[k + 1] - yrp[k]).astype(np.int64)
+        n = int(ylen.sum())
+        if n == 0:
+            continue
+        src = np.repeat(np.arange(len(rows)), ylen)
+        t = np.repeat(yrp[k], ylen) + np.arange(n) - np.repeat(np.cumsum(ylen) - ylen, ylen)
+        key = rows[src].astype(np.int64) * ncols + yci[t]
+        pos = np.searchsorted(keyc, key)
+        assert np.array_equal(keyc[pos], key)          # every candidate lies in C's pattern
+        xb, yb = xv[q][src], yv[t]
+        prod = np.zeros((n, M, P))
+        for r in range(M):
+            for c in range(P):
+                s = np.zeros(n)
+                for l in range(N):
+                    s = s + xb[:, r, l] * yb[:, l, c]
+                prod[:, r, c] = s
+        cv[pos] += prod          # within one j no two candidates share an output block
+    return cv
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_galerkin_product_bitwise_in_row_order(scr, ctx, small_fsi, which):
+    """A_{l+1} = R_l (A_l P_l) of the GPU hierarchy, recomputed on the host from the GPU's own A_l,
+    P_l and R_l in the row order of each left factor: equal bit for bit on every level (dead coarse
+    dofs get their unit diagonal as in the setup).  On this system the products go through both
+    forms of the LDS numeric phase (rows of the right factor spread over the lanes, and one left
+    entry per step where those rows average 32 blocks or more)."""
+    import scipy.sparse as sps
+    h = gpu_setup(scr, ctx, small_fsi, coarse_max=60)
+    nl = h.hier_levels(which)
+    assert nl >= 3
+    for l in range(nl - 1):
+        def g(f, lev=l):
+            return h.hier_level_copy(which, lev, f)
+        i = h.hier_level_info(which, l)
+        na, k = i["nagg"], i["k"]
+        A = (g("A.rp"), g("A.ci"), g("A.v"))
+        P = (g("P.rp"), g("P.ci"), g("P.v"))
+        R = (g("R.rp"), g("R.ci"), g("R.v"))
+        pat = (sps.csr_matrix((np.ones(A[1].size), A[1], A[0]), shape=(i["nr"], i["nr"]))
+               @ sps.csr_matrix((np.ones(P[1].size), P[1], P[0]), shape=(i["nr"], na))).tocsr()
+        pat.sort_indices()
+        aprp, apci = pat.indptr.astype(np.int32), pat.indices.astype(np.int32)
+        AP = _product_in_x_order(A, P, (aprp, apci))
+        crp, cci = g("A.rp", l + 1), g("A.ci", l + 1)
+        Ac = _product_in_x_order(R, (aprp, apci, AP), (crp, cci))
+        dead = g("dead").reshape(na, k)
+        for a in np.nonzero(dead.any(1))[0]:
+            qd = crp[a] + int(np.nonzero(cci[crp[a]:crp[a + 1]] == a)[0][0])
+            for c in np.nonzero(dead[a])[0]:
+                Ac[qd, c, c] = 1.0
+        got = g("A.v", l + 1)
+        assert np.array_equal(got, Ac), (which, l, np.abs(got - Ac).max())
+    h.destroy()
+
+
 @pytest.mark.parametrize("smoother", [0, 1])
 def test_vcycle_parity_fp64(scr, ctx, small_fsi, smoother):
     s = small_fsi
