@@ -86,6 +86,7 @@ void split_blocks(const DBsr& K, DBsr& A, DBsr& G, DBsr& D, DBsr& C, Arena& ar, 
 constexpr int HS_MAX = 8192;       // largest LDS hash table per row
 constexpr int HMAX = HS_MAX / 2;   // unique columns allowed per row
 constexpr int HS_COUNT = 2048;     // first hash table of the counting pass (x4 on each overflow)
+constexpr int SPG_NW_BOUND = 2048; // mean candidates per row from which rows take four wavefronts
 
 // returns 1 if newly inserted (table of hs slots, hs a power of two, never more than half full)
 __device__ __forceinline__ int hash_insert(int* t, int hs, int key) {
@@ -117,15 +118,22 @@ __device__ __forceinline__ void block_max_to(T v, T* out) {
     }
 }
 
-// upper bound of the candidates of each row of X*Y (sum of the lengths of the Y rows it meets)
+// upper bound of the candidates of each row of X*Y (sum of the lengths of the Y rows it meets):
+// its maximum over the rows into *maxub, its sum into *sumub
 __global__ void __launch_bounds__(256) spg_bound_k(int64_t nr, const int32_t* __restrict__ xrp,
                                                    const int32_t* __restrict__ xci, const int32_t* __restrict__ yrp,
-                                                   int* __restrict__ maxub) {
+                                                   int* __restrict__ maxub, unsigned long long* __restrict__ sumub) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t ub = 0;
     if (i < nr)
         for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) ub += yrp[xci[q] + 1] - yrp[xci[q]];
-    block_max_to((int)(ub < (1 << 30) ? ub : (1 << 30)), maxub);
+    __shared__ unsigned long long red[256 / WAVE];
+    unsigned long long su = (unsigned long long)ub;
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) su += __shfl_xor(su, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = su;
+    block_max_to((int)(ub < (1 << 30) ? ub : (1 << 30)), maxub);     // its barrier orders red
+    if (threadIdx.x == 0) atomicAdd(sumub, red[0] + red[1] + red[2] + red[3]);
 }
 
 // largest of n counts (one atomic per workgroup)
@@ -135,14 +143,18 @@ __global__ void __launch_bounds__(256) max_i32_k(int64_t n, const int32_t* __res
     block_max_to(m, out);
 }
 
-// count (phase 0) or emit sorted (phase 1) the structural pattern of row i of X*Y.
-// Dynamic LDS: hs hash slots, then hs/2 + 64 list entries.
-template <int PHASE>
-__global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const int32_t* __restrict__ xrp,
-                                                     const int32_t* __restrict__ xci, const int32_t* __restrict__ yrp,
-                                                     const int32_t* __restrict__ yci, const uint8_t* __restrict__ rowmask,
-                                                     int32_t* __restrict__ cnt, const int32_t* __restrict__ crp,
-                                                     int32_t* __restrict__ cci, int* __restrict__ overflow) {
+// count (phase 0) or emit sorted (phase 1) the structural pattern of row i of X*Y, NW wavefronts
+// per row sharing one LDS hash table (NW = 4 for products whose rows meet thousands of candidates:
+// the table's LDS then serves four wavefronts instead of one).  In the counting pass a row whose
+// unique columns overflow the table gets cnt = -1 and raises the overflow flag; a retry pass
+// (retry = 1, larger table) recounts only those rows.
+// Dynamic LDS: hs hash slots, then hs/2 + NW * 64 list entries.
+template <int PHASE, int NW>
+__global__ void __launch_bounds__(NW * WAVE) spg_symbolic(int64_t nr, int hs, int retry, const int32_t* __restrict__ xrp,
+                                                          const int32_t* __restrict__ xci, const int32_t* __restrict__ yrp,
+                                                          const int32_t* __restrict__ yci, const uint8_t* __restrict__ rowmask,
+                                                          int32_t* __restrict__ cnt, const int32_t* __restrict__ crp,
+                                                          int32_t* __restrict__ cci, int* __restrict__ overflow) {
     extern __shared__ int smem[];
     int* table = smem;
     int* list = smem + hs;
@@ -150,20 +162,23 @@ __global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const i
     const int hmax = hs / 2;
     int64_t i = blockIdx.x;
     if (i >= nr) return;
-    int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    if (PHASE == 0 && retry && cnt[i] >= 0) return;
     if (rowmask && !rowmask[i]) {
-        if (PHASE == 0 && lane == 0) cnt[i] = 0;
+        if (PHASE == 0 && tid == 0) cnt[i] = 0;
         return;
     }
-    for (int t = lane; t < hs; t += WAVE) table[t] = -1;
-    if (lane == 0) nuniq = 0;
+    for (int t = tid; t < hs; t += NW * WAVE) table[t] = -1;
+    if (tid == 0) nuniq = 0;
     __syncthreads();
-    // The candidates (X entry q, Y entry t) of up to 64 X entries at a time are spread over all
-    // lanes: lane l holds the Y row of X entry q0 + l, an inclusive prefix of their lengths maps a
-    // candidate number to its (l, t) by a binary search over the prefix (every lane takes part in
-    // the shuffles).  Only a set is built here, so the order of insertion does not matter.
+    // The candidates (X entry q, Y entry t) of up to 64 X entries at a time are spread over the
+    // lanes of one wavefront (wavefront w takes chunks w, w + NW, ...): lane l holds the Y row of
+    // X entry q0 + l, an inclusive prefix of their lengths maps a candidate number to its (l, t) by
+    // a binary search over the prefix (every lane takes part in the shuffles).  Only a set is
+    // built here, so the order of insertion does not matter.
     const int32_t x0 = xrp[i], x1 = xrp[i + 1];
-    for (int32_t q0 = x0; q0 < x1; q0 += WAVE) {
+    for (int32_t q0 = x0 + (tid / WAVE) * WAVE; q0 < x1; q0 += NW * WAVE) {
         int st = 0, len = 0;
         if (q0 + lane < x1) {
             int32_t k = xci[q0 + lane];
@@ -190,7 +205,7 @@ __global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const i
                 int c = yci[stl + (cidx - excl)];
                 if (hash_insert(table, hs, c)) {
                     int pos = atomicAdd(&nuniq, 1);
-                    if (pos < hmax + WAVE) list[pos] = c;
+                    if (pos < hmax + NW * WAVE) list[pos] = c;
                 }
             }
         }
@@ -198,16 +213,19 @@ __global__ void __launch_bounds__(WAVE) spg_symbolic(int64_t nr, int hs, const i
     __syncthreads();
     int w = nuniq;
     if (w >= hmax) {
-        if (lane == 0) atomicOr(overflow, 1);
+        if (tid == 0) {
+            if (PHASE == 0) cnt[i] = -1;
+            atomicOr(overflow, 1);
+        }
         return;
     }
     if (PHASE == 0) {
-        if (lane == 0) cnt[i] = w;
+        if (tid == 0) cnt[i] = w;
         return;
     }
     // rank sort of the unique columns
     int32_t base = crp[i];
-    for (int a = lane; a < w; a += WAVE) {
+    for (int a = tid; a < w; a += NW * WAVE) {
         int key = list[a], rank = 0;
         for (int b = 0; b < w; ++b) rank += list[b] < key;
         cci[base + rank] = key;
@@ -417,24 +435,35 @@ DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hip
     C.rp = ar.make<int32_t>(X.nr + 1);
     int32_t* cnt = ar.make<int32_t>(X.nr + 1);
     int* flags = ar.make<int>(3);      // [overflow, max candidate bound, max output row length]
+    unsigned long long* csum = ar.make<unsigned long long>(1);   // candidates over all rows
     zero_dev(flags, 3 * sizeof(int), s);
-    if (X.nr > 0) spg_bound_k<<<cdiv(X.nr, 256), 256, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, flags + 1);
+    zero_dev(csum, sizeof(unsigned long long), s);
+    if (X.nr > 0) spg_bound_k<<<cdiv(X.nr, 256), 256, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, flags + 1, csum);
     int hflags[2] = {0, 0};
+    unsigned long long hsum = 0;
     HIPCHK(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&hsum, csum, sizeof(hsum), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    ar.free(csum);
     // hash table of the counting pass: twice the candidate bound, but at most HS_COUNT slots (the
-    // unique columns of a row are far fewer than its candidates); a row that overflows it makes
-    // the pass run again with a table four times larger.  The result does not depend on the table
-    // size.
+    // unique columns of a row are far fewer than its candidates); the rows that overflow it are
+    // counted again with a table four times larger.  The result does not depend on the table size.
+    // Products whose rows meet SPG_NW_BOUND candidates or more on average take four wavefronts
+    // per row.
+    const bool wide = X.nr > 0 && hsum >= (unsigned long long)SPG_NW_BOUND * (unsigned long long)X.nr;
     int need = 2 * (hflags[1] < HMAX ? hflags[1] : HMAX) + 2;
     int hs = 64;
     while (hs < need && hs < HS_COUNT) hs <<= 1;
     int hf[3] = {0, 0, 0};
-    for (;;) {
-        size_t lds = (size_t)(hs + hs / 2 + WAVE) * sizeof(int);
-        if (X.nr > 0)
-            spg_symbolic<0><<<X.nr, WAVE, lds, s>>>(X.nr, hs, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr,
-                                                    flags);
+    for (int retry = 0;; retry = 1) {
+        if (X.nr > 0) {
+            if (wide)
+                spg_symbolic<0, 4><<<X.nr, 4 * WAVE, (size_t)(hs + hs / 2 + 4 * WAVE) * sizeof(int), s>>>(
+                    X.nr, hs, retry, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr, flags);
+            else
+                spg_symbolic<0, 1><<<X.nr, WAVE, (size_t)(hs + hs / 2 + WAVE) * sizeof(int), s>>>(
+                    X.nr, hs, retry, X.rp, X.ci, Y.rp, Y.ci, rowmask, cnt, nullptr, nullptr, flags);
+        }
         check_launch("spg_count");
         HIPCHK(hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -456,9 +485,14 @@ DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hip
     // the filling pass knows the widest row exactly
     int hs1 = 64;
     while (hs1 < 2 * wmax + 2) hs1 <<= 1;
-    size_t lds1 = (size_t)(hs1 + hs1 / 2 + WAVE) * sizeof(int);
-    if (X.nr > 0)
-        spg_symbolic<1><<<X.nr, WAVE, lds1, s>>>(X.nr, hs1, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, flags);
+    if (X.nr > 0) {
+        if (wide)
+            spg_symbolic<1, 4><<<X.nr, 4 * WAVE, (size_t)(hs1 + hs1 / 2 + 4 * WAVE) * sizeof(int), s>>>(
+                X.nr, hs1, 0, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, flags);
+        else
+            spg_symbolic<1, 1><<<X.nr, WAVE, (size_t)(hs1 + hs1 / 2 + WAVE) * sizeof(int), s>>>(
+                X.nr, hs1, 0, X.rp, X.ci, Y.rp, Y.ci, rowmask, nullptr, C.rp, C.ci, flags);
+    }
     check_launch("spg_fill");
     ar.free(flags);
     spgemm_numeric_run(X, Y, C, wmax, s);
