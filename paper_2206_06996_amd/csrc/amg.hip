@@ -27,6 +27,15 @@ __device__ __forceinline__ int32_t find_col(const int32_t* __restrict__ ci, int3
     return (lo < e && ci[lo] == c) ? lo : -1;
 }
 
+// first index in [lo, hi) whose column is >= c (hi if none)
+__device__ __forceinline__ int32_t lower_col(const int32_t* __restrict__ ci, int32_t lo, int32_t hi, int32_t c) {
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (ci[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ uint64_t sm64(uint64_t x) {
     x += 0x9E3779B97F4A7C15ULL;
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -545,29 +554,57 @@ __global__ void diag_scale_D(int64_t nr, const int32_t* __restrict__ rp, const i
         for (int c = 0; c < 3; ++c) X[(int64_t)q * 3 + c] = Dv[(int64_t)q * 3 + c] / d[3 * (int64_t)j + c];
     }
 }
-// union pattern of C and DG (both sorted): count, then fill with C - DG
+// union pattern of C and DG (both sorted, a column at most once per row): count, then fill with
+// C - DG.  One wavefront per row: an entry's place in the union is its index in its own row, plus
+// the entries of the other row with smaller columns, minus the columns the two rows share below it
+// (a prefix count of the shared flags over its own row); a column in both rows is written once, by
+// its C entry.
 template <int PHASE>
-__global__ void merge_sub_k(int64_t nr, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
-                            const double* __restrict__ av, const int32_t* __restrict__ brp, const int32_t* __restrict__ bci,
-                            const double* __restrict__ bv, int32_t* __restrict__ cnt, const int32_t* __restrict__ crp,
-                            int32_t* __restrict__ cci, double* __restrict__ cv) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) merge_sub_k(int64_t nr, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                                                   const double* __restrict__ av, const int32_t* __restrict__ brp,
+                                                   const int32_t* __restrict__ bci, const double* __restrict__ bv,
+                                                   int32_t* __restrict__ cnt, const int32_t* __restrict__ crp,
+                                                   int32_t* __restrict__ cci, double* __restrict__ cv) {
+    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
     if (i >= nr) return;
-    int32_t a = arp[i], ae = arp[i + 1], b = brp[i], be = brp[i + 1];
-    int32_t o = PHASE ? crp[i] : 0;
-    int32_t n = 0;
-    while (a < ae || b < be) {
-        int32_t ca = a < ae ? aci[a] : INT32_MAX, cb = b < be ? bci[b] : INT32_MAX;
-        if (PHASE) {
-            if (ca == cb) { cci[o + n] = ca; cv[o + n] = av[a] - bv[b]; }
-            else if (ca < cb) { cci[o + n] = ca; cv[o + n] = av[a]; }
-            else { cci[o + n] = cb; cv[o + n] = -bv[b]; }
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint64_t below = (1ull << lane) - 1;
+    const int32_t a0 = arp[i], a1 = arp[i + 1], b0 = brp[i], b1 = brp[i + 1];
+    const int32_t o = PHASE ? crp[i] : 0;
+    int shared = 0;
+    for (int32_t base = a0; base < a1; base += WAVE) {
+        const int32_t a = base + lane;
+        const bool in = a < a1;
+        const int32_t ca = in ? aci[a] : 0;
+        const int32_t lb = in ? lower_col(bci, b0, b1, ca) : b1;
+        const bool m = in && lb < b1 && bci[lb] == ca;
+        const uint64_t mask = __ballot(m);
+        if (PHASE && in) {
+            const int32_t pos = (a - a0) + (lb - b0) - (shared + __popcll(mask & below));
+            cci[o + pos] = ca;
+            cv[o + pos] = m ? av[a] - bv[lb] : av[a];
         }
-        if (ca <= cb) ++a;
-        if (cb <= ca) ++b;
-        ++n;
+        shared += __popcll(mask);
     }
-    if (!PHASE) cnt[i] = n;
+    if (!PHASE) {
+        if (lane == 0) cnt[i] = (a1 - a0) + (b1 - b0) - shared;
+        return;
+    }
+    shared = 0;
+    for (int32_t base = b0; base < b1; base += WAVE) {
+        const int32_t b = base + lane;
+        const bool in = b < b1;
+        const int32_t cb = in ? bci[b] : 0;
+        const int32_t la = in ? lower_col(aci, a0, a1, cb) : a1;
+        const bool m = in && la < a1 && aci[la] == cb;
+        const uint64_t mask = __ballot(m);
+        if (in && !m) {
+            const int32_t pos = (la - a0) + (b - b0) - (shared + __popcll(mask & below));
+            cci[o + pos] = cb;
+            cv[o + pos] = -bv[b];
+        }
+        shared += __popcll(mask);
+    }
 }
 
 DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, int mode, double* d, Arena& ar,
@@ -583,13 +620,13 @@ DBsr schur_approx(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, in
     S.nr = C.nr; S.nc = C.nc; S.br = 1; S.bc = 1;
     S.rp = ar.make<int32_t>(C.nr + 1);
     int32_t* cnt = ar.make<int32_t>(C.nr + 1);
-    int64_t nb = cdiv(C.nr, 256);
-    if (nb) merge_sub_k<0><<<nb, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, cnt, nullptr, nullptr, nullptr);
+    int64_t nw = cdiv(C.nr, 256 / WAVE);
+    if (nw) merge_sub_k<0><<<nw, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, cnt, nullptr, nullptr, nullptr);
     S.nnzb = scan_i32(cnt, S.rp, C.nr, ar, s);
     ar.free(cnt);
     S.ci = ar.make<int32_t>(S.nnzb);
     S.v = ar.make<double>(S.nnzb);
-    if (nb) merge_sub_k<1><<<nb, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, nullptr, S.rp, S.ci, S.v);
+    if (nw) merge_sub_k<1><<<nw, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, nullptr, S.rp, S.ci, S.v);
     check_launch("merge_sub");
     bsr_release(DG, ar);
     return S;
@@ -604,8 +641,8 @@ void schur_update(const DBsr& A, const DBsr& G, const DBsr& D, const DBsr& C, in
     check_launch("diag_scale_D");
     DBsr DG = spgemm(X, G, nullptr, ar, s);
     ar.free(X.v);
-    int64_t nb = cdiv(C.nr, 256);
-    if (nb) merge_sub_k<1><<<nb, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, nullptr, S.rp, S.ci, S.v);
+    int64_t nw = cdiv(C.nr, 256 / WAVE);
+    if (nw) merge_sub_k<1><<<nw, 256, 0, s>>>(C.nr, C.rp, C.ci, C.v, DG.rp, DG.ci, DG.v, nullptr, S.rp, S.ci, S.v);
     check_launch("merge_sub");
     bsr_release(DG, ar);
 }
