@@ -287,6 +287,7 @@ __global__ void __launch_bounds__(256) spg_numeric(int64_t nr, const int32_t* __
 // the wave.
 // Dynamic LDS: hs keys, hs positions, wmax * M * P doubles, then wmax owner slots.
 constexpr int SPG_STEP_LEN = 32;
+constexpr int SPG_PF = 4;
 template <int M, int N, int P>
 __global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, int wmax, const int32_t* __restrict__ xrp,
                                                         const int32_t* __restrict__ xci, const double* __restrict__ xv,
@@ -333,6 +334,47 @@ __global__ void __launch_bounds__(WAVE) spg_numeric_lds(int64_t nr, int hs, int 
         const int nq = x1 - q0 < WAVE ? x1 - q0 : WAVE;
         if (total >= SPG_STEP_LEN * nq) {
             // long rows of Y: one X entry per step, its row of Y over the lanes
+            if constexpr (M == 1 && N == 1 && P == 1) {
+                // scalar: the first 64 entries of the Y rows of SPG_PF steps are loaded together
+                // before those steps run in order (the same terms, order and arithmetic as below)
+                const double xl = lane < nq ? xv[q0 + lane] : 0.0;
+                for (int j0 = 0; j0 < nq; j0 += SPG_PF) {
+                    int cpf[SPG_PF];
+                    double ypf[SPG_PF];
+#pragma unroll
+                    for (int u = 0; u < SPG_PF; ++u) {
+                        cpf[u] = -1;
+                        ypf[u] = 0.0;
+                        if (j0 + u < nq) {
+                            const int stj = __builtin_amdgcn_readlane(st, j0 + u);
+                            if (lane < __builtin_amdgcn_readlane(len, j0 + u)) {
+                                cpf[u] = yci[stj + lane];
+                                ypf[u] = yv[stj + lane];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < SPG_PF; ++u) {
+                        const int j = j0 + u;
+                        if (j >= nq) break;
+                        const double xj = __shfl(xl, j, WAVE);
+                        const int stj = __builtin_amdgcn_readlane(st, j);
+                        const int enj = stj + __builtin_amdgcn_readlane(len, j);
+                        for (int32_t t = stj + lane; t < enj; t += WAVE) {
+                            const int c = t == stj + lane ? cpf[u] : yci[t];
+                            const double y = t == stj + lane ? ypf[u] : yv[t];
+                            unsigned h = ((unsigned)c * 2654435761u) & (unsigned)(hs - 1);
+                            for (int g = 0; g < hs && keys[h] != c; ++g) h = (h + 1) & (unsigned)(hs - 1);
+                            if (keys[h] != c) continue;   // not reached: every column met is in the pattern
+                            double sum = 0.0;
+                            sum += xj * y;
+                            acc[pos[h]] += sum;
+                        }
+                        __syncthreads();
+                    }
+                }
+                continue;
+            }
             for (int j = 0; j < nq; ++j) {
                 const int stj = __builtin_amdgcn_readlane(st, j);
                 const int enj = stj + __builtin_amdgcn_readlane(len, j);
