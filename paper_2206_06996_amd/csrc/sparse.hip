@@ -213,27 +213,41 @@ __host__ __device__ __forceinline__ int64_t sell_gpos(int64_t t, int lane) {
     return ((t >> 2) * WAVE + lane) * SELL_G + (t & 3);
 }
 
+// The fill kernels split a slice's slots into SELL_FILL_PARTS consecutive parts (multiples of four
+// slots), one thread per (slice, part, lane): thread g of the grid takes slots [o0, o1) of the slice
+// [ob, e1) that starts at o0 = ob on entry.
+constexpr int SELL_FILL_PARTS = 4;
+__device__ __forceinline__ void sell_fill_part(int64_t g, int64_t& o0, int64_t e1, int64_t& o1) {
+    const int part = (int)((g / WAVE) % SELL_FILL_PARTS);
+    const int64_t cs = ((e1 - o0 + SELL_FILL_PARTS - 1) / SELL_FILL_PARTS + SELL_G - 1) / SELL_G * SELL_G;
+    o0 += part * cs;
+    o1 = o0 + cs < e1 ? o0 + cs : e1;
+}
+
 template <typename T>
 __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const double* __restrict__ v,
                           int br, int bc, int rps, const int32_t* __restrict__ rowid, const int32_t* __restrict__ off,
                           int32_t* __restrict__ sci, T* __restrict__ sv, int64_t nslices) {
     const bool grouped = br == 1 && bc == 1;
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t s = g / WAVE;
+    int64_t s = g / (SELL_FILL_PARTS * WAVE);
     if (s >= nslices) return;
     int lane = (int)(g % WAVE);
     int j = lane / br;
     int r = lane % br;
     int64_t i = j < rps ? rowid[s * rps + j] : -1;
     bool valid = i >= 0;
-    int64_t o0 = off[s], o1 = off[s + 1];
+    int64_t o0 = off[s], o1, e1 = off[s + 1];
+    sell_fill_part(g, o0, e1, o1);
+    if (o0 >= o1) return;
     int32_t lo = 0, hi = 0, pad = 0;
     if (valid) {
         lo = rp[i]; hi = rp[i + 1];
         pad = hi > lo ? ci[hi - 1] : 0;
     }
+    const int64_t ob = off[s];   // first slot of the slice: slot t holds entry lo + (t - ob) of the row
     if (grouped) {
-        // whole groups of four slots (the slice's slot range is a multiple of four)
+        // whole groups of four slots (the slice's slot range and each part are multiples of four)
         typedef int32_t I4 __attribute__((ext_vector_type(4)));
         typedef T V4 __attribute__((ext_vector_type(4)));
         for (int64_t t = o0; t < o1; t += SELL_G) {
@@ -241,7 +255,7 @@ __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restr
             V4 vv;
 #pragma unroll
             for (int u = 0; u < SELL_G; ++u) {
-                const int64_t q = lo + (t + u - o0);
+                const int64_t q = lo + (t + u - ob);
                 const bool real = valid && q < hi;
                 cc[u] = real ? ci[q] : pad;
                 vv[u] = real ? (T)v[q] : (T)0;
@@ -254,7 +268,7 @@ __global__ void sell_fill(const int32_t* __restrict__ rp, const int32_t* __restr
     bool colwriter = j < rps && r == 0;
     const bool paired = sell_paired(bc, (int)sizeof(T));
     for (int64_t t = o0; t < o1; ++t) {
-        int64_t q = lo + (t - o0);
+        int64_t q = lo + (t - ob);
         bool real = valid && q < hi;
         if (colwriter) sci[t * rps + j] = real ? ci[q] : pad;
         for (int k = 0; k < bc; ++k)
@@ -280,18 +294,21 @@ __global__ void sell_fill_rowlane(const int32_t* __restrict__ rp, const int32_t*
                                   const int32_t* __restrict__ off, int32_t* __restrict__ sci, T* __restrict__ sv,
                                   int64_t nslices) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t s = g / WAVE;
+    int64_t s = g / (SELL_FILL_PARTS * WAVE);
     if (s >= nslices) return;
     int lane = (int)(g % WAVE);
-    int64_t i = rowid[g];
+    const int64_t ob = off[s];
+    int64_t o0 = ob, o1, e1 = off[s + 1];
+    sell_fill_part(g, o0, e1, o1);
+    if (o0 >= o1) return;
+    int64_t i = rowid[s * WAVE + lane];
     int32_t lo = 0, hi = 0, pad = 0;
     if (i >= 0) {
         lo = rp[i]; hi = rp[i + 1];
         pad = hi > lo ? ci[hi - 1] : 0;
     }
-    int64_t o0 = off[s], o1 = off[s + 1];
     for (int64_t t = o0; t < o1; ++t) {
-        int64_t q = lo + (t - o0);
+        int64_t q = lo + (t - ob);
         bool real = i >= 0 && q < hi;
         sci[t * WAVE + lane] = real ? ci[q] : pad;
         for (int e = 0; e < nb2; ++e)
@@ -321,11 +338,11 @@ DSell<T> sell_from_bsr(const DBsr& A, Arena& ar, hipStream_t s) {
     S.ci = ar.make<int32_t>(S.slots * S.rps + 1);
     if (S.rowlane) {
         S.v = ar.make<T>(S.slots * WAVE * A.br * A.bc + 1);
-        sell_fill_rowlane<T><<<cdiv(S.nslices * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br * A.bc, S.rowid, S.off,
+        sell_fill_rowlane<T><<<cdiv(S.nslices * SELL_FILL_PARTS * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br * A.bc, S.rowid, S.off,
                                                                         S.ci, S.v, S.nslices);
     } else {
         S.v = ar.make<T>(S.slots * WAVE * A.bc + 1);
-        sell_fill<T><<<cdiv(S.nslices * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br, A.bc, S.rps, S.rowid, S.off,
+        sell_fill<T><<<cdiv(S.nslices * SELL_FILL_PARTS * WAVE, 256), 256, 0, s>>>(A.rp, A.ci, A.v, A.br, A.bc, S.rps, S.rowid, S.off,
                                                                 S.ci, S.v, S.nslices);
     }
     check_launch("sell_fill");
@@ -1304,44 +1321,48 @@ template void dense_mv<float>(int64_t, const double*, const float*, float*, hipS
 // ---------------------------------------------------------------- input validation
 // bits: 1 row_ptr, 2 column out of range, 4 unsorted/duplicate, 8 missing diagonal,
 //       16 non-finite value, 32 zero on the velocity diagonal (bs 4) or the diagonal (bs 1)
-__global__ void validate_k(int64_t nr, int bs, int64_t nnzb, const int32_t* __restrict__ rp,
-                           const int32_t* __restrict__ ci, const double* __restrict__ v, int* __restrict__ flags) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per row (lane l checks entries lo + l, lo + l + 64, ...); the bits found are OR-ed
+// over the wavefront and raised by one atomic.
+__global__ void __launch_bounds__(256) validate_k(int64_t nr, int bs, int64_t nnzb, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                                  int* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
     if (i >= nr) return;
+    const int lane = threadIdx.x & (WAVE - 1);
     int f = 0;
-    int64_t lo = rp[i], hi = rp[i + 1];
+    const int64_t lo = rp[i], hi = rp[i + 1];
     if (i == 0 && lo != 0) f |= 1;
     if (i == nr - 1 && hi != nnzb) f |= 1;
     if (lo < 0 || hi > nnzb || lo > hi) {
-        atomicOr(flags, f | 1);
+        if (lane == 0) atomicOr(flags, f | 1);
         return;
     }
     bool diag = false;
-    int64_t prev = -1;
-    int bb = bs * bs;
-    for (int64_t q = lo; q < hi; ++q) {
-        int64_t c = ci[q];
+    const int bb = bs * bs;
+    const int nd = bs == 4 ? 3 : bs;   // the velocity diagonal (diag(A)) must be nonzero
+    for (int64_t q = lo + lane; q < hi; q += WAVE) {
+        const int64_t c = ci[q];
         if (c < 0 || c >= nr) { f |= 2; continue; }
-        if (c <= prev) f |= 4;
-        prev = c;
+        const int64_t pc = q > lo ? ci[q - 1] : -1;   // an out-of-range neighbour is reported as such
+        if (pc >= 0 && pc < nr && c <= pc) f |= 4;
         for (int e = 0; e < bb; ++e)
             if (!isfinite(v[q * bb + e])) f |= 16;
         if (c == i) {
             diag = true;
-            int nd = bs == 4 ? 3 : bs;   // the velocity diagonal (diag(A)) must be nonzero
             for (int k = 0; k < nd; ++k)
                 if (v[q * bb + k * bs + k] == 0.0) f |= 32;
         }
     }
-    if (!diag) f |= 8;
-    if (f) atomicOr(flags, f);
+    if (!__any(diag)) f |= 8;
+    for (int o = WAVE / 2; o > 0; o >>= 1) f |= __shfl_xor(f, o, WAVE);
+    if (lane == 0 && f) atomicOr(flags, f);
 }
 
 int validate_bsr(int64_t nr, int bs, int64_t nnzb, const int32_t* rp, const int32_t* ci, const double* v, Arena& ar,
                  hipStream_t s) {
     int* flags = ar.make<int>(1);
     zero_dev(flags, sizeof(int), s);
-    if (nr > 0) validate_k<<<cdiv(nr, 256), 256, 0, s>>>(nr, bs, nnzb, rp, ci, v, flags);
+    if (nr > 0) validate_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, bs, nnzb, rp, ci, v, flags);
     check_launch("validate");
     int h = 0;
     HIPCHK(hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s));
