@@ -304,7 +304,7 @@ def kernel_table(trace_dir, levels_json):
             rate, frac = f"{gbs:.0f}", f"{gbs / HBM_PEAK_GBS:.2f}"
         else:
             b_call, rate, frac = "-", "-", "-"
-        short = name.replace("void ", "").split("(")[0][:70]
+        short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0][:70]
         print(f"| {a['ns'] / 1e6:.2f} | {100 * a['ns'] / total_ns:.1f} | {a['calls']} | {a['ns'] / a['calls'] / 1e3:.2f} | "
               f"{b_call} | {rate} | {frac} | {', '.join(sorted(a['where']))[:40]} | `{short}` |")
     for name, a in agg.items():
