@@ -128,21 +128,35 @@ __device__ __forceinline__ void block_max_to(T v, T* out) {
 }
 
 // upper bound of the candidates of each row of X*Y (sum of the lengths of the Y rows it meets):
-// its maximum over the rows into *maxub, its sum into *sumub
+// its maximum over the rows into *maxub, its sum into *sumub.  A wavefront per row (grid-stride over
+// the rows, at most SPG_BOUND_BLOCKS workgroups), one atomic of each kind per workgroup.
+constexpr int SPG_BOUND_BLOCKS = 4096;
 __global__ void __launch_bounds__(256) spg_bound_k(int64_t nr, const int32_t* __restrict__ xrp,
                                                    const int32_t* __restrict__ xci, const int32_t* __restrict__ yrp,
                                                    int* __restrict__ maxub, unsigned long long* __restrict__ sumub) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t ub = 0;
-    if (i < nr)
-        for (int32_t q = xrp[i]; q < xrp[i + 1]; ++q) ub += yrp[xci[q] + 1] - yrp[xci[q]];
-    __shared__ unsigned long long red[256 / WAVE];
-    unsigned long long su = (unsigned long long)ub;
+    __shared__ int64_t redm[256 / WAVE];
+    __shared__ unsigned long long reds[256 / WAVE];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    int64_t mx = 0;
+    unsigned long long sm = 0;
+    for (int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + w; i < nr; i += (int64_t)gridDim.x * (256 / WAVE)) {
+        int64_t ub = 0;
+        for (int32_t q = xrp[i] + lane; q < xrp[i + 1]; q += WAVE) {
+            const int32_t k = xci[q];
+            ub += yrp[k + 1] - yrp[k];
+        }
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) su += __shfl_xor(su, o, WAVE);
-    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = su;
-    block_max_to((int)(ub < (1 << 30) ? ub : (1 << 30)), maxub);     // its barrier orders red
-    if (threadIdx.x == 0) atomicAdd(sumub, red[0] + red[1] + red[2] + red[3]);
+        for (int o = WAVE / 2; o > 0; o >>= 1) ub += __shfl_xor(ub, o, WAVE);
+        mx = ub > mx ? ub : mx;
+        sm += (unsigned long long)ub;
+    }
+    if (lane == 0) { redm[w] = mx; reds[w] = sm; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 256 / WAVE; ++v) { mx = redm[v] > mx ? redm[v] : mx; sm += reds[v]; }
+        atomicMax(maxub, (int)(mx < (1 << 30) ? mx : (1 << 30)));
+        atomicAdd(sumub, sm);
+    }
 }
 
 // largest of n counts (one atomic per workgroup)
@@ -489,7 +503,9 @@ DBsr spgemm(const DBsr& X, const DBsr& Y, const uint8_t* rowmask, Arena& ar, hip
     unsigned long long* csum = ar.make<unsigned long long>(1);   // candidates over all rows
     zero_dev(flags, 3 * sizeof(int), s);
     zero_dev(csum, sizeof(unsigned long long), s);
-    if (X.nr > 0) spg_bound_k<<<cdiv(X.nr, 256), 256, 0, s>>>(X.nr, X.rp, X.ci, Y.rp, flags + 1, csum);
+    if (X.nr > 0)
+        spg_bound_k<<<(unsigned)std::min<int64_t>(cdiv(X.nr, 256 / WAVE), SPG_BOUND_BLOCKS), 256, 0, s>>>(
+            X.nr, X.rp, X.ci, Y.rp, flags + 1, csum);
     int hflags[2] = {0, 0};
     unsigned long long hsum = 0;
     HIPCHK(hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
