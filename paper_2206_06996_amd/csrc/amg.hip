@@ -818,9 +818,11 @@ __global__ void mis_init_k(int64_t nr, const uint8_t* __restrict__ iso, uint64_t
     st[i] = iso[i] ? 0ULL : (ST_UND | mis_key(seed, level, i));
 }
 __global__ void mis_max_k(int64_t nr, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                          const uint8_t* __restrict__ flags, const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+                          const uint8_t* __restrict__ flags, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                          const uint64_t* __restrict__ und_only) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nr) return;
+    if (und_only && (und_only[i] >> 62) != 1) return;
     uint64_t m = in[i];
     for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
         if (flags[q]) {
@@ -832,10 +834,12 @@ __global__ void mis_max_k(int64_t nr, const int32_t* __restrict__ rp, const int3
 // the same with one wavefront per row (levels with long rows)
 __global__ void __launch_bounds__(256) mis_max_wave_k(int64_t nr, const int32_t* __restrict__ rp,
                                                       const int32_t* __restrict__ ci, const uint8_t* __restrict__ flags,
-                                                      const uint64_t* __restrict__ in, uint64_t* __restrict__ out) {
+                                                      const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                      const uint64_t* __restrict__ und_only) {
     const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     if (i >= nr) return;
+    if (und_only && (und_only[i] >> 62) != 1) return;
     uint64_t m = 0;
     for (int32_t q = rp[i] + lane; q < rp[i + 1]; q += WAVE)
         if (flags[q]) {
@@ -1822,12 +1826,13 @@ std::unique_ptr<Hierarchy> build_hierarchy(const DBsr& A0, const double* B0, int
         for (int round = 0;; ++round) {
             if (round > 100000) throw Error(SCR_E_HIP, "MIS-2 did not terminate");
             zero_dev(und, sizeof(int), s);
+            // the second sweep only for the undecided nodes: the decision reads nothing else of m2
             if (wide) {
-                mis_max_wave_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1);
-                mis_max_wave_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2);
+                mis_max_wave_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1, nullptr);
+                mis_max_wave_k<<<cdiv(nr, 256 / WAVE), 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2, st);
             } else {
-                mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1);
-                mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2);
+                mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, st, m1, nullptr);
+                mis_max_k<<<g, 256, 0, s>>>(nr, L.A.rp, L.A.ci, L.strong, m1, m2, st);
             }
             mis_decide_k<<<g, 256, 0, s>>>(nr, st, m2, und);
             check_launch("mis2");
