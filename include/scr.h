@@ -182,7 +182,9 @@ int64_t scr_ctx_bytes_in_use(const scr_ctx* ctx);
  * coords: device, n_brows x 3 FP64 (node coordinates; required for SCR_SYSTEM, ignored for
  * MESH_SYSTEM).  K is copied.  Errors: SCR_E_INVALID for a malformed K (unsorted or
  * out-of-range columns, missing or zero diagonal, non-finite values, bs not 4/1 for the
- * kind), SCR_E_OOM, SCR_E_HIP. */
+ * kind) or for a sparse product of the setup (A P, R (A P)) with a row of more than 4,096
+ * distinct block columns (a row coupled to nodes spread over the whole mesh), SCR_E_OOM,
+ * SCR_E_HIP. */
 scr_status amg_setup(scr_ctx* ctx, int kind, const scr_bsr* K, const double* coords,
                      const scr_amg_opts* opts /* host, NULL = defaults */, void* stream,
                      scr_handle** out /* host */);

@@ -197,6 +197,80 @@ def test_galerkin_product_bitwise_in_row_order(scr, ctx, small_fsi, which):
     h.destroy()
 
 
+def _grid_with_hubs(n=200, hubs=4, stride=2, eps=1e-3, spread=False):
+    """SPD scalar matrix: the 5-point Laplacian of an n x n grid plus `hubs` extra rows, hub h weakly
+    coupled to every `stride`-th node of the h-th of `hubs` equal bands of the grid (or of the whole
+    grid with `spread`); every row diagonally dominant."""
+    import scipy.sparse as sps
+    m = n * n
+    I = sps.identity(n, format="csr")
+    T = sps.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    L = (sps.kron(I, T) + sps.kron(T, I)).tocsr()
+    cols = [np.arange(h, m, stride) if spread else np.arange(h * m // hubs, (h + 1) * m // hubs, stride)
+            for h in range(hubs)]
+    r = np.concatenate([np.full(c.size, h) for h, c in enumerate(cols)])
+    B = sps.csr_matrix((np.full(r.size, -eps), (np.concatenate(cols), r)), shape=(m, hubs))
+    Dh = sps.diags([eps * c.size + 1.0 for c in cols])
+    A = sps.bmat([[L + sps.diags(np.asarray(abs(B).sum(axis=1)).ravel()), B], [B.T, Dh]], format="csr")
+    A.sort_indices()
+    return A
+
+
+def test_galerkin_product_with_rows_wider_than_the_counting_table(scr, ctx):
+    """Rows coupled to thousands of nodes make rows of A_0 P_0 exceed the first counting table (1,024
+    unique columns), so the counting pass recounts those rows with a larger table; every Galerkin
+    product of AMG(L) must still equal the row-order product bit for bit, on the structural pattern."""
+    import scipy.sparse as sps
+    A = _grid_with_hubs()
+    rp, ci, v = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+    print(f"[gpu] mesh amg_setup with hub rows n={A.shape[0]} nnz={A.nnz} widest row {np.diff(rp).max()}", flush=True)
+    h = scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(rp), dev(ci), dev(v), None, scr.amg_opts())
+    nl = h.hier_levels(2)
+    assert nl >= 2
+    widest = 0
+    for l in range(nl - 1):
+        def g(f, lev=l):
+            return h.hier_level_copy(2, lev, f)
+        i = h.hier_level_info(2, l)
+        na = i["nagg"]
+        A_ = (g("A.rp"), g("A.ci"), g("A.v"))
+        P = (g("P.rp"), g("P.ci"), g("P.v"))
+        R = (g("R.rp"), g("R.ci"), g("R.v"))
+        pat = (sps.csr_matrix((np.ones(A_[1].size), A_[1], A_[0]), shape=(i["nr"], i["nr"]))
+               @ sps.csr_matrix((np.ones(P[1].size), P[1], P[0]), shape=(i["nr"], na))).tocsr()
+        pat.sort_indices()
+        aprp, apci = pat.indptr.astype(np.int32), pat.indices.astype(np.int32)
+        widest = max(widest, int(np.diff(aprp).max()))
+        AP = _product_in_x_order(A_, P, (aprp, apci))
+        crp, cci = g("A.rp", l + 1), g("A.ci", l + 1)
+        cpat = (sps.csr_matrix((np.ones(R[1].size), R[1], R[0]), shape=(na, i["nr"])) @ pat).tocsr()
+        cpat.sort_indices()
+        assert np.array_equal(crp, cpat.indptr) and np.array_equal(cci, cpat.indices), l
+        Ac = _product_in_x_order(R, (aprp, apci, AP), (crp, cci))
+        dead = g("dead")
+        for a in np.nonzero(dead)[0]:
+            Ac[crp[a] + int(np.nonzero(cci[crp[a]:crp[a + 1]] == a)[0][0]), 0, 0] = 1.0
+        assert np.array_equal(g("A.v", l + 1), Ac), (l, np.abs(g("A.v", l + 1) - Ac).max())
+    assert widest > 1024        # the recount with the larger table did happen
+    h.destroy()
+
+
+def test_product_row_beyond_the_largest_table_is_an_error(scr, ctx):
+    """A row of A_0 P_0 with more than 4,096 distinct columns (a hub coupled across the whole grid
+    meets every aggregate) is refused with SCR_E_INVALID, and the context still serves a setup."""
+    A = _grid_with_hubs(stride=4, spread=True)
+    rp, ci, v = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+    print(f"[gpu] mesh amg_setup, hub rows across the grid n={A.shape[0]} nnz={A.nnz}", flush=True)
+    with pytest.raises(scr.ScrError) as e:
+        scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(rp), dev(ci), dev(v), None, scr.amg_opts())
+    assert e.value.status == scr.SCR_E_INVALID and "wider than 4096" in str(e.value)
+    A = _grid_with_hubs()
+    h = scr.amg_setup(ctx, scr.MESH_SYSTEM, dev(A.indptr.astype(np.int32)), dev(A.indices.astype(np.int32)),
+                      dev(A.data.astype(np.float64)), None, scr.amg_opts())
+    assert h.hier_levels(2) >= 2
+    h.destroy()
+
+
 @pytest.mark.parametrize("smoother", [0, 1])
 def test_vcycle_parity_fp64(scr, ctx, small_fsi, smoother):
     s = small_fsi
